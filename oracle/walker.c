@@ -1,0 +1,198 @@
+/*
+ * Plain C random walker for the Monte Carlo NEGF estimator (oracle).
+ *
+ * TEST INFRASTRUCTURE ONLY: built and called by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg.  Shares no code with the HIP library.
+ *
+ * The walk is the elastic linear-response procedure of Sec. II E-F of Musland, Bergli and
+ * Flage-Larsen: inject at lead p (steps 3-4 with the channel marginalised), then repeat
+ * step 6' (Eqs. (75), (76)) until a lead is drawn.  The estimator of Eq. (66) is
+ * Tr Gamma_p A times [exit lead == q]; this file only counts exits, the caller multiplies.
+ *
+ * Random numbers: Philox4x32-10, written from its published definition (J. K. Salmon,
+ * M. A. Moraes, R. O. Dror, D. E. Shaw, "Parallel random numbers: as easy as 1, 2, 3",
+ * SC'11): 10 rounds of two 32x32->64 multiplications with constants 0xD2511F53 and
+ * 0xCD9E8D57, Weyl key increments 0x9E3779B9 and 0xBB67AE85.
+ *
+ * Stream layout (the HIP walker draws exactly the same words):
+ *   key     = (seed & 0xffffffff, seed >> 32)
+ *   tag     = (realization << 1) | inject_lead
+ *   block j of walker w at energy index k: counter = (j, w, k, tag)
+ *   step n of a walk uses words (2*(n&1), 2*(n&1)+1) of block n>>1: call them (a, b)
+ *
+ * Two samplers:
+ *   cdf   : the paper's rule (Sec. III B): u = 53-bit uniform from (a, b); cumulative sums
+ *           b_j of the row normalised by the last one; the first j with b_j > u is drawn.
+ *   alias : a given alias table (uint32 thresholds, int32 aliases): bucket c = (a*n)>>32
+ *           with Lemire's rejection of the low word below (2^32 - n) mod n; the r-th redraw
+ *           of step n takes word 0 of Philox(counter = (n, w, k, tag | 0x80000000),
+ *           key = (key0, key1 ^ r)); outcome = (b < thr[c]) ? c : alias[c].
+ *
+ * Tallies per energy (int64, accumulated): [absorbed at L, absorbed at R, truncated,
+ * sum of steps, sum of squared steps].  Injection counts as one step.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+typedef struct {
+    uint32_t key[2];
+    uint32_t w, k, tag;
+    uint32_t block_index;   /* which block is cached in words[] (UINT32_MAX: none) */
+    uint32_t words[4];
+} stream_t;
+
+static void stream_init(stream_t *s, uint64_t seed, uint32_t w, uint32_t k, uint32_t tag)
+{
+    s->key[0] = (uint32_t)(seed & 0xffffffffu);
+    s->key[1] = (uint32_t)(seed >> 32);
+    s->w = w; s->k = k; s->tag = tag;
+    s->block_index = 0xffffffffu;
+}
+
+static void stream_pair(stream_t *s, uint32_t n, uint32_t *a, uint32_t *b)
+{
+    uint32_t j = n >> 1;
+    if (s->block_index != j) {
+        uint32_t ctr[4] = {j, s->w, s->k, s->tag};
+        oracle_philox4x32_10(ctr, s->key, s->words);
+        s->block_index = j;
+    }
+    *a = s->words[2 * (n & 1)];
+    *b = s->words[2 * (n & 1) + 1];
+}
+
+static uint32_t lemire_bucket(stream_t *s, uint32_t n_step, uint32_t a, uint32_t nout)
+{
+    uint32_t r = 0;
+    for (;;) {
+        uint64_t m = (uint64_t)a * (uint64_t)nout;
+        uint32_t lo = (uint32_t)m;
+        if (lo >= nout || lo >= (uint32_t)(0u - nout) % nout)
+            return (uint32_t)(m >> 32);
+        ++r;
+        uint32_t ctr[4] = {n_step, s->w, s->k, s->tag | 0x80000000u};
+        uint32_t key[2] = {s->key[0], s->key[1] ^ r};
+        uint32_t out[4];
+        oracle_philox4x32_10(ctr, key, out);
+        a = out[0];
+    }
+}
+
+/* Paper's step-6' sampler on a dense weight row (Sec. III B). */
+static int32_t draw_cdf(const double *row, int32_t n, uint32_t a, uint32_t b)
+{
+    uint64_t bits = ((uint64_t)a << 21) | (uint64_t)(b >> 11);
+    double u = (double)bits * (1.0 / 9007199254740992.0);
+    double total = 0.0;
+    for (int32_t j = 0; j < n; ++j) total += row[j];
+    double cum = 0.0;
+    for (int32_t j = 0; j < n; ++j) {
+        cum += row[j];
+        if (cum / total > u) return j;
+    }
+    return n - 1;
+}
+
+/* mode 0: cdf on K [nE][n][n] row-major; mode 1: alias tables thr/alias [nE][n][pitch]. */
+static int walk_impl(int mode, const double *K, const uint32_t *thr, const int32_t *alias,
+                     int64_t pitch, int32_t nE, int32_t n, uint64_t seed, uint32_t realization,
+                     uint32_t inject_lead, uint64_t walker_begin, uint64_t n_walkers,
+                     uint32_t max_steps, int64_t *tallies)
+{
+    if (n < 3 || nE < 1 || inject_lead > 1 || realization >= (1u << 30)) return -1;
+    if (walker_begin + n_walkers > 0x100000000ull) return -1;
+    const int32_t N = n - 2;
+    const uint32_t tag = (realization << 1) | inject_lead;
+    for (int32_t k = 0; k < nE; ++k) {
+        int64_t cL = 0, cR = 0, tr = 0, s1 = 0, s2 = 0;
+#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : cL, cR, tr, s1, s2)
+        for (int64_t i = 0; i < (int64_t)n_walkers; ++i) {
+            uint32_t w = (uint32_t)(walker_begin + (uint64_t)i);
+            stream_t st;
+            stream_init(&st, seed, w, (uint32_t)k, tag);
+            int32_t s = N + (int32_t)inject_lead;
+            uint32_t steps = 0;
+            int outcome = -1;
+            while (steps < max_steps) {
+                uint32_t a, b;
+                stream_pair(&st, steps, &a, &b);
+                int32_t next;
+                if (mode == 0) {
+                    next = draw_cdf(K + ((int64_t)k * n + s) * (int64_t)n, n, a, b);
+                } else {
+                    uint32_t c = lemire_bucket(&st, steps, a, (uint32_t)n);
+                    int64_t e = ((int64_t)k * n + s) * pitch + c;
+                    next = (b < thr[e]) ? (int32_t)c : alias[e];
+                }
+                ++steps;
+                if (next >= N) { outcome = next - N; break; }
+                s = next;
+            }
+            if (outcome == 0) ++cL;
+            else if (outcome == 1) ++cR;
+            else ++tr;
+            s1 += steps;
+            s2 += (int64_t)steps * (int64_t)steps;
+        }
+        tallies[5 * k + 0] += cL;
+        tallies[5 * k + 1] += cR;
+        tallies[5 * k + 2] += tr;
+        tallies[5 * k + 3] += s1;
+        tallies[5 * k + 4] += s2;
+    }
+    return 0;
+}
+
+int oracle_walk_cdf(const double *K, int32_t nE, int32_t n, uint64_t seed, uint32_t realization,
+                    uint32_t inject_lead, uint64_t walker_begin, uint64_t n_walkers,
+                    uint32_t max_steps, int64_t *tallies)
+{
+    return walk_impl(0, K, NULL, NULL, 0, nE, n, seed, realization, inject_lead, walker_begin,
+                     n_walkers, max_steps, tallies);
+}
+
+int oracle_walk_alias(const uint32_t *thr, const int32_t *alias, int64_t pitch, int32_t nE,
+                      int32_t n, uint64_t seed, uint32_t realization, uint32_t inject_lead,
+                      uint64_t walker_begin, uint64_t n_walkers, uint32_t max_steps,
+                      int64_t *tallies)
+{
+    if (pitch < n) return -1;
+    return walk_impl(1, NULL, thr, alias, pitch, nE, n, seed, realization, inject_lead,
+                     walker_begin, n_walkers, max_steps, tallies);
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,80 @@
+"""Seeded synthetic workloads shared by the HIP path's callers and the oracle's tests.
+
+This module holds only workload definitions and seeded random inputs (onsite disorder,
+per-site dephasing rates).  It contains none of the method's arithmetic: no Green's
+functions, no transmissions, no quadrature.
+
+The workloads stand in for the paper's CdTe nanowires (Sec. IV: two-by-two unit-cell
+cross-section, 32x32 Hamiltonian blocks, lengths of tens of unit cells, dephasing rates of a
+few percent of the band scale).  The CdTe tight-binding parameters are not available, so a
+square-lattice tight-binding wire of width W and length L with hopping t stands in, with
+uniform Anderson disorder and a site-diagonal dephasing rate eta (Sec. III A: constant
+lifetime, sigma_i = -(i/2) gamma_i).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+RNG_SEED = 180510164          # key of the walkers' counter-based generator
+DISORDER_SEED_BASE = 1805     # disorder realization r uses seed DISORDER_SEED_BASE + r
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    """One synthetic transport problem: a W x L wire between two clean leads."""
+    name: str
+    W: int                    # sites per slice
+    L: int                    # slices
+    t: float = 1.0            # hopping (H_ij = -t between nearest neighbours)
+    eta: float = 0.05         # dephasing rate gamma_i on every site
+    disorder: float = 0.0     # onsite V_i ~ U[-disorder, disorder] (times t)
+    emin: float = -1.9
+    emax: float = 1.9
+    n_energies: int = 64
+    walkers_per_energy: int = 100_000
+    lead_model: int = 0       # 0 clean semi-infinite leads, 1 wide-band leads
+    gamma_l: float = 0.0      # wide-band coupling (lead_model 1)
+    delta_lead: float = 1e-10 # regulator inside the leads, z = E + i delta_lead (times t)
+    realization: int = 0
+
+    @property
+    def N(self) -> int:
+        return self.W * self.L
+
+    def replace(self, **kw) -> "Workload":
+        return dataclasses.replace(self, **kw)
+
+
+# 1D chain, N = 50 sites, eta = 0.05 t, 64 energies in [-1.9 t, 1.9 t], 1e5 walkers / energy.
+CHAIN50 = Workload(name="chain_N50_eta0.05", W=1, L=50, eta=0.05, emin=-1.9, emax=1.9,
+                   n_energies=64, walkers_per_energy=100_000)
+
+# 2D wire W = 10, L = 100 (N = 1000), disorder U[-0.25 t, 0.25 t], 256 energies in
+# [-3.5 t, 3.5 t], 1e6 walkers / energy; eta in {0.01, 0.05, 0.1} t.
+WIRE_W10_L100 = Workload(name="wire_W10_L100", W=10, L=100, eta=0.05, disorder=0.25,
+                         emin=-3.5, emax=3.5, n_energies=256, walkers_per_energy=1_000_000)
+WIRE_ETAS = (0.01, 0.05, 0.1)
+
+
+def onsite(w: Workload) -> np.ndarray:
+    """Onsite energies V_i (float64, length N, slice-major i = x*W + y).
+
+    Uniform iid disorder drawn with numpy's default generator seeded by
+    DISORDER_SEED_BASE + realization; all zeros when the disorder amplitude is zero.
+    """
+    if w.disorder == 0.0:
+        return np.zeros(w.N, dtype=np.float64)
+    rng = np.random.default_rng(DISORDER_SEED_BASE + w.realization)
+    return rng.uniform(-w.disorder * w.t, w.disorder * w.t, size=w.N).astype(np.float64)
+
+
+def dephasing(w: Workload) -> np.ndarray:
+    """Per-site dephasing rates gamma_i = eta (float64, length N)."""
+    return np.full(w.N, w.eta * w.t, dtype=np.float64)
+
+
+def random_sites(n: int, seed: int, lo: float, hi: float) -> np.ndarray:
+    """Seeded uniform values, used by tests for random onsite or dephasing arrays."""
+    return np.random.default_rng(seed).uniform(lo, hi, size=n).astype(np.float64)
