@@ -1,0 +1,221 @@
+/*
+ * mcnegf.h -- C ABI of the MI355X (gfx950) library for the Monte Carlo NEGF method with
+ * elastic Buttiker dephasing of Musland, Bergli and Flage-Larsen, "A Monte Carlo method
+ * for solving the NEGF equations for electron transport".
+ *
+ * The library computes, for every energy E_k of a batch, in FP64 on the GPU:
+ *   1. G^r = (E - H - Sigma_L - Sigma_R - Sigma_B)^{-1} of a W x L tight-binding wire by
+ *      block-tridiagonal recursive Green's functions (Sec. III B; Sec. II A, Eq. (7));
+ *   2. the walker's positive transition kernel: from probe j, weight gamma_i |G_ij|^2 to
+ *      probe i and <psi_j|Gamma_r|psi_j> to lead r with psi_j = G|j> (step 6', Sec. II F,
+ *      Eqs. (75), (76)); from a lead, the eigen-channel marginal of steps 3-4 (Eq. (39));
+ *      one alias table per row;
+ *   3. random walks that inject at a lead, hop between probe sites and are absorbed at a
+ *      lead, counting exits; the estimator of the transmission is Tr Gamma_p A times
+ *      [exit at q] (Sec. II E, Eq. (66));
+ *   4. the effective L->R transmission either from the walk tallies (MC) or from the
+ *      deterministic probe-conservation system (Sec. III C, Eq. (79)), and the current
+ *      I = sum_k w_k T_eff(E_k) (midpoint quadrature, Sec. III C).
+ *
+ * Model.  Sites i = x*W + y (x = 0..L-1 slices, y = 0..W-1), H_ii = V_i, H_ij = -t between
+ * nearest neighbours, hard wall in y.  Leads attach to slices 0 (L) and L-1 (R).  Buttiker
+ * probes: Sigma_B = diag(-(i/2) gamma_i) (Sec. III A, Eq. (77)).  Two lead models:
+ *   0: clean semi-infinite leads with the wire's cross-section, hopping t, zero onsite,
+ *      coupled by -t; surface Green's function taken at z = E + i*delta_lead*t;
+ *   1: wide-band leads Sigma_p = -(i/2) Gamma_l on the end slice (Sec. III A, Eq. (78)).
+ *
+ * Conventions shared by every call.
+ *   - Pointers named d_* are device pointers (HBM of the current HIP device); h_* are host.
+ *     The caller owns every buffer.  The library allocates no device memory and keeps no
+ *     global state; calls on different streams with different workspaces are independent.
+ *   - All calls are asynchronous on `stream` except mc_negf_workspace_bytes (host only),
+ *     mc_negf_current and mc_negf_status (both synchronise `stream`).
+ *   - Every call returns an int32 status: 0 OK, > 0 warning, < 0 error (codes below).
+ *     Arguments are validated on the host before any GPU work; on an error nothing is
+ *     launched.  No C++ exception crosses the ABI.
+ *   - Kernels record numerical trouble in a device status word inside the workspace; it is
+ *     read by mc_negf_current / mc_negf_status.
+ *   - Sizes: 1 <= W <= 16, 1 <= L, N = W*L, N + 2 <= 4096 (one alias row is built in LDS),
+ *     1 <= nE.
+ */
+#ifndef MCNEGF_H
+#define MCNEGF_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------------ */
+#define MCNEGF_OK         0
+#define MCNEGF_WTRUNC     1   /* some walks hit max_steps: the MC estimate is biased low  */
+#define MCNEGF_WNUMERIC   2   /* a kernel invariant check (row sums) exceeded 1e-8         */
+#define MCNEGF_EINVAL    -1   /* bad size, null pointer, out-of-range parameter           */
+#define MCNEGF_EWS       -2   /* workspace too small                                      */
+#define MCNEGF_EHIP      -3   /* a HIP call failed; see mc_negf_last_hip_error()          */
+#define MCNEGF_ENUMERIC  -4   /* NaN/Inf, singular RGF block or non-SPD probe system       */
+#define MCNEGF_ENOTIMPL  -5   /* entry point not implemented                              */
+
+/* ---- bits of the device status word ------------------------------------------------- */
+#define MCNEGF_FLAG_NONFINITE  0x01u  /* NaN or Inf in G, the kernel or a solve           */
+#define MCNEGF_FLAG_SINGULAR   0x02u  /* zero pivot while inverting an RGF block          */
+#define MCNEGF_FLAG_ROWSUM     0x04u  /* a kernel row total differs from A_jj (or         */
+                                      /* Tr Gamma_p A for a lead row) by more than 1e-8    */
+#define MCNEGF_FLAG_NOABSORB   0x08u  /* a lead has no open channel at some energy: its    */
+                                      /* injection row is empty (its walkers exit at once  */
+                                      /* into L and T = 0); happens outside the lead band, */
+                                      /* where Tr Gamma_p <= 1e3 * delta_lead * t * W       */
+#define MCNEGF_FLAG_TRUNC      0x10u  /* a walk reached max_steps                         */
+#define MCNEGF_FLAG_NOTSPD     0x20u  /* non-positive pivot in the probe-system Cholesky  */
+
+/* Number of per-energy lead scalars in mcnegf_kernel.lead, and their slots. */
+#define MCNEGF_LEAD_NTERMS 8
+#define MCNEGF_LEAD_TLL    0  /* Tr Gamma_L G_00 Gamma_L G_00^+                           */
+#define MCNEGF_LEAD_TRL    1  /* Tr Gamma_R G_{L-1,0} Gamma_L G_{L-1,0}^+                 */
+#define MCNEGF_LEAD_TLR    2  /* Tr Gamma_L G_{0,L-1} Gamma_R G_{0,L-1}^+                 */
+#define MCNEGF_LEAD_TRR    3  /* Tr Gamma_R G_{L-1,L-1} Gamma_R G_{L-1,L-1}^+             */
+#define MCNEGF_LEAD_CL     4  /* total weight of the L injection row (= Tr Gamma_L A)     */
+#define MCNEGF_LEAD_CR     5  /* total weight of the R injection row (= Tr Gamma_R A)     */
+#define MCNEGF_LEAD_TRGLA  6  /* Tr Gamma_L A from the diagonal block G_00                */
+#define MCNEGF_LEAD_TRGRA  7  /* Tr Gamma_R A from G_{L-1,L-1}                            */
+
+/* Tally slots of mc_negf_walk, per energy (int64, accumulated with +=). */
+#define MCNEGF_TALLY_N         5
+#define MCNEGF_TALLY_EXIT_L    0
+#define MCNEGF_TALLY_EXIT_R    1
+#define MCNEGF_TALLY_TRUNC     2
+#define MCNEGF_TALLY_STEPS     3
+#define MCNEGF_TALLY_STEPS2    4
+
+/* Physical system (host struct, read during the call only). */
+typedef struct mcnegf_system {
+    int32_t W;            /* sites per slice, 1..16                                        */
+    int32_t L;            /* number of slices, >= 1                                        */
+    double  t;            /* hopping, > 0 (H_ij = -t)                                      */
+    int32_t lead_model;   /* 0 clean semi-infinite leads, 1 wide-band leads                */
+    double  gamma_l;      /* wide-band coupling Gamma_l (lead_model 1), >= 0               */
+    double  delta_lead;   /* regulator in units of t: z = E + i*delta_lead*t (model 0), > 0 */
+} mcnegf_system;
+
+/*
+ * Handle filled by mc_negf_build_kernel: shapes plus device pointers into the caller's
+ * workspace (valid while the workspace lives and until the next build into it).  All
+ * device arrays are FP64 unless stated.  Row-major; energy index outermost.
+ */
+typedef struct mcnegf_kernel {
+    int32_t  W, L, N, n_out, nE;  /* n_out = N + 2: probes 0..N-1, lead L = N, lead R = N+1 */
+    int32_t  lead_model;
+    double   t;
+    double   delta_lead;    /* copied from the system                                       */
+    int64_t  alias_pitch;   /* entries per alias row (>= n_out, multiple of 16)            */
+    int64_t  p_pitch;       /* doubles per row of P (>= N, multiple of 16)                 */
+    const double* energies; /* [nE], borrowed from the caller                              */
+    const double* gamma;    /* [N], borrowed from the caller                               */
+    uint32_t* alias;        /* [nE][n_out][alias_pitch] pairs {thr, alias} of uint32:      */
+                            /*  bucket c keeps outcome c when a uniform 32-bit word r       */
+                            /*  satisfies r < thr, else goes to outcome alias               */
+    double*   P;            /* [nE][N][p_pitch]  |G_ij|^2                                  */
+    double*   wL;           /* [nE][N]  <psi_j|Gamma_L|psi_j>, psi_j = G|j>                 */
+    double*   wR;           /* [nE][N]  <psi_j|Gamma_R|psi_j>                               */
+    double*   Adiag;        /* [nE][N]  A_jj = -2 Im G_jj                                  */
+    double*   lead;         /* [nE][MCNEGF_LEAD_NTERMS]                                    */
+    double*   sigma;        /* [nE][W][W] complex (re, im) lead self-energy (both leads)   */
+    double*   gam_lead;     /* [nE][W][W] Gamma = i(Sigma - Sigma^+), real symmetric       */
+    double*   gL;           /* [nE][L][W][W] complex: left-connected blocks                */
+    double*   gR;           /* [nE][L][W][W] complex: right-connected blocks               */
+    double*   Gd;           /* [nE][L][W][W] complex: diagonal blocks G_kk                  */
+    double*   corner;       /* [nE][2][W][W] complex: G_{L-1,0} and G_{0,L-1}              */
+    double*   direct;       /* [nE][N][p_pitch] probe-system scratch (DIRECT mode)          */
+    double*   direct_vec;   /* [nE][4][N] scratch vectors (DIRECT mode)                    */
+    double*   reduce;       /* [nE + 8] scratch for current reductions                     */
+    uint32_t* status;       /* device status word (MCNEGF_FLAG_* bits)                     */
+    uint32_t* counters;     /* [64] walker work counters                                   */
+    void*     ws;           /* workspace base                                              */
+    uint64_t  ws_bytes;
+} mcnegf_kernel;
+
+/*
+ * Bytes of device workspace that mc_negf_build_kernel needs for `sys` and nE energies.
+ * Host only; no GPU work.  Returns MCNEGF_EINVAL for invalid sizes or null pointers.
+ */
+int32_t mc_negf_workspace_bytes(const mcnegf_system* sys, int32_t nE, uint64_t* bytes_out);
+
+/*
+ * Build the per-energy Green's functions, transition kernels and alias tables.
+ *   sys        physical system (host).
+ *   d_onsite   [N] device, V_i, slice-major.
+ *   d_gamma    [N] device, gamma_i >= 0 (dephasing rate of the probe on site i); the
+ *              kernel handle keeps this pointer, so it must stay valid while k is used.
+ *   d_energies [nE] device, energies E_k (units of t); kept by the handle as well.
+ *   d_ws       device workspace of ws_bytes >= mc_negf_workspace_bytes(sys, nE), 256-byte
+ *              aligned; owned by the caller; overwritten.
+ *   out        host handle, filled on success.
+ * Stages (all on `stream`): lead self-energies; left/right RGF sweeps; diagonal blocks;
+ * off-diagonal blocks streamed into |G_ij|^2, <psi|Gamma_r|psi> and the corner blocks; lead
+ * transmissions; one alias table per kernel row.  Asynchronous.
+ */
+int32_t mc_negf_build_kernel(const mcnegf_system* sys, const double* d_onsite,
+                             const double* d_gamma, const double* d_energies, int32_t nE,
+                             void* d_ws, uint64_t ws_bytes, mcnegf_kernel* out,
+                             hipStream_t stream);
+
+/*
+ * Random walks on the alias tables of k (Sec. II F, step 6' repeated until a lead is drawn).
+ *   seed, realization  key of the Philox4x32-10 streams; realization < 2^30.
+ *   inject_lead        0: walkers start in the L injection row, 1: in the R row.
+ *   walker_begin, n_walkers_per_energy  walker indices [walker_begin, walker_begin + n)
+ *                      are walked at every energy; walker_begin + n <= 2^32.
+ *   max_steps          walks still inside after max_steps draws are counted as truncated
+ *                      (the injection draw counts as one step); >= 1.
+ *   d_tallies          [nE][MCNEGF_TALLY_N] int64 device, accumulated (+=).
+ * Stream layout: key = (seed low, seed high); block j of walker w at energy index e has
+ * counter (j, w, e, (realization << 1) | inject_lead); step n uses words 2(n&1), 2(n&1)+1 of
+ * block n>>1 as (a, b); bucket c = (a * n_out) >> 32 with Lemire's rejection (the r-th redraw
+ * of step n takes word 0 of the block with counter (n, w, e, tag | 2^31) and key
+ * (key0, key1 ^ r)); outcome = b < thr[c] ? c : alias[c].  Results are a pure function of
+ * (tables, seed, realization, inject_lead, walker range); tallies of [a, b) plus [b, c)
+ * equal those of [a, c) exactly.  Asynchronous.
+ */
+int32_t mc_negf_walk(const mcnegf_kernel* k, uint64_t seed, uint32_t realization,
+                     uint32_t inject_lead, uint64_t walker_begin, uint64_t n_walkers_per_energy,
+                     uint32_t max_steps, int64_t* d_tallies, hipStream_t stream);
+
+/*
+ * Effective transmission per energy and the current (Sec. II E, Eq. (66); Sec. III C).
+ *   mode 0 (MC): from d_tallies of walks injected at `inject_lead`:
+ *     p_k = exits at the other lead / walkers,  T_k = c_p p_k,
+ *     sigma_k = c_p sqrt(p_k (1 - p_k) / (walkers - 1)),  c_p = row total of injection row p.
+ *   mode 1 (DIRECT): solve (diag(gamma_j A_jj) - T_PP) f = T_Pp by Cholesky on the GPU and
+ *     T_k = T_qp + sum_j T_qj f_j; sigma_k = 0.  d_tallies is ignored (may be null).
+ *   d_weights [nE] device quadrature weights w_k; d_T, d_sigmaT [nE] device outputs.
+ *   h_I_sigma [2] host output: I = sum_k w_k T_k and sqrt(sum_k w_k^2 sigma_k^2).
+ * Synchronises `stream`, then reads the device status word: returns MCNEGF_ENUMERIC if a
+ * NONFINITE, SINGULAR or NOTSPD bit is set, MCNEGF_WTRUNC if TRUNC is set (MC mode),
+ * MCNEGF_WNUMERIC if ROWSUM is set, else MCNEGF_OK.
+ */
+int32_t mc_negf_current(const mcnegf_kernel* k, int32_t mode, uint32_t inject_lead,
+                        const int64_t* d_tallies, const double* d_weights, double* d_T,
+                        double* d_sigmaT, double* h_I_sigma, hipStream_t stream);
+
+/*
+ * Gradients dI/dV_i and dI/dgamma (adjoint of the build and of the estimator).
+ * Not implemented: returns MCNEGF_ENOTIMPL and launches nothing.
+ */
+int32_t mc_negf_grad(const mcnegf_kernel* k, const double* d_weights, double* d_dI_dV,
+                     double* h_dI_deta, hipStream_t stream);
+
+/* Synchronise `stream` and copy the device status word to *h_flags. */
+int32_t mc_negf_status(const mcnegf_kernel* k, uint32_t* h_flags, hipStream_t stream);
+
+/* The hipError_t of the last failed HIP call in this thread (0 if none). */
+int32_t mc_negf_last_hip_error(void);
+
+/* Library version as an integer (major * 10000 + minor * 100 + patch). */
+int32_t mc_negf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCNEGF_H */

@@ -1,0 +1,317 @@
+// Lead-to-lead transmissions and the walker's alias tables.
+//
+// Kernel rows (one per walker state, n = N + 2 outcomes each; states 0..N-1 are probes,
+// N is lead L, N+1 is lead R):
+//   probe row j : gamma_i |G_ji|^2 to probe i, <psi_j|Gamma_L|psi_j>, <psi_j|Gamma_R|psi_j>
+//                 (step 6', Sec. II F, Eqs. (75), (76)); total A_jj (Sec. II D, Eq. (54));
+//   lead row p  : gamma_i <psi_i|Gamma_p|psi_i> to probe i (equal to the channel marginal
+//                 of steps 3-4 because G is complex symmetric), T_Lp and T_Rp to the leads;
+//                 total Tr Gamma_p A (Eq. (39)).
+// T_ab = Tr Gamma_a G_{ab-block} Gamma_b G^+ from the corner and diagonal blocks.
+//
+// Alias table of one row (Walker's method; construction by prefix sums so that a whole
+// workgroup builds one row): scale the weights to mean one, s_i = w_i n / sum w.  Light
+// items (s < 1) have deficit d_i = 1 - s_i, heavy items (s >= 1) surplus u_i = s_i - 1.
+// Lay the deficits of the light items end to end in index order (light i starts at D_i)
+// and the surpluses of the heavy items likewise (heavy m ends at C_m).  Filling the light
+// buckets from the heavy items in order, heavy m serves exactly the lights whose start D
+// lies in [C_{m-1}, C_m); it is left with 1 + C_m - D* where D* is the first light start at
+// or after C_m (or the total deficit), which becomes its own threshold, and the next heavy
+// fills the rest of its bucket.  So
+//   light i : threshold s_i,            alias = heavy m with C_{m-1} <= D_i < C_m,
+//   heavy m : threshold 1 + C_m - D*,   alias = heavy m+1   (last heavy: threshold 1, itself).
+// Each bucket c keeps outcome c with probability thr_c = floor(q_c 2^32) / 2^32 (a kept mass
+// of 1 is stored as 2^32 - 1 with the bucket aliased to itself).
+#include "common.h"
+
+namespace mcnegf {
+
+// ---------------------------------------------------------------- lead terms
+__device__ inline double block_sum256(double v, double* red) {
+    const int tid = threadIdx.x;
+    red[tid] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// Tr Ga X Gb X^+ summed by thread (q, p): sum_{c,d} Ga[p][q] X[q][c] Gb[c][d] conj(X[p][d]).
+__device__ inline double trace_term(const double2* X, const double* Ga, const double* Gb, int W,
+                                    int q, int p) {
+    double2 y = cmk(0.0, 0.0);
+    for (int c = 0; c < W; ++c) {
+        double2 xg = cmk(0.0, 0.0);
+        for (int d = 0; d < W; ++d) xg = cadd(xg, cscale(cconj(X[p * W + d]), Gb[c * W + d]));
+        cfma(y, X[q * W + c], xg);
+    }
+    return Ga[p * W + q] * y.x;
+}
+
+__global__ void __launch_bounds__(256) lead_terms_kernel(const double2* __restrict__ Gd,
+                                                         const double2* __restrict__ corner,
+                                                         const double* __restrict__ gam_lead,
+                                                         int W, int L, double* __restrict__ lead) {
+    __shared__ double red[256];
+    const int e = blockIdx.x;
+    const int tid = threadIdx.x;
+    const double* gm = gam_lead + (size_t)e * W * W;
+    const double2* G00 = Gd + (size_t)e * L * W * W;
+    const double2* Gll = G00 + (size_t)(L - 1) * W * W;
+    const double2* cRL = corner + (size_t)e * 2 * W * W;
+    const double2* cLR = cRL + W * W;
+    const bool act = tid < W * W;
+    const int q = tid / W, p = tid % W;
+    double tLL = 0, tRL = 0, tLR = 0, tRR = 0, aL = 0, aR = 0;
+    if (act) {
+        tLL = trace_term(G00, gm, gm, W, q, p);
+        tRL = trace_term(cRL, gm, gm, W, q, p);
+        tLR = trace_term(cLR, gm, gm, W, q, p);
+        tRR = trace_term(Gll, gm, gm, W, q, p);
+        // Tr Gamma A over the end block: A[q][p] = i (G[q][p] - conj(G[p][q]))
+        const double aqp0 = -(G00[q * W + p].y + G00[p * W + q].y);
+        const double aqpl = -(Gll[q * W + p].y + Gll[p * W + q].y);
+        aL = gm[p * W + q] * aqp0;
+        aR = gm[p * W + q] * aqpl;
+    }
+    const double s0 = block_sum256(tLL, red), s1 = block_sum256(tRL, red);
+    const double s2 = block_sum256(tLR, red), s3 = block_sum256(tRR, red);
+    const double s6 = block_sum256(aL, red), s7 = block_sum256(aR, red);
+    if (tid == 0) {
+        double* o = lead + (size_t)e * MCNEGF_LEAD_NTERMS;
+        o[MCNEGF_LEAD_TLL] = s0;
+        o[MCNEGF_LEAD_TRL] = s1;
+        o[MCNEGF_LEAD_TLR] = s2;
+        o[MCNEGF_LEAD_TRR] = s3;
+        o[MCNEGF_LEAD_TRGLA] = s6;
+        o[MCNEGF_LEAD_TRGRA] = s7;
+    }
+}
+
+hipError_t launch_lead_terms(const mcnegf_kernel& k, hipStream_t s) {
+    hipLaunchKernelGGL(lead_terms_kernel, dim3(k.nE), dim3(256), 0, s,
+                       reinterpret_cast<const double2*>(k.Gd),
+                       reinterpret_cast<const double2*>(k.corner), k.gam_lead, k.W, k.L, k.lead);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- block scans (256 threads)
+// Exclusive scan of one double and one int per thread, in thread order; returns totals.
+__device__ inline void block_scan2(double& xd, int& xi, double& totd, int& toti, double* sd,
+                                   int* si) {
+    const int tid = threadIdx.x;
+    sd[tid] = xd;
+    si[tid] = xi;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        double ad = 0.0;
+        int ai = 0;
+        if (tid >= off) {
+            ad = sd[tid - off];
+            ai = si[tid - off];
+        }
+        __syncthreads();
+        sd[tid] += ad;
+        si[tid] += ai;
+        __syncthreads();
+    }
+    totd = sd[255];
+    toti = si[255];
+    xd = sd[tid] - xd;  // exclusive
+    xi = si[tid] - xi;
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- alias build
+struct AliasArgs {
+    const double* P;
+    const double* wL;
+    const double* wR;
+    const double* Adiag;
+    const double* gamma;
+    double* lead;
+    uint2* alias;
+    uint32_t* status;
+    const double* gam_lead;
+    int64_t ldP, pitch;
+    int N, W;
+    double open_cut;  // an injection row needs Tr Gamma_p > open_cut
+};
+
+__global__ void __launch_bounds__(256) alias_build_kernel(AliasArgs a) {
+    extern __shared__ double smem[];
+    __shared__ double sd[256];
+    __shared__ int si[256];
+    __shared__ double red[256];
+    const int N = a.N;
+    const int n = N + 2;
+    const int row = blockIdx.x;
+    const int e = blockIdx.y;
+    const int tid = threadIdx.x;
+    double* s = smem;                                  // [n]   scaled weights
+    double* lightD = s + n;                            // [n+1] light starts (+ total deficit)
+    double* heavyC = lightD + n + 1;                   // [n]   heavy ends (inclusive)
+    int* heavyIdx = reinterpret_cast<int*>(heavyC + n);  // [n]
+    int* rankv = heavyIdx + n;                         // [n]   light rank, or ~heavy rank
+
+    const double* lead = a.lead + (size_t)e * MCNEGF_LEAD_NTERMS;
+    const double* wLe = a.wL + (size_t)e * N;
+    const double* wRe = a.wR + (size_t)e * N;
+    // 1. weights of this row
+    for (int i = tid; i < n; i += 256) {
+        double w;
+        if (row < N) {
+            if (i < N) w = a.gamma[i] * a.P[((size_t)e * N + row) * a.ldP + i];
+            else w = (i == N) ? wLe[row] : wRe[row];
+        } else if (row == N) {
+            if (i < N) w = a.gamma[i] * wLe[i];
+            else w = (i == N) ? lead[MCNEGF_LEAD_TLL] : lead[MCNEGF_LEAD_TRL];
+        } else {
+            if (i < N) w = a.gamma[i] * wRe[i];
+            else w = (i == N) ? lead[MCNEGF_LEAD_TLR] : lead[MCNEGF_LEAD_TRR];
+        }
+        s[i] = w > 0.0 ? w : (w == w ? 0.0 : w);   // clamp rounding negatives, keep NaN
+    }
+    __syncthreads();
+    // 2. total over contiguous per-thread chunks (fixed order)
+    const int chunk = (n + 255) / 256;
+    const int i0 = min(tid * chunk, n), i1 = min(i0 + chunk, n);
+    double part = 0.0;
+    for (int i = i0; i < i1; ++i) part += s[i];
+    double total = block_sum256(part, red);
+    if (row >= N) {
+        // no open channel in this lead (outside its band, Gamma only from the regulator)
+        double trg = 0.0;
+        for (int y = 0; y < a.W; ++y) trg += a.gam_lead[((size_t)e * a.W + y) * a.W + y];
+        if (!(trg > a.open_cut)) total = 0.0;
+    }
+
+    uint2* out = a.alias + ((size_t)e * n + row) * a.pitch;
+    if (tid == 0) {
+        double ref;
+        if (row < N) ref = a.Adiag[(size_t)e * N + row];
+        else ref = lead[row == N ? MCNEGF_LEAD_TRGLA : MCNEGF_LEAD_TRGRA];
+        if (row == N) a.lead[(size_t)e * MCNEGF_LEAD_NTERMS + MCNEGF_LEAD_CL] = total;
+        if (row == N + 1) a.lead[(size_t)e * MCNEGF_LEAD_NTERMS + MCNEGF_LEAD_CR] = total;
+        if (!isfinite(total)) atomicOr(a.status, MCNEGF_FLAG_NONFINITE);
+        else if (row < N && total > 0.0 && fabs(total - ref) > 1e-8 * fabs(ref))
+            atomicOr(a.status, MCNEGF_FLAG_ROWSUM);
+        else if (row >= N && total > 0.0 && fabs(total - ref) > 1e-8 * fabs(ref))
+            atomicOr(a.status, MCNEGF_FLAG_ROWSUM);
+        if (row >= N && !(total > 0.0)) atomicOr(a.status, MCNEGF_FLAG_NOABSORB);
+    }
+    if (!(total > 0.0) || !isfinite(total)) {
+        // Degenerate row: every bucket exits at lead L (its estimator weight is zero).
+        for (int i = tid; i < n; i += 256) out[i] = make_uint2(0u, (uint32_t)N);
+        return;
+    }
+    // 3. scale, classify, scan
+    const double scale = (double)n / total;
+    double dl = 0.0, uh = 0.0;
+    int nl = 0, nh = 0;
+    for (int i = i0; i < i1; ++i) {
+        const double si_ = s[i] * scale;
+        s[i] = si_;
+        if (si_ < 1.0) { dl += 1.0 - si_; ++nl; }
+        else { uh += si_ - 1.0; ++nh; }
+    }
+    double Dtot, Utot;
+    int NLtot, NHtot;
+    block_scan2(dl, nl, Dtot, NLtot, sd, si);
+    block_scan2(uh, nh, Utot, NHtot, sd, si);
+    for (int i = i0; i < i1; ++i) {
+        const double v = s[i];
+        if (v < 1.0) {
+            lightD[nl] = dl;
+            rankv[i] = nl;
+            dl += 1.0 - v;
+            ++nl;
+        } else {
+            uh += v - 1.0;
+            heavyC[nh] = uh;
+            heavyIdx[nh] = i;
+            rankv[i] = ~nh;
+            ++nh;
+        }
+    }
+    if (tid == 0) lightD[NLtot] = Dtot;
+    __syncthreads();
+    // 4. thresholds and aliases
+    for (int i = tid; i < n; i += 256) {
+        const int r = rankv[i];
+        double q;
+        int al;
+        if (NHtot == 0) {
+            q = 1.0;
+            al = i;
+        } else if (r >= 0) {
+            // light: first heavy m with heavyC[m] > D_i
+            const double D = lightD[r];
+            int lo = 0, hi = NHtot;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (heavyC[mid] > D) hi = mid; else lo = mid + 1;
+            }
+            if (lo >= NHtot) lo = NHtot - 1;
+            q = s[i];
+            al = heavyIdx[lo];
+        } else {
+            const int m = ~r;
+            if (m == NHtot - 1) {
+                q = 1.0;
+                al = i;
+            } else {
+                const double C = heavyC[m];
+                int lo = 0, hi = NLtot;  // first light start >= C (lightD[NLtot] = Dtot)
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (lightD[mid] >= C) hi = mid; else lo = mid + 1;
+                }
+                q = 1.0 + C - lightD[lo];
+                q = q < 0.0 ? 0.0 : q;
+                al = heavyIdx[m + 1];
+            }
+        }
+        uint32_t thr;
+        if (q >= 1.0) {
+            thr = 0xFFFFFFFFu;
+            al = i;
+        } else {
+            thr = (uint32_t)(q * 4294967296.0);
+        }
+        out[i] = make_uint2(thr, (uint32_t)al);
+    }
+}
+
+hipError_t launch_alias_build(const mcnegf_kernel& k, hipStream_t s) {
+    AliasArgs a;
+    a.P = k.P;
+    a.wL = k.wL;
+    a.wR = k.wR;
+    a.Adiag = k.Adiag;
+    a.gamma = k.gamma;
+    a.lead = k.lead;
+    a.alias = reinterpret_cast<uint2*>(k.alias);
+    a.status = k.status;
+    a.gam_lead = k.gam_lead;
+    a.ldP = k.p_pitch;
+    a.pitch = k.alias_pitch;
+    a.N = k.N;
+    a.W = k.W;
+    a.open_cut = 1e3 * k.delta_lead * k.t * k.W;
+    const int n = k.n_out;
+    const size_t lds = (size_t)n * 8 + (size_t)(n + 1) * 8 + (size_t)n * 8 + (size_t)n * 8;
+    if (lds > 65536) {
+        hipError_t err = hipFuncSetAttribute((const void*)alias_build_kernel,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (err != hipSuccess) return err;
+    }
+    hipLaunchKernelGGL(alias_build_kernel, dim3(n, k.nE), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace mcnegf

@@ -1,0 +1,74 @@
+// Shared device helpers and launcher declarations of the mcnegf HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mcnegf.h"
+
+namespace mcnegf {
+
+constexpr int kMaxW = 16;
+constexpr int kMaxOut = 4096;
+
+// ---- complex FP64 arithmetic on double2 (x = real, y = imaginary) ----------------------
+__host__ __device__ inline double2 cmk(double re, double im) { return make_double2(re, im); }
+__host__ __device__ inline double2 cadd(double2 a, double2 b) { return cmk(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 csub(double2 a, double2 b) { return cmk(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline double2 cmul(double2 a, double2 b) {
+    return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline double2 cscale(double2 a, double s) { return cmk(a.x * s, a.y * s); }
+__host__ __device__ inline double2 cconj(double2 a) { return cmk(a.x, -a.y); }
+__host__ __device__ inline double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+// a += b * c
+__host__ __device__ inline void cfma(double2& a, double2 b, double2 c) {
+    a.x = fma(b.x, c.x, fma(-b.y, c.y, a.x));
+    a.y = fma(b.x, c.y, fma(b.y, c.x, a.y));
+}
+// a -= b * c
+__host__ __device__ inline void cfms(double2& a, double2 b, double2 c) {
+    a.x = fma(-b.x, c.x, fma(b.y, c.y, a.x));
+    a.y = fma(-b.x, c.y, fma(-b.y, c.x, a.y));
+}
+// 1 / a, scaled to avoid overflow
+__host__ __device__ inline double2 crecip(double2 a) {
+    if (fabs(a.x) >= fabs(a.y)) {
+        double r = a.y / a.x, d = a.x + a.y * r;
+        return cmk(1.0 / d, -r / d);
+    }
+    double r = a.x / a.y, d = a.y + a.x * r;
+    return cmk(r / d, -1.0 / d);
+}
+__host__ __device__ inline double2 cdiv(double2 a, double2 b) { return cmul(a, crecip(b)); }
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// ---- workspace layout ------------------------------------------------------------------
+struct Layout {
+    int64_t alias_pitch, p_pitch;
+    uint64_t off_status, off_counters, off_reduce, off_lead, off_sigma, off_gam, off_gL, off_gR,
+        off_Gd, off_corner, off_wL, off_wR, off_Adiag, off_P, off_alias, off_direct,
+        off_direct_vec, total;
+};
+Layout make_layout(int W, int L, int nE);
+
+// ---- launchers (each defined next to its kernel) ----------------------------------------
+hipError_t launch_clear_status(uint32_t* status, uint32_t* counters, hipStream_t s);
+hipError_t launch_lead_sigma(const mcnegf_kernel& k, double gamma_l, double delta,
+                             hipStream_t s);
+hipError_t launch_rgf(const mcnegf_kernel& k, const double* onsite, hipStream_t s);
+hipError_t launch_fullinv(const mcnegf_kernel& k, hipStream_t s);
+hipError_t launch_lead_terms(const mcnegf_kernel& k, hipStream_t s);
+hipError_t launch_alias_build(const mcnegf_kernel& k, hipStream_t s);
+hipError_t launch_walk(const mcnegf_kernel& k, uint64_t seed, uint32_t tag,
+                       uint32_t walker_begin, uint32_t n_walkers, uint32_t max_steps,
+                       int64_t* tallies, hipStream_t s);
+hipError_t launch_mc_current(const mcnegf_kernel& k, uint32_t inject_lead,
+                             const int64_t* tallies, const double* weights, double* T,
+                             double* sigmaT, hipStream_t s);
+hipError_t launch_direct_current(const mcnegf_kernel& k, uint32_t inject_lead,
+                                 const double* weights, double* T, double* sigmaT,
+                                 hipStream_t s);
+
+}  // namespace mcnegf

@@ -1,0 +1,160 @@
+// All blocks of G^r from the RGF blocks, streamed straight into the walker's weights.
+//
+// For a column l (slice of the column), the blocks of G obey (E - H - Sigma) G = I with
+// off-diagonal blocks t I, which gives
+//   above the diagonal  G_{k,l} = -t gL_k G_{k+1,l}   (k < l),
+//   below the diagonal  G_{k,l} = -t gR_k G_{k-1,l}   (k > l),
+// starting from the diagonal block G_{l,l}.  Each lane owns one column j of G (so a
+// wavefront owns 64 consecutive columns) and keeps its W-vector G_{k, j} in registers while
+// the wavefront sweeps k down and then up the wire; the W x W factors gL_k, gR_k are the
+// same for every lane and are read as scalars.  Nothing of G is written except
+//   P[i][j]  = |G_ij|^2                      (probe-to-probe weights, step 6', Eq. (75)),
+//   wL[j]    = <psi_j|Gamma_L|psi_j>, wR[j]  (psi_j = G|j>, exit weights, Eq. (76)),
+//   corner   = G_{L-1,0} and G_{0,L-1}       (lead-to-lead transmissions).
+// Rows of P are written by 64 lanes at consecutive columns (coalesced 512-byte segments).
+// The block products run on the FP64 VALU: at W <= 16 the operands live in registers and
+// scalar registers, and gfx950's FP64 matrix-core rate equals its FP64 FMA rate, so padding
+// W up to a 16x16x4 MFMA shape would only add work.
+#include "common.h"
+
+namespace mcnegf {
+
+template <int W>
+__device__ inline double quad_form(const double2 (&v)[W], const double* __restrict__ gm) {
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+#pragma unroll
+        for (int b = 0; b < W; ++b)
+            acc = fma(gm[a * W + b], v[a].x * v[b].x + v[a].y * v[b].y, acc);
+    }
+    return acc;
+}
+
+template <int W>
+__device__ inline void block_matvec(double2 (&v)[W], const double2* __restrict__ M, double mt) {
+    double2 nv[W];
+#pragma unroll
+    for (int y = 0; y < W; ++y) {
+        double2 acc = cmk(0.0, 0.0);
+#pragma unroll
+        for (int x = 0; x < W; ++x) cfma(acc, M[y * W + x], v[x]);
+        nv[y] = cscale(acc, mt);
+    }
+#pragma unroll
+    for (int y = 0; y < W; ++y) v[y] = nv[y];
+}
+
+template <int W>
+__global__ void __launch_bounds__(256) fullinv_kernel(const double2* __restrict__ gL,
+                                                      const double2* __restrict__ gR,
+                                                      const double2* __restrict__ Gd,
+                                                      const double* __restrict__ gam_lead,
+                                                      int L, double t, int64_t ldP,
+                                                      double* __restrict__ P,
+                                                      double* __restrict__ wL,
+                                                      double* __restrict__ wR,
+                                                      double2* __restrict__ corner) {
+    const int N = W * L;
+    const int e = blockIdx.y;
+    const int wave_first = blockIdx.x * 256 + (threadIdx.x & ~63);
+    if (wave_first >= N) return;  // whole wavefront idle
+    const int col = blockIdx.x * 256 + threadIdx.x;
+    const bool valid = col < N;
+    const int colc = valid ? col : N - 1;
+    const int l = colc / W;
+    const int y0 = colc - l * W;
+    const int wave_last = min(wave_first + 63, N - 1);
+    const int kmin = wave_first / W;
+    const int kmax = wave_last / W;
+    const size_t eb = (size_t)e * L * W * W;
+    const double2* gLe = gL + eb;
+    const double2* gRe = gR + eb;
+    const double2* Gde = Gd + eb;
+    const double* gme = gam_lead + (size_t)e * W * W;
+    double* Pe = P + (size_t)e * N * ldP;
+    double2* cRL = corner + (size_t)e * 2 * W * W;
+    double2* cLR = cRL + W * W;
+    const double mt = -t;
+
+    double2 v[W];
+    // ---- downward: k = l, l+1, ..., L-1 -------------------------------------------------
+#pragma unroll
+    for (int y = 0; y < W; ++y) v[y] = cmk(0.0, 0.0);
+    for (int k = kmin; k < L; ++k) {
+        block_matvec<W>(v, gRe + (size_t)k * W * W, mt);
+        if (k == l) {
+#pragma unroll
+            for (int y = 0; y < W; ++y) v[y] = Gde[(size_t)k * W * W + y * W + y0];
+        }
+        if (k < l) {
+#pragma unroll
+            for (int y = 0; y < W; ++y) v[y] = cmk(0.0, 0.0);
+        }
+        if (valid && k >= l) {
+#pragma unroll
+            for (int y = 0; y < W; ++y) Pe[(size_t)(k * W + y) * ldP + col] = cabs2(v[y]);
+        }
+    }
+    // k = L-1 now: exit weight into R and, for columns of slice 0, the corner G_{L-1,0}.
+    if (valid) {
+        wR[(size_t)e * N + col] = quad_form<W>(v, gme);
+        if (l == 0) {
+#pragma unroll
+            for (int y = 0; y < W; ++y) cRL[y * W + y0] = v[y];
+        }
+    }
+    // ---- upward: k = l, l-1, ..., 0 ------------------------------------------------------
+#pragma unroll
+    for (int y = 0; y < W; ++y) v[y] = cmk(0.0, 0.0);
+    for (int k = kmax; k >= 0; --k) {
+        block_matvec<W>(v, gLe + (size_t)k * W * W, mt);
+        if (k == l) {
+#pragma unroll
+            for (int y = 0; y < W; ++y) v[y] = Gde[(size_t)k * W * W + y * W + y0];
+        }
+        if (k > l) {
+#pragma unroll
+            for (int y = 0; y < W; ++y) v[y] = cmk(0.0, 0.0);
+        }
+        if (valid && k < l) {
+#pragma unroll
+            for (int y = 0; y < W; ++y) Pe[(size_t)(k * W + y) * ldP + col] = cabs2(v[y]);
+        }
+    }
+    if (valid) {
+        wL[(size_t)e * N + col] = quad_form<W>(v, gme);
+        if (l == L - 1) {
+#pragma unroll
+            for (int y = 0; y < W; ++y) cLR[y * W + y0] = v[y];
+        }
+    }
+}
+
+template <int W>
+static hipError_t launch_fullinv_w(const mcnegf_kernel& k, hipStream_t s) {
+    dim3 grid((k.N + 255) / 256, k.nE);
+    hipLaunchKernelGGL(fullinv_kernel<W>, grid, dim3(256), 0, s,
+                       reinterpret_cast<const double2*>(k.gL),
+                       reinterpret_cast<const double2*>(k.gR),
+                       reinterpret_cast<const double2*>(k.Gd), k.gam_lead, k.L, k.t, k.p_pitch,
+                       k.P, k.wL, k.wR, reinterpret_cast<double2*>(k.corner));
+    return hipGetLastError();
+}
+
+hipError_t launch_fullinv(const mcnegf_kernel& k, hipStream_t s) {
+    switch (k.W) {
+#define MCNEGF_CASE(w) \
+    case w:            \
+        return launch_fullinv_w<w>(k, s);
+        MCNEGF_CASE(1) MCNEGF_CASE(2) MCNEGF_CASE(3) MCNEGF_CASE(4) MCNEGF_CASE(5)
+        MCNEGF_CASE(6) MCNEGF_CASE(7) MCNEGF_CASE(8) MCNEGF_CASE(9) MCNEGF_CASE(10)
+        MCNEGF_CASE(11) MCNEGF_CASE(12) MCNEGF_CASE(13) MCNEGF_CASE(14) MCNEGF_CASE(15)
+        MCNEGF_CASE(16)
+#undef MCNEGF_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mcnegf

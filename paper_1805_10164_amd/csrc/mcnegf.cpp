@@ -1,0 +1,216 @@
+// Host side of the C ABI declared in include/mcnegf.h: argument validation, workspace
+// layout and the order of the GPU stages.  Every GPU stage runs on the caller's stream.
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+namespace mcnegf {
+
+static thread_local int32_t g_last_hip_error = 0;
+
+static int32_t hip_fail(hipError_t e) {
+    g_last_hip_error = (int32_t)e;
+    return MCNEGF_EHIP;
+}
+
+static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+Layout make_layout(int W, int L, int nE) {
+    Layout o;
+    const int64_t N = (int64_t)W * L;
+    const int64_t n = N + 2;
+    o.alias_pitch = round_up(n, 16);
+    o.p_pitch = round_up(N, 16);
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t at = off;
+        off = align256(off + bytes);
+        return at;
+    };
+    o.off_status = take(256);
+    o.off_counters = take(64 * 4);
+    o.off_reduce = take((uint64_t)(nE + 8) * 8);
+    o.off_lead = take((uint64_t)nE * MCNEGF_LEAD_NTERMS * 8);
+    o.off_sigma = take((uint64_t)nE * W * W * 16);
+    o.off_gam = take((uint64_t)nE * W * W * 8);
+    o.off_gL = take((uint64_t)nE * L * W * W * 16);
+    o.off_gR = take((uint64_t)nE * L * W * W * 16);
+    o.off_Gd = take((uint64_t)nE * L * W * W * 16);
+    o.off_corner = take((uint64_t)nE * 2 * W * W * 16);
+    o.off_wL = take((uint64_t)nE * N * 8);
+    o.off_wR = take((uint64_t)nE * N * 8);
+    o.off_Adiag = take((uint64_t)nE * N * 8);
+    o.off_direct_vec = take((uint64_t)nE * 4 * N * 8);
+    o.off_P = take((uint64_t)nE * N * o.p_pitch * 8);
+    o.off_alias = take((uint64_t)nE * n * o.alias_pitch * 8);
+    o.off_direct = take((uint64_t)nE * N * o.p_pitch * 8);
+    o.total = off;
+    return o;
+}
+
+static bool valid_system(const mcnegf_system* s) {
+    if (!s) return false;
+    if (s->W < 1 || s->W > kMaxW || s->L < 1) return false;
+    if ((int64_t)s->W * s->L + 2 > kMaxOut) return false;
+    if (!(s->t > 0.0) || !std::isfinite(s->t)) return false;
+    if (s->lead_model == 0) {
+        if (!(s->delta_lead > 0.0) || !std::isfinite(s->delta_lead)) return false;
+    } else if (s->lead_model == 1) {
+        if (!(s->gamma_l >= 0.0) || !std::isfinite(s->gamma_l)) return false;
+    } else {
+        return false;
+    }
+    return true;
+}
+
+static bool valid_kernel(const mcnegf_kernel* k) {
+    return k && k->W >= 1 && k->W <= kMaxW && k->L >= 1 && k->N == k->W * k->L &&
+           k->n_out == k->N + 2 && k->nE >= 1 && k->alias && k->P && k->lead && k->status &&
+           k->counters && k->reduce;
+}
+
+static int32_t status_to_code(uint32_t flags, bool mc) {
+    if (flags & (MCNEGF_FLAG_NONFINITE | MCNEGF_FLAG_SINGULAR | MCNEGF_FLAG_NOTSPD))
+        return MCNEGF_ENUMERIC;
+    if (mc && (flags & MCNEGF_FLAG_TRUNC)) return MCNEGF_WTRUNC;
+    if (flags & MCNEGF_FLAG_ROWSUM) return MCNEGF_WNUMERIC;
+    return MCNEGF_OK;
+}
+
+}  // namespace mcnegf
+
+using namespace mcnegf;
+
+extern "C" {
+
+int32_t mc_negf_version(void) { return 10000; }
+
+int32_t mc_negf_last_hip_error(void) { return g_last_hip_error; }
+
+int32_t mc_negf_workspace_bytes(const mcnegf_system* sys, int32_t nE, uint64_t* bytes_out) {
+    if (!valid_system(sys) || nE < 1 || !bytes_out) return MCNEGF_EINVAL;
+    *bytes_out = make_layout(sys->W, sys->L, nE).total;
+    return MCNEGF_OK;
+}
+
+int32_t mc_negf_build_kernel(const mcnegf_system* sys, const double* d_onsite,
+                             const double* d_gamma, const double* d_energies, int32_t nE,
+                             void* d_ws, uint64_t ws_bytes, mcnegf_kernel* out,
+                             hipStream_t stream) {
+    if (!valid_system(sys) || !d_onsite || !d_gamma || !d_energies || nE < 1 || !d_ws || !out)
+        return MCNEGF_EINVAL;
+    if (((uintptr_t)d_ws & 255u) != 0) return MCNEGF_EINVAL;
+    const Layout lay = make_layout(sys->W, sys->L, nE);
+    if (ws_bytes < lay.total) return MCNEGF_EWS;
+    char* base = static_cast<char*>(d_ws);
+    mcnegf_kernel k;
+    std::memset(&k, 0, sizeof(k));
+    k.W = sys->W;
+    k.L = sys->L;
+    k.N = sys->W * sys->L;
+    k.n_out = k.N + 2;
+    k.nE = nE;
+    k.lead_model = sys->lead_model;
+    k.t = sys->t;
+    k.delta_lead = sys->lead_model == 0 ? sys->delta_lead : 0.0;
+    k.alias_pitch = lay.alias_pitch;
+    k.p_pitch = lay.p_pitch;
+    k.energies = d_energies;
+    k.gamma = d_gamma;
+    k.alias = reinterpret_cast<uint32_t*>(base + lay.off_alias);
+    k.P = reinterpret_cast<double*>(base + lay.off_P);
+    k.wL = reinterpret_cast<double*>(base + lay.off_wL);
+    k.wR = reinterpret_cast<double*>(base + lay.off_wR);
+    k.Adiag = reinterpret_cast<double*>(base + lay.off_Adiag);
+    k.lead = reinterpret_cast<double*>(base + lay.off_lead);
+    k.sigma = reinterpret_cast<double*>(base + lay.off_sigma);
+    k.gam_lead = reinterpret_cast<double*>(base + lay.off_gam);
+    k.gL = reinterpret_cast<double*>(base + lay.off_gL);
+    k.gR = reinterpret_cast<double*>(base + lay.off_gR);
+    k.Gd = reinterpret_cast<double*>(base + lay.off_Gd);
+    k.corner = reinterpret_cast<double*>(base + lay.off_corner);
+    k.direct = reinterpret_cast<double*>(base + lay.off_direct);
+    k.direct_vec = reinterpret_cast<double*>(base + lay.off_direct_vec);
+    k.reduce = reinterpret_cast<double*>(base + lay.off_reduce);
+    k.status = reinterpret_cast<uint32_t*>(base + lay.off_status);
+    k.counters = reinterpret_cast<uint32_t*>(base + lay.off_counters);
+    k.ws = d_ws;
+    k.ws_bytes = ws_bytes;
+
+    hipError_t err;
+    if ((err = launch_clear_status(k.status, k.counters, stream)) != hipSuccess) return hip_fail(err);
+    if ((err = launch_lead_sigma(k, sys->gamma_l, sys->delta_lead, stream)) != hipSuccess)
+        return hip_fail(err);
+    if ((err = launch_rgf(k, d_onsite, stream)) != hipSuccess) return hip_fail(err);
+    if ((err = launch_fullinv(k, stream)) != hipSuccess) return hip_fail(err);
+    if ((err = launch_lead_terms(k, stream)) != hipSuccess) return hip_fail(err);
+    if ((err = launch_alias_build(k, stream)) != hipSuccess) return hip_fail(err);
+    *out = k;
+    return MCNEGF_OK;
+}
+
+int32_t mc_negf_walk(const mcnegf_kernel* k, uint64_t seed, uint32_t realization,
+                     uint32_t inject_lead, uint64_t walker_begin, uint64_t n_walkers_per_energy,
+                     uint32_t max_steps, int64_t* d_tallies, hipStream_t stream) {
+    if (!valid_kernel(k) || !d_tallies || inject_lead > 1 || realization >= (1u << 30) ||
+        max_steps < 1)
+        return MCNEGF_EINVAL;
+    if (walker_begin + n_walkers_per_energy > 0x100000000ull ||
+        walker_begin >= 0x100000000ull)
+        return MCNEGF_EINVAL;
+    if (n_walkers_per_energy == 0) return MCNEGF_OK;
+    const uint32_t tag = (realization << 1) | inject_lead;
+    hipError_t err = launch_walk(*k, seed, tag, (uint32_t)walker_begin,
+                                 (uint32_t)n_walkers_per_energy, max_steps, d_tallies, stream);
+    if (err != hipSuccess) return hip_fail(err);
+    return MCNEGF_OK;
+}
+
+int32_t mc_negf_current(const mcnegf_kernel* k, int32_t mode, uint32_t inject_lead,
+                        const int64_t* d_tallies, const double* d_weights, double* d_T,
+                        double* d_sigmaT, double* h_I_sigma, hipStream_t stream) {
+    if (!valid_kernel(k) || !d_weights || !d_T || !d_sigmaT || !h_I_sigma || inject_lead > 1)
+        return MCNEGF_EINVAL;
+    hipError_t err;
+    if (mode == 0) {
+        if (!d_tallies) return MCNEGF_EINVAL;
+        err = launch_mc_current(*k, inject_lead, d_tallies, d_weights, d_T, d_sigmaT, stream);
+    } else if (mode == 1) {
+        if (!k->direct || !k->direct_vec) return MCNEGF_EINVAL;
+        err = launch_direct_current(*k, inject_lead, d_weights, d_T, d_sigmaT, stream);
+    } else {
+        return MCNEGF_EINVAL;
+    }
+    if (err != hipSuccess) return hip_fail(err);
+    double host[2];
+    uint32_t flags = 0;
+    if ((err = hipMemcpyAsync(host, k->reduce, sizeof(host), hipMemcpyDeviceToHost, stream)) !=
+        hipSuccess)
+        return hip_fail(err);
+    if ((err = hipMemcpyAsync(&flags, k->status, sizeof(flags), hipMemcpyDeviceToHost, stream)) !=
+        hipSuccess)
+        return hip_fail(err);
+    if ((err = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(err);
+    h_I_sigma[0] = host[0];
+    h_I_sigma[1] = std::sqrt(host[1] > 0.0 ? host[1] : 0.0);
+    return status_to_code(flags, mode == 0);
+}
+
+int32_t mc_negf_grad(const mcnegf_kernel* k, const double* d_weights, double* d_dI_dV,
+                     double* h_dI_deta, hipStream_t stream) {
+    (void)k; (void)d_weights; (void)d_dI_dV; (void)h_dI_deta; (void)stream;
+    return MCNEGF_ENOTIMPL;
+}
+
+int32_t mc_negf_status(const mcnegf_kernel* k, uint32_t* h_flags, hipStream_t stream) {
+    if (!valid_kernel(k) || !h_flags) return MCNEGF_EINVAL;
+    hipError_t err;
+    if ((err = hipMemcpyAsync(h_flags, k->status, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                              stream)) != hipSuccess)
+        return hip_fail(err);
+    if ((err = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(err);
+    return MCNEGF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,217 @@
+// Block-tridiagonal recursive Green's functions (Sec. III B: G^r by the RGF algorithm;
+// G^r = (E - H - Sigma^r)^{-1}, Sec. II A, Eq. (7)).
+//
+// With slices k = 0..L-1 of W sites, the diagonal blocks of E - H - Sigma are
+//   A_k = E - H_kk - Sigma_B,kk - [k = 0] Sigma_L - [k = L-1] Sigma_R,
+// H_kk = tridiag(-t, V, -t) and Sigma_B = diag(-(i/2) gamma) (Sec. III A, Eq. (77)); the
+// off-diagonal blocks are t I (H_{k,k+1} = -t I).  Hence
+//   left-connected   gL_0 = A_0^{-1},       gL_k = (A_k - t^2 gL_{k-1})^{-1},
+//   right-connected  gR_{L-1} = A_{L-1}^{-1}, gR_k = (A_k - t^2 gR_{k+1})^{-1},
+//   diagonal         G_kk = (A_k - t^2 gL_{k-1} - t^2 gR_{k+1})^{-1}.
+// The two sweeps are sequential over slices and run as one wavefront per (energy,
+// direction); the diagonal blocks are then independent and run as one wavefront each.
+//
+// Block inverse on one wavefront: lane i < W holds row i of the augmented [X | I] in
+// registers; Gauss-Jordan elimination with partial pivoting chooses, at column p, the
+// not-yet-used row of largest |x_ip| (ties: lowest lane); rows are never swapped, so at
+// the end lane i holds row r_i of X^{-1}, r_i being the column it was pivot for.
+#include "common.h"
+
+namespace mcnegf {
+
+__device__ inline double readlane_d(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Largest mag over lanes 0..15 (every lane of each 16-lane group gets its group's winner).
+__device__ inline int argmax16(double mag, int lane) {
+    int idx = lane;
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) {
+        const double om = __shfl_xor(mag, off, 64);
+        const int oi = __shfl_xor(idx, off, 64);
+        if (om > mag || (om == mag && oi < idx)) {
+            mag = om;
+            idx = oi;
+        }
+    }
+    return idx;
+}
+
+// Inverts the W x W matrix whose row i is a[0..W-1] of lane i (lanes >= W hold zeros).
+// On return a[W..2W-1] of lane i is row `rank` of the inverse.  Returns false when a pivot
+// is zero or not finite.
+template <int W>
+__device__ inline bool gj_invert(double2 (&a)[2 * W], int lane, int& rank) {
+    bool used = lane >= W;
+    bool ok = true;
+    rank = 0;
+#pragma unroll
+    for (int p = 0; p < W; ++p) {
+        const double mag = used ? -1.0 : cabs2(a[p]);
+        const int r = __builtin_amdgcn_readfirstlane(argmax16(mag, lane));
+        double2 piv[2 * W];
+#pragma unroll
+        for (int j = p; j < 2 * W; ++j)
+            piv[j] = cmk(readlane_d(a[j].x, r), readlane_d(a[j].y, r));
+        const double pm = cabs2(piv[p]);
+        if (!(pm > 0.0) || !isfinite(pm)) ok = false;
+        const double2 pinv = crecip(piv[p]);
+#pragma unroll
+        for (int j = p; j < 2 * W; ++j) piv[j] = cmul(piv[j], pinv);
+        if (lane == r) {
+#pragma unroll
+            for (int j = p; j < 2 * W; ++j) a[j] = piv[j];
+            used = true;
+            rank = p;
+        } else {
+            const double2 f = a[p];
+#pragma unroll
+            for (int j = p; j < 2 * W; ++j) cfms(a[j], f, piv[j]);
+        }
+    }
+    return ok;
+}
+
+// Row i (< W) of A_k for energy E, in a[0..W-1]; identity row in a[W..2W-1].
+template <int W>
+__device__ inline void diag_block_row(double2 (&a)[2 * W], int i, int k, int L, double E, double t,
+                                      const double* __restrict__ onsite,
+                                      const double* __restrict__ gamma,
+                                      const double2* __restrict__ sig) {
+#pragma unroll
+    for (int j = 0; j < 2 * W; ++j) a[j] = cmk(0.0, 0.0);
+    if (i >= W) return;
+    const int site = k * W + i;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        double2 v = cmk(0.0, 0.0);
+        if (j == i) v = cmk(E - onsite[site], 0.5 * gamma[site]);
+        if (j == i - 1 || j == i + 1) v = cmk(t, 0.0);
+        if (k == 0) v = csub(v, sig[i * W + j]);
+        if (k == L - 1) v = csub(v, sig[i * W + j]);
+        a[j] = v;
+        a[W + j] = cmk(j == i ? 1.0 : 0.0, 0.0);
+    }
+}
+
+template <int W>
+__global__ void __launch_bounds__(64) rgf_sweep_kernel(const double* __restrict__ energies,
+                                                       const double* __restrict__ onsite,
+                                                       const double* __restrict__ gamma,
+                                                       const double2* __restrict__ sigma, int L,
+                                                       double t, double2* __restrict__ gL,
+                                                       double2* __restrict__ gR,
+                                                       uint32_t* __restrict__ status) {
+    const int e = blockIdx.x >> 1;
+    const int dir = blockIdx.x & 1;
+    const int lane = threadIdx.x;
+    __shared__ double2 prev[W][W];
+    const double E = energies[e];
+    const double2* sig = sigma + (size_t)e * W * W;
+    double2* out = (dir == 0 ? gL : gR) + (size_t)e * L * W * W;
+    const double t2 = t * t;
+    bool ok = true;
+    for (int s = 0; s < L; ++s) {
+        const int k = dir == 0 ? s : L - 1 - s;
+        double2 a[2 * W];
+        diag_block_row<W>(a, lane, k, L, E, t, onsite, gamma, sig);
+        if (s > 0 && lane < W) {
+#pragma unroll
+            for (int j = 0; j < W; ++j) a[j] = csub(a[j], cscale(prev[lane][j], t2));
+        }
+        __syncthreads();
+        int rank;
+        ok &= gj_invert<W>(a, lane, rank);
+        if (lane < W) {
+            double2* o = out + (size_t)k * W * W + rank * W;
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                prev[rank][j] = a[W + j];
+                o[j] = a[W + j];
+            }
+        }
+        __syncthreads();
+    }
+    if (!ok && lane == 0) atomicOr(status, MCNEGF_FLAG_SINGULAR);
+}
+
+template <int W>
+__global__ void __launch_bounds__(64) rgf_diag_kernel(const double* __restrict__ energies,
+                                                      const double* __restrict__ onsite,
+                                                      const double* __restrict__ gamma,
+                                                      const double2* __restrict__ sigma, int L,
+                                                      double t, const double2* __restrict__ gL,
+                                                      const double2* __restrict__ gR,
+                                                      double2* __restrict__ Gd,
+                                                      double* __restrict__ Adiag,
+                                                      uint32_t* __restrict__ status) {
+    const int e = blockIdx.x / L;
+    const int k = blockIdx.x % L;
+    const int lane = threadIdx.x;
+    const double E = energies[e];
+    const double t2 = t * t;
+    double2 a[2 * W];
+    diag_block_row<W>(a, lane, k, L, E, t, onsite, gamma, sigma + (size_t)e * W * W);
+    if (lane < W) {
+        const size_t base = (size_t)e * L * W * W;
+        if (k > 0) {
+            const double2* g = gL + base + (size_t)(k - 1) * W * W + lane * W;
+#pragma unroll
+            for (int j = 0; j < W; ++j) a[j] = csub(a[j], cscale(g[j], t2));
+        }
+        if (k < L - 1) {
+            const double2* g = gR + base + (size_t)(k + 1) * W * W + lane * W;
+#pragma unroll
+            for (int j = 0; j < W; ++j) a[j] = csub(a[j], cscale(g[j], t2));
+        }
+    }
+    int rank;
+    const bool ok = gj_invert<W>(a, lane, rank);
+    if (lane < W) {
+        double2* o = Gd + ((size_t)e * L + k) * W * W + rank * W;
+#pragma unroll
+        for (int j = 0; j < W; ++j) o[j] = a[W + j];
+        // diagonal element (rank, rank): a[W + rank], selected without dynamic indexing
+        double im = 0.0;
+#pragma unroll
+        for (int j = 0; j < W; ++j)
+            if (j == rank) im = a[W + j].y;
+        Adiag[(size_t)e * L * W + k * W + rank] = -2.0 * im;
+    }
+    if (!ok && lane == 0) atomicOr(status, MCNEGF_FLAG_SINGULAR);
+}
+
+template <int W>
+static hipError_t launch_rgf_w(const mcnegf_kernel& k, const double* onsite, hipStream_t s) {
+    const double2* sig = reinterpret_cast<const double2*>(k.sigma);
+    double2* gL = reinterpret_cast<double2*>(k.gL);
+    double2* gR = reinterpret_cast<double2*>(k.gR);
+    hipLaunchKernelGGL(rgf_sweep_kernel<W>, dim3(2 * k.nE), dim3(64), 0, s, k.energies, onsite,
+                       k.gamma, sig, k.L, k.t, gL, gR, k.status);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(rgf_diag_kernel<W>, dim3(k.nE * k.L), dim3(64), 0, s, k.energies,
+                       onsite, k.gamma, sig, k.L, k.t, gL, gR,
+                       reinterpret_cast<double2*>(k.Gd), k.Adiag, k.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_rgf(const mcnegf_kernel& k, const double* onsite, hipStream_t s) {
+    switch (k.W) {
+#define MCNEGF_CASE(w) \
+    case w:            \
+        return launch_rgf_w<w>(k, onsite, s);
+        MCNEGF_CASE(1) MCNEGF_CASE(2) MCNEGF_CASE(3) MCNEGF_CASE(4) MCNEGF_CASE(5)
+        MCNEGF_CASE(6) MCNEGF_CASE(7) MCNEGF_CASE(8) MCNEGF_CASE(9) MCNEGF_CASE(10)
+        MCNEGF_CASE(11) MCNEGF_CASE(12) MCNEGF_CASE(13) MCNEGF_CASE(14) MCNEGF_CASE(15)
+        MCNEGF_CASE(16)
+#undef MCNEGF_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mcnegf

@@ -1,0 +1,227 @@
+"""Thin Python binding of the C ABI in include/mcnegf.h (argument marshalling only).
+
+Every step of the method runs in the HIP library libmcnegf.so; this module only passes
+device pointers of torch tensors and torch's current HIP stream.  Importing it does not
+need a GPU; calling anything that launches work does.  If the library has not been built,
+`lib()` raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmcnegf.so")
+
+# status codes (include/mcnegf.h)
+OK, WTRUNC, WNUMERIC = 0, 1, 2
+EINVAL, EWS, EHIP, ENUMERIC, ENOTIMPL = -1, -2, -3, -4, -5
+FLAG_NONFINITE, FLAG_SINGULAR, FLAG_ROWSUM, FLAG_NOABSORB, FLAG_TRUNC, FLAG_NOTSPD = (
+    0x01, 0x02, 0x04, 0x08, 0x10, 0x20)
+LEAD_NTERMS = 8
+LEAD_TLL, LEAD_TRL, LEAD_TLR, LEAD_TRR, LEAD_CL, LEAD_CR, LEAD_TRGLA, LEAD_TRGRA = range(8)
+TALLY_N = 5
+EXPORTED = ("mc_negf_workspace_bytes", "mc_negf_build_kernel", "mc_negf_walk",
+            "mc_negf_current", "mc_negf_grad", "mc_negf_status", "mc_negf_last_hip_error",
+            "mc_negf_version")
+
+
+class McnegfError(RuntimeError):
+    def __init__(self, call: str, code: int, hip_error: int = 0):
+        super().__init__(f"{call} returned {code}" + (f" (hipError {hip_error})" if hip_error else ""))
+        self.code = code
+
+
+class System(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_int32), ("L", ctypes.c_int32), ("t", ctypes.c_double),
+                ("lead_model", ctypes.c_int32), ("gamma_l", ctypes.c_double),
+                ("delta_lead", ctypes.c_double)]
+
+
+class KernelStruct(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_int32), ("L", ctypes.c_int32), ("N", ctypes.c_int32),
+                ("n_out", ctypes.c_int32), ("nE", ctypes.c_int32),
+                ("lead_model", ctypes.c_int32), ("t", ctypes.c_double),
+                ("delta_lead", ctypes.c_double), ("alias_pitch", ctypes.c_int64), ("p_pitch", ctypes.c_int64),
+                ("energies", ctypes.c_void_p), ("gamma", ctypes.c_void_p),
+                ("alias", ctypes.c_void_p), ("P", ctypes.c_void_p), ("wL", ctypes.c_void_p),
+                ("wR", ctypes.c_void_p), ("Adiag", ctypes.c_void_p), ("lead", ctypes.c_void_p),
+                ("sigma", ctypes.c_void_p), ("gam_lead", ctypes.c_void_p),
+                ("gL", ctypes.c_void_p), ("gR", ctypes.c_void_p), ("Gd", ctypes.c_void_p),
+                ("corner", ctypes.c_void_p), ("direct", ctypes.c_void_p),
+                ("direct_vec", ctypes.c_void_p), ("reduce", ctypes.c_void_p),
+                ("status", ctypes.c_void_p), ("counters", ctypes.c_void_p),
+                ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmcnegf.so (built by paper_1805_10164_amd.build); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1805_10164_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, u32, u64, dp = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64,
+                             ctypes.POINTER(ctypes.c_double))
+    L.mc_negf_workspace_bytes.argtypes = [ctypes.POINTER(System), i32, ctypes.POINTER(u64)]
+    L.mc_negf_build_kernel.argtypes = [ctypes.POINTER(System), vp, vp, vp, i32, vp, u64,
+                                       ctypes.POINTER(KernelStruct), vp]
+    L.mc_negf_walk.argtypes = [ctypes.POINTER(KernelStruct), u64, u32, u32, u64, u64, u32, vp, vp]
+    L.mc_negf_current.argtypes = [ctypes.POINTER(KernelStruct), i32, u32, vp, vp, vp, vp, dp, vp]
+    L.mc_negf_grad.argtypes = [ctypes.POINTER(KernelStruct), vp, vp, dp, vp]
+    L.mc_negf_status.argtypes = [ctypes.POINTER(KernelStruct), ctypes.POINTER(u32), vp]
+    L.mc_negf_last_hip_error.argtypes = []
+    L.mc_negf_version.argtypes = []
+    for name in EXPORTED:
+        getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(call: str, code: int, allow=(OK,)):
+    if code not in allow:
+        raise McnegfError(call, code, lib().mc_negf_last_hip_error())
+    return code
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    if t is None:
+        return ctypes.c_void_p(0)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_system(W: int, L: int, t: float = 1.0, lead_model: int = 0, gamma_l: float = 0.0,
+                delta_lead: float = 1e-10) -> System:
+    return System(W, L, t, lead_model, gamma_l, delta_lead)
+
+
+def energy_grid(emin: float, emax: float, n: int):
+    """Midpoint quadrature on [emin, emax] with n cells (Sec. III C): nodes and weights."""
+    dE = (emax - emin) / n
+    return emin + (np.arange(n) + 0.5) * dE, np.full(n, dE)
+
+
+class Kernel:
+    """A built kernel handle plus the torch tensors it borrows (workspace, gamma, energies)."""
+
+    def __init__(self, struct: KernelStruct, ws, gamma, energies):
+        self.struct = struct
+        self.ws = ws
+        self.gamma = gamma
+        self.energies = energies
+
+    def __getattr__(self, name):
+        return getattr(self.__dict__["struct"], name)
+
+    def view(self, field: str, dtype, shape):
+        """torch view of a workspace region named by a pointer field of the handle."""
+        import torch
+        off = getattr(self.struct, field) - self.ws.data_ptr()
+        nbytes = int(np.prod(shape)) * torch.empty((), dtype=dtype).element_size()
+        return self.ws[off:off + nbytes].view(dtype).view(*shape)
+
+    # named views
+    def P(self):
+        import torch
+        return self.view("P", torch.float64, (self.nE, self.N, self.p_pitch))[:, :, :self.N]
+
+    def wL(self):
+        import torch
+        return self.view("wL", torch.float64, (self.nE, self.N))
+
+    def wR(self):
+        import torch
+        return self.view("wR", torch.float64, (self.nE, self.N))
+
+    def Adiag(self):
+        import torch
+        return self.view("Adiag", torch.float64, (self.nE, self.N))
+
+    def lead(self):
+        import torch
+        return self.view("lead", torch.float64, (self.nE, LEAD_NTERMS))
+
+    def sigma(self):
+        import torch
+        return self.view("sigma", torch.float64, (self.nE, self.W, self.W, 2))
+
+    def Gd(self):
+        import torch
+        return self.view("Gd", torch.float64, (self.nE, self.L, self.W, self.W, 2))
+
+    def alias_table(self):
+        """[nE][n_out][alias_pitch][2] uint32 pairs {thr, alias} (as int32 storage)."""
+        import torch
+        return self.view("alias", torch.int32, (self.nE, self.n_out, self.alias_pitch, 2))
+
+
+def mc_negf_workspace_bytes(system: System, nE: int) -> int:
+    out = ctypes.c_uint64(0)
+    _check("mc_negf_workspace_bytes",
+           lib().mc_negf_workspace_bytes(ctypes.byref(system), int(nE), ctypes.byref(out)))
+    return int(out.value)
+
+
+def mc_negf_build_kernel(system: System, onsite, gamma, energies, ws, stream=None) -> Kernel:
+    """Build G, kernel rows and alias tables for every energy (asynchronous on the stream)."""
+    for name, t in (("onsite", onsite), ("gamma", gamma), ("energies", energies)):
+        if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 8 and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    ks = KernelStruct()
+    code = lib().mc_negf_build_kernel(ctypes.byref(system), _ptr(onsite), _ptr(gamma),
+                                      _ptr(energies), int(energies.numel()), _ptr(ws),
+                                      ws.numel() * ws.element_size(), ctypes.byref(ks),
+                                      _stream(stream))
+    _check("mc_negf_build_kernel", code)
+    return Kernel(ks, ws, gamma, energies)
+
+
+def mc_negf_walk(k: Kernel, seed: int, realization: int, inject_lead: int, walker_begin: int,
+                 n_walkers: int, max_steps: int, tallies, stream=None) -> int:
+    code = lib().mc_negf_walk(ctypes.byref(k.struct), int(seed), int(realization),
+                              int(inject_lead), int(walker_begin), int(n_walkers),
+                              int(max_steps), _ptr(tallies), _stream(stream))
+    return _check("mc_negf_walk", code)
+
+
+def mc_negf_current(k: Kernel, mode: int, inject_lead: int, tallies, weights, T, sigmaT,
+                    stream=None, allow=(OK, WTRUNC, WNUMERIC)):
+    """Returns (status, I, sigma_I); synchronises the stream."""
+    out = (ctypes.c_double * 2)()
+    code = lib().mc_negf_current(ctypes.byref(k.struct), int(mode), int(inject_lead),
+                                 _ptr(tallies), _ptr(weights), _ptr(T), _ptr(sigmaT),
+                                 ctypes.cast(out, ctypes.POINTER(ctypes.c_double)),
+                                 _stream(stream))
+    _check("mc_negf_current", code, allow)
+    return code, float(out[0]), float(out[1])
+
+
+def mc_negf_grad(k: Kernel, weights, dI_dV, stream=None) -> int:
+    out = ctypes.c_double(0.0)
+    return int(lib().mc_negf_grad(ctypes.byref(k.struct), _ptr(weights), _ptr(dI_dV),
+                                  ctypes.byref(out), _stream(stream)))
+
+
+def mc_negf_status(k: Kernel, stream=None) -> int:
+    flags = ctypes.c_uint32(0)
+    _check("mc_negf_status", lib().mc_negf_status(ctypes.byref(k.struct), ctypes.byref(flags),
+                                                  _stream(stream)))
+    return int(flags.value)
+
+
+def allocate_workspace(system: System, nE: int, device="cuda"):
+    import torch
+    nbytes = mc_negf_workspace_bytes(system, nE)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)

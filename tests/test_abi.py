@@ -1,0 +1,94 @@
+"""The C ABI on the CPU: exported symbols, struct layout, host-side validation (no GPU)."""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+from paper_1805_10164_amd import mcnegf as M
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mcnegf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*int32_t\s+(mc_negf_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert set(names) == set(M.EXPORTED)
+    lib = M.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    nm = subprocess.run(["nm", "-D", "--defined-only", M.LIB_PATH], capture_output=True,
+                        text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (mc_negf_\w+)", nm))
+    assert set(names) <= exported
+
+
+def test_struct_layout_matches_header(tmp_path):
+    # compile a host-only probe against the header and compare sizes and offsets
+    cxx = shutil.which("g++")
+    if cxx is None:
+        pytest.skip("g++ not available")
+    src = tmp_path / "probe.cpp"
+    fields = [f for f, _ in M.KernelStruct._fields_]
+    body = "\n".join(f'printf("%zu\\n", offsetof(mcnegf_kernel, {f}));' for f in fields)
+    sfields = [f for f, _ in M.System._fields_]
+    sbody = "\n".join(f'printf("%zu\\n", offsetof(mcnegf_system, {f}));' for f in sfields)
+    src.write_text(f"""
+#include <cstdio>
+#include <cstddef>
+#include "mcnegf.h"
+int main() {{
+printf("%zu\\n", sizeof(mcnegf_kernel));
+{body}
+printf("%zu\\n", sizeof(mcnegf_system));
+{sbody}
+}}
+""")
+    exe = tmp_path / "probe"
+    subprocess.check_call([cxx, "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                           "-I", "/opt/rocm/include", str(src), "-o", str(exe)])
+    out = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    exp = [ctypes.sizeof(M.KernelStruct)] + [getattr(M.KernelStruct, f).offset for f in fields]
+    exp += [ctypes.sizeof(M.System)] + [getattr(M.System, f).offset for f in sfields]
+    assert out == exp
+
+
+def test_workspace_bytes_and_validation():
+    lib = M.lib()
+    assert M.mc_negf_workspace_bytes(M.make_system(10, 100), 256) > 4e9
+    out = ctypes.c_uint64(0)
+    bad = [M.make_system(0, 5), M.make_system(17, 5), M.make_system(16, 300),
+           M.make_system(4, 5, t=-1.0), M.make_system(4, 5, delta_lead=0.0),
+           M.make_system(4, 5, lead_model=2)]
+    for s in bad:
+        assert lib.mc_negf_workspace_bytes(ctypes.byref(s), 4, ctypes.byref(out)) == M.EINVAL
+    s = M.make_system(4, 5)
+    assert lib.mc_negf_workspace_bytes(ctypes.byref(s), 0, ctypes.byref(out)) == M.EINVAL
+    assert lib.mc_negf_workspace_bytes(None, 4, ctypes.byref(out)) == M.EINVAL
+
+
+def test_host_validation_rejects_before_any_gpu_call():
+    # null device pointers and bad sizes are rejected on the host, so this runs without a GPU
+    lib = M.lib()
+    s = M.make_system(4, 5)
+    ks = M.KernelStruct()
+    z = ctypes.c_void_p(0)
+    assert lib.mc_negf_build_kernel(ctypes.byref(s), z, z, z, 3, z, 0, ctypes.byref(ks), z) == M.EINVAL
+    assert lib.mc_negf_walk(ctypes.byref(ks), 1, 0, 0, 0, 10, 10, z, z) == M.EINVAL
+    out = (ctypes.c_double * 2)()
+    assert lib.mc_negf_current(ctypes.byref(ks), 0, 0, z, z, z, z,
+                               ctypes.cast(out, ctypes.POINTER(ctypes.c_double)), z) == M.EINVAL
+    assert lib.mc_negf_grad(ctypes.byref(ks), z, z, None, z) == M.ENOTIMPL
+
+
+def test_energy_grid_is_midpoint():
+    E, w = M.energy_grid(-3.5, 3.5, 256)
+    assert abs(E[0] - (-3.5 + 3.5 / 256)) < 1e-15 and abs(E[-1] - (3.5 - 3.5 / 256)) < 1e-15
+    assert abs(w.sum() - 7.0) < 1e-12
