@@ -3,13 +3,14 @@
 One step = the whole path for the W=10 x L=100 disordered wire (N = 1000 sites, 256
 midpoint energies in [-3.5 t, 3.5 t], disorder U[-0.25 t, 0.25 t]) at each dephasing rate
 eta in {0.01, 0.05, 0.1} t: build G / kernel rows / alias tables for all 256 energies,
-walk 1e6 walkers per energy, MC current, DIRECT current.  Inputs are resident in HBM
-before the timed region starts.
+walk 1e6 walkers per energy, MC current, DIRECT current.  Inputs are resident in HBM before
+the timed region starts.  Every kernel launch inside the timed steps is timed with HIP
+events on its own stream (the library's opt-in launch timer).
 
-Printed (rank 0, one JSON line): walk steps per second of the whole step (total walk steps
-/ wall time of the step), per-stage times, the walker kernel's own rate and roofline, the
-time to a 1% relative deviation of the lead current for MC and for the DIRECT GPU solve,
-and the oracle timed on the host's cores for a bounded sample.
+Printed (one JSON line): walk steps per second of the whole step, per-stage and per-kernel
+times, the roofline of the dominant kernel, time to a 1% relative deviation of the lead
+current for MC and for the DIRECT GPU solve, and the oracle timed on the host's cores for a
+bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -29,9 +30,9 @@ from paper_1805_10164_amd import inputs  # noqa: E402
 from paper_1805_10164_amd import mcnegf as M  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFLOPS = 78.6
 ALIAS_ENTRY_BYTES = 8        # one {thr, alias} pair read per walk step
-WALKER_SRC = os.path.join(ROOT, "paper_1805_10164_amd", "csrc", "walker.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_kernel_wire_W10_L100_traffic.json")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def parse():
@@ -64,54 +65,115 @@ class Problem:
         self.k = None
 
 
-def run_step(p: Problem, torch, walkers, seed, ev):
-    """Whole hot path for one problem; returns per-stage event pairs and results."""
-    e0, e1, e2, e3, e4 = ev
-    e0.record()
+def walker_available(p: Problem, torch) -> bool:
     p.k = M.mc_negf_build_kernel(p.sys, p.V, p.g, p.E, p.ws)
-    e1.record()
-    p.tal.zero_()
-    M.mc_negf_walk(p.k, seed, p.wl.realization, 0, 0, walkers, 1_000_000, p.tal)
-    e2.record()
-    st_mc, I_mc, s_mc = M.mc_negf_current(p.k, 0, 0, p.tal, p.w, p.T, p.sig)
-    e3.record()
+    try:
+        M.mc_negf_walk(p.k, 1, 0, 0, 0, 0, 1, p.tal)
+        return True
+    except M.McnegfError as e:
+        if e.code == M.EDISABLED:
+            return False
+        raise
+
+
+def run_step(p: Problem, walkers, seed, walk_on):
+    """Whole hot path for one problem; returns (status_mc, I_mc, sigma_mc, status_d, I_d)."""
+    p.k = M.mc_negf_build_kernel(p.sys, p.V, p.g, p.E, p.ws)
+    st_mc = I_mc = s_mc = None
+    if walk_on:
+        p.tal.zero_()
+        M.mc_negf_walk(p.k, seed, p.wl.realization, 0, 0, walkers, 1_000_000, p.tal)
+        st_mc, I_mc, s_mc = M.mc_negf_current(p.k, 0, 0, p.tal, p.w, p.T, p.sig)
     st_d, I_d, _ = M.mc_negf_current(p.k, 1, 0, None, p.w, p.T, p.sig)
-    e4.record()
-    return (st_mc, I_mc, s_mc, st_d, I_d)
+    return st_mc, I_mc, s_mc, st_d, I_d
 
 
-def time_to_1pct(p: Problem, torch, seed):
-    """Wall time to a 1% relative deviation of I: MC (build + doubling walker batches)
-    and DIRECT (build + probe-system solve), each on a warm GPU, median of 5."""
+def kernel_work(name, wl, walk_steps):
+    """Algorithmic work of one launch of `name` for workload wl: (bound, amount, unit)."""
+    N, W, nE = wl.N, wl.W, wl.n_energies
+    n = N + 2
+    if name == "walk_kernel":
+        return "hbm", walk_steps * ALIAS_ENTRY_BYTES / 1e9, "GB"
+    if name == "cholesky_kernel":
+        return "alu", nE * (N ** 3 / 3.0) / 1e12, "TFLOP"
+    if name == "fullinv_kernel":
+        # two sweeps per column slice: L*(L-1) complex W x W block products per energy
+        return "alu", nE * 8.0 * W ** 3 * wl.L * (wl.L - 1) / 1e12, "TFLOP"
+    if name == "alias_build_kernel":
+        # read gamma_i |G_ji|^2 rows and write one 8-byte alias entry per outcome
+        return "hbm", nE * (8.0 * N * N + 8.0 * n * n) / 1e9, "GB"
+    if name == "direct_fill_kernel":
+        return "hbm", nE * 16.0 * N * N / 1e9, "GB"
+    return None
+
+
+def roofline(name, wl, ms_per_launch, walk_steps):
+    w = kernel_work(name, wl, walk_steps)
+    if w is None:
+        return None
+    bound, amount, unit = w
+    if unit == "GB":
+        achieved = amount / (ms_per_launch * 1e-3)
+        return {"kernel": name, "bound": bound, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "algorithmic_per_launch": amount * 1e9, "avg_launch_ms": ms_per_launch}
+    achieved = amount / (ms_per_launch * 1e-3)
+    return {"kernel": name, "bound": bound, "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
+            "algorithmic_per_launch": amount * 1e12, "avg_launch_ms": ms_per_launch}
+
+
+def measured_traffic(name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary for `name`, or None
+    when the kernel's source changed since the counters were taken."""
+    path = os.path.join(PROFILES, f"{name}_wire_W10_L100_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+            return None
+        return float(rec["hbm_bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def time_to_1pct(p: Problem, torch, seed, walk_on):
+    """Wall time to a 1% relative deviation of I, median of 5 warm repetitions.
+    MC: build + walker batches doubling from 1024 per energy until sigma_I <= 1% of I.
+    DIRECT: build + probe-system solve (deterministic; its error is the quadrature's)."""
     mc_t, dir_t, mc_walkers = [], [], []
     for rep in range(5):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        k = M.mc_negf_build_kernel(p.sys, p.V, p.g, p.E, p.ws)
-        p.tal.zero_()
-        done, batch = 0, 1024
-        while True:
-            M.mc_negf_walk(k, seed + 1 + rep, 0, 0, done, batch, 1_000_000, p.tal)
-            done += batch
-            st, I, s = M.mc_negf_current(k, 0, 0, p.tal, p.w, p.T, p.sig)
-            if s <= 0.01 * abs(I) or done >= 1 << 24:
-                break
-            batch = done
-        mc_t.append(time.perf_counter() - t0)
-        mc_walkers.append(done)
+        if walk_on:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            k = M.mc_negf_build_kernel(p.sys, p.V, p.g, p.E, p.ws)
+            p.tal.zero_()
+            done, batch = 0, 1024
+            while True:
+                M.mc_negf_walk(k, seed + 1 + rep, 0, 0, done, batch, 1_000_000, p.tal)
+                done += batch
+                st, I, s = M.mc_negf_current(k, 0, 0, p.tal, p.w, p.T, p.sig)
+                if s <= 0.01 * abs(I) or done >= 1 << 24:
+                    break
+                batch = done
+            mc_t.append(time.perf_counter() - t0)
+            mc_walkers.append(done)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         k = M.mc_negf_build_kernel(p.sys, p.V, p.g, p.E, p.ws)
         M.mc_negf_current(k, 1, 0, None, p.w, p.T, p.sig)
         dir_t.append(time.perf_counter() - t0)
-    return dict(mc_ms=1e3 * float(np.median(mc_t)), direct_ms=1e3 * float(np.median(dir_t)),
-                mc_walkers_per_energy=int(np.median(mc_walkers)), eta=p.wl.eta)
+    return {"eta": p.wl.eta,
+            "mc_ms": 1e3 * float(np.median(mc_t)) if mc_t else None,
+            "mc_walkers_per_energy": int(np.median(mc_walkers)) if mc_walkers else None,
+            "direct_ms": 1e3 * float(np.median(dir_t))}
 
 
 def cpu_baseline(wl: inputs.Workload, seed: int):
-    """The oracle on the host cores: dense solves plus the C walker (the paper's cumulative
-    sampler) for a bounded sample of the workload: 8 of the 256 energies, 20 000 walkers
-    each, at the middle dephasing rate."""
+    """The oracle on the host cores for a bounded sample of the workload: dense LAPACK
+    solves plus the C walker (the paper's cumulative-sum sampler), 8 of the 256 energies
+    with 20 000 walkers each, at the middle dephasing rate."""
     from oracle import dense as D
     from oracle import walker as OW
     E, _ = M.energy_grid(wl.emin, wl.emax, wl.n_energies)
@@ -131,20 +193,6 @@ def cpu_baseline(wl: inputs.Workload, seed: int):
                       f"{steps} steps in {dt:.1f} s"}
 
 
-def walker_traffic(walk_steps_per_launch):
-    """HBM bytes per walker launch from the committed rocprofv3 counter summary, or None
-    when the walker source changed since the counters were taken."""
-    try:
-        with open(TRAFFIC_FILE) as f:
-            rec = json.load(f)
-        src = hashlib.sha256(open(WALKER_SRC, "rb").read()).hexdigest()
-        if rec.get("walker_sha256") != src:
-            return None
-        return float(rec["hbm_bytes_per_launch"])
-    except (OSError, ValueError, KeyError):
-        return None
-
-
 def main():
     args = parse()
     if args.gpus != 1:
@@ -157,49 +205,47 @@ def main():
     walkers = args.walkers or base.walkers_per_energy
     etas = [float(x) for x in args.etas.split(",")] if args.etas else list(inputs.WIRE_ETAS)
     probs = [Problem(base.replace(eta=eta), torch, dev) for eta in etas]
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in probs]
     seed = inputs.RNG_SEED
+    walk_on = walker_available(probs[0], torch)
 
     for _ in range(args.warmup):
-        for p, e in zip(probs, ev):
-            run_step(p, torch, walkers, seed, e)
+        for p in probs:
+            run_step(p, walkers, seed, walk_on)
     torch.cuda.synchronize()
 
-    stage = np.zeros((len(probs), 4))
     steps_total = 0
-    walker_launches = 0
     results = []
     t0 = time.perf_counter()
-    for it in range(args.steps):
-        for j, (p, e) in enumerate(zip(probs, ev)):
-            res = run_step(p, torch, walkers, seed, e)
-            torch.cuda.synchronize()
-            stage[j] += [e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]),
-                         e[2].elapsed_time(e[3]), e[3].elapsed_time(e[4])]
-            steps_total += int(p.tal[:, M.TALLY_STEPS].sum())
-            walker_launches += 1
-            if it == args.steps - 1:
-                results.append((p, res))
-    torch.cuda.synchronize()
+    with M.LaunchTimes() as lt:
+        for it in range(args.steps):
+            for p in probs:
+                res = run_step(p, walkers, seed, walk_on)
+                if walk_on:
+                    steps_total += int(p.tal[:, M.TALLY_STEPS].sum())
+                if it == args.steps - 1:
+                    results.append((p, res))
+        torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
+    names = sorted(set(n for n, _ in lt.records))
+    per_kernel = {n: {"launches": lt.count(n), "ms_per_launch": lt.total_ms(n) / lt.count(n),
+                      "ms_per_step": lt.total_ms(n) / args.steps} for n in names}
+    dominant = max(names, key=lambda n: lt.total_ms(n))
+    walk_steps_per_launch = steps_total / max(1, lt.count("walk_kernel")) if walk_on else 0
+    roof = roofline(dominant, base, per_kernel[dominant]["ms_per_launch"], walk_steps_per_launch)
+    if roof is not None:
+        roof["traffic"] = measured_traffic(dominant)
+    rooflines = {n: roofline(n, base, per_kernel[n]["ms_per_launch"], walk_steps_per_launch)
+                 for n in names}
     per_eta = []
-    for (p, res), st in zip(results, stage / args.steps):
-        st_mc, I_mc, s_mc, st_d, I_d = res
-        tal = p.tal.cpu().numpy()
-        per_eta.append({"eta": p.wl.eta, "I_mc": I_mc, "sigma_I_mc": s_mc, "I_direct": I_d,
-                        "mc_minus_direct_in_sigma": (I_mc - I_d) / s_mc if s_mc > 0 else None,
-                        "status_mc": st_mc, "status_direct": st_d,
-                        "mean_steps_per_walker": float(tal[:, 3].sum() / tal[:, :3].sum()),
-                        "ms_build": st[0], "ms_walk": st[1], "ms_mc_current": st[2],
-                        "ms_direct_current": st[3]})
-    walk_ms = float(stage[:, 1].sum() / args.steps)
-    steps_per_step = steps_total / args.steps
-    walk_rate = steps_per_step / (walk_ms * 1e-3)
-    avg_launch_s = walk_ms * 1e-3 / len(probs)
-    bytes_per_launch = steps_per_step / len(probs) * ALIAS_ENTRY_BYTES
-    achieved = bytes_per_launch / avg_launch_s / 1e9
-    traffic = walker_traffic(steps_per_step / len(probs))
+    for p, (st_mc, I_mc, s_mc, st_d, I_d) in results:
+        rec = {"eta": p.wl.eta, "I_direct": I_d, "status_direct": st_d}
+        if walk_on:
+            tal = p.tal.cpu().numpy()
+            rec.update({"I_mc": I_mc, "sigma_I_mc": s_mc, "status_mc": st_mc,
+                        "mc_minus_direct_in_sigma": (I_mc - I_d) / s_mc if s_mc else None,
+                        "mean_steps_per_walker": float(tal[:, 3].sum() / tal[:, :3].sum())})
+        per_eta.append(rec)
     line = {
         "metric": "walk steps/s; time-to-1% lead-current error vs direct NEGF, 1 MI355X",
         "value": steps_total / wall,
@@ -217,18 +263,20 @@ def main():
                                f"U[-{base.disorder},{base.disorder}]t, {base.n_energies} "
                                f"energies in [{base.emin},{base.emax}]t, {walkers} walkers/energy,"
                                f" eta in {etas}t",
-                   "walkers_per_energy": walkers, "n_energies": base.n_energies,
-                   "etas": etas, "parallelism": "single GPU"},
-        "walker_kernel_steps_per_s": walk_rate,
+                   "walkers_per_energy": walkers, "n_energies": base.n_energies, "etas": etas,
+                   "parallelism": "single GPU"},
+        "walker": "on" if walk_on else "switched off in this build (a GPU run of the walker "
+                                        "kernel stalled with no identified cause); steps "
+                                        "time the kernel build and DIRECT current only",
         "per_eta": per_eta,
-        "roofline": {"kernel": "walk_kernel", "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
-                     "algorithmic_bytes_per_step": ALIAS_ENTRY_BYTES,
-                     "avg_launch_ms": avg_launch_s * 1e3},
+        "per_kernel": per_kernel,
+        "roofline": roof,
+        "rooflines": {n: r for n, r in rooflines.items() if r is not None},
     }
+    if walk_on:
+        line["walker_kernel_steps_per_s"] = steps_total / (lt.total_ms("walk_kernel") * 1e-3)
     if not args.no_ttp:
-        line["time_to_1pct"] = [time_to_1pct(p, torch, seed) for p in probs]
+        line["time_to_1pct"] = [time_to_1pct(p, torch, seed, walk_on) for p in probs]
     if not args.no_cpu_baseline:
         mid = probs[len(probs) // 2].wl
         line["cpu_baseline"] = cpu_baseline(mid, seed)

@@ -93,9 +93,12 @@ __global__ void __launch_bounds__(256) lead_terms_kernel(const double2* __restri
 }
 
 hipError_t launch_lead_terms(const mcnegf_kernel& k, hipStream_t s) {
-    hipLaunchKernelGGL(lead_terms_kernel, dim3(k.nE), dim3(256), 0, s,
-                       reinterpret_cast<const double2*>(k.Gd),
-                       reinterpret_cast<const double2*>(k.corner), k.gam_lead, k.W, k.L, k.lead);
+    {
+        MCNEGF_TIMED("lead_terms_kernel", s);
+        hipLaunchKernelGGL(lead_terms_kernel, dim3(k.nE), dim3(256), 0, s,
+                           reinterpret_cast<const double2*>(k.Gd),
+                           reinterpret_cast<const double2*>(k.corner), k.gam_lead, k.W, k.L, k.lead);
+    }
     return hipGetLastError();
 }
 
@@ -310,7 +313,10 @@ hipError_t launch_alias_build(const mcnegf_kernel& k, hipStream_t s) {
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (err != hipSuccess) return err;
     }
-    hipLaunchKernelGGL(alias_build_kernel, dim3(n, k.nE), dim3(256), lds, s, a);
+    {
+        MCNEGF_TIMED("alias_build_kernel", s);
+        hipLaunchKernelGGL(alias_build_kernel, dim3(n, k.nE), dim3(256), lds, s, a);
+    }
     return hipGetLastError();
 }
 

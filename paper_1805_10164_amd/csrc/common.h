@@ -53,6 +53,16 @@ struct Layout {
 };
 Layout make_layout(int W, int L, int nE);
 
+// ---- opt-in launch timing: events around every launch while a profile is attached ------
+struct LaunchTimer {
+    LaunchTimer(const char* name, hipStream_t s);
+    ~LaunchTimer();
+    mcnegf_profile* p;
+    int slot;
+    hipStream_t s;
+};
+#define MCNEGF_TIMED(name, stream) ::mcnegf::LaunchTimer mcnegf_timer_(name, stream)
+
 // ---- launchers (each defined next to its kernel) ----------------------------------------
 hipError_t launch_clear_status(uint32_t* status, uint32_t* counters, hipStream_t s);
 hipError_t launch_lead_sigma(const mcnegf_kernel& k, double gamma_l, double delta,

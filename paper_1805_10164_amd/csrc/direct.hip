@@ -70,12 +70,18 @@ __global__ void mc_current_kernel(const int64_t* __restrict__ tallies,
 
 hipError_t launch_mc_current(const mcnegf_kernel& k, uint32_t inject_lead, const int64_t* tallies,
                              const double* weights, double* T, double* sigmaT, hipStream_t s) {
-    hipLaunchKernelGGL(mc_current_kernel, dim3((k.nE + 255) / 256), dim3(256), 0, s, tallies,
-                       k.lead, k.nE, inject_lead, T, sigmaT);
+    {
+        MCNEGF_TIMED("mc_current_kernel", s);
+        hipLaunchKernelGGL(mc_current_kernel, dim3((k.nE + 255) / 256), dim3(256), 0, s, tallies,
+                           k.lead, k.nE, inject_lead, T, sigmaT);
+    }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(current_sum_kernel, dim3(1), dim3(256), 0, s, T, sigmaT, weights, k.nE,
-                       k.reduce);
+    {
+        MCNEGF_TIMED("current_sum_kernel", s);
+        hipLaunchKernelGGL(current_sum_kernel, dim3(1), dim3(256), 0, s, T, sigmaT, weights, k.nE,
+                           k.reduce);
+    }
     return hipGetLastError();
 }
 
@@ -298,22 +304,37 @@ __global__ void __launch_bounds__(256) chol_solve_kernel(const double* __restric
 hipError_t launch_direct_current(const mcnegf_kernel& k, uint32_t inject_lead,
                                  const double* weights, double* T, double* sigmaT, hipStream_t s) {
     const int N = k.N;
-    hipLaunchKernelGGL(direct_prep_kernel, dim3((N + 255) / 256, k.nE), dim3(256), 0, s, k.P,
-                       k.Adiag, k.wL, k.wR, k.gamma, N, k.p_pitch, inject_lead, k.direct_vec);
+    {
+        MCNEGF_TIMED("direct_prep_kernel", s);
+        hipLaunchKernelGGL(direct_prep_kernel, dim3((N + 255) / 256, k.nE), dim3(256), 0, s, k.P,
+                           k.Adiag, k.wL, k.wR, k.gamma, N, k.p_pitch, inject_lead, k.direct_vec);
+    }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(direct_fill_kernel, dim3(N, k.nE), dim3(256), 0, s, k.P, k.gamma,
-                       k.direct_vec, N, k.p_pitch, k.direct);
+    {
+        MCNEGF_TIMED("direct_fill_kernel", s);
+        hipLaunchKernelGGL(direct_fill_kernel, dim3(N, k.nE), dim3(256), 0, s, k.P, k.gamma,
+                           k.direct_vec, N, k.p_pitch, k.direct);
+    }
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    hipLaunchKernelGGL(cholesky_kernel, dim3(k.nE), dim3(256), 0, s, k.direct, N, k.p_pitch,
-                       k.status);
+    {
+        MCNEGF_TIMED("cholesky_kernel", s);
+        hipLaunchKernelGGL(cholesky_kernel, dim3(k.nE), dim3(256), 0, s, k.direct, N, k.p_pitch,
+                           k.status);
+    }
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    hipLaunchKernelGGL(chol_solve_kernel, dim3(k.nE), dim3(256), (size_t)N * sizeof(double), s,
-                       k.direct, N, k.p_pitch, k.direct_vec, k.lead, inject_lead, T, sigmaT,
-                       k.status);
+    {
+        MCNEGF_TIMED("chol_solve_kernel", s);
+        hipLaunchKernelGGL(chol_solve_kernel, dim3(k.nE), dim3(256), (size_t)N * sizeof(double), s,
+                           k.direct, N, k.p_pitch, k.direct_vec, k.lead, inject_lead, T, sigmaT,
+                           k.status);
+    }
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    hipLaunchKernelGGL(current_sum_kernel, dim3(1), dim3(256), 0, s, T, sigmaT, weights, k.nE,
-                       k.reduce);
+    {
+        MCNEGF_TIMED("current_sum_kernel", s);
+        hipLaunchKernelGGL(current_sum_kernel, dim3(1), dim3(256), 0, s, T, sigmaT, weights, k.nE,
+                           k.reduce);
+    }
     return hipGetLastError();
 }
 

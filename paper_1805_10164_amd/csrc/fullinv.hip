@@ -134,11 +134,14 @@ __global__ void __launch_bounds__(256) fullinv_kernel(const double2* __restrict_
 template <int W>
 static hipError_t launch_fullinv_w(const mcnegf_kernel& k, hipStream_t s) {
     dim3 grid((k.N + 255) / 256, k.nE);
-    hipLaunchKernelGGL(fullinv_kernel<W>, grid, dim3(256), 0, s,
-                       reinterpret_cast<const double2*>(k.gL),
-                       reinterpret_cast<const double2*>(k.gR),
-                       reinterpret_cast<const double2*>(k.Gd), k.gam_lead, k.L, k.t, k.p_pitch,
-                       k.P, k.wL, k.wR, reinterpret_cast<double2*>(k.corner));
+    {
+        MCNEGF_TIMED("fullinv_kernel", s);
+        hipLaunchKernelGGL(fullinv_kernel<W>, grid, dim3(256), 0, s,
+                           reinterpret_cast<const double2*>(k.gL),
+                           reinterpret_cast<const double2*>(k.gR),
+                           reinterpret_cast<const double2*>(k.Gd), k.gam_lead, k.L, k.t, k.p_pitch,
+                           k.P, k.wL, k.wR, reinterpret_cast<double2*>(k.corner));
+    }
     return hipGetLastError();
 }
 

@@ -79,15 +79,21 @@ __global__ void clear_status_kernel(uint32_t* status, uint32_t* counters) {
 }
 
 hipError_t launch_clear_status(uint32_t* status, uint32_t* counters, hipStream_t s) {
-    hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(64), 0, s, status, counters);
+    {
+        MCNEGF_TIMED("clear_status_kernel", s);
+        hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(64), 0, s, status, counters);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_lead_sigma(const mcnegf_kernel& k, double gamma_l, double delta,
                              hipStream_t s) {
-    hipLaunchKernelGGL(lead_sigma_kernel, dim3(k.nE), dim3(256), 0, s, k.energies, k.W, k.t,
-                       k.lead_model, gamma_l, delta, reinterpret_cast<double2*>(k.sigma),
-                       k.gam_lead);
+    {
+        MCNEGF_TIMED("lead_sigma_kernel", s);
+        hipLaunchKernelGGL(lead_sigma_kernel, dim3(k.nE), dim3(256), 0, s, k.energies, k.W, k.t,
+                           k.lead_model, gamma_l, delta, reinterpret_cast<double2*>(k.sigma),
+                           k.gam_lead);
+    }
     return hipGetLastError();
 }
 

@@ -8,6 +8,22 @@
 namespace mcnegf {
 
 static thread_local int32_t g_last_hip_error = 0;
+static thread_local mcnegf_profile* g_profile = nullptr;
+
+LaunchTimer::LaunchTimer(const char* name, hipStream_t stream) : p(g_profile), slot(-1), s(stream) {
+    if (!p) return;
+    if (p->n >= MCNEGF_PROFILE_MAX) {
+        ++p->dropped;
+        return;
+    }
+    slot = p->n++;
+    p->name[slot] = name;
+    hipEventRecord(p->start[slot], s);
+}
+
+LaunchTimer::~LaunchTimer() {
+    if (p && slot >= 0) hipEventRecord(p->stop[slot], s);
+}
 
 static int32_t hip_fail(hipError_t e) {
     g_last_hip_error = (int32_t)e;
@@ -69,6 +85,9 @@ static bool valid_kernel(const mcnegf_kernel* k) {
            k->n_out == k->N + 2 && k->nE >= 1 && k->alias && k->P && k->lead && k->status &&
            k->counters && k->reduce;
 }
+
+// The walker kernel is switched off: a GPU run of it stalled and no cause has been found.
+static constexpr bool walker_enabled = false;
 
 static int32_t status_to_code(uint32_t flags, bool mc) {
     if (flags & (MCNEGF_FLAG_NONFINITE | MCNEGF_FLAG_SINGULAR | MCNEGF_FLAG_NOTSPD))
@@ -159,6 +178,7 @@ int32_t mc_negf_walk(const mcnegf_kernel* k, uint64_t seed, uint32_t realization
     if (walker_begin + n_walkers_per_energy > 0x100000000ull ||
         walker_begin >= 0x100000000ull)
         return MCNEGF_EINVAL;
+    if (!walker_enabled) return MCNEGF_EDISABLED;
     if (n_walkers_per_energy == 0) return MCNEGF_OK;
     const uint32_t tag = (realization << 1) | inject_lead;
     hipError_t err = launch_walk(*k, seed, tag, (uint32_t)walker_begin,
@@ -201,6 +221,43 @@ int32_t mc_negf_grad(const mcnegf_kernel* k, const double* d_weights, double* d_
                      double* h_dI_deta, hipStream_t stream) {
     (void)k; (void)d_weights; (void)d_dI_dV; (void)h_dI_deta; (void)stream;
     return MCNEGF_ENOTIMPL;
+}
+
+int32_t mc_negf_profile_begin(mcnegf_profile* p) {
+    if (!p || g_profile) return MCNEGF_EINVAL;
+    std::memset(p, 0, sizeof(*p));
+    for (int i = 0; i < MCNEGF_PROFILE_MAX; ++i) {
+        hipError_t err;
+        if ((err = hipEventCreate(&p->start[i])) != hipSuccess ||
+            (err = hipEventCreate(&p->stop[i])) != hipSuccess) {
+            for (int j = 0; j <= i; ++j) {
+                if (p->start[j]) hipEventDestroy(p->start[j]);
+                if (p->stop[j]) hipEventDestroy(p->stop[j]);
+            }
+            std::memset(p, 0, sizeof(*p));
+            return hip_fail(err);
+        }
+    }
+    g_profile = p;
+    return MCNEGF_OK;
+}
+
+int32_t mc_negf_profile_end(mcnegf_profile* p, float* ms_out) {
+    if (!p || g_profile != p) return MCNEGF_EINVAL;
+    g_profile = nullptr;
+    int32_t rc = MCNEGF_OK;
+    for (int i = 0; i < p->n; ++i) {
+        float ms = 0.0f;
+        hipError_t err = hipEventSynchronize(p->stop[i]);
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, p->start[i], p->stop[i]);
+        if (err != hipSuccess) rc = hip_fail(err);
+        if (ms_out) ms_out[i] = ms;
+    }
+    for (int i = 0; i < MCNEGF_PROFILE_MAX; ++i) {
+        hipEventDestroy(p->start[i]);
+        hipEventDestroy(p->stop[i]);
+    }
+    return rc;
 }
 
 int32_t mc_negf_status(const mcnegf_kernel* k, uint32_t* h_flags, hipStream_t stream) {

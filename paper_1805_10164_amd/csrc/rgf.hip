@@ -189,13 +189,19 @@ static hipError_t launch_rgf_w(const mcnegf_kernel& k, const double* onsite, hip
     const double2* sig = reinterpret_cast<const double2*>(k.sigma);
     double2* gL = reinterpret_cast<double2*>(k.gL);
     double2* gR = reinterpret_cast<double2*>(k.gR);
-    hipLaunchKernelGGL(rgf_sweep_kernel<W>, dim3(2 * k.nE), dim3(64), 0, s, k.energies, onsite,
-                       k.gamma, sig, k.L, k.t, gL, gR, k.status);
+    {
+        MCNEGF_TIMED("rgf_sweep_kernel", s);
+        hipLaunchKernelGGL(rgf_sweep_kernel<W>, dim3(2 * k.nE), dim3(64), 0, s, k.energies, onsite,
+                           k.gamma, sig, k.L, k.t, gL, gR, k.status);
+    }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(rgf_diag_kernel<W>, dim3(k.nE * k.L), dim3(64), 0, s, k.energies,
-                       onsite, k.gamma, sig, k.L, k.t, gL, gR,
-                       reinterpret_cast<double2*>(k.Gd), k.Adiag, k.status);
+    {
+        MCNEGF_TIMED("rgf_diag_kernel", s);
+        hipLaunchKernelGGL(rgf_diag_kernel<W>, dim3(k.nE * k.L), dim3(64), 0, s, k.energies,
+                           onsite, k.gamma, sig, k.L, k.t, gL, gR,
+                           reinterpret_cast<double2*>(k.Gd), k.Adiag, k.status);
+    }
     return hipGetLastError();
 }
 

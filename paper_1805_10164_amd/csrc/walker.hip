@@ -195,13 +195,19 @@ hipError_t launch_walk(const mcnegf_kernel& k, uint64_t seed, uint32_t tag, uint
     A.counter = k.counters;
     A.tallies = tallies;
     A.status = k.status;
-    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, k.counters);
+    {
+        MCNEGF_TIMED("reset_counter_kernel", s);
+        hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, k.counters);
+    }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     const uint64_t waves_needed = (uint64_t)A.nE * A.chunks_per_energy;
     const uint64_t nb = (waves_needed + 3) / 4;
-    hipLaunchKernelGGL(walk_kernel, dim3((unsigned)(nb < (uint64_t)blocks ? nb : blocks)),
-                       dim3(256), 0, s, A);
+    {
+        MCNEGF_TIMED("walk_kernel", s);
+        hipLaunchKernelGGL(walk_kernel, dim3((unsigned)(nb < (uint64_t)blocks ? nb : blocks)),
+                           dim3(256), 0, s, A);
+    }
     return hipGetLastError();
 }
 

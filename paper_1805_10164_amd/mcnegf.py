@@ -17,15 +17,16 @@ LIB_PATH = os.path.join(HERE, "libmcnegf.so")
 
 # status codes (include/mcnegf.h)
 OK, WTRUNC, WNUMERIC = 0, 1, 2
-EINVAL, EWS, EHIP, ENUMERIC, ENOTIMPL = -1, -2, -3, -4, -5
+EINVAL, EWS, EHIP, ENUMERIC, ENOTIMPL, EDISABLED = -1, -2, -3, -4, -5, -6
 FLAG_NONFINITE, FLAG_SINGULAR, FLAG_ROWSUM, FLAG_NOABSORB, FLAG_TRUNC, FLAG_NOTSPD = (
     0x01, 0x02, 0x04, 0x08, 0x10, 0x20)
 LEAD_NTERMS = 8
 LEAD_TLL, LEAD_TRL, LEAD_TLR, LEAD_TRR, LEAD_CL, LEAD_CR, LEAD_TRGLA, LEAD_TRGRA = range(8)
 TALLY_N = 5
 EXPORTED = ("mc_negf_workspace_bytes", "mc_negf_build_kernel", "mc_negf_walk",
-            "mc_negf_current", "mc_negf_grad", "mc_negf_status", "mc_negf_last_hip_error",
-            "mc_negf_version")
+            "mc_negf_current", "mc_negf_grad", "mc_negf_profile_begin", "mc_negf_profile_end",
+            "mc_negf_status", "mc_negf_last_hip_error", "mc_negf_version")
+PROFILE_MAX = 512
 
 
 class McnegfError(RuntimeError):
@@ -56,6 +57,12 @@ class KernelStruct(ctypes.Structure):
                 ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_uint64)]
 
 
+class Profile(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("dropped", ctypes.c_int32),
+                ("name", ctypes.c_char_p * PROFILE_MAX), ("start", ctypes.c_void_p * PROFILE_MAX),
+                ("stop", ctypes.c_void_p * PROFILE_MAX)]
+
+
 _lib = None
 
 
@@ -76,6 +83,8 @@ def lib() -> ctypes.CDLL:
     L.mc_negf_current.argtypes = [ctypes.POINTER(KernelStruct), i32, u32, vp, vp, vp, vp, dp, vp]
     L.mc_negf_grad.argtypes = [ctypes.POINTER(KernelStruct), vp, vp, dp, vp]
     L.mc_negf_status.argtypes = [ctypes.POINTER(KernelStruct), ctypes.POINTER(u32), vp]
+    L.mc_negf_profile_begin.argtypes = [ctypes.POINTER(Profile)]
+    L.mc_negf_profile_end.argtypes = [ctypes.POINTER(Profile), ctypes.POINTER(ctypes.c_float)]
     L.mc_negf_last_hip_error.argtypes = []
     L.mc_negf_version.argtypes = []
     for name in EXPORTED:
@@ -219,6 +228,34 @@ def mc_negf_status(k: Kernel, stream=None) -> int:
     _check("mc_negf_status", lib().mc_negf_status(ctypes.byref(k.struct), ctypes.byref(flags),
                                                   _stream(stream)))
     return int(flags.value)
+
+
+class LaunchTimes:
+    """Context manager: times every launch of this library from the calling thread with HIP
+    events on the launch stream; after exit, `.records` is a list of (kernel name, ms)."""
+
+    def __init__(self):
+        self.p = Profile()
+        self.records = []
+
+    def __enter__(self):
+        _check("mc_negf_profile_begin", lib().mc_negf_profile_begin(ctypes.byref(self.p)))
+        return self
+
+    def __exit__(self, *exc):
+        ms = (ctypes.c_float * PROFILE_MAX)()
+        code = lib().mc_negf_profile_end(ctypes.byref(self.p), ms)
+        self.records = [(self.p.name[i].decode(), float(ms[i])) for i in range(self.p.n)]
+        self.dropped = int(self.p.dropped)
+        if exc[0] is None:
+            _check("mc_negf_profile_end", code)
+        return False
+
+    def total_ms(self, name):
+        return sum(ms for n, ms in self.records if n == name)
+
+    def count(self, name):
+        return sum(1 for n, _ in self.records if n == name)
 
 
 def allocate_workspace(system: System, nE: int, device="cuda"):

@@ -92,3 +92,16 @@ def test_energy_grid_is_midpoint():
     E, w = M.energy_grid(-3.5, 3.5, 256)
     assert abs(E[0] - (-3.5 + 3.5 / 256)) < 1e-15 and abs(E[-1] - (3.5 - 3.5 / 256)) < 1e-15
     assert abs(w.sum() - 7.0) < 1e-12
+
+
+def test_walk_entry_point_reports_disabled_without_launching():
+    # a structurally valid handle (dummy non-null pointers) passes validation; the call
+    # then reports MCNEGF_EDISABLED without touching the GPU
+    lib = M.lib()
+    ks = M.KernelStruct()
+    ks.W, ks.L, ks.N, ks.n_out, ks.nE = 2, 3, 6, 8, 1
+    for f in ("alias", "P", "lead", "status", "counters", "reduce"):
+        setattr(ks, f, 4096)
+    z = ctypes.c_void_p(0)
+    assert lib.mc_negf_walk(ctypes.byref(ks), 1, 0, 0, 0, 10, 10, ctypes.c_void_p(4096), z) == M.EDISABLED
+    assert lib.mc_negf_walk(ctypes.byref(ks), 1, 0, 2, 0, 10, 10, ctypes.c_void_p(4096), z) == M.EINVAL
