@@ -65,17 +65,6 @@ class Problem:
         self.k = None
 
 
-def walker_available(p: Problem, torch) -> bool:
-    p.k = M.mc_negf_build_kernel(p.sys, p.V, p.g, p.E, p.ws)
-    try:
-        M.mc_negf_walk(p.k, 1, 0, 0, 0, 0, 1, p.tal)
-        return True
-    except M.McnegfError as e:
-        if e.code == M.EDISABLED:
-            return False
-        raise
-
-
 def run_step(p: Problem, walkers, seed, walk_on):
     """Whole hot path for one problem; returns (status_mc, I_mc, sigma_mc, status_d, I_d)."""
     p.k = M.mc_negf_build_kernel(p.sys, p.V, p.g, p.E, p.ws)
@@ -206,7 +195,7 @@ def main():
     etas = [float(x) for x in args.etas.split(",")] if args.etas else list(inputs.WIRE_ETAS)
     probs = [Problem(base.replace(eta=eta), torch, dev) for eta in etas]
     seed = inputs.RNG_SEED
-    walk_on = walker_available(probs[0], torch)
+    walk_on = True
 
     for _ in range(args.warmup):
         for p in probs:
@@ -265,9 +254,6 @@ def main():
                                f" eta in {etas}t",
                    "walkers_per_energy": walkers, "n_energies": base.n_energies, "etas": etas,
                    "parallelism": "single GPU"},
-        "walker": "on" if walk_on else "switched off in this build (a GPU run of the walker "
-                                        "kernel stalled with no identified cause); steps "
-                                        "time the kernel build and DIRECT current only",
         "per_eta": per_eta,
         "per_kernel": per_kernel,
         "roofline": roof,

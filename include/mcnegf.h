@@ -57,7 +57,6 @@ extern "C" {
 #define MCNEGF_EHIP      -3   /* a HIP call failed; see mc_negf_last_hip_error()          */
 #define MCNEGF_ENUMERIC  -4   /* NaN/Inf, singular RGF block or non-SPD probe system       */
 #define MCNEGF_ENOTIMPL  -5   /* entry point not implemented                              */
-#define MCNEGF_EDISABLED -6   /* entry point switched off in this build (see mc_negf_walk) */
 
 /* ---- bits of the device status word ------------------------------------------------- */
 #define MCNEGF_FLAG_NONFINITE  0x01u  /* NaN or Inf in G, the kernel or a solve           */
@@ -164,9 +163,6 @@ int32_t mc_negf_build_kernel(const mcnegf_system* sys, const double* d_onsite,
 
 /*
  * Random walks on the alias tables of k (Sec. II F, step 6' repeated until a lead is drawn).
- * Currently switched off: after validating its arguments it returns MCNEGF_EDISABLED and
- * launches nothing, because a GPU run of the walker kernel stalled without an identified
- * cause; the kernel stays out of use until that cause is found and fixed.
  *   seed, realization  key of the Philox4x32-10 streams; realization < 2^30.
  *   inject_lead        0: walkers start in the L injection row, 1: in the R row.
  *   walker_begin, n_walkers_per_energy  walker indices [walker_begin, walker_begin + n)

@@ -13,6 +13,9 @@ SOURCES = ["mcnegf.cpp", "lead.hip", "rgf.hip", "fullinv.hip", "alias.hip", "wal
            "direct.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature",
          "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result"]
+# The walker keeps every lane of a wavefront active at each cross-lane operation; the atomic
+# optimizer would turn its uniform-address LDS adds into a first-lane-only region.
+EXTRA = {"walker.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
 
 
 def hipcc() -> str:
@@ -33,7 +36,7 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(objdir, src.replace(".", "_") + ".o")
         objs.append(obj)
         lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
-        cmd = [cc, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *FLAGS, *EXTRA.get(src, []), *lang, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

@@ -86,9 +86,6 @@ static bool valid_kernel(const mcnegf_kernel* k) {
            k->counters && k->reduce;
 }
 
-// The walker kernel is switched off: a GPU run of it stalled and no cause has been found.
-static constexpr bool walker_enabled = false;
-
 static int32_t status_to_code(uint32_t flags, bool mc) {
     if (flags & (MCNEGF_FLAG_NONFINITE | MCNEGF_FLAG_SINGULAR | MCNEGF_FLAG_NOTSPD))
         return MCNEGF_ENUMERIC;
@@ -178,7 +175,6 @@ int32_t mc_negf_walk(const mcnegf_kernel* k, uint64_t seed, uint32_t realization
     if (walker_begin + n_walkers_per_energy > 0x100000000ull ||
         walker_begin >= 0x100000000ull)
         return MCNEGF_EINVAL;
-    if (!walker_enabled) return MCNEGF_EDISABLED;
     if (n_walkers_per_energy == 0) return MCNEGF_OK;
     const uint32_t tag = (realization << 1) | inject_lead;
     hipError_t err = launch_walk(*k, seed, tag, (uint32_t)walker_begin,

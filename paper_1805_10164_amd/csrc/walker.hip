@@ -14,10 +14,10 @@
 // outcome = b < thr[c] ? c : alias[c].
 //
 // Execution: persistent wavefronts take chunks of consecutive walker indices of one energy
-// from an atomic counter (energy-major, so the tables being read are those of one or two
-// energies at a time and stay in L2 / MALL); each lane takes the next walker of the chunk
-// as soon as its own walker is absorbed, and every loop iteration performs two steps
-// from one Philox block.  Tallies live in registers and are wave-reduced once per chunk.
+// in grid-stride order (chunk ids are energy-major, so the wavefronts of the grid work on a
+// window of a few energies at a time whose tables stay in L2 / MALL); each lane takes the
+// next walker of its chunk as soon as its own walker is absorbed, and every loop iteration
+// performs two steps from one Philox block.
 #include "common.h"
 
 namespace mcnegf {
@@ -56,159 +56,170 @@ struct WalkArgs {
     int64_t pitch;
     int64_t table_stride;  // entries per energy
     uint32_t n_out, N;
-    uint32_t nE;
+    uint32_t nE;      // energies in this launch
+    uint32_t e_off;   // index of the first of them (the Philox counter uses e_off + e)
     uint32_t key0, key1, tag;
     uint32_t wbegin, wend;  // walker index range [wbegin, wend)
     uint32_t chunk, chunks_per_energy;
     uint32_t max_steps;
-    uint32_t* counter;
     int64_t* tallies;
     uint32_t* status;
 };
 
-__device__ inline uint32_t lemire_redraw(uint32_t a, uint32_t n_out, uint32_t step, uint32_t w,
-                                         uint32_t e, const WalkArgs& A) {
-    const uint32_t thresh = (0u - n_out) % n_out;
+// Every branch in the loops below is wave-uniform (its condition is a ballot or a value
+// computed identically in all lanes), and per-lane differences are expressed as selects:
+// the compiler does not guarantee that lanes which took a divergent branch rejoin the others
+// before a later cross-lane operation (ballot, shuffle, readfirstlane) in the same loop, so
+// the walker keeps the whole wavefront active at every one of them.  Tallies go to LDS
+// (every lane adds its own counts) and reach global memory once, after all loops.
+struct Step {
+    uint32_t s, n;
+    bool active;
+};
+
+// One transition draw for every lane of the wavefront; lanes with !st.active compute and
+// discard.  (a, b) are the step's two Philox words; counts are added for lanes whose walk
+// ends here.
+__device__ inline void walk_step(Step& st, uint32_t w, uint32_t e, uint32_t a, uint32_t b,
+                                 const uint2* __restrict__ tab, const WalkArgs& A,
+                                 uint32_t& cL, uint32_t& cR, uint32_t& tr, uint64_t& s1,
+                                 uint64_t& s2) {
+    const uint32_t n_out = A.n_out;
+    uint64_t m = (uint64_t)a * n_out;
+    uint32_t thresh = (0u - n_out) % n_out;
+    bool rej = st.active && ((uint32_t)m < thresh);
     uint32_t r = 0;
-    for (;;) {
-        const uint64_t m = (uint64_t)a * n_out;
-        if ((uint32_t)m >= thresh) return (uint32_t)(m >> 32);
+    while (__ballot(rej) != 0ull) {  // rare (probability < n / 2^32 per step); uniform loop
         ++r;
-        a = philox4x32_10(step, w, e, A.tag | 0x80000000u, A.key0, A.key1 ^ r).x[0];
+        const uint32_t a2 =
+            philox4x32_10(st.n, w, e, A.tag | 0x80000000u, A.key0, A.key1 ^ r).x[0];
+        const uint64_t m2 = (uint64_t)a2 * n_out;
+        m = rej ? m2 : m;
+        rej = rej && ((uint32_t)m2 < thresh);
     }
+    const uint32_t c = (uint32_t)(m >> 32);
+    const uint2 ent = tab[(size_t)st.s * A.pitch + c];
+    const uint32_t nxt = (b < ent.x) ? c : ent.y;
+    const uint32_t n1 = st.n + 1;
+    const bool absorbed = st.active && nxt >= A.N;
+    const bool trunc = st.active && !absorbed && n1 >= A.max_steps;
+    const bool ends = absorbed || trunc;
+    cL += (absorbed && nxt == A.N) ? 1u : 0u;
+    cR += (absorbed && nxt != A.N) ? 1u : 0u;
+    tr += trunc ? 1u : 0u;
+    s1 += ends ? (uint64_t)n1 : 0ull;
+    s2 += ends ? (uint64_t)n1 * n1 : 0ull;
+    st.s = (st.active && !ends) ? nxt : st.s;
+    st.n = st.active ? n1 : st.n;
+    st.active = st.active && !ends;
 }
 
 __global__ void __launch_bounds__(256) walk_kernel(WalkArgs A) {
+    extern __shared__ unsigned long long lds_tally[];  // [nE][5]
     const int lane = threadIdx.x & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint32_t total_chunks = A.nE * A.chunks_per_energy;
-    const uint32_t n_out = A.n_out;
-    const uint32_t N = A.N;
-    const uint32_t inject_row = N + (A.tag & 1u);
-    for (;;) {
-        uint32_t ch = 0;
-        if (lane == 0) ch = atomicAdd(A.counter, 1u);
-        ch = __builtin_amdgcn_readfirstlane(ch);
-        if (ch >= total_chunks) break;
-        const uint32_t e = ch / A.chunks_per_energy;
-        const uint32_t w0 = A.wbegin + (ch - e * A.chunks_per_energy) * A.chunk;
+    const uint32_t nE = A.nE;
+    for (uint32_t i = threadIdx.x; i < nE * MCNEGF_TALLY_N; i += blockDim.x) lds_tally[i] = 0ull;
+    __syncthreads();
+    const uint32_t total_chunks = nE * A.chunks_per_energy;
+    const uint32_t waves = __builtin_amdgcn_readfirstlane(gridDim.x * (blockDim.x >> 6));
+    const uint32_t wave_id =
+        __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    const uint32_t inject_row = A.N + (A.tag & 1u);
+    uint32_t trunc_any = 0;
+    for (uint32_t ch = wave_id; ch < total_chunks; ch += waves) {
+        const uint32_t el = ch / A.chunks_per_energy;  // energy within this launch
+        const uint32_t e = A.e_off + el;                 // energy index of the streams
+        const uint32_t w0 = A.wbegin + (ch - el * A.chunks_per_energy) * A.chunk;
         const uint32_t w1 = min(w0 + A.chunk, A.wend);
-        const uint2* tab = A.tables + (size_t)e * A.table_stride;
+        const uint2* tab = A.tables + (size_t)el * A.table_stride;
         uint32_t next = w0;
-        bool active = false;
-        uint32_t w = 0, s = 0, n = 0;
+        Step st = {inject_row, 0u, false};
+        uint32_t w = 0;
         uint32_t cL = 0, cR = 0, tr = 0;
         uint64_t s1 = 0, s2 = 0;
         for (;;) {
-            const uint64_t need = __ballot(!active);
-            if (need) {
-                const uint32_t avail = w1 - next;
-                const uint32_t before = __popcll(need & lt_mask);
-                if (!active && before < avail) {
-                    w = next + before;
-                    s = inject_row;
-                    n = 0;
-                    active = true;
-                }
-                const uint32_t cnt = __popcll(need);
-                next += cnt < avail ? cnt : avail;
-            }
-            if (__ballot(active) == 0ull) break;
-            if (active) {
-                const Philox4 x = philox4x32_10(n >> 1, w, e, A.tag, A.key0, A.key1);
-#pragma unroll
-                for (int half = 0; half < 2; ++half) {
-                    if (active) {
-                        const uint32_t a = x.x[2 * half], b = x.x[2 * half + 1];
-                        const uint64_t m = (uint64_t)a * n_out;
-                        uint32_t c = (uint32_t)(m >> 32);
-                        if ((uint32_t)m < n_out) c = lemire_redraw(a, n_out, n, w, e, A);
-                        const uint2 ent = tab[(size_t)s * A.pitch + c];
-                        const uint32_t nxt = (b < ent.x) ? c : ent.y;
-                        ++n;
-                        if (nxt >= N) {
-                            if (nxt == N) ++cL; else ++cR;
-                            s1 += n;
-                            s2 += (uint64_t)n * n;
-                            active = false;
-                        } else if (n >= A.max_steps) {
-                            ++tr;
-                            s1 += n;
-                            s2 += (uint64_t)n * n;
-                            active = false;
-                        } else {
-                            s = nxt;
-                        }
-                    }
-                }
-            }
+            // refill: idle lanes take the next walker indices of the chunk, in lane order
+            const uint64_t need = __ballot(!st.active);
+            const uint32_t avail = w1 - next;
+            const uint32_t before = __popcll(need & lt_mask);
+            const bool take = !st.active && before < avail;
+            w = take ? next + before : w;
+            st.s = take ? inject_row : st.s;
+            st.n = take ? 0u : st.n;
+            st.active = st.active || take;
+            const uint32_t cnt = __popcll(need);
+            next += cnt < avail ? cnt : avail;
+            if (__ballot(st.active) == 0ull) break;
+            // two steps from one Philox block (step n uses words 2(n&1), 2(n&1)+1 of block n>>1;
+            // active walkers enter the iteration at even n)
+            const Philox4 x = philox4x32_10(st.n >> 1, w, e, A.tag, A.key0, A.key1);
+            walk_step(st, w, e, x.x[0], x.x[1], tab, A, cL, cR, tr, s1, s2);
+            walk_step(st, w, e, x.x[2], x.x[3], tab, A, cL, cR, tr, s1, s2);
         }
-        // wave reduction of the chunk's tallies
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            cL += __shfl_xor(cL, off, 64);
-            cR += __shfl_xor(cR, off, 64);
-            tr += __shfl_xor(tr, off, 64);
-            s1 += __shfl_xor(s1, off, 64);
-            s2 += __shfl_xor(s2, off, 64);
-        }
-        if (lane == 0) {
-            unsigned long long* t =
-                reinterpret_cast<unsigned long long*>(A.tallies + (size_t)e * MCNEGF_TALLY_N);
-            atomicAdd(t + MCNEGF_TALLY_EXIT_L, (unsigned long long)cL);
-            atomicAdd(t + MCNEGF_TALLY_EXIT_R, (unsigned long long)cR);
-            if (tr) {
-                atomicAdd(t + MCNEGF_TALLY_TRUNC, (unsigned long long)tr);
-                atomicOr(A.status, MCNEGF_FLAG_TRUNC);
-            }
-            atomicAdd(t + MCNEGF_TALLY_STEPS, (unsigned long long)s1);
-            atomicAdd(t + MCNEGF_TALLY_STEPS2, (unsigned long long)s2);
-        }
+        unsigned long long* t = lds_tally + (size_t)el * MCNEGF_TALLY_N;
+        atomicAdd(t + MCNEGF_TALLY_EXIT_L, (unsigned long long)cL);
+        atomicAdd(t + MCNEGF_TALLY_EXIT_R, (unsigned long long)cR);
+        atomicAdd(t + MCNEGF_TALLY_TRUNC, (unsigned long long)tr);
+        atomicAdd(t + MCNEGF_TALLY_STEPS, (unsigned long long)s1);
+        atomicAdd(t + MCNEGF_TALLY_STEPS2, (unsigned long long)s2);
+        trunc_any |= tr;
     }
+    __syncthreads();
+    unsigned long long* gt = reinterpret_cast<unsigned long long*>(A.tallies);
+    for (uint32_t i = threadIdx.x; i < nE * MCNEGF_TALLY_N; i += blockDim.x) {
+        const unsigned long long v = lds_tally[i];
+        if (v) atomicAdd(gt + i, v);
+    }
+    if (trunc_any) atomicOr(A.status, MCNEGF_FLAG_TRUNC);
 }
-
-__global__ void reset_counter_kernel(uint32_t* counter) { counter[0] = 0u; }
 
 hipError_t launch_walk(const mcnegf_kernel& k, uint64_t seed, uint32_t tag, uint32_t walker_begin,
                        uint32_t n_walkers, uint32_t max_steps, int64_t* tallies, hipStream_t s) {
-    WalkArgs A;
-    A.tables = reinterpret_cast<const uint2*>(k.alias);
-    A.pitch = k.alias_pitch;
-    A.table_stride = (int64_t)k.n_out * k.alias_pitch;
-    A.n_out = (uint32_t)k.n_out;
-    A.N = (uint32_t)k.N;
-    A.nE = (uint32_t)k.nE;
-    A.key0 = (uint32_t)(seed & 0xffffffffu);
-    A.key1 = (uint32_t)(seed >> 32);
-    A.tag = tag;
-    A.wbegin = walker_begin;
-    A.wend = walker_begin + n_walkers;
-    // chunk: about two chunks per wavefront of a full grid, 64..4096 walkers
-    const uint64_t total = (uint64_t)n_walkers * (uint64_t)k.nE;
-    const int blocks = 2048;  // 8192 wavefronts of 64 lanes
-    uint64_t ch = total / ((uint64_t)blocks * 4 * 2);
-    ch = ch < 64 ? 64 : (ch > 4096 ? 4096 : ch);
-    ch = (ch + 63) / 64 * 64;
-    A.chunk = (uint32_t)ch;
-    A.chunks_per_energy = (uint32_t)((n_walkers + ch - 1) / ch);
-    A.max_steps = max_steps;
-    A.counter = k.counters;
-    A.tallies = tallies;
-    A.status = k.status;
-    {
-        MCNEGF_TIMED("reset_counter_kernel", s);
-        hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, k.counters);
-    }
-    hipError_t err = hipGetLastError();
+    // energies per launch: the LDS tallies ([energies][5] int64) must fit the 160 KB of a CU
+    constexpr uint32_t kMaxEnergiesPerLaunch = 2048;
+    const size_t max_lds = (size_t)kMaxEnergiesPerLaunch * MCNEGF_TALLY_N * 8;
+    hipError_t err = hipFuncSetAttribute((const void*)walk_kernel,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
     if (err != hipSuccess) return err;
-    const uint64_t waves_needed = (uint64_t)A.nE * A.chunks_per_energy;
-    const uint64_t nb = (waves_needed + 3) / 4;
-    {
-        MCNEGF_TIMED("walk_kernel", s);
-        hipLaunchKernelGGL(walk_kernel, dim3((unsigned)(nb < (uint64_t)blocks ? nb : blocks)),
-                           dim3(256), 0, s, A);
+    for (uint32_t e_off = 0; e_off < (uint32_t)k.nE; e_off += kMaxEnergiesPerLaunch) {
+        WalkArgs A;
+        const uint32_t nE = min((uint32_t)k.nE - e_off, kMaxEnergiesPerLaunch);
+        A.table_stride = (int64_t)k.n_out * k.alias_pitch;
+        A.tables = reinterpret_cast<const uint2*>(k.alias) + (size_t)e_off * A.table_stride;
+        A.pitch = k.alias_pitch;
+        A.n_out = (uint32_t)k.n_out;
+        A.N = (uint32_t)k.N;
+        A.nE = nE;
+        A.e_off = e_off;
+        A.key0 = (uint32_t)(seed & 0xffffffffu);
+        A.key1 = (uint32_t)(seed >> 32);
+        A.tag = tag;
+        A.wbegin = walker_begin;
+        A.wend = walker_begin + n_walkers;
+        // chunk: about four chunks per wavefront of a full grid, 64..4096 walkers
+        const uint64_t total = (uint64_t)n_walkers * nE;
+        const int max_blocks = 2048;  // 8192 wavefronts of 64 lanes
+        uint64_t ch = total / ((uint64_t)max_blocks * 4 * 4);
+        ch = ch < 64 ? 64 : (ch > 4096 ? 4096 : ch);
+        ch = (ch + 63) / 64 * 64;
+        A.chunk = (uint32_t)ch;
+        A.chunks_per_energy = (uint32_t)((n_walkers + ch - 1) / ch);
+        A.max_steps = max_steps;
+        A.tallies = tallies + (size_t)e_off * MCNEGF_TALLY_N;
+        A.status = k.status;
+        const uint64_t waves_needed = (uint64_t)nE * A.chunks_per_energy;
+        const uint64_t nb = (waves_needed + 3) / 4;
+        const size_t lds = (size_t)nE * MCNEGF_TALLY_N * 8;
+        {
+            MCNEGF_TIMED("walk_kernel", s);
+            hipLaunchKernelGGL(walk_kernel,
+                               dim3((unsigned)(nb < (uint64_t)max_blocks ? nb : max_blocks)),
+                               dim3(256), lds, s, A);
+        }
+        if ((err = hipGetLastError()) != hipSuccess) return err;
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 }  // namespace mcnegf

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libmcnegf.so")
 
 # status codes (include/mcnegf.h)
 OK, WTRUNC, WNUMERIC = 0, 1, 2
-EINVAL, EWS, EHIP, ENUMERIC, ENOTIMPL, EDISABLED = -1, -2, -3, -4, -5, -6
+EINVAL, EWS, EHIP, ENUMERIC, ENOTIMPL = -1, -2, -3, -4, -5
 FLAG_NONFINITE, FLAG_SINGULAR, FLAG_ROWSUM, FLAG_NOABSORB, FLAG_TRUNC, FLAG_NOTSPD = (
     0x01, 0x02, 0x04, 0x08, 0x10, 0x20)
 LEAD_NTERMS = 8

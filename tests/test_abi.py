@@ -82,6 +82,15 @@ def test_host_validation_rejects_before_any_gpu_call():
     z = ctypes.c_void_p(0)
     assert lib.mc_negf_build_kernel(ctypes.byref(s), z, z, z, 3, z, 0, ctypes.byref(ks), z) == M.EINVAL
     assert lib.mc_negf_walk(ctypes.byref(ks), 1, 0, 0, 0, 10, 10, z, z) == M.EINVAL
+    # a structurally valid handle with bad walk arguments is still rejected on the host
+    ks.W, ks.L, ks.N, ks.n_out, ks.nE = 2, 3, 6, 8, 1
+    for f in ("alias", "P", "lead", "status", "counters", "reduce"):
+        setattr(ks, f, 4096)
+    t = ctypes.c_void_p(4096)
+    assert lib.mc_negf_walk(ctypes.byref(ks), 1, 0, 2, 0, 10, 10, t, z) == M.EINVAL      # lead
+    assert lib.mc_negf_walk(ctypes.byref(ks), 1, 1 << 30, 0, 0, 10, 10, t, z) == M.EINVAL  # realization
+    assert lib.mc_negf_walk(ctypes.byref(ks), 1, 0, 0, 0, 10, 0, t, z) == M.EINVAL       # max_steps
+    assert lib.mc_negf_walk(ctypes.byref(ks), 1, 0, 0, 1 << 32, 1, 10, t, z) == M.EINVAL  # range
     out = (ctypes.c_double * 2)()
     assert lib.mc_negf_current(ctypes.byref(ks), 0, 0, z, z, z, z,
                                ctypes.cast(out, ctypes.POINTER(ctypes.c_double)), z) == M.EINVAL
@@ -92,16 +101,3 @@ def test_energy_grid_is_midpoint():
     E, w = M.energy_grid(-3.5, 3.5, 256)
     assert abs(E[0] - (-3.5 + 3.5 / 256)) < 1e-15 and abs(E[-1] - (3.5 - 3.5 / 256)) < 1e-15
     assert abs(w.sum() - 7.0) < 1e-12
-
-
-def test_walk_entry_point_reports_disabled_without_launching():
-    # a structurally valid handle (dummy non-null pointers) passes validation; the call
-    # then reports MCNEGF_EDISABLED without touching the GPU
-    lib = M.lib()
-    ks = M.KernelStruct()
-    ks.W, ks.L, ks.N, ks.n_out, ks.nE = 2, 3, 6, 8, 1
-    for f in ("alias", "P", "lead", "status", "counters", "reduce"):
-        setattr(ks, f, 4096)
-    z = ctypes.c_void_p(0)
-    assert lib.mc_negf_walk(ctypes.byref(ks), 1, 0, 0, 0, 10, 10, ctypes.c_void_p(4096), z) == M.EDISABLED
-    assert lib.mc_negf_walk(ctypes.byref(ks), 1, 0, 2, 0, 10, 10, ctypes.c_void_p(4096), z) == M.EINVAL

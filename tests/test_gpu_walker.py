@@ -1,0 +1,157 @@
+"""Walker and Monte Carlo current on the GPU (through the C ABI) against the oracle.
+
+The walker's tallies are integers: on alias tables handed to it, they must equal the
+oracle walker's bit for bit (same Philox streams, bucket rule and thresholds).  MC currents
+must lie within 3 sigma of the oracle's exact value, with the count of per-energy 3-sigma
+exceedances at most the 99.9% binomial quantile.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import dense as D  # noqa: E402
+from oracle import walker as OW  # noqa: E402
+from paper_1805_10164_amd import inputs  # noqa: E402
+from paper_1805_10164_amd import mcnegf as M  # noqa: E402
+from test_gpu_parity import DEV, SEED, case, gpu_build, oracle_solve, single_site, chain_case  # noqa: E402
+
+
+def oracle_alias_tables(sols, pitch):
+    n = sols[0].N + 2
+    thr = np.zeros((len(sols), n, pitch), np.uint32)
+    al = np.zeros((len(sols), n, pitch), np.int32)
+    for e, s in enumerate(sols):
+        K = s.transition_kernel()
+        for r in range(n):
+            thr[e, r, :n], al[e, r, :n] = D.alias_vose(K[r])
+    return thr, al
+
+
+@pytest.mark.parametrize("inject", [0, 1])
+def test_walker_bit_exact_on_given_tables(inject):
+    # The GPU walker on alias tables built by the oracle must reproduce the oracle walker's
+    # integer tallies exactly (same Philox streams, same bucket and threshold rule).
+    c = case(W=3, L=4, eta=0.3, disorder=0.3, nE=3, emin=-1.5, emax=1.5)
+    k = gpu_build(c)
+    sols = oracle_solve(c)
+    thr, al = oracle_alias_tables(sols, k.alias_pitch)
+    tab = k.alias_table()
+    packed = np.stack([thr.view(np.int32), al], axis=-1)
+    tab.copy_(torch.from_numpy(packed).to(DEV))
+    nw = 50_000
+    tal = torch.zeros((3, 5), dtype=torch.int64, device=DEV)
+    M.mc_negf_walk(k, SEED, 7, inject, 1000, nw, 1_000_000, tal)
+    ref = OW.walk_alias(thr, al, SEED, 7, inject, 1000, nw)
+    assert (tal.cpu().numpy() == ref).all()
+
+
+def test_walker_truncation_and_max_steps():
+    c = case(W=2, L=6, eta=0.5, disorder=0.2, nE=2, emin=-1.0, emax=1.0)
+    k = gpu_build(c)
+    sols = oracle_solve(c)
+    thr, al = oracle_alias_tables(sols, k.alias_pitch)
+    k.alias_table().copy_(torch.from_numpy(np.stack([thr.view(np.int32), al], -1)).to(DEV))
+    tal = torch.zeros((2, 5), dtype=torch.int64, device=DEV)
+    M.mc_negf_walk(k, 11, 0, 0, 0, 20_000, 2, tal)
+    ref = OW.walk_alias(thr, al, 11, 0, 0, 0, 20_000, max_steps=2)
+    assert (tal.cpu().numpy() == ref).all() and ref[:, 2].sum() > 0
+    w = torch.tensor(c["w"], dtype=torch.float64, device=DEV)
+    T = torch.empty(2, dtype=torch.float64, device=DEV)
+    sg = torch.empty(2, dtype=torch.float64, device=DEV)
+    st, _, _ = M.mc_negf_current(k, 0, 0, tal, w, T, sg)
+    assert st == M.WTRUNC
+
+
+def test_walker_split_ranges_and_determinism():
+    c = case(W=4, L=6, eta=0.1, disorder=0.3, nE=4, emin=-2.0, emax=2.0)
+    k = gpu_build(c)
+    a = torch.zeros((4, 5), dtype=torch.int64, device=DEV)
+    b = torch.zeros_like(a)
+    d = torch.zeros_like(a)
+    M.mc_negf_walk(k, 5, 2, 0, 0, 100_000, 1_000_000, a)
+    M.mc_negf_walk(k, 5, 2, 0, 0, 37_001, 1_000_000, b)
+    M.mc_negf_walk(k, 5, 2, 0, 37_001, 100_000 - 37_001, 1_000_000, b)
+    M.mc_negf_walk(k, 5, 2, 0, 0, 100_000, 1_000_000, d)
+    assert torch.equal(a, b) and torch.equal(a, d)
+    assert int(a[:, :3].sum()) == 4 * 100_000
+
+
+def mc_run(c, k, n_walkers, inject=0, seed=SEED):
+    nE = len(c["E"])
+    tal = torch.zeros((nE, 5), dtype=torch.int64, device=DEV)
+    M.mc_negf_walk(k, seed, 0, inject, 0, n_walkers, 1_000_000, tal)
+    w = torch.tensor(c["w"], dtype=torch.float64, device=DEV)
+    T = torch.empty(nE, dtype=torch.float64, device=DEV)
+    sg = torch.empty(nE, dtype=torch.float64, device=DEV)
+    st, I, sI = M.mc_negf_current(k, 0, inject, tal, w, T, sg)
+    return st, I, sI, T.cpu().numpy(), sg.cpu().numpy(), tal.cpu().numpy()
+
+
+def binom_quantile_999(n, p=0.0027):
+    from scipy.stats import binom
+    return int(binom.ppf(0.999, n, p))
+
+
+@pytest.mark.parametrize("inject", [0, 1])
+def test_mc_current_within_3_sigma(inject):
+    c = case(W=4, L=10, eta=0.08, disorder=0.3, nE=24, emin=-3.2, emax=3.2)
+    k = gpu_build(c)
+    sols = oracle_solve(c)
+    st, I, sI, T, sg, tal = mc_run(c, k, 200_000, inject)
+    assert st == M.OK
+    Tref = np.array([s.T_eff for s in sols])
+    Iref = D.current(sols, c["w"])
+    assert abs(I - Iref) <= 3 * sI
+    exceed = int(np.sum(np.abs(T - Tref) > 3 * sg))
+    assert exceed <= binom_quantile_999(len(Tref))
+
+
+def test_single_site_closed_form_mc():
+    c, ref = single_site()
+    k = gpu_build(c)
+    st, I, sI, Tm, sgm, _ = mc_run(c, k, 400_000)
+    assert (np.abs(Tm - ref) < 4 * sgm).all()
+
+
+def test_clean_chain_eta0_mc():
+    c = case(W=1, L=50, eta=0.0, disorder=0.0, nE=8, emin=-1.9, emax=1.9)
+    k = gpu_build(c)
+    st, I, sI, Tm, sgm, tal = mc_run(c, k, 100_000)
+    # every walker leaves at once; half of them into R (c_L = 2)
+    assert (tal[:, 3] == 100_000).all()
+    assert (np.abs(Tm - 1.0) < 4 * sgm).all()
+
+
+def test_full_size_chain_mc():
+    wl, c = chain_case()
+    k = gpu_build(c)
+    sols = oracle_solve(c)
+    st, I, sI, T, sg, tal = mc_run(c, k, wl.walkers_per_energy)
+    Iref = D.current(sols, c["w"])
+    assert abs(I - Iref) <= 3 * sI
+    Tref = np.array([s.T_eff for s in sols])
+    assert int(np.sum(np.abs(T - Tref) > 3 * sg)) <= binom_quantile_999(len(Tref))
+
+
+def test_outside_band_walkers_exit_at_once():
+    c = case(W=1, L=5, eta=0.1, disorder=0.0, nE=2, emin=2.2, emax=2.6)
+    k = gpu_build(c)
+    st, I, sI, Tm, sgm, tal = mc_run(c, k, 1000)
+    assert (Tm == 0).all() and (tal[:, 0] == 1000).all() and (tal[:, 3] == 1000).all()
+
+
+def test_more_energies_than_one_launch_holds():
+    # 2100 energies are walked in two launches (LDS tallies hold 2048 energies); the streams
+    # are keyed by the global energy index, so the oracle walker on the same tables agrees.
+    c = case(W=1, L=3, eta=0.2, disorder=0.0, nE=2100, emin=-1.5, emax=1.5)
+    k = gpu_build(c)
+    sols = oracle_solve(c)
+    thr, al = oracle_alias_tables(sols, k.alias_pitch)
+    k.alias_table().copy_(torch.from_numpy(np.stack([thr.view(np.int32), al], -1)).to(DEV))
+    tal = torch.zeros((2100, 5), dtype=torch.int64, device=DEV)
+    M.mc_negf_walk(k, 3, 1, 0, 5, 200, 1_000_000, tal)
+    ref = OW.walk_alias(thr, al, 3, 1, 0, 5, 200)
+    assert (tal.cpu().numpy() == ref).all()
