@@ -23,6 +23,7 @@ FLAG_NONFINITE, FLAG_SINGULAR, FLAG_ROWSUM, FLAG_NOABSORB, FLAG_TRUNC, FLAG_NOTS
 LEAD_NTERMS = 8
 LEAD_TLL, LEAD_TRL, LEAD_TLR, LEAD_TRR, LEAD_CL, LEAD_CR, LEAD_TRGLA, LEAD_TRGRA = range(8)
 TALLY_N = 5
+TALLY_EXIT_L, TALLY_EXIT_R, TALLY_TRUNC, TALLY_STEPS, TALLY_STEPS2 = range(5)
 EXPORTED = ("mc_negf_workspace_bytes", "mc_negf_build_kernel", "mc_negf_walk",
             "mc_negf_current", "mc_negf_grad", "mc_negf_profile_begin", "mc_negf_profile_end",
             "mc_negf_status", "mc_negf_last_hip_error", "mc_negf_version")
