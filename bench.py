@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--etas", type=str, default=None, help="comma-separated dephasing rates")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttp", action="store_true", help="skip the time-to-1%% measurement")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="before the timed steps, run one plain device copy of this many MiB "
+                         "(reference dispatch for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -84,15 +87,14 @@ def kernel_work(name, wl, walk_steps):
     if name == "walk_kernel":
         return "hbm", walk_steps * ALIAS_ENTRY_BYTES / 1e9, "GB"
     if name == "cholesky_kernel":
-        return "alu", nE * (N ** 3 / 3.0) / 1e12, "TFLOP"
+        # factorization N^3/3 plus the two forward substitutions of the bordered rows, 2 N^2
+        return "mfma", nE * (N ** 3 / 3.0 + 2.0 * N * N) / 1e12, "TFLOP"
     if name == "fullinv_kernel":
         # two sweeps per column slice: L*(L-1) complex W x W block products per energy
         return "alu", nE * 8.0 * W ** 3 * wl.L * (wl.L - 1) / 1e12, "TFLOP"
     if name == "alias_build_kernel":
         # read gamma_i |G_ji|^2 rows and write one 8-byte alias entry per outcome
         return "hbm", nE * (8.0 * N * N + 8.0 * n * n) / 1e9, "GB"
-    if name == "direct_fill_kernel":
-        return "hbm", nE * 16.0 * N * N / 1e9, "GB"
     return None
 
 
@@ -107,6 +109,7 @@ def roofline(name, wl, ms_per_launch, walk_steps):
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                 "algorithmic_per_launch": amount * 1e9, "avg_launch_ms": ms_per_launch}
     achieved = amount / (ms_per_launch * 1e-3)
+    # gfx950's FP64 matrix-core peak equals its FP64 vector FMA peak
     return {"kernel": name, "bound": bound, "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
             "algorithmic_per_launch": amount * 1e12, "avg_launch_ms": ms_per_launch}
@@ -201,6 +204,14 @@ def main():
         for p in probs:
             run_step(p, walkers, seed, walk_on)
     torch.cuda.synchronize()
+    if args.calib_copy_mb > 0:
+        n = args.calib_copy_mb * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)  # reads and writes n * 8 bytes
+        torch.cuda.synchronize()
+        del src, dst
 
     steps_total = 0
     results = []

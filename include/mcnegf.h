@@ -127,7 +127,8 @@ typedef struct mcnegf_kernel {
     double*   gR;           /* [nE][L][W][W] complex: right-connected blocks               */
     double*   Gd;           /* [nE][L][W][W] complex: diagonal blocks G_kk                  */
     double*   corner;       /* [nE][2][W][W] complex: G_{L-1,0} and G_{0,L-1}              */
-    double*   direct;       /* [nE][N][p_pitch] probe-system scratch (DIRECT mode)          */
+    double*   direct;       /* [nE][p_pitch+2][p_pitch] Cholesky factor of the bordered     */
+                            /* scaled probe system (DIRECT mode), lower part                */
     double*   direct_vec;   /* [nE][4][N] scratch vectors (DIRECT mode)                    */
     double*   reduce;       /* [nE + 8] scratch for current reductions                     */
     uint32_t* status;       /* device status word (MCNEGF_FLAG_* bits)                     */

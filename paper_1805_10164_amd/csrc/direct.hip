@@ -8,8 +8,11 @@
 //   gamma_j A_jj n_j - sum_i T_ji n_i = T_jp   (f_p = 1, f_q = 0),  T_ji = gamma_j gamma_i |G_ji|^2,
 // a symmetric, weakly diagonally dominant system with positive diagonal (its row sums are
 // the probe's couplings to the leads), so Cholesky without pivoting applies.  It is solved
-// in the symmetrically scaled form S M S with S = diag(M_jj^{-1/2}); probes with
-// gamma_j = 0 decouple (identity row).  Then T_k = T_qp + sum_j T_qj n_j.
+// in the symmetrically scaled form S M S = L L^T with S = diag(M_jj^{-1/2}); probes with
+// gamma_j = 0 decouple (identity row).  Then
+//   T_k = T_qp + sum_j T_qj n_j = T_qp + (L^{-1} S T_q) . (L^{-1} S T_p),
+// so only forward substitutions are needed; they come out of the factorization itself when
+// the two vectors (S T_p)^T and (S T_q)^T are appended below the matrix as two extra rows.
 // Current: I = sum_k w_k T_k (midpoint quadrature, Sec. III C), sigma_I^2 = sum_k w_k^2 sigma_k^2.
 #include "common.h"
 
@@ -86,7 +89,10 @@ hipError_t launch_mc_current(const mcnegf_kernel& k, uint32_t inject_lead, const
 }
 
 // ---------------------------------------------------------------- DIRECT
-// vec layout per energy: [0] scale s_j, [1] right-hand side (scaled), [2] solution, [3] T_qj
+// vec layout per energy: [0] u_j = gamma_j s_j, [1] u_j w_p(j), [2] u_j w_q(j), [3] T_qj,
+// with s_j = M_jj^{-1/2} (0 for a decoupled probe) and w_p, w_q the exit weights of the
+// injecting and the collecting lead.  Scaled matrix: 1 on the diagonal, -u_i u_j |G_ij|^2 off it;
+// scaled right-hand sides: u_j w_p(j) and u_j w_q(j).
 __global__ void direct_prep_kernel(const double* __restrict__ P, const double* __restrict__ Adiag,
                                    const double* __restrict__ wL, const double* __restrict__ wR,
                                    const double* __restrict__ gamma, int N, int64_t ldP,
@@ -100,204 +106,380 @@ __global__ void direct_prep_kernel(const double* __restrict__ P, const double* _
     const double sj = (g > 0.0 && mjj > 0.0) ? 1.0 / sqrt(mjj) : 0.0;
     const double wp = inject_lead == 0 ? wL[(size_t)e * N + j] : wR[(size_t)e * N + j];
     const double wq = inject_lead == 0 ? wR[(size_t)e * N + j] : wL[(size_t)e * N + j];
+    const double u = g * sj;
     double* v = vec + (size_t)e * 4 * N;
-    v[j] = sj;
-    v[N + j] = g * wp * sj;
+    v[j] = u;
+    v[N + j] = u * wp;
+    v[2 * N + j] = u * wq;
     v[3 * N + j] = g * wq;
 }
 
-__global__ void __launch_bounds__(256) direct_fill_kernel(const double* __restrict__ P,
-                                                          const double* __restrict__ gamma,
-                                                          const double* __restrict__ vec, int N,
-                                                          int64_t ld, double* __restrict__ M) {
-    const int e = blockIdx.y;
-    const int i = blockIdx.x;
-    const double* sv = vec + (size_t)e * 4 * N;
-    const double si = sv[i];
-    const double gi = gamma[i];
-    const double* Pr = P + ((size_t)e * N + i) * ld;
-    double* Mr = M + ((size_t)e * N + i) * ld;
-    for (int j = threadIdx.x; j < N; j += blockDim.x) {
-        double m;
-        if (si == 0.0 || sv[j] == 0.0) m = (i == j) ? 1.0 : 0.0;
-        else if (i == j) m = 1.0;
-        else m = -gi * gamma[j] * Pr[j] * si * sv[j];
-        Mr[j] = m;
+// ---- Left-looking blocked Cholesky of the bordered probe system on FP64 matrix cores.
+//
+// Per energy, logical rows 0..Np-1 are the scaled matrix padded with identity rows up to
+// Np = round_up(N, 16), rows Np and Np+1 are the two scaled right-hand sides; columns
+// 0..Np-1 are factored.  Block column J (columns c0 = 64 J .. c0 + wJ - 1):
+//   V  = A[c0:, J] - L[c0:, 0:c0] L[J, 0:c0]^T      (update, MFMA)
+//   L_JJ = chol(V_JJ),  Z = L_JJ^{-1}                (one wavefront, lane per row / column)
+//   L[below, J] = V_below L_JJ^{-T}   computed as (Z V_below^T)^T   (MFMA)
+// After the last block column, rows Np and Np+1 of L hold L^{-1} S T_p and L^{-1} S T_q.
+// One workgroup of 8 wavefronts per energy; each wavefront owns two 16-row tiles of a
+// 256-row super-tile and keeps their 16 x 64 updates in accumulators.  Block-column rows
+// L[J, 0:c0] are staged through LDS in 64-wide K chunks and serve as the MFMA A operand;
+// the tile rows stream from global memory as the B operand, so the accumulator holds the
+// transposed update, which is directly the B operand of the triangular-solve product.
+// v_mfma_f64_16x16x4f64 operand layouts (lane l, g = l / 16, n = l % 16):
+//   A[m][k]: m = n, k = g;   B[k][c]: k = g, c = n;   D[i][c] (item r): i = 4 r + g, c = n.
+// A lane's four accumulator items are therefore the columns 4 r + g of a 16-column block.
+// Rows of L are stored with the columns of every 16-column block permuted so that these
+// four items are contiguous (logical column 4 r + g at position 4 g + r, an involution):
+// the update contracts over stored positions of two rows of L, which any common column
+// permutation leaves unchanged, and the two bordered rows enter only through their dot
+// product, which it leaves unchanged too.
+typedef double dmfma4 __attribute__((ext_vector_type(4)));
+
+constexpr int CH_NB = 64;            // block-column width
+constexpr int CH_KC = 64;            // K chunk staged in LDS
+constexpr int CH_BP = CH_KC + 4;     // LDS pitch of a staged row (doubles)
+constexpr int CH_VP = CH_NB + 1;     // LDS pitch of the diagonal block
+constexpr int CH_WAVES = 8;
+constexpr int CH_ROWS = CH_WAVES * 32;  // rows per super-tile
+
+struct CholArgs {
+    const double* P;      // [nE][N][ld] |G_ij|^2
+    const double* vec;    // [nE][4][N]
+    const double* lead;   // [nE][8]
+    double* Lall;         // [nE][Np + 2][ld]
+    double* T;
+    double* sig;
+    uint32_t* status;
+    int N, Np;
+    int64_t ld;
+    uint32_t inject_lead;
+};
+
+__device__ inline double readlane_f64(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Entries (i, c + 4 r), r = 0..3, of the bordered scaled matrix (lower part, c + 12 < Np).
+__device__ inline void aorig4(const CholArgs& a, const double* Pe, const double* ve, int i, int c,
+                              double (&out)[4]) {
+    const int N = a.N;
+    if (i < N) {
+        const double* Pr = Pe + (size_t)i * a.ld;
+        const double ui = ve[i];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = c + 4 * r;
+            const double uj = j < N ? ve[j] : 0.0;
+            const double pij = Pr[j];
+            out[r] = (j == i) ? 1.0 : (j < N ? -ui * uj * pij : 0.0);
+        }
+    } else if (i < a.Np) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[r] = (c + 4 * r == i) ? 1.0 : 0.0;
+    } else if (i < a.Np + 2) {
+        const double* rhs = ve + (size_t)(i - a.Np + 1) * N;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[r] = (c + 4 * r < N) ? rhs[c + 4 * r] : 0.0;
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[r] = 0.0;
     }
 }
 
-constexpr int NB = 32;
-
-// Right-looking blocked Cholesky (lower) of one energy's N x N matrix, one workgroup.
-__global__ void __launch_bounds__(256) cholesky_kernel(double* __restrict__ Mall, int N, int64_t ld,
-                                                       uint32_t* __restrict__ status) {
-    __shared__ double D[NB][NB + 1];
-    __shared__ double Pa[NB][NB + 1];
-    __shared__ double Pb[NB][NB + 1];
-    __shared__ int bad;
-    double* A = Mall + (size_t)blockIdx.x * N * ld;
-    const int tid = threadIdx.x;
-    const int nt = (N + NB - 1) / NB;
-    if (tid == 0) bad = 0;
-    for (int jb = 0; jb < nt; ++jb) {
-        const int j0 = jb * NB;
-        const int jn = min(NB, N - j0);
-        for (int idx = tid; idx < NB * NB; idx += 256) {
-            const int r = idx / NB, c = idx % NB;
-            D[r][c] = (r < jn && c < jn) ? A[(size_t)(j0 + r) * ld + j0 + c] : (r == c ? 1.0 : 0.0);
-        }
-        __syncthreads();
-        for (int c = 0; c < NB; ++c) {
-            if (tid == 0) {
-                double d = D[c][c];
-                if (!(d > 0.0)) {
-                    bad = 1;
-                    d = 1.0;
-                }
-                D[c][c] = sqrt(d);
-            }
-            __syncthreads();
-            if (tid > c && tid < NB) D[tid][c] /= D[c][c];
-            __syncthreads();
-            for (int idx = tid; idx < NB * NB; idx += 256) {
-                const int r = idx / NB, q = idx % NB;
-                if (r > c && q > c && q <= r) D[r][q] -= D[r][c] * D[q][c];
-            }
-            __syncthreads();
-        }
-        for (int idx = tid; idx < NB * NB; idx += 256) {
-            const int r = idx / NB, c = idx % NB;
-            if (r < jn && c < jn && c <= r) A[(size_t)(j0 + r) * ld + j0 + c] = D[r][c];
-        }
-        // panel below: X D^T = A_panel, one row per thread
-        for (int i = j0 + NB + tid; i < N; i += 256) {
-            double x[NB];
-            double* Ar = A + (size_t)i * ld + j0;
-#pragma unroll
-            for (int c = 0; c < NB; ++c) x[c] = (c < jn) ? Ar[c] : 0.0;
-#pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                x[c] = x[c] / D[c][c];
-#pragma unroll
-                for (int q = c + 1; q < NB; ++q) x[q] = fma(-x[c], D[q][c], x[q]);
-                __asm__ volatile("" ::: "memory");  // keep the LDS reads of column c here
-            }
-#pragma unroll
-            for (int c = 0; c < NB; ++c)
-                if (c < jn) Ar[c] = x[c];
-        }
-        __threadfence_block();
-        __syncthreads();
-        // trailing update A[ib][kb] -= P_ib P_kb^T for jb < kb <= ib
-        const int tr = tid / 16, tc = tid % 16;  // 2x2 outputs per thread
-        for (int ib = jb + 1; ib < nt; ++ib) {
-            const int i0 = ib * NB;
-            const int in_ = min(NB, N - i0);
-            for (int idx = tid; idx < NB * NB; idx += 256) {
-                const int r = idx / NB, c = idx % NB;
-                Pa[r][c] = (r < in_ && c < jn) ? A[(size_t)(i0 + r) * ld + j0 + c] : 0.0;
-            }
-            for (int kb = jb + 1; kb <= ib; ++kb) {
-                const int k0 = kb * NB;
-                const int kn = min(NB, N - k0);
-                for (int idx = tid; idx < NB * NB; idx += 256) {
-                    const int r = idx / NB, c = idx % NB;
-                    Pb[r][c] = (r < kn && c < jn) ? A[(size_t)(k0 + r) * ld + j0 + c] : 0.0;
-                }
-                __syncthreads();
-                double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-#pragma unroll 8
-                for (int q = 0; q < NB; ++q) {
-                    const double a0 = Pa[2 * tr][q], a1 = Pa[2 * tr + 1][q];
-                    const double b0 = Pb[2 * tc][q], b1 = Pb[2 * tc + 1][q];
-                    acc[0][0] = fma(a0, b0, acc[0][0]);
-                    acc[0][1] = fma(a0, b1, acc[0][1]);
-                    acc[1][0] = fma(a1, b0, acc[1][0]);
-                    acc[1][1] = fma(a1, b1, acc[1][1]);
-                }
-#pragma unroll
-                for (int u = 0; u < 2; ++u)
-#pragma unroll
-                    for (int v = 0; v < 2; ++v) {
-                        const int r = 2 * tr + u, c = 2 * tc + v;
-                        if (r < in_ && c < kn) A[(size_t)(i0 + r) * ld + k0 + c] -= acc[u][v];
-                    }
-                __syncthreads();
-            }
-        }
-        __threadfence_block();
-        __syncthreads();
+// Staging of a block-column row segment (8 doubles at column col) through registers into LDS.
+__device__ inline void stage_load(const double* Le, int64_t ld, int R, int row, int col,
+                                  double4 (&b)[2]) {
+    if (row < R) {
+        const double* src = Le + (size_t)row * ld + col;
+        b[0] = *reinterpret_cast<const double4*>(src);
+        b[1] = *reinterpret_cast<const double4*>(src + 4);
+    } else {
+        b[0] = double4{0, 0, 0, 0};
+        b[1] = double4{0, 0, 0, 0};
     }
-    if (tid == 0 && bad) atomicOr(status, MCNEGF_FLAG_NOTSPD);
 }
 
-// Forward and backward substitution with the Cholesky factor, then T_k.
-__global__ void __launch_bounds__(256) chol_solve_kernel(const double* __restrict__ Mall, int N,
-                                                         int64_t ld, double* __restrict__ vec,
-                                                         const double* __restrict__ lead,
-                                                         uint32_t inject_lead, double* __restrict__ T,
-                                                         double* __restrict__ sig,
-                                                         uint32_t* __restrict__ status) {
-    extern __shared__ double y[];
-    __shared__ double red[256];
+__device__ inline void stage_store(double* Bs, int sm, int sc, const double4 (&b)[2]) {
+    *reinterpret_cast<double4*>(&Bs[sm * CH_BP + sc]) = b[0];
+    *reinterpret_cast<double4*>(&Bs[sm * CH_BP + sc + 4]) = b[1];
+}
+
+// One wavefront: L_JJ = chol(V) for the wJ x wJ lower part of V (LDS, pitch CH_VP, logical
+// column order), written to Ls (identity outside wJ) and to global rows of L (Lg, pitch ld, in
+// the stored column order); then Z = L_JJ^{-1} into V.
+// The LDS arguments carry the LDS address space so that every access is a DS instruction: the
+// lanes exchange rows and columns through LDS, which a wavefront's DS instructions see in
+// program order (generic pointers would turn them into FLAT accesses, which give no such order).
+typedef __attribute__((address_space(3))) double lds_double;
+typedef __attribute__((address_space(3))) int lds_int;
+
+__device__ __noinline__ void factor_diag_block(lds_double* VZs, lds_double* Ls, lds_double* colbuf,
+                                               double* Lg, int64_t ld, int wJ, int lane,
+                                               lds_int* bad_flag) {
+    // lane i holds row i; column k is shared through LDS
+    const int i = lane;
+    double rw[CH_NB];
+#pragma unroll
+    for (int j = 0; j < CH_NB; ++j) rw[j] = (i < wJ && j < wJ && j <= i) ? VZs[i * CH_VP + j] : 0.0;
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < CH_NB; ++k) {
+        if (k < wJ) {
+            double piv = readlane_f64(rw[k], k);
+            const bool good = piv > 0.0 && isfinite(piv);
+            bad |= !good;
+            piv = good ? piv : 1.0;
+            const double d = sqrt(piv);
+            const double lik = (i >= k) ? rw[k] / d : 0.0;
+            rw[k] = lik;
+            colbuf[i] = lik;
+#pragma unroll
+            for (int j = k + 1; j < CH_NB; ++j) {
+                if (j < wJ) rw[j] = fma(-lik, colbuf[j], rw[j]);
+            }
+        }
+    }
+    if (bad && lane == 0) *bad_flag = 1;
+#pragma unroll
+    for (int j = 0; j < CH_NB; ++j) {
+        const double lv = (j <= i && i < wJ) ? rw[j] : (i == j ? 1.0 : 0.0);
+        Ls[i * CH_VP + j] = lv;
+        if (j <= i && i < wJ) Lg[(size_t)i * ld + (j & ~15) + 4 * (j & 3) + ((j >> 2) & 3)] = lv;
+    }
+    // Z = L_JJ^{-1}: lane = column j, forward substitution down the rows (Ls was written by
+    // this wavefront, whose LDS accesses stay in order)
+    const int j = lane;
+    double z[CH_NB];
+#pragma unroll
+    for (int r = 0; r < CH_NB; ++r) {
+        double s = (r == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int m = 0; m < r; ++m) s = fma(-Ls[r * CH_VP + m], z[m], s);
+        z[r] = s / Ls[r * CH_VP + r];
+    }
+#pragma unroll
+    for (int r = 0; r < CH_NB; ++r) VZs[r * CH_VP + j] = z[r];
+}
+
+__global__ void __launch_bounds__(512) cholesky_kernel(CholArgs a) {
+    __shared__ double Bs[CH_NB * CH_BP];
+    __shared__ double VZs[CH_NB * CH_VP];  // diagonal block V, then Z = L_JJ^{-1}
+    __shared__ double Ls[CH_NB * CH_VP];   // L_JJ
+    __shared__ double colbuf[CH_NB];
+    __shared__ double dot_acc;
+    __shared__ int bad_flag;
+
     const int e = blockIdx.x;
-    const double* A = Mall + (size_t)e * N * ld;
-    double* v = vec + (size_t)e * 4 * N;
     const int tid = threadIdx.x;
-    const int nt = (N + NB - 1) / NB;
-    for (int i = tid; i < N; i += 256) y[i] = v[N + i];
-    __syncthreads();
-    // L y = b
-    for (int jb = 0; jb < nt; ++jb) {
-        const int j0 = jb * NB, jn = min(NB, N - j0);
-        if (tid == 0) {
-            for (int c = 0; c < jn; ++c) {
-                double acc = y[j0 + c];
-                for (int q = 0; q < c; ++q) acc -= A[(size_t)(j0 + c) * ld + j0 + q] * y[j0 + q];
-                y[j0 + c] = acc / A[(size_t)(j0 + c) * ld + j0 + c];
-            }
-        }
-        __syncthreads();
-        for (int i = j0 + jn + tid; i < N; i += 256) {
-            double acc = 0.0;
-            for (int q = 0; q < jn; ++q) acc += A[(size_t)i * ld + j0 + q] * y[j0 + q];
-            y[i] -= acc;
-        }
-        __syncthreads();
-    }
-    // L^T x = y
-    for (int jb = nt - 1; jb >= 0; --jb) {
-        const int j0 = jb * NB, jn = min(NB, N - j0);
-        if (tid == 0) {
-            for (int c = jn - 1; c >= 0; --c) {
-                double acc = y[j0 + c];
-                for (int q = c + 1; q < jn; ++q) acc -= A[(size_t)(j0 + q) * ld + j0 + c] * y[j0 + q];
-                y[j0 + c] = acc / A[(size_t)(j0 + c) * ld + j0 + c];
-            }
-        }
-        __syncthreads();
-        for (int r = tid; r < j0; r += 256) {
-            double acc = 0.0;
-            for (int q = 0; q < jn; ++q) acc += A[(size_t)(j0 + q) * ld + r] * y[j0 + q];
-            y[r] -= acc;
-        }
-        __syncthreads();
-    }
-    // n_j = s_j x_j;  T = T_qp + sum_j T_qj n_j
-    double part = 0.0;
-    for (int i = tid; i < N; i += 256) {
-        const double nj = v[i] * y[i];
-        v[2 * N + i] = nj;
-        part += v[3 * N + i] * nj;
-    }
-    const double sum = block_reduce256(part, red);
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int ln = lane & 15;
+    const int g = lane >> 4;
+    const int cq = 4 * g;
+    const int Np = a.Np;
+    const int R = Np + 2;
+    const int64_t ld = a.ld;
+    const double* Pe = a.P + (size_t)e * a.N * ld;
+    const double* ve = a.vec + (size_t)e * 4 * a.N;
+    double* Le = a.Lall + (size_t)e * R * ld;
     if (tid == 0) {
-        const double* ld_ = lead + (size_t)e * MCNEGF_LEAD_NTERMS;
-        const double tqp = inject_lead == 0 ? ld_[MCNEGF_LEAD_TRL] : ld_[MCNEGF_LEAD_TLR];
-        const double Tk = tqp + sum;
-        T[e] = Tk;
-        sig[e] = 0.0;
-        if (!isfinite(Tk)) atomicOr(status, MCNEGF_FLAG_NONFINITE);
+        dot_acc = 0.0;
+        bad_flag = 0;
+    }
+    // staging assignment: row sm of the block column, 8 doubles at column sc
+    const int sm = tid >> 3;
+    const int sc = (tid & 7) * 8;
+
+    const int nJ = (Np + CH_NB - 1) / CH_NB;
+    for (int J = 0; J < nJ; ++J) {
+        const int c0 = J * CH_NB;
+        const int wJ = min(CH_NB, Np - c0);
+        const int ncb = wJ >> 4;
+        // rows of L written below the previous diagonal block (by any wavefront) are read next
+        __syncthreads();
+
+        // ---- diagonal block: V_JJ = A_JJ - L[J, 0:c0] L[J, 0:c0]^T, both operands from LDS.
+        // Wavefront w owns the 16 x 16 blocks p = w and p = w + 8 (block row p / 4, column p % 4).
+        {
+            dmfma4 accd[2] = {dmfma4{0.0, 0.0, 0.0, 0.0}, dmfma4{0.0, 0.0, 0.0, 0.0}};
+            double4 bstage[2];
+            if (c0 > 0) stage_load(Le, ld, R, c0 + sm, sc, bstage);
+            for (int kc = 0; kc < c0; kc += CH_KC) {
+                __syncthreads();
+                stage_store(Bs, sm, sc, bstage);
+                if (kc + CH_KC < c0) stage_load(Le, ld, R, c0 + sm, kc + CH_KC + sc, bstage);
+                __syncthreads();
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int p = wave + 8 * h;
+                    const int tb = p >> 2, cb = p & 3;
+                    if (cb <= tb && tb < ncb) {
+#pragma unroll
+                        for (int kg = 0; kg < 4; ++kg) {
+                            const double4 av = *reinterpret_cast<const double4*>(
+                                &Bs[(16 * cb + ln) * CH_BP + 16 * kg + cq]);
+                            const double4 bv = *reinterpret_cast<const double4*>(
+                                &Bs[(16 * tb + ln) * CH_BP + 16 * kg + cq]);
+                            accd[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, accd[h], 0, 0, 0);
+                            accd[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.y, accd[h], 0, 0, 0);
+                            accd[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.z, bv.z, accd[h], 0, 0, 0);
+                            accd[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.w, bv.w, accd[h], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int p = wave + 8 * h;
+                const int tb = p >> 2, cb = p & 3;
+                if (cb <= tb && tb < ncb) {
+                    double ao[4];
+                    aorig4(a, Pe, ve, c0 + 16 * tb + ln, c0 + 16 * cb + g, ao);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        VZs[(16 * tb + ln) * CH_VP + 16 * cb + 4 * r + g] = ao[r] - accd[h][r];
+                }
+            }
+        }
+        __syncthreads();
+        if (wave == 0)
+            factor_diag_block((lds_double*)VZs, (lds_double*)Ls, (lds_double*)colbuf,
+                              Le + (size_t)c0 * ld + c0, ld, wJ, lane, (lds_int*)&bad_flag);
+        __syncthreads();
+
+        // ---- rows below the diagonal block, in super-tiles of 256 rows
+        for (int st = c0 + wJ; st < R; st += CH_ROWS) {
+            const int r0 = st + wave * 32;  // this wave's rows r0 .. r0 + 31
+            dmfma4 acc[2][4];
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) acc[t][cb] = dmfma4{0.0, 0.0, 0.0, 0.0};
+
+            // update: acc^T = L[tile rows, 0:c0] . L[J rows, 0:c0]^T
+            double4 bstage[2];
+            if (c0 > 0) stage_load(Le, ld, R, c0 + sm, sc, bstage);
+            for (int kc = 0; kc < c0; kc += CH_KC) {
+                double4 av[2][4];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int row = r0 + 16 * t + ln;
+                    const bool ok = row < R;
+                    const double* src = Le + (size_t)(ok ? row : 0) * ld + kc + cq;
+#pragma unroll
+                    for (int kg = 0; kg < 4; ++kg)
+                        av[t][kg] = ok ? *reinterpret_cast<const double4*>(src + 16 * kg)
+                                       : double4{0, 0, 0, 0};
+                }
+                __syncthreads();
+                stage_store(Bs, sm, sc, bstage);
+                if (kc + CH_KC < c0) stage_load(Le, ld, R, c0 + sm, kc + CH_KC + sc, bstage);
+                __syncthreads();
+                if (r0 < R) {
+#pragma unroll
+                    for (int kg = 0; kg < 4; ++kg) {
+                        double4 bf[4];
+#pragma unroll
+                        for (int cb = 0; cb < 4; ++cb)
+                            bf[cb] = *reinterpret_cast<const double4*>(
+                                &Bs[(16 * cb + ln) * CH_BP + 16 * kg + cq]);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                            for (int t = 0; t < 2; ++t) {
+                                const double bv = q == 0 ? av[t][kg].x
+                                                : q == 1 ? av[t][kg].y
+                                                : q == 2 ? av[t][kg].z
+                                                         : av[t][kg].w;
+#pragma unroll
+                                for (int cb = 0; cb < 4; ++cb) {
+                                    if (cb < ncb) {
+                                        const double aval = q == 0 ? bf[cb].x
+                                                            : q == 1 ? bf[cb].y
+                                                            : q == 2 ? bf[cb].z
+                                                                     : bf[cb].w;
+                                        acc[t][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                            aval, bv, acc[t][cb], 0, 0, 0);
+                                    }
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+            // V = A - update (lane: row r0 + 16 t + ln, columns c0 + 16 cb + 4 r + g), then
+            // X^T = Z V^T, stored as rows of L
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int rt = r0 + 16 * t;
+                if (rt < R) {
+                    double v[4][4];
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb) {
+                        double ao[4];
+                        if (cb < ncb) aorig4(a, Pe, ve, rt + ln, c0 + 16 * cb + g, ao);
+                        else ao[0] = ao[1] = ao[2] = ao[3] = 0.0;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) v[cb][r] = ao[r] - acc[t][cb][r];
+                    }
+                    dmfma4 y[4];
+#pragma unroll
+                    for (int mb = 0; mb < 4; ++mb) y[mb] = dmfma4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int mb = 0; mb < 4; ++mb) {
+                        if (mb < ncb) {
+#pragma unroll
+                            for (int kb = 0; kb <= mb; ++kb)
+#pragma unroll
+                                for (int r = 0; r < 4; ++r) {
+                                    const double zv = VZs[(16 * mb + ln) * CH_VP + 16 * kb + 4 * r + g];
+                                    y[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(zv, v[kb][r], y[mb],
+                                                                                  0, 0, 0);
+                                }
+                        }
+                    }
+                    const int row = rt + ln;
+                    if (row < R) {
+#pragma unroll
+                        for (int mb = 0; mb < 4; ++mb)
+                            if (mb < ncb)
+                                *reinterpret_cast<double4*>(Le + (size_t)row * ld + c0 + 16 * mb +
+                                                            cq) =
+                                    double4{y[mb][0], y[mb][1], y[mb][2], y[mb][3]};
+                    }
+                    if (rt == Np) {
+                        // rows Np (lanes ln == 0) and Np + 1 (ln == 1): accumulate y . z
+                        double part = 0.0;
+#pragma unroll
+                        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const double other = __shfl_down(y[mb][r], 1, 64);
+                                part = fma(y[mb][r], other, part);
+                            }
+                        part = ln == 0 ? part : 0.0;
+                        part += __shfl_xor(part, 16, 64);
+                        part += __shfl_xor(part, 32, 64);
+                        if (lane == 0) dot_acc += part;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const double* ld_ = a.lead + (size_t)e * MCNEGF_LEAD_NTERMS;
+        const double tqp = a.inject_lead == 0 ? ld_[MCNEGF_LEAD_TRL] : ld_[MCNEGF_LEAD_TLR];
+        const double Tk = tqp + dot_acc;
+        a.T[e] = Tk;
+        a.sig[e] = 0.0;
+        if (bad_flag) atomicOr(a.status, MCNEGF_FLAG_NOTSPD);
+        if (!isfinite(Tk)) atomicOr(a.status, MCNEGF_FLAG_NONFINITE);
     }
 }
 
@@ -311,23 +493,21 @@ hipError_t launch_direct_current(const mcnegf_kernel& k, uint32_t inject_lead,
     }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    {
-        MCNEGF_TIMED("direct_fill_kernel", s);
-        hipLaunchKernelGGL(direct_fill_kernel, dim3(N, k.nE), dim3(256), 0, s, k.P, k.gamma,
-                           k.direct_vec, N, k.p_pitch, k.direct);
-    }
-    if ((err = hipGetLastError()) != hipSuccess) return err;
+    CholArgs a;
+    a.P = k.P;
+    a.vec = k.direct_vec;
+    a.lead = k.lead;
+    a.Lall = k.direct;
+    a.T = T;
+    a.sig = sigmaT;
+    a.status = k.status;
+    a.N = N;
+    a.Np = (int)k.p_pitch;
+    a.ld = k.p_pitch;
+    a.inject_lead = inject_lead;
     {
         MCNEGF_TIMED("cholesky_kernel", s);
-        hipLaunchKernelGGL(cholesky_kernel, dim3(k.nE), dim3(256), 0, s, k.direct, N, k.p_pitch,
-                           k.status);
-    }
-    if ((err = hipGetLastError()) != hipSuccess) return err;
-    {
-        MCNEGF_TIMED("chol_solve_kernel", s);
-        hipLaunchKernelGGL(chol_solve_kernel, dim3(k.nE), dim3(256), (size_t)N * sizeof(double), s,
-                           k.direct, N, k.p_pitch, k.direct_vec, k.lead, inject_lead, T, sigmaT,
-                           k.status);
+        hipLaunchKernelGGL(cholesky_kernel, dim3(k.nE), dim3(64 * CH_WAVES), 0, s, a);
     }
     if ((err = hipGetLastError()) != hipSuccess) return err;
     {

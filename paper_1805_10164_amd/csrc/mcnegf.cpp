@@ -60,7 +60,7 @@ Layout make_layout(int W, int L, int nE) {
     o.off_direct_vec = take((uint64_t)nE * 4 * N * 8);
     o.off_P = take((uint64_t)nE * N * o.p_pitch * 8);
     o.off_alias = take((uint64_t)nE * n * o.alias_pitch * 8);
-    o.off_direct = take((uint64_t)nE * N * o.p_pitch * 8);
+    o.off_direct = take((uint64_t)nE * (o.p_pitch + 2) * o.p_pitch * 8);
     o.total = off;
     return o;
 }
