@@ -1,0 +1,111 @@
+"""Text summaries of rocprofv3 output, as committed under profiles/.
+
+    python -m paper_1805_10164_amd.profiling stats KERNEL_STATS_CSV --command CMD
+        per-kernel calls, total / average / min / max duration and share of GPU time.
+
+    python -m paper_1805_10164_amd.profiling traffic --fetch COUNTERS_CSV --write COUNTERS_CSV
+        --calib-mib M --kernel NAME --source FILE [--command-fetch CMD --command-write CMD]
+        HBM bytes per launch of kernel NAME from a FETCH_SIZE run and a WRITE_SIZE run (KiB per
+        dispatch).  Each counter is scaled by what it reads for the plain copy dispatch of the
+        same run (a negation that reads and writes M MiB, see bench.py --calib-copy-mb), so the
+        result is in bytes actually moved.  The JSON records the source file's SHA-256; bench.py
+        uses the figure only while the source is unchanged.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CALIB_KERNEL = "neg_kernel"
+
+
+def short_name(name: str) -> str:
+    n = name.split("(")[0].replace("mcnegf::", "").replace("void ", "")
+    return n[:44]
+
+
+def stats(path: str, command: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    out = [f"# command: {command}", f"# source: {os.path.basename(path)}",
+           f"{'kernel':44s} {'calls':>5s} {'total_ms':>9s} {'avg_us':>10s} {'min_us':>10s} "
+           f"{'max_us':>10s} {'pct':>6s}"]
+    for r in rows:
+        out.append(f"{short_name(r['Name']):44s} {int(r['Calls']):5d} "
+                   f"{int(r['TotalDurationNs']) / 1e6:9.3f} {float(r['AverageNs']) / 1e3:10.1f} "
+                   f"{int(r['MinNs']) / 1e3:10.1f} {int(r['MaxNs']) / 1e3:10.1f} "
+                   f"{float(r['Percentage']):6.2f}")
+    return "\n".join(out) + "\n"
+
+
+def _counter(path: str, counter: str):
+    """(values of kernel dispatches by short name, calibration value) for one counter."""
+    per, calib = {}, None
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        v = float(r["Counter_Value"])
+        if CALIB_KERNEL in r["Kernel_Name"]:
+            calib = v
+            continue
+        per.setdefault(short_name(r["Kernel_Name"]), []).append(v)
+    return per, calib
+
+
+def traffic(fetch_csv, write_csv, calib_mib, kernel, source, cmd_fetch="", cmd_write=""):
+    fetch, cf = _counter(fetch_csv, "FETCH_SIZE")
+    write, cw = _counter(write_csv, "WRITE_SIZE")
+    if cf is None or cw is None:
+        raise SystemExit("calibration dispatch not found in the counter files")
+    key = next((k for k in fetch if k.split("<")[0] == kernel), None)
+    if key is None or key not in write:
+        raise SystemExit(f"kernel {kernel} not found in the counter files")
+    known_kib = calib_mib * 1024.0
+    fs, ws = known_kib / cf, known_kib / cw
+    f, w = fetch[key], write[key]
+    per_launch = [1024.0 * (a * fs + b * ws) for a, b in zip(f, w)]
+    src = os.path.join(ROOT, source)
+    return {
+        "kernel": kernel,
+        "source": source,
+        "source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest(),
+        "fetch_kib_per_dispatch": f,
+        "write_kib_per_dispatch": w,
+        "calibration": {"copy_mib_read_and_written": calib_mib, "fetch_kib_read": cf,
+                        "write_kib_read": cw, "fetch_scale": fs, "write_scale": ws},
+        "hbm_bytes_per_dispatch": per_launch,
+        "hbm_bytes_per_launch": sum(per_launch) / len(per_launch),
+        "commands": {"fetch": cmd_fetch, "write": cmd_write},
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("--command", default="")
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--calib-mib", type=float, required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--source", required=True)
+    t.add_argument("--command-fetch", default="")
+    t.add_argument("--command-write", default="")
+    a = ap.parse_args(argv)
+    if a.what == "stats":
+        sys.stdout.write(stats(a.csv, a.command))
+    else:
+        rec = traffic(a.fetch, a.write, a.calib_mib, a.kernel, a.source, a.command_fetch,
+                      a.command_write)
+        json.dump(rec, sys.stdout, indent=1)
+        sys.stdout.write("\n")
+
+
+if __name__ == "__main__":
+    main()
