@@ -31,7 +31,7 @@ from paper_1805_10164_amd import mcnegf as M  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 FP64_VALU_PEAK_TFLOPS = 78.6
-ALIAS_ENTRY_BYTES = 8        # one {thr, alias} pair read per walk step
+ALIAS_ENTRY_BYTES = 4  # one packed alias entry read per step (the low threshold bits only on a 2^-20 tie)
 PROFILES = os.path.join(ROOT, "profiles")
 
 

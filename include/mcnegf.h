@@ -113,9 +113,12 @@ typedef struct mcnegf_kernel {
     int64_t  p_pitch;       /* doubles per row of P (>= N, multiple of 16)                 */
     const double* energies; /* [nE], borrowed from the caller                              */
     const double* gamma;    /* [N], borrowed from the caller                               */
-    uint32_t* alias;        /* [nE][n_out][alias_pitch] pairs {thr, alias} of uint32:      */
-                            /*  bucket c keeps outcome c when a uniform 32-bit word r       */
-                            /*  satisfies r < thr, else goes to outcome alias               */
+    uint32_t* alias;        /* [nE][n_out][alias_pitch] packed alias entries:              */
+                            /*  bits 31..12 = thr >> 12, bits 11..0 = alias (n_out <= 4096) */
+    uint16_t* alias_lo;     /* [nE][n_out][alias_pitch] thr & 0xFFF.  Bucket c keeps        */
+                            /*  outcome c when a uniform 32-bit word r satisfies r < thr,   */
+                            /*  else goes to outcome alias (the low part of thr is read     */
+                            /*  only when r >> 12 == thr >> 12)                             */
     double*   P;            /* [nE][N][p_pitch]  |G_ij|^2                                  */
     double*   wL;           /* [nE][N]  <psi_j|Gamma_L|psi_j>, psi_j = G|j>                 */
     double*   wR;           /* [nE][N]  <psi_j|Gamma_R|psi_j>                               */

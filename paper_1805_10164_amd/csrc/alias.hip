@@ -21,7 +21,10 @@
 //   light i : threshold s_i,            alias = heavy m with C_{m-1} <= D_i < C_m,
 //   heavy m : threshold 1 + C_m - D*,   alias = heavy m+1   (last heavy: threshold 1, itself).
 // Each bucket c keeps outcome c with probability thr_c = floor(q_c 2^32) / 2^32 (a kept mass
-// of 1 is stored as 2^32 - 1 with the bucket aliased to itself).
+// of 1 is stored as 2^32 - 1 with the bucket aliased to itself).  Storage: one 32-bit word
+// per bucket with the high 20 bits of thr_c and the 12-bit alias, plus the low 12 bits of
+// thr_c in a separate 16-bit array that the walker reads only on a tie of the high bits
+// (probability 2^-20), so the comparison is the full 32-bit one at 4 bytes per bucket.
 #include "common.h"
 
 namespace mcnegf {
@@ -137,7 +140,8 @@ struct AliasArgs {
     const double* Adiag;
     const double* gamma;
     double* lead;
-    uint2* alias;
+    uint32_t* alias;     // packed (thr >> 12) << 12 | alias
+    uint16_t* alias_lo;  // thr & 0xFFF
     uint32_t* status;
     const double* gam_lead;
     int64_t ldP, pitch;
@@ -193,7 +197,8 @@ __global__ void __launch_bounds__(256) alias_build_kernel(AliasArgs a) {
         if (!(trg > a.open_cut)) total = 0.0;
     }
 
-    uint2* out = a.alias + ((size_t)e * n + row) * a.pitch;
+    uint32_t* out = a.alias + ((size_t)e * n + row) * a.pitch;
+    uint16_t* out_lo = a.alias_lo + ((size_t)e * n + row) * a.pitch;
     if (tid == 0) {
         double ref;
         if (row < N) ref = a.Adiag[(size_t)e * N + row];
@@ -209,7 +214,10 @@ __global__ void __launch_bounds__(256) alias_build_kernel(AliasArgs a) {
     }
     if (!(total > 0.0) || !isfinite(total)) {
         // Degenerate row: every bucket exits at lead L (its estimator weight is zero).
-        for (int i = tid; i < n; i += 256) out[i] = make_uint2(0u, (uint32_t)N);
+        for (int i = tid; i < n; i += 256) {
+            out[i] = (uint32_t)N;
+            out_lo[i] = 0;
+        }
         return;
     }
     // 3. scale, classify, scan
@@ -286,7 +294,8 @@ __global__ void __launch_bounds__(256) alias_build_kernel(AliasArgs a) {
         } else {
             thr = (uint32_t)(q * 4294967296.0);
         }
-        out[i] = make_uint2(thr, (uint32_t)al);
+        out[i] = (thr & 0xFFFFF000u) | (uint32_t)al;
+        out_lo[i] = (uint16_t)(thr & 0xFFFu);
     }
 }
 
@@ -298,7 +307,8 @@ hipError_t launch_alias_build(const mcnegf_kernel& k, hipStream_t s) {
     a.Adiag = k.Adiag;
     a.gamma = k.gamma;
     a.lead = k.lead;
-    a.alias = reinterpret_cast<uint2*>(k.alias);
+    a.alias = k.alias;
+    a.alias_lo = k.alias_lo;
     a.status = k.status;
     a.gam_lead = k.gam_lead;
     a.ldP = k.p_pitch;

@@ -48,7 +48,7 @@ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 struct Layout {
     int64_t alias_pitch, p_pitch;
     uint64_t off_status, off_counters, off_reduce, off_lead, off_sigma, off_gam, off_gL, off_gR,
-        off_Gd, off_corner, off_wL, off_wR, off_Adiag, off_P, off_alias, off_direct,
+        off_Gd, off_corner, off_wL, off_wR, off_Adiag, off_P, off_alias, off_alias_lo, off_direct,
         off_direct_vec, total;
 };
 Layout make_layout(int W, int L, int nE);

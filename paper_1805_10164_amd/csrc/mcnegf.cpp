@@ -59,7 +59,8 @@ Layout make_layout(int W, int L, int nE) {
     o.off_Adiag = take((uint64_t)nE * N * 8);
     o.off_direct_vec = take((uint64_t)nE * 4 * N * 8);
     o.off_P = take((uint64_t)nE * N * o.p_pitch * 8);
-    o.off_alias = take((uint64_t)nE * n * o.alias_pitch * 8);
+    o.off_alias = take((uint64_t)nE * n * o.alias_pitch * 4);
+    o.off_alias_lo = take((uint64_t)nE * n * o.alias_pitch * 2);
     o.off_direct = take((uint64_t)nE * (o.p_pitch + 2) * o.p_pitch * 8);
     o.total = off;
     return o;
@@ -82,7 +83,7 @@ static bool valid_system(const mcnegf_system* s) {
 
 static bool valid_kernel(const mcnegf_kernel* k) {
     return k && k->W >= 1 && k->W <= kMaxW && k->L >= 1 && k->N == k->W * k->L &&
-           k->n_out == k->N + 2 && k->nE >= 1 && k->alias && k->P && k->lead && k->status &&
+           k->n_out == k->N + 2 && k->nE >= 1 && k->alias && k->alias_lo && k->P && k->lead && k->status &&
            k->counters && k->reduce;
 }
 
@@ -135,6 +136,7 @@ int32_t mc_negf_build_kernel(const mcnegf_system* sys, const double* d_onsite,
     k.energies = d_energies;
     k.gamma = d_gamma;
     k.alias = reinterpret_cast<uint32_t*>(base + lay.off_alias);
+    k.alias_lo = reinterpret_cast<uint16_t*>(base + lay.off_alias_lo);
     k.P = reinterpret_cast<double*>(base + lay.off_P);
     k.wL = reinterpret_cast<double*>(base + lay.off_wL);
     k.wR = reinterpret_cast<double*>(base + lay.off_wR);

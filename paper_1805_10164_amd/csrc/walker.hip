@@ -13,11 +13,11 @@
 // r-th redraw of step n: word 0 of counter (n, w, e, tag | 2^31), key (key0, key1 ^ r)),
 // outcome = b < thr[c] ? c : alias[c].
 //
-// Execution: persistent wavefronts take chunks of consecutive walker indices of one energy
-// in grid-stride order (chunk ids are energy-major, so the wavefronts of the grid work on a
-// window of a few energies at a time whose tables stay in L2 / MALL); each lane takes the
-// next walker of its chunk as soon as its own walker is absorbed, and every loop iteration
-// performs two steps from one Philox block.
+// Execution: persistent wavefronts, one energy group per XCD (see walk_kernel); each lane
+// takes the next walker of its wavefront's chunk as soon as its own walker is absorbed, and
+// every loop iteration performs two steps from one Philox block.  The keep test compares the
+// high 20 bits of b with the bucket's packed entry and reads the low 12 threshold bits only
+// on a tie.
 #include "common.h"
 
 namespace mcnegf {
@@ -52,7 +52,8 @@ __device__ inline Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, u
 }
 
 struct WalkArgs {
-    const uint2* tables;
+    const uint32_t* tables;  // packed (thr >> 12) << 12 | alias
+    const uint16_t* lows;    // thr & 0xFFF
     int64_t pitch;
     int64_t table_stride;  // entries per energy
     uint32_t n_out, N;
@@ -61,59 +62,125 @@ struct WalkArgs {
     uint32_t key0, key1, tag;
     uint32_t wbegin, wend;  // walker index range [wbegin, wend)
     uint32_t chunk, chunks_per_energy;
+    uint32_t groups;  // energy groups: energy el belongs to group el % groups
     uint32_t max_steps;
     int64_t* tallies;
     uint32_t* status;
 };
 
-// Every branch in the loops below is wave-uniform (its condition is a ballot or a value
-// computed identically in all lanes), and per-lane differences are expressed as selects:
-// the compiler does not guarantee that lanes which took a divergent branch rejoin the others
-// before a later cross-lane operation (ballot, shuffle, readfirstlane) in the same loop, so
-// the walker keeps the whole wavefront active at every one of them.  Tallies go to LDS
-// (every lane adds its own counts) and reach global memory once, after all loops.
+// Every branch in the loops below that encloses a cross-lane operation is wave-uniform (its
+// condition is a ballot or a value computed identically in all lanes), and per-lane
+// differences are expressed as selects: the compiler does not guarantee that lanes which took
+// a divergent branch rejoin the others before a later cross-lane operation (ballot, shuffle,
+// readfirstlane) in the same loop, so the walker keeps the whole wavefront active at every
+// one of them.  The only divergent regions hold a table load or LDS atomics.
 struct Step {
     uint32_t s, n;
     bool active;
 };
 
-// One transition draw for every lane of the wavefront; lanes with !st.active compute and
-// discard.  (a, b) are the step's two Philox words; counts are added for lanes whose walk
-// ends here.
-__device__ inline void walk_step(Step& st, uint32_t w, uint32_t e, uint32_t a, uint32_t b,
-                                 const uint2* __restrict__ tab, const WalkArgs& A,
-                                 uint32_t& cL, uint32_t& cR, uint32_t& tr, uint64_t& s1,
-                                 uint64_t& s2) {
+struct Tally {
+    uint32_t cL, cR, tr;
+    uint64_t s1, s2;
+};
+
+// One transition draw for each of the K walker slots of every lane; inactive slots compute and
+// discard.  (a[k], b[k]) are slot k's two Philox words for this step.  The K table loads are
+// independent and issued together, so a wavefront keeps K memory requests in flight per lane.
+// Counts are added for slots whose walk ends here.
+template <int K>
+__device__ inline void walk_steps(Step (&st)[K], const uint32_t (&w)[K], const uint32_t (&el)[K],
+                                  const uint32_t (&a)[K], const uint32_t (&b)[K],
+                                  const WalkArgs& A, Tally (&t)[K]) {
     const uint32_t n_out = A.n_out;
-    uint64_t m = (uint64_t)a * n_out;
-    uint32_t thresh = (0u - n_out) % n_out;
-    bool rej = st.active && ((uint32_t)m < thresh);
-    uint32_t r = 0;
-    while (__ballot(rej) != 0ull) {  // rare (probability < n / 2^32 per step); uniform loop
-        ++r;
-        const uint32_t a2 =
-            philox4x32_10(st.n, w, e, A.tag | 0x80000000u, A.key0, A.key1 ^ r).x[0];
-        const uint64_t m2 = (uint64_t)a2 * n_out;
-        m = rej ? m2 : m;
-        rej = rej && ((uint32_t)m2 < thresh);
+    const uint32_t thresh = (0u - n_out) % n_out;
+    uint64_t m[K];
+    bool rej[K];
+    uint64_t rb = 0ull;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        m[k] = (uint64_t)a[k] * n_out;
+        rej[k] = st[k].active && ((uint32_t)m[k] < thresh);
+        rb |= __ballot(rej[k]);
     }
-    const uint32_t c = (uint32_t)(m >> 32);
-    const uint2 ent = tab[(size_t)st.s * A.pitch + c];
-    const uint32_t nxt = (b < ent.x) ? c : ent.y;
-    const uint32_t n1 = st.n + 1;
-    const bool absorbed = st.active && nxt >= A.N;
-    const bool trunc = st.active && !absorbed && n1 >= A.max_steps;
-    const bool ends = absorbed || trunc;
-    cL += (absorbed && nxt == A.N) ? 1u : 0u;
-    cR += (absorbed && nxt != A.N) ? 1u : 0u;
-    tr += trunc ? 1u : 0u;
-    s1 += ends ? (uint64_t)n1 : 0ull;
-    s2 += ends ? (uint64_t)n1 * n1 : 0ull;
-    st.s = (st.active && !ends) ? nxt : st.s;
-    st.n = st.active ? n1 : st.n;
-    st.active = st.active && !ends;
+    uint32_t r = 0;
+    while (rb != 0ull) {  // rare (probability < n / 2^32 per step); uniform loop
+        ++r;
+        rb = 0ull;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t a2 = philox4x32_10(st[k].n, w[k], A.e_off + el[k],
+                                              A.tag | 0x80000000u, A.key0, A.key1 ^ r).x[0];
+            const uint64_t m2 = (uint64_t)a2 * n_out;
+            m[k] = rej[k] ? m2 : m[k];
+            rej[k] = rej[k] && ((uint32_t)m2 < thresh);
+            rb |= __ballot(rej[k]);
+        }
+    }
+    uint32_t c[K], ent[K];
+    size_t at[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        c[k] = (uint32_t)(m[k] >> 32);
+        at[k] = (size_t)el[k] * A.table_stride + (size_t)st[k].s * A.pitch + c[k];
+        ent[k] = A.tables[at[k]];
+    }
+    bool keep[K], tie[K];
+    uint64_t tb = 0ull;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        keep[k] = (b[k] >> 12) < (ent[k] >> 12);
+        tie[k] = st[k].active && (b[k] >> 12) == (ent[k] >> 12);
+        tb |= __ballot(tie[k]);
+    }
+    if (tb != 0ull) {  // rare (probability 2^-20 per step); uniform branch
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t lo = tie[k] ? (uint32_t)A.lows[at[k]] : 0u;
+            keep[k] = tie[k] ? (b[k] & 0xFFFu) < lo : keep[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const uint32_t nxt = keep[k] ? c[k] : (ent[k] & 0xFFFu);
+        const uint32_t n1 = st[k].n + 1;
+        const bool active = st[k].active;
+        const bool absorbed = active && nxt >= A.N;
+        const bool trunc = active && !absorbed && n1 >= A.max_steps;
+        const bool ends = absorbed || trunc;
+        t[k].cL += (absorbed && nxt == A.N) ? 1u : 0u;
+        t[k].cR += (absorbed && nxt != A.N) ? 1u : 0u;
+        t[k].tr += trunc ? 1u : 0u;
+        t[k].s1 += ends ? (uint64_t)n1 : 0ull;
+        t[k].s2 += ends ? (uint64_t)n1 * n1 : 0ull;
+        st[k].s = (active && !ends) ? nxt : st[k].s;
+        st[k].n = active ? n1 : st[k].n;
+        st[k].active = active && !ends;
+    }
 }
 
+// Adds a slot's counts for energy el to the block's LDS tallies (per-lane; called in
+// divergent code, no cross-lane operation inside).
+__device__ inline void tally_flush(unsigned long long* lds_tally, uint32_t el, const Tally& t) {
+    unsigned long long* p = lds_tally + (size_t)el * MCNEGF_TALLY_N;
+    if (t.cL) atomicAdd(p + MCNEGF_TALLY_EXIT_L, (unsigned long long)t.cL);
+    if (t.cR) atomicAdd(p + MCNEGF_TALLY_EXIT_R, (unsigned long long)t.cR);
+    if (t.tr) atomicAdd(p + MCNEGF_TALLY_TRUNC, (unsigned long long)t.tr);
+    if (t.s1) atomicAdd(p + MCNEGF_TALLY_STEPS, (unsigned long long)t.s1);
+    if (t.s2) atomicAdd(p + MCNEGF_TALLY_STEPS2, (unsigned long long)t.s2);
+}
+
+// Work layout.  Energy el belongs to group el % groups and workgroup b to group b % groups;
+// consecutive workgroups are dispatched to the 8 XCDs in turn, so with 8 groups all walkers of
+// an energy run on one XCD, whose L2 then holds that energy's table.  A group's work is the
+// energy-major list of chunks (chunk c of its q-th energy has id q * chunks_per_energy + c);
+// its wavefronts take ids in stride order, and with one chunk per wavefront and energy the
+// wavefronts of a group walk one energy at a time.  Every lane runs K walker slots.  A slot
+// whose walk has ended takes the next walker index of the wavefront's current chunk, moving
+// on to the wavefront's next chunk (the next energy) when the current one is used up, so no
+// slot waits for the slowest walk of a chunk; a slot's counts are kept in registers for its
+// current energy and added to LDS when it changes energy.
+template <int K>
 __global__ void __launch_bounds__(256) walk_kernel(WalkArgs A) {
     extern __shared__ unsigned long long lds_tally[];  // [nE][5]
     const int lane = threadIdx.x & 63;
@@ -121,50 +188,99 @@ __global__ void __launch_bounds__(256) walk_kernel(WalkArgs A) {
     const uint32_t nE = A.nE;
     for (uint32_t i = threadIdx.x; i < nE * MCNEGF_TALLY_N; i += blockDim.x) lds_tally[i] = 0ull;
     __syncthreads();
-    const uint32_t total_chunks = nE * A.chunks_per_energy;
-    const uint32_t waves = __builtin_amdgcn_readfirstlane(gridDim.x * (blockDim.x >> 6));
-    const uint32_t wave_id =
-        __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    const uint32_t G = A.groups;
+    const uint32_t grp = blockIdx.x % G;
+    const uint32_t wpb = blockDim.x >> 6;
+    const uint32_t waves = __builtin_amdgcn_readfirstlane((gridDim.x / G) * wpb);
+    const uint32_t lw =
+        __builtin_amdgcn_readfirstlane((blockIdx.x / G) * wpb + (threadIdx.x >> 6));
+    const uint32_t nq = (nE - grp + G - 1) / G;  // energies of this group
+    const uint32_t total = nq * A.chunks_per_energy;
     const uint32_t inject_row = A.N + (A.tag & 1u);
-    uint32_t trunc_any = 0;
-    for (uint32_t ch = wave_id; ch < total_chunks; ch += waves) {
-        const uint32_t el = ch / A.chunks_per_energy;  // energy within this launch
-        const uint32_t e = A.e_off + el;                 // energy index of the streams
-        const uint32_t w0 = A.wbegin + (ch - el * A.chunks_per_energy) * A.chunk;
-        const uint32_t w1 = min(w0 + A.chunk, A.wend);
-        const uint2* tab = A.tables + (size_t)el * A.table_stride;
-        uint32_t next = w0;
-        Step st = {inject_row, 0u, false};
-        uint32_t w = 0;
-        uint32_t cL = 0, cR = 0, tr = 0;
-        uint64_t s1 = 0, s2 = 0;
-        for (;;) {
-            // refill: idle lanes take the next walker indices of the chunk, in lane order
-            const uint64_t need = __ballot(!st.active);
-            const uint32_t avail = w1 - next;
-            const uint32_t before = __popcll(need & lt_mask);
-            const bool take = !st.active && before < avail;
-            w = take ? next + before : w;
-            st.s = take ? inject_row : st.s;
-            st.n = take ? 0u : st.n;
-            st.active = st.active || take;
-            const uint32_t cnt = __popcll(need);
-            next += cnt < avail ? cnt : avail;
-            if (__ballot(st.active) == 0ull) break;
-            // two steps from one Philox block (step n uses words 2(n&1), 2(n&1)+1 of block n>>1;
-            // active walkers enter the iteration at even n)
-            const Philox4 x = philox4x32_10(st.n >> 1, w, e, A.tag, A.key0, A.key1);
-            walk_step(st, w, e, x.x[0], x.x[1], tab, A, cL, cR, tr, s1, s2);
-            walk_step(st, w, e, x.x[2], x.x[3], tab, A, cL, cR, tr, s1, s2);
-        }
-        unsigned long long* t = lds_tally + (size_t)el * MCNEGF_TALLY_N;
-        atomicAdd(t + MCNEGF_TALLY_EXIT_L, (unsigned long long)cL);
-        atomicAdd(t + MCNEGF_TALLY_EXIT_R, (unsigned long long)cR);
-        atomicAdd(t + MCNEGF_TALLY_TRUNC, (unsigned long long)tr);
-        atomicAdd(t + MCNEGF_TALLY_STEPS, (unsigned long long)s1);
-        atomicAdd(t + MCNEGF_TALLY_STEPS2, (unsigned long long)s2);
-        trunc_any |= tr;
+
+    // the wavefront's cursor: chunk id, its energy, next walker index and end
+    uint32_t cid = lw, cel = 0, next = 0, wend = 0;
+    auto open_chunk = [&](uint32_t id) {
+        const uint32_t q = id / A.chunks_per_energy;
+        cel = grp + q * G;
+        next = A.wbegin + (id - q * A.chunks_per_energy) * A.chunk;
+        wend = min(next + A.chunk, A.wend);
+    };
+    if (cid < total) open_chunk(cid);
+
+    Step st[K];
+    uint32_t w[K], el[K], tel[K];  // walker index, its energy, energy of the counts in t
+    Tally t[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        st[k] = Step{inject_row, 0u, false};
+        w[k] = el[k] = tel[k] = 0u;
+        t[k] = Tally{0u, 0u, 0u, 0ull, 0ull};
     }
+    uint32_t trunc_any = 0;
+    for (;;) {
+        // refill idle slots (slot-major, then lane order) from the cursor's chunks
+        while (cid < total) {
+            uint64_t need[K];
+            uint32_t tot = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                need[k] = __ballot(!st[k].active);
+                tot += __popcll(need[k]);
+            }
+            if (tot == 0) break;
+            const uint32_t avail = wend - next;
+            uint32_t base = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const uint32_t before = base + __popcll(need[k] & lt_mask);
+                const bool take = !st[k].active && before < avail;
+                const bool flush = take && cel != tel[k];
+                if (__ballot(flush) != 0ull) {
+                    if (flush) tally_flush(lds_tally, tel[k], t[k]);
+                    t[k].cL = flush ? 0u : t[k].cL;
+                    t[k].cR = flush ? 0u : t[k].cR;
+                    t[k].tr = flush ? 0u : t[k].tr;
+                    t[k].s1 = flush ? 0ull : t[k].s1;
+                    t[k].s2 = flush ? 0ull : t[k].s2;
+                    tel[k] = flush ? cel : tel[k];
+                }
+                w[k] = take ? next + before : w[k];
+                el[k] = take ? cel : el[k];
+                st[k].s = take ? inject_row : st[k].s;
+                st[k].n = take ? 0u : st[k].n;
+                st[k].active = st[k].active || take;
+                base += __popcll(need[k]);
+            }
+            next += tot < avail ? tot : avail;
+            if (next >= wend) {
+                cid += waves;
+                if (cid < total) open_chunk(cid);
+            }
+        }
+        uint64_t any = 0ull;
+#pragma unroll
+        for (int k = 0; k < K; ++k) any |= __ballot(st[k].active);
+        if (any == 0ull) break;
+        // two steps from one Philox block per slot (step n uses words 2(n&1), 2(n&1)+1 of
+        // block n>>1; active walkers enter the iteration at even n)
+        uint32_t a0[K], b0[K], a1[K], b1[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const Philox4 x =
+                philox4x32_10(st[k].n >> 1, w[k], A.e_off + el[k], A.tag, A.key0, A.key1);
+            a0[k] = x.x[0];
+            b0[k] = x.x[1];
+            a1[k] = x.x[2];
+            b1[k] = x.x[3];
+        }
+        walk_steps<K>(st, w, el, a0, b0, A, t);
+        walk_steps<K>(st, w, el, a1, b1, A, t);
+#pragma unroll
+        for (int k = 0; k < K; ++k) trunc_any |= t[k].tr;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) tally_flush(lds_tally, tel[k], t[k]);
     __syncthreads();
     unsigned long long* gt = reinterpret_cast<unsigned long long*>(A.tallies);
     for (uint32_t i = threadIdx.x; i < nE * MCNEGF_TALLY_N; i += blockDim.x) {
@@ -174,19 +290,37 @@ __global__ void __launch_bounds__(256) walk_kernel(WalkArgs A) {
     if (trunc_any) atomicOr(A.status, MCNEGF_FLAG_TRUNC);
 }
 
+constexpr int kWalkSlots = 3;
+
 hipError_t launch_walk(const mcnegf_kernel& k, uint64_t seed, uint32_t tag, uint32_t walker_begin,
                        uint32_t n_walkers, uint32_t max_steps, int64_t* tallies, hipStream_t s) {
-    // energies per launch: the LDS tallies ([energies][5] int64) must fit the 160 KB of a CU
-    constexpr uint32_t kMaxEnergiesPerLaunch = 2048;
-    const size_t max_lds = (size_t)kMaxEnergiesPerLaunch * MCNEGF_TALLY_N * 8;
-    hipError_t err = hipFuncSetAttribute((const void*)walk_kernel,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
-    if (err != hipSuccess) return err;
+    if (n_walkers == 0) return hipSuccess;
+    // One launch per round of kXcds * kEnergiesPerXcd energies: a kernel boundary keeps the
+    // wavefronts of an XCD on the same energies, whose tables then stay in that XCD's L2
+    // (without it, wavefronts drift apart over many energies and the L2 thrashes).  Fewer than
+    // kXcds energies go in one launch in a single group.
+    constexpr uint32_t kXcds = 8;
+    constexpr uint32_t kEnergiesPerXcd = 4;
+    constexpr uint32_t kMaxEnergiesPerLaunch = kXcds * kEnergiesPerXcd;
+    const void* fn = (const void*)walk_kernel<kWalkSlots>;
+    int dev = 0, cus = 0;
+    hipError_t err;
+    if ((err = hipGetDevice(&dev)) != hipSuccess) return err;
+    if ((err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
+        hipSuccess)
+        return err;
+    const size_t lds = (size_t)kMaxEnergiesPerLaunch * MCNEGF_TALLY_N * 8;
+    // persistent grid: no more workgroups than can be resident at once
+    int per_cu = 0;
+    if ((err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds)) != hipSuccess)
+        return err;
+    const uint32_t max_blocks = (uint32_t)(per_cu < 1 ? 1 : per_cu) * (uint32_t)cus;
     for (uint32_t e_off = 0; e_off < (uint32_t)k.nE; e_off += kMaxEnergiesPerLaunch) {
         WalkArgs A;
         const uint32_t nE = min((uint32_t)k.nE - e_off, kMaxEnergiesPerLaunch);
         A.table_stride = (int64_t)k.n_out * k.alias_pitch;
-        A.tables = reinterpret_cast<const uint2*>(k.alias) + (size_t)e_off * A.table_stride;
+        A.tables = k.alias + (size_t)e_off * A.table_stride;
+        A.lows = k.alias_lo + (size_t)e_off * A.table_stride;
         A.pitch = k.alias_pitch;
         A.n_out = (uint32_t)k.n_out;
         A.N = (uint32_t)k.N;
@@ -197,25 +331,26 @@ hipError_t launch_walk(const mcnegf_kernel& k, uint64_t seed, uint32_t tag, uint
         A.tag = tag;
         A.wbegin = walker_begin;
         A.wend = walker_begin + n_walkers;
-        // chunk: about four chunks per wavefront of a full grid, 64..4096 walkers
-        const uint64_t total = (uint64_t)n_walkers * nE;
-        const int max_blocks = 2048;  // 8192 wavefronts of 64 lanes
-        uint64_t ch = total / ((uint64_t)max_blocks * 4 * 4);
-        ch = ch < 64 ? 64 : (ch > 4096 ? 4096 : ch);
-        ch = (ch + 63) / 64 * 64;
+        A.groups = nE >= kXcds ? kXcds : 1u;
+        // wavefronts per group: at most the grid's share, and about two walkers per slot
+        const uint64_t nq = (nE + A.groups - 1) / A.groups;
+        const uint64_t walkers_per_group = nq * n_walkers;
+        uint64_t wg = walkers_per_group / (64ull * kWalkSlots * 2);
+        uint64_t wg_max = (uint64_t)max_blocks / A.groups * 4;
+        wg_max = wg_max < 4 ? 4 : wg_max;
+        wg = wg < 4 ? 4 : (wg > wg_max ? wg_max : wg);
+        const uint64_t bpg = (wg + 3) / 4;
+        // one chunk per wavefront and energy
+        const uint64_t ch = (n_walkers + bpg * 4 - 1) / (bpg * 4);
         A.chunk = (uint32_t)ch;
         A.chunks_per_energy = (uint32_t)((n_walkers + ch - 1) / ch);
         A.max_steps = max_steps;
         A.tallies = tallies + (size_t)e_off * MCNEGF_TALLY_N;
         A.status = k.status;
-        const uint64_t waves_needed = (uint64_t)nE * A.chunks_per_energy;
-        const uint64_t nb = (waves_needed + 3) / 4;
-        const size_t lds = (size_t)nE * MCNEGF_TALLY_N * 8;
         {
             MCNEGF_TIMED("walk_kernel", s);
-            hipLaunchKernelGGL(walk_kernel,
-                               dim3((unsigned)(nb < (uint64_t)max_blocks ? nb : max_blocks)),
-                               dim3(256), lds, s, A);
+            hipLaunchKernelGGL(walk_kernel<kWalkSlots>, dim3((unsigned)(bpg * A.groups)),
+                               dim3(256), (size_t)nE * MCNEGF_TALLY_N * 8, s, A);
         }
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }

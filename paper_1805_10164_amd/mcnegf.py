@@ -48,7 +48,7 @@ class KernelStruct(ctypes.Structure):
                 ("lead_model", ctypes.c_int32), ("t", ctypes.c_double),
                 ("delta_lead", ctypes.c_double), ("alias_pitch", ctypes.c_int64), ("p_pitch", ctypes.c_int64),
                 ("energies", ctypes.c_void_p), ("gamma", ctypes.c_void_p),
-                ("alias", ctypes.c_void_p), ("P", ctypes.c_void_p), ("wL", ctypes.c_void_p),
+                ("alias", ctypes.c_void_p), ("alias_lo", ctypes.c_void_p), ("P", ctypes.c_void_p), ("wL", ctypes.c_void_p),
                 ("wR", ctypes.c_void_p), ("Adiag", ctypes.c_void_p), ("lead", ctypes.c_void_p),
                 ("sigma", ctypes.c_void_p), ("gam_lead", ctypes.c_void_p),
                 ("gL", ctypes.c_void_p), ("gR", ctypes.c_void_p), ("Gd", ctypes.c_void_p),
@@ -171,10 +171,34 @@ class Kernel:
         import torch
         return self.view("Gd", torch.float64, (self.nE, self.L, self.W, self.W, 2))
 
-    def alias_table(self):
-        """[nE][n_out][alias_pitch][2] uint32 pairs {thr, alias} (as int32 storage)."""
+    def alias_packed(self):
+        """[nE][n_out][alias_pitch] packed entries (thr >> 12) << 12 | alias, int32 storage."""
         import torch
-        return self.view("alias", torch.int32, (self.nE, self.n_out, self.alias_pitch, 2))
+        return self.view("alias", torch.int32, (self.nE, self.n_out, self.alias_pitch))
+
+    def alias_low(self):
+        """[nE][n_out][alias_pitch] low 12 bits of the thresholds, int16 storage."""
+        import torch
+        return self.view("alias_lo", torch.int16, (self.nE, self.n_out, self.alias_pitch))
+
+    def alias_tables(self):
+        """(thr uint32, alias int32) numpy arrays [nE][n_out][alias_pitch] read back from the
+        device format (format conversion only)."""
+        packed = self.alias_packed().cpu().numpy().view(np.uint32)
+        low = self.alias_low().cpu().numpy().view(np.uint16).astype(np.uint32)
+        return (packed & np.uint32(0xFFFFF000)) | low, (packed & np.uint32(0xFFF)).astype(np.int32)
+
+    def set_alias_tables(self, thr, alias):
+        """Store uint32 thresholds and alias indices [nE][n_out][alias_pitch] in the device
+        format (format conversion only)."""
+        import torch
+        thr = np.asarray(thr, dtype=np.uint32)
+        alias = np.asarray(alias, dtype=np.uint32)
+        packed = (thr & np.uint32(0xFFFFF000)) | (alias & np.uint32(0xFFF))
+        low = (thr & np.uint32(0xFFF)).astype(np.uint16)
+        dev = self.ws.device
+        self.alias_packed().copy_(torch.from_numpy(packed.view(np.int32)).to(dev))
+        self.alias_low().copy_(torch.from_numpy(low.view(np.int16)).to(dev))
 
 
 def mc_negf_workspace_bytes(system: System, nE: int) -> int:

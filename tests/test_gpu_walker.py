@@ -38,9 +38,7 @@ def test_walker_bit_exact_on_given_tables(inject):
     k = gpu_build(c)
     sols = oracle_solve(c)
     thr, al = oracle_alias_tables(sols, k.alias_pitch)
-    tab = k.alias_table()
-    packed = np.stack([thr.view(np.int32), al], axis=-1)
-    tab.copy_(torch.from_numpy(packed).to(DEV))
+    k.set_alias_tables(thr, al)
     nw = 50_000
     tal = torch.zeros((3, 5), dtype=torch.int64, device=DEV)
     M.mc_negf_walk(k, SEED, 7, inject, 1000, nw, 1_000_000, tal)
@@ -53,7 +51,7 @@ def test_walker_truncation_and_max_steps():
     k = gpu_build(c)
     sols = oracle_solve(c)
     thr, al = oracle_alias_tables(sols, k.alias_pitch)
-    k.alias_table().copy_(torch.from_numpy(np.stack([thr.view(np.int32), al], -1)).to(DEV))
+    k.set_alias_tables(thr, al)
     tal = torch.zeros((2, 5), dtype=torch.int64, device=DEV)
     M.mc_negf_walk(k, 11, 0, 0, 0, 20_000, 2, tal)
     ref = OW.walk_alias(thr, al, 11, 0, 0, 0, 20_000, max_steps=2)
@@ -144,13 +142,14 @@ def test_outside_band_walkers_exit_at_once():
 
 
 def test_more_energies_than_one_launch_holds():
-    # 2100 energies are walked in two launches (LDS tallies hold 2048 energies); the streams
-    # are keyed by the global energy index, so the oracle walker on the same tables agrees.
+    # 2100 energies are walked in many launches (one per round of energies, the last one
+    # partial); the streams are keyed by the global energy index, so the oracle walker on the
+    # same tables agrees.
     c = case(W=1, L=3, eta=0.2, disorder=0.0, nE=2100, emin=-1.5, emax=1.5)
     k = gpu_build(c)
     sols = oracle_solve(c)
     thr, al = oracle_alias_tables(sols, k.alias_pitch)
-    k.alias_table().copy_(torch.from_numpy(np.stack([thr.view(np.int32), al], -1)).to(DEV))
+    k.set_alias_tables(thr, al)
     tal = torch.zeros((2100, 5), dtype=torch.int64, device=DEV)
     M.mc_negf_walk(k, 3, 1, 0, 5, 200, 1_000_000, tal)
     ref = OW.walk_alias(thr, al, 3, 1, 0, 5, 200)
