@@ -93,8 +93,8 @@ def kernel_work(name, wl, walk_steps):
         # two sweeps per column slice: L*(L-1) complex W x W block products per energy
         return "alu", nE * 8.0 * W ** 3 * wl.L * (wl.L - 1) / 1e12, "TFLOP"
     if name == "alias_build_kernel":
-        # read gamma_i |G_ji|^2 rows and write one 8-byte alias entry per outcome
-        return "hbm", nE * (8.0 * N * N + 8.0 * n * n) / 1e9, "GB"
+        # read gamma_i |G_ji|^2 rows and write one 4-byte entry plus 2 low threshold bytes per outcome
+        return "hbm", nE * (8.0 * N * N + 6.0 * n * n) / 1e9, "GB"
     return None
 
 
