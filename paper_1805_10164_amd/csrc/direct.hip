@@ -139,8 +139,9 @@ __global__ void direct_prep_kernel(const double* __restrict__ P, const double* _
 typedef double dmfma4 __attribute__((ext_vector_type(4)));
 
 constexpr int CH_NB = 64;            // block-column width
-constexpr int CH_KC = 64;            // K chunk staged in LDS
+constexpr int CH_KC = 32;            // K chunk staged in LDS (double-buffered)
 constexpr int CH_BP = CH_KC + 4;     // LDS pitch of a staged row (doubles)
+constexpr int CH_KG = CH_KC / 16;    // 16-column MFMA groups per chunk
 constexpr int CH_VP = CH_NB + 1;     // LDS pitch of the diagonal block
 constexpr int CH_WAVES = 8;
 constexpr int CH_ROWS = CH_WAVES * 32;  // rows per super-tile
@@ -191,27 +192,16 @@ __device__ inline void aorig4(const CholArgs& a, const double* Pe, const double*
     }
 }
 
-// Staging of a block-column row segment (8 doubles at column col) through registers into LDS.
-__device__ inline void stage_load(const double* Le, int64_t ld, int R, int row, int col,
-                                  double4 (&b)[2]) {
-    if (row < R) {
-        const double* src = Le + (size_t)row * ld + col;
-        b[0] = *reinterpret_cast<const double4*>(src);
-        b[1] = *reinterpret_cast<const double4*>(src + 4);
-    } else {
-        b[0] = double4{0, 0, 0, 0};
-        b[1] = double4{0, 0, 0, 0};
-    }
+// Staging of a block-column row segment (4 doubles at column col) through registers into LDS.
+__device__ inline double4 stage_load(const double* Le, int64_t ld, int R, int row, int col) {
+    return row < R ? *reinterpret_cast<const double4*>(Le + (size_t)row * ld + col)
+                   : double4{0.0, 0.0, 0.0, 0.0};
 }
 
-__device__ inline void stage_store(double* Bs, int sm, int sc, const double4 (&b)[2]) {
-    *reinterpret_cast<double4*>(&Bs[sm * CH_BP + sc]) = b[0];
-    *reinterpret_cast<double4*>(&Bs[sm * CH_BP + sc + 4]) = b[1];
+__device__ inline void stage_store(double* Bs, int sm, int sc, const double4& b) {
+    *reinterpret_cast<double4*>(&Bs[sm * CH_BP + sc]) = b;
 }
 
-// One wavefront: L_JJ = chol(V) for the wJ x wJ lower part of V (LDS, pitch CH_VP, logical
-// column order), written to Ls (identity outside wJ) and to global rows of L (Lg, pitch ld, in
-// the stored column order); then Z = L_JJ^{-1} into V.
 // The LDS arguments carry the LDS address space so that every access is a DS instruction: the
 // lanes exchange rows and columns through LDS, which a wavefront's DS instructions see in
 // program order (generic pointers would turn them into FLAT accesses, which give no such order).
@@ -267,7 +257,7 @@ __device__ __noinline__ void factor_diag_block(lds_double* VZs, lds_double* Ls, 
 }
 
 __global__ void __launch_bounds__(512) cholesky_kernel(CholArgs a) {
-    __shared__ double Bs[CH_NB * CH_BP];
+    __shared__ double Bs[2][CH_NB * CH_BP];  // double-buffered K chunk of block-column rows
     __shared__ double VZs[CH_NB * CH_VP];  // diagonal block V, then Z = L_JJ^{-1}
     __shared__ double Ls[CH_NB * CH_VP];   // L_JJ
     __shared__ double colbuf[CH_NB];
@@ -291,9 +281,9 @@ __global__ void __launch_bounds__(512) cholesky_kernel(CholArgs a) {
         dot_acc = 0.0;
         bad_flag = 0;
     }
-    // staging assignment: row sm of the block column, 8 doubles at column sc
+    // staging assignment: row sm of the block column, 4 doubles at column sc of a chunk
     const int sm = tid >> 3;
-    const int sc = (tid & 7) * 8;
+    const int sc = (tid & 7) * 4;
 
     const int nJ = (Np + CH_NB - 1) / CH_NB;
     for (int J = 0; J < nJ; ++J) {
@@ -307,24 +297,26 @@ __global__ void __launch_bounds__(512) cholesky_kernel(CholArgs a) {
         // Wavefront w owns the 16 x 16 blocks p = w and p = w + 8 (block row p / 4, column p % 4).
         {
             dmfma4 accd[2] = {dmfma4{0.0, 0.0, 0.0, 0.0}, dmfma4{0.0, 0.0, 0.0, 0.0}};
-            double4 bstage[2];
-            if (c0 > 0) stage_load(Le, ld, R, c0 + sm, sc, bstage);
-            for (int kc = 0; kc < c0; kc += CH_KC) {
+            if (c0 > 0) {
+                stage_store(Bs[0], sm, sc, stage_load(Le, ld, R, c0 + sm, sc));
                 __syncthreads();
-                stage_store(Bs, sm, sc, bstage);
-                if (kc + CH_KC < c0) stage_load(Le, ld, R, c0 + sm, kc + CH_KC + sc, bstage);
-                __syncthreads();
+            }
+            for (int kc = 0, it = 0; kc < c0; kc += CH_KC, ++it) {
+                const double* B = Bs[it & 1];
+                const bool more = kc + CH_KC < c0;
+                double4 bst = {0.0, 0.0, 0.0, 0.0};
+                if (more) bst = stage_load(Le, ld, R, c0 + sm, kc + CH_KC + sc);
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int p = wave + 8 * h;
                     const int tb = p >> 2, cb = p & 3;
                     if (cb <= tb && tb < ncb) {
 #pragma unroll
-                        for (int kg = 0; kg < 4; ++kg) {
+                        for (int kg = 0; kg < CH_KG; ++kg) {
                             const double4 av = *reinterpret_cast<const double4*>(
-                                &Bs[(16 * cb + ln) * CH_BP + 16 * kg + cq]);
+                                &B[(16 * cb + ln) * CH_BP + 16 * kg + cq]);
                             const double4 bv = *reinterpret_cast<const double4*>(
-                                &Bs[(16 * tb + ln) * CH_BP + 16 * kg + cq]);
+                                &B[(16 * tb + ln) * CH_BP + 16 * kg + cq]);
                             accd[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, accd[h], 0, 0, 0);
                             accd[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.y, accd[h], 0, 0, 0);
                             accd[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.z, bv.z, accd[h], 0, 0, 0);
@@ -332,6 +324,8 @@ __global__ void __launch_bounds__(512) cholesky_kernel(CholArgs a) {
                         }
                     }
                 }
+                if (more) stage_store(Bs[(it & 1) ^ 1], sm, sc, bst);
+                __syncthreads();
             }
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -361,55 +355,67 @@ __global__ void __launch_bounds__(512) cholesky_kernel(CholArgs a) {
 #pragma unroll
                 for (int cb = 0; cb < 4; ++cb) acc[t][cb] = dmfma4{0.0, 0.0, 0.0, 0.0};
 
-            // update: acc^T = L[tile rows, 0:c0] . L[J rows, 0:c0]^T
-            double4 bstage[2];
-            if (c0 > 0) stage_load(Le, ld, R, c0 + sm, sc, bstage);
-            for (int kc = 0; kc < c0; kc += CH_KC) {
-                double4 av[2][4];
+            // update: acc^T = L[tile rows, 0:c0] . L[J rows, 0:c0]^T.  Chunk it of the
+            // block-column rows is in Bs[it & 1] while chunk it + 1 is staged into the other
+            // buffer and this wavefront's tile rows of chunk it + 1 are loaded: one barrier per
+            // chunk, loads in flight across the chunk's MFMAs.
+            if (c0 > 0) {
+                double4 av[2][CH_KG];
 #pragma unroll
-                for (int t = 0; t < 2; ++t) {
-                    const int row = r0 + 16 * t + ln;
-                    const bool ok = row < R;
-                    const double* src = Le + (size_t)(ok ? row : 0) * ld + kc + cq;
+                for (int t = 0; t < 2; ++t)
 #pragma unroll
-                    for (int kg = 0; kg < 4; ++kg)
-                        av[t][kg] = ok ? *reinterpret_cast<const double4*>(src + 16 * kg)
-                                       : double4{0, 0, 0, 0};
-                }
+                    for (int kg = 0; kg < CH_KG; ++kg)
+                        av[t][kg] = stage_load(Le, ld, R, r0 + 16 * t + ln, 16 * kg + cq);
+                stage_store(Bs[0], sm, sc, stage_load(Le, ld, R, c0 + sm, sc));
                 __syncthreads();
-                stage_store(Bs, sm, sc, bstage);
-                if (kc + CH_KC < c0) stage_load(Le, ld, R, c0 + sm, kc + CH_KC + sc, bstage);
-                __syncthreads();
-                if (r0 < R) {
+                for (int kc = 0, it = 0; kc < c0; kc += CH_KC, ++it) {
+                    const double* B = Bs[it & 1];
+                    const bool more = kc + CH_KC < c0;
+                    const int kn = more ? kc + CH_KC : kc;
+                    const double4 bst = stage_load(Le, ld, R, c0 + sm, kn + sc);
+                    double4 an[2][CH_KG];
 #pragma unroll
-                    for (int kg = 0; kg < 4; ++kg) {
-                        double4 bf[4];
+                    for (int t = 0; t < 2; ++t)
 #pragma unroll
-                        for (int cb = 0; cb < 4; ++cb)
-                            bf[cb] = *reinterpret_cast<const double4*>(
-                                &Bs[(16 * cb + ln) * CH_BP + 16 * kg + cq]);
+                        for (int kg = 0; kg < CH_KG; ++kg)
+                            an[t][kg] = stage_load(Le, ld, R, r0 + 16 * t + ln, kn + 16 * kg + cq);
+                    if (r0 < R) {
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
+                        for (int kg = 0; kg < CH_KG; ++kg) {
+                            double4 bf[4];
 #pragma unroll
-                            for (int t = 0; t < 2; ++t) {
-                                const double bv = q == 0 ? av[t][kg].x
-                                                : q == 1 ? av[t][kg].y
-                                                : q == 2 ? av[t][kg].z
-                                                         : av[t][kg].w;
+                            for (int cb = 0; cb < 4; ++cb)
+                                bf[cb] = *reinterpret_cast<const double4*>(
+                                    &B[(16 * cb + ln) * CH_BP + 16 * kg + cq]);
 #pragma unroll
-                                for (int cb = 0; cb < 4; ++cb) {
-                                    if (cb < ncb) {
-                                        const double aval = q == 0 ? bf[cb].x
-                                                            : q == 1 ? bf[cb].y
-                                                            : q == 2 ? bf[cb].z
-                                                                     : bf[cb].w;
-                                        acc[t][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                                            aval, bv, acc[t][cb], 0, 0, 0);
+                            for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                                for (int t = 0; t < 2; ++t) {
+                                    const double bv = q == 0 ? av[t][kg].x
+                                                    : q == 1 ? av[t][kg].y
+                                                    : q == 2 ? av[t][kg].z
+                                                             : av[t][kg].w;
+#pragma unroll
+                                    for (int cb = 0; cb < 4; ++cb) {
+                                        if (cb < ncb) {
+                                            const double aval = q == 0 ? bf[cb].x
+                                                                : q == 1 ? bf[cb].y
+                                                                : q == 2 ? bf[cb].z
+                                                                         : bf[cb].w;
+                                            acc[t][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                                aval, bv, acc[t][cb], 0, 0, 0);
+                                        }
                                     }
                                 }
                             }
                         }
                     }
+                    if (more) stage_store(Bs[(it & 1) ^ 1], sm, sc, bst);
+                    __syncthreads();
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int kg = 0; kg < CH_KG; ++kg) av[t][kg] = an[t][kg];
                 }
             }
             // V = A - update (lane: row r0 + 16 t + ln, columns c0 + 16 cb + 4 r + g), then
