@@ -193,9 +193,39 @@ __device__ inline void aorig4(const CholArgs& a, const double* Pe, const double*
 }
 
 // Staging of a block-column row segment (4 doubles at column col) through registers into LDS.
+// Rows beyond R read row R - 1 and are then zeroed by a select, so no load is predicated.
 __device__ inline double4 stage_load(const double* Le, int64_t ld, int R, int row, int col) {
-    return row < R ? *reinterpret_cast<const double4*>(Le + (size_t)row * ld + col)
-                   : double4{0.0, 0.0, 0.0, 0.0};
+    const bool ok = row < R;
+    const double4 v = *reinterpret_cast<const double4*>(Le + (size_t)(ok ? row : R - 1) * ld + col);
+    return ok ? v : double4{0.0, 0.0, 0.0, 0.0};
+}
+
+// MFMAs of one staged chunk for a wavefront's two 16-row tiles: NCB 16-column blocks of the
+// block column (A operand from LDS), tile rows (B operand) from registers.
+template <int NCB>
+__device__ inline void chunk_mfma(const double* B, const double4 (&av)[2][CH_KG],
+                                  dmfma4 (&acc)[2][4], int ln, int cq) {
+#pragma unroll
+    for (int kg = 0; kg < CH_KG; ++kg) {
+        double4 bf[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+            bf[cb] = *reinterpret_cast<const double4*>(&B[(16 * cb + ln) * CH_BP + 16 * kg + cq]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const double bv = q == 0 ? av[t][kg].x : q == 1 ? av[t][kg].y
+                                : q == 2 ? av[t][kg].z : av[t][kg].w;
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) {
+                    const double aval = q == 0 ? bf[cb].x : q == 1 ? bf[cb].y
+                                      : q == 2 ? bf[cb].z : bf[cb].w;
+                    acc[t][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(aval, bv, acc[t][cb], 0, 0, 0);
+                }
+            }
+        }
+    }
 }
 
 __device__ inline void stage_store(double* Bs, int sm, int sc, const double4& b) {
@@ -211,7 +241,8 @@ typedef __attribute__((address_space(3))) int lds_int;
 __device__ __noinline__ void factor_diag_block(lds_double* VZs, lds_double* Ls, lds_double* colbuf,
                                                double* Lg, int64_t ld, int wJ, int lane,
                                                lds_int* bad_flag) {
-    // lane i holds row i; column k is shared through LDS
+    // Lane i holds row i; column k is shared through LDS.  The step branch is uniform; the
+    // updates of columns from wJ on are harmless (their entries stay zero).
     const int i = lane;
     double rw[CH_NB];
 #pragma unroll
@@ -230,7 +261,7 @@ __device__ __noinline__ void factor_diag_block(lds_double* VZs, lds_double* Ls, 
             colbuf[i] = lik;
 #pragma unroll
             for (int j = k + 1; j < CH_NB; ++j) {
-                if (j < wJ) rw[j] = fma(-lik, colbuf[j], rw[j]);
+                rw[j] = fma(-lik, colbuf[j], rw[j]);
             }
         }
     }
@@ -241,19 +272,27 @@ __device__ __noinline__ void factor_diag_block(lds_double* VZs, lds_double* Ls, 
         Ls[i * CH_VP + j] = lv;
         if (j <= i && i < wJ) Lg[(size_t)i * ld + (j & ~15) + 4 * (j & 3) + ((j >> 2) & 3)] = lv;
     }
-    // Z = L_JJ^{-1}: lane = column j, forward substitution down the rows (Ls was written by
-    // this wavefront, whose LDS accesses stay in order)
-    const int j = lane;
-    double z[CH_NB];
+    // Inverses of the four 16 x 16 diagonal sub-blocks of L_JJ: lane (b, c) = (lane / 16,
+    // lane % 16) computes column c of L_bb^{-1} by forward substitution and stores it in the
+    // diagonal sub-block b of V (Ls was written by this wavefront, whose LDS accesses stay in
+    // order).
+    const int b = lane >> 4, c = lane & 15;
+    const lds_double* Lb = Ls + (16 * b) * CH_VP + 16 * b;
+    double z[16];
 #pragma unroll
-    for (int r = 0; r < CH_NB; ++r) {
-        double s = (r == j) ? 1.0 : 0.0;
+    for (int r = 0; r < 16; ++r) {
+        double s0 = (r == c) ? 1.0 : 0.0, s1 = 0.0;
 #pragma unroll
-        for (int m = 0; m < r; ++m) s = fma(-Ls[r * CH_VP + m], z[m], s);
-        z[r] = s / Ls[r * CH_VP + r];
+        for (int m = 0; m + 1 < r; m += 2) {
+            s0 = fma(-Lb[r * CH_VP + m], z[m], s0);
+            s1 = fma(-Lb[r * CH_VP + m + 1], z[m + 1], s1);
+        }
+        if (r & 1) s0 = fma(-Lb[r * CH_VP + r - 1], z[r - 1], s0);
+        z[r] = (s0 + s1) / Lb[r * CH_VP + r];
     }
+    lds_double* Zb = VZs + (16 * b) * CH_VP + 16 * b;
 #pragma unroll
-    for (int r = 0; r < CH_NB; ++r) VZs[r * CH_VP + j] = z[r];
+    for (int r = 0; r < 16; ++r) Zb[r * CH_VP + c] = z[r];
 }
 
 __global__ void __launch_bounds__(512) cholesky_kernel(CholArgs a) {
@@ -380,34 +419,11 @@ __global__ void __launch_bounds__(512) cholesky_kernel(CholArgs a) {
                         for (int kg = 0; kg < CH_KG; ++kg)
                             an[t][kg] = stage_load(Le, ld, R, r0 + 16 * t + ln, kn + 16 * kg + cq);
                     if (r0 < R) {
-#pragma unroll
-                        for (int kg = 0; kg < CH_KG; ++kg) {
-                            double4 bf[4];
-#pragma unroll
-                            for (int cb = 0; cb < 4; ++cb)
-                                bf[cb] = *reinterpret_cast<const double4*>(
-                                    &B[(16 * cb + ln) * CH_BP + 16 * kg + cq]);
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) {
-#pragma unroll
-                                for (int t = 0; t < 2; ++t) {
-                                    const double bv = q == 0 ? av[t][kg].x
-                                                    : q == 1 ? av[t][kg].y
-                                                    : q == 2 ? av[t][kg].z
-                                                             : av[t][kg].w;
-#pragma unroll
-                                    for (int cb = 0; cb < 4; ++cb) {
-                                        if (cb < ncb) {
-                                            const double aval = q == 0 ? bf[cb].x
-                                                                : q == 1 ? bf[cb].y
-                                                                : q == 2 ? bf[cb].z
-                                                                         : bf[cb].w;
-                                            acc[t][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                                                aval, bv, acc[t][cb], 0, 0, 0);
-                                        }
-                                    }
-                                }
-                            }
+                        switch (ncb) {
+                            case 4: chunk_mfma<4>(B, av, acc, ln, cq); break;
+                            case 3: chunk_mfma<3>(B, av, acc, ln, cq); break;
+                            case 2: chunk_mfma<2>(B, av, acc, ln, cq); break;
+                            default: chunk_mfma<1>(B, av, acc, ln, cq); break;
                         }
                     }
                     if (more) stage_store(Bs[(it & 1) ^ 1], sm, sc, bst);
@@ -419,34 +435,40 @@ __global__ void __launch_bounds__(512) cholesky_kernel(CholArgs a) {
                 }
             }
             // V = A - update (lane: row r0 + 16 t + ln, columns c0 + 16 cb + 4 r + g), then
-            // X^T = Z V^T, stored as rows of L
+            // X L_JJ^T = V by 16-column blocks: X_b^T = L_bb^{-1} (V_b^T - sum_{a<b} L_ba X_a^T),
+            // stored as rows of L.  V^T and X^T blocks are in accumulator layout, which is the
+            // B-operand layout of the next product.
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
                 const int rt = r0 + 16 * t;
                 if (rt < R) {
-                    double v[4][4];
+                    dmfma4 y[4];
 #pragma unroll
                     for (int cb = 0; cb < 4; ++cb) {
                         double ao[4];
                         if (cb < ncb) aorig4(a, Pe, ve, rt + ln, c0 + 16 * cb + g, ao);
                         else ao[0] = ao[1] = ao[2] = ao[3] = 0.0;
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) v[cb][r] = ao[r] - acc[t][cb][r];
+                        for (int r = 0; r < 4; ++r) y[cb][r] = ao[r] - acc[t][cb][r];
                     }
-                    dmfma4 y[4];
-#pragma unroll
-                    for (int mb = 0; mb < 4; ++mb) y[mb] = dmfma4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                     for (int mb = 0; mb < 4; ++mb) {
                         if (mb < ncb) {
+                            dmfma4 u = y[mb];
 #pragma unroll
-                            for (int kb = 0; kb <= mb; ++kb)
+                            for (int kb = 0; kb < mb; ++kb)
 #pragma unroll
                                 for (int r = 0; r < 4; ++r) {
-                                    const double zv = VZs[(16 * mb + ln) * CH_VP + 16 * kb + 4 * r + g];
-                                    y[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(zv, v[kb][r], y[mb],
-                                                                                  0, 0, 0);
+                                    const double lv = Ls[(16 * mb + ln) * CH_VP + 16 * kb + 4 * r + g];
+                                    u = __builtin_amdgcn_mfma_f64_16x16x4f64(-lv, y[kb][r], u, 0, 0, 0);
                                 }
+                            dmfma4 x = dmfma4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const double zv = VZs[(16 * mb + ln) * CH_VP + 16 * mb + 4 * r + g];
+                                x = __builtin_amdgcn_mfma_f64_16x16x4f64(zv, u[r], x, 0, 0, 0);
+                            }
+                            y[mb] = x;
                         }
                     }
                     const int row = rt + ln;
