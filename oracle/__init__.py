@@ -12,4 +12,6 @@ Contents:
   walker.c    a plain C random walker on the same Philox4x32-10 streams as the GPU
               (the paper's cumulative-sum sampler, or an alias table given to it).
   walker.py   ctypes wrapper and build step for walker.c.
+  grad.py     dI/dV_i and dI/dgamma_i of the DIRECT current: reverse-mode differentiation
+              (torch autograd, CPU) of a dense evaluation, and central differences.
 """
