@@ -204,11 +204,29 @@ int32_t mc_negf_current(const mcnegf_kernel* k, int32_t mode, uint32_t inject_le
                         double* d_sigmaT, double* h_I_sigma, hipStream_t stream);
 
 /*
- * Gradients dI/dV_i and dI/dgamma (adjoint of the build and of the estimator).
- * Not implemented: returns MCNEGF_ENOTIMPL and launches nothing.
+ * Bytes of device workspace mc_negf_grad needs for the built kernel `k` (host only):
+ * 3 complex [nE][N][p_pitch] arrays plus O(nE N) vectors.  MCNEGF_EINVAL for a bad handle.
  */
-int32_t mc_negf_grad(const mcnegf_kernel* k, const double* d_weights, double* d_dI_dV,
-                     double* h_dI_deta, hipStream_t stream);
+int32_t mc_negf_grad_workspace_bytes(const mcnegf_kernel* k, uint64_t* bytes_out);
+
+/*
+ * Gradient of the DIRECT current I = sum_k w_k T_eff(E_k) (Sec. III C, Eq. (79) read as the
+ * diagonal of Eq. (8)) with respect to the onsite potentials V_i (H_ii) and the dephasing
+ * rates gamma_i (Sigma_s,ii = -(i/2) gamma_i, Sec. III A, Eq. (77)), by the adjoint of the
+ * probe system and of G = (E - H - Sigma)^{-1} (dI/deta for uniform gamma_i = eta is the sum
+ * of dI/dgamma_i).  The lead self-energies are held fixed.
+ *   k            handle from mc_negf_build_kernel (reads its tables; reruns the DIRECT solve).
+ *   inject_lead  0: T_RL (f_L = 1), 1: T_LR.
+ *   d_weights    [nE] device, quadrature weights w_k.
+ *   d_gws        device workspace of >= mc_negf_grad_workspace_bytes, caller-owned.
+ *   d_dI_dV      [N] device output dI/dV_i;  d_dI_dgamma [N] device output dI/dgamma_i.
+ *   h_I          host output, the DIRECT current I.
+ * Synchronises `stream`; status as mc_negf_current in DIRECT mode.  MCNEGF_EWS if the
+ * workspace is too small; MCNEGF_EHIP if a launch (or the batched complex GEMM) fails.
+ */
+int32_t mc_negf_grad(const mcnegf_kernel* k, uint32_t inject_lead, const double* d_weights,
+                     void* d_gws, uint64_t gws_bytes, double* d_dI_dV, double* d_dI_dgamma,
+                     double* h_I, hipStream_t stream);
 
 /*
  * Per-launch timing (opt-in, for benchmarks).  Between mc_negf_profile_begin(p) and

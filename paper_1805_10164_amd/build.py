@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmcnegf.so")
 SOURCES = ["mcnegf.cpp", "lead.hip", "rgf.hip", "fullinv.hip", "alias.hip", "walker.hip",
-           "direct.hip"]
+           "direct.hip", "grad.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature",
          "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result"]
 # The walker keeps every lane of a wavefront active at each cross-lane operation; the atomic
@@ -51,7 +51,8 @@ def build(verbose: bool = False) -> str:
         msg = "\n".join(f"--- {s}\n{o}" for s, o in failed)
         raise RuntimeError(f"hipcc failed:\n{msg}")
     tmp = LIB + ".tmp"
-    subprocess.check_call([cc, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs])
+    subprocess.check_call([cc, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs,
+                           "-lrocblas"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -53,6 +53,20 @@ struct Layout {
 };
 Layout make_layout(int W, int L, int nE);
 
+// gradient workspace (caller-owned, separate from the build workspace)
+struct GradBuffers {
+    double2* G;   // [nE][N][ld] complex G, row-major
+    double2* H;   // [nE][N][ld] G diag(v) on the fast index
+    double2* Q;   // [nE][N][ld] conj(G) diag(v) G, Q[i][a] = Q_ai
+    double* xl;   // [nE][2][ld] x, lambda
+    double* gV;   // [nE][N] dT/dV per energy
+    double* gG;   // [nE][N] dT/dgamma per energy
+    double* T;    // [nE] DIRECT transmissions (scratch)
+    double* sig;  // [nE] (zero)
+    int64_t ld;
+};
+uint64_t grad_layout(const mcnegf_kernel& k, void* base, GradBuffers* out);
+
 // ---- opt-in launch timing: events around every launch while a profile is attached ------
 struct LaunchTimer {
     LaunchTimer(const char* name, hipStream_t s);
@@ -69,6 +83,8 @@ hipError_t launch_lead_sigma(const mcnegf_kernel& k, double gamma_l, double delt
                              hipStream_t s);
 hipError_t launch_rgf(const mcnegf_kernel& k, const double* onsite, hipStream_t s);
 hipError_t launch_fullinv(const mcnegf_kernel& k, hipStream_t s);
+hipError_t launch_fullinv_store_g(const mcnegf_kernel& k, double2* Gc, int64_t ldG,
+                                  hipStream_t s);
 hipError_t launch_lead_terms(const mcnegf_kernel& k, hipStream_t s);
 hipError_t launch_alias_build(const mcnegf_kernel& k, hipStream_t s);
 hipError_t launch_walk(const mcnegf_kernel& k, uint64_t seed, uint32_t tag,
@@ -80,5 +96,7 @@ hipError_t launch_mc_current(const mcnegf_kernel& k, uint32_t inject_lead,
 hipError_t launch_direct_current(const mcnegf_kernel& k, uint32_t inject_lead,
                                  const double* weights, double* T, double* sigmaT,
                                  hipStream_t s);
+hipError_t launch_grad(const mcnegf_kernel& k, const GradBuffers& gb, uint32_t inject_lead,
+                       const double* weights, double* dI_dV, double* dI_dgamma, hipStream_t s);
 
 }  // namespace mcnegf

@@ -89,7 +89,7 @@ hipError_t launch_mc_current(const mcnegf_kernel& k, uint32_t inject_lead, const
 }
 
 // ---------------------------------------------------------------- DIRECT
-// vec layout per energy: [0] u_j = gamma_j s_j, [1] u_j w_p(j), [2] u_j w_q(j), [3] T_qj,
+// vec layout per energy: [0] u_j = gamma_j s_j, [1] u_j w_p(j), [2] u_j w_q(j), [3] s_j,
 // with s_j = M_jj^{-1/2} (0 for a decoupled probe) and w_p, w_q the exit weights of the
 // injecting and the collecting lead.  Scaled matrix: 1 on the diagonal, -u_i u_j |G_ij|^2 off it;
 // scaled right-hand sides: u_j w_p(j) and u_j w_q(j).
@@ -111,7 +111,7 @@ __global__ void direct_prep_kernel(const double* __restrict__ P, const double* _
     v[j] = u;
     v[N + j] = u * wp;
     v[2 * N + j] = u * wq;
-    v[3 * N + j] = g * wq;
+    v[3 * N + j] = sj;
 }
 
 // ---- Left-looking blocked Cholesky of the bordered probe system on FP64 matrix cores.

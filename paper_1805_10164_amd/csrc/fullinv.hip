@@ -45,7 +45,9 @@ __device__ inline void block_matvec(double2 (&v)[W], const double2* __restrict__
     for (int y = 0; y < W; ++y) v[y] = nv[y];
 }
 
-template <int W>
+// STORE_G: write the complex blocks of G (row-major, pitch ldG, Gc) instead of |G_ij|^2,
+// the exit weights and the corners.
+template <int W, bool STORE_G>
 __global__ void __launch_bounds__(256) fullinv_kernel(const double2* __restrict__ gL,
                                                       const double2* __restrict__ gR,
                                                       const double2* __restrict__ Gd,
@@ -54,7 +56,8 @@ __global__ void __launch_bounds__(256) fullinv_kernel(const double2* __restrict_
                                                       double* __restrict__ P,
                                                       double* __restrict__ wL,
                                                       double* __restrict__ wR,
-                                                      double2* __restrict__ corner) {
+                                                      double2* __restrict__ corner,
+                                                      double2* __restrict__ Gc, int64_t ldG) {
     const int N = W * L;
     const int e = blockIdx.y;
     const int wave_first = blockIdx.x * 256 + (threadIdx.x & ~63);
@@ -92,12 +95,18 @@ __global__ void __launch_bounds__(256) fullinv_kernel(const double2* __restrict_
             for (int y = 0; y < W; ++y) v[y] = cmk(0.0, 0.0);
         }
         if (valid && k >= l) {
+            if (STORE_G) {
+                double2* Ge = Gc + (size_t)e * N * ldG;
 #pragma unroll
-            for (int y = 0; y < W; ++y) Pe[(size_t)(k * W + y) * ldP + col] = cabs2(v[y]);
+                for (int y = 0; y < W; ++y) Ge[(size_t)(k * W + y) * ldG + col] = v[y];
+            } else {
+#pragma unroll
+                for (int y = 0; y < W; ++y) Pe[(size_t)(k * W + y) * ldP + col] = cabs2(v[y]);
+            }
         }
     }
     // k = L-1 now: exit weight into R and, for columns of slice 0, the corner G_{L-1,0}.
-    if (valid) {
+    if (valid && !STORE_G) {
         wR[(size_t)e * N + col] = quad_form<W>(v, gme);
         if (l == 0) {
 #pragma unroll
@@ -118,11 +127,17 @@ __global__ void __launch_bounds__(256) fullinv_kernel(const double2* __restrict_
             for (int y = 0; y < W; ++y) v[y] = cmk(0.0, 0.0);
         }
         if (valid && k < l) {
+            if (STORE_G) {
+                double2* Ge = Gc + (size_t)e * N * ldG;
 #pragma unroll
-            for (int y = 0; y < W; ++y) Pe[(size_t)(k * W + y) * ldP + col] = cabs2(v[y]);
+                for (int y = 0; y < W; ++y) Ge[(size_t)(k * W + y) * ldG + col] = v[y];
+            } else {
+#pragma unroll
+                for (int y = 0; y < W; ++y) Pe[(size_t)(k * W + y) * ldP + col] = cabs2(v[y]);
+            }
         }
     }
-    if (valid) {
+    if (valid && !STORE_G) {
         wL[(size_t)e * N + col] = quad_form<W>(v, gme);
         if (l == L - 1) {
 #pragma unroll
@@ -131,25 +146,28 @@ __global__ void __launch_bounds__(256) fullinv_kernel(const double2* __restrict_
     }
 }
 
-template <int W>
-static hipError_t launch_fullinv_w(const mcnegf_kernel& k, hipStream_t s) {
+template <int W, bool STORE_G>
+static hipError_t launch_fullinv_w(const mcnegf_kernel& k, double2* Gc, int64_t ldG,
+                                   hipStream_t s) {
     dim3 grid((k.N + 255) / 256, k.nE);
     {
-        MCNEGF_TIMED("fullinv_kernel", s);
-        hipLaunchKernelGGL(fullinv_kernel<W>, grid, dim3(256), 0, s,
+        MCNEGF_TIMED(STORE_G ? "fullinv_store_g_kernel" : "fullinv_kernel", s);
+        hipLaunchKernelGGL((fullinv_kernel<W, STORE_G>), grid, dim3(256), 0, s,
                            reinterpret_cast<const double2*>(k.gL),
                            reinterpret_cast<const double2*>(k.gR),
                            reinterpret_cast<const double2*>(k.Gd), k.gam_lead, k.L, k.t, k.p_pitch,
-                           k.P, k.wL, k.wR, reinterpret_cast<double2*>(k.corner));
+                           k.P, k.wL, k.wR, reinterpret_cast<double2*>(k.corner), Gc, ldG);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_fullinv(const mcnegf_kernel& k, hipStream_t s) {
+template <bool STORE_G>
+static hipError_t launch_fullinv_any(const mcnegf_kernel& k, double2* Gc, int64_t ldG,
+                                     hipStream_t s) {
     switch (k.W) {
 #define MCNEGF_CASE(w) \
     case w:            \
-        return launch_fullinv_w<w>(k, s);
+        return launch_fullinv_w<w, STORE_G>(k, Gc, ldG, s);
         MCNEGF_CASE(1) MCNEGF_CASE(2) MCNEGF_CASE(3) MCNEGF_CASE(4) MCNEGF_CASE(5)
         MCNEGF_CASE(6) MCNEGF_CASE(7) MCNEGF_CASE(8) MCNEGF_CASE(9) MCNEGF_CASE(10)
         MCNEGF_CASE(11) MCNEGF_CASE(12) MCNEGF_CASE(13) MCNEGF_CASE(14) MCNEGF_CASE(15)
@@ -158,6 +176,15 @@ hipError_t launch_fullinv(const mcnegf_kernel& k, hipStream_t s) {
         default:
             return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_fullinv(const mcnegf_kernel& k, hipStream_t s) {
+    return launch_fullinv_any<false>(k, nullptr, 0, s);
+}
+
+hipError_t launch_fullinv_store_g(const mcnegf_kernel& k, double2* Gc, int64_t ldG,
+                                  hipStream_t s) {
+    return launch_fullinv_any<true>(k, Gc, ldG, s);
 }
 
 }  // namespace mcnegf

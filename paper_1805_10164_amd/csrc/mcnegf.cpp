@@ -83,7 +83,7 @@ static bool valid_system(const mcnegf_system* s) {
 
 static bool valid_kernel(const mcnegf_kernel* k) {
     return k && k->W >= 1 && k->W <= kMaxW && k->L >= 1 && k->N == k->W * k->L &&
-           k->n_out == k->N + 2 && k->nE >= 1 && k->alias && k->alias_lo && k->P && k->lead && k->status &&
+           k->n_out == k->N + 2 && k->nE >= 1 && k->p_pitch >= k->N && k->p_pitch % 16 == 0 && k->alias && k->alias_lo && k->P && k->lead && k->status &&
            k->counters && k->reduce;
 }
 
@@ -93,6 +93,37 @@ static int32_t status_to_code(uint32_t flags, bool mc) {
     if (mc && (flags & MCNEGF_FLAG_TRUNC)) return MCNEGF_WTRUNC;
     if (flags & MCNEGF_FLAG_ROWSUM) return MCNEGF_WNUMERIC;
     return MCNEGF_OK;
+}
+
+uint64_t grad_layout(const mcnegf_kernel& k, void* base, GradBuffers* out) {
+    const int64_t N = k.N, nE = k.nE, ld = k.p_pitch;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t at = off;
+        off = align256(off + bytes);
+        return at;
+    };
+    const uint64_t oG = take((uint64_t)nE * N * ld * 16);
+    const uint64_t oH = take((uint64_t)nE * N * ld * 16);
+    const uint64_t oQ = take((uint64_t)nE * N * ld * 16);
+    const uint64_t oX = take((uint64_t)nE * 2 * ld * 8);
+    const uint64_t oV = take((uint64_t)nE * N * 8);
+    const uint64_t oGg = take((uint64_t)nE * N * 8);
+    const uint64_t oT = take((uint64_t)nE * 8);
+    const uint64_t oS = take((uint64_t)nE * 8);
+    if (out) {
+        char* b = static_cast<char*>(base);
+        out->G = reinterpret_cast<double2*>(b + oG);
+        out->H = reinterpret_cast<double2*>(b + oH);
+        out->Q = reinterpret_cast<double2*>(b + oQ);
+        out->xl = reinterpret_cast<double*>(b + oX);
+        out->gV = reinterpret_cast<double*>(b + oV);
+        out->gG = reinterpret_cast<double*>(b + oGg);
+        out->T = reinterpret_cast<double*>(b + oT);
+        out->sig = reinterpret_cast<double*>(b + oS);
+        out->ld = ld;
+    }
+    return off;
 }
 
 }  // namespace mcnegf
@@ -215,10 +246,36 @@ int32_t mc_negf_current(const mcnegf_kernel* k, int32_t mode, uint32_t inject_le
     return status_to_code(flags, mode == 0);
 }
 
-int32_t mc_negf_grad(const mcnegf_kernel* k, const double* d_weights, double* d_dI_dV,
-                     double* h_dI_deta, hipStream_t stream) {
-    (void)k; (void)d_weights; (void)d_dI_dV; (void)h_dI_deta; (void)stream;
-    return MCNEGF_ENOTIMPL;
+int32_t mc_negf_grad_workspace_bytes(const mcnegf_kernel* k, uint64_t* bytes_out) {
+    if (!valid_kernel(k) || !bytes_out) return MCNEGF_EINVAL;
+    *bytes_out = grad_layout(*k, nullptr, nullptr);
+    return MCNEGF_OK;
+}
+
+int32_t mc_negf_grad(const mcnegf_kernel* k, uint32_t inject_lead, const double* d_weights,
+                     void* d_gws, uint64_t gws_bytes, double* d_dI_dV, double* d_dI_dgamma,
+                     double* h_I, hipStream_t stream) {
+    if (!valid_kernel(k) || !d_weights || !d_gws || !d_dI_dV || !d_dI_dgamma || !h_I ||
+        inject_lead > 1 || !k->direct || !k->direct_vec)
+        return MCNEGF_EINVAL;
+    GradBuffers gb;
+    if (grad_layout(*k, d_gws, &gb) > gws_bytes) return MCNEGF_EWS;
+    hipError_t err = launch_direct_current(*k, inject_lead, d_weights, gb.T, gb.sig, stream);
+    if (err != hipSuccess) return hip_fail(err);
+    if ((err = launch_grad(*k, gb, inject_lead, d_weights, d_dI_dV, d_dI_dgamma, stream)) !=
+        hipSuccess)
+        return hip_fail(err);
+    double host[2];
+    uint32_t flags = 0;
+    if ((err = hipMemcpyAsync(host, k->reduce, sizeof(host), hipMemcpyDeviceToHost, stream)) !=
+        hipSuccess)
+        return hip_fail(err);
+    if ((err = hipMemcpyAsync(&flags, k->status, sizeof(flags), hipMemcpyDeviceToHost, stream)) !=
+        hipSuccess)
+        return hip_fail(err);
+    if ((err = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(err);
+    *h_I = host[0];
+    return status_to_code(flags, false);
 }
 
 int32_t mc_negf_profile_begin(mcnegf_profile* p) {

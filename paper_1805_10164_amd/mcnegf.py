@@ -25,8 +25,9 @@ LEAD_TLL, LEAD_TRL, LEAD_TLR, LEAD_TRR, LEAD_CL, LEAD_CR, LEAD_TRGLA, LEAD_TRGRA
 TALLY_N = 5
 TALLY_EXIT_L, TALLY_EXIT_R, TALLY_TRUNC, TALLY_STEPS, TALLY_STEPS2 = range(5)
 EXPORTED = ("mc_negf_workspace_bytes", "mc_negf_build_kernel", "mc_negf_walk",
-            "mc_negf_current", "mc_negf_grad", "mc_negf_profile_begin", "mc_negf_profile_end",
-            "mc_negf_status", "mc_negf_last_hip_error", "mc_negf_version")
+            "mc_negf_current", "mc_negf_grad_workspace_bytes", "mc_negf_grad",
+            "mc_negf_profile_begin", "mc_negf_profile_end", "mc_negf_status",
+            "mc_negf_last_hip_error", "mc_negf_version")
 PROFILE_MAX = 512
 
 
@@ -82,7 +83,8 @@ def lib() -> ctypes.CDLL:
                                        ctypes.POINTER(KernelStruct), vp]
     L.mc_negf_walk.argtypes = [ctypes.POINTER(KernelStruct), u64, u32, u32, u64, u64, u32, vp, vp]
     L.mc_negf_current.argtypes = [ctypes.POINTER(KernelStruct), i32, u32, vp, vp, vp, vp, dp, vp]
-    L.mc_negf_grad.argtypes = [ctypes.POINTER(KernelStruct), vp, vp, dp, vp]
+    L.mc_negf_grad_workspace_bytes.argtypes = [ctypes.POINTER(KernelStruct), ctypes.POINTER(u64)]
+    L.mc_negf_grad.argtypes = [ctypes.POINTER(KernelStruct), u32, vp, vp, u64, vp, vp, dp, vp]
     L.mc_negf_status.argtypes = [ctypes.POINTER(KernelStruct), ctypes.POINTER(u32), vp]
     L.mc_negf_profile_begin.argtypes = [ctypes.POINTER(Profile)]
     L.mc_negf_profile_end.argtypes = [ctypes.POINTER(Profile), ctypes.POINTER(ctypes.c_float)]
@@ -242,10 +244,24 @@ def mc_negf_current(k: Kernel, mode: int, inject_lead: int, tallies, weights, T,
     return code, float(out[0]), float(out[1])
 
 
-def mc_negf_grad(k: Kernel, weights, dI_dV, stream=None) -> int:
+def mc_negf_grad_workspace_bytes(k: Kernel) -> int:
+    out = ctypes.c_uint64(0)
+    _check("mc_negf_grad_workspace_bytes",
+           lib().mc_negf_grad_workspace_bytes(ctypes.byref(k.struct), ctypes.byref(out)))
+    return int(out.value)
+
+
+def mc_negf_grad(k: Kernel, inject_lead, weights, gws, dI_dV, dI_dgamma, stream=None,
+                 allow=(OK, WNUMERIC)):
+    """dI/dV_i and dI/dgamma_i of the DIRECT current into the [N] device tensors dI_dV and
+    dI_dgamma; gws is a device byte tensor of >= mc_negf_grad_workspace_bytes(k).  Returns
+    (status, I)."""
     out = ctypes.c_double(0.0)
-    return int(lib().mc_negf_grad(ctypes.byref(k.struct), _ptr(weights), _ptr(dI_dV),
+    code = int(lib().mc_negf_grad(ctypes.byref(k.struct), int(inject_lead), _ptr(weights),
+                                  _ptr(gws), int(gws.numel()), _ptr(dI_dV), _ptr(dI_dgamma),
                                   ctypes.byref(out), _stream(stream)))
+    _check("mc_negf_grad", code, allow)
+    return code, float(out.value)
 
 
 def mc_negf_status(k: Kernel, stream=None) -> int:

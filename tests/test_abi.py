@@ -83,8 +83,8 @@ def test_host_validation_rejects_before_any_gpu_call():
     assert lib.mc_negf_build_kernel(ctypes.byref(s), z, z, z, 3, z, 0, ctypes.byref(ks), z) == M.EINVAL
     assert lib.mc_negf_walk(ctypes.byref(ks), 1, 0, 0, 0, 10, 10, z, z) == M.EINVAL
     # a structurally valid handle with bad walk arguments is still rejected on the host
-    ks.W, ks.L, ks.N, ks.n_out, ks.nE = 2, 3, 6, 8, 1
-    for f in ("alias", "P", "lead", "status", "counters", "reduce"):
+    ks.W, ks.L, ks.N, ks.n_out, ks.nE, ks.p_pitch = 2, 3, 6, 8, 1, 16
+    for f in ("alias", "alias_lo", "P", "lead", "status", "counters", "reduce"):
         setattr(ks, f, 4096)
     t = ctypes.c_void_p(4096)
     assert lib.mc_negf_walk(ctypes.byref(ks), 1, 0, 2, 0, 10, 10, t, z) == M.EINVAL      # lead
@@ -94,7 +94,12 @@ def test_host_validation_rejects_before_any_gpu_call():
     out = (ctypes.c_double * 2)()
     assert lib.mc_negf_current(ctypes.byref(ks), 0, 0, z, z, z, z,
                                ctypes.cast(out, ctypes.POINTER(ctypes.c_double)), z) == M.EINVAL
-    assert lib.mc_negf_grad(ctypes.byref(ks), z, z, None, z) == M.ENOTIMPL
+    assert lib.mc_negf_grad(ctypes.byref(ks), 0, z, z, 0, z, z, None, z) == M.EINVAL
+    assert lib.mc_negf_grad(ctypes.byref(ks), 2, t, t, 1 << 40, t, t,
+                            ctypes.cast(out, ctypes.POINTER(ctypes.c_double)), z) == M.EINVAL  # lead
+    gb = ctypes.c_uint64(0)
+    assert lib.mc_negf_grad_workspace_bytes(ctypes.byref(ks), ctypes.byref(gb)) == M.OK
+    assert gb.value >= 3 * 6 * 16 * 16  # three complex N x p_pitch arrays at nE = 1
 
 
 def test_energy_grid_is_midpoint():
