@@ -51,8 +51,7 @@ def build(verbose: bool = False) -> str:
         msg = "\n".join(f"--- {s}\n{o}" for s, o in failed)
         raise RuntimeError(f"hipcc failed:\n{msg}")
     tmp = LIB + ".tmp"
-    subprocess.check_call([cc, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs,
-                           "-lrocblas"])
+    subprocess.check_call([cc, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs])
     os.replace(tmp, LIB)
     return LIB
 

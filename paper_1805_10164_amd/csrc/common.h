@@ -55,15 +55,16 @@ Layout make_layout(int W, int L, int nE);
 
 // gradient workspace (caller-owned, separate from the build workspace)
 struct GradBuffers {
-    double2* G;   // [nE][N][ld] complex G, row-major
-    double2* H;   // [nE][N][ld] G diag(v) on the fast index
-    double2* Q;   // [nE][N][ld] conj(G) diag(v) G, Q[i][a] = Q_ai
-    double* xl;   // [nE][2][ld] x, lambda
-    double* gV;   // [nE][N] dT/dV per energy
-    double* gG;   // [nE][N] dT/dgamma per energy
-    double* T;    // [nE] DIRECT transmissions (scratch)
-    double* sig;  // [nE] (zero)
-    int64_t ld;
+    double2* G;       // [nE][N][ld] complex G, row-major
+    double2* Y;       // [nE][N][ldY] adjoint solves, column c: Q (c < N) or R (c = N + b)
+    double2* part_k;  // [nE][2][N] dense and diagonal parts of K per site
+    double* part_p;   // [nE][2][N] (P v)_i, (P u)_i
+    double* xl;       // [nE][2][ld] x, lambda
+    double* gV;       // [nE][N] dT/dV per energy
+    double* gG;       // [nE][N] dT/dgamma per energy
+    double* T;        // [nE] DIRECT transmissions (scratch)
+    double* sig;      // [nE] (zero)
+    int64_t ld, ldY;
 };
 uint64_t grad_layout(const mcnegf_kernel& k, void* base, GradBuffers* out);
 

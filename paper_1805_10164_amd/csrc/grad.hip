@@ -16,12 +16,15 @@
 // and dG = G dV G (dA = -dV), so dT/dV_i = Re K_i with K = diag(G Psi G); a change of
 // gamma_i changes A by (i/2) e_i e_i^T, giving Im K_i / 2, plus the explicit terms
 //   lambda_i w_p(i) + x_i w_q(i) - lambda_i A_ii x_i + lambda_i (P v)_i + x_i (P u)_i.
-// G is complex symmetric, so G_ij = G_ji and Q = conj(G) diag(v) G is Hermitian; the dense
-// part of K is 2 sum_a G_ia u_a Q_ai, with Q from one batched complex GEMM.
-#include <rocblas/rocblas.h>
-
-#include <mutex>
-
+// G is complex symmetric (G_ij = G_ji), so with Q = conj(G) diag(v) G and R = conj(G) diag(u) G
+//   dense part of K_i = 2 sum_a G_ia u_a Q_ai,
+//   lead parts:  sum_j G_ij u_j conj(G_{j,sp+b}) = conj(R_{i,sp+b}),
+//                sum_j G_ij v_j conj(G_{j,sq+b}) = conj(Q_{i,sq+b}).
+// A column of Q or R is conj(A)^{-1} applied to d o G_{:,c} (A = E - H - Sigma, block
+// tridiagonal with off-diagonal blocks t I), solved by the block LU of A that the stored
+// left-connected blocks gL_k provide:
+//   forward   y_k = conj(gL_k) (h_k - t y_{k-1}),   backward  q_k = y_k - t conj(gL_k) q_{k+1},
+// O(N W) per column instead of a dense O(N^2) product.
 #include "common.h"
 
 namespace mcnegf {
@@ -101,29 +104,114 @@ __global__ void __launch_bounds__(256) backsolve_kernel(const double* __restrict
     }
 }
 
-// H[i][b] = G[i][b] v_b with v = gamma x (row-major, pitch ld; columns < N).
-__global__ void grad_scale_kernel(const double2* __restrict__ Gc, const double* __restrict__ xl,
-                                  const double* __restrict__ gamma, int N, int64_t ld,
-                                  double2* __restrict__ H) {
-    const int e = blockIdx.z;
-    const int i = blockIdx.y;
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= N) return;
-    const double vb = gamma[b] * xl[(size_t)e * 2 * ld + b];
-    const size_t at = ((size_t)e * N + i) * ld + b;
-    const double2 g = Gc[at];
-    H[at] = cmk(g.x * vb, g.y * vb);
+// out = conj(M) in for a W x W block M (row-major; uniform across the wavefront).
+template <int W>
+__device__ inline void conj_block_matvec(double2 (&out)[W], const double2 (&in)[W],
+                                         const double2* __restrict__ M) {
+#pragma unroll
+    for (int y = 0; y < W; ++y) {
+        double2 acc = cmk(0.0, 0.0);
+#pragma unroll
+        for (int x = 0; x < W; ++x) cfma(acc, cconj(M[y * W + x]), in[x]);
+        out[y] = acc;
+    }
 }
 
-// Per energy and row i: K_i and the explicit gamma terms (see the top of the file).
-// Threads run over i, the loop over j reads G[j][i] = G_ij and Q_mem[j][i] = Q_ij (both
-// coalesced) and the slice entries G[j][sp..], G[j][sq..] (uniform).
+// One thread per right-hand side c of one energy: c < N is column c of Q (d = v), c = N + b
+// is column sp + b of R (d = u).  The forward sweep keeps y in Y[.][c]; the backward sweep
+// overwrites it with q only where the assembly reads it (columns sq.. sq+W-1 and N..N+W-1),
+// and for c < N accumulates, over the rows a of the column,
+//   kd = sum_a G_ac u_a Q_ac,  kg = sum_a G_ac^2 u_a x_a,  pv = sum_a |G_ac|^2 v_a,  pu (u).
+template <int W>
+__global__ void __launch_bounds__(256) adjoint_solve_kernel(
+    const double2* __restrict__ gL, const double2* __restrict__ Gc, const double* __restrict__ xl,
+    const double* __restrict__ gamma, int L, double t, int64_t ld, int64_t ldY,
+    uint32_t inject_lead, double2* __restrict__ Y, double2* __restrict__ part_k,
+    double* __restrict__ part_p) {
+    const int N = W * L;
+    const int NC = N + W;
+    const int e = blockIdx.y;
+    if (blockIdx.x * 256 + (threadIdx.x & ~63) >= NC) return;  // whole wavefront idle
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    const bool valid = c < NC;
+    const bool dense = c < N;
+    const int sp = inject_lead == 0 ? 0 : (L - 1) * W;
+    const int sq = inject_lead == 0 ? (L - 1) * W : 0;
+    const int col = dense ? c : (valid ? sp + (c - N) : 0);
+    const bool keep_q = valid && (!dense || (c >= sq && c < sq + W));
+    const int cl = valid ? c : 0;  // column that idle lanes of a partial wavefront read
+    const double2* Ge = Gc + (size_t)e * N * ld;
+    double2* Ye = Y + (size_t)e * N * ldY;
+    const double* xe = xl + (size_t)e * 2 * ld;
+    const double* le = xe + ld;
+    const double2* gLe = gL + (size_t)e * L * W * W;
+
+    double2 y[W], z[W];
+#pragma unroll
+    for (int r = 0; r < W; ++r) y[r] = cmk(0.0, 0.0);
+    for (int k = 0; k < L; ++k) {
+#pragma unroll
+        for (int r = 0; r < W; ++r) {
+            const int row = k * W + r;
+            const double d = gamma[row] * (dense ? xe[row] : le[row]);
+            const double2 g = Ge[(size_t)row * ld + col];
+            z[r] = cmk(fma(d, g.x, -t * y[r].x), fma(d, g.y, -t * y[r].y));
+        }
+        conj_block_matvec<W>(y, z, gLe + (size_t)k * W * W);
+        if (valid) {
+#pragma unroll
+            for (int r = 0; r < W; ++r) Ye[(size_t)(k * W + r) * ldY + c] = y[r];
+        }
+    }
+    // y now holds y_{L-1} = q_{L-1}
+    double2 kd = cmk(0.0, 0.0), kg = cmk(0.0, 0.0);
+    double pv = 0.0, pu = 0.0;
+    for (int k = L - 1; k >= 0; --k) {
+        if (k < L - 1) {
+            conj_block_matvec<W>(z, y, gLe + (size_t)k * W * W);
+#pragma unroll
+            for (int r = 0; r < W; ++r) {
+                const double2 yk = Ye[(size_t)(k * W + r) * ldY + cl];
+                y[r] = cmk(fma(-t, z[r].x, yk.x), fma(-t, z[r].y, yk.y));
+            }
+        }
+        if (keep_q) {
+#pragma unroll
+            for (int r = 0; r < W; ++r) Ye[(size_t)(k * W + r) * ldY + c] = y[r];
+        }
+        if (dense) {
+#pragma unroll
+            for (int r = 0; r < W; ++r) {
+                const int row = k * W + r;
+                const double2 g = Ge[(size_t)row * ld + col];
+                const double gm = gamma[row];
+                const double ua = gm * le[row], va = gm * xe[row];
+                cfma(kd, cscale(g, ua), y[r]);
+                kg = cadd(kg, cscale(cmul(g, g), ua * xe[row]));
+                const double p = cabs2(g);
+                pv = fma(p, va, pv);
+                pu = fma(p, ua, pu);
+            }
+        }
+    }
+    if (dense) {
+        part_k[((size_t)e * 2 + 0) * N + c] = kd;
+        part_k[((size_t)e * 2 + 1) * N + c] = kg;
+        part_p[((size_t)e * 2 + 0) * N + c] = pv;
+        part_p[((size_t)e * 2 + 1) * N + c] = pu;
+    }
+}
+
+// Per energy and site i: K_i and the explicit gamma terms (see the top of the file), from
+// the column partials of adjoint_solve_kernel, the rows i of Q (columns sq..) and R
+// (columns N..) in Y, and the slice entries G_{sp+c,i}, G_{sq+c,i}.
 template <int W>
 __global__ void __launch_bounds__(256) grad_assemble_kernel(
-    const double2* __restrict__ Gc, const double2* __restrict__ Q, const double* __restrict__ xl,
+    const double2* __restrict__ Gc, const double2* __restrict__ Y, const double* __restrict__ xl,
     const double* __restrict__ gamma, const double* __restrict__ wL, const double* __restrict__ wR,
     const double* __restrict__ Adiag, const double* __restrict__ gam_lead,
-    const double2* __restrict__ corner, int L, int64_t ld, uint32_t inject_lead,
+    const double2* __restrict__ corner, const double2* __restrict__ part_k,
+    const double* __restrict__ part_p, int L, int64_t ld, int64_t ldY, uint32_t inject_lead,
     double* __restrict__ gV, double* __restrict__ gG) {
     constexpr int WW = W * W;
     __shared__ double2 psi5[WW];  // Psi5[a][b], a in slice q, b in slice p
@@ -150,46 +238,23 @@ __global__ void __launch_bounds__(256) grad_assemble_kernel(
     __syncthreads();
     if (i >= N) return;
     const double2* Ge = Gc + (size_t)e * N * ld;
-    const double2* Qe = Q + (size_t)e * N * ld;
+    const double2* Yi = Y + ((size_t)e * N + i) * ldY;
     const double* xe = xl + (size_t)e * 2 * ld;
     const double* le = xe + ld;
-    double2 kd = cmk(0.0, 0.0), kg = cmk(0.0, 0.0);
-    double2 al[W], be[W];
-#pragma unroll
-    for (int b = 0; b < W; ++b) {
-        al[b] = cmk(0.0, 0.0);
-        be[b] = cmk(0.0, 0.0);
-    }
-    double pv = 0.0, pu = 0.0;
-    for (int j = 0; j < N; ++j) {
-        const double2 gij = Ge[(size_t)j * ld + i];
-        const double2 qji = Qe[(size_t)j * ld + i];  // Q_mem[j][i] = Q_ij; Q_ji = conj(Q_ij)
-        const double gj = gamma[j];
-        const double uj = gj * le[j], vj = gj * xe[j];
-        // dense: G_ij u_j Q_ji
-        const double2 gu = cscale(gij, uj);
-        kd = cadd(kd, cmul(gu, cconj(qji)));
-        // diagonal: G_ij^2 u_j x_j
-        kg = cadd(kg, cscale(cmul(gij, gij), uj * xe[j]));
-        const double pij = cabs2(gij);
-        pv = fma(pij, vj, pv);
-        pu = fma(pij, uj, pu);
-        const double2 gv = cscale(gij, vj);
-#pragma unroll
-        for (int b = 0; b < W; ++b) {
-            al[b] = cadd(al[b], cmul(gu, cconj(Ge[(size_t)j * ld + sp + b])));
-            be[b] = cadd(be[b], cmul(gv, cconj(Ge[(size_t)j * ld + sq + b])));
-        }
-    }
+    const double2 kd = part_k[((size_t)e * 2 + 0) * N + i];
+    const double2 kg = part_k[((size_t)e * 2 + 1) * N + i];
+    const double pv = part_p[((size_t)e * 2 + 0) * N + i];
+    const double pu = part_p[((size_t)e * 2 + 1) * N + i];
     double2 K = cadd(cscale(kd, 2.0), cmk(2.0 * kg.y, -2.0 * kg.x));  // 2 kd - 2i kg
-    // lead terms: 2 sum_b al_b (Gamma_p G_{p,i})_b + 2 sum_b be_b (Gamma_q G_{q,i})_b
+    // lead terms: 2 sum_b al_b (Gamma_p G_{p,i})_b + 2 sum_b be_b (Gamma_q G_{q,i})_b with
+    // al_b = conj(R_{i,sp+b}), be_b = conj(Q_{i,sq+b})
     double2 gpi[W], gqi[W];
 #pragma unroll
     for (int c = 0; c < W; ++c) {
         gpi[c] = Ge[(size_t)(sp + c) * ld + i];
         gqi[c] = Ge[(size_t)(sq + c) * ld + i];
     }
-#pragma unroll
+#pragma unroll 1
     for (int b = 0; b < W; ++b) {
         double2 tp = cmk(0.0, 0.0), tq = cmk(0.0, 0.0);
 #pragma unroll
@@ -197,15 +262,17 @@ __global__ void __launch_bounds__(256) grad_assemble_kernel(
             tp = cadd(tp, cscale(gpi[c], gm[b * W + c]));
             tq = cadd(tq, cscale(gqi[c], gm[b * W + c]));
         }
-        K = cadd(K, cscale(cadd(cmul(al[b], tp), cmul(be[b], tq)), 2.0));
+        const double2 al = cconj(Yi[N + b]);
+        const double2 be = cconj(Yi[sq + b]);
+        K = cadd(K, cscale(cadd(cmul(al, tp), cmul(be, tq)), 2.0));
     }
     // T_qp term: sum_{a in q, b in p} G_ia Psi5_ab G_bi
-#pragma unroll
+#pragma unroll 1
     for (int a = 0; a < W; ++a) {
         double2 s = cmk(0.0, 0.0);
 #pragma unroll
         for (int b = 0; b < W; ++b) s = cadd(s, cmul(psi5[a * W + b], gpi[b]));
-        K = cadd(K, cmul(gqi[a], s));
+        K = cadd(K, cmul(Ge[(size_t)(sq + a) * ld + i], s));
     }
     const double wp = inject_lead == 0 ? wL[(size_t)e * N + i] : wR[(size_t)e * N + i];
     const double wq = inject_lead == 0 ? wR[(size_t)e * N + i] : wL[(size_t)e * N + i];
@@ -236,27 +303,23 @@ __global__ void grad_reduce_kernel(const double* __restrict__ gV, const double* 
     dG[i] = b;
 }
 
-static rocblas_handle blas_handle(hipError_t& err) {
-    static std::mutex mu;
-    static rocblas_handle handles[64] = {};
-    int dev = 0;
-    if ((err = hipGetDevice(&dev)) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
-    std::lock_guard<std::mutex> lock(mu);
-    if (!handles[dev] && rocblas_create_handle(&handles[dev]) != rocblas_status_success)
-        handles[dev] = nullptr;
-    if (!handles[dev]) err = hipErrorNotInitialized;
-    return handles[dev];
-}
-
 template <int W>
-static hipError_t launch_assemble_w(const mcnegf_kernel& k, const GradBuffers& gb,
-                                    uint32_t inject_lead, hipStream_t s) {
+static hipError_t launch_adjoint_w(const mcnegf_kernel& k, const GradBuffers& gb,
+                                   uint32_t inject_lead, hipStream_t s) {
+    {
+        MCNEGF_TIMED("adjoint_solve_kernel", s);
+        hipLaunchKernelGGL(adjoint_solve_kernel<W>, dim3((k.N + W + 255) / 256, k.nE), dim3(256),
+                           0, s, reinterpret_cast<const double2*>(k.gL), gb.G, gb.xl, k.gamma, k.L,
+                           k.t, gb.ld, gb.ldY, inject_lead, gb.Y, gb.part_k, gb.part_p);
+    }
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
     {
         MCNEGF_TIMED("grad_assemble_kernel", s);
         hipLaunchKernelGGL(grad_assemble_kernel<W>, dim3((k.N + 255) / 256, k.nE), dim3(256), 0,
-                           s, gb.G, gb.Q, gb.xl, k.gamma, k.wL, k.wR, k.Adiag, k.gam_lead,
-                           reinterpret_cast<const double2*>(k.corner), k.L, gb.ld, inject_lead,
-                           gb.gV, gb.gG);
+                           s, gb.G, gb.Y, gb.xl, k.gamma, k.wL, k.wR, k.Adiag, k.gam_lead,
+                           reinterpret_cast<const double2*>(k.corner), gb.part_k, gb.part_p, k.L,
+                           gb.ld, gb.ldY, inject_lead, gb.gV, gb.gG);
     }
     return hipGetLastError();
 }
@@ -273,34 +336,11 @@ hipError_t launch_grad(const mcnegf_kernel& k, const GradBuffers& gb, uint32_t i
     }
     if ((err = hipGetLastError()) != hipSuccess) return err;
     if ((err = launch_fullinv_store_g(k, gb.G, gb.ld, s)) != hipSuccess) return err;
-    {
-        MCNEGF_TIMED("grad_scale_kernel", s);
-        hipLaunchKernelGGL(grad_scale_kernel, dim3((N + 255) / 256, N, nE), dim3(256), 0, s, gb.G,
-                           gb.xl, k.gamma, N, gb.ld, gb.H);
-    }
-    if ((err = hipGetLastError()) != hipSuccess) return err;
-    {
-        // Q = conj(G) H in column-major terms: the row-major arrays of the symmetric G and of
-        // H read column-major are G and diag(v) G; op C on G gives G^+ = conj(G); Q lands as
-        // Q_mem[i][a] = Q_ai.
-        rocblas_handle h = blas_handle(err);
-        if (!h) return err;
-        if (rocblas_set_stream(h, s) != rocblas_status_success) return hipErrorInvalidValue;
-        const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
-        const rocblas_stride st = (rocblas_stride)N * gb.ld;
-        MCNEGF_TIMED("grad_zgemm", s);
-        const rocblas_status rs = rocblas_zgemm_strided_batched(
-            h, rocblas_operation_conjugate_transpose, rocblas_operation_none, N, N, N, &one,
-            reinterpret_cast<const rocblas_double_complex*>(gb.G), (rocblas_int)gb.ld, st,
-            reinterpret_cast<const rocblas_double_complex*>(gb.H), (rocblas_int)gb.ld, st, &zero,
-            reinterpret_cast<rocblas_double_complex*>(gb.Q), (rocblas_int)gb.ld, st, nE);
-        if (rs != rocblas_status_success) return hipErrorLaunchFailure;
-    }
     switch (k.W) {
-#define MCNEGF_CASE(w)                                                         \
-    case w:                                                                    \
-        if ((err = launch_assemble_w<w>(k, gb, inject_lead, s)) != hipSuccess) \
-            return err;                                                        \
+#define MCNEGF_CASE(w)                                                        \
+    case w:                                                                   \
+        if ((err = launch_adjoint_w<w>(k, gb, inject_lead, s)) != hipSuccess) \
+            return err;                                                       \
         break;
         MCNEGF_CASE(1) MCNEGF_CASE(2) MCNEGF_CASE(3) MCNEGF_CASE(4) MCNEGF_CASE(5)
         MCNEGF_CASE(6) MCNEGF_CASE(7) MCNEGF_CASE(8) MCNEGF_CASE(9) MCNEGF_CASE(10)

@@ -96,7 +96,7 @@ static int32_t status_to_code(uint32_t flags, bool mc) {
 }
 
 uint64_t grad_layout(const mcnegf_kernel& k, void* base, GradBuffers* out) {
-    const int64_t N = k.N, nE = k.nE, ld = k.p_pitch;
+    const int64_t N = k.N, nE = k.nE, ld = k.p_pitch, ldY = round_up(N + k.W, 16);
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) {
         const uint64_t at = off;
@@ -104,8 +104,9 @@ uint64_t grad_layout(const mcnegf_kernel& k, void* base, GradBuffers* out) {
         return at;
     };
     const uint64_t oG = take((uint64_t)nE * N * ld * 16);
-    const uint64_t oH = take((uint64_t)nE * N * ld * 16);
-    const uint64_t oQ = take((uint64_t)nE * N * ld * 16);
+    const uint64_t oY = take((uint64_t)nE * N * ldY * 16);
+    const uint64_t oK = take((uint64_t)nE * 2 * N * 16);
+    const uint64_t oP = take((uint64_t)nE * 2 * N * 8);
     const uint64_t oX = take((uint64_t)nE * 2 * ld * 8);
     const uint64_t oV = take((uint64_t)nE * N * 8);
     const uint64_t oGg = take((uint64_t)nE * N * 8);
@@ -114,14 +115,16 @@ uint64_t grad_layout(const mcnegf_kernel& k, void* base, GradBuffers* out) {
     if (out) {
         char* b = static_cast<char*>(base);
         out->G = reinterpret_cast<double2*>(b + oG);
-        out->H = reinterpret_cast<double2*>(b + oH);
-        out->Q = reinterpret_cast<double2*>(b + oQ);
+        out->Y = reinterpret_cast<double2*>(b + oY);
+        out->part_k = reinterpret_cast<double2*>(b + oK);
+        out->part_p = reinterpret_cast<double*>(b + oP);
         out->xl = reinterpret_cast<double*>(b + oX);
         out->gV = reinterpret_cast<double*>(b + oV);
         out->gG = reinterpret_cast<double*>(b + oGg);
         out->T = reinterpret_cast<double*>(b + oT);
         out->sig = reinterpret_cast<double*>(b + oS);
         out->ld = ld;
+        out->ldY = ldY;
     }
     return off;
 }

@@ -57,6 +57,11 @@ WIRE_W10_L100 = Workload(name="wire_W10_L100", W=10, L=100, eta=0.05, disorder=0
                          emin=-3.5, emax=3.5, n_energies=256, walkers_per_energy=1_000_000)
 WIRE_ETAS = (0.01, 0.05, 0.1)
 
+# Differentiation workload: W = 16, L = 200 (N = 3200), eta = 0.02 t, disorder U[-0.5 t, 0.5 t],
+# 128 energies in [-3.5 t, 3.5 t]; dI/dV_i for every site and dI/deta = sum_i dI/dgamma_i.
+DIFF_W16_L200 = Workload(name="diff_W16_L200", W=16, L=200, eta=0.02, disorder=0.5,
+                         emin=-3.5, emax=3.5, n_energies=128, walkers_per_energy=0)
+
 
 def onsite(w: Workload) -> np.ndarray:
     """Onsite energies V_i (float64, length N, slice-major i = x*W + y).

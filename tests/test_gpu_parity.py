@@ -263,6 +263,28 @@ def test_grad_matches_adjoint_oracle(name):
         assert rel(dg, dgref) < 1e-9, (name, lead, rel(dg, dgref))
 
 
+def test_full_size_grad_on_sampled_energies():
+    # The W = 16 x L = 200 (N = 3200) differentiation workload with all 128 energies in one
+    # call; weights vanish except at two sampled energies, which the oracle differentiates
+    # (dense N = 3200 solves).  Both injection sides.
+    wl = inputs.DIFF_W16_L200
+    E, wq = M.energy_grid(wl.emin, wl.emax, wl.n_energies)
+    idx = [21, 90]
+    w = np.zeros_like(wq)
+    w[idx] = wq[idx]
+    c = dict(W=wl.W, L=wl.L, V=inputs.onsite(wl), g=inputs.dephasing(wl), E=E, w=w,
+             lead_model=0, gamma_l=0.0)
+    k = gpu_build(c)
+    Iref, dVref, dgref = OG.adjoint(wl.W, wl.L, 1.0, c["V"], c["g"], E[idx], w[idx], 0, 1e-10,
+                                    0.0)
+    for lead in (0, 1):
+        st, I, dV, dg = gpu_grad(k, c, lead)
+        assert st == M.OK
+        assert abs(I - Iref) <= 1e-10 * abs(Iref)
+        assert rel(dV, dVref) < 1e-9, rel(dV, dVref)
+        assert rel(dg, dgref) < 1e-9, rel(dg, dgref)
+
+
 def test_grad_single_site_closed_form():
     # N = 1, wide-band leads: T = g G_t / 2 / ((E - V)^2 + G_t^2 / 4) with G_t = 2 g + gamma,
     # g = 0.4; differentiate the closed form in V (at V = 0) and gamma.
