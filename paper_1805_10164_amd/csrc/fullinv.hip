@@ -4,17 +4,19 @@
 // off-diagonal blocks t I, which gives
 //   above the diagonal  G_{k,l} = -t gL_k G_{k+1,l}   (k < l),
 //   below the diagonal  G_{k,l} = -t gR_k G_{k-1,l}   (k > l),
-// starting from the diagonal block G_{l,l}.  Each lane owns one column j of G (so a
-// wavefront owns 64 consecutive columns) and keeps its W-vector G_{k, j} in registers while
-// the wavefront sweeps k down and then up the wire; the W x W factors gL_k, gR_k are the
-// same for every lane and are read as scalars.  Nothing of G is written except
+// starting from the diagonal block G_{l,l}.  Each lane owns one column j of G (a workgroup
+// is one wavefront owning 64 consecutive columns) and keeps its W-vector G_{k, j} in
+// registers while the wavefront sweeps k down and then up the wire; the W x W factors gL_k,
+// gR_k are the same for every lane: the wavefront stages them in LDS one slice ahead
+// (double-buffered) and every lane reads the same address (a broadcast), which keeps the
+// block operands off the scalar path and the texture units.  Nothing of G is written except
 //   P[i][j]  = |G_ij|^2                      (probe-to-probe weights, step 6', Eq. (75)),
 //   wL[j]    = <psi_j|Gamma_L|psi_j>, wR[j]  (psi_j = G|j>, exit weights, Eq. (76)),
 //   corner   = G_{L-1,0} and G_{0,L-1}       (lead-to-lead transmissions).
 // Rows of P are written by 64 lanes at consecutive columns (coalesced 512-byte segments).
 // The block products run on the FP64 VALU: at W <= 16 the operands live in registers and
-// scalar registers, and gfx950's FP64 matrix-core rate equals its FP64 FMA rate, so padding
-// W up to a 16x16x4 MFMA shape would only add work.
+// LDS, and gfx950's FP64 matrix-core rate equals its FP64 FMA rate, so padding W up to a
+// 16x16x4 MFMA shape would only add work.
 #include "common.h"
 
 namespace mcnegf {
@@ -31,24 +33,38 @@ __device__ inline double quad_form(const double2 (&v)[W], const double* __restri
     return acc;
 }
 
+typedef __attribute__((address_space(3))) double lds_double;
+
+// v <- mt * M v for a W x W complex block M staged in LDS as (re, im) pairs, row-major.
 template <int W>
-__device__ inline void block_matvec(double2 (&v)[W], const double2* __restrict__ M, double mt) {
+__device__ inline void block_matvec(double2 (&v)[W], const lds_double* M, double mt) {
     double2 nv[W];
 #pragma unroll
     for (int y = 0; y < W; ++y) {
         double2 acc = cmk(0.0, 0.0);
 #pragma unroll
-        for (int x = 0; x < W; ++x) cfma(acc, M[y * W + x], v[x]);
+        for (int x = 0; x < W; ++x) cfma(acc, cmk(M[2 * (y * W + x)], M[2 * (y * W + x) + 1]), v[x]);
         nv[y] = cscale(acc, mt);
     }
 #pragma unroll
     for (int y = 0; y < W; ++y) v[y] = nv[y];
 }
 
+// The 64 lanes copy the W x W block src into the LDS buffer dst.
+template <int W>
+__device__ inline void stage_block(lds_double* dst, const double2* __restrict__ src, int lane) {
+#pragma unroll
+    for (int i = lane; i < W * W; i += 64) {
+        const double2 v = src[i];
+        dst[2 * i] = v.x;
+        dst[2 * i + 1] = v.y;
+    }
+}
+
 // STORE_G: write the complex blocks of G (row-major, pitch ldG, Gc) instead of |G_ij|^2,
 // the exit weights and the corners.
 template <int W, bool STORE_G>
-__global__ void __launch_bounds__(256) fullinv_kernel(const double2* __restrict__ gL,
+__global__ void __launch_bounds__(64) fullinv_kernel(const double2* __restrict__ gL,
                                                       const double2* __restrict__ gR,
                                                       const double2* __restrict__ Gd,
                                                       const double* __restrict__ gam_lead,
@@ -60,9 +76,9 @@ __global__ void __launch_bounds__(256) fullinv_kernel(const double2* __restrict_
                                                       double2* __restrict__ Gc, int64_t ldG) {
     const int N = W * L;
     const int e = blockIdx.y;
-    const int wave_first = blockIdx.x * 256 + (threadIdx.x & ~63);
-    if (wave_first >= N) return;  // whole wavefront idle
-    const int col = blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x;
+    const int wave_first = blockIdx.x * 64;
+    const int col = wave_first + lane;
     const bool valid = col < N;
     const int colc = valid ? col : N - 1;
     const int l = colc / W;
@@ -79,13 +95,20 @@ __global__ void __launch_bounds__(256) fullinv_kernel(const double2* __restrict_
     double2* cRL = corner + (size_t)e * 2 * W * W;
     double2* cLR = cRL + W * W;
     const double mt = -t;
+    constexpr int BS = 2 * W * W;  // doubles per staged block
+    __shared__ double Ms_raw[2 * BS];
+    lds_double* Ms = (lds_double*)Ms_raw;
 
     double2 v[W];
     // ---- downward: k = l, l+1, ..., L-1 -------------------------------------------------
 #pragma unroll
     for (int y = 0; y < W; ++y) v[y] = cmk(0.0, 0.0);
+    stage_block<W>(Ms, gRe + (size_t)kmin * W * W, lane);
     for (int k = kmin; k < L; ++k) {
-        block_matvec<W>(v, gRe + (size_t)k * W * W, mt);
+        __syncthreads();  // block k staged; the other buffer is free
+        const int b = (k - kmin) & 1;
+        if (k + 1 < L) stage_block<W>(Ms + (b ^ 1) * BS, gRe + (size_t)(k + 1) * W * W, lane);
+        block_matvec<W>(v, Ms + b * BS, mt);
         if (k == l) {
 #pragma unroll
             for (int y = 0; y < W; ++y) v[y] = Gde[(size_t)k * W * W + y * W + y0];
@@ -116,8 +139,13 @@ __global__ void __launch_bounds__(256) fullinv_kernel(const double2* __restrict_
     // ---- upward: k = l, l-1, ..., 0 ------------------------------------------------------
 #pragma unroll
     for (int y = 0; y < W; ++y) v[y] = cmk(0.0, 0.0);
+    __syncthreads();  // downward reads done
+    stage_block<W>(Ms, gLe + (size_t)kmax * W * W, lane);
     for (int k = kmax; k >= 0; --k) {
-        block_matvec<W>(v, gLe + (size_t)k * W * W, mt);
+        __syncthreads();
+        const int b = (kmax - k) & 1;
+        if (k > 0) stage_block<W>(Ms + (b ^ 1) * BS, gLe + (size_t)(k - 1) * W * W, lane);
+        block_matvec<W>(v, Ms + b * BS, mt);
         if (k == l) {
 #pragma unroll
             for (int y = 0; y < W; ++y) v[y] = Gde[(size_t)k * W * W + y * W + y0];
@@ -149,10 +177,10 @@ __global__ void __launch_bounds__(256) fullinv_kernel(const double2* __restrict_
 template <int W, bool STORE_G>
 static hipError_t launch_fullinv_w(const mcnegf_kernel& k, double2* Gc, int64_t ldG,
                                    hipStream_t s) {
-    dim3 grid((k.N + 255) / 256, k.nE);
+    dim3 grid((k.N + 63) / 64, k.nE);
     {
         MCNEGF_TIMED(STORE_G ? "fullinv_store_g_kernel" : "fullinv_kernel", s);
-        hipLaunchKernelGGL((fullinv_kernel<W, STORE_G>), grid, dim3(256), 0, s,
+        hipLaunchKernelGGL((fullinv_kernel<W, STORE_G>), grid, dim3(64), 0, s,
                            reinterpret_cast<const double2*>(k.gL),
                            reinterpret_cast<const double2*>(k.gR),
                            reinterpret_cast<const double2*>(k.Gd), k.gam_lead, k.L, k.t, k.p_pitch,

@@ -104,15 +104,19 @@ __global__ void __launch_bounds__(256) backsolve_kernel(const double* __restrict
     }
 }
 
-// out = conj(M) in for a W x W block M (row-major; uniform across the wavefront).
+typedef __attribute__((address_space(3))) double lds_double;
+
+// out = conj(M) in for a W x W complex block M (row-major, (re, im) pairs in LDS; the same
+// address on every lane, so each read is a broadcast).
 template <int W>
 __device__ inline void conj_block_matvec(double2 (&out)[W], const double2 (&in)[W],
-                                         const double2* __restrict__ M) {
+                                         const lds_double* M) {
 #pragma unroll
     for (int y = 0; y < W; ++y) {
         double2 acc = cmk(0.0, 0.0);
 #pragma unroll
-        for (int x = 0; x < W; ++x) cfma(acc, cconj(M[y * W + x]), in[x]);
+        for (int x = 0; x < W; ++x)
+            cfma(acc, cmk(M[2 * (y * W + x)], -M[2 * (y * W + x) + 1]), in[x]);
         out[y] = acc;
     }
 }
@@ -123,7 +127,7 @@ __device__ inline void conj_block_matvec(double2 (&out)[W], const double2 (&in)[
 // and for c < N accumulates, over the rows a of the column,
 //   kd = sum_a G_ac u_a Q_ac,  kg = sum_a G_ac^2 u_a x_a,  pv = sum_a |G_ac|^2 v_a,  pu (u).
 template <int W>
-__global__ void __launch_bounds__(256) adjoint_solve_kernel(
+__global__ void __launch_bounds__(64) adjoint_solve_kernel(
     const double2* __restrict__ gL, const double2* __restrict__ Gc, const double* __restrict__ xl,
     const double* __restrict__ gamma, int L, double t, int64_t ld, int64_t ldY,
     uint32_t inject_lead, double2* __restrict__ Y, double2* __restrict__ part_k,
@@ -131,25 +135,43 @@ __global__ void __launch_bounds__(256) adjoint_solve_kernel(
     const int N = W * L;
     const int NC = N + W;
     const int e = blockIdx.y;
-    if (blockIdx.x * 256 + (threadIdx.x & ~63) >= NC) return;  // whole wavefront idle
-    const int c = blockIdx.x * 256 + threadIdx.x;
+    // One wavefront per workgroup; the blocks gL_k are staged in LDS one slice ahead
+    // (double-buffered, one barrier per slice); idle lanes compute on column 0.
+    __shared__ double Ms_raw[2 * 2 * W * W];  // two buffers of W x W (re, im)
+    const int tid = threadIdx.x;
+    const int c = blockIdx.x * 64 + tid;
     const bool valid = c < NC;
     const bool dense = c < N;
     const int sp = inject_lead == 0 ? 0 : (L - 1) * W;
     const int sq = inject_lead == 0 ? (L - 1) * W : 0;
     const int col = dense ? c : (valid ? sp + (c - N) : 0);
     const bool keep_q = valid && (!dense || (c >= sq && c < sq + W));
-    const int cl = valid ? c : 0;  // column that idle lanes of a partial wavefront read
+    const int cl = valid ? c : 0;  // column that idle lanes read
     const double2* Ge = Gc + (size_t)e * N * ld;
     double2* Ye = Y + (size_t)e * N * ldY;
     const double* xe = xl + (size_t)e * 2 * ld;
     const double* le = xe + ld;
     const double2* gLe = gL + (size_t)e * L * W * W;
+    lds_double* Ms = (lds_double*)Ms_raw;
+    constexpr int BS = 2 * W * W;  // doubles per buffer
+    // the 64 lanes copy block gL_slice into LDS buffer buf
+    auto stage = [&](int buf, int slice) {
+#pragma unroll
+        for (int i = tid; i < W * W; i += 64) {
+            const double2 v = gLe[(size_t)slice * W * W + i];
+            Ms[buf * BS + 2 * i] = v.x;
+            Ms[buf * BS + 2 * i + 1] = v.y;
+        }
+    };
 
     double2 y[W], z[W];
 #pragma unroll
     for (int r = 0; r < W; ++r) y[r] = cmk(0.0, 0.0);
+    stage(0, 0);
     for (int k = 0; k < L; ++k) {
+        __syncthreads();  // block k visible in buffer k & 1; buffer (k + 1) & 1 no longer read
+        const lds_double* cur = Ms + (k & 1) * BS;
+        if (k + 1 < L) stage((k + 1) & 1, k + 1);
 #pragma unroll
         for (int r = 0; r < W; ++r) {
             const int row = k * W + r;
@@ -157,18 +179,24 @@ __global__ void __launch_bounds__(256) adjoint_solve_kernel(
             const double2 g = Ge[(size_t)row * ld + col];
             z[r] = cmk(fma(d, g.x, -t * y[r].x), fma(d, g.y, -t * y[r].y));
         }
-        conj_block_matvec<W>(y, z, gLe + (size_t)k * W * W);
+        conj_block_matvec<W>(y, z, cur);
         if (valid) {
 #pragma unroll
             for (int r = 0; r < W; ++r) Ye[(size_t)(k * W + r) * ldY + c] = y[r];
         }
     }
-    // y now holds y_{L-1} = q_{L-1}
+    // y now holds y_{L-1} = q_{L-1}; the backward sweep stages gL_{L-2}, gL_{L-3}, ...
     double2 kd = cmk(0.0, 0.0), kg = cmk(0.0, 0.0);
     double pv = 0.0, pu = 0.0;
+    __syncthreads();  // forward reads of both buffers done
+    if (L > 1) stage(0, L - 2);
     for (int k = L - 1; k >= 0; --k) {
         if (k < L - 1) {
-            conj_block_matvec<W>(z, y, gLe + (size_t)k * W * W);
+            const int j = L - 2 - k;  // 0, 1, ... : buffer parity
+            __syncthreads();
+            const lds_double* cur = Ms + (j & 1) * BS;
+            if (k > 0) stage((j + 1) & 1, k - 1);
+            conj_block_matvec<W>(z, y, cur);
 #pragma unroll
             for (int r = 0; r < W; ++r) {
                 const double2 yk = Ye[(size_t)(k * W + r) * ldY + cl];
@@ -308,7 +336,7 @@ static hipError_t launch_adjoint_w(const mcnegf_kernel& k, const GradBuffers& gb
                                    uint32_t inject_lead, hipStream_t s) {
     {
         MCNEGF_TIMED("adjoint_solve_kernel", s);
-        hipLaunchKernelGGL(adjoint_solve_kernel<W>, dim3((k.N + W + 255) / 256, k.nE), dim3(256),
+        hipLaunchKernelGGL(adjoint_solve_kernel<W>, dim3((k.N + W + 63) / 64, k.nE), dim3(64),
                            0, s, reinterpret_cast<const double2*>(k.gL), gb.G, gb.xl, k.gamma, k.L,
                            k.t, gb.ld, gb.ldY, inject_lead, gb.Y, gb.part_k, gb.part_p);
     }

@@ -285,6 +285,30 @@ def test_full_size_grad_on_sampled_energies():
         assert rel(dg, dgref) < 1e-9, rel(dg, dgref)
 
 
+def test_autograd_direct_current_and_eta_derivative():
+    # torch.autograd through the library adjoint: dI/dV_i and, with gamma = eta * ones,
+    # dI/deta = sum_i dI/dgamma_i against the dense adjoint; plus a loss that is not I itself.
+    from paper_1805_10164_amd.autograd import direct_current
+    c = case(**GRAD_CASES["w4l13"])
+    N = c["W"] * c["L"]
+    sysm = M.make_system(c["W"], c["L"], 1.0, c["lead_model"], c["gamma_l"], 1e-10)
+    V = torch.tensor(c["V"], dtype=torch.float64, device=DEV, requires_grad=True)
+    eta = torch.tensor(0.1, dtype=torch.float64, device=DEV, requires_grad=True)
+    E = torch.tensor(c["E"], dtype=torch.float64, device=DEV)
+    w = torch.tensor(c["w"], dtype=torch.float64, device=DEV)
+    I = direct_current(sysm, V, eta * torch.ones(N, dtype=torch.float64, device=DEV), E, w)
+    loss = 3.0 * I * I
+    loss.backward()
+    Iref, dVref, dgref = OG.adjoint(c["W"], c["L"], 1.0, c["V"], np.full(N, 0.1), c["E"], c["w"])
+    assert abs(I.item() - Iref) <= 1e-10 * abs(Iref)
+    assert rel(V.grad.cpu().numpy(), 6.0 * Iref * dVref) < 1e-9
+    assert abs(eta.grad.item() - 6.0 * Iref * dgref.sum()) <= 1e-9 * abs(6.0 * Iref * dgref.sum())
+    # no gradient requested: the forward pass runs the plain DIRECT current
+    with torch.no_grad():
+        I2 = direct_current(sysm, V, 0.1 * torch.ones(N, dtype=torch.float64, device=DEV), E, w)
+    assert abs(I2.item() - Iref) <= 1e-10 * abs(Iref)
+
+
 def test_grad_single_site_closed_form():
     # N = 1, wide-band leads: T = g G_t / 2 / ((E - V)^2 + G_t^2 / 4) with G_t = 2 g + gamma,
     # g = 0.4; differentiate the closed form in V (at V = 0) and gamma.
