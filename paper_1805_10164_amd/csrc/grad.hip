@@ -40,67 +40,95 @@ __device__ inline double readlane_dbl(double v, int lane) {
 // L^T xt = y and L^T lt = z with L the Cholesky factor of the bordered scaled probe system
 // (lower part, columns of each 16-block stored permuted) and y, z its bordered rows Np and
 // Np + 1; then x = s xt and lambda = s lt (s_j = M_jj^{-1/2}, vector slot 3).  One workgroup
-// of 256 threads per energy, block columns of 64 from the last one down: the rows below a
-// block contribute by a transposed matrix-vector product (thread = stored column position p
-// x row group), the 64 x 64 diagonal block by back substitution in one wavefront.  xt and
-// lt are solved in place in xl ([nE][2][ld], the solved entries stay in L2); padded entries
-// N..Np-1 are left as solved (zero).
-__global__ void __launch_bounds__(256) backsolve_kernel(const double* __restrict__ Lall,
-                                                        const double* __restrict__ vec, int N,
-                                                        int Np, int64_t ld,
-                                                        double* __restrict__ xl) {
-    __shared__ double part[4][64][2];
+// of 1024 threads per energy, right-looking over block rows of 64 from the last one down:
+//   solve  L_II^T x_I = r_I       (diagonal block staged in LDS, one wavefront, lane per row)
+//   update r_j -= sum_{i in I} L_ij x_i   for every j < 64 I
+// Thread tid owns the stored positions p = tid + 1024 q of r (in registers), so the update
+// reads the rows of block I coalesced with 64 independent loads per position.
+constexpr int BSV_THREADS = 1024;
+constexpr int BSV_Q = kMaxOut / BSV_THREADS;  // positions per thread (Np <= kMaxOut)
+
+__global__ void __launch_bounds__(BSV_THREADS) backsolve_kernel(const double* __restrict__ Lall,
+                                                                const double* __restrict__ vec,
+                                                                int N, int Np, int64_t ld,
+                                                                double* __restrict__ xl) {
+    __shared__ double dg[64][65];
+    __shared__ double rI[2][64];
+    __shared__ double xI[2][64];
     const int e = blockIdx.x;
-    double* sol = xl + (size_t)e * 2 * ld;  // [0, Np): xt, [ld, ld + Np): lt
     const int tid = threadIdx.x;
-    const int p = tid & 63, grp = tid >> 6;
-    const int R = Np + 2;
-    const double* Le = Lall + (size_t)e * R * ld;
-    const int nJ = (Np + 63) / 64;
-    for (int J = nJ - 1; J >= 0; --J) {
-        const int c0 = 64 * J;
-        const int wJ = min(64, Np - c0);
-        double sx = 0.0, sl = 0.0;
-        if (p < wJ) {
-            for (int i = c0 + wJ + grp; i < Np; i += 4) {
-                const double lij = Le[(size_t)i * ld + c0 + p];
-                sx = fma(lij, sol[i], sx);
-                sl = fma(lij, sol[ld + i], sl);
-            }
-        }
-        part[grp][p][0] = sx;
-        part[grp][p][1] = sl;
-        __syncthreads();
-        if (grp == 0) {
-            // lane m: logical column m of the block, stored at position perm16(m)
-            const int m = tid;
-            const int pm = perm16(m);
-            double rx = 0.0, rl = 0.0;
-            if (m < wJ) {
-                rx = Le[(size_t)Np * ld + c0 + pm] -
-                     (part[0][pm][0] + part[1][pm][0] + part[2][pm][0] + part[3][pm][0]);
-                rl = Le[(size_t)(Np + 1) * ld + c0 + pm] -
-                     (part[0][pm][1] + part[1][pm][1] + part[2][pm][1] + part[3][pm][1]);
-            }
-            for (int k = wJ - 1; k >= 0; --k) {  // uniform loop, whole wavefront active
-                const double lkk = Le[(size_t)(c0 + k) * ld + c0 + perm16(k)];
-                const double xk = readlane_dbl(rx, k) / lkk;
-                const double lk = readlane_dbl(rl, k) / lkk;
-                const double lkm = (m < k) ? Le[(size_t)(c0 + k) * ld + c0 + pm] : 0.0;
-                rx = (m == k) ? xk : fma(-lkm, xk, rx);
-                rl = (m == k) ? lk : fma(-lkm, lk, rl);
-            }
-            if (m < wJ) {
-                sol[c0 + m] = rx;
-                sol[ld + c0 + m] = rl;
-            }
-        }
-        __syncthreads();
-    }
+    const double* Le = Lall + (size_t)e * (Np + 2) * ld;
     const double* s = vec + (size_t)e * 4 * N + 3 * N;
-    for (int j = tid; j < N; j += 256) {  // each entry read and written by one thread
-        sol[j] *= s[j];
-        sol[ld + j] *= s[j];
+    double* xo = xl + (size_t)e * 2 * ld;
+    double rx[BSV_Q], rl[BSV_Q];
+#pragma unroll
+    for (int q = 0; q < BSV_Q; ++q) {
+        const int p = tid + BSV_THREADS * q;
+        rx[q] = p < Np ? Le[(size_t)Np * ld + p] : 0.0;
+        rl[q] = p < Np ? Le[(size_t)(Np + 1) * ld + p] : 0.0;
+    }
+    const int nJ = (Np + 63) / 64;
+    for (int I = nJ - 1; I >= 0; --I) {
+        const int c0 = 64 * I;
+        const int wI = min(64, Np - c0);  // a multiple of 16
+        for (int t = tid; t < 64 * 64; t += BSV_THREADS) {
+            const int i = t >> 6, pp = t & 63;
+            dg[i][pp] = (i < wI && pp < wI) ? Le[(size_t)(c0 + i) * ld + c0 + pp] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < BSV_Q; ++q) {
+            const int p = tid + BSV_THREADS * q;
+            if (p >= c0 && p < c0 + wI) {  // logical column perm16(p), row perm16(p) - c0
+                const int m = perm16(p) - c0;
+                rI[0][m] = rx[q];
+                rI[1][m] = rl[q];
+            }
+        }
+        __syncthreads();
+        if (tid < 64) {
+            const int m = tid;         // logical column c0 + m of the block
+            const int pm = perm16(m);  // its stored position
+            double ax = m < wI ? rI[0][m] : 0.0, al = m < wI ? rI[1][m] : 0.0;
+            // lane m holds 1 / L_mm, so the sequential loop below only multiplies
+            const double inv = m < wI ? 1.0 / dg[m][pm] : 0.0;
+            for (int k = wI - 1; k >= 0; --k) {  // uniform loop, whole wavefront active
+                const double ik = readlane_dbl(inv, k);
+                const double xk = readlane_dbl(ax, k) * ik;
+                const double lk = readlane_dbl(al, k) * ik;
+                const double lkm = (m < k) ? dg[k][pm] : 0.0;
+                ax = (m == k) ? xk : fma(-lkm, xk, ax);
+                al = (m == k) ? lk : fma(-lkm, lk, al);
+            }
+            if (m < wI) {
+                xI[0][m] = ax;
+                xI[1][m] = al;
+                if (c0 + m < N) {
+                    xo[c0 + m] = s[c0 + m] * ax;
+                    xo[ld + c0 + m] = s[c0 + m] * al;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < BSV_Q; ++q) {
+            const int p = tid + BSV_THREADS * q;
+            if (p < c0) {
+                double ax = 0.0, al = 0.0;
+                for (int i0 = 0; i0 < wI; i0 += 16) {  // 16 independent loads, then use
+                    double lip[16];
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) lip[i] = Le[(size_t)(c0 + i0 + i) * ld + p];
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        ax = fma(lip[i], xI[0][i0 + i], ax);
+                        al = fma(lip[i], xI[1][i0 + i], al);
+                    }
+                }
+                rx[q] -= ax;
+                rl[q] -= al;
+            }
+        }
+        __syncthreads();  // dg, rI and xI are rewritten for the next block
     }
 }
 
@@ -359,7 +387,8 @@ hipError_t launch_grad(const mcnegf_kernel& k, const GradBuffers& gb, uint32_t i
     hipError_t err;
     {
         MCNEGF_TIMED("backsolve_kernel", s);
-        hipLaunchKernelGGL(backsolve_kernel, dim3(nE), dim3(256), 0, s, k.direct, k.direct_vec,
+        hipLaunchKernelGGL(backsolve_kernel, dim3(nE), dim3(BSV_THREADS), 0, s, k.direct,
+                           k.direct_vec,
                            N, Np, k.p_pitch, gb.xl);
     }
     if ((err = hipGetLastError()) != hipSuccess) return err;
