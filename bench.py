@@ -10,7 +10,9 @@ events on its own stream (the library's opt-in launch timer).
 Printed (one JSON line): walk steps per second of the whole step, per-stage and per-kernel
 times, the roofline of the dominant kernel, time to a 1% relative deviation of the lead
 current for MC and for the DIRECT GPU solve, and the oracle timed on the host's cores for a
-bounded sample of the same workload.
+bounded sample of the same workload.  A "grad" object adds the gradient (dI/dV_i for all
+sites, dI/dgamma_i) on the W=16 x L=200 differentiation workload with its own roofline and
+oracle sample.
 """
 from __future__ import annotations
 
@@ -44,6 +46,8 @@ def parse():
     ap.add_argument("--etas", type=str, default=None, help="comma-separated dephasing rates")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttp", action="store_true", help="skip the time-to-1%% measurement")
+    ap.add_argument("--no-grad", action="store_true",
+                    help="skip the gradient measurement on the differentiation workload")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the timed steps, run one plain device copy of this many MiB "
                          "(reference dispatch for HBM byte counters)")
@@ -115,10 +119,10 @@ def roofline(name, wl, ms_per_launch, walk_steps):
             "algorithmic_per_launch": amount * 1e12, "avg_launch_ms": ms_per_launch}
 
 
-def measured_traffic(name):
-    """HBM bytes per launch from the committed rocprofv3 counter summary for `name`, or None
-    when the kernel's source changed since the counters were taken."""
-    path = os.path.join(PROFILES, f"{name}_wire_W10_L100_traffic.json")
+def measured_traffic(name, workload="wire_W10_L100"):
+    """HBM bytes per launch from the committed rocprofv3 counter summary for `name` on
+    `workload`, or None when the kernel's source changed since the counters were taken."""
+    path = os.path.join(PROFILES, f"{name}_{workload}_traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -128,6 +132,75 @@ def measured_traffic(name):
         return float(rec["hbm_bytes_per_launch"])
     except (OSError, ValueError, KeyError):
         return None
+
+
+def grad_work(wl: inputs.Workload):
+    """Algorithmic work of one adjoint_solve_kernel launch (all energies): HBM bytes (G read
+    in both sweeps, the forward results written and read back) and FP64 flops (two complex
+    W x W block products per slice for N + W right-hand sides)."""
+    N, W, nE = wl.N, wl.W, wl.n_energies
+    nbytes = nE * (2.0 * 16 * N * N + 2.0 * 16 * N * (N + W))
+    flops = nE * (N + W) * 2.0 * wl.L * 8.0 * W * W
+    return nbytes, flops
+
+
+def grad_bench(torch, dev, steps, warmup, with_cpu):
+    """dI/dV_i for every site and dI/deta on the differentiation workload (mc_negf_grad:
+    DIRECT solve, back substitution, G columns, adjoint solves, assembly), HIP-event timed."""
+    wl = inputs.DIFF_W16_L200
+    sysm = M.make_system(wl.W, wl.L, wl.t, wl.lead_model, wl.gamma_l, wl.delta_lead)
+    E, w = M.energy_grid(wl.emin, wl.emax, wl.n_energies)
+    V = torch.tensor(inputs.onsite(wl), device=dev)
+    g = torch.tensor(inputs.dephasing(wl), device=dev)
+    tE, tw = torch.tensor(E, device=dev), torch.tensor(w, device=dev)
+    ws = M.allocate_workspace(sysm, wl.n_energies, dev)
+    k = M.mc_negf_build_kernel(sysm, V, g, tE, ws)
+    gws = torch.empty(M.mc_negf_grad_workspace_bytes(k), dtype=torch.uint8, device=dev)
+    dV = torch.empty(wl.N, dtype=torch.float64, device=dev)
+    dg = torch.empty_like(dV)
+    for _ in range(max(1, warmup)):
+        M.mc_negf_grad(k, 0, tw, gws, dV, dg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with M.LaunchTimes() as lt:
+        for _ in range(steps):
+            st, I = M.mc_negf_grad(k, 0, tw, gws, dV, dg)
+        torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    names = sorted(set(n for n, _ in lt.records))
+    per_kernel = {n: {"launches": lt.count(n), "ms_per_launch": lt.total_ms(n) / lt.count(n)}
+                  for n in names}
+    adj_ms = per_kernel["adjoint_solve_kernel"]["ms_per_launch"]
+    nbytes, flops = grad_work(wl)
+    achieved = nbytes / 1e9 / (adj_ms * 1e-3)
+    out = {
+        "workload": f"W={wl.W} L={wl.L} N={wl.N}, eta={wl.eta}t, disorder U[-{wl.disorder},"
+                    f"{wl.disorder}]t, {wl.n_energies} energies in [{wl.emin},{wl.emax}]t",
+        "value": 1.0 / wall, "unit": "gradients/s (dI/dV_i for all N sites and dI/dgamma_i)",
+        "ms_per_grad": 1e3 * wall, "I": I, "dI_deta": float(dg.sum().item()),
+        "status": st, "per_kernel": per_kernel,
+        "roofline": {"kernel": "adjoint_solve_kernel", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "algorithmic_per_launch": nbytes, "avg_launch_ms": adj_ms,
+                     "fp64_tflops": flops / 1e12 / (adj_ms * 1e-3),
+                     "traffic": measured_traffic("adjoint_solve_kernel", "diff_W16_L200")},
+    }
+    del k, ws, gws
+    torch.cuda.empty_cache()
+    if with_cpu:
+        # the oracle's reverse-mode dense adjoint on one of the energies, scaled to all of them
+        from oracle import grad as OG
+        import torch as _t
+        j = wl.n_energies // 3
+        t0 = time.perf_counter()
+        OG.adjoint(wl.W, wl.L, wl.t, inputs.onsite(wl), inputs.dephasing(wl), E[j:j + 1],
+                   w[j:j + 1])
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 1.0 / (dt * wl.n_energies), "unit": "gradients/s",
+                               "cores": _t.get_num_threads(), "kind": "oracle",
+                               "sample": f"1 of {wl.n_energies} energies (dense torch adjoint, "
+                                         f"{dt:.1f} s), scaled to all energies"}
+    return out
 
 
 def time_to_1pct(p: Problem, torch, seed, walk_on):
@@ -277,6 +350,10 @@ def main():
     if not args.no_cpu_baseline:
         mid = probs[len(probs) // 2].wl
         line["cpu_baseline"] = cpu_baseline(mid, seed)
+    if not args.no_grad:
+        del probs, results
+        torch.cuda.empty_cache()
+        line["grad"] = grad_bench(torch, dev, args.steps, args.warmup, not args.no_cpu_baseline)
     print(json.dumps(line), flush=True)
 
 

@@ -5,6 +5,7 @@
 
     python -m paper_1805_10164_amd.profiling traffic --fetch COUNTERS_CSV --write COUNTERS_CSV
         --calib-mib M --kernel NAME --source FILE [--command-fetch CMD --command-write CMD]
+        [--grid-size ITEMS] [--match SHORT_NAME_PREFIX]
         HBM bytes per launch of kernel NAME from a FETCH_SIZE run and a WRITE_SIZE run (KiB per
         dispatch).  Each counter is scaled by what it reads for the plain copy dispatch of the
         same run (a negation that reads and writes M MiB, see bench.py --calib-copy-mb), so the
@@ -42,8 +43,9 @@ def stats(path: str, command: str) -> str:
     return "\n".join(out) + "\n"
 
 
-def _counter(path: str, counter: str):
-    """(values of kernel dispatches by short name, calibration value) for one counter."""
+def _counter(path: str, counter: str, grid_size=None):
+    """(values of kernel dispatches by short name, calibration value) for one counter; with
+    grid_size, only dispatches of that many work-items (one workload of a multi-workload run)."""
     per, calib = {}, None
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] != counter:
@@ -52,16 +54,22 @@ def _counter(path: str, counter: str):
         if CALIB_KERNEL in r["Kernel_Name"]:
             calib = v
             continue
+        if grid_size is not None and int(r["Grid_Size"]) != int(grid_size):
+            continue
         per.setdefault(short_name(r["Kernel_Name"]), []).append(v)
     return per, calib
 
 
-def traffic(fetch_csv, write_csv, calib_mib, kernel, source, cmd_fetch="", cmd_write=""):
-    fetch, cf = _counter(fetch_csv, "FETCH_SIZE")
-    write, cw = _counter(write_csv, "WRITE_SIZE")
+def traffic(fetch_csv, write_csv, calib_mib, kernel, source, cmd_fetch="", cmd_write="",
+            grid_size=None, match=None):
+    fetch, cf = _counter(fetch_csv, "FETCH_SIZE", grid_size)
+    write, cw = _counter(write_csv, "WRITE_SIZE", grid_size)
     if cf is None or cw is None:
         raise SystemExit("calibration dispatch not found in the counter files")
-    key = next((k for k in fetch if k.split("<")[0] == kernel), None)
+    if match:  # a short-name prefix that picks one template instance
+        key = next((k for k in fetch if k.startswith(match)), None)
+    else:
+        key = next((k for k in fetch if k.split("<")[0] == kernel), None)
     if key is None or key not in write:
         raise SystemExit(f"kernel {kernel} not found in the counter files")
     known_kib = calib_mib * 1024.0
@@ -79,6 +87,7 @@ def traffic(fetch_csv, write_csv, calib_mib, kernel, source, cmd_fetch="", cmd_w
                         "write_kib_read": cw, "fetch_scale": fs, "write_scale": ws},
         "hbm_bytes_per_dispatch": per_launch,
         "hbm_bytes_per_launch": sum(per_launch) / len(per_launch),
+        "dispatch": {"short_name": key, "grid_size": grid_size},
         "commands": {"fetch": cmd_fetch, "write": cmd_write},
     }
 
@@ -97,12 +106,15 @@ def main(argv=None):
     t.add_argument("--source", required=True)
     t.add_argument("--command-fetch", default="")
     t.add_argument("--command-write", default="")
+    t.add_argument("--grid-size", type=int, default=None,
+                   help="only dispatches of this many work-items")
+    t.add_argument("--match", default=None, help="short-name prefix of the dispatches")
     a = ap.parse_args(argv)
     if a.what == "stats":
         sys.stdout.write(stats(a.csv, a.command))
     else:
         rec = traffic(a.fetch, a.write, a.calib_mib, a.kernel, a.source, a.command_fetch,
-                      a.command_write)
+                      a.command_write, a.grid_size, a.match)
         json.dump(rec, sys.stdout, indent=1)
         sys.stdout.write("\n")
 
