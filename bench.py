@@ -60,6 +60,9 @@ class Problem:
     def __init__(self, wl: inputs.Workload, torch, dev):
         self.wl = wl
         self.sys = M.make_system(wl.W, wl.L, wl.t, wl.lead_model, wl.gamma_l, wl.delta_lead)
+        # the DIRECT current alone needs no alias tables
+        self.sys_direct = M.make_system(wl.W, wl.L, wl.t, wl.lead_model, wl.gamma_l,
+                                        wl.delta_lead, M.BUILD_NO_ALIAS)
         E, w = M.energy_grid(wl.emin, wl.emax, wl.n_energies)
         self.V = torch.tensor(inputs.onsite(wl), device=dev)
         self.g = torch.tensor(inputs.dephasing(wl), device=dev)
@@ -148,7 +151,8 @@ def grad_bench(torch, dev, steps, warmup, with_cpu):
     """dI/dV_i for every site and dI/deta on the differentiation workload (mc_negf_grad:
     DIRECT solve, back substitution, G columns, adjoint solves, assembly), HIP-event timed."""
     wl = inputs.DIFF_W16_L200
-    sysm = M.make_system(wl.W, wl.L, wl.t, wl.lead_model, wl.gamma_l, wl.delta_lead)
+    sysm = M.make_system(wl.W, wl.L, wl.t, wl.lead_model, wl.gamma_l, wl.delta_lead,
+                         M.BUILD_NO_ALIAS)
     E, w = M.energy_grid(wl.emin, wl.emax, wl.n_energies)
     V = torch.tensor(inputs.onsite(wl), device=dev)
     g = torch.tensor(inputs.dephasing(wl), device=dev)
@@ -206,7 +210,8 @@ def grad_bench(torch, dev, steps, warmup, with_cpu):
 def time_to_1pct(p: Problem, torch, seed, walk_on):
     """Wall time to a 1% relative deviation of I, median of 5 warm repetitions.
     MC: build + walker batches doubling from 1024 per energy until sigma_I <= 1% of I.
-    DIRECT: build + probe-system solve (deterministic; its error is the quadrature's)."""
+    DIRECT: build without alias tables + probe-system solve (deterministic; its error is the
+    quadrature's)."""
     mc_t, dir_t, mc_walkers = [], [], []
     for rep in range(5):
         if walk_on:
@@ -226,7 +231,7 @@ def time_to_1pct(p: Problem, torch, seed, walk_on):
             mc_walkers.append(done)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        k = M.mc_negf_build_kernel(p.sys, p.V, p.g, p.E, p.ws)
+        k = M.mc_negf_build_kernel(p.sys_direct, p.V, p.g, p.E, p.ws)
         M.mc_negf_current(k, 1, 0, None, p.w, p.T, p.sig)
         dir_t.append(time.perf_counter() - t0)
     return {"eta": p.wl.eta,

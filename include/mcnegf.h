@@ -97,7 +97,14 @@ typedef struct mcnegf_system {
     int32_t lead_model;   /* 0 clean semi-infinite leads, 1 wide-band leads                */
     double  gamma_l;      /* wide-band coupling Gamma_l (lead_model 1), >= 0               */
     double  delta_lead;   /* regulator in units of t: z = E + i*delta_lead*t (model 0), > 0 */
+    uint32_t flags;       /* MCNEGF_BUILD_* bits; 0 builds everything                      */
 } mcnegf_system;
+
+/* mcnegf_system.flags.  MCNEGF_BUILD_NO_ALIAS: build G, the kernel rows' ingredients and
+ * the lead terms but no alias tables (their workspace is not reserved; the handle's alias
+ * and alias_lo are NULL).  Such a kernel serves the DIRECT current and its gradient;
+ * mc_negf_walk and the MC mode of mc_negf_current reject it with MCNEGF_EINVAL. */
+#define MCNEGF_BUILD_NO_ALIAS  0x1u
 
 /*
  * Handle filled by mc_negf_build_kernel: shapes plus device pointers into the caller's
@@ -147,7 +154,8 @@ typedef struct mcnegf_kernel {
 int32_t mc_negf_workspace_bytes(const mcnegf_system* sys, int32_t nE, uint64_t* bytes_out);
 
 /*
- * Build the per-energy Green's functions, transition kernels and alias tables.
+ * Build the per-energy Green's functions, transition kernels and alias tables (no alias
+ * tables when sys->flags has MCNEGF_BUILD_NO_ALIAS).
  *   sys        physical system (host).
  *   d_onsite   [N] device, V_i, slice-major.
  *   d_gamma    [N] device, gamma_i >= 0 (dephasing rate of the probe on site i); the

@@ -22,8 +22,11 @@ class DirectCurrent(torch.autograd.Function):
         onsite = onsite.detach().contiguous()
         gamma = gamma.detach().contiguous()
         nE = int(energies.numel())
-        ws = M.allocate_workspace(system, nE, onsite.device)
-        k = M.mc_negf_build_kernel(system, onsite, gamma, energies, ws)
+        # no alias tables: only the DIRECT current and its adjoint read this build
+        sysd = M.System(system.W, system.L, system.t, system.lead_model, system.gamma_l,
+                        system.delta_lead, system.flags | M.BUILD_NO_ALIAS)
+        ws = M.allocate_workspace(sysd, nE, onsite.device)
+        k = M.mc_negf_build_kernel(sysd, onsite, gamma, energies, ws)
         if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
             gws = torch.empty(M.mc_negf_grad_workspace_bytes(k), dtype=torch.uint8,
                               device=onsite.device)

@@ -51,7 +51,7 @@ struct Layout {
         off_Gd, off_corner, off_wL, off_wR, off_Adiag, off_P, off_alias, off_alias_lo, off_direct,
         off_direct_vec, total;
 };
-Layout make_layout(int W, int L, int nE);
+Layout make_layout(int W, int L, int nE, bool with_alias);
 
 // gradient workspace (caller-owned, separate from the build workspace)
 struct GradBuffers {

@@ -32,7 +32,7 @@ static int32_t hip_fail(hipError_t e) {
 
 static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
-Layout make_layout(int W, int L, int nE) {
+Layout make_layout(int W, int L, int nE, bool with_alias) {
     Layout o;
     const int64_t N = (int64_t)W * L;
     const int64_t n = N + 2;
@@ -59,8 +59,8 @@ Layout make_layout(int W, int L, int nE) {
     o.off_Adiag = take((uint64_t)nE * N * 8);
     o.off_direct_vec = take((uint64_t)nE * 4 * N * 8);
     o.off_P = take((uint64_t)nE * N * o.p_pitch * 8);
-    o.off_alias = take((uint64_t)nE * n * o.alias_pitch * 4);
-    o.off_alias_lo = take((uint64_t)nE * n * o.alias_pitch * 2);
+    o.off_alias = take(with_alias ? (uint64_t)nE * n * o.alias_pitch * 4 : 0);
+    o.off_alias_lo = take(with_alias ? (uint64_t)nE * n * o.alias_pitch * 2 : 0);
     o.off_direct = take((uint64_t)nE * (o.p_pitch + 2) * o.p_pitch * 8);
     o.total = off;
     return o;
@@ -78,12 +78,15 @@ static bool valid_system(const mcnegf_system* s) {
     } else {
         return false;
     }
+    if (s->flags & ~MCNEGF_BUILD_NO_ALIAS) return false;
     return true;
 }
 
+static bool with_alias(const mcnegf_system* s) { return !(s->flags & MCNEGF_BUILD_NO_ALIAS); }
+
 static bool valid_kernel(const mcnegf_kernel* k) {
     return k && k->W >= 1 && k->W <= kMaxW && k->L >= 1 && k->N == k->W * k->L &&
-           k->n_out == k->N + 2 && k->nE >= 1 && k->p_pitch >= k->N && k->p_pitch % 16 == 0 && k->alias && k->alias_lo && k->P && k->lead && k->status &&
+           k->n_out == k->N + 2 && k->nE >= 1 && k->p_pitch >= k->N && k->p_pitch % 16 == 0 && k->P && k->lead && k->status &&
            k->counters && k->reduce;
 }
 
@@ -141,7 +144,7 @@ int32_t mc_negf_last_hip_error(void) { return g_last_hip_error; }
 
 int32_t mc_negf_workspace_bytes(const mcnegf_system* sys, int32_t nE, uint64_t* bytes_out) {
     if (!valid_system(sys) || nE < 1 || !bytes_out) return MCNEGF_EINVAL;
-    *bytes_out = make_layout(sys->W, sys->L, nE).total;
+    *bytes_out = make_layout(sys->W, sys->L, nE, with_alias(sys)).total;
     return MCNEGF_OK;
 }
 
@@ -152,7 +155,7 @@ int32_t mc_negf_build_kernel(const mcnegf_system* sys, const double* d_onsite,
     if (!valid_system(sys) || !d_onsite || !d_gamma || !d_energies || nE < 1 || !d_ws || !out)
         return MCNEGF_EINVAL;
     if (((uintptr_t)d_ws & 255u) != 0) return MCNEGF_EINVAL;
-    const Layout lay = make_layout(sys->W, sys->L, nE);
+    const Layout lay = make_layout(sys->W, sys->L, nE, with_alias(sys));
     if (ws_bytes < lay.total) return MCNEGF_EWS;
     char* base = static_cast<char*>(d_ws);
     mcnegf_kernel k;
@@ -169,8 +172,10 @@ int32_t mc_negf_build_kernel(const mcnegf_system* sys, const double* d_onsite,
     k.p_pitch = lay.p_pitch;
     k.energies = d_energies;
     k.gamma = d_gamma;
-    k.alias = reinterpret_cast<uint32_t*>(base + lay.off_alias);
-    k.alias_lo = reinterpret_cast<uint16_t*>(base + lay.off_alias_lo);
+    if (with_alias(sys)) {
+        k.alias = reinterpret_cast<uint32_t*>(base + lay.off_alias);
+        k.alias_lo = reinterpret_cast<uint16_t*>(base + lay.off_alias_lo);
+    }
     k.P = reinterpret_cast<double*>(base + lay.off_P);
     k.wL = reinterpret_cast<double*>(base + lay.off_wL);
     k.wR = reinterpret_cast<double*>(base + lay.off_wR);
@@ -197,7 +202,8 @@ int32_t mc_negf_build_kernel(const mcnegf_system* sys, const double* d_onsite,
     if ((err = launch_rgf(k, d_onsite, stream)) != hipSuccess) return hip_fail(err);
     if ((err = launch_fullinv(k, stream)) != hipSuccess) return hip_fail(err);
     if ((err = launch_lead_terms(k, stream)) != hipSuccess) return hip_fail(err);
-    if ((err = launch_alias_build(k, stream)) != hipSuccess) return hip_fail(err);
+    if (with_alias(sys) && (err = launch_alias_build(k, stream)) != hipSuccess)
+        return hip_fail(err);
     *out = k;
     return MCNEGF_OK;
 }
@@ -205,8 +211,8 @@ int32_t mc_negf_build_kernel(const mcnegf_system* sys, const double* d_onsite,
 int32_t mc_negf_walk(const mcnegf_kernel* k, uint64_t seed, uint32_t realization,
                      uint32_t inject_lead, uint64_t walker_begin, uint64_t n_walkers_per_energy,
                      uint32_t max_steps, int64_t* d_tallies, hipStream_t stream) {
-    if (!valid_kernel(k) || !d_tallies || inject_lead > 1 || realization >= (1u << 30) ||
-        max_steps < 1)
+    if (!valid_kernel(k) || !k->alias || !k->alias_lo || !d_tallies || inject_lead > 1 ||
+        realization >= (1u << 30) || max_steps < 1)
         return MCNEGF_EINVAL;
     if (walker_begin + n_walkers_per_energy > 0x100000000ull ||
         walker_begin >= 0x100000000ull)
@@ -226,7 +232,7 @@ int32_t mc_negf_current(const mcnegf_kernel* k, int32_t mode, uint32_t inject_le
         return MCNEGF_EINVAL;
     hipError_t err;
     if (mode == 0) {
-        if (!d_tallies) return MCNEGF_EINVAL;
+        if (!d_tallies || !k->alias) return MCNEGF_EINVAL;  // tallies need a walked kernel
         err = launch_mc_current(*k, inject_lead, d_tallies, d_weights, d_T, d_sigmaT, stream);
     } else if (mode == 1) {
         if (!k->direct || !k->direct_vec) return MCNEGF_EINVAL;

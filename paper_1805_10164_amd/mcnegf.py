@@ -40,7 +40,7 @@ class McnegfError(RuntimeError):
 class System(ctypes.Structure):
     _fields_ = [("W", ctypes.c_int32), ("L", ctypes.c_int32), ("t", ctypes.c_double),
                 ("lead_model", ctypes.c_int32), ("gamma_l", ctypes.c_double),
-                ("delta_lead", ctypes.c_double)]
+                ("delta_lead", ctypes.c_double), ("flags", ctypes.c_uint32)]
 
 
 class KernelStruct(ctypes.Structure):
@@ -114,9 +114,13 @@ def _ptr(t) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr())
 
 
+BUILD_NO_ALIAS = 0x1
+
+
 def make_system(W: int, L: int, t: float = 1.0, lead_model: int = 0, gamma_l: float = 0.0,
-                delta_lead: float = 1e-10) -> System:
-    return System(W, L, t, lead_model, gamma_l, delta_lead)
+                delta_lead: float = 1e-10, flags: int = 0) -> System:
+    """flags: BUILD_NO_ALIAS builds no alias tables (DIRECT current and gradient only)."""
+    return System(W, L, t, lead_model, gamma_l, delta_lead, flags)
 
 
 def energy_grid(emin: float, emax: float, n: int):
@@ -140,7 +144,10 @@ class Kernel:
     def view(self, field: str, dtype, shape):
         """torch view of a workspace region named by a pointer field of the handle."""
         import torch
-        off = getattr(self.struct, field) - self.ws.data_ptr()
+        ptr = getattr(self.struct, field)
+        if not ptr:
+            raise ValueError(f"this kernel has no {field} (built with BUILD_NO_ALIAS?)")
+        off = ptr - self.ws.data_ptr()
         nbytes = int(np.prod(shape)) * torch.empty((), dtype=dtype).element_size()
         return self.ws[off:off + nbytes].view(dtype).view(*shape)
 

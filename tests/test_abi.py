@@ -102,6 +102,33 @@ def test_host_validation_rejects_before_any_gpu_call():
     assert gb.value >= 3 * 6 * 16 * 16  # three complex N x p_pitch arrays at nE = 1
 
 
+def test_no_alias_build_flag():
+    # the flag drops exactly the alias regions from the workspace; unknown bits are rejected
+    lib = M.lib()
+    full, small = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    s = M.make_system(10, 100)
+    assert lib.mc_negf_workspace_bytes(ctypes.byref(s), 4, ctypes.byref(full)) == M.OK
+    s2 = M.make_system(10, 100, flags=M.BUILD_NO_ALIAS)
+    assert lib.mc_negf_workspace_bytes(ctypes.byref(s2), 4, ctypes.byref(small)) == M.OK
+    n = 1002
+    alias_bytes = 4 * n * 1008 * 4 + 4 * n * 1008 * 2
+    assert full.value - small.value >= alias_bytes - 512
+    assert full.value - small.value <= alias_bytes + 512
+    s3 = M.make_system(10, 100, flags=0x2)
+    assert lib.mc_negf_workspace_bytes(ctypes.byref(s3), 4, ctypes.byref(small)) == M.EINVAL
+    # a handle without alias tables is rejected by the walker and the MC current
+    ks = M.KernelStruct()
+    ks.W, ks.L, ks.N, ks.n_out, ks.nE, ks.p_pitch = 2, 3, 6, 8, 1, 16
+    for f in ("P", "lead", "status", "counters", "reduce"):
+        setattr(ks, f, 4096)
+    t = ctypes.c_void_p(4096)
+    z = ctypes.c_void_p(0)
+    assert lib.mc_negf_walk(ctypes.byref(ks), 1, 0, 0, 0, 10, 10, t, z) == M.EINVAL
+    out = (ctypes.c_double * 2)()
+    assert lib.mc_negf_current(ctypes.byref(ks), 0, 0, t, t, t, t,
+                               ctypes.cast(out, ctypes.POINTER(ctypes.c_double)), z) == M.EINVAL
+
+
 def test_energy_grid_is_midpoint():
     E, w = M.energy_grid(-3.5, 3.5, 256)
     assert abs(E[0] - (-3.5 + 3.5 / 256)) < 1e-15 and abs(E[-1] - (3.5 - 3.5 / 256)) < 1e-15

@@ -309,6 +309,33 @@ def test_autograd_direct_current_and_eta_derivative():
     assert abs(I2.item() - Iref) <= 1e-10 * abs(Iref)
 
 
+def test_no_alias_build_serves_direct_and_grad():
+    # A build without alias tables gives the same DIRECT current and gradient bit for bit
+    # (the same kernels run on the same inputs) and cannot be walked.
+    c = case(**GRAD_CASES["w4l13"])
+    k = gpu_build(c)
+    sysn = M.make_system(c["W"], c["L"], 1.0, c["lead_model"], c["gamma_l"], 1e-10,
+                         M.BUILD_NO_ALIAS)
+    ws = M.allocate_workspace(sysn, len(c["E"]))
+    V = torch.tensor(c["V"], dtype=torch.float64, device=DEV)
+    g = torch.tensor(c["g"], dtype=torch.float64, device=DEV)
+    E = torch.tensor(c["E"], dtype=torch.float64, device=DEV)
+    kn = M.mc_negf_build_kernel(sysn, V, g, E, ws)
+    assert kn.struct.alias is None and kn.struct.alias_lo is None
+    w = torch.tensor(c["w"], dtype=torch.float64, device=DEV)
+    T = torch.empty(len(c["E"]), dtype=torch.float64, device=DEV)
+    sg = torch.empty_like(T)
+    _, I1, _ = M.mc_negf_current(k, 1, 0, None, w, T, sg)
+    _, I2, _ = M.mc_negf_current(kn, 1, 0, None, w, T, sg)
+    assert I1 == I2
+    r1, r2 = gpu_grad(k, c, 0), gpu_grad(kn, c, 0)
+    assert r1[1] == r2[1] and (r1[2] == r2[2]).all() and (r1[3] == r2[3]).all()
+    tal = torch.zeros((len(c["E"]), M.TALLY_N), dtype=torch.int64, device=DEV)
+    with pytest.raises(M.McnegfError) as ei:
+        M.mc_negf_walk(kn, 1, 0, 0, 0, 16, 100, tal)
+    assert ei.value.code == M.EINVAL
+
+
 def test_grad_single_site_closed_form():
     # N = 1, wide-band leads: T = g G_t / 2 / ((E - V)^2 + G_t^2 / 4) with G_t = 2 g + gamma,
     # g = 0.4; differentiate the closed form in V (at V = 0) and gamma.
