@@ -105,6 +105,10 @@ typedef struct mcnegf_system {
  * and alias_lo are NULL).  Such a kernel serves the DIRECT current and its gradient;
  * mc_negf_walk and the MC mode of mc_negf_current reject it with MCNEGF_EINVAL. */
 #define MCNEGF_BUILD_NO_ALIAS  0x1u
+/* MCNEGF_BUILD_NO_DIRECT: reserve no workspace for the DIRECT solve (the handle's direct
+ * and direct_vec are NULL); the DIRECT mode of mc_negf_current and mc_negf_grad reject such
+ * a kernel with MCNEGF_EINVAL.  For Monte Carlo-only batches of large systems. */
+#define MCNEGF_BUILD_NO_DIRECT 0x2u
 
 /*
  * Handle filled by mc_negf_build_kernel: shapes plus device pointers into the caller's
@@ -235,6 +239,94 @@ int32_t mc_negf_grad_workspace_bytes(const mcnegf_kernel* k, uint64_t* bytes_out
 int32_t mc_negf_grad(const mcnegf_kernel* k, uint32_t inject_lead, const double* d_weights,
                      void* d_gws, uint64_t gws_bytes, double* d_dI_dV, double* d_dI_dgamma,
                      double* h_I, hipStream_t stream);
+
+/*
+ * Like mc_negf_current, but asynchronous and capturable in a HIP graph: I and the standard
+ * error go to d_I_sigma ([2] device) instead of the host, nothing is synchronised and the
+ * status word is left for mc_negf_status to read.  Same argument rules and errors
+ * (MCNEGF_EINVAL, MCNEGF_EHIP) as mc_negf_current.
+ */
+int32_t mc_negf_current_async(const mcnegf_kernel* k, int32_t mode, uint32_t inject_lead,
+                              const int64_t* d_tallies, const double* d_weights, double* d_T,
+                              double* d_sigmaT, double* d_I_sigma, hipStream_t stream);
+
+/*
+ * Batched walks over many built kernels (systems of different sizes; every energy of every
+ * kernel is one unit), in one persistent launch (Sec. II F step 6', walked as in
+ * mc_negf_walk).  The tallies equal those of mc_negf_walk on each kernel with the same seed,
+ * realization, injection lead and walker range, bit for bit, for every launch shape.
+ *
+ * mc_negf_batch_bytes: device bytes of the batch buffer for these kernels (host only).
+ * mc_negf_batch_prepare: write the unit table for `kernels` (each built with alias tables)
+ *   into d_buf (caller-owned device memory of >= mc_negf_batch_bytes, 256-byte aligned) and
+ *   fill *out.  realizations[i] and inject_lead form kernel i's Philox tag as in
+ *   mc_negf_walk; d_tallies[i] is kernel i's [nE][MCNEGF_TALLY_N] tally array (device,
+ *   accumulated).  Copies the table from the host and synchronises `stream`: call it before
+ *   a graph capture, not inside one.  The kernels' workspaces must outlive the batch.
+ * mc_negf_walk_batch: walk walkers [walker_begin, walker_begin + n_walkers_per_energy) of
+ *   every unit; one kernel launch, asynchronous, capturable.  cfg NULL = the default shape.
+ * mc_negf_walk_batch_autotune: time every candidate launch shape (walker slots per lane
+ *   1-4, workgroup size 64 / 256, chunk of 2 / 8 / 32 walks per slot, XCD groups 1 / 8) on
+ *   this batch with n_walkers_per_energy walkers, counting into the batch buffer's scratch
+ *   tallies (the kernels' tallies are untouched), and return the fastest in *best and its
+ *   time in *best_ms.  Synchronises `stream`.
+ * Errors: MCNEGF_EINVAL (null pointers, a kernel without alias tables, a bad shape),
+ * MCNEGF_EWS (buffer too small or misaligned), MCNEGF_EHIP.
+ */
+typedef struct mcnegf_walk_config {
+    int32_t slots;           /* walker slots per lane, 1..4                                 */
+    int32_t wg_size;         /* threads per workgroup: 64, 128, 256 or 512                  */
+    int32_t groups;          /* 1, or 8 (units spread over the XCDs, unit u on XCD u % 8)  */
+    int32_t walks_per_slot;  /* chunk = 64 * slots * walks_per_slot walkers (chunk == 0)    */
+    int32_t chunk;           /* walkers per chunk; 0 = from walks_per_slot                  */
+} mcnegf_walk_config;
+
+typedef struct mcnegf_batch {
+    void*    d_units;           /* device unit table (inside the batch buffer)             */
+    int64_t* d_scratch_tallies; /* [n_units][MCNEGF_TALLY_N] (inside the batch buffer)     */
+    uint32_t n_units;           /* sum of the kernels' nE                                  */
+    uint32_t n_kernels;
+} mcnegf_batch;
+
+int32_t mc_negf_batch_bytes(const mcnegf_kernel* kernels, int32_t n_kernels, uint64_t* bytes_out);
+int32_t mc_negf_batch_prepare(const mcnegf_kernel* kernels, int32_t n_kernels,
+                              const uint32_t* realizations, uint32_t inject_lead,
+                              int64_t* const* d_tallies, void* d_buf, uint64_t buf_bytes,
+                              mcnegf_batch* out, hipStream_t stream);
+int32_t mc_negf_walk_batch(const mcnegf_batch* b, uint64_t seed, uint64_t walker_begin,
+                           uint64_t n_walkers_per_energy, uint32_t max_steps,
+                           const mcnegf_walk_config* cfg, hipStream_t stream);
+int32_t mc_negf_walk_batch_autotune(const mcnegf_batch* b, uint64_t seed,
+                                    uint64_t n_walkers_per_energy, uint32_t max_steps,
+                                    mcnegf_walk_config* best, float* best_ms,
+                                    hipStream_t stream);
+
+/*
+ * Memory-bounded schedule of many systems (host only, no GPU work): assign each of the n
+ * systems (nE energies each) to a wave so that the build workspaces of one wave (as
+ * mc_negf_workspace_bytes gives them, with each system's flags) fit in budget_bytes.  Systems
+ * are taken in decreasing order of their N^2 W cost and put into the first wave with room
+ * (first-fit decreasing), so every wave starts with its largest systems; order[k] is the k-th
+ * system in that order, wave_of[i] the wave of system i, *n_waves the number of waves.
+ * Errors: MCNEGF_EINVAL (bad system, n < 1), MCNEGF_EWS (one system alone exceeds the budget).
+ */
+int32_t mc_negf_plan_waves(const mcnegf_system* systems, int32_t n, int32_t nE,
+                           uint64_t budget_bytes, int32_t* order, int32_t* wave_of,
+                           int32_t* n_waves);
+
+/*
+ * HIP graph capture of this library's calls (and any other work) on a non-default stream:
+ * mc_negf_graph_begin starts capturing `stream`; mc_negf_graph_end stops it and instantiates
+ * the graph into *out (a host handle, freed by mc_negf_graph_destroy); mc_negf_graph_launch
+ * replays it on `stream`.  Between begin and end only asynchronous calls may be made
+ * (mc_negf_build_kernel, mc_negf_walk, mc_negf_walk_batch, mc_negf_current_async): the
+ * synchronising calls fail inside a capture.  No launch timing while capturing.
+ */
+typedef struct mcnegf_graph_s* mcnegf_graph;
+int32_t mc_negf_graph_begin(hipStream_t stream);
+int32_t mc_negf_graph_end(hipStream_t stream, mcnegf_graph* out);
+int32_t mc_negf_graph_launch(mcnegf_graph g, hipStream_t stream);
+int32_t mc_negf_graph_destroy(mcnegf_graph g);
 
 /*
  * Per-launch timing (opt-in, for benchmarks).  Between mc_negf_profile_begin(p) and

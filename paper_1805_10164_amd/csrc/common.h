@@ -51,7 +51,7 @@ struct Layout {
         off_Gd, off_corner, off_wL, off_wR, off_Adiag, off_P, off_alias, off_alias_lo, off_direct,
         off_direct_vec, total;
 };
-Layout make_layout(int W, int L, int nE, bool with_alias);
+Layout make_layout(int W, int L, int nE, bool with_alias, bool with_direct);
 
 // gradient workspace (caller-owned, separate from the build workspace)
 struct GradBuffers {
@@ -97,6 +97,12 @@ hipError_t launch_mc_current(const mcnegf_kernel& k, uint32_t inject_lead,
 hipError_t launch_direct_current(const mcnegf_kernel& k, uint32_t inject_lead,
                                  const double* weights, double* T, double* sigmaT,
                                  hipStream_t s);
+hipError_t launch_walk_batch(const mcnegf_batch& b, uint64_t seed, uint32_t walker_begin,
+                             uint32_t n_walkers, uint32_t max_steps, const mcnegf_walk_config& c,
+                             int64_t* tally_override, hipStream_t s);
+hipError_t launch_current_out(const mcnegf_kernel& k, double* d_I_sigma, hipStream_t s);
+size_t walk_unit_bytes();
+void fill_walk_unit(void* dst, const mcnegf_kernel& k, int e, uint32_t tag, int64_t* tally);
 hipError_t launch_grad(const mcnegf_kernel& k, const GradBuffers& gb, uint32_t inject_lead,
                        const double* weights, double* dI_dV, double* dI_dgamma, hipStream_t s);
 

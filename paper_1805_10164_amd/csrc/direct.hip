@@ -511,6 +511,22 @@ __global__ void __launch_bounds__(512) cholesky_kernel(CholArgs a) {
     }
 }
 
+// d_I_sigma[0] = I, d_I_sigma[1] = sqrt(sum_k w_k^2 sigma_k^2), from the weighted sums.
+__global__ void current_out_kernel(const double* __restrict__ reduce, double* __restrict__ out) {
+    if (threadIdx.x == 0) {
+        out[0] = reduce[0];
+        out[1] = sqrt(reduce[1] > 0.0 ? reduce[1] : 0.0);
+    }
+}
+
+hipError_t launch_current_out(const mcnegf_kernel& k, double* d_I_sigma, hipStream_t s) {
+    {
+        MCNEGF_TIMED("current_out_kernel", s);
+        hipLaunchKernelGGL(current_out_kernel, dim3(1), dim3(64), 0, s, k.reduce, d_I_sigma);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_direct_current(const mcnegf_kernel& k, uint32_t inject_lead,
                                  const double* weights, double* T, double* sigmaT, hipStream_t s) {
     const int N = k.N;

@@ -1,7 +1,10 @@
 // Host side of the C ABI declared in include/mcnegf.h: argument validation, workspace
 // layout and the order of the GPU stages.  Every GPU stage runs on the caller's stream.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <numeric>
+#include <vector>
 
 #include "common.h"
 
@@ -32,7 +35,7 @@ static int32_t hip_fail(hipError_t e) {
 
 static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
-Layout make_layout(int W, int L, int nE, bool with_alias) {
+Layout make_layout(int W, int L, int nE, bool with_alias, bool with_direct) {
     Layout o;
     const int64_t N = (int64_t)W * L;
     const int64_t n = N + 2;
@@ -57,11 +60,11 @@ Layout make_layout(int W, int L, int nE, bool with_alias) {
     o.off_wL = take((uint64_t)nE * N * 8);
     o.off_wR = take((uint64_t)nE * N * 8);
     o.off_Adiag = take((uint64_t)nE * N * 8);
-    o.off_direct_vec = take((uint64_t)nE * 4 * N * 8);
+    o.off_direct_vec = take(with_direct ? (uint64_t)nE * 4 * N * 8 : 0);
     o.off_P = take((uint64_t)nE * N * o.p_pitch * 8);
     o.off_alias = take(with_alias ? (uint64_t)nE * n * o.alias_pitch * 4 : 0);
     o.off_alias_lo = take(with_alias ? (uint64_t)nE * n * o.alias_pitch * 2 : 0);
-    o.off_direct = take((uint64_t)nE * (o.p_pitch + 2) * o.p_pitch * 8);
+    o.off_direct = take(with_direct ? (uint64_t)nE * (o.p_pitch + 2) * o.p_pitch * 8 : 0);
     o.total = off;
     return o;
 }
@@ -78,11 +81,15 @@ static bool valid_system(const mcnegf_system* s) {
     } else {
         return false;
     }
-    if (s->flags & ~MCNEGF_BUILD_NO_ALIAS) return false;
+    if (s->flags & ~(MCNEGF_BUILD_NO_ALIAS | MCNEGF_BUILD_NO_DIRECT)) return false;
     return true;
 }
 
 static bool with_alias(const mcnegf_system* s) { return !(s->flags & MCNEGF_BUILD_NO_ALIAS); }
+static bool with_direct(const mcnegf_system* s) { return !(s->flags & MCNEGF_BUILD_NO_DIRECT); }
+static Layout layout_of(const mcnegf_system* s, int nE) {
+    return make_layout(s->W, s->L, nE, with_alias(s), with_direct(s));
+}
 
 static bool valid_kernel(const mcnegf_kernel* k) {
     return k && k->W >= 1 && k->W <= kMaxW && k->L >= 1 && k->N == k->W * k->L &&
@@ -144,7 +151,7 @@ int32_t mc_negf_last_hip_error(void) { return g_last_hip_error; }
 
 int32_t mc_negf_workspace_bytes(const mcnegf_system* sys, int32_t nE, uint64_t* bytes_out) {
     if (!valid_system(sys) || nE < 1 || !bytes_out) return MCNEGF_EINVAL;
-    *bytes_out = make_layout(sys->W, sys->L, nE, with_alias(sys)).total;
+    *bytes_out = layout_of(sys, nE).total;
     return MCNEGF_OK;
 }
 
@@ -155,7 +162,7 @@ int32_t mc_negf_build_kernel(const mcnegf_system* sys, const double* d_onsite,
     if (!valid_system(sys) || !d_onsite || !d_gamma || !d_energies || nE < 1 || !d_ws || !out)
         return MCNEGF_EINVAL;
     if (((uintptr_t)d_ws & 255u) != 0) return MCNEGF_EINVAL;
-    const Layout lay = make_layout(sys->W, sys->L, nE, with_alias(sys));
+    const Layout lay = layout_of(sys, nE);
     if (ws_bytes < lay.total) return MCNEGF_EWS;
     char* base = static_cast<char*>(d_ws);
     mcnegf_kernel k;
@@ -187,8 +194,10 @@ int32_t mc_negf_build_kernel(const mcnegf_system* sys, const double* d_onsite,
     k.gR = reinterpret_cast<double*>(base + lay.off_gR);
     k.Gd = reinterpret_cast<double*>(base + lay.off_Gd);
     k.corner = reinterpret_cast<double*>(base + lay.off_corner);
-    k.direct = reinterpret_cast<double*>(base + lay.off_direct);
-    k.direct_vec = reinterpret_cast<double*>(base + lay.off_direct_vec);
+    if (with_direct(sys)) {
+        k.direct = reinterpret_cast<double*>(base + lay.off_direct);
+        k.direct_vec = reinterpret_cast<double*>(base + lay.off_direct_vec);
+    }
     k.reduce = reinterpret_cast<double*>(base + lay.off_reduce);
     k.status = reinterpret_cast<uint32_t*>(base + lay.off_status);
     k.counters = reinterpret_cast<uint32_t*>(base + lay.off_counters);
@@ -331,6 +340,247 @@ int32_t mc_negf_status(const mcnegf_kernel* k, uint32_t* h_flags, hipStream_t st
                               stream)) != hipSuccess)
         return hip_fail(err);
     if ((err = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(err);
+    return MCNEGF_OK;
+}
+
+int32_t mc_negf_current_async(const mcnegf_kernel* k, int32_t mode, uint32_t inject_lead,
+                              const int64_t* d_tallies, const double* d_weights, double* d_T,
+                              double* d_sigmaT, double* d_I_sigma, hipStream_t stream) {
+    if (!valid_kernel(k) || !d_weights || !d_T || !d_sigmaT || !d_I_sigma || inject_lead > 1)
+        return MCNEGF_EINVAL;
+    hipError_t err;
+    if (mode == 0) {
+        if (!d_tallies || !k->alias) return MCNEGF_EINVAL;
+        err = launch_mc_current(*k, inject_lead, d_tallies, d_weights, d_T, d_sigmaT, stream);
+    } else if (mode == 1) {
+        if (!k->direct || !k->direct_vec) return MCNEGF_EINVAL;
+        err = launch_direct_current(*k, inject_lead, d_weights, d_T, d_sigmaT, stream);
+    } else {
+        return MCNEGF_EINVAL;
+    }
+    if (err != hipSuccess) return hip_fail(err);
+    if ((err = launch_current_out(*k, d_I_sigma, stream)) != hipSuccess) return hip_fail(err);
+    return MCNEGF_OK;
+}
+
+static bool batch_units(const mcnegf_kernel* kernels, int32_t n, uint64_t* units) {
+    if (!kernels || n < 1) return false;
+    uint64_t u = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (!valid_kernel(&kernels[i]) || !kernels[i].alias || !kernels[i].alias_lo) return false;
+        u += (uint64_t)kernels[i].nE;
+    }
+    if (u >= (1ull << 31)) return false;
+    *units = u;
+    return true;
+}
+
+static uint64_t batch_table_bytes(uint64_t units) { return align256(units * walk_unit_bytes()); }
+
+int32_t mc_negf_batch_bytes(const mcnegf_kernel* kernels, int32_t n_kernels, uint64_t* bytes_out) {
+    uint64_t units = 0;
+    if (!bytes_out || !batch_units(kernels, n_kernels, &units)) return MCNEGF_EINVAL;
+    *bytes_out = batch_table_bytes(units) + align256(units * MCNEGF_TALLY_N * 8);
+    return MCNEGF_OK;
+}
+
+int32_t mc_negf_batch_prepare(const mcnegf_kernel* kernels, int32_t n_kernels,
+                              const uint32_t* realizations, uint32_t inject_lead,
+                              int64_t* const* d_tallies, void* d_buf, uint64_t buf_bytes,
+                              mcnegf_batch* out, hipStream_t stream) {
+    uint64_t units = 0;
+    if (!batch_units(kernels, n_kernels, &units) || !realizations || !d_tallies || !d_buf ||
+        !out || inject_lead > 1)
+        return MCNEGF_EINVAL;
+    for (int32_t i = 0; i < n_kernels; ++i)
+        if (!d_tallies[i] || realizations[i] >= (1u << 30)) return MCNEGF_EINVAL;
+    if (((uintptr_t)d_buf & 255u) != 0) return MCNEGF_EWS;
+    const uint64_t table = batch_table_bytes(units);
+    if (buf_bytes < table + align256(units * MCNEGF_TALLY_N * 8)) return MCNEGF_EWS;
+    const size_t ub = walk_unit_bytes();
+    std::vector<unsigned char> host(units * ub);
+    uint64_t u = 0;
+    for (int32_t i = 0; i < n_kernels; ++i) {
+        const uint32_t tag = (realizations[i] << 1) | inject_lead;
+        for (int32_t e = 0; e < kernels[i].nE; ++e, ++u)
+            fill_walk_unit(host.data() + u * ub, kernels[i], e, tag, d_tallies[i]);
+    }
+    hipError_t err;
+    if ((err = hipMemcpyAsync(d_buf, host.data(), host.size(), hipMemcpyHostToDevice, stream)) !=
+        hipSuccess)
+        return hip_fail(err);
+    if ((err = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(err);
+    out->d_units = d_buf;
+    out->d_scratch_tallies = reinterpret_cast<int64_t*>(static_cast<char*>(d_buf) + table);
+    out->n_units = (uint32_t)units;
+    out->n_kernels = (uint32_t)n_kernels;
+    return MCNEGF_OK;
+}
+
+static bool valid_walk_config(const mcnegf_walk_config& c) {
+    if (c.slots < 1 || c.slots > 4) return false;
+    if (c.wg_size != 64 && c.wg_size != 128 && c.wg_size != 256 && c.wg_size != 512) return false;
+    if (c.groups != 1 && c.groups != 8) return false;
+    if (c.chunk < 0 || (c.chunk == 0 && (c.walks_per_slot < 1 || c.walks_per_slot > 4096)))
+        return false;
+    return true;
+}
+
+static mcnegf_walk_config default_walk_config() {
+    mcnegf_walk_config c;
+    c.slots = 3;
+    c.wg_size = 256;
+    c.groups = 8;
+    c.walks_per_slot = 8;
+    c.chunk = 0;
+    return c;
+}
+
+static bool valid_batch(const mcnegf_batch* b) {
+    return b && b->d_units && b->d_scratch_tallies && b->n_units >= 1;
+}
+
+int32_t mc_negf_walk_batch(const mcnegf_batch* b, uint64_t seed, uint64_t walker_begin,
+                           uint64_t n_walkers_per_energy, uint32_t max_steps,
+                           const mcnegf_walk_config* cfg, hipStream_t stream) {
+    if (!valid_batch(b) || max_steps < 1) return MCNEGF_EINVAL;
+    if (walker_begin >= 0x100000000ull || walker_begin + n_walkers_per_energy > 0x100000000ull)
+        return MCNEGF_EINVAL;
+    const mcnegf_walk_config c = cfg ? *cfg : default_walk_config();
+    if (!valid_walk_config(c)) return MCNEGF_EINVAL;
+    if (n_walkers_per_energy == 0) return MCNEGF_OK;
+    hipError_t err = launch_walk_batch(*b, seed, (uint32_t)walker_begin,
+                                       (uint32_t)n_walkers_per_energy, max_steps, c, nullptr,
+                                       stream);
+    return err == hipSuccess ? MCNEGF_OK : hip_fail(err);
+}
+
+int32_t mc_negf_walk_batch_autotune(const mcnegf_batch* b, uint64_t seed,
+                                    uint64_t n_walkers_per_energy, uint32_t max_steps,
+                                    mcnegf_walk_config* best, float* best_ms,
+                                    hipStream_t stream) {
+    if (!valid_batch(b) || !best || max_steps < 1 || n_walkers_per_energy < 1 ||
+        n_walkers_per_energy > 0xffffffffull)
+        return MCNEGF_EINVAL;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t err;
+    if ((err = hipEventCreate(&e0)) != hipSuccess) return hip_fail(err);
+    if ((err = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(err);
+    }
+    const size_t tally_bytes = (size_t)b->n_units * MCNEGF_TALLY_N * 8;
+    float best_t = -1.0f;
+    mcnegf_walk_config best_c = default_walk_config();
+    const int slots[] = {1, 2, 3, 4};
+    const int wgs[] = {64, 256};
+    const int wps[] = {2, 8, 32};
+    const int groups[] = {1, 8};
+    for (int sl : slots)
+        for (int wg : wgs)
+            for (int wp : wps)
+                for (int gr : groups) {
+                    mcnegf_walk_config c;
+                    c.slots = sl;
+                    c.wg_size = wg;
+                    c.groups = gr;
+                    c.walks_per_slot = wp;
+                    c.chunk = 0;
+                    float ms = 0.0f;
+                    for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {  // warm, timed
+                        err = hipMemsetAsync(b->d_scratch_tallies, 0, tally_bytes, stream);
+                        if (err == hipSuccess) err = hipEventRecord(e0, stream);
+                        if (err == hipSuccess)
+                            err = launch_walk_batch(*b, seed, 0u, (uint32_t)n_walkers_per_energy,
+                                                    max_steps, c, b->d_scratch_tallies, stream);
+                        if (err == hipSuccess) err = hipEventRecord(e1, stream);
+                        if (err == hipSuccess) err = hipEventSynchronize(e1);
+                        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+                    }
+                    if (err != hipSuccess) break;
+                    if (best_t < 0.0f || ms < best_t) {
+                        best_t = ms;
+                        best_c = c;
+                    }
+                }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return hip_fail(err);
+    *best = best_c;
+    if (best_ms) *best_ms = best_t;
+    return MCNEGF_OK;
+}
+
+int32_t mc_negf_plan_waves(const mcnegf_system* systems, int32_t n, int32_t nE,
+                           uint64_t budget_bytes, int32_t* order, int32_t* wave_of,
+                           int32_t* n_waves) {
+    if (!systems || n < 1 || nE < 1 || !order || !wave_of || !n_waves) return MCNEGF_EINVAL;
+    std::vector<uint64_t> bytes(n);
+    std::vector<double> cost(n);
+    for (int32_t i = 0; i < n; ++i) {
+        if (!valid_system(&systems[i])) return MCNEGF_EINVAL;
+        bytes[i] = layout_of(&systems[i], nE).total;
+        if (bytes[i] > budget_bytes) return MCNEGF_EWS;
+        const double N = (double)systems[i].W * systems[i].L;
+        cost[i] = N * N * systems[i].W;
+    }
+    std::vector<int32_t> idx(n);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    std::vector<uint64_t> used;
+    for (int32_t k = 0; k < n; ++k) {
+        const int32_t i = idx[k];
+        order[k] = i;
+        size_t w = 0;
+        while (w < used.size() && used[w] + bytes[i] > budget_bytes) ++w;
+        if (w == used.size()) used.push_back(0);
+        used[w] += bytes[i];
+        wave_of[i] = (int32_t)w;
+    }
+    *n_waves = (int32_t)used.size();
+    return MCNEGF_OK;
+}
+
+}  // extern "C"
+
+struct mcnegf_graph_s {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+extern "C" {
+
+int32_t mc_negf_graph_begin(hipStream_t stream) {
+    if (!stream) return MCNEGF_EINVAL;  // the legacy default stream cannot be captured
+    hipError_t err = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+    return err == hipSuccess ? MCNEGF_OK : hip_fail(err);
+}
+
+int32_t mc_negf_graph_end(hipStream_t stream, mcnegf_graph* out) {
+    if (!stream || !out) return MCNEGF_EINVAL;
+    hipGraph_t g = nullptr;
+    hipError_t err = hipStreamEndCapture(stream, &g);
+    if (err != hipSuccess) return hip_fail(err);
+    hipGraphExec_t e = nullptr;
+    if ((err = hipGraphInstantiate(&e, g, nullptr, nullptr, 0)) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(err);
+    }
+    *out = new mcnegf_graph_s{g, e};
+    return MCNEGF_OK;
+}
+
+int32_t mc_negf_graph_launch(mcnegf_graph g, hipStream_t stream) {
+    if (!g || !stream) return MCNEGF_EINVAL;
+    hipError_t err = hipGraphLaunch(g->exec, stream);
+    return err == hipSuccess ? MCNEGF_OK : hip_fail(err);
+}
+
+int32_t mc_negf_graph_destroy(mcnegf_graph g) {
+    if (!g) return MCNEGF_EINVAL;
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    delete g;
     return MCNEGF_OK;
 }
 

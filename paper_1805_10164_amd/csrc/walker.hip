@@ -68,6 +68,26 @@ struct WalkArgs {
     uint32_t* status;
 };
 
+// One unit of a batched walk: one energy of one built kernel.
+struct WalkUnit {
+    const uint32_t* tables;  // this energy's packed alias rows
+    const uint16_t* lows;
+    int64_t* tally;          // this energy's [5] tallies
+    uint32_t* status;        // the kernel's status word
+    uint32_t pitch, n_out, N, e, tag, pad;
+};
+
+struct WalkBatchArgs {
+    const WalkUnit* units;
+    uint32_t n_units;
+    uint32_t key0, key1;
+    uint32_t wbegin, wend;
+    uint32_t chunk, chunks_per_unit;
+    uint32_t groups;
+    uint32_t max_steps;
+    int64_t* tally_override;  // non-null: unit u's counts go to tally_override[u][5]
+};
+
 // Every branch in the loops below that encloses a cross-lane operation is wave-uniform (its
 // condition is a ballot or a value computed identically in all lanes), and per-lane
 // differences are expressed as selects: the compiler does not guarantee that lanes which took
@@ -355,6 +375,272 @@ hipError_t launch_walk(const mcnegf_kernel& k, uint64_t seed, uint32_t tag, uint
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
     return hipSuccess;
+}
+
+// ---- batched walk over many built kernels (systems of different sizes, all energies) ------
+//
+// Work list: units u = (kernel, energy), each with the same walker index range, cut into
+// chunks of `chunk` walkers.  Unit u belongs to group u % groups and workgroup b to group
+// b % groups (with 8 groups, each XCD walks its own units); a group's wavefronts take its
+// chunks in stride order.  A wavefront walks one chunk at a time, so the unit's table, sizes
+// and Philox tag are wave-uniform; its K slots per lane refill from the chunk until it is used
+// up, and when every slot has finished the chunk's counts are reduced across the wavefront and
+// added to the unit's tallies with one atomic per slot of the tally.  A walker's path depends
+// only on (seed, step, walker, energy, tag), so the tallies equal those of mc_negf_walk on each
+// kernel for any launch shape.
+
+// A pointer that is the same in every lane, moved to scalar registers.
+__device__ inline const void* uniform_ptr(const void* p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (const void*)(((uint64_t)hi << 32) | lo);
+}
+
+// 64-bit sum over the wavefront (every lane gets it); all lanes active.
+__device__ inline uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int K>
+__global__ void walk_batch_kernel(WalkBatchArgs A) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t G = A.groups;
+    const uint32_t grp = blockIdx.x % G;
+    const uint32_t wpb = blockDim.x >> 6;
+    const uint32_t waves = __builtin_amdgcn_readfirstlane((gridDim.x / G) * wpb);
+    const uint32_t lw =
+        __builtin_amdgcn_readfirstlane((blockIdx.x / G) * wpb + (threadIdx.x >> 6));
+    const uint32_t nq = (A.n_units > grp) ? (A.n_units - grp + G - 1) / G : 0u;  // units of the group
+    const uint32_t total = nq * A.chunks_per_unit;
+    uint32_t trunc_any = 0;
+    for (uint32_t cid0 = lw; cid0 < total; cid0 += waves) {  // uniform loop
+        const uint32_t cid = __builtin_amdgcn_readfirstlane(cid0);
+        const uint32_t q = cid / A.chunks_per_unit;
+        const uint32_t u = __builtin_amdgcn_readfirstlane(grp + q * G);  // scalar unit loads
+        const WalkUnit Uv = A.units[u];
+        // the descriptor is the same in every lane: keep its fields in scalar registers
+        WalkUnit U;
+        U.tables = (const uint32_t*)uniform_ptr(Uv.tables);
+        U.lows = (const uint16_t*)uniform_ptr(Uv.lows);
+        U.tally = (int64_t*)uniform_ptr(Uv.tally);
+        U.status = (uint32_t*)uniform_ptr(Uv.status);
+        U.pitch = __builtin_amdgcn_readfirstlane(Uv.pitch);
+        U.n_out = __builtin_amdgcn_readfirstlane(Uv.n_out);
+        U.N = __builtin_amdgcn_readfirstlane(Uv.N);
+        U.e = __builtin_amdgcn_readfirstlane(Uv.e);
+        U.tag = __builtin_amdgcn_readfirstlane(Uv.tag);
+        uint32_t next = A.wbegin + (cid - q * A.chunks_per_unit) * A.chunk;
+        const uint32_t wend = min(next + A.chunk, A.wend);
+        const uint32_t n_out = U.n_out, N = U.N;
+        const uint32_t thresh = (0u - n_out) % n_out;
+        const uint32_t inject_row = N + (U.tag & 1u);
+        Step st[K];
+        uint32_t w[K];
+        uint32_t cL = 0, cR = 0, tr = 0;
+        uint64_t s1 = 0, s2 = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            st[k] = Step{inject_row, 0u, false};
+            w[k] = 0u;
+        }
+        for (;;) {
+            // refill idle slots (slot-major, then lane order) from the chunk
+            if (next < wend) {
+                uint64_t need[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) need[k] = __ballot(!st[k].active);
+                const uint32_t avail = wend - next;
+                uint32_t base = 0;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const uint32_t before = base + __popcll(need[k] & lt_mask);
+                    const bool take = !st[k].active && before < avail;
+                    w[k] = take ? next + before : w[k];
+                    st[k].s = take ? inject_row : st[k].s;
+                    st[k].n = take ? 0u : st[k].n;
+                    st[k].active = st[k].active || take;
+                    base += __popcll(need[k]);
+                }
+                next += base < avail ? base : avail;
+            }
+            uint64_t any = 0ull;
+#pragma unroll
+            for (int k = 0; k < K; ++k) any |= __ballot(st[k].active);
+            if (any == 0ull) break;
+            uint32_t ab[2][2][K];  // [step][word][slot]
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const Philox4 x = philox4x32_10(st[k].n >> 1, w[k], U.e, U.tag, A.key0, A.key1);
+                ab[0][0][k] = x.x[0];
+                ab[0][1][k] = x.x[1];
+                ab[1][0][k] = x.x[2];
+                ab[1][1][k] = x.x[3];
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                uint64_t m[K];
+                bool rej[K];
+                uint64_t rb = 0ull;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    m[k] = (uint64_t)ab[h][0][k] * n_out;
+                    rej[k] = st[k].active && ((uint32_t)m[k] < thresh);
+                    rb |= __ballot(rej[k]);
+                }
+                uint32_t r = 0;
+                while (rb != 0ull) {  // rare; uniform loop
+                    ++r;
+                    rb = 0ull;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const uint32_t a2 = philox4x32_10(st[k].n, w[k], U.e, U.tag | 0x80000000u,
+                                                          A.key0, A.key1 ^ r).x[0];
+                        const uint64_t m2 = (uint64_t)a2 * n_out;
+                        m[k] = rej[k] ? m2 : m[k];
+                        rej[k] = rej[k] && ((uint32_t)m2 < thresh);
+                        rb |= __ballot(rej[k]);
+                    }
+                }
+                uint32_t c[K], ent[K];
+                size_t at[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    c[k] = (uint32_t)(m[k] >> 32);
+                    at[k] = (size_t)st[k].s * U.pitch + c[k];
+                    ent[k] = U.tables[at[k]];
+                }
+                bool keep[K], tie[K];
+                uint64_t tb = 0ull;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const uint32_t b = ab[h][1][k];
+                    keep[k] = (b >> 12) < (ent[k] >> 12);
+                    tie[k] = st[k].active && (b >> 12) == (ent[k] >> 12);
+                    tb |= __ballot(tie[k]);
+                }
+                if (tb != 0ull) {  // rare; uniform branch
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const uint32_t lo = tie[k] ? (uint32_t)U.lows[at[k]] : 0u;
+                        keep[k] = tie[k] ? (ab[h][1][k] & 0xFFFu) < lo : keep[k];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const uint32_t nxt = keep[k] ? c[k] : (ent[k] & 0xFFFu);
+                    const uint32_t n1 = st[k].n + 1;
+                    const bool active = st[k].active;
+                    const bool absorbed = active && nxt >= N;
+                    const bool trunc = active && !absorbed && n1 >= A.max_steps;
+                    const bool ends = absorbed || trunc;
+                    cL += (absorbed && nxt == N) ? 1u : 0u;
+                    cR += (absorbed && nxt != N) ? 1u : 0u;
+                    tr += trunc ? 1u : 0u;
+                    s1 += ends ? (uint64_t)n1 : 0ull;
+                    s2 += ends ? (uint64_t)n1 * n1 : 0ull;
+                    st[k].s = (active && !ends) ? nxt : st[k].s;
+                    st[k].n = active ? n1 : st[k].n;
+                    st[k].active = active && !ends;
+                }
+            }
+        }
+        // the chunk is done: one atomic per tally slot for the wavefront
+        const uint64_t v0 = wave_sum_u64(cL), v1 = wave_sum_u64(cR), v2 = wave_sum_u64(tr);
+        const uint64_t v3 = wave_sum_u64(s1), v4 = wave_sum_u64(s2);
+        trunc_any |= (uint32_t)(v2 != 0);
+        unsigned long long* gt = reinterpret_cast<unsigned long long*>(
+            A.tally_override ? A.tally_override + (size_t)u * MCNEGF_TALLY_N : U.tally);
+        if (lane == 0) {
+            if (v0) atomicAdd(gt + MCNEGF_TALLY_EXIT_L, (unsigned long long)v0);
+            if (v1) atomicAdd(gt + MCNEGF_TALLY_EXIT_R, (unsigned long long)v1);
+            if (v2) atomicAdd(gt + MCNEGF_TALLY_TRUNC, (unsigned long long)v2);
+            if (v3) atomicAdd(gt + MCNEGF_TALLY_STEPS, (unsigned long long)v3);
+            if (v4) atomicAdd(gt + MCNEGF_TALLY_STEPS2, (unsigned long long)v4);
+            if (v2 && U.status) atomicOr(U.status, MCNEGF_FLAG_TRUNC);
+        }
+    }
+    (void)trunc_any;
+}
+
+size_t walk_unit_bytes() { return sizeof(WalkUnit); }
+
+void fill_walk_unit(void* dst, const mcnegf_kernel& k, int e, uint32_t tag, int64_t* tally) {
+    WalkUnit U;
+    const size_t stride = (size_t)k.n_out * (size_t)k.alias_pitch;
+    U.tables = k.alias + (size_t)e * stride;
+    U.lows = k.alias_lo + (size_t)e * stride;
+    U.tally = tally + (size_t)e * MCNEGF_TALLY_N;
+    U.status = k.status;
+    U.pitch = (uint32_t)k.alias_pitch;
+    U.n_out = (uint32_t)k.n_out;
+    U.N = (uint32_t)k.N;
+    U.e = (uint32_t)e;
+    U.tag = tag;
+    U.pad = 0;
+    *static_cast<WalkUnit*>(dst) = U;
+}
+
+template <int K>
+static hipError_t launch_walk_batch_k(const WalkBatchArgs& A, uint32_t blocks, uint32_t wg,
+                                      hipStream_t s) {
+    MCNEGF_TIMED("walk_batch_kernel", s);
+    hipLaunchKernelGGL(walk_batch_kernel<K>, dim3(blocks), dim3(wg), 0, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_walk_batch(const mcnegf_batch& b, uint64_t seed, uint32_t walker_begin,
+                             uint32_t n_walkers, uint32_t max_steps, const mcnegf_walk_config& c,
+                             int64_t* tally_override, hipStream_t s) {
+    if (n_walkers == 0 || b.n_units == 0) return hipSuccess;
+    WalkBatchArgs A;
+    A.units = static_cast<const WalkUnit*>(b.d_units);
+    A.n_units = b.n_units;
+    A.key0 = (uint32_t)(seed & 0xffffffffu);
+    A.key1 = (uint32_t)(seed >> 32);
+    A.wbegin = walker_begin;
+    A.wend = walker_begin + n_walkers;
+    A.max_steps = max_steps;
+    A.groups = (uint32_t)c.groups;
+    A.tally_override = tally_override;
+    // chunk: c.chunk walkers, or about `walks_per_slot` walks per slot of a wavefront
+    uint64_t ch = c.chunk > 0 ? (uint64_t)c.chunk
+                              : (uint64_t)64 * (uint64_t)c.slots * (uint64_t)c.walks_per_slot;
+    if (ch > n_walkers) ch = n_walkers;
+    A.chunk = (uint32_t)ch;
+    A.chunks_per_unit = (uint32_t)((n_walkers + ch - 1) / ch);
+    int dev = 0, cus = 0;
+    hipError_t err;
+    if ((err = hipGetDevice(&dev)) != hipSuccess) return err;
+    if ((err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
+        hipSuccess)
+        return err;
+    const void* fn = c.slots == 1   ? (const void*)walk_batch_kernel<1>
+                     : c.slots == 2 ? (const void*)walk_batch_kernel<2>
+                     : c.slots == 3 ? (const void*)walk_batch_kernel<3>
+                                    : (const void*)walk_batch_kernel<4>;
+    int per_cu = 0;
+    if ((err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, c.wg_size, 0)) !=
+        hipSuccess)
+        return err;
+    // persistent grid: every resident workgroup slot, rounded to whole groups, but no more
+    // wavefronts than chunks
+    const uint64_t wpb = (uint64_t)c.wg_size / 64;
+    uint64_t blocks = (uint64_t)(per_cu < 1 ? 1 : per_cu) * (uint64_t)cus;
+    const uint64_t chunks = (uint64_t)A.n_units * A.chunks_per_unit;
+    const uint64_t need = (chunks + wpb - 1) / wpb;
+    if (blocks > need) blocks = need;
+    blocks = (blocks + A.groups - 1) / A.groups * A.groups;
+    switch (c.slots) {
+        case 1: return launch_walk_batch_k<1>(A, (uint32_t)blocks, (uint32_t)c.wg_size, s);
+        case 2: return launch_walk_batch_k<2>(A, (uint32_t)blocks, (uint32_t)c.wg_size, s);
+        case 3: return launch_walk_batch_k<3>(A, (uint32_t)blocks, (uint32_t)c.wg_size, s);
+        case 4: return launch_walk_batch_k<4>(A, (uint32_t)blocks, (uint32_t)c.wg_size, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace mcnegf

@@ -26,8 +26,11 @@ TALLY_N = 5
 TALLY_EXIT_L, TALLY_EXIT_R, TALLY_TRUNC, TALLY_STEPS, TALLY_STEPS2 = range(5)
 EXPORTED = ("mc_negf_workspace_bytes", "mc_negf_build_kernel", "mc_negf_walk",
             "mc_negf_current", "mc_negf_grad_workspace_bytes", "mc_negf_grad",
-            "mc_negf_profile_begin", "mc_negf_profile_end", "mc_negf_status",
-            "mc_negf_last_hip_error", "mc_negf_version")
+            "mc_negf_current_async", "mc_negf_batch_bytes", "mc_negf_batch_prepare",
+            "mc_negf_walk_batch", "mc_negf_walk_batch_autotune", "mc_negf_plan_waves",
+            "mc_negf_graph_begin", "mc_negf_graph_end", "mc_negf_graph_launch",
+            "mc_negf_graph_destroy", "mc_negf_profile_begin", "mc_negf_profile_end",
+            "mc_negf_status", "mc_negf_last_hip_error", "mc_negf_version")
 PROFILE_MAX = 512
 
 
@@ -41,6 +44,19 @@ class System(ctypes.Structure):
     _fields_ = [("W", ctypes.c_int32), ("L", ctypes.c_int32), ("t", ctypes.c_double),
                 ("lead_model", ctypes.c_int32), ("gamma_l", ctypes.c_double),
                 ("delta_lead", ctypes.c_double), ("flags", ctypes.c_uint32)]
+
+
+class WalkConfig(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("wg_size", ctypes.c_int32), ("groups", ctypes.c_int32),
+                ("walks_per_slot", ctypes.c_int32), ("chunk", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("d_units", ctypes.c_void_p), ("d_scratch_tallies", ctypes.c_void_p),
+                ("n_units", ctypes.c_uint32), ("n_kernels", ctypes.c_uint32)]
 
 
 class KernelStruct(ctypes.Structure):
@@ -86,6 +102,23 @@ def lib() -> ctypes.CDLL:
     L.mc_negf_grad_workspace_bytes.argtypes = [ctypes.POINTER(KernelStruct), ctypes.POINTER(u64)]
     L.mc_negf_grad.argtypes = [ctypes.POINTER(KernelStruct), u32, vp, vp, u64, vp, vp, dp, vp]
     L.mc_negf_status.argtypes = [ctypes.POINTER(KernelStruct), ctypes.POINTER(u32), vp]
+    L.mc_negf_current_async.argtypes = [ctypes.POINTER(KernelStruct), i32, u32, vp, vp, vp, vp,
+                                        vp, vp]
+    L.mc_negf_batch_bytes.argtypes = [ctypes.POINTER(KernelStruct), i32, ctypes.POINTER(u64)]
+    L.mc_negf_batch_prepare.argtypes = [ctypes.POINTER(KernelStruct), i32,
+                                        ctypes.POINTER(u32), u32, ctypes.POINTER(vp), vp, u64,
+                                        ctypes.POINTER(Batch), vp]
+    L.mc_negf_walk_batch.argtypes = [ctypes.POINTER(Batch), u64, u64, u64, u32,
+                                     ctypes.POINTER(WalkConfig), vp]
+    L.mc_negf_walk_batch_autotune.argtypes = [ctypes.POINTER(Batch), u64, u64, u32,
+                                              ctypes.POINTER(WalkConfig),
+                                              ctypes.POINTER(ctypes.c_float), vp]
+    L.mc_negf_plan_waves.argtypes = [ctypes.POINTER(System), i32, i32, u64,
+                                     ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.mc_negf_graph_begin.argtypes = [vp]
+    L.mc_negf_graph_end.argtypes = [vp, ctypes.POINTER(vp)]
+    L.mc_negf_graph_launch.argtypes = [vp, vp]
+    L.mc_negf_graph_destroy.argtypes = [vp]
     L.mc_negf_profile_begin.argtypes = [ctypes.POINTER(Profile)]
     L.mc_negf_profile_end.argtypes = [ctypes.POINTER(Profile), ctypes.POINTER(ctypes.c_float)]
     L.mc_negf_last_hip_error.argtypes = []
@@ -115,11 +148,13 @@ def _ptr(t) -> ctypes.c_void_p:
 
 
 BUILD_NO_ALIAS = 0x1
+BUILD_NO_DIRECT = 0x2
 
 
 def make_system(W: int, L: int, t: float = 1.0, lead_model: int = 0, gamma_l: float = 0.0,
                 delta_lead: float = 1e-10, flags: int = 0) -> System:
-    """flags: BUILD_NO_ALIAS builds no alias tables (DIRECT current and gradient only)."""
+    """flags: BUILD_NO_ALIAS builds no alias tables (DIRECT current and gradient only),
+    BUILD_NO_DIRECT reserves nothing for the DIRECT solve (Monte Carlo only)."""
     return System(W, L, t, lead_model, gamma_l, delta_lead, flags)
 
 
@@ -310,3 +345,113 @@ def allocate_workspace(system: System, nE: int, device="cuda"):
     import torch
     nbytes = mc_negf_workspace_bytes(system, nE)
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+# ---- async current, batched walks, wave planning, graphs ------------------------------------
+
+def mc_negf_current_async(k: Kernel, mode: int, inject_lead: int, tallies, weights, T, sigmaT,
+                          I_sigma, stream=None) -> int:
+    """As mc_negf_current, but writes (I, sigma_I) into the [2] device tensor I_sigma and
+    does not synchronise (capturable)."""
+    code = lib().mc_negf_current_async(ctypes.byref(k.struct), int(mode), int(inject_lead),
+                                       _ptr(tallies), _ptr(weights), _ptr(T), _ptr(sigmaT),
+                                       _ptr(I_sigma), _stream(stream))
+    return _check("mc_negf_current_async", code)
+
+
+class WalkBatch:
+    """A batched walk over built kernels: the C batch handle plus the buffers it borrows."""
+
+    def __init__(self, struct: Batch, buf, kernels, tallies):
+        self.struct = struct
+        self.buf = buf
+        self.kernels = kernels
+        self.tallies = tallies
+
+
+def _kernel_array(kernels):
+    arr = (KernelStruct * len(kernels))()
+    for i, k in enumerate(kernels):
+        arr[i] = k.struct
+    return arr
+
+
+def mc_negf_batch_prepare(kernels, realizations, inject_lead, tallies, device="cuda",
+                          stream=None) -> WalkBatch:
+    """Unit table for walking every energy of every kernel in one launch; tallies[i] is
+    kernel i's [nE][5] int64 device tensor (accumulated).  Synchronises the stream."""
+    import torch
+    arr = _kernel_array(kernels)
+    nbytes = ctypes.c_uint64(0)
+    _check("mc_negf_batch_bytes", lib().mc_negf_batch_bytes(arr, len(kernels), ctypes.byref(nbytes)))
+    buf = torch.empty(int(nbytes.value), dtype=torch.uint8, device=device)
+    reals = (ctypes.c_uint32 * len(kernels))(*[int(r) for r in realizations])
+    tp = (ctypes.c_void_p * len(kernels))(*[t.data_ptr() for t in tallies])
+    b = Batch()
+    _check("mc_negf_batch_prepare",
+           lib().mc_negf_batch_prepare(arr, len(kernels), reals, int(inject_lead), tp, _ptr(buf),
+                                       int(nbytes.value), ctypes.byref(b), _stream(stream)))
+    return WalkBatch(b, buf, list(kernels), list(tallies))
+
+
+def walk_config(slots=3, wg_size=256, groups=8, walks_per_slot=8, chunk=0) -> WalkConfig:
+    return WalkConfig(slots, wg_size, groups, walks_per_slot, chunk)
+
+
+def mc_negf_walk_batch(b: WalkBatch, seed: int, walker_begin: int, n_walkers: int,
+                       max_steps: int, cfg: WalkConfig = None, stream=None) -> int:
+    code = lib().mc_negf_walk_batch(ctypes.byref(b.struct), int(seed), int(walker_begin),
+                                    int(n_walkers), int(max_steps),
+                                    ctypes.byref(cfg) if cfg is not None else None,
+                                    _stream(stream))
+    return _check("mc_negf_walk_batch", code)
+
+
+def mc_negf_walk_batch_autotune(b: WalkBatch, seed: int, n_walkers: int, max_steps: int,
+                                stream=None):
+    """(fastest WalkConfig, its time in ms) over the library's candidate launch shapes."""
+    best = WalkConfig()
+    ms = ctypes.c_float(0.0)
+    _check("mc_negf_walk_batch_autotune",
+           lib().mc_negf_walk_batch_autotune(ctypes.byref(b.struct), int(seed), int(n_walkers),
+                                             int(max_steps), ctypes.byref(best),
+                                             ctypes.byref(ms), _stream(stream)))
+    return best, float(ms.value)
+
+
+def mc_negf_plan_waves(systems, nE: int, budget_bytes: int):
+    """(order, wave_of, n_waves): first-fit-decreasing assignment of systems to waves whose
+    build workspaces fit budget_bytes (host only)."""
+    n = len(systems)
+    arr = (System * n)(*systems)
+    order = (ctypes.c_int32 * n)()
+    wave_of = (ctypes.c_int32 * n)()
+    nw = ctypes.c_int32(0)
+    _check("mc_negf_plan_waves", lib().mc_negf_plan_waves(arr, n, int(nE), int(budget_bytes),
+                                                          order, wave_of, ctypes.byref(nw)))
+    return list(order), list(wave_of), int(nw.value)
+
+
+class Graph:
+    """A captured and instantiated HIP graph of library calls (and other stream work)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def launch(self, stream=None):
+        _check("mc_negf_graph_launch", lib().mc_negf_graph_launch(self.handle, _stream(stream)))
+
+    def destroy(self):
+        if self.handle:
+            _check("mc_negf_graph_destroy", lib().mc_negf_graph_destroy(self.handle))
+            self.handle = None
+
+
+def mc_negf_graph_begin(stream=None):
+    _check("mc_negf_graph_begin", lib().mc_negf_graph_begin(_stream(stream)))
+
+
+def mc_negf_graph_end(stream=None) -> Graph:
+    h = ctypes.c_void_p(0)
+    _check("mc_negf_graph_end", lib().mc_negf_graph_end(_stream(stream), ctypes.byref(h)))
+    return Graph(h)

@@ -114,7 +114,7 @@ def test_no_alias_build_flag():
     alias_bytes = 4 * n * 1008 * 4 + 4 * n * 1008 * 2
     assert full.value - small.value >= alias_bytes - 512
     assert full.value - small.value <= alias_bytes + 512
-    s3 = M.make_system(10, 100, flags=0x2)
+    s3 = M.make_system(10, 100, flags=0x4)
     assert lib.mc_negf_workspace_bytes(ctypes.byref(s3), 4, ctypes.byref(small)) == M.EINVAL
     # a handle without alias tables is rejected by the walker and the MC current
     ks = M.KernelStruct()
@@ -127,6 +127,82 @@ def test_no_alias_build_flag():
     out = (ctypes.c_double * 2)()
     assert lib.mc_negf_current(ctypes.byref(ks), 0, 0, t, t, t, t,
                                ctypes.cast(out, ctypes.POINTER(ctypes.c_double)), z) == M.EINVAL
+
+
+def test_no_direct_build_flag():
+    lib = M.lib()
+    full, small = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    s = M.make_system(10, 100)
+    assert lib.mc_negf_workspace_bytes(ctypes.byref(s), 4, ctypes.byref(full)) == M.OK
+    s2 = M.make_system(10, 100, flags=M.BUILD_NO_DIRECT | M.BUILD_NO_ALIAS)
+    assert lib.mc_negf_workspace_bytes(ctypes.byref(s2), 4, ctypes.byref(small)) == M.OK
+    direct = 4 * 1010 * 1008 * 8 + 4 * 4 * 1000 * 8  # [nE][Np+2][Np] factor + vectors
+    alias = 4 * 1002 * 1008 * 6
+    assert abs((full.value - small.value) - (direct + alias)) <= 1024
+
+
+def test_plan_waves_first_fit_decreasing():
+    # every system in one wave whose workspaces fit the budget; largest systems first
+    lib = M.lib()
+    Ls = [50, 400, 100, 200, 400, 50, 200, 100]
+    systems = [M.make_system(8, L) for L in Ls]
+    nE = 16
+    sizes = []
+    for sm in systems:
+        b = ctypes.c_uint64(0)
+        assert lib.mc_negf_workspace_bytes(ctypes.byref(sm), nE, ctypes.byref(b)) == M.OK
+        sizes.append(b.value)
+    budget = max(sizes) + sizes[1] // 2
+    order, wave_of, nw = M.mc_negf_plan_waves(systems, nE, budget)
+    assert sorted(order) == list(range(len(Ls)))
+    assert [Ls[i] for i in order] == sorted(Ls, reverse=True)
+    used = [0] * nw
+    for i, w in enumerate(wave_of):
+        used[w] += sizes[i]
+    assert all(u <= budget for u in used)
+    # the two largest cannot share a wave; first fit puts every later system in the first
+    # wave with room
+    assert wave_of[1] != wave_of[4]
+    for k, i in enumerate(order):
+        for w in range(wave_of[i]):
+            room = budget - sum(sizes[j] for j in order[:k] if wave_of[j] == w)
+            assert sizes[i] > room
+    # all in one wave with a large budget; a system above the budget is an error
+    assert M.mc_negf_plan_waves(systems, nE, sum(sizes))[2] == 1
+    with pytest.raises(M.McnegfError) as ei:
+        M.mc_negf_plan_waves(systems, nE, max(sizes) - 1)
+    assert ei.value.code == M.EWS
+
+
+def test_batch_and_graph_validation_without_gpu():
+    lib = M.lib()
+    z = ctypes.c_void_p(0)
+    nb = ctypes.c_uint64(0)
+    assert lib.mc_negf_batch_bytes(None, 1, ctypes.byref(nb)) == M.EINVAL
+    ks = (M.KernelStruct * 1)()
+    ks[0].W, ks[0].L, ks[0].N, ks[0].n_out, ks[0].nE, ks[0].p_pitch = 2, 3, 6, 8, 5, 16
+    for f in ("P", "lead", "status", "counters", "reduce"):
+        setattr(ks[0], f, 4096)
+    assert lib.mc_negf_batch_bytes(ks, 1, ctypes.byref(nb)) == M.EINVAL  # no alias tables
+    ks[0].alias, ks[0].alias_lo = 4096, 4096
+    assert lib.mc_negf_batch_bytes(ks, 1, ctypes.byref(nb)) == M.OK
+    assert nb.value >= 5 * (32 + 24) and nb.value >= 5 * 5 * 8
+    b = M.Batch()
+    assert lib.mc_negf_walk_batch(ctypes.byref(b), 1, 0, 10, 10, None, z) == M.EINVAL
+    b.d_units, b.d_scratch_tallies, b.n_units = 4096, 4096, 5
+    bad = M.walk_config(slots=5)
+    assert lib.mc_negf_walk_batch(ctypes.byref(b), 1, 0, 10, 10, ctypes.byref(bad), z) == M.EINVAL
+    bad = M.walk_config(wg_size=96)
+    assert lib.mc_negf_walk_batch(ctypes.byref(b), 1, 0, 10, 10, ctypes.byref(bad), z) == M.EINVAL
+    bad = M.walk_config(groups=4)
+    assert lib.mc_negf_walk_batch(ctypes.byref(b), 1, 0, 10, 10, ctypes.byref(bad), z) == M.EINVAL
+    assert lib.mc_negf_walk_batch(ctypes.byref(b), 1, 1 << 32, 1, 10, None, z) == M.EINVAL
+    assert lib.mc_negf_walk_batch(ctypes.byref(b), 1, 0, 10, 0, None, z) == M.EINVAL
+    out = (ctypes.c_double * 2)()
+    assert lib.mc_negf_current_async(ctypes.byref(ks[0]), 2, 0, z, z, z, z, z, z) == M.EINVAL
+    assert lib.mc_negf_graph_begin(z) == M.EINVAL   # the default stream cannot be captured
+    assert lib.mc_negf_graph_launch(z, z) == M.EINVAL
+    assert lib.mc_negf_graph_destroy(z) == M.EINVAL
 
 
 def test_energy_grid_is_midpoint():

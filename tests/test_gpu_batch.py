@@ -1,0 +1,184 @@
+"""Batched walks over many built kernels, launch-shape autotuning and HIP graph replay.
+
+The batched walker must reproduce mc_negf_walk's tallies bit for bit (a walker's path depends
+only on (seed, step, walker, energy, tag)), for every launch shape; a captured graph of the
+Monte Carlo step must give, on every replay, exactly the eager results.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from paper_1805_10164_amd import inputs  # noqa: E402
+from paper_1805_10164_amd import mcnegf as M  # noqa: E402
+
+DEV = "cuda"
+SHAPES = [  # (W, L, nE, eta, realization)
+    (2, 5, 3, 0.10, 0),
+    (4, 13, 5, 0.05, 1),
+    (1, 50, 7, 0.05, 2),
+    (8, 6, 2, 0.20, 3),
+    (3, 1, 4, 0.30, 4),
+]
+
+
+def build(W, L, nE, eta, r, flags=0):
+    sysm = M.make_system(W, L, flags=flags)
+    E, w = M.energy_grid(-2.5, 2.5, nE)
+    V = torch.tensor(inputs.random_sites(W * L, 500 + r, -0.4, 0.4), device=DEV)
+    g = torch.full((W * L,), eta, dtype=torch.float64, device=DEV)
+    ws = M.allocate_workspace(sysm, nE)
+    k = M.mc_negf_build_kernel(sysm, V, g, torch.tensor(E, device=DEV), ws)
+    k._keep = (V,)
+    return k, torch.tensor(w, device=DEV)
+
+
+@pytest.fixture(scope="module")
+def kernels():
+    ks = [build(*s) for s in SHAPES]
+    torch.cuda.synchronize()
+    return ks
+
+
+def reference_tallies(ks, seed, lead, wbegin, n):
+    out = []
+    for (k, _), s in zip(ks, SHAPES):
+        t = torch.zeros((k.nE, M.TALLY_N), dtype=torch.int64, device=DEV)
+        M.mc_negf_walk(k, seed, s[4], lead, wbegin, n, 1_000_000, t)
+        out.append(t)
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in out]
+
+
+CONFIGS = [
+    None,
+    dict(slots=1, wg_size=64, groups=1, walks_per_slot=2),
+    dict(slots=2, wg_size=128, groups=8, walks_per_slot=32),
+    dict(slots=3, wg_size=256, groups=8, walks_per_slot=8),
+    dict(slots=4, wg_size=512, groups=8, chunk=100),
+    dict(slots=4, wg_size=64, groups=1, chunk=1),
+]
+
+
+@pytest.mark.parametrize("lead", [0, 1])
+def test_walk_batch_matches_per_kernel_walks(kernels, lead):
+    seed, wbegin, n = 0x1234_5678_9ABC, 777, 3001  # ragged against every chunk size
+    ref = reference_tallies(kernels, seed, lead, wbegin, n)
+    for cfg in CONFIGS:
+        tal = [torch.zeros((k.nE, M.TALLY_N), dtype=torch.int64, device=DEV) for k, _ in kernels]
+        b = M.mc_negf_batch_prepare([k for k, _ in kernels], [s[4] for s in SHAPES], lead, tal)
+        assert b.struct.n_units == sum(s[2] for s in SHAPES)
+        M.mc_negf_walk_batch(b, seed, wbegin, n, 1_000_000,
+                             M.walk_config(**cfg) if cfg else None)
+        torch.cuda.synchronize()
+        for i, t in enumerate(tal):
+            got = t.cpu().numpy()
+            assert (got == ref[i]).all(), (cfg, i)
+            assert (got[:, 0] + got[:, 1] + got[:, 2] == n).all()
+
+
+def test_walk_batch_split_ranges_add_up(kernels):
+    # two batched calls over [a, b) and [b, c) equal one call over [a, c)
+    seed = 99
+    ref = reference_tallies(kernels, seed, 0, 0, 2000)
+    tal = [torch.zeros((k.nE, M.TALLY_N), dtype=torch.int64, device=DEV) for k, _ in kernels]
+    b = M.mc_negf_batch_prepare([k for k, _ in kernels], [s[4] for s in SHAPES], 0, tal)
+    M.mc_negf_walk_batch(b, seed, 0, 1234, 1_000_000)
+    M.mc_negf_walk_batch(b, seed, 1234, 766, 1_000_000, M.walk_config(slots=1, groups=1))
+    torch.cuda.synchronize()
+    for i, t in enumerate(tal):
+        assert (t.cpu().numpy() == ref[i]).all()
+
+
+def test_walk_batch_autotune_leaves_tallies_and_picks_a_valid_shape(kernels):
+    tal = [torch.zeros((k.nE, M.TALLY_N), dtype=torch.int64, device=DEV) for k, _ in kernels]
+    b = M.mc_negf_batch_prepare([k for k, _ in kernels], [s[4] for s in SHAPES], 0, tal)
+    best, ms = M.mc_negf_walk_batch_autotune(b, 5, 2000, 1_000_000)
+    assert ms > 0.0
+    assert best.slots in (1, 2, 3, 4) and best.wg_size in (64, 256) and best.groups in (1, 8)
+    assert best.walks_per_slot in (2, 8, 32)
+    torch.cuda.synchronize()
+    assert all((t == 0).all().item() for t in tal)
+    ref = reference_tallies(kernels, 5, 0, 0, 2000)
+    M.mc_negf_walk_batch(b, 5, 0, 2000, 1_000_000, best)
+    torch.cuda.synchronize()
+    for i, t in enumerate(tal):
+        assert (t.cpu().numpy() == ref[i]).all()
+
+
+def test_batch_rejects_kernel_without_alias_tables():
+    k, _ = build(2, 4, 2, 0.1, 0, flags=M.BUILD_NO_ALIAS)
+    t = torch.zeros((2, M.TALLY_N), dtype=torch.int64, device=DEV)
+    with pytest.raises(M.McnegfError) as ei:
+        M.mc_negf_batch_prepare([k], [0], 0, [t])
+    assert ei.value.code == M.EINVAL
+
+
+def test_current_async_matches_current(kernels):
+    k, w = kernels[1]
+    nE = k.nE
+    T = torch.empty(nE, dtype=torch.float64, device=DEV)
+    sg = torch.empty_like(T)
+    tal = torch.zeros((nE, M.TALLY_N), dtype=torch.int64, device=DEV)
+    M.mc_negf_walk(k, 3, 1, 0, 0, 5000, 1_000_000, tal)
+    _, I0, s0 = M.mc_negf_current(k, 0, 0, tal, w, T, sg)
+    _, I1, _ = M.mc_negf_current(k, 1, 0, None, w, T, sg)
+    out = torch.full((2,), np.nan, dtype=torch.float64, device=DEV)
+    M.mc_negf_current_async(k, 0, 0, tal, w, T, sg, out)
+    torch.cuda.synchronize()
+    assert out[0].item() == I0 and out[1].item() == s0
+    M.mc_negf_current_async(k, 1, 0, None, w, T, sg, out)
+    torch.cuda.synchronize()
+    assert out[0].item() == I1 and out[1].item() == 0.0
+
+
+def test_graph_replays_match_eager(kernels):
+    # Capture: zero the tallies (a fill kernel, no memset node), one batched walk, the MC and
+    # DIRECT currents of every kernel into device outputs.  Replay three times with eager
+    # work and synchronisations between replays; every replay must equal the eager run.
+    ks = [k for k, _ in kernels]
+    ws_ = [w for _, w in kernels]
+    tal = [torch.zeros((k.nE, M.TALLY_N), dtype=torch.int64, device=DEV) for k in ks]
+    T = [torch.empty(k.nE, dtype=torch.float64, device=DEV) for k in ks]
+    sg = [torch.empty(k.nE, dtype=torch.float64, device=DEV) for k in ks]
+    out = torch.zeros((len(ks), 2, 2), dtype=torch.float64, device=DEV)
+    b = M.mc_negf_batch_prepare(ks, [s[4] for s in SHAPES], 0, tal)
+    cfg = M.walk_config(slots=2, wg_size=256, groups=8, walks_per_slot=8)
+    seed, n = 4242, 4000
+
+    def step(stream):
+        for t in tal:
+            t.zero_()
+        M.mc_negf_walk_batch(b, seed, 0, n, 1_000_000, cfg, stream)
+        for i, k in enumerate(ks):
+            M.mc_negf_current_async(k, 0, 0, tal[i], ws_[i], T[i], sg[i], out[i, 0], stream)
+            M.mc_negf_current_async(k, 1, 0, None, ws_[i], T[i], sg[i], out[i, 1], stream)
+
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        step(s)
+    s.synchronize()
+    eager_out = out.cpu().numpy().copy()
+    eager_tal = [t.cpu().numpy().copy() for t in tal]
+    with torch.cuda.stream(s):
+        M.mc_negf_graph_begin(s)
+        step(s)
+        g = M.mc_negf_graph_end(s)
+    try:
+        for rep in range(3):
+            out.fill_(np.nan)
+            for t in tal:
+                t.fill_(-1)
+            # unrelated eager work between replays
+            x = torch.randn(1 << 16, device=DEV, dtype=torch.float64)
+            (x * x).sum().item()
+            g.launch(s)
+            s.synchronize()
+            assert (out.cpu().numpy() == eager_out).all(), rep
+            for t, e in zip(tal, eager_tal):
+                assert (t.cpu().numpy() == e).all(), rep
+    finally:
+        g.destroy()
