@@ -12,7 +12,9 @@ times, the roofline of the dominant kernel, time to a 1% relative deviation of t
 current for MC and for the DIRECT GPU solve, and the oracle timed on the host's cores for a
 bounded sample of the same workload.  A "grad" object adds the gradient (dI/dV_i for all
 sites, dI/dgamma_i) on the W=16 x L=200 differentiation workload with its own roofline and
-oracle sample.
+oracle sample.  A "batched" object adds the batched uneven workload (64 realizations x 256
+energies of W=8 wires of four lengths) walked in memory-bounded waves, each wave one replayed
+HIP graph with one batched walker launch.
 """
 from __future__ import annotations
 
@@ -48,6 +50,10 @@ def parse():
     ap.add_argument("--no-ttp", action="store_true", help="skip the time-to-1%% measurement")
     ap.add_argument("--no-grad", action="store_true",
                     help="skip the gradient measurement on the differentiation workload")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched uneven workload (64 realizations x 256 energies)")
+    ap.add_argument("--batch-budget-gb", type=float, default=160.0,
+                    help="device memory for one wave of build workspaces in the batched leg")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the timed steps, run one plain device copy of this many MiB "
                          "(reference dispatch for HBM byte counters)")
@@ -207,6 +213,101 @@ def grad_bench(torch, dev, steps, warmup, with_cpu):
     return out
 
 
+def batched_bench(torch, dev, steps, warmup, budget_gb, seed):
+    """The batched uneven workload: realizations planned into memory-bounded waves
+    (mc_negf_plan_waves), each wave captured once as a HIP graph of its builds, one batched
+    walk of all its (realization, energy) units with the autotuned launch shape, and the MC
+    current of every realization; one step replays every wave's graph."""
+    wls = inputs.batch_workloads()
+    base = inputs.BATCH_W8
+    flags = M.BUILD_NO_DIRECT  # Monte Carlo only
+    systems = [M.make_system(w.W, w.L, w.t, w.lead_model, w.gamma_l, w.delta_lead, flags)
+               for w in wls]
+    nE, nw = base.n_energies, base.walkers_per_energy
+    budget = int(budget_gb * (1 << 30))
+    order, wave_of, n_waves = M.mc_negf_plan_waves(systems, nE, budget)
+    sizes = [M.mc_negf_workspace_bytes(sm, nE) for sm in systems]
+    waves = [[i for i in order if wave_of[i] == wv] for wv in range(n_waves)]
+    pool_bytes = max(sum((sizes[i] + 255) // 256 * 256 for i in wv) for wv in waves)
+    pool = torch.empty(pool_bytes, dtype=torch.uint8, device=dev)
+    E, w = M.energy_grid(base.emin, base.emax, nE)
+    tE, tw = torch.tensor(E, device=dev), torch.tensor(w, device=dev)
+    V = [torch.tensor(inputs.onsite(wl), device=dev) for wl in wls]
+    g = [torch.tensor(inputs.dephasing(wl), device=dev) for wl in wls]
+    tal = [torch.zeros((nE, M.TALLY_N), dtype=torch.int64, device=dev) for _ in wls]
+    T = [torch.empty(nE, dtype=torch.float64, device=dev) for _ in wls]
+    sg = [torch.empty(nE, dtype=torch.float64, device=dev) for _ in wls]
+    out = torch.zeros((len(wls), 2), dtype=torch.float64, device=dev)
+    s = torch.cuda.Stream()
+    plans = []
+    cfg, tune_ms = None, None
+    with torch.cuda.stream(s):
+        for wv in waves:
+            off, ks = 0, {}
+            for i in wv:
+                ws = pool[off:off + sizes[i]]
+                off += (sizes[i] + 255) // 256 * 256
+                ks[i] = (ws, M.mc_negf_build_kernel(systems[i], V[i], g[i], tE, ws, s))
+            b = M.mc_negf_batch_prepare([ks[i][1] for i in wv], [wls[i].realization for i in wv],
+                                        0, [tal[i] for i in wv], dev, s)
+            if cfg is None:  # tune the launch shape once, on the first (largest) wave
+                cfg, tune_ms = M.mc_negf_walk_batch_autotune(b, seed, max(1, nw // 10),
+                                                             1_000_000, s)
+            plans.append((wv, ks, b))
+        graphs = []
+        for wv, ks, b in plans:
+            M.mc_negf_graph_begin(s)
+            for i in wv:
+                tal[i].zero_()
+                M.mc_negf_build_kernel(systems[i], V[i], g[i], tE, ks[i][0], s)
+            M.mc_negf_walk_batch(b, seed, 0, nw, 1_000_000, cfg, s)
+            for i in wv:
+                M.mc_negf_current_async(ks[i][1], 0, 0, tal[i], tw, T[i], sg[i], out[i], s)
+            graphs.append(M.mc_negf_graph_end(s))
+    try:
+        for _ in range(max(1, warmup)):
+            for gr in graphs:
+                gr.launch(s)
+        s.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in graphs]
+        wave_ms = [0.0] * len(graphs)
+        walk_steps = 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for j, gr in enumerate(graphs):
+                ev[j][0].record(s)
+                gr.launch(s)
+                ev[j][1].record(s)
+            s.synchronize()
+            for j in range(len(graphs)):
+                wave_ms[j] += ev[j][0].elapsed_time(ev[j][1]) / steps
+            walk_steps += int(sum(t[:, M.TALLY_STEPS].sum().item() for t in tal))
+        wall = (time.perf_counter() - t0) / steps
+    finally:
+        for gr in graphs:
+            gr.destroy()
+    res = out.cpu().numpy()
+    tally = np.stack([t.cpu().numpy() for t in tal])
+    counts = dict(zip(*np.unique([wl.L for wl in wls], return_counts=True)))
+    result = {
+        "workload": f"{len(wls)} realizations x {nE} energies, W={base.W}, L drawn from "
+                    f"{list(inputs.BATCH_LENGTHS)} (counts {dict((int(k), int(v)) for k, v in counts.items())}), "
+                    f"eta={base.eta}t, disorder U[-{base.disorder},{base.disorder}]t, {nw} walkers/energy",
+        "value": walk_steps / steps / wall, "unit": "walk steps/s",
+        "ms_per_batch": 1e3 * wall, "waves": n_waves, "wave_ms": wave_ms,
+        "wave_sizes": [len(wv) for wv in waves], "pool_gb": pool_bytes / 2 ** 30,
+        "walk_config": cfg.as_dict(), "autotune_best_ms_at_tenth_walkers": tune_ms,
+        "walkers": int(len(wls) * nE * nw), "steps_per_batch": walk_steps // steps,
+        "truncated": int(tally[:, :, M.TALLY_TRUNC].sum()),
+        "I_mc": [float(x) for x in res[:, 0]], "sigma_I_mc": [float(x) for x in res[:, 1]],
+        "graph": "one captured graph per wave (builds, batched walk, MC currents), replayed",
+    }
+    del pool, plans
+    torch.cuda.empty_cache()
+    return result
+
+
 def time_to_1pct(p: Problem, torch, seed, walk_on):
     """Wall time to a 1% relative deviation of I, median of 5 warm repetitions.
     MC: build + walker batches doubling from 1024 per energy until sigma_I <= 1% of I.
@@ -355,10 +456,13 @@ def main():
     if not args.no_cpu_baseline:
         mid = probs[len(probs) // 2].wl
         line["cpu_baseline"] = cpu_baseline(mid, seed)
+    del probs, results
+    torch.cuda.empty_cache()
     if not args.no_grad:
-        del probs, results
-        torch.cuda.empty_cache()
         line["grad"] = grad_bench(torch, dev, args.steps, args.warmup, not args.no_cpu_baseline)
+    if not args.no_batched:
+        line["batched"] = batched_bench(torch, dev, args.steps, args.warmup, args.batch_budget_gb,
+                                        seed)
     print(json.dumps(line), flush=True)
 
 

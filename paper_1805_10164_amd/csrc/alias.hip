@@ -105,15 +105,30 @@ hipError_t launch_lead_terms(const mcnegf_kernel& k, hipStream_t s) {
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- block scans (256 threads)
+// ---------------------------------------------------------------- block reductions (BT threads)
+template <int BT>
+__device__ inline double block_sum(double v, double* red) {
+    const int tid = threadIdx.x;
+    red[tid] = v;
+    __syncthreads();
+    for (int s = BT / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
 // Exclusive scan of one double and one int per thread, in thread order; returns totals.
+template <int BT>
 __device__ inline void block_scan2(double& xd, int& xi, double& totd, int& toti, double* sd,
                                    int* si) {
     const int tid = threadIdx.x;
     sd[tid] = xd;
     si[tid] = xi;
     __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
+    for (int off = 1; off < BT; off <<= 1) {
         double ad = 0.0;
         int ai = 0;
         if (tid >= off) {
@@ -125,8 +140,8 @@ __device__ inline void block_scan2(double& xd, int& xi, double& totd, int& toti,
         si[tid] += ai;
         __syncthreads();
     }
-    totd = sd[255];
-    toti = si[255];
+    totd = sd[BT - 1];
+    toti = si[BT - 1];
     xd = sd[tid] - xd;  // exclusive
     xi = si[tid] - xi;
     __syncthreads();
@@ -149,27 +164,32 @@ struct AliasArgs {
     double open_cut;  // an injection row needs Tr Gamma_p > open_cut
 };
 
-__global__ void __launch_bounds__(256) alias_build_kernel(AliasArgs a) {
+// One workgroup of BT threads per row.  LDS per row: the scaled weights (n doubles), the
+// light starts and heavy ends in one array of n + 1 doubles (lights from the front with the
+// total deficit after the last one, heavies from the back: heavy m at n - m), the heavy
+// items' indices and every item's rank (n ints each): 24 n bytes.
+template <int BT>
+__global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
     extern __shared__ double smem[];
-    __shared__ double sd[256];
-    __shared__ int si[256];
-    __shared__ double red[256];
+    __shared__ double sd[BT];
+    __shared__ int si[BT];
     const int N = a.N;
     const int n = N + 2;
     const int row = blockIdx.x;
     const int e = blockIdx.y;
     const int tid = threadIdx.x;
-    double* s = smem;                                  // [n]   scaled weights
-    double* lightD = s + n;                            // [n+1] light starts (+ total deficit)
-    double* heavyC = lightD + n + 1;                   // [n]   heavy ends (inclusive)
-    int* heavyIdx = reinterpret_cast<int*>(heavyC + n);  // [n]
-    int* rankv = heavyIdx + n;                         // [n]   light rank, or ~heavy rank
+    double* s = smem;                                    // [n]   scaled weights
+    double* lh = s + n;                                  // [n+1] light starts | heavy ends
+    int* heavyIdx = reinterpret_cast<int*>(lh + n + 1);  // [n]
+    int* rankv = heavyIdx + n;                           // [n]   light rank, or ~heavy rank
+    auto lightD = [&](int r) -> double& { return lh[r]; };
+    auto heavyC = [&](int m) -> double& { return lh[n - m]; };
 
     const double* lead = a.lead + (size_t)e * MCNEGF_LEAD_NTERMS;
     const double* wLe = a.wL + (size_t)e * N;
     const double* wRe = a.wR + (size_t)e * N;
     // 1. weights of this row
-    for (int i = tid; i < n; i += 256) {
+    for (int i = tid; i < n; i += BT) {
         double w;
         if (row < N) {
             if (i < N) w = a.gamma[i] * a.P[((size_t)e * N + row) * a.ldP + i];
@@ -185,11 +205,11 @@ __global__ void __launch_bounds__(256) alias_build_kernel(AliasArgs a) {
     }
     __syncthreads();
     // 2. total over contiguous per-thread chunks (fixed order)
-    const int chunk = (n + 255) / 256;
+    const int chunk = (n + BT - 1) / BT;
     const int i0 = min(tid * chunk, n), i1 = min(i0 + chunk, n);
     double part = 0.0;
     for (int i = i0; i < i1; ++i) part += s[i];
-    double total = block_sum256(part, red);
+    double total = block_sum<BT>(part, sd);
     if (row >= N) {
         // no open channel in this lead (outside its band, Gamma only from the regulator)
         double trg = 0.0;
@@ -214,7 +234,7 @@ __global__ void __launch_bounds__(256) alias_build_kernel(AliasArgs a) {
     }
     if (!(total > 0.0) || !isfinite(total)) {
         // Degenerate row: every bucket exits at lead L (its estimator weight is zero).
-        for (int i = tid; i < n; i += 256) {
+        for (int i = tid; i < n; i += BT) {
             out[i] = (uint32_t)N;
             out_lo[i] = 0;
         }
@@ -232,27 +252,27 @@ __global__ void __launch_bounds__(256) alias_build_kernel(AliasArgs a) {
     }
     double Dtot, Utot;
     int NLtot, NHtot;
-    block_scan2(dl, nl, Dtot, NLtot, sd, si);
-    block_scan2(uh, nh, Utot, NHtot, sd, si);
+    block_scan2<BT>(dl, nl, Dtot, NLtot, sd, si);
+    block_scan2<BT>(uh, nh, Utot, NHtot, sd, si);
     for (int i = i0; i < i1; ++i) {
         const double v = s[i];
         if (v < 1.0) {
-            lightD[nl] = dl;
+            lightD(nl) = dl;
             rankv[i] = nl;
             dl += 1.0 - v;
             ++nl;
         } else {
             uh += v - 1.0;
-            heavyC[nh] = uh;
+            heavyC(nh) = uh;
             heavyIdx[nh] = i;
             rankv[i] = ~nh;
             ++nh;
         }
     }
-    if (tid == 0) lightD[NLtot] = Dtot;
+    if (tid == 0) lightD(NLtot) = Dtot;  // index NLtot = n - NHtot: below every heavy slot
     __syncthreads();
     // 4. thresholds and aliases
-    for (int i = tid; i < n; i += 256) {
+    for (int i = tid; i < n; i += BT) {
         const int r = rankv[i];
         double q;
         int al;
@@ -260,12 +280,12 @@ __global__ void __launch_bounds__(256) alias_build_kernel(AliasArgs a) {
             q = 1.0;
             al = i;
         } else if (r >= 0) {
-            // light: first heavy m with heavyC[m] > D_i
-            const double D = lightD[r];
+            // light: first heavy m with heavyC(m) > D_i
+            const double D = lightD(r);
             int lo = 0, hi = NHtot;
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
-                if (heavyC[mid] > D) hi = mid; else lo = mid + 1;
+                if (heavyC(mid) > D) hi = mid; else lo = mid + 1;
             }
             if (lo >= NHtot) lo = NHtot - 1;
             q = s[i];
@@ -276,13 +296,13 @@ __global__ void __launch_bounds__(256) alias_build_kernel(AliasArgs a) {
                 q = 1.0;
                 al = i;
             } else {
-                const double C = heavyC[m];
-                int lo = 0, hi = NLtot;  // first light start >= C (lightD[NLtot] = Dtot)
+                const double C = heavyC(m);
+                int lo = 0, hi = NLtot;  // first light start >= C (lightD(NLtot) = Dtot)
                 while (lo < hi) {
                     const int mid = (lo + hi) >> 1;
-                    if (lightD[mid] >= C) hi = mid; else lo = mid + 1;
+                    if (lightD(mid) >= C) hi = mid; else lo = mid + 1;
                 }
-                q = 1.0 + C - lightD[lo];
+                q = 1.0 + C - lightD(lo);
                 q = q < 0.0 ? 0.0 : q;
                 al = heavyIdx[m + 1];
             }
@@ -317,15 +337,21 @@ hipError_t launch_alias_build(const mcnegf_kernel& k, hipStream_t s) {
     a.W = k.W;
     a.open_cut = 1e3 * k.delta_lead * k.t * k.W;
     const int n = k.n_out;
-    const size_t lds = (size_t)n * 8 + (size_t)(n + 1) * 8 + (size_t)n * 8 + (size_t)n * 8;
+    const size_t lds = (size_t)n * 8 + (size_t)(n + 1) * 8 + (size_t)n * 4 + (size_t)n * 4;
+    // long rows: 1024 threads per row keep 16 wavefronts per CU although one row's LDS
+    // allows few workgroups per CU
+    const bool wide = n > 1536;
+    const void* fn = wide ? (const void*)alias_build_kernel<1024> : (const void*)alias_build_kernel<256>;
     if (lds > 65536) {
-        hipError_t err = hipFuncSetAttribute((const void*)alias_build_kernel,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (err != hipSuccess) return err;
     }
     {
         MCNEGF_TIMED("alias_build_kernel", s);
-        hipLaunchKernelGGL(alias_build_kernel, dim3(n, k.nE), dim3(256), lds, s, a);
+        if (wide)
+            hipLaunchKernelGGL(alias_build_kernel<1024>, dim3(n, k.nE), dim3(1024), lds, s, a);
+        else
+            hipLaunchKernelGGL(alias_build_kernel<256>, dim3(n, k.nE), dim3(256), lds, s, a);
     }
     return hipGetLastError();
 }

@@ -63,6 +63,26 @@ DIFF_W16_L200 = Workload(name="diff_W16_L200", W=16, L=200, eta=0.02, disorder=0
                          emin=-3.5, emax=3.5, n_energies=128, walkers_per_energy=0)
 
 
+# Batched workload: 64 disorder realizations x 256 energies, W = 8, L drawn uniformly from
+# {50, 100, 200, 400} per realization (seeded), eta = 0.05 t, disorder U[-0.5 t, 0.5 t],
+# energies in [-3.5 t, 3.5 t] (inside the W = 8 lead band |E| < 3.879 t), 1e5 walkers/energy.
+BATCH_W8 = Workload(name="batch_W8", W=8, L=50, eta=0.05, disorder=0.5, emin=-3.5, emax=3.5,
+                    n_energies=256, walkers_per_energy=100_000)
+BATCH_LENGTHS = (50, 100, 200, 400)
+BATCH_REALIZATIONS = 64
+BATCH_LENGTH_SEED = 1806
+
+
+def batch_workloads(n: int = BATCH_REALIZATIONS):
+    """The batched workload's realizations: realization r has length L_r drawn uniformly
+    from BATCH_LENGTHS with numpy's default generator seeded by BATCH_LENGTH_SEED, and the
+    disorder of realization r (see onsite)."""
+    rng = np.random.default_rng(BATCH_LENGTH_SEED)
+    Ls = rng.choice(np.array(BATCH_LENGTHS), size=n)
+    return [BATCH_W8.replace(L=int(L), realization=r, name=f"batch_W8_L{int(L)}_r{r}")
+            for r, L in enumerate(Ls)]
+
+
 def onsite(w: Workload) -> np.ndarray:
     """Onsite energies V_i (float64, length N, slice-major i = x*W + y).
 

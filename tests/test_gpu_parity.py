@@ -157,6 +157,26 @@ def test_alias_tables_sample_the_kernel_rows(built):
             assert np.abs(p - ref).max() < 4.0 * 2.0 ** -32 + 1e-12, (name, e, r)
 
 
+def test_alias_tables_of_long_rows():
+    # n = N + 2 > 1536 takes the 1024-thread row build; same bound as the short rows
+    c = case(W=16, L=100, eta=0.04, disorder=0.3, nE=2, emin=-3.0, emax=2.0)
+    k = gpu_build(c)
+    sols = oracle_solve(c)
+    thr_all, al_all = k.alias_tables()
+    n = k.n_out
+    assert n > 1536
+    rng = np.random.default_rng(1)
+    for e, s_ in enumerate(sols):
+        K = s_.transition_kernel()
+        rows = sorted(set([0, 1, n - 1, n - 2, n - 3] + list(rng.integers(0, n, 6))))
+        for r in rows:
+            thr, al = thr_all[e, r, :n], al_all[e, r, :n]
+            assert (al < n).all()
+            p = table_distribution(thr, al)
+            ref = K[r] / K[r].sum()
+            assert np.abs(p - ref).max() < 4.0 * 2.0 ** -32 + 1e-12, (e, r)
+
+
 def test_direct_current_matches_oracle(built):
     name, c, k, sols = built
     nE = len(c["E"])
