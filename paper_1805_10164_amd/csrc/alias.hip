@@ -12,8 +12,10 @@
 // Alias table of one row (Walker's method; construction by prefix sums so that a whole
 // workgroup builds one row): scale the weights to mean one, s_i = w_i n / sum w.  Light
 // items (s < 1) have deficit d_i = 1 - s_i, heavy items (s >= 1) surplus u_i = s_i - 1.
-// Lay the deficits of the light items end to end in index order (light i starts at D_i)
-// and the surpluses of the heavy items likewise (heavy m ends at C_m).  Filling the light
+// Lay the deficits of the light items end to end in a fixed order (light i starts at D_i;
+// thread t of the row's workgroup owns items t, t + BT, ..., and the order is by thread,
+// then by item) and the surpluses of the heavy items likewise (heavy m ends at C_m); any
+// fixed order gives an exact table.  Filling the light
 // buckets from the heavy items in order, heavy m serves exactly the lights whose start D
 // lies in [C_{m-1}, C_m); it is left with 1 + C_m - D* where D* is the first light start at
 // or after C_m (or the total deficit), which becomes its own threshold, and the next heavy
@@ -106,16 +108,34 @@ hipError_t launch_lead_terms(const mcnegf_kernel& k, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- block reductions (BT threads)
+// Sums and exclusive scans in a fixed order (lanes within a wavefront by shuffles, then the
+// wavefronts in order through LDS): two barriers each instead of one per tree level.
+__device__ inline double wave_incl_scan(double v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double t = __shfl_up(v, o, 64);
+        v = lane >= o ? v + t : v;
+    }
+    return v;
+}
+__device__ inline int wave_incl_scan_int(int v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        v = lane >= o ? v + t : v;
+    }
+    return v;
+}
+
 template <int BT>
 __device__ inline double block_sum(double v, double* red) {
-    const int tid = threadIdx.x;
-    red[tid] = v;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const double incl = wave_incl_scan(v, lane);
+    if (lane == 63) red[wv] = incl;
     __syncthreads();
-    for (int s = BT / 2; s > 0; s >>= 1) {
-        if (tid < s) red[tid] += red[tid + s];
-        __syncthreads();
-    }
-    const double r = red[0];
+    double r = 0.0;
+#pragma unroll
+    for (int w = 0; w < BT / 64; ++w) r += red[w];
     __syncthreads();
     return r;
 }
@@ -124,26 +144,27 @@ __device__ inline double block_sum(double v, double* red) {
 template <int BT>
 __device__ inline void block_scan2(double& xd, int& xi, double& totd, int& toti, double* sd,
                                    int* si) {
-    const int tid = threadIdx.x;
-    sd[tid] = xd;
-    si[tid] = xi;
-    __syncthreads();
-    for (int off = 1; off < BT; off <<= 1) {
-        double ad = 0.0;
-        int ai = 0;
-        if (tid >= off) {
-            ad = sd[tid - off];
-            ai = si[tid - off];
-        }
-        __syncthreads();
-        sd[tid] += ad;
-        si[tid] += ai;
-        __syncthreads();
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const double id = wave_incl_scan(xd, lane);
+    const int ii = wave_incl_scan_int(xi, lane);
+    if (lane == 63) {
+        sd[wv] = id;
+        si[wv] = ii;
     }
-    totd = sd[BT - 1];
-    toti = si[BT - 1];
-    xd = sd[tid] - xd;  // exclusive
-    xi = si[tid] - xi;
+    __syncthreads();
+    double pd = 0.0, td = 0.0;
+    int pi = 0, ti = 0;
+#pragma unroll
+    for (int w = 0; w < BT / 64; ++w) {
+        pd += w < wv ? sd[w] : 0.0;
+        pi += w < wv ? si[w] : 0;
+        td += sd[w];
+        ti += si[w];
+    }
+    totd = td;
+    toti = ti;
+    xd = pd + id - xd;  // exclusive
+    xi = pi + ii - xi;
     __syncthreads();
 }
 
@@ -164,51 +185,54 @@ struct AliasArgs {
     double open_cut;  // an injection row needs Tr Gamma_p > open_cut
 };
 
-// One workgroup of BT threads per row.  LDS per row: the scaled weights (n doubles), the
-// light starts and heavy ends in one array of n + 1 doubles (lights from the front with the
-// total deficit after the last one, heavies from the back: heavy m at n - m), the heavy
-// items' indices and every item's rank (n ints each): 24 n bytes.
-template <int BT>
+// One workgroup of BT threads per row; thread t owns the items t + BT k (k < KM, n <= BT KM)
+// and keeps their weights, ranks and starts / ends in registers.  LDS holds what other
+// threads search: the light starts and heavy ends in one array of n + 1 doubles (lights from
+// the front with the total deficit after the last one, heavies from the back: heavy m at
+// n - m) and the heavy items' indices: 12 n bytes per row.
+template <int BT, int KM>
 __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
     extern __shared__ double smem[];
-    __shared__ double sd[BT];
-    __shared__ int si[BT];
+    __shared__ double sd[BT / 64];  // one partial per wavefront
+    __shared__ int si[BT / 64];
     const int N = a.N;
     const int n = N + 2;
     const int row = blockIdx.x;
     const int e = blockIdx.y;
     const int tid = threadIdx.x;
-    double* s = smem;                                    // [n]   scaled weights
-    double* lh = s + n;                                  // [n+1] light starts | heavy ends
+    double* lh = smem;                                   // [n+1] light starts | heavy ends
     int* heavyIdx = reinterpret_cast<int*>(lh + n + 1);  // [n]
-    int* rankv = heavyIdx + n;                           // [n]   light rank, or ~heavy rank
     auto lightD = [&](int r) -> double& { return lh[r]; };
     auto heavyC = [&](int m) -> double& { return lh[n - m]; };
 
     const double* lead = a.lead + (size_t)e * MCNEGF_LEAD_NTERMS;
     const double* wLe = a.wL + (size_t)e * N;
     const double* wRe = a.wR + (size_t)e * N;
-    // 1. weights of this row
-    for (int i = tid; i < n; i += BT) {
-        double w;
-        if (row < N) {
-            if (i < N) w = a.gamma[i] * a.P[((size_t)e * N + row) * a.ldP + i];
-            else w = (i == N) ? wLe[row] : wRe[row];
-        } else if (row == N) {
-            if (i < N) w = a.gamma[i] * wLe[i];
-            else w = (i == N) ? lead[MCNEGF_LEAD_TLL] : lead[MCNEGF_LEAD_TRL];
-        } else {
-            if (i < N) w = a.gamma[i] * wRe[i];
-            else w = (i == N) ? lead[MCNEGF_LEAD_TLR] : lead[MCNEGF_LEAD_TRR];
+    // 1. weights of this row (items beyond n weigh 0 and are skipped below)
+    double w[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        const int i = tid + BT * k;
+        double v = 0.0;
+        if (i < n) {
+            if (row < N) {
+                if (i < N) v = a.gamma[i] * a.P[((size_t)e * N + row) * a.ldP + i];
+                else v = (i == N) ? wLe[row] : wRe[row];
+            } else if (row == N) {
+                if (i < N) v = a.gamma[i] * wLe[i];
+                else v = (i == N) ? lead[MCNEGF_LEAD_TLL] : lead[MCNEGF_LEAD_TRL];
+            } else {
+                if (i < N) v = a.gamma[i] * wRe[i];
+                else v = (i == N) ? lead[MCNEGF_LEAD_TLR] : lead[MCNEGF_LEAD_TRR];
+            }
+            v = v > 0.0 ? v : (v == v ? 0.0 : v);  // clamp rounding negatives, keep NaN
         }
-        s[i] = w > 0.0 ? w : (w == w ? 0.0 : w);   // clamp rounding negatives, keep NaN
+        w[k] = v;
     }
-    __syncthreads();
-    // 2. total over contiguous per-thread chunks (fixed order)
-    const int chunk = (n + BT - 1) / BT;
-    const int i0 = min(tid * chunk, n), i1 = min(i0 + chunk, n);
+    // 2. total (fixed order: by thread, then by item)
     double part = 0.0;
-    for (int i = i0; i < i1; ++i) part += s[i];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) part += w[k];
     double total = block_sum<BT>(part, sd);
     if (row >= N) {
         // no open channel in this lead (outside its band, Gamma only from the regulator)
@@ -244,36 +268,52 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
     const double scale = (double)n / total;
     double dl = 0.0, uh = 0.0;
     int nl = 0, nh = 0;
-    for (int i = i0; i < i1; ++i) {
-        const double si_ = s[i] * scale;
-        s[i] = si_;
-        if (si_ < 1.0) { dl += 1.0 - si_; ++nl; }
-        else { uh += si_ - 1.0; ++nh; }
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        const double v = w[k] * scale;
+        w[k] = v;
+        if (tid + BT * k < n) {
+            if (v < 1.0) { dl += 1.0 - v; ++nl; }
+            else { uh += v - 1.0; ++nh; }
+        }
     }
     double Dtot, Utot;
     int NLtot, NHtot;
     block_scan2<BT>(dl, nl, Dtot, NLtot, sd, si);
     block_scan2<BT>(uh, nh, Utot, NHtot, sd, si);
-    for (int i = i0; i < i1; ++i) {
-        const double v = s[i];
-        if (v < 1.0) {
-            lightD(nl) = dl;
-            rankv[i] = nl;
-            dl += 1.0 - v;
-            ++nl;
-        } else {
-            uh += v - 1.0;
-            heavyC(nh) = uh;
-            heavyIdx[nh] = i;
-            rankv[i] = ~nh;
-            ++nh;
+    int rk[KM];     // light rank, or ~heavy rank
+    double dc[KM];  // light start D, or heavy end C
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        const int i = tid + BT * k;
+        const double v = w[k];
+        rk[k] = 0;
+        dc[k] = 0.0;
+        if (i < n) {
+            if (v < 1.0) {
+                lightD(nl) = dl;
+                rk[k] = nl;
+                dc[k] = dl;
+                dl += 1.0 - v;
+                ++nl;
+            } else {
+                uh += v - 1.0;
+                heavyC(nh) = uh;
+                heavyIdx[nh] = i;
+                rk[k] = ~nh;
+                dc[k] = uh;
+                ++nh;
+            }
         }
     }
     if (tid == 0) lightD(NLtot) = Dtot;  // index NLtot = n - NHtot: below every heavy slot
     __syncthreads();
     // 4. thresholds and aliases
-    for (int i = tid; i < n; i += BT) {
-        const int r = rankv[i];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        const int i = tid + BT * k;
+        if (i >= n) continue;
+        const int r = rk[k];
         double q;
         int al;
         if (NHtot == 0) {
@@ -281,14 +321,14 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
             al = i;
         } else if (r >= 0) {
             // light: first heavy m with heavyC(m) > D_i
-            const double D = lightD(r);
+            const double D = dc[k];
             int lo = 0, hi = NHtot;
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
                 if (heavyC(mid) > D) hi = mid; else lo = mid + 1;
             }
             if (lo >= NHtot) lo = NHtot - 1;
-            q = s[i];
+            q = w[k];
             al = heavyIdx[lo];
         } else {
             const int m = ~r;
@@ -296,7 +336,7 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
                 q = 1.0;
                 al = i;
             } else {
-                const double C = heavyC(m);
+                const double C = dc[k];
                 int lo = 0, hi = NLtot;  // first light start >= C (lightD(NLtot) = Dtot)
                 while (lo < hi) {
                     const int mid = (lo + hi) >> 1;
@@ -337,11 +377,12 @@ hipError_t launch_alias_build(const mcnegf_kernel& k, hipStream_t s) {
     a.W = k.W;
     a.open_cut = 1e3 * k.delta_lead * k.t * k.W;
     const int n = k.n_out;
-    const size_t lds = (size_t)n * 8 + (size_t)(n + 1) * 8 + (size_t)n * 4 + (size_t)n * 4;
-    // long rows: 1024 threads per row keep 16 wavefronts per CU although one row's LDS
-    // allows few workgroups per CU
-    const bool wide = n > 1536;
-    const void* fn = wide ? (const void*)alias_build_kernel<1024> : (const void*)alias_build_kernel<256>;
+    const size_t lds = (size_t)(n + 1) * 8 + (size_t)n * 4;
+    // rows up to 1536 outcomes: 256 threads x 6 items; longer rows (n <= kMaxOut = 4096):
+    // 512 threads x 8 items
+    const bool wide = n > 256 * 6;
+    const void* fn = wide ? (const void*)alias_build_kernel<512, 8>
+                          : (const void*)alias_build_kernel<256, 6>;
     if (lds > 65536) {
         hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (err != hipSuccess) return err;
@@ -349,9 +390,9 @@ hipError_t launch_alias_build(const mcnegf_kernel& k, hipStream_t s) {
     {
         MCNEGF_TIMED("alias_build_kernel", s);
         if (wide)
-            hipLaunchKernelGGL(alias_build_kernel<1024>, dim3(n, k.nE), dim3(1024), lds, s, a);
+            hipLaunchKernelGGL((alias_build_kernel<512, 8>), dim3(n, k.nE), dim3(512), lds, s, a);
         else
-            hipLaunchKernelGGL(alias_build_kernel<256>, dim3(n, k.nE), dim3(256), lds, s, a);
+            hipLaunchKernelGGL((alias_build_kernel<256, 6>), dim3(n, k.nE), dim3(256), lds, s, a);
     }
     return hipGetLastError();
 }
