@@ -378,21 +378,24 @@ hipError_t launch_alias_build(const mcnegf_kernel& k, hipStream_t s) {
     a.open_cut = 1e3 * k.delta_lead * k.t * k.W;
     const int n = k.n_out;
     const size_t lds = (size_t)(n + 1) * 8 + (size_t)n * 4;
-    // rows up to 1536 outcomes: 256 threads x 6 items; longer rows (n <= kMaxOut = 4096):
-    // 512 threads x 8 items
-    const bool wide = n > 256 * 6;
-    const void* fn = wide ? (const void*)alias_build_kernel<512, 8>
-                          : (const void*)alias_build_kernel<256, 6>;
+    // rows up to 1024 outcomes: 256 threads x 4 items; up to 1536: 256 x 6; longer rows
+    // (n <= kMaxOut = 4096): 512 x 8
+    const int shape = n <= 256 * 4 ? 0 : (n <= 256 * 6 ? 1 : 2);
+    const void* fn = shape == 0   ? (const void*)alias_build_kernel<256, 4>
+                     : shape == 1 ? (const void*)alias_build_kernel<256, 6>
+                                  : (const void*)alias_build_kernel<512, 8>;
     if (lds > 65536) {
         hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (err != hipSuccess) return err;
     }
     {
         MCNEGF_TIMED("alias_build_kernel", s);
-        if (wide)
-            hipLaunchKernelGGL((alias_build_kernel<512, 8>), dim3(n, k.nE), dim3(512), lds, s, a);
-        else
+        if (shape == 0)
+            hipLaunchKernelGGL((alias_build_kernel<256, 4>), dim3(n, k.nE), dim3(256), lds, s, a);
+        else if (shape == 1)
             hipLaunchKernelGGL((alias_build_kernel<256, 6>), dim3(n, k.nE), dim3(256), lds, s, a);
+        else
+            hipLaunchKernelGGL((alias_build_kernel<512, 8>), dim3(n, k.nE), dim3(512), lds, s, a);
     }
     return hipGetLastError();
 }
