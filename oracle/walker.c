@@ -187,6 +187,101 @@ int oracle_walk_alias(const uint32_t *thr, const int32_t *alias, int64_t pitch, 
                      walker_begin, n_walkers, max_steps, tallies);
 }
 
+/*
+ * Energy-sampled walks (Sec. II F step 2 with h(E_k) = w_k / W, W = sum_k w_k): walker w draws
+ * its energy from words 0-1 of Philox(counter = (0, w, 0xFFFFFFFF, tag)) as the 53-bit
+ * uniform u; with the cumulative weights c_0 = 0, c_{k+1} = c_k + w_k (index order), the
+ * energy is the first k with c_{k+1} > u c_nE.  The walk itself is then the ordinary walk of
+ * walker w at energy k (same counters as above), with either sampler; tallies go to the
+ * drawn energy.  Negative or non-finite weights are rejected.
+ */
+static int32_t draw_energy(const double *cum, int32_t nE, uint64_t seed, uint32_t w, uint32_t tag)
+{
+    const uint32_t ctr[4] = {0u, w, 0xFFFFFFFFu, tag};
+    const uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    oracle_philox4x32_10(ctr, key, x);
+    const uint64_t bits = (((uint64_t)x[0] << 32) | x[1]) >> 11;
+    const double target = (double)bits * 0x1.0p-53 * cum[nE];
+    for (int32_t k = 0; k < nE; ++k)
+        if (cum[k + 1] > target) return k;
+    return nE - 1;
+}
+
+static int walk_sampled_impl(int mode, const double *K, const uint32_t *thr, const int32_t *alias,
+                             int64_t pitch, int32_t nE, int32_t n, const double *weights,
+                             uint64_t seed, uint32_t realization, uint32_t inject_lead,
+                             uint64_t walker_begin, uint64_t n_walkers, uint32_t max_steps,
+                             int64_t *tallies)
+{
+    if (n < 3 || nE < 1 || inject_lead > 1 || realization >= (1u << 30)) return -1;
+    if (walker_begin + n_walkers > 0x100000000ull) return -1;
+    double *cum = (double *)malloc(sizeof(double) * (size_t)(nE + 1));
+    if (!cum) return -1;
+    cum[0] = 0.0;
+    for (int32_t k = 0; k < nE; ++k) {
+        if (!(weights[k] >= 0.0) || weights[k] > 1e308) { free(cum); return -1; }
+        cum[k + 1] = cum[k] + weights[k];
+    }
+    if (!(cum[nE] > 0.0)) { free(cum); return -1; }
+    const int32_t N = n - 2;
+    const uint32_t tag = (realization << 1) | inject_lead;
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int64_t i = 0; i < (int64_t)n_walkers; ++i) {
+        uint32_t w = (uint32_t)(walker_begin + (uint64_t)i);
+        const int32_t k = draw_energy(cum, nE, seed, w, tag);
+        stream_t st;
+        stream_init(&st, seed, w, (uint32_t)k, tag);
+        int32_t s = N + (int32_t)inject_lead;
+        uint32_t steps = 0;
+        int outcome = -1;
+        while (steps < max_steps) {
+            uint32_t a, b;
+            stream_pair(&st, steps, &a, &b);
+            int32_t next;
+            if (mode == 0) {
+                next = draw_cdf(K + ((int64_t)k * n + s) * (int64_t)n, n, a, b);
+            } else {
+                uint32_t c = lemire_bucket(&st, steps, a, (uint32_t)n);
+                int64_t e = ((int64_t)k * n + s) * pitch + c;
+                next = (b < thr[e]) ? (int32_t)c : alias[e];
+            }
+            ++steps;
+            if (next >= N) { outcome = next - N; break; }
+            s = next;
+        }
+        int64_t *t = tallies + 5 * (int64_t)k;
+        const int slot = outcome == 0 ? 0 : (outcome == 1 ? 1 : 2);
+#pragma omp atomic
+        t[slot] += 1;
+#pragma omp atomic
+        t[3] += steps;
+#pragma omp atomic
+        t[4] += (int64_t)steps * (int64_t)steps;
+    }
+    free(cum);
+    return 0;
+}
+
+int oracle_walk_sampled_cdf(const double *K, int32_t nE, int32_t n, const double *weights,
+                            uint64_t seed, uint32_t realization, uint32_t inject_lead,
+                            uint64_t walker_begin, uint64_t n_walkers, uint32_t max_steps,
+                            int64_t *tallies)
+{
+    return walk_sampled_impl(0, K, NULL, NULL, 0, nE, n, weights, seed, realization,
+                             inject_lead, walker_begin, n_walkers, max_steps, tallies);
+}
+
+int oracle_walk_sampled_alias(const uint32_t *thr, const int32_t *alias, int64_t pitch,
+                              int32_t nE, int32_t n, const double *weights, uint64_t seed,
+                              uint32_t realization, uint32_t inject_lead, uint64_t walker_begin,
+                              uint64_t n_walkers, uint32_t max_steps, int64_t *tallies)
+{
+    if (pitch < n) return -1;
+    return walk_sampled_impl(1, NULL, thr, alias, pitch, nE, n, weights, seed, realization,
+                             inject_lead, walker_begin, n_walkers, max_steps, tallies);
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP

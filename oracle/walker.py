@@ -45,6 +45,17 @@ def lib():
                                         ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
                                         ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p]
         L.oracle_walk_alias.restype = ctypes.c_int
+        L.oracle_walk_sampled_cdf.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                                              ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
+                                              ctypes.c_uint32, ctypes.c_void_p]
+        L.oracle_walk_sampled_cdf.restype = ctypes.c_int
+        L.oracle_walk_sampled_alias.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                                ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                                ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                                ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+                                                ctypes.c_void_p]
+        L.oracle_walk_sampled_alias.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -91,6 +102,58 @@ def walk_alias(thr, alias, seed, realization, inject_lead, walker_begin, n_walke
     if rc != 0:
         raise ValueError("oracle_walk_alias rejected its arguments")
     return tallies
+
+
+def walk_sampled_cdf(K, weights, seed, realization, inject_lead, walker_begin, n_walkers,
+                     max_steps=1_000_000, tallies=None):
+    """Energy-sampled walks: walker w draws its energy with probability weights[k] / sum,
+    then walks on the dense rows K[k] with the paper's sampler; tallies[k] collects the
+    walkers that drew energy k."""
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    wts = np.ascontiguousarray(weights, dtype=np.float64)
+    nE, n, _ = K.shape
+    if tallies is None:
+        tallies = np.zeros((nE, 5), dtype=np.int64)
+    rc = lib().oracle_walk_sampled_cdf(K.ctypes.data, nE, n, wts.ctypes.data, seed, realization,
+                                       inject_lead, walker_begin, n_walkers, max_steps,
+                                       tallies.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_walk_sampled_cdf rejected its arguments")
+    return tallies
+
+
+def walk_sampled_alias(thr, alias, weights, seed, realization, inject_lead, walker_begin,
+                       n_walkers, max_steps=1_000_000, tallies=None):
+    """Energy-sampled walks on given alias tables thr/alias[nE][n][pitch]."""
+    thr = np.ascontiguousarray(thr, dtype=np.uint32)
+    alias = np.ascontiguousarray(alias, dtype=np.int32)
+    wts = np.ascontiguousarray(weights, dtype=np.float64)
+    nE, n, pitch = thr.shape
+    if tallies is None:
+        tallies = np.zeros((nE, 5), dtype=np.int64)
+    rc = lib().oracle_walk_sampled_alias(thr.ctypes.data, alias.ctypes.data, pitch, nE, n,
+                                         wts.ctypes.data, seed, realization, inject_lead,
+                                         walker_begin, n_walkers, max_steps, tallies.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_walk_sampled_alias rejected its arguments")
+    return tallies
+
+
+def sampled_current(tallies, c, weights, inject_lead=0):
+    """(I, sigma_I) of energy-sampled walks: the variable X = W c_p(E_k) when the walker exits
+    at the collecting lead, 0 otherwise (Eq. (66) with the energy density h proportional to
+    the weights, W = sum of the weights), averaged over all N walkers; sigma_I from the sample
+    variance of X."""
+    t = np.asarray(tallies, dtype=np.int64)
+    c = np.asarray(c, dtype=np.float64)
+    W = float(np.sum(weights))
+    hits = t[:, 1] if inject_lead == 0 else t[:, 0]
+    N = float(t[:, :3].sum())
+    X = W * c  # the value of X for an exit at q at each energy
+    mean = float(np.dot(X, hits)) / N
+    mean_sq = float(np.dot(X * X, hits)) / N
+    var = (mean_sq - mean * mean) * N / (N - 1.0) if N > 1 else 0.0
+    return mean, float(np.sqrt(max(var, 0.0) / N))
 
 
 def num_threads() -> int:
