@@ -205,10 +205,15 @@ int32_t mc_negf_walk(const mcnegf_kernel* k, uint64_t seed, uint32_t realization
  *     sigma_k = c_p sqrt(p_k (1 - p_k) / (walkers - 1)),  c_p = row total of injection row p.
  *   mode 1 (DIRECT): solve (diag(gamma_j A_jj) - T_PP) f = T_Pp by Cholesky on the GPU and
  *     T_k = T_qp + sum_j T_qj f_j; sigma_k = 0.  d_tallies is ignored (may be null).
+ *   mode 2 (energy-sampled MC, tallies of mc_negf_walk_sampled with the same weights): the
+ *     constant estimator X = W c_p(E_k) [exit at q] over all N walkers, W = sum_k w_k:
+ *     I = (W / N) sum_k c_p,k R_k (R_k exits at q at energy k), sigma_I^2 = (W^2 S2 / N - I^2)
+ *     / (N - 1) with S2 = sum_k c_p,k^2 R_k; T_k and sigma_k per energy as in mode 0.
  *   d_weights [nE] device quadrature weights w_k; d_T, d_sigmaT [nE] device outputs.
- *   h_I_sigma [2] host output: I = sum_k w_k T_k and sqrt(sum_k w_k^2 sigma_k^2).
+ *   h_I_sigma [2] host output: I = sum_k w_k T_k and sqrt(sum_k w_k^2 sigma_k^2) (modes 0, 1),
+ *     or the mode-2 I and sigma_I.
  * Synchronises `stream`, then reads the device status word: returns MCNEGF_ENUMERIC if a
- * NONFINITE, SINGULAR or NOTSPD bit is set, MCNEGF_WTRUNC if TRUNC is set (MC mode),
+ * NONFINITE, SINGULAR or NOTSPD bit is set, MCNEGF_WTRUNC if TRUNC is set (MC modes),
  * MCNEGF_WNUMERIC if ROWSUM is set, else MCNEGF_OK.
  */
 int32_t mc_negf_current(const mcnegf_kernel* k, int32_t mode, uint32_t inject_lead,
@@ -239,6 +244,27 @@ int32_t mc_negf_grad_workspace_bytes(const mcnegf_kernel* k, uint64_t* bytes_out
 int32_t mc_negf_grad(const mcnegf_kernel* k, uint32_t inject_lead, const double* d_weights,
                      void* d_gws, uint64_t gws_bytes, double* d_dI_dV, double* d_dI_dgamma,
                      double* h_I, hipStream_t stream);
+
+/*
+ * Energy-sampled walks (Sec. II F step 2: the starting energy drawn from a density h; with
+ * h proportional to the quadrature weights the estimator of Eq. (66) becomes the constant
+ * W c_p(E_0) [exit at q], W = sum_k w_k — the paper's choice h = Th(E) when w_k = Th(E_k) dE).
+ * Walker w of [walker_begin, walker_begin + n_walkers) draws its energy index k with
+ * probability d_weights[k] / W from Philox4x32-10 counter (0, w, 0xFFFFFFFF, tag) (words 0-1
+ * as a 53-bit uniform u; k = the first index with cdf_{k+1} > u cdf_nE, cdf the running sum
+ * of the weights in index order) and then walks exactly as in mc_negf_walk at energy k; its
+ * counts go to d_tallies[k] (accumulated).  The walkers are sorted by energy on the device
+ * and walked in one launch; everything is asynchronous (capturable).  Estimate the current
+ * with mc_negf_current mode 2.  Needs nE <= 16384 and a kernel with alias tables; d_scratch
+ * (caller-owned, 256-byte aligned) of >= mc_negf_walk_sampled_bytes(k, n_walkers) bytes.
+ * A negative or non-finite weight counts as 0 and sets MCNEGF_FLAG_NONFINITE.
+ */
+int32_t mc_negf_walk_sampled_bytes(const mcnegf_kernel* k, uint64_t n_walkers,
+                                   uint64_t* bytes_out);
+int32_t mc_negf_walk_sampled(const mcnegf_kernel* k, uint64_t seed, uint32_t realization,
+                             uint32_t inject_lead, uint64_t walker_begin, uint64_t n_walkers,
+                             uint32_t max_steps, const double* d_weights, int64_t* d_tallies,
+                             void* d_scratch, uint64_t scratch_bytes, hipStream_t stream);
 
 /*
  * Like mc_negf_current, but asynchronous and capturable in a HIP graph: I and the standard

@@ -103,6 +103,31 @@ hipError_t launch_walk_batch(const mcnegf_batch& b, uint64_t seed, uint32_t walk
 hipError_t launch_current_out(const mcnegf_kernel& k, double* d_I_sigma, hipStream_t s);
 size_t walk_unit_bytes();
 void fill_walk_unit(void* dst, const mcnegf_kernel& k, int e, uint32_t tag, int64_t* tally);
+void fill_walk_unit_ids(void* dst, const mcnegf_kernel& k, int e, uint32_t tag, int64_t* tally,
+                        const uint32_t* ids, uint32_t nw);
+hipError_t launch_walk_units(const void* d_units, uint32_t n_units, const uint32_t* d_chunk_start,
+                             uint32_t total_chunks, uint32_t chunk, uint64_t seed,
+                             uint32_t max_steps, hipStream_t s);
+// scratch of an energy-sampled walk (caller-owned device memory)
+struct SampledScratch {
+    double* cdf;            // [nE + 1]
+    uint32_t* blockhist;    // [nE][blocks]
+    uint32_t* blockoff;     // [nE][blocks]
+    uint32_t* counts;       // [nE]
+    uint32_t* base;         // [nE + 1]
+    uint32_t* chunk_start;  // [nE + 1]
+    void* units;            // [nE] walk unit descriptors
+    uint32_t* draws;        // [n] energy of each walker
+    uint32_t* ids;          // [n] walker indices sorted by energy
+};
+uint64_t sampled_scratch_layout(int nE, uint64_t n, SampledScratch* out, void* base);
+hipError_t launch_walk_sampled(const mcnegf_kernel& k, const SampledScratch& sc, uint64_t seed,
+                               uint32_t tag, uint32_t walker_begin, uint32_t n_walkers,
+                               uint32_t max_steps, const double* weights, int64_t* tallies,
+                               hipStream_t s);
+hipError_t launch_sampled_current(const mcnegf_kernel& k, uint32_t inject_lead,
+                                  const int64_t* tallies, const double* weights, double* T,
+                                  double* sigmaT, hipStream_t s);
 hipError_t launch_grad(const mcnegf_kernel& k, const GradBuffers& gb, uint32_t inject_lead,
                        const double* weights, double* dI_dV, double* dI_dgamma, hipStream_t s);
 

@@ -88,6 +88,62 @@ hipError_t launch_mc_current(const mcnegf_kernel& k, uint32_t inject_lead, const
     return hipGetLastError();
 }
 
+// Energies drawn with probability w_k / W (W = sum_k w_k, Sec. II F step 2 with h = w / W)
+// and the estimator of the linear-response transmission with h proportional to the weight
+// (Sec. II G, Eq. (66) read with f -> w): X = W c_p(E_k) for an exit at q, else 0, so that
+// E[X] = sum_k w_k T_k.  Over the N walkers of the tallies: I = W S1 / N with
+// S1 = sum_k c_k R_k (R_k exits at q), and sigma_I^2 = (W^2 S2 / N - I^2) / (N - 1) with
+// S2 = sum_k c_k^2 R_k (the sample variance of X over N).  T_k and sigma_k are the per-energy
+// ratios as in MC mode.  out[0] = I, out[1] = sigma_I^2.
+__global__ void __launch_bounds__(256) sampled_current_kernel(const int64_t* __restrict__ tallies,
+                                                              const double* __restrict__ lead,
+                                                              const double* __restrict__ w,
+                                                              int nE, uint32_t inject_lead,
+                                                              double* __restrict__ T,
+                                                              double* __restrict__ sig,
+                                                              double* __restrict__ out) {
+    __shared__ double red[256];
+    double sw = 0.0, s1 = 0.0, s2 = 0.0, nw = 0.0;
+    for (int k = threadIdx.x; k < nE; k += 256) {
+        const int64_t* t = tallies + (size_t)k * MCNEGF_TALLY_N;
+        const double walkers =
+            (double)(t[MCNEGF_TALLY_EXIT_L] + t[MCNEGF_TALLY_EXIT_R] + t[MCNEGF_TALLY_TRUNC]);
+        const double hits =
+            (double)(inject_lead == 0 ? t[MCNEGF_TALLY_EXIT_R] : t[MCNEGF_TALLY_EXIT_L]);
+        const double c = lead[(size_t)k * MCNEGF_LEAD_NTERMS +
+                              (inject_lead == 0 ? MCNEGF_LEAD_CL : MCNEGF_LEAD_CR)];
+        sw += w[k];
+        s1 += c * hits;
+        s2 += c * c * hits;
+        nw += walkers;
+        const double p = walkers > 0.0 ? hits / walkers : 0.0;
+        T[k] = c * p;
+        sig[k] = walkers > 1.0 ? c * sqrt(p * (1.0 - p) / (walkers - 1.0)) : 0.0;
+    }
+    sw = block_reduce256(sw, red);
+    s1 = block_reduce256(s1, red);
+    s2 = block_reduce256(s2, red);
+    nw = block_reduce256(nw, red);
+    if (threadIdx.x == 0) {
+        const double I = nw > 0.0 ? sw * s1 / nw : 0.0;
+        const double m2 = nw > 0.0 ? sw * sw * s2 / nw : 0.0;
+        const double var = nw > 1.0 ? (m2 - I * I) / (nw - 1.0) : 0.0;
+        out[0] = I;
+        out[1] = var > 0.0 ? var : 0.0;
+    }
+}
+
+hipError_t launch_sampled_current(const mcnegf_kernel& k, uint32_t inject_lead,
+                                  const int64_t* tallies, const double* weights, double* T,
+                                  double* sigmaT, hipStream_t s) {
+    {
+        MCNEGF_TIMED("sampled_current_kernel", s);
+        hipLaunchKernelGGL(sampled_current_kernel, dim3(1), dim3(256), 0, s, tallies, k.lead,
+                           weights, k.nE, inject_lead, T, sigmaT, k.reduce);
+    }
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- DIRECT
 // vec layout per energy: [0] u_j = gamma_j s_j, [1] u_j w_p(j), [2] u_j w_q(j), [3] s_j,
 // with s_j = M_jj^{-1/2} (0 for a decoupled probe) and w_p, w_q the exit weights of the

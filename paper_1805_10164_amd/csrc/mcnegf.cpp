@@ -240,9 +240,12 @@ int32_t mc_negf_current(const mcnegf_kernel* k, int32_t mode, uint32_t inject_le
     if (!valid_kernel(k) || !d_weights || !d_T || !d_sigmaT || !h_I_sigma || inject_lead > 1)
         return MCNEGF_EINVAL;
     hipError_t err;
-    if (mode == 0) {
+    if (mode == 0 || mode == 2) {
         if (!d_tallies || !k->alias) return MCNEGF_EINVAL;  // tallies need a walked kernel
-        err = launch_mc_current(*k, inject_lead, d_tallies, d_weights, d_T, d_sigmaT, stream);
+        err = mode == 0 ? launch_mc_current(*k, inject_lead, d_tallies, d_weights, d_T, d_sigmaT,
+                                            stream)
+                        : launch_sampled_current(*k, inject_lead, d_tallies, d_weights, d_T,
+                                                 d_sigmaT, stream);
     } else if (mode == 1) {
         if (!k->direct || !k->direct_vec) return MCNEGF_EINVAL;
         err = launch_direct_current(*k, inject_lead, d_weights, d_T, d_sigmaT, stream);
@@ -261,7 +264,7 @@ int32_t mc_negf_current(const mcnegf_kernel* k, int32_t mode, uint32_t inject_le
     if ((err = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(err);
     h_I_sigma[0] = host[0];
     h_I_sigma[1] = std::sqrt(host[1] > 0.0 ? host[1] : 0.0);
-    return status_to_code(flags, mode == 0);
+    return status_to_code(flags, mode != 1);
 }
 
 int32_t mc_negf_grad_workspace_bytes(const mcnegf_kernel* k, uint64_t* bytes_out) {
@@ -349,9 +352,12 @@ int32_t mc_negf_current_async(const mcnegf_kernel* k, int32_t mode, uint32_t inj
     if (!valid_kernel(k) || !d_weights || !d_T || !d_sigmaT || !d_I_sigma || inject_lead > 1)
         return MCNEGF_EINVAL;
     hipError_t err;
-    if (mode == 0) {
+    if (mode == 0 || mode == 2) {
         if (!d_tallies || !k->alias) return MCNEGF_EINVAL;
-        err = launch_mc_current(*k, inject_lead, d_tallies, d_weights, d_T, d_sigmaT, stream);
+        err = mode == 0 ? launch_mc_current(*k, inject_lead, d_tallies, d_weights, d_T, d_sigmaT,
+                                            stream)
+                        : launch_sampled_current(*k, inject_lead, d_tallies, d_weights, d_T,
+                                                 d_sigmaT, stream);
     } else if (mode == 1) {
         if (!k->direct || !k->direct_vec) return MCNEGF_EINVAL;
         err = launch_direct_current(*k, inject_lead, d_weights, d_T, d_sigmaT, stream);
@@ -361,6 +367,39 @@ int32_t mc_negf_current_async(const mcnegf_kernel* k, int32_t mode, uint32_t inj
     if (err != hipSuccess) return hip_fail(err);
     if ((err = launch_current_out(*k, d_I_sigma, stream)) != hipSuccess) return hip_fail(err);
     return MCNEGF_OK;
+}
+
+constexpr int kMaxSampledEnergies = 16384;  // one u32 counter per energy in LDS
+
+int32_t mc_negf_walk_sampled_bytes(const mcnegf_kernel* k, uint64_t n_walkers,
+                                   uint64_t* bytes_out) {
+    if (!valid_kernel(k) || !bytes_out || k->nE > kMaxSampledEnergies ||
+        n_walkers > 0xffffffffull)
+        return MCNEGF_EINVAL;
+    *bytes_out = sampled_scratch_layout(k->nE, n_walkers, nullptr, nullptr);
+    return MCNEGF_OK;
+}
+
+int32_t mc_negf_walk_sampled(const mcnegf_kernel* k, uint64_t seed, uint32_t realization,
+                             uint32_t inject_lead, uint64_t walker_begin, uint64_t n_walkers,
+                             uint32_t max_steps, const double* d_weights, int64_t* d_tallies,
+                             void* d_scratch, uint64_t scratch_bytes, hipStream_t stream) {
+    if (!valid_kernel(k) || !k->alias || !k->alias_lo || !d_weights || !d_tallies ||
+        !d_scratch || inject_lead > 1 || realization >= (1u << 30) || max_steps < 1 ||
+        k->nE > kMaxSampledEnergies)
+        return MCNEGF_EINVAL;
+    if (walker_begin >= 0x100000000ull || walker_begin + n_walkers > 0x100000000ull)
+        return MCNEGF_EINVAL;
+    if (((uintptr_t)d_scratch & 255u) != 0) return MCNEGF_EWS;
+    SampledScratch sc;
+    if (sampled_scratch_layout(k->nE, n_walkers, &sc, d_scratch) > scratch_bytes)
+        return MCNEGF_EWS;
+    if (n_walkers == 0) return MCNEGF_OK;
+    const uint32_t tag = (realization << 1) | inject_lead;
+    hipError_t err = launch_walk_sampled(*k, sc, seed, tag, (uint32_t)walker_begin,
+                                         (uint32_t)n_walkers, max_steps, d_weights, d_tallies,
+                                         stream);
+    return err == hipSuccess ? MCNEGF_OK : hip_fail(err);
 }
 
 static bool batch_units(const mcnegf_kernel* kernels, int32_t n, uint64_t* units) {

@@ -74,7 +74,8 @@ struct WalkUnit {
     const uint16_t* lows;
     int64_t* tally;          // this energy's [5] tallies
     uint32_t* status;        // the kernel's status word
-    uint32_t pitch, n_out, N, e, tag, pad;
+    const uint32_t* ids;     // with per-unit counts: the unit's walker indices (else null)
+    uint32_t pitch, n_out, N, e, tag, nw;  // nw: the unit's walker count (per-unit mode)
 };
 
 struct WalkBatchArgs {
@@ -86,6 +87,10 @@ struct WalkBatchArgs {
     uint32_t groups;
     uint32_t max_steps;
     int64_t* tally_override;  // non-null: unit u's counts go to tally_override[u][5]
+    // Per-unit counts (energy-sampled walks): chunk_start[u] = first chunk of unit u
+    // ([n_units + 1], device); unit u walks U.ids[0 .. U.nw) in chunks of `chunk`.  Null:
+    // every unit walks [wbegin, wend).
+    const uint32_t* chunk_start;
 };
 
 // Every branch in the loops below that encloses a cross-lane operation is wave-uniform (its
@@ -415,12 +420,24 @@ __global__ void walk_batch_kernel(WalkBatchArgs A) {
     const uint32_t lw =
         __builtin_amdgcn_readfirstlane((blockIdx.x / G) * wpb + (threadIdx.x >> 6));
     const uint32_t nq = (A.n_units > grp) ? (A.n_units - grp + G - 1) / G : 0u;  // units of the group
-    const uint32_t total = nq * A.chunks_per_unit;
+    const bool per_unit = A.chunk_start != nullptr;  // (then G == 1)
+    const uint32_t total = per_unit ? A.chunk_start[A.n_units] : nq * A.chunks_per_unit;
     uint32_t trunc_any = 0;
     for (uint32_t cid0 = lw; cid0 < total; cid0 += waves) {  // uniform loop
         const uint32_t cid = __builtin_amdgcn_readfirstlane(cid0);
-        const uint32_t q = cid / A.chunks_per_unit;
-        const uint32_t u = __builtin_amdgcn_readfirstlane(grp + q * G);  // scalar unit loads
+        uint32_t q, u;
+        if (per_unit) {  // last unit whose first chunk is <= cid (uniform binary search)
+            uint32_t lo = 0, hi = A.n_units;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (A.chunk_start[mid] <= cid) lo = mid; else hi = mid;
+            }
+            u = __builtin_amdgcn_readfirstlane(lo);
+            q = 0;
+        } else {
+            q = cid / A.chunks_per_unit;
+            u = __builtin_amdgcn_readfirstlane(grp + q * G);
+        }
         const WalkUnit Uv = A.units[u];
         // the descriptor is the same in every lane: keep its fields in scalar registers
         WalkUnit U;
@@ -433,8 +450,17 @@ __global__ void walk_batch_kernel(WalkBatchArgs A) {
         U.N = __builtin_amdgcn_readfirstlane(Uv.N);
         U.e = __builtin_amdgcn_readfirstlane(Uv.e);
         U.tag = __builtin_amdgcn_readfirstlane(Uv.tag);
-        uint32_t next = A.wbegin + (cid - q * A.chunks_per_unit) * A.chunk;
-        const uint32_t wend = min(next + A.chunk, A.wend);
+        U.ids = (const uint32_t*)uniform_ptr(Uv.ids);
+        U.nw = __builtin_amdgcn_readfirstlane(Uv.nw);
+        // positions [next, wend) of this chunk: walker indices, or indices into U.ids
+        uint32_t next, wend;
+        if (per_unit) {
+            next = (cid - A.chunk_start[u]) * A.chunk;
+            wend = min(next + A.chunk, U.nw);
+        } else {
+            next = A.wbegin + (cid - q * A.chunks_per_unit) * A.chunk;
+            wend = min(next + A.chunk, A.wend);
+        }
         const uint32_t n_out = U.n_out, N = U.N;
         const uint32_t thresh = (0u - n_out) % n_out;
         const uint32_t inject_row = N + (U.tag & 1u);
@@ -459,7 +485,11 @@ __global__ void walk_batch_kernel(WalkBatchArgs A) {
                 for (int k = 0; k < K; ++k) {
                     const uint32_t before = base + __popcll(need[k] & lt_mask);
                     const bool take = !st[k].active && before < avail;
-                    w[k] = take ? next + before : w[k];
+                    uint32_t wid = next + before;
+                    if (U.ids) {  // uniform branch; the load is per lane
+                        if (take) wid = U.ids[wid];
+                    }
+                    w[k] = take ? wid : w[k];
                     st[k].s = take ? inject_row : st[k].s;
                     st[k].n = take ? 0u : st[k].n;
                     st[k].active = st[k].active || take;
@@ -580,8 +610,17 @@ void fill_walk_unit(void* dst, const mcnegf_kernel& k, int e, uint32_t tag, int6
     U.N = (uint32_t)k.N;
     U.e = (uint32_t)e;
     U.tag = tag;
-    U.pad = 0;
+    U.ids = nullptr;
+    U.nw = 0;
     *static_cast<WalkUnit*>(dst) = U;
+}
+
+void fill_walk_unit_ids(void* dst, const mcnegf_kernel& k, int e, uint32_t tag, int64_t* tally,
+                        const uint32_t* ids, uint32_t nw) {
+    fill_walk_unit(dst, k, e, tag, tally);
+    WalkUnit* U = static_cast<WalkUnit*>(dst);
+    U->ids = ids;
+    U->nw = nw;
 }
 
 template <int K>
@@ -606,6 +645,7 @@ hipError_t launch_walk_batch(const mcnegf_batch& b, uint64_t seed, uint32_t walk
     A.max_steps = max_steps;
     A.groups = (uint32_t)c.groups;
     A.tally_override = tally_override;
+    A.chunk_start = nullptr;
     // chunk: c.chunk walkers, or about `walks_per_slot` walks per slot of a wavefront
     uint64_t ch = c.chunk > 0 ? (uint64_t)c.chunk
                               : (uint64_t)64 * (uint64_t)c.slots * (uint64_t)c.walks_per_slot;
@@ -641,6 +681,257 @@ hipError_t launch_walk_batch(const mcnegf_batch& b, uint64_t seed, uint32_t walk
         case 4: return launch_walk_batch_k<4>(A, (uint32_t)blocks, (uint32_t)c.wg_size, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+// ---- energies drawn from the weights (importance sampling of E_0, Sec. II F step 2) ------
+//
+// Walker w (global index) draws its energy from p_k = w_k / sum_j w_j with the Philox block of
+// counter (0, w, 0xFFFFFFFF, tag) — an energy index no walk step uses — as the 53-bit uniform u
+// of words 0-1: energy = the first k with cdf_{k+1} > u cdf_nE.  The walkers are then sorted by
+// energy (counting sort: block histograms, a scan per energy, a scatter) and walked by
+// walk_batch_kernel with one unit per energy whose walker indices are its sorted list; a walker
+// keeps its global index w in the walk's counters, so the result depends only on the seed,
+// tag and walker range.  Everything runs on the device (no host round trip).
+
+// cdf[0] = 0, cdf[k + 1] = cdf[k] + w_k; a negative or non-finite weight counts as 0 and sets
+// NONFINITE, as does a zero total.
+__global__ void energy_cdf_kernel(const double* __restrict__ w, int nE, double* __restrict__ cdf,
+                                  uint32_t* __restrict__ status) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double c = 0.0;
+    bool bad = false;
+    cdf[0] = 0.0;
+    for (int k = 0; k < nE; ++k) {
+        double v = w[k];
+        if (!(v >= 0.0) || !isfinite(v)) {
+            bad = true;
+            v = 0.0;
+        }
+        c += v;
+        cdf[k + 1] = c;
+    }
+    if (bad || !(c > 0.0)) atomicOr(status, MCNEGF_FLAG_NONFINITE);
+}
+
+// Block b draws the energies of walkers [b per, (b + 1) per) and writes its histogram
+// blockhist[k][b].
+__global__ void __launch_bounds__(256) energy_draw_kernel(const double* __restrict__ cdf, int nE,
+                                                          uint32_t key0, uint32_t key1,
+                                                          uint32_t tag, uint32_t wbegin,
+                                                          uint32_t n, uint32_t per, int nblk,
+                                                          uint32_t* __restrict__ blockhist,
+                                                          uint32_t* __restrict__ draws) {
+    extern __shared__ uint32_t hist[];
+    const int b = blockIdx.x;
+    for (int k = threadIdx.x; k < nE; k += 256) hist[k] = 0u;
+    __syncthreads();
+    const double total = cdf[nE];
+    const uint32_t i0 = (uint32_t)min((uint64_t)b * per, (uint64_t)n);
+    const uint32_t i1 = (uint32_t)min((uint64_t)i0 + per, (uint64_t)n);
+    for (uint32_t i = i0 + threadIdx.x; i < i1; i += 256) {
+        const Philox4 x = philox4x32_10(0u, wbegin + i, 0xFFFFFFFFu, tag, key0, key1);
+        const uint64_t bits = (((uint64_t)x.x[0] << 32) | x.x[1]) >> 11;
+        const double target = (double)bits * 0x1.0p-53 * total;
+        int lo = 0, hi = nE - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (cdf[mid + 1] > target) hi = mid; else lo = mid + 1;
+        }
+        draws[i] = (uint32_t)lo;
+        atomicAdd(&hist[lo], 1u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nE; k += 256) blockhist[(size_t)k * nblk + b] = hist[k];
+}
+
+// Per energy k (one thread): blockoff[k][b] = sum_{b' < b} blockhist[k][b'], counts[k].
+__global__ void energy_scan_kernel(const uint32_t* __restrict__ blockhist, int nE, int nblk,
+                                   uint32_t* __restrict__ blockoff, uint32_t* __restrict__ counts) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nE) return;
+    uint32_t c = 0;
+    for (int b = 0; b < nblk; ++b) {
+        blockoff[(size_t)k * nblk + b] = c;
+        c += blockhist[(size_t)k * nblk + b];
+    }
+    counts[k] = c;
+}
+
+// One thread: base[k] (first position of energy k in the sorted list), chunk_start[k] and the
+// unit descriptors of every energy.
+__global__ void energy_units_kernel(const uint32_t* __restrict__ counts, int nE, uint32_t chunk,
+                                    uint32_t* __restrict__ base, uint32_t* __restrict__ chunk_start,
+                                    WalkUnit* __restrict__ units, const uint32_t* alias,
+                                    const uint16_t* alias_lo, int64_t pitch, uint32_t n_out,
+                                    uint32_t N, uint32_t tag, int64_t* tallies, uint32_t* status,
+                                    const uint32_t* ids) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    uint32_t pos = 0, ch = 0;
+    const size_t stride = (size_t)n_out * (size_t)pitch;
+    for (int k = 0; k < nE; ++k) {
+        base[k] = pos;
+        chunk_start[k] = ch;
+        WalkUnit U;
+        U.tables = alias + (size_t)k * stride;
+        U.lows = alias_lo + (size_t)k * stride;
+        U.tally = tallies + (size_t)k * MCNEGF_TALLY_N;
+        U.status = status;
+        U.ids = ids + pos;
+        U.pitch = (uint32_t)pitch;
+        U.n_out = n_out;
+        U.N = N;
+        U.e = (uint32_t)k;
+        U.tag = tag;
+        U.nw = counts[k];
+        units[k] = U;
+        pos += counts[k];
+        ch += (counts[k] + chunk - 1) / chunk;
+    }
+    base[nE] = pos;
+    chunk_start[nE] = ch;
+}
+
+// Block b writes the indices of its walkers into their energies' lists.
+__global__ void __launch_bounds__(256) energy_scatter_kernel(const uint32_t* __restrict__ draws,
+                                                             int nE, uint32_t wbegin, uint32_t n,
+                                                             uint32_t per, int nblk,
+                                                             const uint32_t* __restrict__ base,
+                                                             const uint32_t* __restrict__ blockoff,
+                                                             uint32_t* __restrict__ ids) {
+    extern __shared__ uint32_t cur[];
+    const int b = blockIdx.x;
+    for (int k = threadIdx.x; k < nE; k += 256) cur[k] = base[k] + blockoff[(size_t)k * nblk + b];
+    __syncthreads();
+    const uint32_t i0 = (uint32_t)min((uint64_t)b * per, (uint64_t)n);
+    const uint32_t i1 = (uint32_t)min((uint64_t)i0 + per, (uint64_t)n);
+    for (uint32_t i = i0 + threadIdx.x; i < i1; i += 256) {
+        const uint32_t k = draws[i];
+        ids[atomicAdd(&cur[k], 1u)] = wbegin + i;
+    }
+}
+
+constexpr int kSampledBlocks = 1024;  // draw / scatter blocks (per-block histograms)
+constexpr uint32_t kSampledChunk = 64u * 3u * 8u;
+
+uint64_t sampled_scratch_layout(int nE, uint64_t n, SampledScratch* out, void* base) {
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t at = off;
+        off = (off + bytes + 255) & ~uint64_t(255);
+        return at;
+    };
+    const uint64_t oc = take((uint64_t)(nE + 1) * 8);
+    const uint64_t oh = take((uint64_t)nE * kSampledBlocks * 4);
+    const uint64_t oo = take((uint64_t)nE * kSampledBlocks * 4);
+    const uint64_t on = take((uint64_t)nE * 4);
+    const uint64_t ob = take((uint64_t)(nE + 1) * 4);
+    const uint64_t os = take((uint64_t)(nE + 1) * 4);
+    const uint64_t ou = take((uint64_t)nE * sizeof(WalkUnit));
+    const uint64_t od = take(n * 4);
+    const uint64_t oi = take(n * 4);
+    if (out) {
+        char* p = static_cast<char*>(base);
+        out->cdf = reinterpret_cast<double*>(p + oc);
+        out->blockhist = reinterpret_cast<uint32_t*>(p + oh);
+        out->blockoff = reinterpret_cast<uint32_t*>(p + oo);
+        out->counts = reinterpret_cast<uint32_t*>(p + on);
+        out->base = reinterpret_cast<uint32_t*>(p + ob);
+        out->chunk_start = reinterpret_cast<uint32_t*>(p + os);
+        out->units = p + ou;
+        out->draws = reinterpret_cast<uint32_t*>(p + od);
+        out->ids = reinterpret_cast<uint32_t*>(p + oi);
+    }
+    return off;
+}
+
+hipError_t launch_walk_sampled(const mcnegf_kernel& k, const SampledScratch& sc, uint64_t seed,
+                               uint32_t tag, uint32_t walker_begin, uint32_t n_walkers,
+                               uint32_t max_steps, const double* weights, int64_t* tallies,
+                               hipStream_t s);
+
+// Per-unit counts: unit u walks the walker indices ids[0 .. nw_u) of its descriptor; the
+// chunk prefix (device, [n_units + 1]) was written by the caller.  One XCD group.
+hipError_t launch_walk_units(const void* d_units, uint32_t n_units, const uint32_t* d_chunk_start,
+                             uint32_t total_chunks, uint32_t chunk, uint64_t seed,
+                             uint32_t max_steps, hipStream_t s) {
+    if (total_chunks == 0) return hipSuccess;
+    constexpr int K = 3;
+    WalkBatchArgs A;
+    A.units = static_cast<const WalkUnit*>(d_units);
+    A.n_units = n_units;
+    A.key0 = (uint32_t)(seed & 0xffffffffu);
+    A.key1 = (uint32_t)(seed >> 32);
+    A.wbegin = 0;
+    A.wend = 0;
+    A.chunk = chunk;
+    A.chunks_per_unit = 0;
+    A.groups = 1;
+    A.max_steps = max_steps;
+    A.tally_override = nullptr;
+    A.chunk_start = d_chunk_start;
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t err;
+    if ((err = hipGetDevice(&dev)) != hipSuccess) return err;
+    if ((err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
+        hipSuccess)
+        return err;
+    if ((err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
+                                                            (const void*)walk_batch_kernel<K>,
+                                                            256, 0)) != hipSuccess)
+        return err;
+    uint64_t blocks = (uint64_t)(per_cu < 1 ? 1 : per_cu) * (uint64_t)cus;
+    const uint64_t need = ((uint64_t)total_chunks + 3) / 4;
+    if (blocks > need) blocks = need;
+    return launch_walk_batch_k<K>(A, (uint32_t)blocks, 256u, s);
+}
+
+hipError_t launch_walk_sampled(const mcnegf_kernel& k, const SampledScratch& sc, uint64_t seed,
+                               uint32_t tag, uint32_t walker_begin, uint32_t n_walkers,
+                               uint32_t max_steps, const double* weights, int64_t* tallies,
+                               hipStream_t s) {
+    if (n_walkers == 0) return hipSuccess;
+    const int nE = k.nE;
+    const uint32_t key0 = (uint32_t)(seed & 0xffffffffu), key1 = (uint32_t)(seed >> 32);
+    const uint32_t per = (n_walkers + kSampledBlocks - 1) / kSampledBlocks;
+    const size_t lds = (size_t)nE * 4;
+    hipError_t err;
+    {
+        MCNEGF_TIMED("energy_cdf_kernel", s);
+        hipLaunchKernelGGL(energy_cdf_kernel, dim3(1), dim3(64), 0, s, weights, nE, sc.cdf,
+                           k.status);
+    }
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    {
+        MCNEGF_TIMED("energy_draw_kernel", s);
+        hipLaunchKernelGGL(energy_draw_kernel, dim3(kSampledBlocks), dim3(256), lds, s, sc.cdf, nE,
+                           key0, key1, tag, walker_begin, n_walkers, per, kSampledBlocks,
+                           sc.blockhist, sc.draws);
+    }
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    {
+        MCNEGF_TIMED("energy_scan_kernel", s);
+        hipLaunchKernelGGL(energy_scan_kernel, dim3((nE + 255) / 256), dim3(256), 0, s,
+                           sc.blockhist, nE, kSampledBlocks, sc.blockoff, sc.counts);
+    }
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    {
+        MCNEGF_TIMED("energy_units_kernel", s);
+        hipLaunchKernelGGL(energy_units_kernel, dim3(1), dim3(64), 0, s, sc.counts, nE,
+                           kSampledChunk, sc.base, sc.chunk_start,
+                           static_cast<WalkUnit*>(sc.units), k.alias, k.alias_lo, k.alias_pitch,
+                           (uint32_t)k.n_out, (uint32_t)k.N, tag, tallies, k.status, sc.ids);
+    }
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    {
+        MCNEGF_TIMED("energy_scatter_kernel", s);
+        hipLaunchKernelGGL(energy_scatter_kernel, dim3(kSampledBlocks), dim3(256), lds, s,
+                           sc.draws, nE, walker_begin, n_walkers, per, kSampledBlocks, sc.base,
+                           sc.blockoff, sc.ids);
+    }
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    // persistent grid; the kernel reads the number of chunks from chunk_start[nE]
+    return launch_walk_units(sc.units, (uint32_t)nE, sc.chunk_start, 0xFFFFFFFFu, kSampledChunk,
+                             seed, max_steps, s);
 }
 
 }  // namespace mcnegf

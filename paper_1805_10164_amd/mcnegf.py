@@ -26,7 +26,8 @@ TALLY_N = 5
 TALLY_EXIT_L, TALLY_EXIT_R, TALLY_TRUNC, TALLY_STEPS, TALLY_STEPS2 = range(5)
 EXPORTED = ("mc_negf_workspace_bytes", "mc_negf_build_kernel", "mc_negf_walk",
             "mc_negf_current", "mc_negf_grad_workspace_bytes", "mc_negf_grad",
-            "mc_negf_current_async", "mc_negf_batch_bytes", "mc_negf_batch_prepare",
+            "mc_negf_current_async", "mc_negf_walk_sampled_bytes", "mc_negf_walk_sampled",
+            "mc_negf_batch_bytes", "mc_negf_batch_prepare",
             "mc_negf_walk_batch", "mc_negf_walk_batch_autotune", "mc_negf_plan_waves",
             "mc_negf_graph_begin", "mc_negf_graph_end", "mc_negf_graph_launch",
             "mc_negf_graph_destroy", "mc_negf_profile_begin", "mc_negf_profile_end",
@@ -104,6 +105,10 @@ def lib() -> ctypes.CDLL:
     L.mc_negf_status.argtypes = [ctypes.POINTER(KernelStruct), ctypes.POINTER(u32), vp]
     L.mc_negf_current_async.argtypes = [ctypes.POINTER(KernelStruct), i32, u32, vp, vp, vp, vp,
                                         vp, vp]
+    L.mc_negf_walk_sampled_bytes.argtypes = [ctypes.POINTER(KernelStruct), u64,
+                                             ctypes.POINTER(u64)]
+    L.mc_negf_walk_sampled.argtypes = [ctypes.POINTER(KernelStruct), u64, u32, u32, u64, u64,
+                                       u32, vp, vp, vp, u64, vp]
     L.mc_negf_batch_bytes.argtypes = [ctypes.POINTER(KernelStruct), i32, ctypes.POINTER(u64)]
     L.mc_negf_batch_prepare.argtypes = [ctypes.POINTER(KernelStruct), i32,
                                         ctypes.POINTER(u32), u32, ctypes.POINTER(vp), vp, u64,
@@ -455,3 +460,23 @@ def mc_negf_graph_end(stream=None) -> Graph:
     h = ctypes.c_void_p(0)
     _check("mc_negf_graph_end", lib().mc_negf_graph_end(_stream(stream), ctypes.byref(h)))
     return Graph(h)
+
+
+def mc_negf_walk_sampled_bytes(k: Kernel, n_walkers: int) -> int:
+    out = ctypes.c_uint64(0)
+    _check("mc_negf_walk_sampled_bytes",
+           lib().mc_negf_walk_sampled_bytes(ctypes.byref(k.struct), int(n_walkers),
+                                            ctypes.byref(out)))
+    return int(out.value)
+
+
+def mc_negf_walk_sampled(k: Kernel, seed: int, realization: int, inject_lead: int,
+                         walker_begin: int, n_walkers: int, max_steps: int, weights, tallies,
+                         scratch, stream=None) -> int:
+    """Walkers draw their energies with probability weights[k] / sum (device draws and
+    sort), then walk; counts go to tallies[k].  Estimate with mc_negf_current mode 2."""
+    code = lib().mc_negf_walk_sampled(ctypes.byref(k.struct), int(seed), int(realization),
+                                      int(inject_lead), int(walker_begin), int(n_walkers),
+                                      int(max_steps), _ptr(weights), _ptr(tallies), _ptr(scratch),
+                                      int(scratch.numel()), _stream(stream))
+    return _check("mc_negf_walk_sampled", code)
