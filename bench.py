@@ -76,21 +76,37 @@ class Problem:
         self.w = torch.tensor(w, device=dev)
         self.ws = M.allocate_workspace(self.sys, wl.n_energies, dev)
         self.tal = torch.zeros((wl.n_energies, M.TALLY_N), dtype=torch.int64, device=dev)
+        self.sampled_scratch = None  # energy-sampled walks (time-to-1%), allocated on first use
         self.T = torch.empty(wl.n_energies, dtype=torch.float64, device=dev)
         self.sig = torch.empty_like(self.T)
+        self.Td = torch.empty_like(self.T)
+        self.sigd = torch.empty_like(self.T)
+        self.out = torch.zeros((2, 2), dtype=torch.float64, device=dev)  # (MC, DIRECT) x (I, sigma)
         self.k = None
 
 
 def run_step(p: Problem, walkers, seed, walk_on):
-    """Whole hot path for one problem; returns (status_mc, I_mc, sigma_mc, status_d, I_d)."""
+    """Whole hot path for one problem, asynchronous on the current stream: build, walks, MC
+    current and DIRECT current into p.out (read after the stream is synchronised)."""
     p.k = M.mc_negf_build_kernel(p.sys, p.V, p.g, p.E, p.ws)
-    st_mc = I_mc = s_mc = None
     if walk_on:
         p.tal.zero_()
         M.mc_negf_walk(p.k, seed, p.wl.realization, 0, 0, walkers, 1_000_000, p.tal)
-        st_mc, I_mc, s_mc = M.mc_negf_current(p.k, 0, 0, p.tal, p.w, p.T, p.sig)
-    st_d, I_d, _ = M.mc_negf_current(p.k, 1, 0, None, p.w, p.T, p.sig)
-    return st_mc, I_mc, s_mc, st_d, I_d
+        M.mc_negf_current_async(p.k, 0, 0, p.tal, p.w, p.T, p.sig, p.out[0])
+    M.mc_negf_current_async(p.k, 1, 0, None, p.w, p.Td, p.sigd, p.out[1])
+
+
+def step_results(p: Problem, walk_on):
+    """(status_mc, I_mc, sigma_mc, status_d, I_d) after the stream is synchronised."""
+    out = p.out.cpu().numpy()
+    flags = M.mc_negf_status(p.k)
+    bad = flags & (M.FLAG_NONFINITE | M.FLAG_SINGULAR | M.FLAG_NOTSPD)
+    st_d = M.ENUMERIC if bad else (M.WNUMERIC if flags & M.FLAG_ROWSUM else M.OK)
+    st_mc = None
+    if walk_on:
+        st_mc = M.ENUMERIC if bad else (M.WTRUNC if flags & M.FLAG_TRUNC else st_d)
+    return (st_mc, float(out[0, 0]) if walk_on else None, float(out[0, 1]) if walk_on else None,
+            st_d, float(out[1, 0]))
 
 
 def kernel_work(name, wl, walk_steps):
@@ -311,9 +327,16 @@ def batched_bench(torch, dev, steps, warmup, budget_gb, seed):
 def time_to_1pct(p: Problem, torch, seed, walk_on):
     """Wall time to a 1% relative deviation of I, median of 5 warm repetitions.
     MC: build + walker batches doubling from 1024 per energy until sigma_I <= 1% of I.
+    MC, energy-sampled (the paper's estimator: energies drawn from the weights, constant
+    estimator): build + batches of walkers over all energies doubling from 1024 in total.
     DIRECT: build without alias tables + probe-system solve (deterministic; its error is the
     quadrature's)."""
-    mc_t, dir_t, mc_walkers = [], [], []
+    mc_t, dir_t, mc_walkers, smp_t, smp_walkers = [], [], [], [], []
+    max_sampled = 1 << 24
+    if walk_on and p.sampled_scratch is None:
+        k0 = M.mc_negf_build_kernel(p.sys, p.V, p.g, p.E, p.ws)
+        p.sampled_scratch = torch.empty(M.mc_negf_walk_sampled_bytes(k0, max_sampled),
+                                        dtype=torch.uint8, device=p.E.device)
     for rep in range(5):
         if walk_on:
             torch.cuda.synchronize()
@@ -330,6 +353,21 @@ def time_to_1pct(p: Problem, torch, seed, walk_on):
                 batch = done
             mc_t.append(time.perf_counter() - t0)
             mc_walkers.append(done)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            k = M.mc_negf_build_kernel(p.sys, p.V, p.g, p.E, p.ws)
+            p.tal.zero_()
+            done, batch = 0, 1024
+            while True:
+                M.mc_negf_walk_sampled(k, seed + 101 + rep, 0, 0, done, batch, 1_000_000, p.w,
+                                       p.tal, p.sampled_scratch)
+                done += batch
+                st, I, s = M.mc_negf_current(k, 2, 0, p.tal, p.w, p.T, p.sig)
+                if s <= 0.01 * abs(I) or done + 2 * batch > max_sampled:
+                    break
+                batch = done
+            smp_t.append(time.perf_counter() - t0)
+            smp_walkers.append(done)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         k = M.mc_negf_build_kernel(p.sys_direct, p.V, p.g, p.E, p.ws)
@@ -338,6 +376,8 @@ def time_to_1pct(p: Problem, torch, seed, walk_on):
     return {"eta": p.wl.eta,
             "mc_ms": 1e3 * float(np.median(mc_t)) if mc_t else None,
             "mc_walkers_per_energy": int(np.median(mc_walkers)) if mc_walkers else None,
+            "mc_energy_sampled_ms": 1e3 * float(np.median(smp_t)) if smp_t else None,
+            "mc_energy_sampled_walkers": int(np.median(smp_walkers)) if smp_walkers else None,
             "direct_ms": 1e3 * float(np.median(dir_t))}
 
 
@@ -392,19 +432,16 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    steps_total = 0
-    results = []
     t0 = time.perf_counter()
     with M.LaunchTimes() as lt:
         for it in range(args.steps):
             for p in probs:
-                res = run_step(p, walkers, seed, walk_on)
-                if walk_on:
-                    steps_total += int(p.tal[:, M.TALLY_STEPS].sum())
-                if it == args.steps - 1:
-                    results.append((p, res))
+                run_step(p, walkers, seed, walk_on)
         torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # every step walks the same seeded walkers, so each step's counts are the last step's
+    results = [(p, step_results(p, walk_on)) for p in probs]
+    steps_total = args.steps * sum(int(p.tal[:, M.TALLY_STEPS].sum()) for p in probs) if walk_on else 0
 
     names = sorted(set(n for n, _ in lt.records))
     per_kernel = {n: {"launches": lt.count(n), "ms_per_launch": lt.total_ms(n) / lt.count(n),
