@@ -35,8 +35,8 @@
  *     launched.  No C++ exception crosses the ABI.
  *   - Kernels record numerical trouble in a device status word inside the workspace; it is
  *     read by mc_negf_current / mc_negf_status.
- *   - Sizes: 1 <= W <= 16, 1 <= L, N = W*L, N + 2 <= 4096 (one alias row is built in LDS),
- *     1 <= nE.
+ *   - Sizes: 1 <= W <= 32, 1 <= L, N = W*L, N + 2 <= 4096 (12-bit outcome index in the
+ *     packed alias entries), 1 <= nE; mc_negf_grad needs W <= 16.
  */
 #ifndef MCNEGF_H
 #define MCNEGF_H
@@ -91,7 +91,7 @@ extern "C" {
 
 /* Physical system (host struct, read during the call only). */
 typedef struct mcnegf_system {
-    int32_t W;            /* sites per slice, 1..16                                        */
+    int32_t W;            /* sites per slice, 1..32                                        */
     int32_t L;            /* number of slices, >= 1                                        */
     double  t;            /* hopping, > 0 (H_ij = -t)                                      */
     int32_t lead_model;   /* 0 clean semi-infinite leads, 1 wide-band leads                */
@@ -221,8 +221,9 @@ int32_t mc_negf_current(const mcnegf_kernel* k, int32_t mode, uint32_t inject_le
                         double* d_sigmaT, double* h_I_sigma, hipStream_t stream);
 
 /*
- * Bytes of device workspace mc_negf_grad needs for the built kernel `k` (host only):
- * 3 complex [nE][N][p_pitch] arrays plus O(nE N) vectors.  MCNEGF_EINVAL for a bad handle.
+ * Bytes of device workspace mc_negf_grad needs for the built kernel `k` (host only): the
+ * complex G [nE][N][p_pitch], the adjoint solves [nE][N][roundup(N + W, 16)] and O(nE N)
+ * vectors.  MCNEGF_EINVAL for a bad handle.
  */
 int32_t mc_negf_grad_workspace_bytes(const mcnegf_kernel* k, uint64_t* bytes_out);
 
@@ -238,8 +239,9 @@ int32_t mc_negf_grad_workspace_bytes(const mcnegf_kernel* k, uint64_t* bytes_out
  *   d_gws        device workspace of >= mc_negf_grad_workspace_bytes, caller-owned.
  *   d_dI_dV      [N] device output dI/dV_i;  d_dI_dgamma [N] device output dI/dgamma_i.
  *   h_I          host output, the DIRECT current I.
+ * Needs W <= 16 and a kernel built with the DIRECT workspace (else MCNEGF_EINVAL).
  * Synchronises `stream`; status as mc_negf_current in DIRECT mode.  MCNEGF_EWS if the
- * workspace is too small; MCNEGF_EHIP if a launch (or the batched complex GEMM) fails.
+ * workspace is too small; MCNEGF_EHIP if a launch fails.
  */
 int32_t mc_negf_grad(const mcnegf_kernel* k, uint32_t inject_lead, const double* d_weights,
                      void* d_gws, uint64_t gws_bytes, double* d_dI_dV, double* d_dI_dgamma,

@@ -69,19 +69,18 @@ __global__ void __launch_bounds__(256) lead_terms_kernel(const double2* __restri
     const double2* Gll = G00 + (size_t)(L - 1) * W * W;
     const double2* cRL = corner + (size_t)e * 2 * W * W;
     const double2* cLR = cRL + W * W;
-    const bool act = tid < W * W;
-    const int q = tid / W, p = tid % W;
     double tLL = 0, tRL = 0, tLR = 0, tRR = 0, aL = 0, aR = 0;
-    if (act) {
-        tLL = trace_term(G00, gm, gm, W, q, p);
-        tRL = trace_term(cRL, gm, gm, W, q, p);
-        tLR = trace_term(cLR, gm, gm, W, q, p);
-        tRR = trace_term(Gll, gm, gm, W, q, p);
+    for (int i = tid; i < W * W; i += 256) {  // thread sums of the (q, p) terms
+        const int q = i / W, p = i % W;
+        tLL += trace_term(G00, gm, gm, W, q, p);
+        tRL += trace_term(cRL, gm, gm, W, q, p);
+        tLR += trace_term(cLR, gm, gm, W, q, p);
+        tRR += trace_term(Gll, gm, gm, W, q, p);
         // Tr Gamma A over the end block: A[q][p] = i (G[q][p] - conj(G[p][q]))
         const double aqp0 = -(G00[q * W + p].y + G00[p * W + q].y);
         const double aqpl = -(Gll[q * W + p].y + Gll[p * W + q].y);
-        aL = gm[p * W + q] * aqp0;
-        aR = gm[p * W + q] * aqpl;
+        aL += gm[p * W + q] * aqp0;
+        aR += gm[p * W + q] * aqpl;
     }
     const double s0 = block_sum256(tLL, red), s1 = block_sum256(tRL, red);
     const double s2 = block_sum256(tLR, red), s3 = block_sum256(tRR, red);

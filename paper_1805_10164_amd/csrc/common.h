@@ -8,7 +8,8 @@
 
 namespace mcnegf {
 
-constexpr int kMaxW = 16;
+constexpr int kMaxW = 32;
+constexpr int kMaxGradW = 16;  // the gradient kernels keep W-vectors in registers
 constexpr int kMaxOut = 4096;
 
 // ---- complex FP64 arithmetic on double2 (x = real, y = imaginary) ----------------------

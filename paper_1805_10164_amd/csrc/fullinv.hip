@@ -14,9 +14,10 @@
 //   wL[j]    = <psi_j|Gamma_L|psi_j>, wR[j]  (psi_j = G|j>, exit weights, Eq. (76)),
 //   corner   = G_{L-1,0} and G_{0,L-1}       (lead-to-lead transmissions).
 // Rows of P are written by 64 lanes at consecutive columns (coalesced 512-byte segments).
-// The block products run on the FP64 VALU: at W <= 16 the operands live in registers and
-// LDS, and gfx950's FP64 matrix-core rate equals its FP64 FMA rate, so padding W up to a
-// 16x16x4 MFMA shape would only add work.
+// The block products run on the FP64 VALU: the operands live in registers and LDS, and
+// gfx950's FP64 matrix-core rate equals its FP64 FMA rate, so padding W up to a 16x16x4 MFMA
+// shape would only add work.  Up to W = 24 the column and the product fit the register file;
+// at W = 32 a few values spill.
 #include "common.h"
 
 namespace mcnegf {
@@ -199,7 +200,10 @@ static hipError_t launch_fullinv_any(const mcnegf_kernel& k, double2* Gc, int64_
         MCNEGF_CASE(1) MCNEGF_CASE(2) MCNEGF_CASE(3) MCNEGF_CASE(4) MCNEGF_CASE(5)
         MCNEGF_CASE(6) MCNEGF_CASE(7) MCNEGF_CASE(8) MCNEGF_CASE(9) MCNEGF_CASE(10)
         MCNEGF_CASE(11) MCNEGF_CASE(12) MCNEGF_CASE(13) MCNEGF_CASE(14) MCNEGF_CASE(15)
-        MCNEGF_CASE(16)
+        MCNEGF_CASE(16) MCNEGF_CASE(17) MCNEGF_CASE(18) MCNEGF_CASE(19) MCNEGF_CASE(20)
+        MCNEGF_CASE(21) MCNEGF_CASE(22) MCNEGF_CASE(23) MCNEGF_CASE(24) MCNEGF_CASE(25)
+        MCNEGF_CASE(26) MCNEGF_CASE(27) MCNEGF_CASE(28) MCNEGF_CASE(29) MCNEGF_CASE(30)
+        MCNEGF_CASE(31) MCNEGF_CASE(32)
 #undef MCNEGF_CASE
         default:
             return hipErrorInvalidValue;

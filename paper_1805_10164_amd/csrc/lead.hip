@@ -41,10 +41,10 @@ __global__ void __launch_bounds__(256) lead_sigma_kernel(const double* __restric
     double2* sig = sigma + (size_t)e * W * W;
     double* gm = gam + (size_t)e * W * W;
     if (lead_model == 1) {
-        if (tid < W * W) {
-            int a = tid / W, b = tid % W;
-            sig[tid] = cmk(0.0, a == b ? -0.5 * gamma_l : 0.0);
-            gm[tid] = a == b ? gamma_l : 0.0;
+        for (int i = tid; i < W * W; i += blockDim.x) {
+            const int a = i / W, b = i % W;
+            sig[i] = cmk(0.0, a == b ? -0.5 * gamma_l : 0.0);
+            gm[i] = a == b ? gamma_l : 0.0;
         }
         return;
     }
@@ -58,17 +58,17 @@ __global__ void __launch_bounds__(256) lead_sigma_kernel(const double* __restric
         const double2 big = cscale(plus ? cadd(zm, sq) : csub(zm, sq), 0.5);
         s_mode[tid] = cscale(crecip(big), t * t);
     }
-    if (tid < W * W) {
-        const int y = tid / W, m = tid % W;
+    for (int i = tid; i < W * W; i += blockDim.x) {
+        const int y = i / W, m = i % W;
         chi[y][m] = sqrt(2.0 / (W + 1)) * sinpi((double)((m + 1) * (y + 1)) / (double)(W + 1));
     }
     __syncthreads();
-    if (tid < W * W) {
-        const int a = tid / W, b = tid % W;
+    for (int i = tid; i < W * W; i += blockDim.x) {
+        const int a = i / W, b = i % W;
         double2 acc = cmk(0.0, 0.0);
         for (int m = 0; m < W; ++m) acc = cadd(acc, cscale(s_mode[m], chi[a][m] * chi[b][m]));
-        sig[tid] = acc;
-        gm[tid] = -2.0 * acc.y;
+        sig[i] = acc;
+        gm[i] = -2.0 * acc.y;
     }
 }
 

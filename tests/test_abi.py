@@ -64,7 +64,7 @@ def test_workspace_bytes_and_validation():
     lib = M.lib()
     assert M.mc_negf_workspace_bytes(M.make_system(10, 100), 256) > 4e9
     out = ctypes.c_uint64(0)
-    bad = [M.make_system(0, 5), M.make_system(17, 5), M.make_system(16, 300),
+    bad = [M.make_system(0, 5), M.make_system(33, 5), M.make_system(16, 300),
            M.make_system(4, 5, t=-1.0), M.make_system(4, 5, delta_lead=0.0),
            M.make_system(4, 5, lead_model=2)]
     for s in bad:

@@ -64,6 +64,11 @@ CASES = {
     "w7l9_wideband": dict(W=7, L=9, eta=0.08, disorder=0.4, nE=4, emin=-2.5, emax=2.5,
                           lead_model=1, gamma_l=0.6),
     "w5l70_ragged": dict(W=5, L=70, eta=0.03, disorder=0.25, nE=3, emin=-2.0, emax=1.0),
+    # wide blocks (column-per-lane block inversions), up to the paper's 32 x 32 blocks
+    "w20l7": dict(W=20, L=7, eta=0.06, disorder=0.4, nE=3, emin=-3.2, emax=3.0),
+    "w24l5_wideband": dict(W=24, L=5, eta=0.05, disorder=0.3, nE=2, emin=-2.0, emax=2.5,
+                           lead_model=1, gamma_l=0.5),
+    "w32l6": dict(W=32, L=6, eta=0.02, disorder=0.3, nE=3, emin=-3.5, emax=3.5),
 }
 
 
@@ -356,6 +361,17 @@ def test_no_alias_build_serves_direct_and_grad():
     assert ei.value.code == M.EINVAL
 
 
+def test_grad_rejects_wide_blocks():
+    c = case(W=20, L=2, eta=0.1, disorder=0.0, nE=1, emin=0.0, emax=0.1)
+    k = gpu_build(c)
+    w = torch.tensor(c["w"], dtype=torch.float64, device=DEV)
+    gws = torch.empty(M.mc_negf_grad_workspace_bytes(k), dtype=torch.uint8, device=DEV)
+    x = torch.empty(40, dtype=torch.float64, device=DEV)
+    with pytest.raises(M.McnegfError) as ei:
+        M.mc_negf_grad(k, 0, w, gws, x, x)
+    assert ei.value.code == M.EINVAL
+
+
 def test_grad_single_site_closed_form():
     # N = 1, wide-band leads: T = g G_t / 2 / ((E - V)^2 + G_t^2 / 4) with G_t = 2 g + gamma,
     # g = 0.4; differentiate the closed form in V (at V = 0) and gamma.
@@ -393,7 +409,7 @@ def test_errors_are_reported_before_launch():
         M.mc_negf_build_kernel(s, x, x, E, ws)
     assert ei.value.code == M.EWS
     with pytest.raises(M.McnegfError) as ei:
-        M.mc_negf_build_kernel(M.make_system(17, 5), x, x, E, ws)
+        M.mc_negf_build_kernel(M.make_system(33, 5), x, x, E, ws)
     assert ei.value.code == M.EINVAL
 
 
