@@ -190,9 +190,246 @@ static hipError_t launch_fullinv_w(const mcnegf_kernel& k, double2* Gc, int64_t 
     return hipGetLastError();
 }
 
+// ---- W = 16 and W = 32 on FP64 matrix cores ----------------------------------------------
+//
+// The same sweeps, with the block products on v_mfma_f64_16x16x4f64 (no padding at these
+// widths).  A wavefront owns TC tiles of 16 consecutive columns; lane (n, g) = (l % 16, l / 16)
+// holds, for tile t and row tile rt, the rows 16 rt + 4 r + g (r = 0..3) of column n, which is
+// both the accumulator layout of the product (item r of lane n + 16 g is row 4 r + g) and the
+// B-operand layout of the next product (K-step s takes rows 4 s + g from lane n + 16 g), so the
+// columns stay in registers from slice to slice.  The A operand of K-step s and row tile rt,
+// lane (m, g): (-t) M[16 rt + m][4 s + g], read from the LDS-staged block.  A complex product
+// is four real products (re re, -im im into the real part; re im, im re into the imaginary).
+typedef double dmfma4 __attribute__((ext_vector_type(4)));
+
+template <int W, int TC, bool STORE_G>
+__global__ void __launch_bounds__(64) fullinv_mfma_kernel(const double2* __restrict__ gL,
+                                                          const double2* __restrict__ gR,
+                                                          const double2* __restrict__ Gd,
+                                                          const double* __restrict__ gam_lead,
+                                                          int L, double t, int64_t ldP,
+                                                          double* __restrict__ P,
+                                                          double* __restrict__ wL,
+                                                          double* __restrict__ wR,
+                                                          double2* __restrict__ corner,
+                                                          double2* __restrict__ Gc, int64_t ldG) {
+    constexpr int RT = W / 16;  // row tiles
+    constexpr int S = W / 4;    // K-steps
+    constexpr int BS = 2 * W * W;
+    __shared__ double Ms_raw[2 * BS];
+    lds_double* Ms = (lds_double*)Ms_raw;
+    const int N = W * L;
+    const int e = blockIdx.y;
+    const int lane = threadIdx.x;
+    const int n = lane & 15, g = lane >> 4;
+    const int c0 = blockIdx.x * 16 * TC;
+    const int kmin = c0 / W;
+    const int kmax = (min(c0 + 16 * TC, N) - 1) / W;
+    const size_t eb = (size_t)e * L * W * W;
+    const double2* gLe = gL + eb;
+    const double2* gRe = gR + eb;
+    const double2* Gde = Gd + eb;
+    const double* gme = gam_lead + (size_t)e * W * W;
+    double* Pe = P + (size_t)e * N * ldP;
+    double2* cRL = corner + (size_t)e * 2 * W * W;
+    double2* cLR = cRL + W * W;
+    double2* Ge = Gc + (size_t)e * N * ldG;
+    const double mt = -t;
+
+    int col[TC], l[TC], y0[TC];
+    bool valid[TC];
+#pragma unroll
+    for (int tc = 0; tc < TC; ++tc) {
+        col[tc] = c0 + 16 * tc + n;
+        valid[tc] = col[tc] < N;
+        const int cc = valid[tc] ? col[tc] : N - 1;
+        l[tc] = cc / W;
+        y0[tc] = cc - l[tc] * W;
+    }
+    double vr[TC][RT][4], vi[TC][RT][4];
+
+    // one slice: v <- (-t) M v with M the block staged at buf
+    auto product = [&](const lds_double* buf) {
+        dmfma4 cr[TC][RT], ci[TC][RT];
+#pragma unroll
+        for (int tc = 0; tc < TC; ++tc)
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                cr[tc][rt] = dmfma4{0.0, 0.0, 0.0, 0.0};
+                ci[tc][rt] = dmfma4{0.0, 0.0, 0.0, 0.0};
+            }
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int at = 2 * ((16 * rt + n) * W + 4 * s + g);
+                const double ar = mt * buf[at], ai = mt * buf[at + 1];
+#pragma unroll
+                for (int tc = 0; tc < TC; ++tc) {
+                    const double br = vr[tc][s >> 2][s & 3], bi = vi[tc][s >> 2][s & 3];
+                    cr[tc][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, cr[tc][rt], 0, 0, 0);
+                    cr[tc][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, cr[tc][rt], 0, 0, 0);
+                    ci[tc][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, ci[tc][rt], 0, 0, 0);
+                    ci[tc][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, ci[tc][rt], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int tc = 0; tc < TC; ++tc)
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    vr[tc][rt][r] = cr[tc][rt][r];
+                    vi[tc][rt][r] = ci[tc][rt][r];
+                }
+    };
+    // at slice k: the diagonal block's column for columns of slice k, zero for columns whose
+    // slice is beyond k in the sweep direction (`before`)
+    auto fix = [&](int k, bool down) {
+#pragma unroll
+        for (int tc = 0; tc < TC; ++tc) {
+            const bool here = k == l[tc];
+            const bool before = down ? k < l[tc] : k > l[tc];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int y = 16 * rt + 4 * r + g;
+                    double2 d = cmk(0.0, 0.0);
+                    if (here) d = Gde[(size_t)k * W * W + y * W + y0[tc]];
+                    vr[tc][rt][r] = here ? d.x : (before ? 0.0 : vr[tc][rt][r]);
+                    vi[tc][rt][r] = here ? d.y : (before ? 0.0 : vi[tc][rt][r]);
+                }
+        }
+    };
+    auto store = [&](int k, bool down) {
+#pragma unroll
+        for (int tc = 0; tc < TC; ++tc) {
+            const bool on = valid[tc] && (down ? k >= l[tc] : k < l[tc]);
+            if (!on) continue;
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int y = 16 * rt + 4 * r + g;
+                    if (STORE_G)
+                        Ge[(size_t)(k * W + y) * ldG + col[tc]] = cmk(vr[tc][rt][r], vi[tc][rt][r]);
+                    else
+                        Pe[(size_t)(k * W + y) * ldP + col[tc]] =
+                            vr[tc][rt][r] * vr[tc][rt][r] + vi[tc][rt][r] * vi[tc][rt][r];
+                }
+        }
+    };
+    // Re v^+ Gamma v per column (Gamma real symmetric): u = Gamma v on the matrix cores, the
+    // row sum of Re(conj(v) u) over the four lanes of each column; lane g = 0 gets the result.
+    auto quad = [&](int tc) -> double {
+        dmfma4 ur[RT], ui[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            ur[rt] = dmfma4{0.0, 0.0, 0.0, 0.0};
+            ui[rt] = dmfma4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const double a = gme[(16 * rt + n) * W + 4 * s + g];
+                ur[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, vr[tc][s >> 2][s & 3], ur[rt], 0, 0, 0);
+                ui[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, vi[tc][s >> 2][s & 3], ui[rt], 0, 0, 0);
+            }
+        }
+        double q = 0.0;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                q = fma(vr[tc][rt][r], ur[rt][r], fma(vi[tc][rt][r], ui[rt][r], q));
+        q += __shfl_xor(q, 16, 64);
+        q += __shfl_xor(q, 32, 64);
+        return q;
+    };
+
+    // ---- downward: k = kmin .. L-1 (gR) -------------------------------------------------
+#pragma unroll
+    for (int tc = 0; tc < TC; ++tc)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) vr[tc][rt][r] = vi[tc][rt][r] = 0.0;
+    stage_block<W>(Ms, gRe + (size_t)kmin * W * W, lane);
+    for (int k = kmin; k < L; ++k) {
+        __syncthreads();
+        const int b = (k - kmin) & 1;
+        if (k + 1 < L) stage_block<W>(Ms + (b ^ 1) * BS, gRe + (size_t)(k + 1) * W * W, lane);
+        product(Ms + b * BS);
+        fix(k, true);
+        store(k, true);
+    }
+    if (!STORE_G) {
+#pragma unroll
+        for (int tc = 0; tc < TC; ++tc) {
+            const double q = quad(tc);
+            if (valid[tc] && g == 0) wR[(size_t)e * N + col[tc]] = q;
+            if (valid[tc] && l[tc] == 0) {
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        cRL[(16 * rt + 4 * r + g) * W + y0[tc]] = cmk(vr[tc][rt][r], vi[tc][rt][r]);
+            }
+        }
+    }
+    // ---- upward: k = kmax .. 0 (gL) -----------------------------------------------------
+#pragma unroll
+    for (int tc = 0; tc < TC; ++tc)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) vr[tc][rt][r] = vi[tc][rt][r] = 0.0;
+    __syncthreads();
+    stage_block<W>(Ms, gLe + (size_t)kmax * W * W, lane);
+    for (int k = kmax; k >= 0; --k) {
+        __syncthreads();
+        const int b = (kmax - k) & 1;
+        if (k > 0) stage_block<W>(Ms + (b ^ 1) * BS, gLe + (size_t)(k - 1) * W * W, lane);
+        product(Ms + b * BS);
+        fix(k, false);
+        store(k, false);
+    }
+    if (!STORE_G) {
+#pragma unroll
+        for (int tc = 0; tc < TC; ++tc) {
+            const double q = quad(tc);
+            if (valid[tc] && g == 0) wL[(size_t)e * N + col[tc]] = q;
+            if (valid[tc] && l[tc] == L - 1) {
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        cLR[(16 * rt + 4 * r + g) * W + y0[tc]] = cmk(vr[tc][rt][r], vi[tc][rt][r]);
+            }
+        }
+    }
+}
+
+template <int W, int TC, bool STORE_G>
+static hipError_t launch_fullinv_mfma(const mcnegf_kernel& k, double2* Gc, int64_t ldG,
+                                      hipStream_t s) {
+    dim3 grid((k.N + 16 * TC - 1) / (16 * TC), k.nE);
+    {
+        MCNEGF_TIMED(STORE_G ? "fullinv_store_g_kernel" : "fullinv_kernel", s);
+        hipLaunchKernelGGL((fullinv_mfma_kernel<W, TC, STORE_G>), grid, dim3(64), 0, s,
+                           reinterpret_cast<const double2*>(k.gL),
+                           reinterpret_cast<const double2*>(k.gR),
+                           reinterpret_cast<const double2*>(k.Gd), k.gam_lead, k.L, k.t, k.p_pitch,
+                           k.P, k.wL, k.wR, reinterpret_cast<double2*>(k.corner), Gc, ldG);
+    }
+    return hipGetLastError();
+}
+
 template <bool STORE_G>
 static hipError_t launch_fullinv_any(const mcnegf_kernel& k, double2* Gc, int64_t ldG,
                                      hipStream_t s) {
+    if (k.W == 16) return launch_fullinv_mfma<16, 4, STORE_G>(k, Gc, ldG, s);
+    if (k.W == 32) return launch_fullinv_mfma<32, 2, STORE_G>(k, Gc, ldG, s);
     switch (k.W) {
 #define MCNEGF_CASE(w) \
     case w:            \
