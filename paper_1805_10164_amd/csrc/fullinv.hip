@@ -264,13 +264,20 @@ __global__ void __launch_bounds__(64) fullinv_mfma_kernel(const double2* __restr
             for (int s = 0; s < S; ++s) {
                 const int at = 2 * ((16 * rt + n) * W + 4 * s + g);
                 const double ar = mt * buf[at], ai = mt * buf[at + 1];
+                // consecutive products go to different accumulators (2 TC independent chains)
 #pragma unroll
                 for (int tc = 0; tc < TC; ++tc) {
-                    const double br = vr[tc][s >> 2][s & 3], bi = vi[tc][s >> 2][s & 3];
-                    cr[tc][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, cr[tc][rt], 0, 0, 0);
-                    cr[tc][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, cr[tc][rt], 0, 0, 0);
-                    ci[tc][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, ci[tc][rt], 0, 0, 0);
-                    ci[tc][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, ci[tc][rt], 0, 0, 0);
+                    cr[tc][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, vr[tc][s >> 2][s & 3],
+                                                                      cr[tc][rt], 0, 0, 0);
+                    ci[tc][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, vi[tc][s >> 2][s & 3],
+                                                                      ci[tc][rt], 0, 0, 0);
+                }
+#pragma unroll
+                for (int tc = 0; tc < TC; ++tc) {
+                    cr[tc][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, vi[tc][s >> 2][s & 3],
+                                                                      cr[tc][rt], 0, 0, 0);
+                    ci[tc][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, vr[tc][s >> 2][s & 3],
+                                                                      ci[tc][rt], 0, 0, 0);
                 }
             }
         }
