@@ -213,6 +213,12 @@ struct CholArgs {
     int N, Np;
     int64_t ld;
     uint32_t inject_lead;
+    // Block columns [J0, J1) in this launch, and workgroups per energy.  One launch over all
+    // block columns (nsplit = 1) also forms T from the bordered rows as it goes; with several
+    // launches (one per block column, nsplit workgroups per energy taking every nsplit-th
+    // super-tile) T is formed afterwards by direct_dot_kernel.
+    int J0, J1, nsplit;
+    bool single;
 };
 
 __device__ inline double readlane_f64(double v, int lane) {
@@ -296,7 +302,7 @@ typedef __attribute__((address_space(3))) int lds_int;
 
 __device__ __noinline__ void factor_diag_block(lds_double* VZs, lds_double* Ls, lds_double* colbuf,
                                                double* Lg, int64_t ld, int wJ, int lane,
-                                               lds_int* bad_flag) {
+                                               lds_int* bad_flag, bool store) {
     // Lane i holds row i; column k is shared through LDS.  The step branch is uniform; the
     // updates of columns from wJ on are harmless (their entries stay zero).
     const int i = lane;
@@ -326,7 +332,8 @@ __device__ __noinline__ void factor_diag_block(lds_double* VZs, lds_double* Ls, 
     for (int j = 0; j < CH_NB; ++j) {
         const double lv = (j <= i && i < wJ) ? rw[j] : (i == j ? 1.0 : 0.0);
         Ls[i * CH_VP + j] = lv;
-        if (j <= i && i < wJ) Lg[(size_t)i * ld + (j & ~15) + 4 * (j & 3) + ((j >> 2) & 3)] = lv;
+        if (store && j <= i && i < wJ)
+            Lg[(size_t)i * ld + (j & ~15) + 4 * (j & 3) + ((j >> 2) & 3)] = lv;
     }
     // Inverses of the four 16 x 16 diagonal sub-blocks of L_JJ: lane (b, c) = (lane / 16,
     // lane % 16) computes column c of L_bb^{-1} by forward substitution and stores it in the
@@ -359,7 +366,8 @@ __global__ void __launch_bounds__(512) cholesky_kernel(CholArgs a) {
     __shared__ double dot_acc;
     __shared__ int bad_flag;
 
-    const int e = blockIdx.x;
+    const int e = blockIdx.x / a.nsplit;
+    const int part = blockIdx.x - e * a.nsplit;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -380,8 +388,7 @@ __global__ void __launch_bounds__(512) cholesky_kernel(CholArgs a) {
     const int sm = tid >> 3;
     const int sc = (tid & 7) * 4;
 
-    const int nJ = (Np + CH_NB - 1) / CH_NB;
-    for (int J = 0; J < nJ; ++J) {
+    for (int J = a.J0; J < a.J1; ++J) {
         const int c0 = J * CH_NB;
         const int wJ = min(CH_NB, Np - c0);
         const int ncb = wJ >> 4;
@@ -438,11 +445,12 @@ __global__ void __launch_bounds__(512) cholesky_kernel(CholArgs a) {
         __syncthreads();
         if (wave == 0)
             factor_diag_block((lds_double*)VZs, (lds_double*)Ls, (lds_double*)colbuf,
-                              Le + (size_t)c0 * ld + c0, ld, wJ, lane, (lds_int*)&bad_flag);
+                              Le + (size_t)c0 * ld + c0, ld, wJ, lane, (lds_int*)&bad_flag,
+                              part == 0);
         __syncthreads();
 
         // ---- rows below the diagonal block, in super-tiles of 256 rows
-        for (int st = c0 + wJ; st < R; st += CH_ROWS) {
+        for (int st = c0 + wJ + part * CH_ROWS; st < R; st += a.nsplit * CH_ROWS) {
             const int r0 = st + wave * 32;  // this wave's rows r0 .. r0 + 31
             dmfma4 acc[2][4];
 #pragma unroll
@@ -536,7 +544,7 @@ __global__ void __launch_bounds__(512) cholesky_kernel(CholArgs a) {
                                                             cq) =
                                     double4{y[mb][0], y[mb][1], y[mb][2], y[mb][3]};
                     }
-                    if (rt == Np) {
+                    if (a.single && rt == Np) {
                         // rows Np (lanes ln == 0) and Np + 1 (ln == 1): accumulate y . z
                         double part = 0.0;
 #pragma unroll
@@ -557,12 +565,36 @@ __global__ void __launch_bounds__(512) cholesky_kernel(CholArgs a) {
     }
     __syncthreads();
     if (tid == 0) {
+        if (bad_flag) atomicOr(a.status, MCNEGF_FLAG_NOTSPD);
+        if (a.single) {
+            const double* ld_ = a.lead + (size_t)e * MCNEGF_LEAD_NTERMS;
+            const double tqp = a.inject_lead == 0 ? ld_[MCNEGF_LEAD_TRL] : ld_[MCNEGF_LEAD_TLR];
+            const double Tk = tqp + dot_acc;
+            a.T[e] = Tk;
+            a.sig[e] = 0.0;
+            if (!isfinite(Tk)) atomicOr(a.status, MCNEGF_FLAG_NONFINITE);
+        }
+    }
+}
+
+// T_k = T_qp + (row Np of L) . (row Np + 1 of L) after a factorization in several launches
+// (fixed-order sum; both rows carry the same column permutation).
+__global__ void __launch_bounds__(256) direct_dot_kernel(CholArgs a) {
+    __shared__ double red[256];
+    const int e = blockIdx.x;
+    const int Np = a.Np;
+    const double* Le = a.Lall + (size_t)e * (Np + 2) * a.ld;
+    const double* y = Le + (size_t)Np * a.ld;
+    const double* z = y + a.ld;
+    double part = 0.0;
+    for (int j = threadIdx.x; j < Np; j += 256) part = fma(y[j], z[j], part);
+    const double dot = block_reduce256(part, red);
+    if (threadIdx.x == 0) {
         const double* ld_ = a.lead + (size_t)e * MCNEGF_LEAD_NTERMS;
         const double tqp = a.inject_lead == 0 ? ld_[MCNEGF_LEAD_TRL] : ld_[MCNEGF_LEAD_TLR];
-        const double Tk = tqp + dot_acc;
+        const double Tk = tqp + dot;
         a.T[e] = Tk;
         a.sig[e] = 0.0;
-        if (bad_flag) atomicOr(a.status, MCNEGF_FLAG_NOTSPD);
         if (!isfinite(Tk)) atomicOr(a.status, MCNEGF_FLAG_NONFINITE);
     }
 }
@@ -605,11 +637,47 @@ hipError_t launch_direct_current(const mcnegf_kernel& k, uint32_t inject_lead,
     a.Np = (int)k.p_pitch;
     a.ld = k.p_pitch;
     a.inject_lead = inject_lead;
-    {
-        MCNEGF_TIMED("cholesky_kernel", s);
-        hipLaunchKernelGGL(cholesky_kernel, dim3(k.nE), dim3(64 * CH_WAVES), 0, s, a);
+    const int nJ = (a.Np + CH_NB - 1) / CH_NB;
+    // One workgroup (one CU) per energy.  When the energies leave CUs idle and the matrix is
+    // large, split each energy over several workgroups, one launch per block column (the
+    // launch boundary orders the block columns; no cross-workgroup waits).
+    int dev = 0, cus = 0;
+    if ((err = hipGetDevice(&dev)) != hipSuccess) return err;
+    if ((err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
+        hipSuccess)
+        return err;
+    int nsplit = cus / (k.nE > 0 ? k.nE : 1);
+    nsplit = nsplit > 4 ? 4 : nsplit;
+    if (a.Np < 1024 || nJ < 4) nsplit = 1;
+    if (nsplit <= 1) {
+        a.J0 = 0;
+        a.J1 = nJ;
+        a.nsplit = 1;
+        a.single = true;
+        {
+            MCNEGF_TIMED("cholesky_kernel", s);
+            hipLaunchKernelGGL(cholesky_kernel, dim3(k.nE), dim3(64 * CH_WAVES), 0, s, a);
+        }
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+    } else {
+        a.nsplit = nsplit;
+        a.single = false;
+        for (int J = 0; J < nJ; ++J) {
+            a.J0 = J;
+            a.J1 = J + 1;
+            {
+                MCNEGF_TIMED("cholesky_kernel", s);
+                hipLaunchKernelGGL(cholesky_kernel, dim3(k.nE * nsplit), dim3(64 * CH_WAVES), 0, s,
+                                   a);
+            }
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+        }
+        {
+            MCNEGF_TIMED("direct_dot_kernel", s);
+            hipLaunchKernelGGL(direct_dot_kernel, dim3(k.nE), dim3(256), 0, s, a);
+        }
+        if ((err = hipGetLastError()) != hipSuccess) return err;
     }
-    if ((err = hipGetLastError()) != hipSuccess) return err;
     {
         MCNEGF_TIMED("current_sum_kernel", s);
         hipLaunchKernelGGL(current_sum_kernel, dim3(1), dim3(256), 0, s, T, sigmaT, weights, k.nE,

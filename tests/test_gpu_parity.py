@@ -182,6 +182,23 @@ def test_alias_tables_of_long_rows():
             assert np.abs(p - ref).max() < 4.0 * 2.0 ** -32 + 1e-12, (e, r)
 
 
+def test_direct_current_few_energies_split_factorization():
+    # N = 1280 with 3 energies: each energy's factorization is split over several workgroups,
+    # one launch per block column; T from the stored bordered rows.
+    c = case(W=16, L=80, eta=0.05, disorder=0.3, nE=3, emin=-2.5, emax=2.0)
+    k = gpu_build(c)
+    w = torch.tensor(c["w"], dtype=torch.float64, device=DEV)
+    T = torch.empty(3, dtype=torch.float64, device=DEV)
+    sg = torch.empty_like(T)
+    for lead in (0, 1):
+        st, I, _ = M.mc_negf_current(k, 1, lead, None, w, T, sg)
+        assert st == M.OK
+        sols = oracle_solve(c)
+        Tref = np.array([s_.T_eff for s_ in sols])
+        assert (np.abs(T.cpu().numpy() - Tref) <= 1e-10 * np.abs(Tref)).all()
+        assert abs(I - D.current(sols, c["w"])) <= 1e-10 * abs(I)
+
+
 def test_direct_current_matches_oracle(built):
     name, c, k, sols = built
     nE = len(c["E"])
