@@ -75,7 +75,27 @@ __device__ inline bool gj_invert(double2 (&a)[2 * W], int lane, int& rank) {
     return ok;
 }
 
-// Row i (< W) of A_k for energy E, in a[0..W-1]; identity row in a[W..2W-1].
+// Row i (< W) of A_k for energy E, in a[0..W-1]; identity row in a[W..2W-1]; Vi, gi are the
+// onsite energy and dephasing rate of site (k, i).
+template <int W>
+__device__ inline void diag_block_row_v(double2 (&a)[2 * W], int i, int k, int L, double E,
+                                        double t, double Vi, double gi,
+                                        const double2* __restrict__ sig) {
+#pragma unroll
+    for (int j = 0; j < 2 * W; ++j) a[j] = cmk(0.0, 0.0);
+    if (i >= W) return;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        double2 v = cmk(0.0, 0.0);
+        if (j == i) v = cmk(E - Vi, 0.5 * gi);
+        if (j == i - 1 || j == i + 1) v = cmk(t, 0.0);
+        if (k == 0) v = csub(v, sig[i * W + j]);
+        if (k == L - 1) v = csub(v, sig[i * W + j]);
+        a[j] = v;
+        a[W + j] = cmk(j == i ? 1.0 : 0.0, 0.0);
+    }
+}
+
 template <int W>
 __device__ inline void diag_block_row(double2 (&a)[2 * W], int i, int k, int L, double E, double t,
                                       const double* __restrict__ onsite,
@@ -114,10 +134,20 @@ __global__ void __launch_bounds__(64) rgf_sweep_kernel(const double* __restrict_
     double2* out = (dir == 0 ? gL : gR) + (size_t)e * L * W * W;
     const double t2 = t * t;
     bool ok = true;
+    // the onsite energy and dephasing rate of this lane's site, loaded one slice ahead
+    const int i_site = lane < W ? lane : 0;
+    const int k_first = dir == 0 ? 0 : L - 1;
+    double Vn = onsite[k_first * W + i_site], gn = gamma[k_first * W + i_site];
     for (int s = 0; s < L; ++s) {
         const int k = dir == 0 ? s : L - 1 - s;
+        const double Vi = Vn, gi = gn;
+        if (s + 1 < L) {
+            const int kn = dir == 0 ? s + 1 : L - 2 - s;
+            Vn = onsite[kn * W + i_site];
+            gn = gamma[kn * W + i_site];
+        }
         double2 a[2 * W];
-        diag_block_row<W>(a, lane, k, L, E, t, onsite, gamma, sig);
+        diag_block_row_v<W>(a, lane, k, L, E, t, Vi, gi, sig);
         if (s > 0 && lane < W) {
 #pragma unroll
             for (int j = 0; j < W; ++j) a[j] = csub(a[j], cscale(prev[lane][j], t2));
