@@ -35,8 +35,9 @@
  *     launched.  No C++ exception crosses the ABI.
  *   - Kernels record numerical trouble in a device status word inside the workspace; it is
  *     read by mc_negf_current / mc_negf_status.
- *   - Sizes: 1 <= W <= 32, 1 <= L, N = W*L, N + 2 <= 4096 (12-bit outcome index in the
- *     packed alias entries), 1 <= nE; mc_negf_grad needs W <= 16.
+ *   - Sizes: 1 <= W <= 32, 1 <= L, N = W*L, N + 2 <= 16320 (the alias build keeps 10 bytes
+ *     per outcome of a row in one workgroup's LDS), 1 <= nE; mc_negf_grad needs W <= 16 and
+ *     N <= 4096.
  */
 #ifndef MCNEGF_H
 #define MCNEGF_H
@@ -125,11 +126,11 @@ typedef struct mcnegf_kernel {
     const double* energies; /* [nE], borrowed from the caller                              */
     const double* gamma;    /* [N], borrowed from the caller                               */
     uint32_t* alias;        /* [nE][n_out][alias_pitch] packed alias entries:              */
-                            /*  bits 31..12 = thr >> 12, bits 11..0 = alias (n_out <= 4096) */
-    uint16_t* alias_lo;     /* [nE][n_out][alias_pitch] thr & 0xFFF.  Bucket c keeps        */
+                            /*  bits 31..16 = thr >> 16, bits 15..0 = alias                 */
+    uint16_t* alias_lo;     /* [nE][n_out][alias_pitch] thr & 0xFFFF.  Bucket c keeps       */
                             /*  outcome c when a uniform 32-bit word r satisfies r < thr,   */
                             /*  else goes to outcome alias (the low part of thr is read     */
-                            /*  only when r >> 12 == thr >> 12)                             */
+                            /*  only when r >> 16 == thr >> 16)                             */
     double*   P;            /* [nE][N][p_pitch]  |G_ij|^2                                  */
     double*   wL;           /* [nE][N]  <psi_j|Gamma_L|psi_j>, psi_j = G|j>                 */
     double*   wR;           /* [nE][N]  <psi_j|Gamma_R|psi_j>                               */
@@ -239,7 +240,8 @@ int32_t mc_negf_grad_workspace_bytes(const mcnegf_kernel* k, uint64_t* bytes_out
  *   d_gws        device workspace of >= mc_negf_grad_workspace_bytes, caller-owned.
  *   d_dI_dV      [N] device output dI/dV_i;  d_dI_dgamma [N] device output dI/dgamma_i.
  *   h_I          host output, the DIRECT current I.
- * Needs W <= 16 and a kernel built with the DIRECT workspace (else MCNEGF_EINVAL).
+ * Needs W <= 16, N <= 4096 and a kernel built with the DIRECT workspace (else
+ * MCNEGF_EINVAL).
  * Synchronises `stream`; status as mc_negf_current in DIRECT mode.  MCNEGF_EWS if the
  * workspace is too small; MCNEGF_EHIP if a launch fails.
  */

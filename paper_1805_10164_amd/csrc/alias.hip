@@ -24,9 +24,9 @@
 //   heavy m : threshold 1 + C_m - D*,   alias = heavy m+1   (last heavy: threshold 1, itself).
 // Each bucket c keeps outcome c with probability thr_c = floor(q_c 2^32) / 2^32 (a kept mass
 // of 1 is stored as 2^32 - 1 with the bucket aliased to itself).  Storage: one 32-bit word
-// per bucket with the high 20 bits of thr_c and the 12-bit alias, plus the low 12 bits of
+// per bucket with the high 16 bits of thr_c and the 16-bit alias, plus the low 16 bits of
 // thr_c in a separate 16-bit array that the walker reads only on a tie of the high bits
-// (probability 2^-20), so the comparison is the full 32-bit one at 4 bytes per bucket.
+// (probability 2^-16), so the comparison is the full 32-bit one at 4 bytes per bucket.
 #include "common.h"
 
 namespace mcnegf {
@@ -175,8 +175,8 @@ struct AliasArgs {
     const double* Adiag;
     const double* gamma;
     double* lead;
-    uint32_t* alias;     // packed (thr >> 12) << 12 | alias
-    uint16_t* alias_lo;  // thr & 0xFFF
+    uint32_t* alias;     // packed (thr >> 16) << 16 | alias
+    uint16_t* alias_lo;  // thr & 0xFFFF
     uint32_t* status;
     const double* gam_lead;
     int64_t ldP, pitch;
@@ -188,7 +188,7 @@ struct AliasArgs {
 // and keeps their weights, ranks and starts / ends in registers.  LDS holds what other
 // threads search: the light starts and heavy ends in one array of n + 1 doubles (lights from
 // the front with the total deficit after the last one, heavies from the back: heavy m at
-// n - m) and the heavy items' indices: 12 n bytes per row.
+// n - m) and the heavy items' indices (16 bits): 10 n bytes per row.
 template <int BT, int KM>
 __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
     extern __shared__ double smem[];
@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
     const int e = blockIdx.y;
     const int tid = threadIdx.x;
     double* lh = smem;                                   // [n+1] light starts | heavy ends
-    int* heavyIdx = reinterpret_cast<int*>(lh + n + 1);  // [n]
+    uint16_t* heavyIdx = reinterpret_cast<uint16_t*>(lh + n + 1);  // [n]
     auto lightD = [&](int r) -> double& { return lh[r]; };
     auto heavyC = [&](int m) -> double& { return lh[n - m]; };
 
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
             } else {
                 uh += v - 1.0;
                 heavyC(nh) = uh;
-                heavyIdx[nh] = i;
+                heavyIdx[nh] = (uint16_t)i;
                 rk[k] = ~nh;
                 dc[k] = uh;
                 ++nh;
@@ -353,8 +353,8 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
         } else {
             thr = (uint32_t)(q * 4294967296.0);
         }
-        out[i] = (thr & 0xFFFFF000u) | (uint32_t)al;
-        out_lo[i] = (uint16_t)(thr & 0xFFFu);
+        out[i] = (thr & ~kAliasIdxMask) | (uint32_t)al;
+        out_lo[i] = (uint16_t)(thr & kAliasIdxMask);
     }
 }
 
@@ -376,25 +376,45 @@ hipError_t launch_alias_build(const mcnegf_kernel& k, hipStream_t s) {
     a.W = k.W;
     a.open_cut = 1e3 * k.delta_lead * k.t * k.W;
     const int n = k.n_out;
-    const size_t lds = (size_t)(n + 1) * 8 + (size_t)n * 4;
-    // rows up to 1024 outcomes: 256 threads x 4 items; up to 1536: 256 x 6; longer rows
-    // (n <= kMaxOut = 4096): 512 x 8
-    const int shape = n <= 256 * 4 ? 0 : (n <= 256 * 6 ? 1 : 2);
-    const void* fn = shape == 0   ? (const void*)alias_build_kernel<256, 4>
-                     : shape == 1 ? (const void*)alias_build_kernel<256, 6>
-                                  : (const void*)alias_build_kernel<512, 8>;
+    const size_t lds = (size_t)(n + 1) * 8 + (size_t)n * 2;
+    // rows up to 1024 outcomes: 256 threads x 4 items; up to 1536: 256 x 6; up to 4096:
+    // 512 x 8; up to 8192: 512 x 16; longer rows (n <= kMaxOut): 512 x 32
+    const int shape = n <= 256 * 4 ? 0 : n <= 256 * 6 ? 1 : n <= 512 * 8 ? 2 : n <= 512 * 16 ? 3 : 4;
+    const void* fns[5] = {(const void*)alias_build_kernel<256, 4>,
+                          (const void*)alias_build_kernel<256, 6>,
+                          (const void*)alias_build_kernel<512, 8>,
+                          (const void*)alias_build_kernel<512, 16>,
+                          (const void*)alias_build_kernel<512, 32>};
+    const int bts[5] = {256, 256, 512, 512, 512};
     if (lds > 65536) {
-        hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        // rows beyond 6.5k outcomes need more than 64 KB of LDS per workgroup (gfx950: 160 KB)
+        int dev = 0, per_block = 0, optin = 0;
+        hipError_t err = hipGetDevice(&dev);
+        if (err == hipSuccess)
+            err = hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (err != hipSuccess) return err;
+        if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) !=
+            hipSuccess) {
+            optin = 0;
+            (void)hipGetLastError();  // the launch below reports its own error
+        }
+        const int max_lds = optin > per_block ? optin : per_block;
+        hipFuncAttributes fa;
+        if ((err = hipFuncGetAttributes(&fa, fns[shape])) != hipSuccess) return err;
+        if (lds + fa.sharedSizeBytes > (size_t)max_lds) return hipErrorInvalidConfiguration;
+        err = hipFuncSetAttribute(fns[shape], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (err != hipSuccess) return err;
     }
     {
         MCNEGF_TIMED("alias_build_kernel", s);
-        if (shape == 0)
-            hipLaunchKernelGGL((alias_build_kernel<256, 4>), dim3(n, k.nE), dim3(256), lds, s, a);
-        else if (shape == 1)
-            hipLaunchKernelGGL((alias_build_kernel<256, 6>), dim3(n, k.nE), dim3(256), lds, s, a);
-        else
-            hipLaunchKernelGGL((alias_build_kernel<512, 8>), dim3(n, k.nE), dim3(512), lds, s, a);
+        const dim3 grid(n, k.nE), block(bts[shape]);
+        switch (shape) {
+            case 0: hipLaunchKernelGGL((alias_build_kernel<256, 4>), grid, block, lds, s, a); break;
+            case 1: hipLaunchKernelGGL((alias_build_kernel<256, 6>), grid, block, lds, s, a); break;
+            case 2: hipLaunchKernelGGL((alias_build_kernel<512, 8>), grid, block, lds, s, a); break;
+            case 3: hipLaunchKernelGGL((alias_build_kernel<512, 16>), grid, block, lds, s, a); break;
+            default: hipLaunchKernelGGL((alias_build_kernel<512, 32>), grid, block, lds, s, a); break;
+        }
     }
     return hipGetLastError();
 }

@@ -10,7 +10,14 @@ namespace mcnegf {
 
 constexpr int kMaxW = 32;
 constexpr int kMaxGradW = 16;  // the gradient kernels keep W-vectors in registers
-constexpr int kMaxOut = 4096;
+// Outcomes per row (N + 2): the alias build holds 10 bytes per outcome of its row in LDS
+// (160 KB per CU), and a packed alias entry has a 16-bit outcome index.
+constexpr int kMaxOut = 16320;
+constexpr int kMaxGradOut = 4096;  // the back substitution keeps a row in registers
+// Packed alias entry: the high 16 bits of the 32-bit threshold over the 16-bit alias; the
+// low 16 threshold bits sit in a separate u16 array.
+constexpr uint32_t kAliasIdxBits = 16;
+constexpr uint32_t kAliasIdxMask = 0xFFFFu;
 
 // ---- complex FP64 arithmetic on double2 (x = real, y = imaginary) ----------------------
 __host__ __device__ inline double2 cmk(double re, double im) { return make_double2(re, im); }

@@ -646,8 +646,12 @@ hipError_t launch_direct_current(const mcnegf_kernel& k, uint32_t inject_lead,
     if ((err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
         hipSuccess)
         return err;
+    // Each workgroup of an energy forms the diagonal factor itself, so keep at least two
+    // super-tiles of the first block column per workgroup (four workgroups at any size).
+    const int nst = (a.Np - CH_NB + CH_ROWS - 1) / CH_ROWS;
+    const int cap = (nst + 1) / 2 > 4 ? (nst + 1) / 2 : 4;
     int nsplit = cus / (k.nE > 0 ? k.nE : 1);
-    nsplit = nsplit > 4 ? 4 : nsplit;
+    nsplit = nsplit > cap ? cap : nsplit;
     if (a.Np < 1024 || nJ < 4) nsplit = 1;
     if (nsplit <= 1) {
         a.J0 = 0;

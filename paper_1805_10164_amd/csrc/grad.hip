@@ -46,7 +46,7 @@ __device__ inline double readlane_dbl(double v, int lane) {
 // Thread tid owns the stored positions p = tid + 1024 q of r (in registers), so the update
 // reads the rows of block I coalesced with 64 independent loads per position.
 constexpr int BSV_THREADS = 1024;
-constexpr int BSV_Q = kMaxOut / BSV_THREADS;  // positions per thread (Np <= kMaxOut)
+constexpr int BSV_Q = kMaxGradOut / BSV_THREADS;  // positions per thread (Np <= kMaxGradOut)
 
 __global__ void __launch_bounds__(BSV_THREADS) backsolve_kernel(const double* __restrict__ Lall,
                                                                 const double* __restrict__ vec,

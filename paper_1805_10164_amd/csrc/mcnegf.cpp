@@ -277,7 +277,8 @@ int32_t mc_negf_grad(const mcnegf_kernel* k, uint32_t inject_lead, const double*
                      void* d_gws, uint64_t gws_bytes, double* d_dI_dV, double* d_dI_dgamma,
                      double* h_I, hipStream_t stream) {
     if (!valid_kernel(k) || !d_weights || !d_gws || !d_dI_dV || !d_dI_dgamma || !h_I ||
-        inject_lead > 1 || !k->direct || !k->direct_vec || k->W > kMaxGradW)
+        inject_lead > 1 || !k->direct || !k->direct_vec || k->W > kMaxGradW ||
+        k->p_pitch > kMaxGradOut)
         return MCNEGF_EINVAL;
     GradBuffers gb;
     if (grad_layout(*k, d_gws, &gb) > gws_bytes) return MCNEGF_EWS;

@@ -52,8 +52,8 @@ __device__ inline Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, u
 }
 
 struct WalkArgs {
-    const uint32_t* tables;  // packed (thr >> 12) << 12 | alias
-    const uint16_t* lows;    // thr & 0xFFF
+    const uint32_t* tables;  // packed (thr >> 16) << 16 | alias
+    const uint16_t* lows;    // thr & 0xFFFF
     int64_t pitch;
     int64_t table_stride;  // entries per energy
     uint32_t n_out, N;
@@ -154,20 +154,20 @@ __device__ inline void walk_steps(Step (&st)[K], const uint32_t (&w)[K], const u
     uint64_t tb = 0ull;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        keep[k] = (b[k] >> 12) < (ent[k] >> 12);
-        tie[k] = st[k].active && (b[k] >> 12) == (ent[k] >> 12);
+        keep[k] = (b[k] >> kAliasIdxBits) < (ent[k] >> kAliasIdxBits);
+        tie[k] = st[k].active && (b[k] >> kAliasIdxBits) == (ent[k] >> kAliasIdxBits);
         tb |= __ballot(tie[k]);
     }
-    if (tb != 0ull) {  // rare (probability 2^-20 per step); uniform branch
+    if (tb != 0ull) {  // rare (probability 2^-16 per lane and step); uniform branch
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const uint32_t lo = tie[k] ? (uint32_t)A.lows[at[k]] : 0u;
-            keep[k] = tie[k] ? (b[k] & 0xFFFu) < lo : keep[k];
+            keep[k] = tie[k] ? (b[k] & kAliasIdxMask) < lo : keep[k];
         }
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const uint32_t nxt = keep[k] ? c[k] : (ent[k] & 0xFFFu);
+        const uint32_t nxt = keep[k] ? c[k] : (ent[k] & kAliasIdxMask);
         const uint32_t n1 = st[k].n + 1;
         const bool active = st[k].active;
         const bool absorbed = active && nxt >= A.N;
@@ -548,20 +548,20 @@ __global__ void walk_batch_kernel(WalkBatchArgs A) {
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const uint32_t b = ab[h][1][k];
-                    keep[k] = (b >> 12) < (ent[k] >> 12);
-                    tie[k] = st[k].active && (b >> 12) == (ent[k] >> 12);
+                    keep[k] = (b >> kAliasIdxBits) < (ent[k] >> kAliasIdxBits);
+                    tie[k] = st[k].active && (b >> kAliasIdxBits) == (ent[k] >> kAliasIdxBits);
                     tb |= __ballot(tie[k]);
                 }
                 if (tb != 0ull) {  // rare; uniform branch
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
                         const uint32_t lo = tie[k] ? (uint32_t)U.lows[at[k]] : 0u;
-                        keep[k] = tie[k] ? (ab[h][1][k] & 0xFFFu) < lo : keep[k];
+                        keep[k] = tie[k] ? (ab[h][1][k] & kAliasIdxMask) < lo : keep[k];
                     }
                 }
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const uint32_t nxt = keep[k] ? c[k] : (ent[k] & 0xFFFu);
+                    const uint32_t nxt = keep[k] ? c[k] : (ent[k] & kAliasIdxMask);
                     const uint32_t n1 = st[k].n + 1;
                     const bool active = st[k].active;
                     const bool absorbed = active && nxt >= N;

@@ -83,6 +83,15 @@ def batch_workloads(n: int = BATCH_REALIZATIONS):
             for r, L in enumerate(Ls)]
 
 
+# Precision at scale: W = 32, L = 500 (N = 16000; the paper's 32 x 32 blocks, Sec. IV),
+# eta = 0.01 t, disorder U[-0.3 t, 0.3 t], 512 energies in [-3.5 t, 3.5 t] (inside the W = 32
+# lead band |E| < 3.991 t), 1e7 walkers/energy.  One energy's |G|^2, alias tables and probe
+# matrix take 5.6 GB, so the energies are processed in batches (SCALE_BATCH per build).
+SCALE_W32_L500 = Workload(name="scale_W32_L500", W=32, L=500, eta=0.01, disorder=0.3,
+                          emin=-3.5, emax=3.5, n_energies=512, walkers_per_energy=10_000_000)
+SCALE_BATCH = 32
+
+
 def onsite(w: Workload) -> np.ndarray:
     """Onsite energies V_i (float64, length N, slice-major i = x*W + y).
 

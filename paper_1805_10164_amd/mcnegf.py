@@ -221,12 +221,12 @@ class Kernel:
         return self.view("Gd", torch.float64, (self.nE, self.L, self.W, self.W, 2))
 
     def alias_packed(self):
-        """[nE][n_out][alias_pitch] packed entries (thr >> 12) << 12 | alias, int32 storage."""
+        """[nE][n_out][alias_pitch] packed entries (thr >> 16) << 16 | alias, int32 storage."""
         import torch
         return self.view("alias", torch.int32, (self.nE, self.n_out, self.alias_pitch))
 
     def alias_low(self):
-        """[nE][n_out][alias_pitch] low 12 bits of the thresholds, int16 storage."""
+        """[nE][n_out][alias_pitch] low 16 bits of the thresholds, int16 storage."""
         import torch
         return self.view("alias_lo", torch.int16, (self.nE, self.n_out, self.alias_pitch))
 
@@ -235,7 +235,18 @@ class Kernel:
         device format (format conversion only)."""
         packed = self.alias_packed().cpu().numpy().view(np.uint32)
         low = self.alias_low().cpu().numpy().view(np.uint16).astype(np.uint32)
-        return (packed & np.uint32(0xFFFFF000)) | low, (packed & np.uint32(0xFFF)).astype(np.int32)
+        return (packed & np.uint32(0xFFFF0000)) | low, (packed & np.uint32(0xFFFF)).astype(np.int32)
+
+    def alias_rows(self, e, rows):
+        """(thr uint32, alias int32) [len(rows)][n_out] of energy e's alias rows `rows`, read
+        back from the device format (format conversion only; copies only those rows)."""
+        import torch
+        idx = torch.as_tensor(list(rows), dtype=torch.int64, device=self.ws.device)
+        n = self.n_out
+        packed = self.alias_packed()[e].index_select(0, idx)[:, :n].cpu().numpy().view(np.uint32)
+        low = (self.alias_low()[e].index_select(0, idx)[:, :n].cpu().numpy().view(np.uint16)
+               .astype(np.uint32))
+        return (packed & np.uint32(0xFFFF0000)) | low, (packed & np.uint32(0xFFFF)).astype(np.int32)
 
     def set_alias_tables(self, thr, alias):
         """Store uint32 thresholds and alias indices [nE][n_out][alias_pitch] in the device
@@ -243,8 +254,8 @@ class Kernel:
         import torch
         thr = np.asarray(thr, dtype=np.uint32)
         alias = np.asarray(alias, dtype=np.uint32)
-        packed = (thr & np.uint32(0xFFFFF000)) | (alias & np.uint32(0xFFF))
-        low = (thr & np.uint32(0xFFF)).astype(np.uint16)
+        packed = (thr & np.uint32(0xFFFF0000)) | (alias & np.uint32(0xFFFF))
+        low = (thr & np.uint32(0xFFFF)).astype(np.uint16)
         dev = self.ws.device
         self.alias_packed().copy_(torch.from_numpy(packed.view(np.int32)).to(dev))
         self.alias_low().copy_(torch.from_numpy(low.view(np.int16)).to(dev))

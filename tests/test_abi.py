@@ -64,7 +64,7 @@ def test_workspace_bytes_and_validation():
     lib = M.lib()
     assert M.mc_negf_workspace_bytes(M.make_system(10, 100), 256) > 4e9
     out = ctypes.c_uint64(0)
-    bad = [M.make_system(0, 5), M.make_system(33, 5), M.make_system(16, 300),
+    bad = [M.make_system(0, 5), M.make_system(33, 5), M.make_system(32, 510),
            M.make_system(4, 5, t=-1.0), M.make_system(4, 5, delta_lead=0.0),
            M.make_system(4, 5, lead_model=2)]
     for s in bad:
@@ -72,6 +72,12 @@ def test_workspace_bytes_and_validation():
     s = M.make_system(4, 5)
     assert lib.mc_negf_workspace_bytes(ctypes.byref(s), 0, ctypes.byref(out)) == M.EINVAL
     assert lib.mc_negf_workspace_bytes(None, 4, ctypes.byref(out)) == M.EINVAL
+    # the largest rows: N + 2 = 16290 <= 16320 outcomes; one energy of W32 x L500 (N = 16000)
+    # holds |G|^2, the alias tables and the bordered probe matrix: 5.6 GB
+    assert lib.mc_negf_workspace_bytes(ctypes.byref(M.make_system(32, 509)), 1,
+                                       ctypes.byref(out)) == M.OK
+    nb = M.mc_negf_workspace_bytes(M.make_system(32, 500), 1)
+    assert 16000 * 16000 * (8 + 6 + 8) < nb < 16016 * 16016 * 23
 
 
 def test_host_validation_rejects_before_any_gpu_call():
