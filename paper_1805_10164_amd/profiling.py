@@ -3,6 +3,11 @@
     python -m paper_1805_10164_amd.profiling stats KERNEL_STATS_CSV --command CMD
         per-kernel calls, total / average / min / max duration and share of GPU time.
 
+    python -m paper_1805_10164_amd.profiling valu COUNTERS_CSV --command CMD [--steps-per-launch K=S]
+        per-kernel averages of the SQ / GRBM counters of one --pmc run, with the VALU issue
+        fraction SQ_ACTIVE_INST_VALU * 4 / (SIMDs * GRBM_GUI_ACTIVE per XCD) and, for kernels
+        given a work count, VALU lane-instructions per unit of work.
+
     python -m paper_1805_10164_amd.profiling traffic --fetch COUNTERS_CSV --write COUNTERS_CSV
         --calib-mib M --kernel NAME --source FILE [--command-fetch CMD --command-write CMD]
         [--grid-size ITEMS] [--match SHORT_NAME_PREFIX]
@@ -40,6 +45,38 @@ def stats(path: str, command: str) -> str:
                    f"{int(r['TotalDurationNs']) / 1e6:9.3f} {float(r['AverageNs']) / 1e3:10.1f} "
                    f"{int(r['MinNs']) / 1e3:10.1f} {int(r['MaxNs']) / 1e3:10.1f} "
                    f"{float(r['Percentage']):6.2f}")
+    return "\n".join(out) + "\n"
+
+
+SIMDS = 256 * 4  # compute units x SIMDs per CU
+XCDS = 8
+
+
+def valu(path: str, command: str, work=None) -> str:
+    """Per-kernel averages of every counter in a --pmc CSV plus the VALU issue fraction.
+    GRBM_GUI_ACTIVE is summed over the XCDs, so one XCD's busy cycles are its 1/XCDS."""
+    per = {}
+    for r in csv.DictReader(open(path)):
+        k = short_name(r["Kernel_Name"])
+        d = per.setdefault(k, {})
+        d.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    out = [f"# command: {command}", f"# source: {os.path.basename(path)}",
+           "# valu_issue = SQ_ACTIVE_INST_VALU * 4 / (1024 SIMDs * GRBM_GUI_ACTIVE / 8 XCDs)"]
+    names = sorted({c for d in per.values() for c in d})
+    out.append(f"{'kernel':44s} " + " ".join(f"{c:>20s}" for c in names) + f" {'valu_issue':>10s}")
+    for k, d in per.items():
+        avg = {c: sum(v) / len(v) for c, v in d.items()}
+        line = f"{k:44s} " + " ".join(f"{avg.get(c, float('nan')):20.4g}" for c in names)
+        g = avg.get("GRBM_GUI_ACTIVE", 0.0)
+        a = avg.get("SQ_ACTIVE_INST_VALU")
+        line += f" {a * 4 / (SIMDS * g / XCDS):10.3f}" if g and a is not None else f" {'-':>10s}"
+        out.append(line)
+    for k, units in (work or {}).items():
+        d = per.get(k)
+        if d and "SQ_INSTS_VALU" in d:
+            v = sum(d["SQ_INSTS_VALU"]) / len(d["SQ_INSTS_VALU"])
+            out.append(f"# {k}: {v * 64 / units:.1f} VALU lane-instructions per unit "
+                       f"({units:.4g} units per launch)")
     return "\n".join(out) + "\n"
 
 
@@ -98,6 +135,11 @@ def main(argv=None):
     s = sub.add_parser("stats")
     s.add_argument("csv")
     s.add_argument("--command", default="")
+    v = sub.add_parser("valu")
+    v.add_argument("csv")
+    v.add_argument("--command", default="")
+    v.add_argument("--work", action="append", default=[],
+                   help="SHORT_NAME=UNITS_PER_LAUNCH (e.g. walk steps of one launch)")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -112,6 +154,9 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.what == "stats":
         sys.stdout.write(stats(a.csv, a.command))
+    elif a.what == "valu":
+        work = {w.split("=")[0]: float(w.split("=")[1]) for w in a.work}
+        sys.stdout.write(valu(a.csv, a.command, work))
     else:
         rec = traffic(a.fetch, a.write, a.calib_mib, a.kernel, a.source, a.command_fetch,
                       a.command_write, a.grid_size, a.match)
