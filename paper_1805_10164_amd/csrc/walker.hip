@@ -22,6 +22,10 @@
 
 namespace mcnegf {
 
+// Pointer into device global memory; a per-lane pointer chosen by a select keeps its address
+// space, so table reads stay global (not flat) loads.
+typedef const __attribute__((address_space(1))) uint32_t* gtable_ptr;
+
 struct Philox4 {
     uint32_t x[4];
 };
@@ -55,6 +59,7 @@ struct WalkArgs {
     const uint32_t* tables;  // packed (thr >> 16) << 16 | alias
     const uint16_t* lows;    // thr & 0xFFFF
     int64_t pitch;
+    uint32_t pitch32;      // the same, below 2^24
     int64_t table_stride;  // entries per energy
     uint32_t n_out, N;
     uint32_t nE;      // energies in this launch
@@ -64,6 +69,7 @@ struct WalkArgs {
     uint32_t chunk, chunks_per_energy;
     uint32_t groups;  // energy groups: energy el belongs to group el % groups
     uint32_t max_steps;
+    uint32_t stage_inject;  // 1: each workgroup copies its energies' injection rows into LDS
     int64_t* tallies;
     uint32_t* status;
 };
@@ -110,13 +116,17 @@ struct Tally {
 };
 
 // One transition draw for each of the K walker slots of every lane; inactive slots compute and
-// discard.  (a[k], b[k]) are slot k's two Philox words for this step.  The K table loads are
-// independent and issued together, so a wavefront keeps K memory requests in flight per lane.
-// Counts are added for slots whose walk ends here.
+// discard.  (a[k], b[k]) are slot k's two Philox words for this step; tb[k] is the first
+// packed entry of slot k's energy.  The K table loads are independent and issued together, so
+// a wavefront keeps K memory requests in flight per lane.  A walk that ends leaves its exit
+// state in s (lead L = N, lead R = N + 1, a probe when truncated) and its step count in n; it
+// is counted when its slot is refilled (count_ended), not here.
 template <int K>
-__device__ inline void walk_steps(Step (&st)[K], const uint32_t (&w)[K], const uint32_t (&el)[K],
+__device__ inline void walk_steps(Step (&st)[K], const gtable_ptr (&tb)[K],
+                                  const uint32_t (&w)[K], const uint32_t (&el)[K],
+                                  const uint32_t (&lq)[K], const uint32_t* lds_inj,
                                   const uint32_t (&a)[K], const uint32_t (&b)[K],
-                                  const WalkArgs& A, Tally (&t)[K]) {
+                                  const WalkArgs& A) {
     const uint32_t n_out = A.n_out;
     const uint32_t thresh = (0u - n_out) % n_out;
     uint64_t m[K];
@@ -142,26 +152,44 @@ __device__ inline void walk_steps(Step (&st)[K], const uint32_t (&w)[K], const u
             rb |= __ballot(rej[k]);
         }
     }
-    uint32_t c[K], ent[K];
-    size_t at[K];
+    // entry offset within the energy's table: row * pitch + bucket, both below 2^24 and the
+    // sum below 2^32 (at most 16320 rows of pitch 16320)
+    // Only active slots read: a walk's first step (n = 0, the injection row) from the copy of
+    // that row in LDS when the launch staged it, every other step from the table in memory.
+    // The two kinds of read go to separate registers (one register for both would make the
+    // second wait for the first) and are merged by a select once all K are issued.
+    uint32_t c[K], off[K], ent[K], eg[K], el_[K];
+    bool inj[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         c[k] = (uint32_t)(m[k] >> 32);
-        at[k] = (size_t)el[k] * A.table_stride + (size_t)st[k].s * A.pitch + c[k];
-        ent[k] = A.tables[at[k]];
+        off[k] = __umul24(st[k].s, A.pitch32) + c[k];
+        inj[k] = A.stage_inject && st[k].n == 0u;
+        eg[k] = 0u;
+        el_[k] = 0u;
     }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (st[k].active && !inj[k]) eg[k] = tb[k][off[k]];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (st[k].active && inj[k]) el_[k] = lds_inj[lq[k] + c[k]];
+#pragma unroll
+    for (int k = 0; k < K; ++k) ent[k] = inj[k] ? el_[k] : eg[k];
     bool keep[K], tie[K];
-    uint64_t tb = 0ull;
+    uint64_t tb_any = 0ull;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        keep[k] = (b[k] >> kAliasIdxBits) < (ent[k] >> kAliasIdxBits);
-        tie[k] = st[k].active && (b[k] >> kAliasIdxBits) == (ent[k] >> kAliasIdxBits);
-        tb |= __ballot(tie[k]);
+        // high 16 threshold bits: b keeps the bucket below them, ties read the low 16 bits
+        keep[k] = b[k] < (ent[k] & ~kAliasIdxMask);
+        tie[k] = st[k].active && ((b[k] ^ ent[k]) >> kAliasIdxBits) == 0u;
+        tb_any |= __ballot(tie[k]);
     }
-    if (tb != 0ull) {  // rare (probability 2^-16 per lane and step); uniform branch
+    if (tb_any != 0ull) {  // rare (probability 2^-16 per lane and step); uniform branch
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const uint32_t lo = tie[k] ? (uint32_t)A.lows[at[k]] : 0u;
+            const uint32_t lo =
+                tie[k] ? (uint32_t)A.lows[(size_t)el[k] * A.table_stride + off[k]] : 0u;
             keep[k] = tie[k] ? (b[k] & kAliasIdxMask) < lo : keep[k];
         }
     }
@@ -170,18 +198,23 @@ __device__ inline void walk_steps(Step (&st)[K], const uint32_t (&w)[K], const u
         const uint32_t nxt = keep[k] ? c[k] : (ent[k] & kAliasIdxMask);
         const uint32_t n1 = st[k].n + 1;
         const bool active = st[k].active;
-        const bool absorbed = active && nxt >= A.N;
-        const bool trunc = active && !absorbed && n1 >= A.max_steps;
-        const bool ends = absorbed || trunc;
-        t[k].cL += (absorbed && nxt == A.N) ? 1u : 0u;
-        t[k].cR += (absorbed && nxt != A.N) ? 1u : 0u;
-        t[k].tr += trunc ? 1u : 0u;
-        t[k].s1 += ends ? (uint64_t)n1 : 0ull;
-        t[k].s2 += ends ? (uint64_t)n1 * n1 : 0ull;
-        st[k].s = (active && !ends) ? nxt : st[k].s;
+        // absorbed at a lead (nxt >= N) or truncated at max_steps
+        const bool ends = nxt >= A.N || n1 >= A.max_steps;
+        st[k].s = active ? nxt : st[k].s;
         st[k].n = active ? n1 : st[k].n;
         st[k].active = active && !ends;
     }
+}
+
+// Adds the walk that ended in a slot (done: the slot holds one that is not counted yet) to
+// the slot's counts: exit by its final state, its step count and squared step count.
+__device__ inline void count_ended(Tally& t, bool done, const Step& s, uint32_t N) {
+    const uint64_t n = done ? (uint64_t)s.n : 0ull;
+    t.cL += (done && s.s == N) ? 1u : 0u;
+    t.cR += (done && s.s > N) ? 1u : 0u;
+    t.tr += (done && s.s < N) ? 1u : 0u;
+    t.s1 += n;
+    t.s2 += n * n;
 }
 
 // Adds a slot's counts for energy el to the block's LDS tallies (per-lane; called in
@@ -207,27 +240,39 @@ __device__ inline void tally_flush(unsigned long long* lds_tally, uint32_t el, c
 // current energy and added to LDS when it changes energy.
 template <int K>
 __global__ void __launch_bounds__(256) walk_kernel(WalkArgs A) {
-    extern __shared__ unsigned long long lds_tally[];  // [nE][5]
+    // LDS: tallies [nE][5], then (stage_inject) the injection row of each of the group's
+    // energies, [nq][n_out] packed entries
+    extern __shared__ unsigned long long lds_tally[];
+    uint32_t* lds_inj = reinterpret_cast<uint32_t*>(lds_tally + (size_t)A.nE * MCNEGF_TALLY_N);
     const int lane = threadIdx.x & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint32_t nE = A.nE;
-    for (uint32_t i = threadIdx.x; i < nE * MCNEGF_TALLY_N; i += blockDim.x) lds_tally[i] = 0ull;
-    __syncthreads();
     const uint32_t G = A.groups;
     const uint32_t grp = blockIdx.x % G;
+    const uint32_t nq = (nE - grp + G - 1) / G;  // energies of this group
+    const uint32_t inject_row = A.N + (A.tag & 1u);
+    for (uint32_t i = threadIdx.x; i < nE * MCNEGF_TALLY_N; i += blockDim.x) lds_tally[i] = 0ull;
+    if (A.stage_inject) {
+        for (uint32_t q = 0; q < nq; ++q) {
+            const uint32_t* row = A.tables + (size_t)(grp + q * G) * A.table_stride +
+                                  (size_t)inject_row * A.pitch32;
+            for (uint32_t i = threadIdx.x; i < A.n_out; i += blockDim.x)
+                lds_inj[q * A.n_out + i] = row[i];
+        }
+    }
+    __syncthreads();
     const uint32_t wpb = blockDim.x >> 6;
     const uint32_t waves = __builtin_amdgcn_readfirstlane((gridDim.x / G) * wpb);
     const uint32_t lw =
         __builtin_amdgcn_readfirstlane((blockIdx.x / G) * wpb + (threadIdx.x >> 6));
-    const uint32_t nq = (nE - grp + G - 1) / G;  // energies of this group
     const uint32_t total = nq * A.chunks_per_energy;
-    const uint32_t inject_row = A.N + (A.tag & 1u);
 
     // the wavefront's cursor: chunk id, its energy, next walker index and end
-    uint32_t cid = lw, cel = 0, next = 0, wend = 0;
+    uint32_t cid = lw, cel = 0, clq = 0, next = 0, wend = 0;
     auto open_chunk = [&](uint32_t id) {
         const uint32_t q = id / A.chunks_per_energy;
         cel = grp + q * G;
+        clq = q * A.n_out;
         next = A.wbegin + (id - q * A.chunks_per_energy) * A.chunk;
         wend = min(next + A.chunk, A.wend);
     };
@@ -235,11 +280,14 @@ __global__ void __launch_bounds__(256) walk_kernel(WalkArgs A) {
 
     Step st[K];
     uint32_t w[K], el[K], tel[K];  // walker index, its energy, energy of the counts in t
+    gtable_ptr tb[K];              // the packed table of energy el
+    uint32_t lq[K];                // the LDS offset of energy el's injection row
     Tally t[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         st[k] = Step{inject_row, 0u, false};
-        w[k] = el[k] = tel[k] = 0u;
+        w[k] = el[k] = tel[k] = lq[k] = 0u;
+        tb[k] = (gtable_ptr)A.tables;
         t[k] = Tally{0u, 0u, 0u, 0ull, 0ull};
     }
     uint32_t trunc_any = 0;
@@ -260,8 +308,12 @@ __global__ void __launch_bounds__(256) walk_kernel(WalkArgs A) {
             for (int k = 0; k < K; ++k) {
                 const uint32_t before = base + __popcll(need[k] & lt_mask);
                 const bool take = !st[k].active && before < avail;
+                // the walk this slot finished (a slot that never walked has n = 0) is counted
+                // for its energy el[k] == tel[k] before the slot moves on
+                count_ended(t[k], take && st[k].n != 0u, st[k], A.N);
                 const bool flush = take && cel != tel[k];
                 if (__ballot(flush) != 0ull) {
+                    trunc_any |= flush ? t[k].tr : 0u;
                     if (flush) tally_flush(lds_tally, tel[k], t[k]);
                     t[k].cL = flush ? 0u : t[k].cL;
                     t[k].cR = flush ? 0u : t[k].cR;
@@ -272,6 +324,8 @@ __global__ void __launch_bounds__(256) walk_kernel(WalkArgs A) {
                 }
                 w[k] = take ? next + before : w[k];
                 el[k] = take ? cel : el[k];
+                lq[k] = take ? clq : lq[k];
+                tb[k] = take ? (gtable_ptr)(A.tables + (size_t)cel * A.table_stride) : tb[k];
                 st[k].s = take ? inject_row : st[k].s;
                 st[k].n = take ? 0u : st[k].n;
                 st[k].active = st[k].active || take;
@@ -299,13 +353,16 @@ __global__ void __launch_bounds__(256) walk_kernel(WalkArgs A) {
             a1[k] = x.x[2];
             b1[k] = x.x[3];
         }
-        walk_steps<K>(st, w, el, a0, b0, A, t);
-        walk_steps<K>(st, w, el, a1, b1, A, t);
-#pragma unroll
-        for (int k = 0; k < K; ++k) trunc_any |= t[k].tr;
+        walk_steps<K>(st, tb, w, el, lq, lds_inj, a0, b0, A);
+        walk_steps<K>(st, tb, w, el, lq, lds_inj, a1, b1, A);
     }
+    // walks that ended after their slot's last refill
 #pragma unroll
-    for (int k = 0; k < K; ++k) tally_flush(lds_tally, tel[k], t[k]);
+    for (int k = 0; k < K; ++k) {
+        count_ended(t[k], st[k].n != 0u, st[k], A.N);
+        trunc_any |= t[k].tr;
+        tally_flush(lds_tally, tel[k], t[k]);
+    }
     __syncthreads();
     unsigned long long* gt = reinterpret_cast<unsigned long long*>(A.tallies);
     for (uint32_t i = threadIdx.x; i < nE * MCNEGF_TALLY_N; i += blockDim.x) {
@@ -334,7 +391,10 @@ hipError_t launch_walk(const mcnegf_kernel& k, uint64_t seed, uint32_t tag, uint
     if ((err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
         hipSuccess)
         return err;
-    const size_t lds = (size_t)kMaxEnergiesPerLaunch * MCNEGF_TALLY_N * 8;
+    // A workgroup copies the injection rows of its group's energies into LDS (a walk's first
+    // step then reads LDS, not memory) while they take at most kInjectLdsBytes.
+    constexpr size_t kInjectLdsBytes = 32768;
+    const size_t lds = (size_t)kMaxEnergiesPerLaunch * MCNEGF_TALLY_N * 8 + kInjectLdsBytes;
     // persistent grid: no more workgroups than can be resident at once
     int per_cu = 0;
     if ((err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, lds)) != hipSuccess)
@@ -347,6 +407,7 @@ hipError_t launch_walk(const mcnegf_kernel& k, uint64_t seed, uint32_t tag, uint
         A.tables = k.alias + (size_t)e_off * A.table_stride;
         A.lows = k.alias_lo + (size_t)e_off * A.table_stride;
         A.pitch = k.alias_pitch;
+        A.pitch32 = (uint32_t)k.alias_pitch;
         A.n_out = (uint32_t)k.n_out;
         A.N = (uint32_t)k.N;
         A.nE = nE;
@@ -372,10 +433,14 @@ hipError_t launch_walk(const mcnegf_kernel& k, uint64_t seed, uint32_t tag, uint
         A.max_steps = max_steps;
         A.tallies = tallies + (size_t)e_off * MCNEGF_TALLY_N;
         A.status = k.status;
+        const size_t inj_bytes = (size_t)nq * (size_t)k.n_out * 4;
+        A.stage_inject = inj_bytes <= kInjectLdsBytes ? 1u : 0u;
+        const size_t lds_launch =
+            (size_t)nE * MCNEGF_TALLY_N * 8 + (A.stage_inject ? inj_bytes : 0);
         {
             MCNEGF_TIMED("walk_kernel", s);
             hipLaunchKernelGGL(walk_kernel<kWalkSlots>, dim3((unsigned)(bpg * A.groups)),
-                               dim3(256), (size_t)nE * MCNEGF_TALLY_N * 8, s, A);
+                               dim3(256), lds_launch, s, A);
         }
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
