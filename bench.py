@@ -52,6 +52,10 @@ def parse():
                     help="skip the gradient measurement on the differentiation workload")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched uneven workload (64 realizations x 256 energies)")
+    ap.add_argument("--no-scale", action="store_true",
+                    help="skip the W=32 x L=500 (N = 16000) batch of energies")
+    ap.add_argument("--only", choices=["grad", "batched", "scale"], default=None,
+                    help="run only this leg and print its object (profiling; no top-level metric)")
     ap.add_argument("--batch-budget-gb", type=float, default=160.0,
                     help="device memory for one wave of build workspaces in the batched leg")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -381,6 +385,121 @@ def time_to_1pct(p: Problem, torch, seed, walk_on):
             "direct_ms": 1e3 * float(np.median(dir_t))}
 
 
+def scale_bench(torch, dev, steps, warmup, with_cpu, seed):
+    """The W=32 x L=500 wire (N = 16000, the paper's 32 x 32 blocks): one batch of SCALE_BATCH
+    of its 512 energies (every 16th) per build, as the full energy grid is processed: build,
+    1e7 walks per energy, MC and DIRECT currents, all FP64.  One energy's tables are 1 GB, so
+    here every walk step reads memory (no table stays in L2)."""
+    wl = inputs.SCALE_W32_L500
+    Eall, wall_w = M.energy_grid(wl.emin, wl.emax, wl.n_energies)
+    n_batches = wl.n_energies // inputs.SCALE_BATCH
+    pick = np.arange(0, wl.n_energies, n_batches)
+    E, w = Eall[pick], wall_w[pick]
+    nE, nw = len(E), wl.walkers_per_energy
+    sysm = M.make_system(wl.W, wl.L, wl.t, wl.lead_model, wl.gamma_l, wl.delta_lead)
+    V = torch.tensor(inputs.onsite(wl), device=dev)
+    g = torch.tensor(inputs.dephasing(wl), device=dev)
+    tE, tw = torch.tensor(E, device=dev), torch.tensor(w, device=dev)
+    ws = M.allocate_workspace(sysm, nE, dev)
+    tal = torch.zeros((nE, M.TALLY_N), dtype=torch.int64, device=dev)
+    T, sg = torch.empty(nE, dtype=torch.float64, device=dev), torch.empty(nE, dtype=torch.float64,
+                                                                          device=dev)
+    Td, sgd = torch.empty_like(T), torch.empty_like(T)
+    out = torch.zeros((2, 2), dtype=torch.float64, device=dev)
+    holder = {}
+
+    def one_batch():
+        k = M.mc_negf_build_kernel(sysm, V, g, tE, ws)
+        tal.zero_()
+        M.mc_negf_walk(k, seed, 0, 0, 0, nw, 1_000_000, tal)
+        M.mc_negf_current_async(k, 0, 0, tal, tw, T, sg, out[0])
+        M.mc_negf_current_async(k, 1, 0, None, tw, Td, sgd, out[1])
+        holder["k"] = k
+
+    for _ in range(max(1, warmup)):
+        one_batch()
+    torch.cuda.synchronize()
+    # one timing window per batch: a batch launches about 270 kernels (the factorization of
+    # a 16000-row system is one launch per 64-column block) and a window records 512
+    records = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        with M.LaunchTimes() as lt:
+            one_batch()
+        if lt.dropped:
+            raise RuntimeError("launch timer dropped records")
+        records += lt.records
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    lt = M.LaunchTimes()
+    lt.records = records
+    k = holder["k"]
+    o = out.cpu().numpy()
+    flags = M.mc_negf_status(k)
+    ta = tal.cpu().numpy()
+    walk_steps = int(ta[:, M.TALLY_STEPS].sum())
+    names = sorted(set(n for n, _ in lt.records))
+    per_kernel = {n: {"launches": lt.count(n) // steps, "ms_per_batch": lt.total_ms(n) / steps}
+                  for n in names}
+    walk_ms = lt.total_ms("walk_kernel") / steps
+    chol_ms = lt.total_ms("cholesky_kernel") / steps
+    chol_flop = nE * (wl.N ** 3 / 3.0 + 2.0 * wl.N * wl.N)
+    res = {
+        "workload": f"W={wl.W} L={wl.L} N={wl.N}, eta={wl.eta}t, disorder U[-{wl.disorder},"
+                    f"{wl.disorder}]t, {wl.n_energies} energies in [{wl.emin},{wl.emax}]t in "
+                    f"{n_batches} batches of {nE} (timed: every {n_batches}th energy), "
+                    f"{nw} walkers/energy",
+        "ms_per_batch": 1e3 * wall,
+        "projected_s_all_energies": wall * n_batches,
+        "walk_steps_per_batch": walk_steps,
+        "walker_kernel_steps_per_s": walk_steps / (walk_ms * 1e-3) if walk_ms else None,
+        "mean_steps_per_walker": float(ta[:, M.TALLY_STEPS].sum() / ta[:, :3].sum()),
+        "truncated": int(ta[:, M.TALLY_TRUNC].sum()),
+        "I_direct_batch": float(o[1, 0]), "I_mc_batch": float(o[0, 0]),
+        "sigma_I_mc_batch": float(o[0, 1]),
+        "mc_minus_direct_in_sigma": float((o[0, 0] - o[1, 0]) / o[0, 1]) if o[0, 1] else None,
+        "status_flags": int(flags),
+        "per_kernel": per_kernel,
+        "rooflines": {
+            "walk_kernel": {"bound": "hbm", "achieved": walk_steps * ALIAS_ENTRY_BYTES / 1e9 /
+                            (walk_ms * 1e-3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": walk_steps * ALIAS_ENTRY_BYTES / 1e9 / (walk_ms * 1e-3) /
+                            HBM_PEAK_GBS,
+                            "algorithmic_per_launch": walk_steps * ALIAS_ENTRY_BYTES,
+                            "avg_launch_ms": walk_ms,
+                            "traffic": measured_traffic("walk_kernel", "scale_W32_L500")},
+            "cholesky_kernel": {"bound": "mfma", "achieved": chol_flop / 1e12 / (chol_ms * 1e-3),
+                                "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                "frac": chol_flop / 1e12 / (chol_ms * 1e-3) /
+                                FP64_VALU_PEAK_TFLOPS},
+        },
+    }
+    j = 1  # an energy of the batch away from the window's edge
+    T_gpu = float(Td[j].item())
+    del holder, k, ws
+    torch.cuda.empty_cache()
+    if with_cpu:
+        # the oracle's T_eff at one energy of the batch: every column of G by a sparse LU,
+        # then the dense probe system
+        from oracle import columns as OC
+        import threadpoolctl
+        blas = max((i["num_threads"] for i in threadpoolctl.threadpool_info()), default=1)
+        t0 = time.perf_counter()
+        ora = OC.SparseEnergy(E[j], wl.W, wl.L, wl.t, inputs.onsite(wl), inputs.dephasing(wl),
+                              wl.lead_model, wl.delta_lead, wl.gamma_l)
+        T_ref = ora.effective_transmission()
+        dt = time.perf_counter() - t0
+        del ora
+        res["cpu_baseline"] = {
+            "value": 1.0 / dt, "unit": "energies/s (DIRECT T_eff)", "cores": blas,
+            "kind": "oracle",
+            "sample": f"energy {E[j]:.6f}t (1 of {wl.n_energies}): sparse LU columns (one "
+                      f"thread) + dense probe solve ({blas} BLAS threads), {dt:.1f} s",
+            "T_oracle": T_ref, "T_gpu_direct": T_gpu,
+            "rel_err_direct": abs(T_gpu - T_ref) / abs(T_ref)}
+    return res
+
+
 def cpu_baseline(wl: inputs.Workload, seed: int):
     """The oracle on the host cores for a bounded sample of the workload: dense LAPACK
     solves plus the C walker (the paper's cumulative-sum sampler), 8 of the 256 energies
@@ -404,6 +523,18 @@ def cpu_baseline(wl: inputs.Workload, seed: int):
                       f"{steps} steps in {dt:.1f} s"}
 
 
+def calibration_copy(torch, dev, mib):
+    """One plain device copy of `mib` MiB (read and written): the reference dispatch that
+    scales the HBM byte counters of a profiled run."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.neg(src, out=dst)  # reads and writes n * 8 bytes
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -412,6 +543,19 @@ def main():
     import torch
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    if args.only:
+        if args.calib_copy_mb > 0:
+            calibration_copy(torch, dev, args.calib_copy_mb)
+        with_cpu = not args.no_cpu_baseline
+        if args.only == "grad":
+            leg = grad_bench(torch, dev, args.steps, args.warmup, with_cpu)
+        elif args.only == "batched":
+            leg = batched_bench(torch, dev, args.steps, args.warmup, args.batch_budget_gb,
+                                inputs.RNG_SEED)
+        else:
+            leg = scale_bench(torch, dev, args.steps, args.warmup, with_cpu, inputs.RNG_SEED)
+        print(json.dumps({args.only: leg}), flush=True)
+        return
     base = inputs.WIRE_W10_L100
     walkers = args.walkers or base.walkers_per_energy
     etas = [float(x) for x in args.etas.split(",")] if args.etas else list(inputs.WIRE_ETAS)
@@ -424,13 +568,7 @@ def main():
             run_step(p, walkers, seed, walk_on)
     torch.cuda.synchronize()
     if args.calib_copy_mb > 0:
-        n = args.calib_copy_mb * (1 << 20) // 8
-        src = torch.ones(n, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        torch.neg(src, out=dst)  # reads and writes n * 8 bytes
-        torch.cuda.synchronize()
-        del src, dst
+        calibration_copy(torch, dev, args.calib_copy_mb)
 
     t0 = time.perf_counter()
     with M.LaunchTimes() as lt:
@@ -500,6 +638,10 @@ def main():
     if not args.no_batched:
         line["batched"] = batched_bench(torch, dev, args.steps, args.warmup, args.batch_budget_gb,
                                         seed)
+        torch.cuda.empty_cache()
+    if not args.no_scale:
+        line["scale"] = scale_bench(torch, dev, min(args.steps, 2), args.warmup,
+                                    not args.no_cpu_baseline, seed)
     print(json.dumps(line), flush=True)
 
 
