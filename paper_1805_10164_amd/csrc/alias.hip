@@ -107,29 +107,49 @@ hipError_t launch_lead_terms(const mcnegf_kernel& k, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- block reductions (BT threads)
-// Sums and exclusive scans in a fixed order (lanes within a wavefront by shuffles, then the
+// Sums and exclusive scans in a fixed order (lanes within a wavefront by DPP, then the
 // wavefronts in order through LDS): two barriers each instead of one per tree level.
-__device__ inline double wave_incl_scan(double v, int lane) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const double t = __shfl_up(v, o, 64);
-        v = lane >= o ? v + t : v;
-    }
+//
+// Inclusive wavefront scan by data-parallel primitives: row_shr:1, 2, 4, 8 scan each row of
+// 16 lanes; row_bcast:15 adds the last lane of rows 0 and 2 to rows 1 and 3; row_bcast:31
+// adds lane 31 to rows 2 and 3.  A lane without a source (first lanes of a row, rows outside
+// the row mask) reads the 0 given as `old`.  Every lane of the wavefront must be active.
+template <int CTRL, int ROW_MASK>
+__device__ inline int dpp_or_zero(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xF, false);
+}
+template <int CTRL, int ROW_MASK>
+__device__ inline double dpp_or_zero_d(double v) {
+    const int lo = dpp_or_zero<CTRL, ROW_MASK>(__double2loint(v));
+    const int hi = dpp_or_zero<CTRL, ROW_MASK>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
+__device__ inline double wave_incl_scan(double v) {
+    v += dpp_or_zero_d<kDppRowShr1, 0xF>(v);
+    v += dpp_or_zero_d<kDppRowShr2, 0xF>(v);
+    v += dpp_or_zero_d<kDppRowShr4, 0xF>(v);
+    v += dpp_or_zero_d<kDppRowShr8, 0xF>(v);
+    v += dpp_or_zero_d<kDppRowBcast15, 0xA>(v);
+    v += dpp_or_zero_d<kDppRowBcast31, 0xC>(v);
     return v;
 }
-__device__ inline int wave_incl_scan_int(int v, int lane) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(v, o, 64);
-        v = lane >= o ? v + t : v;
-    }
+__device__ inline int wave_incl_scan_int(int v) {
+    v += dpp_or_zero<kDppRowShr1, 0xF>(v);
+    v += dpp_or_zero<kDppRowShr2, 0xF>(v);
+    v += dpp_or_zero<kDppRowShr4, 0xF>(v);
+    v += dpp_or_zero<kDppRowShr8, 0xF>(v);
+    v += dpp_or_zero<kDppRowBcast15, 0xA>(v);
+    v += dpp_or_zero<kDppRowBcast31, 0xC>(v);
     return v;
 }
 
 template <int BT>
 __device__ inline double block_sum(double v, double* red) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const double incl = wave_incl_scan(v, lane);
+    const double incl = wave_incl_scan(v);
     if (lane == 63) red[wv] = incl;
     __syncthreads();
     double r = 0.0;
@@ -144,8 +164,8 @@ template <int BT>
 __device__ inline void block_scan2(double& xd, int& xi, double& totd, int& toti, double* sd,
                                    int* si) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const double id = wave_incl_scan(xd, lane);
-    const int ii = wave_incl_scan_int(xi, lane);
+    const double id = wave_incl_scan(xd);
+    const int ii = wave_incl_scan_int(xi);
     if (lane == 63) {
         sd[wv] = id;
         si[wv] = ii;
@@ -352,6 +372,10 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
             al = i;
         } else {
             thr = (uint32_t)(q * 4294967296.0);
+        }
+        if ((unsigned)al >= (unsigned)n) {  // never for a consistent row; keeps walks in range
+            al = i;
+            atomicOr(a.status, MCNEGF_FLAG_NONFINITE);
         }
         out[i] = (thr & ~kAliasIdxMask) | (uint32_t)al;
         out_lo[i] = (uint16_t)(thr & kAliasIdxMask);
