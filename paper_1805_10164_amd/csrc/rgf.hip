@@ -11,109 +11,115 @@
 // The two sweeps are sequential over slices and run as one wavefront per (energy,
 // direction); the diagonal blocks are then independent and run as one wavefront each.
 //
-// Block inverse on one wavefront: lane i < W holds row i of the augmented [X | I] in
-// registers; Gauss-Jordan elimination with partial pivoting chooses, at column p, the
-// not-yet-used row of largest |x_ip| (ties: lowest lane); rows are never swapped, so at
-// the end lane i holds row r_i of X^{-1}, r_i being the column it was pivot for.
+// Block inverse on one wavefront (W <= 16): the augmented [X | I] is spread over the 64 lanes,
+// lane l = i + 16 q holding row i at the columns j = q + 4 m (m < M = (2W + 3) / 4).
+// Gauss-Jordan elimination with partial pivoting chooses, at column p, the not-yet-used row of
+// largest |x_ip| (ties: lowest row); rows are never swapped, so at the end row i holds row r_i
+// of X^{-1}, r_i being the column it was pivot for.  Each lane updates its own M entries, so a
+// pivot step costs a few cross-lane reads and M complex multiply-adds per lane.
 #include "common.h"
 
 namespace mcnegf {
 
+template <int W>
+struct Narrow {
+    static constexpr int M = (2 * W + 3) / 4;  // entries per lane
+};
+
+// One step of an argmax over each row of 16 lanes: compare with the lane CTRL rotates in
+// (DPP row_ror); every lane must be active.
+template <int CTRL>
+__device__ inline void argmax_step(double& mag, int& idx) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(mag), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(mag), CTRL, 0xF, 0xF, false);
+    const int oi = __builtin_amdgcn_mov_dpp(idx, CTRL, 0xF, 0xF, false);
+    const double om = __hiloint2double(hi, lo);
+    const bool take = (om > mag) | ((om == mag) & (oi < idx));  // no short-circuit branches
+    mag = take ? om : mag;
+    idx = take ? oi : idx;
+}
+// Index of the largest mag in each row of 16 lanes (ties: lowest index), in every lane of it:
+// rotations by 8, 4, 2, 1 combine all 16 values under a total order.
+__device__ inline int argmax_row16(double mag, int idx) {
+    argmax_step<0x128>(mag, idx);  // row_ror:8
+    argmax_step<0x124>(mag, idx);  // row_ror:4
+    argmax_step<0x122>(mag, idx);  // row_ror:2
+    argmax_step<0x121>(mag, idx);  // row_ror:1
+    return idx;
+}
+
+__device__ inline double2 shfl_c(double2 v, int src) {
+    return cmk(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
+}
 __device__ inline double readlane_d(double v, int lane) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
     return __hiloint2double(hi, lo);
 }
 
-// Largest mag over lanes 0..15 (every lane of each 16-lane group gets its group's winner).
-__device__ inline int argmax16(double mag, int lane) {
-    int idx = lane;
-#pragma unroll
-    for (int off = 8; off >= 1; off >>= 1) {
-        const double om = __shfl_xor(mag, off, 64);
-        const int oi = __shfl_xor(idx, off, 64);
-        if (om > mag || (om == mag && oi < idx)) {
-            mag = om;
-            idx = oi;
-        }
-    }
-    return idx;
-}
-
-// Inverts the W x W matrix whose row i is a[0..W-1] of lane i (lanes >= W hold zeros).
-// On return a[W..2W-1] of lane i is row `rank` of the inverse.  Returns false when a pivot
-// is zero or not finite.
+// Inverts the W x W matrix X held as described above (row i < W of [X | I]; rows >= W zero).
+// On return row i's entries at columns W + c are (X^{-1})[rank][c].  Returns false when a
+// pivot is zero or not finite.  Every lane of the wavefront must be active.
 template <int W>
-__device__ inline bool gj_invert(double2 (&a)[2 * W], int lane, int& rank) {
-    bool used = lane >= W;
+__device__ inline bool gj_invert(double2 (&a)[Narrow<W>::M], int i, int q, int& rank) {
+    constexpr int M = Narrow<W>::M;
+    bool used = i >= W;
     bool ok = true;
     rank = 0;
-#pragma unroll
+    // fully unrolled: the column index p selects registers, never a memory array
+#pragma clang loop unroll(full)
     for (int p = 0; p < W; ++p) {
-        const double mag = used ? -1.0 : cabs2(a[p]);
-        const int r = __builtin_amdgcn_readfirstlane(argmax16(mag, lane));
-        double2 piv[2 * W];
+        const int qp = p & 3, mp = p >> 2;  // column p: lanes of group qp, entry mp
+        const double mag = used ? -1.0 : cabs2(a[mp]);
+        const int r = __builtin_amdgcn_readlane(argmax_row16(mag, i), 16 * qp);
+        // the pivot row's entries at this lane's columns, and this row's entry in column p
+        double2 piv[M];
 #pragma unroll
-        for (int j = p; j < 2 * W; ++j)
-            piv[j] = cmk(readlane_d(a[j].x, r), readlane_d(a[j].y, r));
-        const double pm = cabs2(piv[p]);
+        for (int m = 0; m < M; ++m) piv[m] = shfl_c(a[m], r + 16 * q);
+        const double2 f = shfl_c(a[mp], i + 16 * qp);
+        const double2 pp = cmk(readlane_d(a[mp].x, r + 16 * qp), readlane_d(a[mp].y, r + 16 * qp));
+        const double pm = cabs2(pp);
         if (!(pm > 0.0) || !isfinite(pm)) ok = false;
-        const double2 pinv = crecip(piv[p]);
+        const double2 pinv = crecip(pp);
+        // per-lane choices as selects: every lane stays active for the next pivot's cross-lane
+        // reads
 #pragma unroll
-        for (int j = p; j < 2 * W; ++j) piv[j] = cmul(piv[j], pinv);
-        if (lane == r) {
-#pragma unroll
-            for (int j = p; j < 2 * W; ++j) a[j] = piv[j];
-            used = true;
-            rank = p;
-        } else {
-            const double2 f = a[p];
-#pragma unroll
-            for (int j = p; j < 2 * W; ++j) cfms(a[j], f, piv[j]);
+        for (int m = 0; m < M; ++m) {
+            const int j = q + 4 * m;
+            const double2 pj = cmul(piv[m], pinv);
+            double2 u = a[m];
+            cfms(u, f, pj);
+            // component selects (a select of whole double2 values goes through memory)
+            const bool upd = j >= p && j < 2 * W, piv_row = i == r;
+            a[m].x = upd ? (piv_row ? pj.x : u.x) : a[m].x;
+            a[m].y = upd ? (piv_row ? pj.y : u.y) : a[m].y;
         }
+        used = used || i == r;
+        rank = i == r ? p : rank;
     }
     return ok;
 }
 
-// Row i (< W) of A_k for energy E, in a[0..W-1]; identity row in a[W..2W-1]; Vi, gi are the
-// onsite energy and dephasing rate of site (k, i).
+// This lane's entries of row i of [A_k | I] for energy E (A_k = E - H_kk - Sigma_B,kk - the
+// lead self-energy on an end slice); Vi, gi are the onsite energy and dephasing rate of site
+// (k, i).
 template <int W>
-__device__ inline void diag_block_row_v(double2 (&a)[2 * W], int i, int k, int L, double E,
-                                        double t, double Vi, double gi,
-                                        const double2* __restrict__ sig) {
+__device__ inline void diag_block_entries(double2 (&a)[Narrow<W>::M], int i, int q, int k, int L,
+                                          double E, double t, double Vi, double gi,
+                                          const double2* __restrict__ sig) {
 #pragma unroll
-    for (int j = 0; j < 2 * W; ++j) a[j] = cmk(0.0, 0.0);
-    if (i >= W) return;
-#pragma unroll
-    for (int j = 0; j < W; ++j) {
+    for (int m = 0; m < Narrow<W>::M; ++m) {
+        const int j = q + 4 * m;
         double2 v = cmk(0.0, 0.0);
-        if (j == i) v = cmk(E - Vi, 0.5 * gi);
-        if (j == i - 1 || j == i + 1) v = cmk(t, 0.0);
-        if (k == 0) v = csub(v, sig[i * W + j]);
-        if (k == L - 1) v = csub(v, sig[i * W + j]);
-        a[j] = v;
-        a[W + j] = cmk(j == i ? 1.0 : 0.0, 0.0);
-    }
-}
-
-template <int W>
-__device__ inline void diag_block_row(double2 (&a)[2 * W], int i, int k, int L, double E, double t,
-                                      const double* __restrict__ onsite,
-                                      const double* __restrict__ gamma,
-                                      const double2* __restrict__ sig) {
-#pragma unroll
-    for (int j = 0; j < 2 * W; ++j) a[j] = cmk(0.0, 0.0);
-    if (i >= W) return;
-    const int site = k * W + i;
-#pragma unroll
-    for (int j = 0; j < W; ++j) {
-        double2 v = cmk(0.0, 0.0);
-        if (j == i) v = cmk(E - onsite[site], 0.5 * gamma[site]);
-        if (j == i - 1 || j == i + 1) v = cmk(t, 0.0);
-        if (k == 0) v = csub(v, sig[i * W + j]);
-        if (k == L - 1) v = csub(v, sig[i * W + j]);
-        a[j] = v;
-        a[W + j] = cmk(j == i ? 1.0 : 0.0, 0.0);
+        if (i < W && j < W) {
+            if (j == i) v = cmk(E - Vi, 0.5 * gi);
+            if (j == i - 1 || j == i + 1) v = cmk(t, 0.0);
+            if (k == 0) v = csub(v, sig[i * W + j]);
+            if (k == L - 1) v = csub(v, sig[i * W + j]);
+        } else if (i < W && j < 2 * W) {
+            v = cmk(j - W == i ? 1.0 : 0.0, 0.0);
+        }
+        a[m] = v;
     }
 }
 
@@ -125,9 +131,11 @@ __global__ void __launch_bounds__(64) rgf_sweep_kernel(const double* __restrict_
                                                        double t, double2* __restrict__ gL,
                                                        double2* __restrict__ gR,
                                                        uint32_t* __restrict__ status) {
+    constexpr int M = Narrow<W>::M;
     const int e = blockIdx.x >> 1;
     const int dir = blockIdx.x & 1;
     const int lane = threadIdx.x;
+    const int i = lane & 15, q = lane >> 4;
     __shared__ double2 prev[W][W];
     const double E = energies[e];
     const double2* sig = sigma + (size_t)e * W * W;
@@ -135,7 +143,7 @@ __global__ void __launch_bounds__(64) rgf_sweep_kernel(const double* __restrict_
     const double t2 = t * t;
     bool ok = true;
     // the onsite energy and dephasing rate of this lane's site, loaded one slice ahead
-    const int i_site = lane < W ? lane : 0;
+    const int i_site = i < W ? i : 0;
     const int k_first = dir == 0 ? 0 : L - 1;
     double Vn = onsite[k_first * W + i_site], gn = gamma[k_first * W + i_site];
     for (int s = 0; s < L; ++s) {
@@ -146,21 +154,27 @@ __global__ void __launch_bounds__(64) rgf_sweep_kernel(const double* __restrict_
             Vn = onsite[kn * W + i_site];
             gn = gamma[kn * W + i_site];
         }
-        double2 a[2 * W];
-        diag_block_row_v<W>(a, lane, k, L, E, t, Vi, gi, sig);
-        if (s > 0 && lane < W) {
+        double2 a[M];
+        diag_block_entries<W>(a, i, q, k, L, E, t, Vi, gi, sig);
+        if (s > 0 && i < W) {
 #pragma unroll
-            for (int j = 0; j < W; ++j) a[j] = csub(a[j], cscale(prev[lane][j], t2));
+            for (int m = 0; m < M; ++m) {
+                const int j = q + 4 * m;
+                if (j < W) a[m] = csub(a[m], cscale(prev[i][j], t2));
+            }
         }
         __syncthreads();
         int rank;
-        ok &= gj_invert<W>(a, lane, rank);
-        if (lane < W) {
+        ok &= gj_invert<W>(a, i, q, rank);
+        if (i < W) {
             double2* o = out + (size_t)k * W * W + rank * W;
 #pragma unroll
-            for (int j = 0; j < W; ++j) {
-                prev[rank][j] = a[W + j];
-                o[j] = a[W + j];
+            for (int m = 0; m < M; ++m) {
+                const int j = q + 4 * m;
+                if (j >= W && j < 2 * W) {
+                    prev[rank][j - W] = a[m];
+                    o[j - W] = a[m];
+                }
             }
         }
         __syncthreads();
@@ -178,38 +192,49 @@ __global__ void __launch_bounds__(64) rgf_diag_kernel(const double* __restrict__
                                                       double2* __restrict__ Gd,
                                                       double* __restrict__ Adiag,
                                                       uint32_t* __restrict__ status) {
+    constexpr int M = Narrow<W>::M;
     const int e = blockIdx.x / L;
     const int k = blockIdx.x % L;
     const int lane = threadIdx.x;
+    const int i = lane & 15, q = lane >> 4;
     const double E = energies[e];
     const double t2 = t * t;
-    double2 a[2 * W];
-    diag_block_row<W>(a, lane, k, L, E, t, onsite, gamma, sigma + (size_t)e * W * W);
-    if (lane < W) {
+    const int i_site = i < W ? i : 0;
+    double2 a[M];
+    diag_block_entries<W>(a, i, q, k, L, E, t, onsite[k * W + i_site], gamma[k * W + i_site],
+                          sigma + (size_t)e * W * W);
+    if (i < W) {
         const size_t base = (size_t)e * L * W * W;
         if (k > 0) {
-            const double2* g = gL + base + (size_t)(k - 1) * W * W + lane * W;
+            const double2* g = gL + base + (size_t)(k - 1) * W * W + i * W;
 #pragma unroll
-            for (int j = 0; j < W; ++j) a[j] = csub(a[j], cscale(g[j], t2));
+            for (int m = 0; m < M; ++m) {
+                const int j = q + 4 * m;
+                if (j < W) a[m] = csub(a[m], cscale(g[j], t2));
+            }
         }
         if (k < L - 1) {
-            const double2* g = gR + base + (size_t)(k + 1) * W * W + lane * W;
+            const double2* g = gR + base + (size_t)(k + 1) * W * W + i * W;
 #pragma unroll
-            for (int j = 0; j < W; ++j) a[j] = csub(a[j], cscale(g[j], t2));
+            for (int m = 0; m < M; ++m) {
+                const int j = q + 4 * m;
+                if (j < W) a[m] = csub(a[m], cscale(g[j], t2));
+            }
         }
     }
     int rank;
-    const bool ok = gj_invert<W>(a, lane, rank);
-    if (lane < W) {
+    const bool ok = gj_invert<W>(a, i, q, rank);
+    if (i < W) {
         double2* o = Gd + ((size_t)e * L + k) * W * W + rank * W;
 #pragma unroll
-        for (int j = 0; j < W; ++j) o[j] = a[W + j];
-        // diagonal element (rank, rank): a[W + rank], selected without dynamic indexing
-        double im = 0.0;
-#pragma unroll
-        for (int j = 0; j < W; ++j)
-            if (j == rank) im = a[W + j].y;
-        Adiag[(size_t)e * L * W + k * W + rank] = -2.0 * im;
+        for (int m = 0; m < M; ++m) {
+            const int j = q + 4 * m;
+            if (j >= W && j < 2 * W) {
+                o[j - W] = a[m];
+                // the diagonal element (rank, rank) of the inverse
+                if (j - W == rank) Adiag[(size_t)e * L * W + k * W + rank] = -2.0 * a[m].y;
+            }
+        }
     }
     if (!ok && lane == 0) atomicOr(status, MCNEGF_FLAG_SINGULAR);
 }
