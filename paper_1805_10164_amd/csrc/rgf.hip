@@ -80,7 +80,9 @@ __device__ inline bool gj_invert(double2 (&a)[Narrow<W>::M], int i, int q, int& 
         const double2 pp = cmk(readlane_d(a[mp].x, r + 16 * qp), readlane_d(a[mp].y, r + 16 * qp));
         const double pm = cabs2(pp);
         if (!(pm > 0.0) || !isfinite(pm)) ok = false;
-        const double2 pinv = crecip(pp);
+        // 1 / pp = conj(pp) / |pp|^2: one division on the pivot step's critical path
+        const double rpm = 1.0 / pm;
+        const double2 pinv = cmk(pp.x * rpm, -pp.y * rpm);
         // per-lane choices as selects: every lane stays active for the next pivot's cross-lane
         // reads
 #pragma unroll
