@@ -477,3 +477,28 @@ def test_full_size_chain_direct():
     Tref = np.array([s.T_eff for s in sols])
     assert st == M.OK and np.abs(T.cpu().numpy() - Tref).max() <= 1e-10 * Tref.max()
     assert abs(I - D.current(sols, c["w"])) <= 1e-10 * abs(I)
+
+
+@pytest.mark.parametrize("W", list(range(1, 17)))
+def test_every_narrow_width_blocks_and_direct_current(W):
+    # each block width of the narrow RGF path (one template instance per W, with the augmented
+    # block spread over 4 column groups x 16 rows): diagonal blocks, A_jj and the DIRECT T_eff
+    # against the dense oracle, with disorder, both end slices and a pivot-heavy energy range
+    c = case(W=W, L=3, eta=0.07, disorder=0.6, nE=2, emin=-1.7, emax=0.9, seed=W)
+    k = gpu_build(c)
+    sols = oracle_solve(c)
+    Gd = k.Gd().cpu().numpy()
+    Ad = k.Adiag().cpu().numpy()
+    for e, s in enumerate(sols):
+        got = Gd[e, ..., 0] + 1j * Gd[e, ..., 1]
+        for x in range(c["L"]):
+            ref = s.G[x * W:(x + 1) * W, x * W:(x + 1) * W]
+            assert rel(got[x], ref) < 1e-10, (W, e, x)
+        assert rel(Ad[e], s.Adiag) < 1e-10, (W, e)
+    wt = torch.tensor(c["w"], device=DEV)
+    T = torch.empty(len(c["E"]), dtype=torch.float64, device=DEV)
+    sg = torch.empty_like(T)
+    st, I, _ = M.mc_negf_current(k, 1, 0, None, wt, T, sg)
+    assert st == M.OK
+    Tref = np.array([s.T_eff for s in sols])
+    assert rel(T.cpu().numpy(), Tref) < 1e-10, W
