@@ -51,11 +51,11 @@ __device__ inline void block_matvec(double2 (&v)[W], const lds_double* M, double
     for (int y = 0; y < W; ++y) v[y] = nv[y];
 }
 
-// The 64 lanes copy the W x W block src into the LDS buffer dst.
-template <int W>
-__device__ inline void stage_block(lds_double* dst, const double2* __restrict__ src, int lane) {
+// The NT threads copy the W x W block src into the LDS buffer dst (thread tid).
+template <int W, int NT = 64>
+__device__ inline void stage_block(lds_double* dst, const double2* __restrict__ src, int tid) {
 #pragma unroll
-    for (int i = lane; i < W * W; i += 64) {
+    for (int i = tid; i < W * W; i += NT) {
         const double2 v = src[i];
         dst[2 * i] = v.x;
         dst[2 * i + 1] = v.y;
@@ -193,7 +193,10 @@ static hipError_t launch_fullinv_w(const mcnegf_kernel& k, double2* Gc, int64_t 
 // ---- W = 16 and W = 32 on FP64 matrix cores ----------------------------------------------
 //
 // The same sweeps, with the block products on v_mfma_f64_16x16x4f64 (no padding at these
-// widths).  A wavefront owns TC tiles of 16 consecutive columns; lane (n, g) = (l % 16, l / 16)
+// widths).  A workgroup of NW wavefronts shares one double-buffered staged block (so the LDS of
+// a workgroup does not limit the wavefronts a CU holds) and sweeps from its first column's
+// slice (downward) and its last column's slice (upward); a wavefront's columns stay zero until
+// their own slice.  A wavefront owns TC tiles of 16 consecutive columns; lane (n, g) = (l % 16, l / 16)
 // holds, for tile t and row tile rt, the rows 16 rt + 4 r + g (r = 0..3) of column n, which is
 // both the accumulator layout of the product (item r of lane n + 16 g is row 4 r + g) and the
 // B-operand layout of the next product (K-step s takes rows 4 s + g from lane n + 16 g), so the
@@ -202,8 +205,8 @@ static hipError_t launch_fullinv_w(const mcnegf_kernel& k, double2* Gc, int64_t 
 // is four real products (re re, -im im into the real part; re im, im re into the imaginary).
 typedef double dmfma4 __attribute__((ext_vector_type(4)));
 
-template <int W, int TC, bool STORE_G>
-__global__ void __launch_bounds__(64) fullinv_mfma_kernel(const double2* __restrict__ gL,
+template <int W, int TC, int NW, bool STORE_G>
+__global__ void __launch_bounds__(64 * NW) fullinv_mfma_kernel(const double2* __restrict__ gL,
                                                           const double2* __restrict__ gR,
                                                           const double2* __restrict__ Gd,
                                                           const double* __restrict__ gam_lead,
@@ -220,11 +223,13 @@ __global__ void __launch_bounds__(64) fullinv_mfma_kernel(const double2* __restr
     lds_double* Ms = (lds_double*)Ms_raw;
     const int N = W * L;
     const int e = blockIdx.y;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
     const int n = lane & 15, g = lane >> 4;
-    const int c0 = blockIdx.x * 16 * TC;
-    const int kmin = c0 / W;
-    const int kmax = (min(c0 + 16 * TC, N) - 1) / W;
+    const int cg0 = blockIdx.x * NW * 16 * TC;  // the workgroup's first column
+    const int c0 = cg0 + (tid >> 6) * 16 * TC;  // this wavefront's first column
+    const int kmin = cg0 / W;
+    const int kmax = (min(cg0 + NW * 16 * TC, N) - 1) / W;
     const size_t eb = (size_t)e * L * W * W;
     const double2* gLe = gL + eb;
     const double2* gRe = gR + eb;
@@ -361,11 +366,12 @@ __global__ void __launch_bounds__(64) fullinv_mfma_kernel(const double2* __restr
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
             for (int r = 0; r < 4; ++r) vr[tc][rt][r] = vi[tc][rt][r] = 0.0;
-    stage_block<W>(Ms, gRe + (size_t)kmin * W * W, lane);
+    stage_block<W, 64 * NW>(Ms, gRe + (size_t)kmin * W * W, tid);
     for (int k = kmin; k < L; ++k) {
         __syncthreads();
         const int b = (k - kmin) & 1;
-        if (k + 1 < L) stage_block<W>(Ms + (b ^ 1) * BS, gRe + (size_t)(k + 1) * W * W, lane);
+        if (k + 1 < L)
+            stage_block<W, 64 * NW>(Ms + (b ^ 1) * BS, gRe + (size_t)(k + 1) * W * W, tid);
         product(Ms + b * BS);
         fix(k, true);
         store(k, true);
@@ -392,11 +398,11 @@ __global__ void __launch_bounds__(64) fullinv_mfma_kernel(const double2* __restr
 #pragma unroll
             for (int r = 0; r < 4; ++r) vr[tc][rt][r] = vi[tc][rt][r] = 0.0;
     __syncthreads();
-    stage_block<W>(Ms, gLe + (size_t)kmax * W * W, lane);
+    stage_block<W, 64 * NW>(Ms, gLe + (size_t)kmax * W * W, tid);
     for (int k = kmax; k >= 0; --k) {
         __syncthreads();
         const int b = (kmax - k) & 1;
-        if (k > 0) stage_block<W>(Ms + (b ^ 1) * BS, gLe + (size_t)(k - 1) * W * W, lane);
+        if (k > 0) stage_block<W, 64 * NW>(Ms + (b ^ 1) * BS, gLe + (size_t)(k - 1) * W * W, tid);
         product(Ms + b * BS);
         fix(k, false);
         store(k, false);
@@ -417,13 +423,13 @@ __global__ void __launch_bounds__(64) fullinv_mfma_kernel(const double2* __restr
     }
 }
 
-template <int W, int TC, bool STORE_G>
+template <int W, int TC, int NW, bool STORE_G>
 static hipError_t launch_fullinv_mfma(const mcnegf_kernel& k, double2* Gc, int64_t ldG,
                                       hipStream_t s) {
-    dim3 grid((k.N + 16 * TC - 1) / (16 * TC), k.nE);
+    dim3 grid((k.N + 16 * TC * NW - 1) / (16 * TC * NW), k.nE);
     {
         MCNEGF_TIMED(STORE_G ? "fullinv_store_g_kernel" : "fullinv_kernel", s);
-        hipLaunchKernelGGL((fullinv_mfma_kernel<W, TC, STORE_G>), grid, dim3(64), 0, s,
+        hipLaunchKernelGGL((fullinv_mfma_kernel<W, TC, NW, STORE_G>), grid, dim3(64 * NW), 0, s,
                            reinterpret_cast<const double2*>(k.gL),
                            reinterpret_cast<const double2*>(k.gR),
                            reinterpret_cast<const double2*>(k.Gd), k.gam_lead, k.L, k.t, k.p_pitch,
@@ -432,11 +438,15 @@ static hipError_t launch_fullinv_mfma(const mcnegf_kernel& k, double2* Gc, int64
     return hipGetLastError();
 }
 
+// wavefronts per workgroup sharing one staged block
+constexpr int kFullinvWaves16 = 1;
+constexpr int kFullinvWaves32 = 4;
+
 template <bool STORE_G>
 static hipError_t launch_fullinv_any(const mcnegf_kernel& k, double2* Gc, int64_t ldG,
                                      hipStream_t s) {
-    if (k.W == 16) return launch_fullinv_mfma<16, 4, STORE_G>(k, Gc, ldG, s);
-    if (k.W == 32) return launch_fullinv_mfma<32, 2, STORE_G>(k, Gc, ldG, s);
+    if (k.W == 16) return launch_fullinv_mfma<16, 4, kFullinvWaves16, STORE_G>(k, Gc, ldG, s);
+    if (k.W == 32) return launch_fullinv_mfma<32, 2, kFullinvWaves32, STORE_G>(k, Gc, ldG, s);
     switch (k.W) {
 #define MCNEGF_CASE(w) \
     case w:            \
