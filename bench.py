@@ -444,6 +444,13 @@ def scale_bench(torch, dev, steps, warmup, with_cpu, seed):
     walk_ms = lt.total_ms("walk_kernel") / steps
     chol_ms = lt.total_ms("cholesky_kernel") / steps
     chol_flop = nE * (wl.N ** 3 / 3.0 + 2.0 * wl.N * wl.N)
+    fi_ms = lt.total_ms("fullinv_kernel") / steps
+    fi_flop = nE * 8.0 * wl.W ** 3 * wl.L * (wl.L - 1)
+
+    def per_batch_traffic(name, pk):
+        t = measured_traffic(name, "scale_W32_L500")
+        return None if t is None else t * pk[name]["launches"]
+
     res = {
         "workload": f"W={wl.W} L={wl.L} N={wl.N}, eta={wl.eta}t, disorder U[-{wl.disorder},"
                     f"{wl.disorder}]t, {wl.n_energies} energies in [{wl.emin},{wl.emax}]t in "
@@ -468,10 +475,21 @@ def scale_bench(torch, dev, steps, warmup, with_cpu, seed):
                             "algorithmic_per_launch": walk_steps * ALIAS_ENTRY_BYTES,
                             "avg_launch_ms": walk_ms,
                             "traffic": measured_traffic("walk_kernel", "scale_W32_L500")},
+            # the factorization is one launch per 64-column block: figures per batch
             "cholesky_kernel": {"bound": "mfma", "achieved": chol_flop / 1e12 / (chol_ms * 1e-3),
                                 "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                                 "frac": chol_flop / 1e12 / (chol_ms * 1e-3) /
-                                FP64_VALU_PEAK_TFLOPS},
+                                FP64_VALU_PEAK_TFLOPS, "algorithmic_per_batch": chol_flop,
+                                "ms_per_batch": chol_ms,
+                                "traffic_per_batch": per_batch_traffic("cholesky_kernel",
+                                                                       per_kernel)},
+            # the RGF block products of the full inverse (v_mfma_f64_16x16x4f64)
+            "fullinv_kernel": {"bound": "mfma", "achieved": fi_flop / 1e12 / (fi_ms * 1e-3),
+                               "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                               "frac": fi_flop / 1e12 / (fi_ms * 1e-3) / FP64_VALU_PEAK_TFLOPS,
+                               "algorithmic_per_launch": fi_flop, "avg_launch_ms": fi_ms,
+                               "traffic": measured_traffic("fullinv_mfma_kernel",
+                                                           "scale_W32_L500")},
         },
     }
     j = 1  # an energy of the batch away from the window's edge
