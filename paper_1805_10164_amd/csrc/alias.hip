@@ -327,58 +327,164 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
     }
     if (tid == 0) lightD(NLtot) = Dtot;  // index NLtot = n - NHtot: below every heavy slot
     __syncthreads();
-    // 4. thresholds and aliases
+    // 4. thresholds and aliases.  Light r is served by heavy m*(r), the first heavy with
+    // C_m > D_r (the last heavy when there is none); heavy m keeps 1 + C_m - D_a with a the
+    // first light with D_a >= C_m (D_NL = the total deficit) and aliases to heavy m + 1.
+    if constexpr (KM <= 8) {
+        // Both are ranks in the merge of the ascending D and C with a heavy before a light on
+        // ties: thread t merges positions [t KM, t KM + KM) from the split its binary search
+        // finds, keeps the results of the merged items in registers and, once every merge has
+        // read D and C, passes them through the lh array (one 64-bit slot per item: light r at
+        // slot r, heavy m at slot n - 1 - m) to the threads that own the items.
+        uint64_t res[KM];
+        int slot[KM];
 #pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        const int i = tid + BT * k;
-        if (i >= n) continue;
-        const int r = rk[k];
-        double q;
-        int al;
-        if (NHtot == 0) {
-            q = 1.0;
-            al = i;
-        } else if (r >= 0) {
-            // light: first heavy m with heavyC(m) > D_i
-            const double D = dc[k];
-            int lo = 0, hi = NHtot;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (heavyC(mid) > D) hi = mid; else lo = mid + 1;
+        for (int k = 0; k < KM; ++k) {
+            res[k] = 0;
+            slot[k] = -1;
+        }
+        if (NHtot > 0) {
+            const int d0 = tid * KM;
+            int a = 0, b = 0;
+            if (d0 < n) {
+                int lo = d0 > NHtot ? d0 - NHtot : 0, hi = d0 < NLtot ? d0 : NLtot;
+                while (lo < hi) {  // lights among the first d0 merged items
+                    const int mid = (lo + hi) >> 1;
+                    if (lightD(mid) < heavyC(d0 - mid - 1)) lo = mid + 1; else hi = mid;
+                }
+                a = lo;
+                b = d0 - lo;
             }
-            if (lo >= NHtot) lo = NHtot - 1;
-            q = w[k];
-            al = heavyIdx[lo];
-        } else {
-            const int m = ~r;
-            if (m == NHtot - 1) {
+            double dA = lightD(a);  // lightD(NLtot) = Dtot
+            double cB = b < NHtot ? heavyC(b) : 0.0;
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                if (d0 + k >= n) continue;
+                const bool heavy = b < NHtot && (a >= NLtot || cB <= dA);
+                if (heavy) {
+                    const int i = heavyIdx[b];
+                    double q;
+                    int al;
+                    if (b == NHtot - 1) {
+                        q = 1.0;
+                        al = i;
+                    } else {
+                        q = 1.0 + cB - dA;
+                        q = q < 0.0 ? 0.0 : q;
+                        al = heavyIdx[b + 1];
+                    }
+                    uint32_t thr;
+                    if (q >= 1.0) {
+                        thr = 0xFFFFFFFFu;
+                        al = i;
+                    } else {
+                        thr = (uint32_t)(q * 4294967296.0);
+                    }
+                    res[k] = (uint64_t)((thr & ~kAliasIdxMask) | (uint32_t)al) |
+                             ((uint64_t)(thr & kAliasIdxMask) << 32);
+                    slot[k] = n - 1 - b;
+                    ++b;
+                    cB = b < NHtot ? heavyC(b) : 0.0;
+                } else {
+                    res[k] = heavyIdx[b < NHtot ? b : NHtot - 1];
+                    slot[k] = a;
+                    ++a;
+                    dA = lightD(a);
+                }
+            }
+        }
+        __syncthreads();  // every merge has read D and C
+        uint64_t* slots = reinterpret_cast<uint64_t*>(lh);
+#pragma unroll
+        for (int k = 0; k < KM; ++k)
+            if (slot[k] >= 0) slots[slot[k]] = res[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            const int i = tid + BT * k;
+            if (i >= n) continue;
+            const int r = rk[k];
+            uint32_t packed, low;
+            if (NHtot == 0) {
+                packed = (0xFFFFFFFFu & ~kAliasIdxMask) | (uint32_t)i;
+                low = 0xFFFFFFFFu & kAliasIdxMask;
+            } else if (r >= 0) {
+                int al = (int)slots[r];
+                uint32_t thr;
+                if (w[k] >= 1.0) {
+                    thr = 0xFFFFFFFFu;
+                    al = i;
+                } else {
+                    thr = (uint32_t)(w[k] * 4294967296.0);
+                }
+                packed = (thr & ~kAliasIdxMask) | (uint32_t)al;
+                low = thr & kAliasIdxMask;
+            } else {
+                const uint64_t v = slots[n - 1 - ~r];
+                packed = (uint32_t)v;
+                low = (uint32_t)(v >> 32);
+            }
+            if ((packed & kAliasIdxMask) >= (uint32_t)n) {  // never for a consistent row
+                packed = (packed & ~kAliasIdxMask) | (uint32_t)i;
+                atomicOr(a.status, MCNEGF_FLAG_NONFINITE);
+            }
+            out[i] = packed;
+            out_lo[i] = (uint16_t)low;
+        }
+    } else {
+        // long rows: each item finds its partner by binary search
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            const int i = tid + BT * k;
+            if (i >= n) continue;
+            const int r = rk[k];
+            double q;
+            int al;
+            if (NHtot == 0) {
                 q = 1.0;
                 al = i;
-            } else {
-                const double C = dc[k];
-                int lo = 0, hi = NLtot;  // first light start >= C (lightD(NLtot) = Dtot)
+            } else if (r >= 0) {
+                // light: first heavy m with heavyC(m) > D_i
+                const double D = dc[k];
+                int lo = 0, hi = NHtot;
                 while (lo < hi) {
                     const int mid = (lo + hi) >> 1;
-                    if (lightD(mid) >= C) hi = mid; else lo = mid + 1;
+                    if (heavyC(mid) > D) hi = mid; else lo = mid + 1;
                 }
-                q = 1.0 + C - lightD(lo);
-                q = q < 0.0 ? 0.0 : q;
-                al = heavyIdx[m + 1];
+                if (lo >= NHtot) lo = NHtot - 1;
+                q = w[k];
+                al = heavyIdx[lo];
+            } else {
+                const int m = ~r;
+                if (m == NHtot - 1) {
+                    q = 1.0;
+                    al = i;
+                } else {
+                    const double C = dc[k];
+                    int lo = 0, hi = NLtot;  // first light start >= C (lightD(NLtot) = Dtot)
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (lightD(mid) >= C) hi = mid; else lo = mid + 1;
+                    }
+                    q = 1.0 + C - lightD(lo);
+                    q = q < 0.0 ? 0.0 : q;
+                    al = heavyIdx[m + 1];
+                }
             }
+            uint32_t thr;
+            if (q >= 1.0) {
+                thr = 0xFFFFFFFFu;
+                al = i;
+            } else {
+                thr = (uint32_t)(q * 4294967296.0);
+            }
+            if ((unsigned)al >= (unsigned)n) {  // never for a consistent row; keeps walks in range
+                al = i;
+                atomicOr(a.status, MCNEGF_FLAG_NONFINITE);
+            }
+            out[i] = (thr & ~kAliasIdxMask) | (uint32_t)al;
+            out_lo[i] = (uint16_t)(thr & kAliasIdxMask);
         }
-        uint32_t thr;
-        if (q >= 1.0) {
-            thr = 0xFFFFFFFFu;
-            al = i;
-        } else {
-            thr = (uint32_t)(q * 4294967296.0);
-        }
-        if ((unsigned)al >= (unsigned)n) {  // never for a consistent row; keeps walks in range
-            al = i;
-            atomicOr(a.status, MCNEGF_FLAG_NONFINITE);
-        }
-        out[i] = (thr & ~kAliasIdxMask) | (uint32_t)al;
-        out_lo[i] = (uint16_t)(thr & kAliasIdxMask);
     }
 }
 
