@@ -16,8 +16,9 @@
 // Execution: persistent wavefronts, one energy group per XCD (see walk_kernel); each lane
 // takes the next walker of its wavefront's chunk as soon as its own walker is absorbed, and
 // every loop iteration performs two steps from one Philox block.  The keep test compares the
-// high 20 bits of b with the bucket's packed entry and reads the low 12 threshold bits only
-// on a tie.
+// high 16 bits of b with the bucket's packed entry and reads the low 16 threshold bits only
+// on a tie.  A walk's first step reads its injection row from an LDS copy when the launch
+// staged one; a finished walk is counted once, when its slot takes the next walker.
 #include "common.h"
 
 namespace mcnegf {

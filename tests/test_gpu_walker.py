@@ -46,15 +46,17 @@ def test_walker_bit_exact_on_given_tables(inject):
     assert (tal.cpu().numpy() == ref).all()
 
 
-def test_walker_truncation_and_max_steps():
+@pytest.mark.parametrize("max_steps", [1, 2])
+def test_walker_truncation_and_max_steps(max_steps):
+    # max_steps = 1: every walk ends at its injection step, at a lead or truncated at a probe
     c = case(W=2, L=6, eta=0.5, disorder=0.2, nE=2, emin=-1.0, emax=1.0)
     k = gpu_build(c)
     sols = oracle_solve(c)
     thr, al = oracle_alias_tables(sols, k.alias_pitch)
     k.set_alias_tables(thr, al)
     tal = torch.zeros((2, 5), dtype=torch.int64, device=DEV)
-    M.mc_negf_walk(k, 11, 0, 0, 0, 20_000, 2, tal)
-    ref = OW.walk_alias(thr, al, 11, 0, 0, 0, 20_000, max_steps=2)
+    M.mc_negf_walk(k, 11, 0, 0, 0, 20_000, max_steps, tal)
+    ref = OW.walk_alias(thr, al, 11, 0, 0, 0, 20_000, max_steps=max_steps)
     assert (tal.cpu().numpy() == ref).all() and ref[:, 2].sum() > 0
     w = torch.tensor(c["w"], dtype=torch.float64, device=DEV)
     T = torch.empty(2, dtype=torch.float64, device=DEV)
