@@ -328,11 +328,22 @@ def batched_bench(torch, dev, steps, warmup, budget_gb, seed):
     return result
 
 
+def next_batch(done, I, s, first, cap):
+    """Walkers for the next batch: the count that would bring sigma_I to 1% of I (sigma falls
+    as 1 / sqrt(walkers)), with a 20% margin, at least `first`, at most cap - done."""
+    if s > 0.0 and I != 0.0:
+        want = int(1.2 * done * (s / (0.01 * abs(I))) ** 2) - done
+    else:
+        want = done
+    return max(first, min(want, cap - done))
+
+
 def time_to_1pct(p: Problem, torch, seed, walk_on):
     """Wall time to a 1% relative deviation of I, median of 5 warm repetitions.
-    MC: build + walker batches doubling from 1024 per energy until sigma_I <= 1% of I.
+    MC: build + a first batch of 1024 walkers per energy, then batches sized from the
+    measured sigma_I until sigma_I <= 1% of I.
     MC, energy-sampled (the paper's estimator: energies drawn from the weights, constant
-    estimator): build + batches of walkers over all energies doubling from 1024 in total.
+    estimator): build + a first batch of 4096 walkers over all energies, then likewise.
     DIRECT: build without alias tables + probe-system solve (deterministic; its error is the
     quadrature's)."""
     mc_t, dir_t, mc_walkers, smp_t, smp_walkers = [], [], [], [], []
@@ -354,22 +365,22 @@ def time_to_1pct(p: Problem, torch, seed, walk_on):
                 st, I, s = M.mc_negf_current(k, 0, 0, p.tal, p.w, p.T, p.sig)
                 if s <= 0.01 * abs(I) or done >= 1 << 24:
                     break
-                batch = done
+                batch = next_batch(done, I, s, 1024, 1 << 24)
             mc_t.append(time.perf_counter() - t0)
             mc_walkers.append(done)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             k = M.mc_negf_build_kernel(p.sys, p.V, p.g, p.E, p.ws)
             p.tal.zero_()
-            done, batch = 0, 1024
+            done, batch = 0, 4096
             while True:
                 M.mc_negf_walk_sampled(k, seed + 101 + rep, 0, 0, done, batch, 1_000_000, p.w,
                                        p.tal, p.sampled_scratch)
                 done += batch
                 st, I, s = M.mc_negf_current(k, 2, 0, p.tal, p.w, p.T, p.sig)
-                if s <= 0.01 * abs(I) or done + 2 * batch > max_sampled:
+                if s <= 0.01 * abs(I) or done >= max_sampled:
                     break
-                batch = done
+                batch = next_batch(done, I, s, 4096, max_sampled)
             smp_t.append(time.perf_counter() - t0)
             smp_walkers.append(done)
         torch.cuda.synchronize()
