@@ -432,7 +432,12 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
             out_lo[i] = (uint16_t)low;
         }
     } else {
-        // long rows: each item finds its partner by binary search
+        // Long rows: a thread's lights have consecutive ranks, and so have its heavies, so in
+        // item order their partners never decrease: each search starts where the thread's
+        // previous one ended, steps forward up to kWalk times and finishes by bisection.
+        constexpr int kWalk = 8;
+        int mlo = 0;  // first heavy that can serve this thread's next light
+        int alo = 0;  // first light start that can bound this thread's next heavy
 #pragma unroll
         for (int k = 0; k < KM; ++k) {
             const int i = tid + BT * k;
@@ -446,11 +451,15 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
             } else if (r >= 0) {
                 // light: first heavy m with heavyC(m) > D_i
                 const double D = dc[k];
-                int lo = 0, hi = NHtot;
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (heavyC(mid) > D) hi = mid; else lo = mid + 1;
+                int lo = mlo, hi = NHtot;
+                for (int s = 0; s < kWalk && lo < hi && !(heavyC(lo) > D); ++s) ++lo;
+                if (lo < hi && !(heavyC(lo) > D)) {
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (heavyC(mid) > D) hi = mid; else lo = mid + 1;
+                    }
                 }
+                mlo = lo;
                 if (lo >= NHtot) lo = NHtot - 1;
                 q = w[k];
                 al = heavyIdx[lo];
@@ -461,11 +470,16 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
                     al = i;
                 } else {
                     const double C = dc[k];
-                    int lo = 0, hi = NLtot;  // first light start >= C (lightD(NLtot) = Dtot)
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (lightD(mid) >= C) hi = mid; else lo = mid + 1;
+                    // first light start >= C (lightD(NLtot) = Dtot)
+                    int lo = alo, hi = NLtot;
+                    for (int s = 0; s < kWalk && lo < hi && !(lightD(lo) >= C); ++s) ++lo;
+                    if (lo < hi && !(lightD(lo) >= C)) {
+                        while (lo < hi) {
+                            const int mid = (lo + hi) >> 1;
+                            if (lightD(mid) >= C) hi = mid; else lo = mid + 1;
+                        }
                     }
+                    alo = lo;
                     q = 1.0 + C - lightD(lo);
                     q = q < 0.0 ? 0.0 : q;
                     al = heavyIdx[m + 1];
