@@ -567,7 +567,7 @@ def calibration_copy(torch, dev, mib):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only (one GPU's share of the workload); use --gpus 1"}))
         sys.exit(2)
     import torch
     dev = "cuda:0"

@@ -22,7 +22,7 @@ class DirectCurrent(torch.autograd.Function):
         onsite = onsite.detach().contiguous()
         gamma = gamma.detach().contiguous()
         nE = int(energies.numel())
-        # no alias tables: only the DIRECT current and its adjoint read this build
+        # no alias tables: only the DIRECT current and its adjoint read this workspace
         sysd = M.System(system.W, system.L, system.t, system.lead_model, system.gamma_l,
                         system.delta_lead, system.flags | M.BUILD_NO_ALIAS)
         ws = M.allocate_workspace(sysd, nE, onsite.device)
