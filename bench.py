@@ -163,6 +163,17 @@ def measured_traffic(name, workload="wire_W10_L100"):
         return None
 
 
+def add_traffic_rate(roof):
+    """The measured HBM bytes per launch (`traffic`, rocprofv3) as a rate over the launch's
+    measured duration, and its fraction of the HBM peak: what the kernel moves, beside what it
+    needs (`achieved`)."""
+    t, ms = roof.get("traffic"), roof.get("avg_launch_ms")
+    if t is not None and ms:
+        roof["traffic_gbs"] = t / 1e9 / (ms * 1e-3)
+        roof["traffic_frac_of_hbm_peak"] = roof["traffic_gbs"] / HBM_PEAK_GBS
+    return roof
+
+
 def grad_work(wl: inputs.Workload):
     """Algorithmic work of one adjoint_solve_kernel launch (all energies): HBM bytes (G read
     in both sweeps, the forward results written and read back) and FP64 flops (two complex
@@ -215,6 +226,7 @@ def grad_bench(torch, dev, steps, warmup, with_cpu):
                      "fp64_tflops": flops / 1e12 / (adj_ms * 1e-3),
                      "traffic": measured_traffic("adjoint_solve_kernel", "diff_W16_L200")},
     }
+    add_traffic_rate(out["roofline"])
     del k, ws, gws
     torch.cuda.empty_cache()
     if with_cpu:
@@ -503,6 +515,8 @@ def scale_bench(torch, dev, steps, warmup, with_cpu, seed):
                                                            "scale_W32_L500")},
         },
     }
+    add_traffic_rate(res["rooflines"]["walk_kernel"])
+    add_traffic_rate(res["rooflines"]["fullinv_kernel"])
     j = 1  # an energy of the batch away from the window's edge
     T_gpu = float(Td[j].item())
     del holder, k, ws
@@ -618,6 +632,7 @@ def main():
     roof = roofline(dominant, base, per_kernel[dominant]["ms_per_launch"], walk_steps_per_launch)
     if roof is not None:
         roof["traffic"] = measured_traffic(dominant)
+        add_traffic_rate(roof)
     rooflines = {n: roofline(n, base, per_kernel[n]["ms_per_launch"], walk_steps_per_launch)
                  for n in names}
     per_eta = []
