@@ -218,6 +218,17 @@ __device__ inline void count_ended(Tally& t, bool done, const Step& s, uint32_t 
     t.s2 += n * n;
 }
 
+// The same for counts kept per lane (the batched walker's slots all walk one unit at a time).
+__device__ inline void count_ended_lane(uint32_t& cL, uint32_t& cR, uint32_t& tr, uint64_t& s1,
+                                        uint64_t& s2, bool done, const Step& s, uint32_t N) {
+    const uint64_t n = done ? (uint64_t)s.n : 0ull;
+    cL += (done && s.s == N) ? 1u : 0u;
+    cR += (done && s.s > N) ? 1u : 0u;
+    tr += (done && s.s < N) ? 1u : 0u;
+    s1 += n;
+    s2 += n * n;
+}
+
 // Adds a slot's counts for energy el to the block's LDS tallies (per-lane; called in
 // divergent code, no cross-lane operation inside).
 __device__ inline void tally_flush(unsigned long long* lds_tally, uint32_t el, const Tally& t) {
@@ -551,6 +562,8 @@ __global__ void walk_batch_kernel(WalkBatchArgs A) {
                 for (int k = 0; k < K; ++k) {
                     const uint32_t before = base + __popcll(need[k] & lt_mask);
                     const bool take = !st[k].active && before < avail;
+                    // the walk this slot finished is counted before the slot takes the next one
+                    count_ended_lane(cL, cR, tr, s1, s2, take && st[k].n != 0u, st[k], N);
                     uint32_t wid = next + before;
                     if (U.ids) {  // uniform branch; the load is per lane
                         if (take) wid = U.ids[wid];
@@ -601,14 +614,18 @@ __global__ void walk_batch_kernel(WalkBatchArgs A) {
                         rb |= __ballot(rej[k]);
                     }
                 }
-                uint32_t c[K], ent[K];
-                size_t at[K];
+                // entry offset row * pitch + bucket (both below 2^24, the sum below 2^32); idle
+                // slots read nothing
+                uint32_t c[K], ent[K], at[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     c[k] = (uint32_t)(m[k] >> 32);
-                    at[k] = (size_t)st[k].s * U.pitch + c[k];
-                    ent[k] = U.tables[at[k]];
+                    at[k] = __umul24(st[k].s, U.pitch) + c[k];
+                    ent[k] = 0u;
                 }
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (st[k].active) ent[k] = U.tables[at[k]];
                 bool keep[K], tie[K];
                 uint64_t tb = 0ull;
 #pragma unroll
@@ -627,23 +644,20 @@ __global__ void walk_batch_kernel(WalkBatchArgs A) {
                 }
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
+                    // a walk that ends keeps its exit state and step count (counted at refill)
                     const uint32_t nxt = keep[k] ? c[k] : (ent[k] & kAliasIdxMask);
                     const uint32_t n1 = st[k].n + 1;
                     const bool active = st[k].active;
-                    const bool absorbed = active && nxt >= N;
-                    const bool trunc = active && !absorbed && n1 >= A.max_steps;
-                    const bool ends = absorbed || trunc;
-                    cL += (absorbed && nxt == N) ? 1u : 0u;
-                    cR += (absorbed && nxt != N) ? 1u : 0u;
-                    tr += trunc ? 1u : 0u;
-                    s1 += ends ? (uint64_t)n1 : 0ull;
-                    s2 += ends ? (uint64_t)n1 * n1 : 0ull;
-                    st[k].s = (active && !ends) ? nxt : st[k].s;
+                    const bool ends = nxt >= N || n1 >= A.max_steps;
+                    st[k].s = active ? nxt : st[k].s;
                     st[k].n = active ? n1 : st[k].n;
                     st[k].active = active && !ends;
                 }
             }
         }
+        // walks that ended after their slot's last refill
+#pragma unroll
+        for (int k = 0; k < K; ++k) count_ended_lane(cL, cR, tr, s1, s2, st[k].n != 0u, st[k], N);
         // the chunk is done: one atomic per tally slot for the wavefront
         const uint64_t v0 = wave_sum_u64(cL), v1 = wave_sum_u64(cR), v2 = wave_sum_u64(tr);
         const uint64_t v3 = wave_sum_u64(s1), v4 = wave_sum_u64(s2);
