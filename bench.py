@@ -544,15 +544,15 @@ def scale_bench(torch, dev, steps, warmup, with_cpu, seed):
 
 
 def cpu_baseline(wl: inputs.Workload, seed: int):
-    """The oracle on the host cores for a bounded sample of the workload: dense LAPACK
-    solves plus the C walker (the paper's cumulative-sum sampler), 8 of the 256 energies
-    with 20 000 walkers each, at the middle dephasing rate."""
+    """The oracle on the host cores for a bounded sample of the workload (about 10 s): dense
+    LAPACK solves plus the C walker (the paper's cumulative-sum sampler), 24 of the 256
+    energies with 25 000 walkers each, at the middle dephasing rate."""
     from oracle import dense as D
     from oracle import walker as OW
     E, _ = M.energy_grid(wl.emin, wl.emax, wl.n_energies)
-    idx = np.linspace(0, wl.n_energies - 1, 8).round().astype(int)
+    idx = np.linspace(0, wl.n_energies - 1, 24).round().astype(int)
     V, g = inputs.onsite(wl), inputs.dephasing(wl)
-    nw = 20_000
+    nw = 25_000
     t0 = time.perf_counter()
     sols = D.solve_workload(wl.W, wl.L, wl.t, V, g, E[idx])
     K = np.stack([s.transition_kernel() for s in sols])
