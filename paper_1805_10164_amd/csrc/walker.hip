@@ -59,8 +59,7 @@ __device__ inline Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, u
 struct WalkArgs {
     const uint32_t* tables;  // packed (thr >> 16) << 16 | alias
     const uint16_t* lows;    // thr & 0xFFFF
-    int64_t pitch;
-    uint32_t pitch32;      // the same, below 2^24
+    uint32_t pitch32;      // entries per table row (below 2^24)
     int64_t table_stride;  // entries per energy
     uint32_t n_out, N;
     uint32_t nE;      // energies in this launch
@@ -208,17 +207,8 @@ __device__ inline void walk_steps(Step (&st)[K], const gtable_ptr (&tb)[K],
 }
 
 // Adds the walk that ended in a slot (done: the slot holds one that is not counted yet) to
-// the slot's counts: exit by its final state, its step count and squared step count.
-__device__ inline void count_ended(Tally& t, bool done, const Step& s, uint32_t N) {
-    const uint64_t n = done ? (uint64_t)s.n : 0ull;
-    t.cL += (done && s.s == N) ? 1u : 0u;
-    t.cR += (done && s.s > N) ? 1u : 0u;
-    t.tr += (done && s.s < N) ? 1u : 0u;
-    t.s1 += n;
-    t.s2 += n * n;
-}
-
-// The same for counts kept per lane (the batched walker's slots all walk one unit at a time).
+// counts: exit by its final state (lead L = N, lead R = N + 1, a probe when truncated), its
+// step count and squared step count.
 __device__ inline void count_ended_lane(uint32_t& cL, uint32_t& cR, uint32_t& tr, uint64_t& s1,
                                         uint64_t& s2, bool done, const Step& s, uint32_t N) {
     const uint64_t n = done ? (uint64_t)s.n : 0ull;
@@ -227,6 +217,10 @@ __device__ inline void count_ended_lane(uint32_t& cL, uint32_t& cR, uint32_t& tr
     tr += (done && s.s < N) ? 1u : 0u;
     s1 += n;
     s2 += n * n;
+}
+// The same into a slot's counts (the per-kernel walker's slots move between energies).
+__device__ inline void count_ended(Tally& t, bool done, const Step& s, uint32_t N) {
+    count_ended_lane(t.cL, t.cR, t.tr, t.s1, t.s2, done, s, N);
 }
 
 // Adds a slot's counts for energy el to the block's LDS tallies (per-lane; called in
@@ -418,7 +412,6 @@ hipError_t launch_walk(const mcnegf_kernel& k, uint64_t seed, uint32_t tag, uint
         A.table_stride = (int64_t)k.n_out * k.alias_pitch;
         A.tables = k.alias + (size_t)e_off * A.table_stride;
         A.lows = k.alias_lo + (size_t)e_off * A.table_stride;
-        A.pitch = k.alias_pitch;
         A.pitch32 = (uint32_t)k.alias_pitch;
         A.n_out = (uint32_t)k.n_out;
         A.N = (uint32_t)k.N;
