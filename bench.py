@@ -519,6 +519,43 @@ def scale_bench(torch, dev, steps, warmup, with_cpu, seed):
     add_traffic_rate(res["rooflines"]["fullinv_kernel"])
     j = 1  # an energy of the batch away from the window's edge
     T_gpu = float(Td[j].item())
+    T64 = Td.cpu().numpy()
+    I64 = float(o[1, 0])
+
+    # the same batch with the full inverse's block products in FP32 (same workspace)
+    sys32 = M.make_system(wl.W, wl.L, wl.t, wl.lead_model, wl.gamma_l, wl.delta_lead,
+                          M.BUILD_FP32_PRODUCTS)
+
+    def one_batch32():
+        k32 = M.mc_negf_build_kernel(sys32, V, g, tE, ws)
+        tal.zero_()
+        M.mc_negf_walk(k32, seed, 0, 0, 0, nw, 1_000_000, tal)
+        M.mc_negf_current_async(k32, 0, 0, tal, tw, T, sg, out[0])
+        M.mc_negf_current_async(k32, 1, 0, None, tw, Td, sgd, out[1])
+        holder["k"] = k32
+
+    one_batch32()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with M.LaunchTimes() as lt32:
+        one_batch32()
+    torch.cuda.synchronize()
+    wall32 = time.perf_counter() - t0
+    o32 = out.cpu().numpy()
+    T32 = Td.cpu().numpy()
+    flags32 = M.mc_negf_status(holder["k"])
+    res["fp32_products"] = {
+        "what": "full-inverse block products in FP32 on the matrix cores (FP64 RGF blocks, "
+                "|G|^2, alias tables, probe solve, tallies); no refinement step",
+        "ms_per_batch": 1e3 * wall32,
+        "fullinv_ms": lt32.total_ms("fullinv_kernel"),
+        "fullinv_ms_fp64": fi_ms,
+        "max_rel_err_T_direct_vs_fp64": float(np.max(np.abs(T32 - T64) / np.abs(T64))),
+        "rel_err_I_direct_vs_fp64": abs(float(o32[1, 0]) - I64) / abs(I64),
+        "mc_minus_fp64_direct_in_sigma": (float(o32[0, 0]) - I64) / float(o32[0, 1]),
+        "status_flags": int(flags32),
+    }
+    T_gpu32 = float(T32[j])
     del holder, k, ws
     torch.cuda.empty_cache()
     if with_cpu:
@@ -539,7 +576,8 @@ def scale_bench(torch, dev, steps, warmup, with_cpu, seed):
             "sample": f"energy {E[j]:.6f}t (1 of {wl.n_energies}): sparse LU columns (one "
                       f"thread) + dense probe solve ({blas} BLAS threads), {dt:.1f} s",
             "T_oracle": T_ref, "T_gpu_direct": T_gpu,
-            "rel_err_direct": abs(T_gpu - T_ref) / abs(T_ref)}
+            "rel_err_direct": abs(T_gpu - T_ref) / abs(T_ref),
+            "rel_err_direct_fp32_products": abs(T_gpu32 - T_ref) / abs(T_ref)}
     return res
 
 

@@ -52,7 +52,8 @@ extern "C" {
 /* ---- status codes ------------------------------------------------------------------ */
 #define MCNEGF_OK         0
 #define MCNEGF_WTRUNC     1   /* some walks hit max_steps: the MC estimate is biased low  */
-#define MCNEGF_WNUMERIC   2   /* a kernel invariant check (row sums) exceeded 1e-8         */
+#define MCNEGF_WNUMERIC   2   /* a kernel invariant check (row sums) exceeded 1e-8 (1e-4   */
+                              /* with MCNEGF_BUILD_FP32_PRODUCTS)                          */
 #define MCNEGF_EINVAL    -1   /* bad size, null pointer, out-of-range parameter           */
 #define MCNEGF_EWS       -2   /* workspace too small                                      */
 #define MCNEGF_EHIP      -3   /* a HIP call failed; see mc_negf_last_hip_error()          */
@@ -64,6 +65,7 @@ extern "C" {
 #define MCNEGF_FLAG_SINGULAR   0x02u  /* zero pivot while inverting an RGF block          */
 #define MCNEGF_FLAG_ROWSUM     0x04u  /* a kernel row total differs from A_jj (or         */
                                       /* Tr Gamma_p A for a lead row) by more than 1e-8    */
+                                      /* (1e-4 with MCNEGF_BUILD_FP32_PRODUCTS)            */
 #define MCNEGF_FLAG_NOABSORB   0x08u  /* a lead has no open channel at some energy: its    */
                                       /* injection row is empty (its walkers exit at once  */
                                       /* into L and T = 0); happens outside the lead band, */
@@ -110,6 +112,14 @@ typedef struct mcnegf_system {
  * and direct_vec are NULL); the DIRECT mode of mc_negf_current and mc_negf_grad reject such
  * a kernel with MCNEGF_EINVAL.  For Monte Carlo-only batches of large systems. */
 #define MCNEGF_BUILD_NO_DIRECT 0x2u
+/* MCNEGF_BUILD_FP32_PRODUCTS: the block products of the full inverse (the sweeps that
+ * produce every block of G from the RGF blocks, Sec. III B) run as FP32 complex products on
+ * the matrix cores, with the column state in FP32; the RGF blocks, |G_ij|^2, the exit
+ * weights, the lead terms, the alias tables, the probe solve and all tallies stay FP64.
+ * Only W = 16 and W = 32 (mc_negf_build_kernel returns MCNEGF_EINVAL for other widths);
+ * |G_ij|^2 then carries FP32 rounding (relative error of order 1e-6 after hundreds of
+ * slices), and so do the currents.  No refinement step is applied. */
+#define MCNEGF_BUILD_FP32_PRODUCTS 0x4u
 
 /*
  * Handle filled by mc_negf_build_kernel: shapes plus device pointers into the caller's

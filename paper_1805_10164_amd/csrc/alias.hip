@@ -202,6 +202,7 @@ struct AliasArgs {
     int64_t ldP, pitch;
     int N, W;
     double open_cut;  // an injection row needs Tr Gamma_p > open_cut
+    double rowsum_tol;  // relative tolerance of the row-total check
 };
 
 // One workgroup of BT threads per row; thread t owns the items t + BT k (k < KM, n <= BT KM)
@@ -269,9 +270,9 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
         if (row == N) a.lead[(size_t)e * MCNEGF_LEAD_NTERMS + MCNEGF_LEAD_CL] = total;
         if (row == N + 1) a.lead[(size_t)e * MCNEGF_LEAD_NTERMS + MCNEGF_LEAD_CR] = total;
         if (!isfinite(total)) atomicOr(a.status, MCNEGF_FLAG_NONFINITE);
-        else if (row < N && total > 0.0 && fabs(total - ref) > 1e-8 * fabs(ref))
+        else if (row < N && total > 0.0 && fabs(total - ref) > a.rowsum_tol * fabs(ref))
             atomicOr(a.status, MCNEGF_FLAG_ROWSUM);
-        else if (row >= N && total > 0.0 && fabs(total - ref) > 1e-8 * fabs(ref))
+        else if (row >= N && total > 0.0 && fabs(total - ref) > a.rowsum_tol * fabs(ref))
             atomicOr(a.status, MCNEGF_FLAG_ROWSUM);
         if (row >= N && !(total > 0.0)) atomicOr(a.status, MCNEGF_FLAG_NOABSORB);
     }
@@ -502,7 +503,7 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
     }
 }
 
-hipError_t launch_alias_build(const mcnegf_kernel& k, hipStream_t s) {
+hipError_t launch_alias_build(const mcnegf_kernel& k, double rowsum_tol, hipStream_t s) {
     AliasArgs a;
     a.P = k.P;
     a.wL = k.wL;
@@ -519,6 +520,7 @@ hipError_t launch_alias_build(const mcnegf_kernel& k, hipStream_t s) {
     a.N = k.N;
     a.W = k.W;
     a.open_cut = 1e3 * k.delta_lead * k.t * k.W;
+    a.rowsum_tol = rowsum_tol;
     const int n = k.n_out;
     const size_t lds = (size_t)(n + 1) * 8 + (size_t)n * 2;
     // rows up to 1024 outcomes: 256 threads x 4 items; up to 1536: 256 x 6; up to 4096:

@@ -92,10 +92,12 @@ hipError_t launch_lead_sigma(const mcnegf_kernel& k, double gamma_l, double delt
                              hipStream_t s);
 hipError_t launch_rgf(const mcnegf_kernel& k, const double* onsite, hipStream_t s);
 hipError_t launch_fullinv(const mcnegf_kernel& k, hipStream_t s);
+hipError_t launch_fullinv_fp32(const mcnegf_kernel& k, hipStream_t s);
 hipError_t launch_fullinv_store_g(const mcnegf_kernel& k, double2* Gc, int64_t ldG,
                                   hipStream_t s);
 hipError_t launch_lead_terms(const mcnegf_kernel& k, hipStream_t s);
-hipError_t launch_alias_build(const mcnegf_kernel& k, hipStream_t s);
+// rowsum_tol: relative tolerance of the check of each row's total against its spectral value
+hipError_t launch_alias_build(const mcnegf_kernel& k, double rowsum_tol, hipStream_t s);
 hipError_t launch_walk(const mcnegf_kernel& k, uint64_t seed, uint32_t tag,
                        uint32_t walker_begin, uint32_t n_walkers, uint32_t max_steps,
                        int64_t* tallies, hipStream_t s);

@@ -204,8 +204,32 @@ static hipError_t launch_fullinv_w(const mcnegf_kernel& k, double2* Gc, int64_t 
 // lane (m, g): (-t) M[16 rt + m][4 s + g], read from the LDS-staged block.  A complex product
 // is four real products (re re, -im im into the real part; re im, im re into the imaginary).
 typedef double dmfma4 __attribute__((ext_vector_type(4)));
+typedef float fmfma4 __attribute__((ext_vector_type(4)));
 
-template <int W, int TC, int NW, bool STORE_G>
+// One 16x16x4 product on the matrix cores in the column state's precision.
+__device__ inline dmfma4 mfma4(double a, double b, dmfma4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline fmfma4 mfma4(float a, float b, fmfma4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename T> struct Mfma4;
+template <> struct Mfma4<double> { typedef dmfma4 type; };
+template <> struct Mfma4<float> { typedef fmfma4 type; };
+
+// Row of item r in lane group g within a 16-row tile: the FP64 product returns row 4 r + g,
+// the FP32 product row 4 g + r.  In both cases K-step s of the next product takes item
+// s & 3 of tile s >> 2 from every lane group, i.e. the contraction runs over the rows in the
+// order the accumulator holds them, and the A operand is read in that column order.
+template <typename T>
+__device__ inline int tile_row(int r, int g) {
+    return sizeof(T) == 8 ? 4 * r + g : 4 * g + r;
+}
+
+// T = double: FP64 products throughout.  T = float (a build with FP32 block products): the
+// column state and the products are FP32 (the staged FP64 blocks are rounded as they are
+// read), |G|^2, the exit weights and the corners are formed from the FP32 state in FP64.
+template <int W, int TC, int NW, bool STORE_G, typename T = double>
 __global__ void __launch_bounds__(64 * NW) fullinv_mfma_kernel(const double2* __restrict__ gL,
                                                           const double2* __restrict__ gR,
                                                           const double2* __restrict__ Gd,
@@ -251,38 +275,37 @@ __global__ void __launch_bounds__(64 * NW) fullinv_mfma_kernel(const double2* __
         l[tc] = cc / W;
         y0[tc] = cc - l[tc] * W;
     }
-    double vr[TC][RT][4], vi[TC][RT][4];
+    typedef typename Mfma4<T>::type acc4;
+    T vr[TC][RT][4], vi[TC][RT][4];
 
     // one slice: v <- (-t) M v with M the block staged at buf
     auto product = [&](const lds_double* buf) {
-        dmfma4 cr[TC][RT], ci[TC][RT];
+        acc4 cr[TC][RT], ci[TC][RT];
 #pragma unroll
         for (int tc = 0; tc < TC; ++tc)
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
-                cr[tc][rt] = dmfma4{0.0, 0.0, 0.0, 0.0};
-                ci[tc][rt] = dmfma4{0.0, 0.0, 0.0, 0.0};
+                cr[tc][rt] = acc4{0, 0, 0, 0};
+                ci[tc][rt] = acc4{0, 0, 0, 0};
             }
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                const int at = 2 * ((16 * rt + n) * W + 4 * s + g);
-                const double ar = mt * buf[at], ai = mt * buf[at + 1];
+                // column of M that K-step s pairs with lane group g (see tile_row)
+                const int kc = 16 * (s >> 2) + tile_row<T>(s & 3, g);
+                const int at = 2 * ((16 * rt + n) * W + kc);
+                const T ar = (T)(mt * buf[at]), ai = (T)(mt * buf[at + 1]);
                 // consecutive products go to different accumulators (2 TC independent chains)
 #pragma unroll
                 for (int tc = 0; tc < TC; ++tc) {
-                    cr[tc][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, vr[tc][s >> 2][s & 3],
-                                                                      cr[tc][rt], 0, 0, 0);
-                    ci[tc][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, vi[tc][s >> 2][s & 3],
-                                                                      ci[tc][rt], 0, 0, 0);
+                    cr[tc][rt] = mfma4(ar, vr[tc][s >> 2][s & 3], cr[tc][rt]);
+                    ci[tc][rt] = mfma4(ar, vi[tc][s >> 2][s & 3], ci[tc][rt]);
                 }
 #pragma unroll
                 for (int tc = 0; tc < TC; ++tc) {
-                    cr[tc][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, vi[tc][s >> 2][s & 3],
-                                                                      cr[tc][rt], 0, 0, 0);
-                    ci[tc][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, vr[tc][s >> 2][s & 3],
-                                                                      ci[tc][rt], 0, 0, 0);
+                    cr[tc][rt] = mfma4(-ai, vi[tc][s >> 2][s & 3], cr[tc][rt]);
+                    ci[tc][rt] = mfma4(ai, vr[tc][s >> 2][s & 3], ci[tc][rt]);
                 }
             }
         }
@@ -307,11 +330,11 @@ __global__ void __launch_bounds__(64 * NW) fullinv_mfma_kernel(const double2* __
             for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int y = 16 * rt + 4 * r + g;
+                    const int y = 16 * rt + tile_row<T>(r, g);
                     double2 d = cmk(0.0, 0.0);
                     if (here) d = Gde[(size_t)k * W * W + y * W + y0[tc]];
-                    vr[tc][rt][r] = here ? d.x : (before ? 0.0 : vr[tc][rt][r]);
-                    vi[tc][rt][r] = here ? d.y : (before ? 0.0 : vi[tc][rt][r]);
+                    vr[tc][rt][r] = here ? (T)d.x : (before ? (T)0 : vr[tc][rt][r]);
+                    vi[tc][rt][r] = here ? (T)d.y : (before ? (T)0 : vi[tc][rt][r]);
                 }
         }
     };
@@ -324,28 +347,28 @@ __global__ void __launch_bounds__(64 * NW) fullinv_mfma_kernel(const double2* __
             for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int y = 16 * rt + 4 * r + g;
+                    const int y = 16 * rt + tile_row<T>(r, g);
+                    const double xr = vr[tc][rt][r], xi = vi[tc][rt][r];
                     if (STORE_G)
-                        Ge[(size_t)(k * W + y) * ldG + col[tc]] = cmk(vr[tc][rt][r], vi[tc][rt][r]);
+                        Ge[(size_t)(k * W + y) * ldG + col[tc]] = cmk(xr, xi);
                     else
-                        Pe[(size_t)(k * W + y) * ldP + col[tc]] =
-                            vr[tc][rt][r] * vr[tc][rt][r] + vi[tc][rt][r] * vi[tc][rt][r];
+                        Pe[(size_t)(k * W + y) * ldP + col[tc]] = xr * xr + xi * xi;
                 }
         }
     };
     // Re v^+ Gamma v per column (Gamma real symmetric): u = Gamma v on the matrix cores, the
     // row sum of Re(conj(v) u) over the four lanes of each column; lane g = 0 gets the result.
     auto quad = [&](int tc) -> double {
-        dmfma4 ur[RT], ui[RT];
+        acc4 ur[RT], ui[RT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
-            ur[rt] = dmfma4{0.0, 0.0, 0.0, 0.0};
-            ui[rt] = dmfma4{0.0, 0.0, 0.0, 0.0};
+            ur[rt] = acc4{0, 0, 0, 0};
+            ui[rt] = acc4{0, 0, 0, 0};
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                const double a = gme[(16 * rt + n) * W + 4 * s + g];
-                ur[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, vr[tc][s >> 2][s & 3], ur[rt], 0, 0, 0);
-                ui[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, vi[tc][s >> 2][s & 3], ui[rt], 0, 0, 0);
+                const T a = (T)gme[(16 * rt + n) * W + 16 * (s >> 2) + tile_row<T>(s & 3, g)];
+                ur[rt] = mfma4(a, vr[tc][s >> 2][s & 3], ur[rt]);
+                ui[rt] = mfma4(a, vi[tc][s >> 2][s & 3], ui[rt]);
             }
         }
         double q = 0.0;
@@ -353,7 +376,8 @@ __global__ void __launch_bounds__(64 * NW) fullinv_mfma_kernel(const double2* __
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                q = fma(vr[tc][rt][r], ur[rt][r], fma(vi[tc][rt][r], ui[rt][r], q));
+                q = fma((double)vr[tc][rt][r], (double)ur[rt][r],
+                        fma((double)vi[tc][rt][r], (double)ui[rt][r], q));
         q += __shfl_xor(q, 16, 64);
         q += __shfl_xor(q, 32, 64);
         return q;
@@ -365,7 +389,7 @@ __global__ void __launch_bounds__(64 * NW) fullinv_mfma_kernel(const double2* __
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) vr[tc][rt][r] = vi[tc][rt][r] = 0.0;
+            for (int r = 0; r < 4; ++r) vr[tc][rt][r] = vi[tc][rt][r] = (T)0;
     stage_block<W, 64 * NW>(Ms, gRe + (size_t)kmin * W * W, tid);
     for (int k = kmin; k < L; ++k) {
         __syncthreads();
@@ -386,7 +410,7 @@ __global__ void __launch_bounds__(64 * NW) fullinv_mfma_kernel(const double2* __
                 for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        cRL[(16 * rt + 4 * r + g) * W + y0[tc]] = cmk(vr[tc][rt][r], vi[tc][rt][r]);
+                        cRL[(16 * rt + tile_row<T>(r, g)) * W + y0[tc]] = cmk(vr[tc][rt][r], vi[tc][rt][r]);
             }
         }
     }
@@ -396,7 +420,7 @@ __global__ void __launch_bounds__(64 * NW) fullinv_mfma_kernel(const double2* __
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) vr[tc][rt][r] = vi[tc][rt][r] = 0.0;
+            for (int r = 0; r < 4; ++r) vr[tc][rt][r] = vi[tc][rt][r] = (T)0;
     __syncthreads();
     stage_block<W, 64 * NW>(Ms, gLe + (size_t)kmax * W * W, tid);
     for (int k = kmax; k >= 0; --k) {
@@ -417,19 +441,19 @@ __global__ void __launch_bounds__(64 * NW) fullinv_mfma_kernel(const double2* __
                 for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        cLR[(16 * rt + 4 * r + g) * W + y0[tc]] = cmk(vr[tc][rt][r], vi[tc][rt][r]);
+                        cLR[(16 * rt + tile_row<T>(r, g)) * W + y0[tc]] = cmk(vr[tc][rt][r], vi[tc][rt][r]);
             }
         }
     }
 }
 
-template <int W, int TC, int NW, bool STORE_G>
+template <int W, int TC, int NW, bool STORE_G, typename T = double>
 static hipError_t launch_fullinv_mfma(const mcnegf_kernel& k, double2* Gc, int64_t ldG,
                                       hipStream_t s) {
     dim3 grid((k.N + 16 * TC * NW - 1) / (16 * TC * NW), k.nE);
     {
         MCNEGF_TIMED(STORE_G ? "fullinv_store_g_kernel" : "fullinv_kernel", s);
-        hipLaunchKernelGGL((fullinv_mfma_kernel<W, TC, NW, STORE_G>), grid, dim3(64 * NW), 0, s,
+        hipLaunchKernelGGL((fullinv_mfma_kernel<W, TC, NW, STORE_G, T>), grid, dim3(64 * NW), 0, s,
                            reinterpret_cast<const double2*>(k.gL),
                            reinterpret_cast<const double2*>(k.gR),
                            reinterpret_cast<const double2*>(k.Gd), k.gam_lead, k.L, k.t, k.p_pitch,
@@ -466,6 +490,13 @@ static hipError_t launch_fullinv_any(const mcnegf_kernel& k, double2* Gc, int64_
 
 hipError_t launch_fullinv(const mcnegf_kernel& k, hipStream_t s) {
     return launch_fullinv_any<false>(k, nullptr, 0, s);
+}
+
+// The full inverse with FP32 block products (W = 16 and 32 only; any other width is refused).
+hipError_t launch_fullinv_fp32(const mcnegf_kernel& k, hipStream_t s) {
+    if (k.W == 16) return launch_fullinv_mfma<16, 4, kFullinvWaves16, false, float>(k, nullptr, 0, s);
+    if (k.W == 32) return launch_fullinv_mfma<32, 2, kFullinvWaves32, false, float>(k, nullptr, 0, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_fullinv_store_g(const mcnegf_kernel& k, double2* Gc, int64_t ldG,

@@ -81,7 +81,9 @@ static bool valid_system(const mcnegf_system* s) {
     } else {
         return false;
     }
-    if (s->flags & ~(MCNEGF_BUILD_NO_ALIAS | MCNEGF_BUILD_NO_DIRECT)) return false;
+    if (s->flags & ~(MCNEGF_BUILD_NO_ALIAS | MCNEGF_BUILD_NO_DIRECT | MCNEGF_BUILD_FP32_PRODUCTS))
+        return false;
+    if ((s->flags & MCNEGF_BUILD_FP32_PRODUCTS) && s->W != 16 && s->W != 32) return false;
     return true;
 }
 
@@ -209,9 +211,15 @@ int32_t mc_negf_build_kernel(const mcnegf_system* sys, const double* d_onsite,
     if ((err = launch_lead_sigma(k, sys->gamma_l, sys->delta_lead, stream)) != hipSuccess)
         return hip_fail(err);
     if ((err = launch_rgf(k, d_onsite, stream)) != hipSuccess) return hip_fail(err);
-    if ((err = launch_fullinv(k, stream)) != hipSuccess) return hip_fail(err);
+    if ((err = (sys->flags & MCNEGF_BUILD_FP32_PRODUCTS) ? launch_fullinv_fp32(k, stream)
+                                                            : launch_fullinv(k, stream)) !=
+        hipSuccess)
+        return hip_fail(err);
     if ((err = launch_lead_terms(k, stream)) != hipSuccess) return hip_fail(err);
-    if (with_alias(sys) && (err = launch_alias_build(k, stream)) != hipSuccess)
+    // row totals against A_jj and Tr Gamma_p A: FP64 products agree to rounding, FP32 block
+    // products to their own rounding accumulated over the slices
+    const double rowsum_tol = (sys->flags & MCNEGF_BUILD_FP32_PRODUCTS) ? 1e-4 : 1e-8;
+    if (with_alias(sys) && (err = launch_alias_build(k, rowsum_tol, stream)) != hipSuccess)
         return hip_fail(err);
     *out = k;
     return MCNEGF_OK;

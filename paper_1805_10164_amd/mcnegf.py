@@ -154,12 +154,14 @@ def _ptr(t) -> ctypes.c_void_p:
 
 BUILD_NO_ALIAS = 0x1
 BUILD_NO_DIRECT = 0x2
+BUILD_FP32_PRODUCTS = 0x4
 
 
 def make_system(W: int, L: int, t: float = 1.0, lead_model: int = 0, gamma_l: float = 0.0,
                 delta_lead: float = 1e-10, flags: int = 0) -> System:
     """flags: BUILD_NO_ALIAS builds no alias tables (DIRECT current and gradient only),
-    BUILD_NO_DIRECT reserves nothing for the DIRECT solve (Monte Carlo only)."""
+    BUILD_NO_DIRECT reserves nothing for the DIRECT solve (Monte Carlo only),
+    BUILD_FP32_PRODUCTS runs the full inverse's block products in FP32 (W = 16, 32)."""
     return System(W, L, t, lead_model, gamma_l, delta_lead, flags)
 
 

@@ -215,3 +215,15 @@ def test_energy_grid_is_midpoint():
     E, w = M.energy_grid(-3.5, 3.5, 256)
     assert abs(E[0] - (-3.5 + 3.5 / 256)) < 1e-15 and abs(E[-1] - (3.5 - 3.5 / 256)) < 1e-15
     assert abs(w.sum() - 7.0) < 1e-12
+
+
+def test_fp32_products_only_at_widths_16_and_32():
+    lib = M.lib()
+    out = ctypes.c_uint64(0)
+    for W, ok in ((16, True), (32, True), (10, False), (8, False), (20, False)):
+        s = M.make_system(W, 20, flags=M.BUILD_FP32_PRODUCTS)
+        code = lib.mc_negf_workspace_bytes(ctypes.byref(s), 4, ctypes.byref(out))
+        assert (code == M.OK) == ok, (W, code)
+    # unknown flag bits are refused
+    s = M.make_system(16, 20, flags=0x8)
+    assert lib.mc_negf_workspace_bytes(ctypes.byref(s), 4, ctypes.byref(out)) == M.EINVAL

@@ -502,3 +502,37 @@ def test_every_narrow_width_blocks_and_direct_current(W):
     assert st == M.OK
     Tref = np.array([s.T_eff for s in sols])
     assert rel(T.cpu().numpy(), Tref) < 1e-10, W
+
+
+@pytest.mark.parametrize("W,L", [(16, 9), (32, 7)])
+def test_fp32_products_build_against_fp64_and_oracle(W, L):
+    # the full inverse's block products in FP32: |G|^2, the exit weights and T_eff carry FP32
+    # rounding only (well within 1e-5 relative at these lengths); the tables still sample
+    # within the walker's statistics
+    c = case(W=W, L=L, eta=0.05, disorder=0.3, nE=3, emin=-2.7, emax=2.2, seed=W + L)
+    k64 = gpu_build(c)
+    s32 = M.make_system(W, L, 1.0, 0, 0.0, 1e-10, M.BUILD_FP32_PRODUCTS)
+    ws = M.allocate_workspace(s32, len(c["E"]))
+    V = torch.tensor(c["V"], dtype=torch.float64, device=DEV)
+    g = torch.tensor(c["g"], dtype=torch.float64, device=DEV)
+    E = torch.tensor(c["E"], dtype=torch.float64, device=DEV)
+    k32 = M.mc_negf_build_kernel(s32, V, g, E, ws)
+    P64, P32 = k64.P().cpu().numpy(), k32.P().cpu().numpy()
+    scale = np.abs(P64).max(axis=2, keepdims=True)
+    errP = (np.abs(P32 - P64) / scale).max()
+    assert 0.0 < errP < 1e-5, errP  # FP32 rounding is present, and small
+    for f in ("wL", "wR"):
+        a, b = getattr(k64, f)().cpu().numpy(), getattr(k32, f)().cpu().numpy()
+        assert rel(b, a) < 1e-5, f
+    sols = oracle_solve(c)
+    Tref = np.array([s.T_eff for s in sols])
+    wt = torch.tensor(c["w"], device=DEV)
+    T = torch.empty(len(c["E"]), dtype=torch.float64, device=DEV)
+    sg = torch.empty_like(T)
+    st, I, _ = M.mc_negf_current(k32, 1, 0, None, wt, T, sg)
+    assert st == M.OK
+    assert rel(T.cpu().numpy(), Tref) < 1e-5
+    tal = torch.zeros((len(c["E"]), M.TALLY_N), dtype=torch.int64, device=DEV)
+    M.mc_negf_walk(k32, SEED, 0, 0, 0, 200_000, 1_000_000, tal)
+    st, I_mc, s_mc = M.mc_negf_current(k32, 0, 0, tal, wt, T, sg)
+    assert st == M.OK and abs(I_mc - D.current(sols, c["w"])) < 4 * s_mc
