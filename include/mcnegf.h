@@ -118,7 +118,8 @@ typedef struct mcnegf_system {
  * weights, the lead terms, the alias tables, the probe solve and all tallies stay FP64.
  * Only W = 16 and W = 32 (mc_negf_build_kernel returns MCNEGF_EINVAL for other widths);
  * |G_ij|^2 then carries FP32 rounding (relative error of order 1e-6 after hundreds of
- * slices), and so do the currents.  No refinement step is applied. */
+ * slices), and so do the currents, and the probe solve inside mc_negf_grad on such a build
+ * (its complex G is recomputed in FP64).  No refinement step is applied. */
 #define MCNEGF_BUILD_FP32_PRODUCTS 0x4u
 
 /*
