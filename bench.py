@@ -35,7 +35,12 @@ from paper_1805_10164_amd import mcnegf as M  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 FP64_VALU_PEAK_TFLOPS = 78.6
-ALIAS_ENTRY_BYTES = 4  # one packed alias entry read per step (the low threshold bits only on a 2^-20 tie)
+# Algorithmic bytes of one walk step: one alias entry of an FP64 threshold and an int32 alias
+# index.  The walker stores entries packed into 4 bytes (16 threshold bits and a 16-bit alias
+# index; the low 16 threshold bits are read only on a 2^-16 tie), and that figure is reported
+# beside the algorithmic one.
+STEP_BYTES = 12
+ALIAS_ENTRY_BYTES = 4
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -73,7 +78,7 @@ class Problem:
         # the DIRECT current alone needs no alias tables
         self.sys_direct = M.make_system(wl.W, wl.L, wl.t, wl.lead_model, wl.gamma_l,
                                         wl.delta_lead, M.BUILD_NO_ALIAS)
-        E, w = M.energy_grid(wl.emin, wl.emax, wl.n_energies)
+        E, w = inputs.energy_grid(wl.emin, wl.emax, wl.n_energies)
         self.V = torch.tensor(inputs.onsite(wl), device=dev)
         self.g = torch.tensor(inputs.dephasing(wl), device=dev)
         self.E = torch.tensor(E, device=dev)
@@ -118,7 +123,7 @@ def kernel_work(name, wl, walk_steps):
     N, W, nE = wl.N, wl.W, wl.n_energies
     n = N + 2
     if name == "walk_kernel":
-        return "hbm", walk_steps * ALIAS_ENTRY_BYTES / 1e9, "GB"
+        return "hbm", walk_steps * STEP_BYTES / 1e9, "GB"
     if name == "cholesky_kernel":
         # factorization N^3/3 plus the two forward substitutions of the bordered rows, 2 N^2
         return "mfma", nE * (N ** 3 / 3.0 + 2.0 * N * N) / 1e12, "TFLOP"
@@ -138,14 +143,74 @@ def roofline(name, wl, ms_per_launch, walk_steps):
     bound, amount, unit = w
     if unit == "GB":
         achieved = amount / (ms_per_launch * 1e-3)
-        return {"kernel": name, "bound": bound, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "algorithmic_per_launch": amount * 1e9, "avg_launch_ms": ms_per_launch}
+        r = {"kernel": name, "bound": bound, "achieved": achieved, "peak": HBM_PEAK_GBS,
+             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+             "algorithmic_per_launch": amount * 1e9, "avg_launch_ms": ms_per_launch}
+        if name == "walk_kernel":
+            r.update(walker_entry_figures(walk_steps, ms_per_launch))
+        return r
     achieved = amount / (ms_per_launch * 1e-3)
     # gfx950's FP64 matrix-core peak equals its FP64 vector FMA peak
     return {"kernel": name, "bound": bound, "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
             "algorithmic_per_launch": amount * 1e12, "avg_launch_ms": ms_per_launch}
+
+
+def walker_entry_figures(steps_per_launch, ms_per_launch):
+    """The walker's rate in walk steps and in the bytes of the packed entries it reads (4 per
+    step), beside the algorithmic 12 bytes per step of the roofline."""
+    sps = steps_per_launch / (ms_per_launch * 1e-3)
+    return {"bytes_per_step": STEP_BYTES, "steps_per_launch": steps_per_launch,
+            "steps_per_s": sps, "entry_bytes_per_step": ALIAS_ENTRY_BYTES,
+            "entry_gbs": sps * ALIAS_ENTRY_BYTES / 1e9,
+            "entry_frac": sps * ALIAS_ENTRY_BYTES / 1e9 / HBM_PEAK_GBS}
+
+
+def window_plan(n_steps, launches_per_step, cap):
+    """Steps per launch-timer window: whole steps, at most `cap` launches in a window (the
+    timer records at most that many), n_steps in all."""
+    per = max(1, cap // max(1, launches_per_step))
+    if launches_per_step > cap:
+        raise RuntimeError(f"one step issues {launches_per_step} launches; the launch timer "
+                           f"holds {cap}")
+    plan = []
+    left = n_steps
+    while left > 0:
+        plan.append(min(per, left))
+        left -= plan[-1]
+    return plan
+
+
+def require_complete(lt):
+    """Raise if a launch-timer window dropped records (its per-launch figures would cover
+    only part of the work that the wall time and the tallies cover)."""
+    if getattr(lt, "dropped", 0):
+        raise RuntimeError(f"launch timer dropped {lt.dropped} records")
+    return lt
+
+
+def timed_records(n_steps, launches_per_step, issue, cap=None):
+    """Issue n_steps steps (issue() issues one) under launch-timer windows of whole steps;
+    returns every launch's (name, ms).  Every window is checked for dropped records."""
+    cap = M.PROFILE_MAX if cap is None else cap
+    records = []
+    for n in window_plan(n_steps, launches_per_step, cap):
+        with M.LaunchTimes() as lt:
+            for _ in range(n):
+                issue()
+        records += require_complete(lt).records
+    return records
+
+
+def per_kernel_table(records, steps):
+    """Per kernel: launches, mean ms per launch and ms per step over `steps` steps."""
+    names = sorted(set(n for n, _ in records))
+    out = {}
+    for n in names:
+        ms = [m for k, m in records if k == n]
+        out[n] = {"launches": len(ms), "ms_per_launch": sum(ms) / len(ms),
+                  "ms_per_step": sum(ms) / steps}
+    return out
 
 
 def measured_traffic(name, workload="wire_W10_L100"):
@@ -190,7 +255,7 @@ def grad_bench(torch, dev, steps, warmup, with_cpu):
     wl = inputs.DIFF_W16_L200
     sysm = M.make_system(wl.W, wl.L, wl.t, wl.lead_model, wl.gamma_l, wl.delta_lead,
                          M.BUILD_NO_ALIAS)
-    E, w = M.energy_grid(wl.emin, wl.emax, wl.n_energies)
+    E, w = inputs.energy_grid(wl.emin, wl.emax, wl.n_energies)
     V = torch.tensor(inputs.onsite(wl), device=dev)
     g = torch.tensor(inputs.dephasing(wl), device=dev)
     tE, tw = torch.tensor(E, device=dev), torch.tensor(w, device=dev)
@@ -202,15 +267,21 @@ def grad_bench(torch, dev, steps, warmup, with_cpu):
     for _ in range(max(1, warmup)):
         M.mc_negf_grad(k, 0, tw, gws, dV, dg)
     torch.cuda.synchronize()
+    res = {}
+
+    def one_grad():
+        res["st"], res["I"] = M.mc_negf_grad(k, 0, tw, gws, dV, dg)
+
+    with M.LaunchTimes() as lt0:
+        one_grad()
+    per_grad = len(require_complete(lt0).records)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    with M.LaunchTimes() as lt:
-        for _ in range(steps):
-            st, I = M.mc_negf_grad(k, 0, tw, gws, dV, dg)
-        torch.cuda.synchronize()
+    records = timed_records(steps, per_grad, one_grad)
+    torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
-    names = sorted(set(n for n, _ in lt.records))
-    per_kernel = {n: {"launches": lt.count(n), "ms_per_launch": lt.total_ms(n) / lt.count(n)}
-                  for n in names}
+    st, I = res["st"], res["I"]
+    per_kernel = per_kernel_table(records, steps)
     adj_ms = per_kernel["adjoint_solve_kernel"]["ms_per_launch"]
     nbytes, flops = grad_work(wl)
     achieved = nbytes / 1e9 / (adj_ms * 1e-3)
@@ -262,7 +333,7 @@ def batched_bench(torch, dev, steps, warmup, budget_gb, seed):
     waves = [[i for i in order if wave_of[i] == wv] for wv in range(n_waves)]
     pool_bytes = max(sum((sizes[i] + 255) // 256 * 256 for i in wv) for wv in waves)
     pool = torch.empty(pool_bytes, dtype=torch.uint8, device=dev)
-    E, w = M.energy_grid(base.emin, base.emax, nE)
+    E, w = inputs.energy_grid(base.emin, base.emax, nE)
     tE, tw = torch.tensor(E, device=dev), torch.tensor(w, device=dev)
     V = [torch.tensor(inputs.onsite(wl), device=dev) for wl in wls]
     g = [torch.tensor(inputs.dephasing(wl), device=dev) for wl in wls]
@@ -357,8 +428,13 @@ def time_to_1pct(p: Problem, torch, seed, walk_on):
     MC, energy-sampled (the paper's estimator: energies drawn from the weights, constant
     estimator): build + a first batch of 4096 walkers over all energies, then likewise.
     DIRECT: build without alias tables + probe-system solve (deterministic; its error is the
-    quadrature's)."""
+    quadrature's).
+    The stop is sigma_I / I <= 1%, a one-sigma rule: the realized deviation from the DIRECT
+    current of the same system (|I_MC - I_DIRECT| / I_DIRECT, reported for every repetition)
+    lies within 1% with probability about 0.68 and within 3% with probability about 0.997."""
     mc_t, dir_t, mc_walkers, smp_t, smp_walkers = [], [], [], [], []
+    mc_I, smp_I = [], []
+    I_dir = None
     max_sampled = 1 << 24
     if walk_on and p.sampled_scratch is None:
         k0 = M.mc_negf_build_kernel(p.sys, p.V, p.g, p.E, p.ws)
@@ -380,6 +456,7 @@ def time_to_1pct(p: Problem, torch, seed, walk_on):
                 batch = next_batch(done, I, s, 1024, 1 << 24)
             mc_t.append(time.perf_counter() - t0)
             mc_walkers.append(done)
+            mc_I.append(I)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             k = M.mc_negf_build_kernel(p.sys, p.V, p.g, p.E, p.ws)
@@ -395,17 +472,32 @@ def time_to_1pct(p: Problem, torch, seed, walk_on):
                 batch = next_batch(done, I, s, 4096, max_sampled)
             smp_t.append(time.perf_counter() - t0)
             smp_walkers.append(done)
+            smp_I.append(I)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         k = M.mc_negf_build_kernel(p.sys_direct, p.V, p.g, p.E, p.ws)
-        M.mc_negf_current(k, 1, 0, None, p.w, p.T, p.sig)
+        _, I_dir, _ = M.mc_negf_current(k, 1, 0, None, p.w, p.T, p.sig)
         dir_t.append(time.perf_counter() - t0)
-    return {"eta": p.wl.eta,
-            "mc_ms": 1e3 * float(np.median(mc_t)) if mc_t else None,
-            "mc_walkers_per_energy": int(np.median(mc_walkers)) if mc_walkers else None,
-            "mc_energy_sampled_ms": 1e3 * float(np.median(smp_t)) if smp_t else None,
-            "mc_energy_sampled_walkers": int(np.median(smp_walkers)) if smp_walkers else None,
-            "direct_ms": 1e3 * float(np.median(dir_t))}
+    out = {"eta": p.wl.eta,
+           "mc_ms": 1e3 * float(np.median(mc_t)) if mc_t else None,
+           "mc_walkers_per_energy": int(np.median(mc_walkers)) if mc_walkers else None,
+           "mc_energy_sampled_ms": 1e3 * float(np.median(smp_t)) if smp_t else None,
+           "mc_energy_sampled_walkers": int(np.median(smp_walkers)) if smp_walkers else None,
+           "direct_ms": 1e3 * float(np.median(dir_t)), "I_direct": I_dir}
+    out.update(realized_errors(mc_I, smp_I, I_dir))
+    return out
+
+
+def realized_errors(mc_I, smp_I, I_dir):
+    """|I_MC - I_DIRECT| / I_DIRECT at the 1% stop of every repetition, for both estimators."""
+    out = {"stop_rule": "sigma_I / I <= 0.01 (one sigma: |error| <= 1% with p ~ 0.68, "
+                        "<= 3% with p ~ 0.997)"}
+    for key, vals in (("mc", mc_I), ("mc_energy_sampled", smp_I)):
+        if vals and I_dir:
+            errs = [abs(v - I_dir) / abs(I_dir) for v in vals]
+            out[f"{key}_rel_err_at_stop"] = errs
+            out[f"{key}_rel_err_at_stop_max"] = max(errs)
+    return out
 
 
 def scale_bench(torch, dev, steps, warmup, with_cpu, seed):
@@ -414,7 +506,7 @@ def scale_bench(torch, dev, steps, warmup, with_cpu, seed):
     1e7 walks per energy, MC and DIRECT currents, all FP64.  One energy's tables are 1 GB, so
     here every walk step reads memory (no table stays in L2)."""
     wl = inputs.SCALE_W32_L500
-    Eall, wall_w = M.energy_grid(wl.emin, wl.emax, wl.n_energies)
+    Eall, wall_w = inputs.energy_grid(wl.emin, wl.emax, wl.n_energies)
     n_batches = wl.n_energies // inputs.SCALE_BATCH
     pick = np.arange(0, wl.n_energies, n_batches)
     E, w = Eall[pick], wall_w[pick]
@@ -587,7 +679,7 @@ def cpu_baseline(wl: inputs.Workload, seed: int):
     energies with 25 000 walkers each, at the middle dephasing rate."""
     from oracle import dense as D
     from oracle import walker as OW
-    E, _ = M.energy_grid(wl.emin, wl.emax, wl.n_energies)
+    E, _ = inputs.energy_grid(wl.emin, wl.emax, wl.n_energies)
     idx = np.linspace(0, wl.n_energies - 1, 24).round().astype(int)
     V, g = inputs.onsite(wl), inputs.dephasing(wl)
     nw = 25_000
@@ -651,22 +743,28 @@ def main():
     if args.calib_copy_mb > 0:
         calibration_copy(torch, dev, args.calib_copy_mb)
 
+    def one_step():
+        for p in probs:
+            run_step(p, walkers, seed, walk_on)
+
+    # launches per step, from one more untimed step
+    with M.LaunchTimes() as lt0:
+        one_step()
+    per_step = len(require_complete(lt0).records)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    with M.LaunchTimes() as lt:
-        for it in range(args.steps):
-            for p in probs:
-                run_step(p, walkers, seed, walk_on)
-        torch.cuda.synchronize()
+    records = timed_records(args.steps, per_step, one_step)
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     # every step walks the same seeded walkers, so each step's counts are the last step's
     results = [(p, step_results(p, walk_on)) for p in probs]
     steps_total = args.steps * sum(int(p.tal[:, M.TALLY_STEPS].sum()) for p in probs) if walk_on else 0
 
-    names = sorted(set(n for n, _ in lt.records))
-    per_kernel = {n: {"launches": lt.count(n), "ms_per_launch": lt.total_ms(n) / lt.count(n),
-                      "ms_per_step": lt.total_ms(n) / args.steps} for n in names}
-    dominant = max(names, key=lambda n: lt.total_ms(n))
-    walk_steps_per_launch = steps_total / max(1, lt.count("walk_kernel")) if walk_on else 0
+    per_kernel = per_kernel_table(records, args.steps)
+    names = sorted(per_kernel)
+    dominant = max(names, key=lambda n: per_kernel[n]["ms_per_step"])
+    n_walk = per_kernel.get("walk_kernel", {}).get("launches", 0)
+    walk_steps_per_launch = steps_total / n_walk if (walk_on and n_walk) else 0
     roof = roofline(dominant, base, per_kernel[dominant]["ms_per_launch"], walk_steps_per_launch)
     if roof is not None:
         roof["traffic"] = measured_traffic(dominant)
@@ -707,7 +805,8 @@ def main():
         "rooflines": {n: r for n, r in rooflines.items() if r is not None},
     }
     if walk_on:
-        line["walker_kernel_steps_per_s"] = steps_total / (lt.total_ms("walk_kernel") * 1e-3)
+        line["walker_kernel_steps_per_s"] = steps_total / (
+            per_kernel["walk_kernel"]["ms_per_step"] * args.steps * 1e-3)
     if not args.no_ttp:
         line["time_to_1pct"] = [time_to_1pct(p, torch, seed, walk_on) for p in probs]
     if not args.no_cpu_baseline:

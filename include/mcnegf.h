@@ -194,7 +194,8 @@ int32_t mc_negf_build_kernel(const mcnegf_system* sys, const double* d_onsite,
  *   seed, realization  key of the Philox4x32-10 streams; realization < 2^30.
  *   inject_lead        0: walkers start in the L injection row, 1: in the R row.
  *   walker_begin, n_walkers_per_energy  walker indices [walker_begin, walker_begin + n)
- *                      are walked at every energy; walker_begin + n <= 2^32.
+ *                      are walked at every energy; walker_begin + n < 2^32 (the range
+ *                      end is held in 32 bits), else MCNEGF_EINVAL.
  *   max_steps          walks still inside after max_steps draws are counted as truncated
  *                      (the injection draw counts as one step); >= 1.
  *   d_tallies          [nE][MCNEGF_TALLY_N] int64 device, accumulated (+=).
@@ -270,8 +271,9 @@ int32_t mc_negf_grad(const mcnegf_kernel* k, uint32_t inject_lead, const double*
  * of the weights in index order) and then walks exactly as in mc_negf_walk at energy k; its
  * counts go to d_tallies[k] (accumulated).  The walkers are sorted by energy on the device
  * and walked in one launch; everything is asynchronous (capturable).  Estimate the current
- * with mc_negf_current mode 2.  Needs nE <= 16384 and a kernel with alias tables; d_scratch
- * (caller-owned, 256-byte aligned) of >= mc_negf_walk_sampled_bytes(k, n_walkers) bytes.
+ * with mc_negf_current mode 2.  Needs nE <= 16384, walker_begin + n_walkers < 2^32 and a
+ * kernel with alias tables; d_scratch (caller-owned, 256-byte aligned) of
+ * >= mc_negf_walk_sampled_bytes(k, n_walkers) bytes.
  * A negative or non-finite weight counts as 0 and sets MCNEGF_FLAG_NONFINITE.
  */
 int32_t mc_negf_walk_sampled_bytes(const mcnegf_kernel* k, uint64_t n_walkers,
@@ -304,7 +306,8 @@ int32_t mc_negf_current_async(const mcnegf_kernel* k, int32_t mode, uint32_t inj
  *   mc_negf_walk; d_tallies[i] is kernel i's [nE][MCNEGF_TALLY_N] tally array (device,
  *   accumulated).  Copies the table from the host and synchronises `stream`: call it before
  *   a graph capture, not inside one.  The kernels' workspaces must outlive the batch.
- * mc_negf_walk_batch: walk walkers [walker_begin, walker_begin + n_walkers_per_energy) of
+ * mc_negf_walk_batch: walk walkers [walker_begin, walker_begin + n_walkers_per_energy)
+ *   (walker_begin + n_walkers_per_energy < 2^32) of
  *   every unit; one kernel launch, asynchronous, capturable.  cfg NULL = the default shape.
  * mc_negf_walk_batch_autotune: time every candidate launch shape (walker slots per lane
  *   1-4, workgroup size 64 / 256, chunk of 2 / 8 / 32 walks per slot, XCD groups 1 / 8) on

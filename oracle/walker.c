@@ -87,14 +87,19 @@ static void stream_pair(stream_t *s, uint32_t n, uint32_t *a, uint32_t *b)
     *b = s->words[2 * (n & 1) + 1];
 }
 
-static uint32_t lemire_bucket(stream_t *s, uint32_t n_step, uint32_t a, uint32_t nout)
+/* Lemire's bucket of step n_step from its first word a; *redraws (if not NULL) receives the
+ * number of rejected words before the accepted one. */
+static uint32_t lemire_bucket_count(stream_t *s, uint32_t n_step, uint32_t a, uint32_t nout,
+                                    uint32_t *redraws)
 {
     uint32_t r = 0;
     for (;;) {
         uint64_t m = (uint64_t)a * (uint64_t)nout;
         uint32_t lo = (uint32_t)m;
-        if (lo >= nout || lo >= (uint32_t)(0u - nout) % nout)
+        if (lo >= nout || lo >= (uint32_t)(0u - nout) % nout) {
+            if (redraws) *redraws = r;
             return (uint32_t)(m >> 32);
+        }
         ++r;
         uint32_t ctr[4] = {n_step, s->w, s->k, s->tag | 0x80000000u};
         uint32_t key[2] = {s->key[0], s->key[1] ^ r};
@@ -102,6 +107,11 @@ static uint32_t lemire_bucket(stream_t *s, uint32_t n_step, uint32_t a, uint32_t
         oracle_philox4x32_10(ctr, key, out);
         a = out[0];
     }
+}
+
+static uint32_t lemire_bucket(stream_t *s, uint32_t n_step, uint32_t a, uint32_t nout)
+{
+    return lemire_bucket_count(s, n_step, a, nout, NULL);
 }
 
 /* Paper's step-6' sampler on a dense weight row (Sec. III B). */
@@ -280,6 +290,58 @@ int oracle_walk_sampled_alias(const uint32_t *thr, const int32_t *alias, int64_t
     if (pitch < n) return -1;
     return walk_sampled_impl(1, NULL, thr, alias, pitch, nE, n, weights, seed, realization,
                              inject_lead, walker_begin, n_walkers, max_steps, tallies);
+}
+
+/*
+ * Search for rejected bucket words: walkers w of [w_begin, w_begin + count) at energy index k
+ * whose draw of step n_step over nout outcomes needs at least min_redraws redraws (Lemire's
+ * rejection above).  Writes up to max_out walker indices, their redraw counts and their
+ * accepted buckets (in increasing walker order) and returns how many walkers qualify in all.
+ */
+int64_t oracle_find_redraws(uint64_t seed, uint32_t realization, uint32_t inject_lead,
+                            uint32_t k, uint32_t n_step, uint32_t nout, uint64_t w_begin,
+                            uint64_t count, uint32_t min_redraws, uint32_t *out_w,
+                            uint32_t *out_r, uint32_t *out_c, int64_t max_out)
+{
+    if (nout < 1 || inject_lead > 1 || realization >= (1u << 30)) return -1;
+    if (w_begin + count > 0x100000000ull) return -1;
+    const uint32_t tag = (realization << 1) | inject_lead;
+    const uint32_t thresh = (uint32_t)(0u - nout) % nout;
+    int64_t found = 0;
+    const int64_t nblk = 4096;
+    const int64_t blocks = ((int64_t)count + nblk - 1) / nblk;
+#pragma omp parallel for schedule(static) ordered
+    for (int64_t b = 0; b < blocks; ++b) {
+        uint32_t hit_w[64], hit_r[64], hit_c[64];
+        int nh = 0;
+        const uint64_t i0 = (uint64_t)b * nblk;
+        const uint64_t i1 = i0 + nblk < count ? i0 + nblk : count;
+        for (uint64_t i = i0; i < i1; ++i) {
+            stream_t st;
+            stream_init(&st, seed, (uint32_t)(w_begin + i), k, tag);
+            uint32_t a, bb;
+            stream_pair(&st, n_step, &a, &bb);
+            if ((uint32_t)((uint64_t)a * nout) >= thresh) continue;
+            uint32_t r = 0;
+            const uint32_t c = lemire_bucket_count(&st, n_step, a, nout, &r);
+            if (r >= min_redraws && nh < 64) {
+                hit_w[nh] = (uint32_t)(w_begin + i);
+                hit_r[nh] = r;
+                hit_c[nh] = c;
+                ++nh;
+            }
+        }
+#pragma omp ordered
+        for (int h = 0; h < nh; ++h) {
+            if (found < max_out) {
+                out_w[found] = hit_w[h];
+                out_r[found] = hit_r[h];
+                out_c[found] = hit_c[h];
+            }
+            ++found;
+        }
+    }
+    return found;
 }
 
 int oracle_num_threads(void)

@@ -139,6 +139,38 @@ def walk_sampled_alias(thr, alias, weights, seed, realization, inject_lead, walk
     return tallies
 
 
+def mc_current(tallies, c, weights, inject_lead=0):
+    """Per-energy transmission estimates, their standard errors and the current from exit
+    counts of walks injected at lead p (p = inject_lead; the collecting lead q is the other
+    one).  Every walker scores X = c_p [exit at q] (Eq. (66), c_p = Tr Gamma_p A, the total
+    of the injection row); a truncated walk scores 0 and still counts as a walker.  Per
+    energy k with N_k walkers of which R_k exit at q:
+        T_k = c_k R_k / N_k,
+        sigma_k = sqrt(s^2 / N_k), s^2 = the sample variance (divisor N_k - 1) of the N_k
+                  scores, i.e. c_k sqrt(p (1 - p) / (N_k - 1)) with p = R_k / N_k,
+        I = sum_k w_k T_k,  sigma_I = sqrt(sum_k w_k^2 sigma_k^2)  (midpoint rule, Sec. III C;
+                  energies walked independently).
+    Returns (T[nE], sigma[nE], I, sigma_I)."""
+    t = np.asarray(tallies, dtype=np.int64)
+    c = np.asarray(c, dtype=np.float64)
+    w = np.asarray(weights, dtype=np.float64)
+    nE = t.shape[0]
+    T = np.zeros(nE)
+    sig = np.zeros(nE)
+    for k in range(nE):
+        walkers = int(t[k, 0] + t[k, 1] + t[k, 2])
+        hits = int(t[k, 1] if inject_lead == 0 else t[k, 0])
+        if walkers <= 0:
+            continue
+        p = hits / walkers
+        T[k] = c[k] * p
+        if walkers > 1:
+            sig[k] = c[k] * np.sqrt(p * (1.0 - p) / (walkers - 1))
+    I = float(np.sum(w * T))
+    sI = float(np.sqrt(np.sum(w * w * sig * sig)))
+    return T, sig, I, sI
+
+
 def sampled_current(tallies, c, weights, inject_lead=0):
     """(I, sigma_I) of energy-sampled walks: the variable X = W c_p(E_k) when the walker exits
     at the collecting lead, 0 otherwise (Eq. (66) with the energy density h proportional to
@@ -158,3 +190,26 @@ def sampled_current(tallies, c, weights, inject_lead=0):
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def find_redraws(seed, realization, inject_lead, k, n_step, nout, w_begin, count, min_redraws,
+                 max_out=64):
+    """Walkers of [w_begin, w_begin + count) at energy index k whose step-n_step bucket over
+    nout outcomes needs at least min_redraws redraws of Lemire's rejection: (number found,
+    [(walker, redraws, accepted bucket), ...] for the first max_out of them)."""
+    L = lib()
+    f = L.oracle_find_redraws
+    f.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                  ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
+                  ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_int64]
+    f.restype = ctypes.c_int64
+    ow = np.zeros(max_out, np.uint32)
+    orr = np.zeros(max_out, np.uint32)
+    oc = np.zeros(max_out, np.uint32)
+    n = f(seed, realization, inject_lead, k, n_step, nout, w_begin, count, min_redraws,
+          ow.ctypes.data, orr.ctypes.data, oc.ctypes.data, max_out)
+    if n < 0:
+        raise ValueError("oracle_find_redraws rejected its arguments")
+    m = min(int(n), max_out)
+    return int(n), [(int(ow[i]), int(orr[i]), int(oc[i])) for i in range(m)]

@@ -231,8 +231,9 @@ int32_t mc_negf_walk(const mcnegf_kernel* k, uint64_t seed, uint32_t realization
     if (!valid_kernel(k) || !k->alias || !k->alias_lo || !d_tallies || inject_lead > 1 ||
         realization >= (1u << 30) || max_steps < 1)
         return MCNEGF_EINVAL;
-    if (walker_begin + n_walkers_per_energy > 0x100000000ull ||
-        walker_begin >= 0x100000000ull)
+    // walker indices and the end of the range are held in 32 bits
+    if (walker_begin >= 0x100000000ull || n_walkers_per_energy >= 0x100000000ull ||
+        walker_begin + n_walkers_per_energy >= 0x100000000ull)
         return MCNEGF_EINVAL;
     if (n_walkers_per_energy == 0) return MCNEGF_OK;
     const uint32_t tag = (realization << 1) | inject_lead;
@@ -397,7 +398,8 @@ int32_t mc_negf_walk_sampled(const mcnegf_kernel* k, uint64_t seed, uint32_t rea
         !d_scratch || inject_lead > 1 || realization >= (1u << 30) || max_steps < 1 ||
         k->nE > kMaxSampledEnergies)
         return MCNEGF_EINVAL;
-    if (walker_begin >= 0x100000000ull || walker_begin + n_walkers > 0x100000000ull)
+    if (walker_begin >= 0x100000000ull || n_walkers >= 0x100000000ull ||
+        walker_begin + n_walkers >= 0x100000000ull)
         return MCNEGF_EINVAL;
     if (((uintptr_t)d_scratch & 255u) != 0) return MCNEGF_EWS;
     SampledScratch sc;
@@ -492,7 +494,8 @@ int32_t mc_negf_walk_batch(const mcnegf_batch* b, uint64_t seed, uint64_t walker
                            uint64_t n_walkers_per_energy, uint32_t max_steps,
                            const mcnegf_walk_config* cfg, hipStream_t stream) {
     if (!valid_batch(b) || max_steps < 1) return MCNEGF_EINVAL;
-    if (walker_begin >= 0x100000000ull || walker_begin + n_walkers_per_energy > 0x100000000ull)
+    if (walker_begin >= 0x100000000ull || n_walkers_per_energy >= 0x100000000ull ||
+        walker_begin + n_walkers_per_energy >= 0x100000000ull)
         return MCNEGF_EINVAL;
     const mcnegf_walk_config c = cfg ? *cfg : default_walk_config();
     if (!valid_walk_config(c)) return MCNEGF_EINVAL;

@@ -280,7 +280,7 @@ __global__ void __launch_bounds__(256) walk_kernel(WalkArgs A) {
         cel = grp + q * G;
         clq = q * A.n_out;
         next = A.wbegin + (id - q * A.chunks_per_energy) * A.chunk;
-        wend = min(next + A.chunk, A.wend);
+        wend = (uint32_t)min((uint64_t)next + A.chunk, (uint64_t)A.wend);
     };
     if (cid < total) open_chunk(cid);
 
@@ -526,10 +526,10 @@ __global__ void walk_batch_kernel(WalkBatchArgs A) {
         uint32_t next, wend;
         if (per_unit) {
             next = (cid - A.chunk_start[u]) * A.chunk;
-            wend = min(next + A.chunk, U.nw);
+            wend = (uint32_t)min((uint64_t)next + A.chunk, (uint64_t)U.nw);
         } else {
             next = A.wbegin + (cid - q * A.chunks_per_unit) * A.chunk;
-            wend = min(next + A.chunk, A.wend);
+            wend = (uint32_t)min((uint64_t)next + A.chunk, (uint64_t)A.wend);
         }
         const uint32_t n_out = U.n_out, N = U.N;
         const uint32_t thresh = (0u - n_out) % n_out;

@@ -1,8 +1,9 @@
 """Seeded synthetic workloads shared by the HIP path's callers and the oracle's tests.
 
 This module holds only workload definitions and seeded random inputs (onsite disorder,
-per-site dephasing rates).  It contains none of the method's arithmetic: no Green's
-functions, no transmissions, no quadrature.
+per-site dephasing rates) and the energy points and weights of a workload's window, which
+the library takes as inputs.  It contains none of the method's arithmetic: no Green's
+functions, no transmissions, no walks, no sums over energies.
 
 The workloads stand in for the paper's CdTe nanowires (Sec. IV: two-by-two unit-cell
 cross-section, 32x32 Hamiltonian blocks, lengths of tens of unit cells, dephasing rates of a
@@ -112,3 +113,11 @@ def dephasing(w: Workload) -> np.ndarray:
 def random_sites(n: int, seed: int, lo: float, hi: float) -> np.ndarray:
     """Seeded uniform values, used by tests for random onsite or dephasing arrays."""
     return np.random.default_rng(seed).uniform(lo, hi, size=n).astype(np.float64)
+
+
+def energy_grid(emin: float, emax: float, n: int):
+    """Energy points and weights of a window [emin, emax] (caller inputs of the library): the
+    centres of n equal cells and the cell width as every point's weight, i.e. the midpoint
+    rule of Sec. III C.  The library forms the weighted sum over energies itself."""
+    dE = (emax - emin) / n
+    return emin + (np.arange(n) + 0.5) * dE, np.full(n, dE)

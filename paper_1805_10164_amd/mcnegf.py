@@ -165,12 +165,6 @@ def make_system(W: int, L: int, t: float = 1.0, lead_model: int = 0, gamma_l: fl
     return System(W, L, t, lead_model, gamma_l, delta_lead, flags)
 
 
-def energy_grid(emin: float, emax: float, n: int):
-    """Midpoint quadrature on [emin, emax] with n cells (Sec. III C): nodes and weights."""
-    dE = (emax - emin) / n
-    return emin + (np.arange(n) + 0.5) * dE, np.full(n, dE)
-
-
 class Kernel:
     """A built kernel handle plus the torch tensors it borrows (workspace, gamma, energies)."""
 

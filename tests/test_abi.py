@@ -7,6 +7,7 @@ import subprocess
 
 import pytest
 
+from paper_1805_10164_amd import inputs
 from paper_1805_10164_amd import mcnegf as M
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -97,6 +98,14 @@ def test_host_validation_rejects_before_any_gpu_call():
     assert lib.mc_negf_walk(ctypes.byref(ks), 1, 1 << 30, 0, 0, 10, 10, t, z) == M.EINVAL  # realization
     assert lib.mc_negf_walk(ctypes.byref(ks), 1, 0, 0, 0, 10, 0, t, z) == M.EINVAL       # max_steps
     assert lib.mc_negf_walk(ctypes.byref(ks), 1, 0, 0, 1 << 32, 1, 10, t, z) == M.EINVAL  # range
+    # the end of the walker range is held in 32 bits: it must stay below 2^32
+    assert lib.mc_negf_walk(ctypes.byref(ks), 1, 0, 0, 0, 1 << 32, 10, t, z) == M.EINVAL
+    assert lib.mc_negf_walk(ctypes.byref(ks), 1, 0, 0, 5, (1 << 32) - 5, 10, t, z) == M.EINVAL
+    w = ctypes.c_void_p(4096)
+    assert lib.mc_negf_walk_sampled(ctypes.byref(ks), 1, 0, 0, 0, 1 << 32, 10, w, t, w, 1 << 40,
+                                    z) == M.EINVAL
+    assert lib.mc_negf_walk_sampled(ctypes.byref(ks), 1, 0, 0, 7, (1 << 32) - 7, 10, w, t, w,
+                                    1 << 40, z) == M.EINVAL
     out = (ctypes.c_double * 2)()
     assert lib.mc_negf_current(ctypes.byref(ks), 0, 0, z, z, z, z,
                                ctypes.cast(out, ctypes.POINTER(ctypes.c_double)), z) == M.EINVAL
@@ -203,6 +212,8 @@ def test_batch_and_graph_validation_without_gpu():
     bad = M.walk_config(groups=4)
     assert lib.mc_negf_walk_batch(ctypes.byref(b), 1, 0, 10, 10, ctypes.byref(bad), z) == M.EINVAL
     assert lib.mc_negf_walk_batch(ctypes.byref(b), 1, 1 << 32, 1, 10, None, z) == M.EINVAL
+    assert lib.mc_negf_walk_batch(ctypes.byref(b), 1, 0, 1 << 32, 10, None, z) == M.EINVAL
+    assert lib.mc_negf_walk_batch(ctypes.byref(b), 1, 3, (1 << 32) - 3, 10, None, z) == M.EINVAL
     assert lib.mc_negf_walk_batch(ctypes.byref(b), 1, 0, 10, 0, None, z) == M.EINVAL
     out = (ctypes.c_double * 2)()
     assert lib.mc_negf_current_async(ctypes.byref(ks[0]), 2, 0, z, z, z, z, z, z) == M.EINVAL
@@ -212,7 +223,7 @@ def test_batch_and_graph_validation_without_gpu():
 
 
 def test_energy_grid_is_midpoint():
-    E, w = M.energy_grid(-3.5, 3.5, 256)
+    E, w = inputs.energy_grid(-3.5, 3.5, 256)
     assert abs(E[0] - (-3.5 + 3.5 / 256)) < 1e-15 and abs(E[-1] - (3.5 - 3.5 / 256)) < 1e-15
     assert abs(w.sum() - 7.0) < 1e-12
 

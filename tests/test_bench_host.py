@@ -34,7 +34,8 @@ def test_next_batch_bounds():
 def test_kernel_work_of_the_wire():
     wl = inputs.WIRE_W10_L100
     N, n, nE = wl.N, wl.N + 2, wl.n_energies
-    assert bench.kernel_work("walk_kernel", wl, 1e8) == ("hbm", 1e8 * 4 / 1e9, "GB")
+    # one alias entry (FP64 threshold + int32 alias) per step: 12 algorithmic bytes
+    assert bench.kernel_work("walk_kernel", wl, 1e8) == ("hbm", 1e8 * 12 / 1e9, "GB")
     bound, amount, unit = bench.kernel_work("cholesky_kernel", wl, 0)
     assert (bound, unit) == ("mfma", "TFLOP")
     assert amount == pytest.approx(nE * (N ** 3 / 3 + 2 * N * N) / 1e12)
@@ -48,8 +49,12 @@ def test_kernel_work_of_the_wire():
 def test_roofline_fraction():
     wl = inputs.WIRE_W10_L100
     r = bench.roofline("walk_kernel", wl, 0.5, 1e8)
-    assert r["achieved"] == pytest.approx(0.4 / 0.5e-3)
+    assert r["achieved"] == pytest.approx(1.2 / 0.5e-3)
     assert r["frac"] == pytest.approx(r["achieved"] / bench.HBM_PEAK_GBS)
+    # the packed 4-byte entries the walker reads, beside the algorithmic bytes
+    assert r["steps_per_s"] == pytest.approx(1e8 / 0.5e-3)
+    assert r["entry_gbs"] == pytest.approx(0.4 / 0.5e-3)
+    assert r["entry_frac"] == pytest.approx(r["frac"] / 3)
     r = bench.roofline("cholesky_kernel", wl, 3.0, 0)
     assert r["unit"] == "TFLOP/s" and r["frac"] == pytest.approx(r["achieved"] / 78.6)
 
@@ -87,3 +92,79 @@ def test_committed_summaries_name_existing_sources():
             rec = json.load(open(os.path.join(prof, f)))
             assert os.path.exists(os.path.join(ROOT, rec["source"])), f
             assert rec["hbm_bytes_per_launch"] > 0, f
+
+
+def test_window_plan_holds_whole_steps_within_the_timer():
+    for steps, per, cap in ((20, 66, 512), (3, 66, 512), (1, 512, 512), (100, 7, 512), (5, 1, 2)):
+        plan = bench.window_plan(steps, per, cap)
+        assert sum(plan) == steps and all(n * per <= cap for n in plan)
+    with pytest.raises(RuntimeError):
+        bench.window_plan(2, 600, 512)
+
+
+class FakeTimes:
+    """Stands in for the library's launch timer: records at most `cap` launches of a window
+    and counts the rest as dropped, as the library does."""
+    cap = 512
+
+    def __init__(self):
+        self.records, self.dropped = [], 0
+
+    def __enter__(self):
+        FakeTimes.current = self
+        return self
+
+    def __exit__(self, *exc):
+        FakeTimes.current = None
+        return False
+
+    @classmethod
+    def launch(cls, name, ms):
+        w = cls.current
+        if len(w.records) < cls.cap:
+            w.records.append((name, ms))
+        else:
+            w.dropped += 1
+
+
+def test_timed_records_cover_every_step(monkeypatch):
+    # a step of 66 launches (8 of them walker launches of 0.5 ms) timed for 20 steps: every
+    # launch is recorded, so per-launch figures and per-step sums cover all 20 steps
+    monkeypatch.setattr(bench.M, "LaunchTimes", FakeTimes)
+
+    def step():
+        for i in range(66):
+            FakeTimes.launch("walk_kernel" if i < 8 else "other_kernel", 0.5 if i < 8 else 0.1)
+
+    rec = bench.timed_records(20, 66, step)
+    assert len(rec) == 20 * 66
+    pk = bench.per_kernel_table(rec, 20)
+    assert pk["walk_kernel"]["launches"] == 160
+    assert pk["walk_kernel"]["ms_per_launch"] == pytest.approx(0.5)
+    assert pk["walk_kernel"]["ms_per_step"] == pytest.approx(4.0)
+    assert sum(v["ms_per_step"] for v in pk.values()) == pytest.approx(4.0 + 58 * 0.1)
+
+
+def test_a_window_that_drops_records_raises(monkeypatch):
+    monkeypatch.setattr(bench.M, "LaunchTimes", FakeTimes)
+
+    def step():
+        for _ in range(66):
+            FakeTimes.launch("k", 1.0)
+
+    with FakeTimes() as lt:
+        for _ in range(20):
+            step()
+    assert lt.dropped == 20 * 66 - 512
+    with pytest.raises(RuntimeError):
+        bench.require_complete(lt)
+    # a plan that claims fewer launches per step than are issued also overflows and raises
+    with pytest.raises(RuntimeError):
+        bench.timed_records(20, 10, step)
+
+
+def test_realized_errors_at_the_stop():
+    r = bench.realized_errors([1.01, 0.98], [1.0], 1.0)
+    assert r["mc_rel_err_at_stop"] == pytest.approx([0.01, 0.02])
+    assert r["mc_rel_err_at_stop_max"] == pytest.approx(0.02)
+    assert r["mc_energy_sampled_rel_err_at_stop"] == [0.0]

@@ -1,8 +1,10 @@
 """Batched walks over many built kernels, launch-shape autotuning and HIP graph replay.
 
-The batched walker must reproduce mc_negf_walk's tallies bit for bit (a walker's path depends
-only on (seed, step, walker, energy, tag)), for every launch shape; a captured graph of the
-Monte Carlo step must give, on every replay, exactly the eager results.
+The batched walker must reproduce mc_negf_walk's tallies and the oracle's C walker on the same
+tables bit for bit (a walker's path depends only on (seed, step, walker, energy, tag)), for
+every launch shape; the Monte Carlo current of a batched system must lie within 3 sigma of
+its DIRECT current; a captured graph of the Monte Carlo step must give, on every replay,
+exactly the eager results.
 """
 import numpy as np
 import pytest
@@ -11,6 +13,8 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
+from oracle import dense as D  # noqa: E402
+from oracle import walker as OW  # noqa: E402
 from paper_1805_10164_amd import inputs  # noqa: E402
 from paper_1805_10164_amd import mcnegf as M  # noqa: E402
 
@@ -26,7 +30,7 @@ SHAPES = [  # (W, L, nE, eta, realization)
 
 def build(W, L, nE, eta, r, flags=0):
     sysm = M.make_system(W, L, flags=flags)
-    E, w = M.energy_grid(-2.5, 2.5, nE)
+    E, w = inputs.energy_grid(-2.5, 2.5, nE)
     V = torch.tensor(inputs.random_sites(W * L, 500 + r, -0.4, 0.4), device=DEV)
     g = torch.full((W * L,), eta, dtype=torch.float64, device=DEV)
     ws = M.allocate_workspace(sysm, nE)
@@ -77,6 +81,63 @@ def test_walk_batch_matches_per_kernel_walks(kernels, lead):
             got = t.cpu().numpy()
             assert (got == ref[i]).all(), (cfg, i)
             assert (got[:, 0] + got[:, 1] + got[:, 2] == n).all()
+
+
+@pytest.mark.parametrize("lead", [0, 1])
+def test_walk_batch_matches_oracle_walker(kernels, lead):
+    # every unit of a batched walk against the oracle's C walker replaying the same walkers on
+    # the GPU's own alias tables (read back), for two launch shapes
+    seed, wbegin, n = 0x0BADC0DE, 12_345, 2_500
+    refs = []
+    for (k, _), s in zip(kernels, SHAPES):
+        thr, al = k.alias_tables()
+        refs.append(OW.walk_alias(thr, al, seed, s[4], lead, wbegin, n))
+    for cfg in (M.walk_config(slots=3, wg_size=256, groups=8, walks_per_slot=8),
+                M.walk_config(slots=1, wg_size=64, groups=1, chunk=37)):
+        tal = [torch.zeros((k.nE, M.TALLY_N), dtype=torch.int64, device=DEV) for k, _ in kernels]
+        b = M.mc_negf_batch_prepare([k for k, _ in kernels], [s[4] for s in SHAPES], lead, tal)
+        M.mc_negf_walk_batch(b, seed, wbegin, n, 1_000_000, cfg)
+        torch.cuda.synchronize()
+        for i, t in enumerate(tal):
+            assert (t.cpu().numpy() == refs[i]).all(), (cfg.as_dict(), i)
+
+
+def test_batched_mc_current_of_a_long_system_within_3_sigma_of_direct():
+    # the batched workload's longest system (W = 8, L = 400, eta = 0.05, disorder +-0.5,
+    # 256 energies, 1e5 walkers per energy) walked in a batch beside a short one: its MC
+    # current against the DIRECT current of the same build (which the parity tests pin to the
+    # oracle), and the DIRECT transmission at two energies against the dense oracle
+    wl = next(w for w in inputs.batch_workloads() if w.L == 400)
+    short = next(w for w in inputs.batch_workloads() if w.L == 50)
+    E, wq = inputs.energy_grid(wl.emin, wl.emax, wl.n_energies)
+    tE, tw = torch.tensor(E, device=DEV), torch.tensor(wq, device=DEV)
+    ks, keep = [], []
+    for x in (wl, short):
+        sysm = M.make_system(x.W, x.L, x.t, x.lead_model, x.gamma_l, x.delta_lead)
+        V = torch.tensor(inputs.onsite(x), device=DEV)
+        g = torch.tensor(inputs.dephasing(x), device=DEV)
+        ws = M.allocate_workspace(sysm, x.n_energies)
+        ks.append(M.mc_negf_build_kernel(sysm, V, g, tE, ws))
+        keep.append((V, g, ws))
+    tal = [torch.zeros((wl.n_energies, M.TALLY_N), dtype=torch.int64, device=DEV) for _ in ks]
+    b = M.mc_negf_batch_prepare(ks, [wl.realization, short.realization], 0, tal)
+    M.mc_negf_walk_batch(b, inputs.RNG_SEED, 0, wl.walkers_per_energy, 1_000_000)
+    nE = wl.n_energies
+    T = torch.empty(nE, dtype=torch.float64, device=DEV)
+    sg = torch.empty_like(T)
+    st, I_mc, s_mc = M.mc_negf_current(ks[0], 0, 0, tal[0], tw, T, sg)
+    assert st == M.OK
+    Tm, sgm = T.cpu().numpy(), sg.cpu().numpy()
+    st, I_d, _ = M.mc_negf_current(ks[0], 1, 0, None, tw, T, sg)
+    assert st == M.OK
+    Td = T.cpu().numpy()
+    assert abs(I_mc - I_d) <= 3 * s_mc, (I_mc, I_d, s_mc)
+    from test_gpu_walker import binom_quantile_999
+    assert int(np.sum(np.abs(Tm - Td) > 3 * sgm)) <= binom_quantile_999(nE)
+    idx = [nE // 5, (3 * nE) // 4]
+    sols = D.solve_workload(wl.W, wl.L, wl.t, inputs.onsite(wl), inputs.dephasing(wl), E[idx])
+    for j, s_ in zip(idx, sols):
+        assert abs(Td[j] - s_.T_eff) <= 1e-10 * abs(s_.T_eff)
 
 
 def test_walk_batch_split_ranges_add_up(kernels):

@@ -76,7 +76,7 @@ def flags_ok(k):
 @pytest.mark.parametrize("L,nE", [(130, 2), (260, 1)])
 def test_w32_long_rows_match_sparse_oracle(L, nE):
     wl = inputs.SCALE_W32_L500.replace(L=L, n_energies=nE)
-    E, w = M.energy_grid(-3.1, 2.9, nE)
+    E, w = inputs.energy_grid(-3.1, 2.9, nE)
     k = build(wl, E)
     N = k.N
     assert k.n_out > 4096 * (L // 130)
@@ -99,7 +99,7 @@ def test_w32_l130_walker_replays_long_tables_bit_for_bit():
     # outcome indices above 4095 in the packed entries: the oracle's C walker, given the
     # GPU's tables, must reproduce the GPU walker's tallies exactly
     wl = inputs.SCALE_W32_L500.replace(L=130, n_energies=2, eta=0.05)
-    E, _ = M.energy_grid(-1.3, 0.7, 2)
+    E, _ = inputs.energy_grid(-1.3, 0.7, 2)
     k = build(wl, E)
     thr, al = k.alias_tables()
     nw = 20_000
@@ -114,7 +114,7 @@ def test_w32_l130_walker_replays_long_tables_bit_for_bit():
 def test_full_size_w32_l500_batch():
     # N = 16000 (n = 16002 outcomes per row) with the benchmark's batch of energies
     wl = inputs.SCALE_W32_L500
-    Eall, wall = M.energy_grid(wl.emin, wl.emax, wl.n_energies)
+    Eall, wall = inputs.energy_grid(wl.emin, wl.emax, wl.n_energies)
     pick = np.arange(0, wl.n_energies, wl.n_energies // inputs.SCALE_BATCH)
     E, w = Eall[pick], wall[pick]
     nE = len(E)

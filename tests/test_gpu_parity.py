@@ -28,7 +28,7 @@ SEED = inputs.RNG_SEED
 def case(W, L, eta, disorder, nE, emin, emax, lead_model=0, gamma_l=0.0, seed=0):
     V = inputs.random_sites(W * L, 100 + seed, -disorder, disorder) if disorder else np.zeros(W * L)
     g = np.full(W * L, eta) if np.isscalar(eta) else np.asarray(eta, dtype=np.float64)
-    E, w = M.energy_grid(emin, emax, nE)
+    E, w = inputs.energy_grid(emin, emax, nE)
     return dict(W=W, L=L, V=V, g=g, E=E, w=w, lead_model=lead_model, gamma_l=gamma_l)
 
 
@@ -310,7 +310,7 @@ def test_full_size_grad_on_sampled_energies():
     # call; weights vanish except at two sampled energies, which the oracle differentiates
     # (dense N = 3200 solves).  Both injection sides.
     wl = inputs.DIFF_W16_L200
-    E, wq = M.energy_grid(wl.emin, wl.emax, wl.n_energies)
+    E, wq = inputs.energy_grid(wl.emin, wl.emax, wl.n_energies)
     idx = [21, 90]
     w = np.zeros_like(wq)
     w[idx] = wq[idx]
@@ -437,7 +437,7 @@ def test_full_size_wire_direct_on_sampled_energies():
     wl = inputs.WIRE_W10_L100
     V = inputs.onsite(wl)
     g = inputs.dephasing(wl)
-    E, wq = M.energy_grid(wl.emin, wl.emax, wl.n_energies)
+    E, wq = inputs.energy_grid(wl.emin, wl.emax, wl.n_energies)
     c = dict(W=wl.W, L=wl.L, V=V, g=g, E=E, w=wq, lead_model=0, gamma_l=0.0)
     k = gpu_build(c)
     nE = wl.n_energies
@@ -460,7 +460,7 @@ def test_full_size_wire_direct_on_sampled_energies():
 
 def chain_case():
     wl = inputs.CHAIN50
-    E, wq = M.energy_grid(wl.emin, wl.emax, wl.n_energies)
+    E, wq = inputs.energy_grid(wl.emin, wl.emax, wl.n_energies)
     return wl, dict(W=1, L=50, V=inputs.onsite(wl), g=inputs.dephasing(wl), E=E, w=wq,
                     lead_model=0, gamma_l=0.0)
 

@@ -21,7 +21,7 @@ def thermal_weights(E, mu, kT):
 
 
 def setup(W, L, eta, nE, disorder, seed):
-    E, _ = M.energy_grid(-2.5, 2.5, nE)
+    E, _ = inputs.energy_grid(-2.5, 2.5, nE)
     V = inputs.random_sites(W * L, 900 + seed, -disorder, disorder) if disorder else np.zeros(W * L)
     g = np.full(W * L, eta)
     sysm = M.make_system(W, L)

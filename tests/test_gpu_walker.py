@@ -156,3 +156,36 @@ def test_more_energies_than_one_launch_holds():
     M.mc_negf_walk(k, 3, 1, 0, 5, 200, 1_000_000, tal)
     ref = OW.walk_alias(thr, al, 3, 1, 0, 5, 200)
     assert (tal.cpu().numpy() == ref).all()
+
+
+@pytest.mark.parametrize("inject,max_steps", [(0, 1_000_000), (1, 1_000_000), (0, 2), (1, 3)])
+def test_mc_estimator_matches_oracle_estimator(inject, max_steps):
+    # mode 0 of mc_negf_current against the oracle's estimator on the same tallies, element by
+    # element: with the GPU's own row totals c_p (only the estimator's arithmetic differs,
+    # 1e-12) and with the oracle's c_p from its dense solve (1e-10); small max_steps gives
+    # truncated walks, which score 0 and count as walkers
+    c = case(W=3, L=7, eta=0.15, disorder=0.3, nE=11, emin=-2.8, emax=2.8)
+    k = gpu_build(c)
+    sols = oracle_solve(c)
+    nE = len(c["E"])
+    tal = torch.zeros((nE, 5), dtype=torch.int64, device=DEV)
+    M.mc_negf_walk(k, SEED, 3, inject, 0, 30_000, max_steps, tal)
+    w = torch.tensor(c["w"], dtype=torch.float64, device=DEV)
+    T = torch.empty(nE, dtype=torch.float64, device=DEV)
+    sg = torch.empty(nE, dtype=torch.float64, device=DEV)
+    st, I, sI = M.mc_negf_current(k, 0, inject, tal, w, T, sg)
+    t = tal.cpu().numpy()
+    if max_steps < 10:
+        assert t[:, 2].sum() > 0 and st == M.WTRUNC
+    else:
+        assert t[:, 2].sum() == 0 and st == M.OK
+    T, sg = T.cpu().numpy(), sg.cpu().numpy()
+    c_gpu = k.lead().cpu().numpy()[:, M.LEAD_CL if inject == 0 else M.LEAD_CR]
+    To, so, Io, sIo = OW.mc_current(t, c_gpu, c["w"], inject)
+    assert np.allclose(T, To, rtol=1e-12, atol=0) and np.allclose(sg, so, rtol=1e-12, atol=0)
+    assert abs(I - Io) <= 1e-12 * abs(Io) and abs(sI - sIo) <= 1e-12 * sIo
+    row = sols[0].N + inject
+    c_ora = np.array([s.transition_kernel()[row].sum() for s in sols])
+    To, so, Io, sIo = OW.mc_current(t, c_ora, c["w"], inject)
+    assert np.allclose(T, To, rtol=1e-10, atol=0) and np.allclose(sg, so, rtol=1e-10, atol=0)
+    assert abs(I - Io) <= 1e-10 * abs(Io) and abs(sI - sIo) <= 1e-10 * sIo
