@@ -284,6 +284,25 @@ int32_t mc_negf_walk_sampled(const mcnegf_kernel* k, uint64_t seed, uint32_t rea
                              void* d_scratch, uint64_t scratch_bytes, hipStream_t stream);
 
 /*
+ * mc_negf_walk_sampled without a scratch argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments (less d_scratch, scratch_bytes), same walks and the same
+ * tallies bit for bit as mc_negf_walk_sampled; no device memory is allocated or freed.  Its
+ * scratch is one fixed array of MCNEGF_STATIC_SCRATCH_BYTES per device, held from the first
+ * call on that device until the process ends; returns MCNEGF_EWS when
+ * mc_negf_walk_sampled_bytes(k, n_walkers) exceeds it (e.g. 256 energies: up to about 8e6
+ * walkers per call).  Every call on a device shares that device's array, so calls that
+ * overlap on one device (concurrent streams or threads) race; calls in order on one stream
+ * do not.  Nothing in the array needs to start at zero.  Asynchronous.
+ */
+#define MCNEGF_STATIC_SCRATCH_BYTES (64ull << 20)
+int32_t mc_negf_walk_sampled_noalloc(const mcnegf_kernel* k, uint64_t seed,
+                                     uint32_t realization, uint32_t inject_lead,
+                                     uint64_t walker_begin, uint64_t n_walkers,
+                                     uint32_t max_steps, const double* d_weights,
+                                     int64_t* d_tallies, hipStream_t stream);
+
+/*
  * Like mc_negf_current, but asynchronous and capturable in a HIP graph: I and the standard
  * error go to d_I_sigma ([2] device) instead of the host, nothing is synchronised and the
  * status word is left for mc_negf_status to read.  Same argument rules and errors

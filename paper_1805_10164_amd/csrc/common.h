@@ -131,6 +131,9 @@ struct SampledScratch {
     uint32_t* ids;          // [n] walker indices sorted by energy
 };
 uint64_t sampled_scratch_layout(int nE, uint64_t n, SampledScratch* out, void* base);
+// Device address of the library's fixed scratch array (MCNEGF_STATIC_SCRATCH_BYTES) on the
+// current device, looked up once per device.
+hipError_t static_scratch_address(void** out);
 hipError_t launch_walk_sampled(const mcnegf_kernel& k, const SampledScratch& sc, uint64_t seed,
                                uint32_t tag, uint32_t walker_begin, uint32_t n_walkers,
                                uint32_t max_steps, const double* weights, int64_t* tallies,

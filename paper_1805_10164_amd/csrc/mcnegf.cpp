@@ -390,16 +390,25 @@ int32_t mc_negf_walk_sampled_bytes(const mcnegf_kernel* k, uint64_t n_walkers,
     return MCNEGF_OK;
 }
 
+static bool valid_sampled_args(const mcnegf_kernel* k, uint32_t realization,
+                               uint32_t inject_lead, uint64_t walker_begin, uint64_t n_walkers,
+                               uint32_t max_steps, const double* d_weights,
+                               const int64_t* d_tallies) {
+    if (!valid_kernel(k) || !k->alias || !k->alias_lo || !d_weights || !d_tallies ||
+        inject_lead > 1 || realization >= (1u << 30) || max_steps < 1 ||
+        k->nE > kMaxSampledEnergies)
+        return false;
+    return walker_begin < 0x100000000ull && n_walkers < 0x100000000ull &&
+           walker_begin + n_walkers < 0x100000000ull;
+}
+
 int32_t mc_negf_walk_sampled(const mcnegf_kernel* k, uint64_t seed, uint32_t realization,
                              uint32_t inject_lead, uint64_t walker_begin, uint64_t n_walkers,
                              uint32_t max_steps, const double* d_weights, int64_t* d_tallies,
                              void* d_scratch, uint64_t scratch_bytes, hipStream_t stream) {
-    if (!valid_kernel(k) || !k->alias || !k->alias_lo || !d_weights || !d_tallies ||
-        !d_scratch || inject_lead > 1 || realization >= (1u << 30) || max_steps < 1 ||
-        k->nE > kMaxSampledEnergies)
-        return MCNEGF_EINVAL;
-    if (walker_begin >= 0x100000000ull || n_walkers >= 0x100000000ull ||
-        walker_begin + n_walkers >= 0x100000000ull)
+    if (!valid_sampled_args(k, realization, inject_lead, walker_begin, n_walkers, max_steps,
+                            d_weights, d_tallies) ||
+        !d_scratch)
         return MCNEGF_EINVAL;
     if (((uintptr_t)d_scratch & 255u) != 0) return MCNEGF_EWS;
     SampledScratch sc;
@@ -410,6 +419,29 @@ int32_t mc_negf_walk_sampled(const mcnegf_kernel* k, uint64_t seed, uint32_t rea
     hipError_t err = launch_walk_sampled(*k, sc, seed, tag, (uint32_t)walker_begin,
                                          (uint32_t)n_walkers, max_steps, d_weights, d_tallies,
                                          stream);
+    return err == hipSuccess ? MCNEGF_OK : hip_fail(err);
+}
+
+int32_t mc_negf_walk_sampled_noalloc(const mcnegf_kernel* k, uint64_t seed,
+                                     uint32_t realization, uint32_t inject_lead,
+                                     uint64_t walker_begin, uint64_t n_walkers,
+                                     uint32_t max_steps, const double* d_weights,
+                                     int64_t* d_tallies, hipStream_t stream) {
+    if (!valid_sampled_args(k, realization, inject_lead, walker_begin, n_walkers, max_steps,
+                            d_weights, d_tallies))
+        return MCNEGF_EINVAL;
+    // the fixed scratch must hold the draws, the walker lists and the per-energy tables
+    if (sampled_scratch_layout(k->nE, n_walkers, nullptr, nullptr) > MCNEGF_STATIC_SCRATCH_BYTES)
+        return MCNEGF_EWS;
+    if (n_walkers == 0) return MCNEGF_OK;
+    void* base = nullptr;
+    hipError_t err = static_scratch_address(&base);
+    if (err != hipSuccess) return hip_fail(err);
+    SampledScratch sc;
+    sampled_scratch_layout(k->nE, n_walkers, &sc, base);
+    const uint32_t tag = (realization << 1) | inject_lead;
+    err = launch_walk_sampled(*k, sc, seed, tag, (uint32_t)walker_begin, (uint32_t)n_walkers,
+                              max_steps, d_weights, d_tallies, stream);
     return err == hipSuccess ? MCNEGF_OK : hip_fail(err);
 }
 

@@ -19,6 +19,8 @@
 // high 16 bits of b with the bucket's packed entry and reads the low 16 threshold bits only
 // on a tie.  A walk's first step reads its injection row from an LDS copy when the launch
 // staged one; a finished walk is counted once, when its slot takes the next walker.
+#include <mutex>
+
 #include "common.h"
 
 namespace mcnegf {
@@ -921,6 +923,32 @@ hipError_t launch_walk_sampled(const mcnegf_kernel& k, const SampledScratch& sc,
                                uint32_t tag, uint32_t walker_begin, uint32_t n_walkers,
                                uint32_t max_steps, const double* weights, int64_t* tallies,
                                hipStream_t s);
+
+// Fixed scratch of the allocation-free energy-sampled walk (mc_negf_walk_sampled_noalloc):
+// each device that runs it holds one copy until the process ends.  In host code `scratch`
+// names a host-side stand-in, not a device address; the device address comes from
+// hipGetSymbolAddress, once per device, and only that address is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[MCNEGF_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[kMaxDevices] = {};
+
+hipError_t static_scratch_address(void** out) {
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return err;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        if ((err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return err;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return hipSuccess;
+}
 
 // Per-unit counts: unit u walks the walker indices ids[0 .. nw_u) of its descriptor; the
 // chunk prefix (device, [n_units + 1]) was written by the caller.  One XCD group.

@@ -27,6 +27,7 @@ TALLY_EXIT_L, TALLY_EXIT_R, TALLY_TRUNC, TALLY_STEPS, TALLY_STEPS2 = range(5)
 EXPORTED = ("mc_negf_workspace_bytes", "mc_negf_build_kernel", "mc_negf_walk",
             "mc_negf_current", "mc_negf_grad_workspace_bytes", "mc_negf_grad",
             "mc_negf_current_async", "mc_negf_walk_sampled_bytes", "mc_negf_walk_sampled",
+            "mc_negf_walk_sampled_noalloc",
             "mc_negf_batch_bytes", "mc_negf_batch_prepare",
             "mc_negf_walk_batch", "mc_negf_walk_batch_autotune", "mc_negf_plan_waves",
             "mc_negf_graph_begin", "mc_negf_graph_end", "mc_negf_graph_launch",
@@ -109,6 +110,8 @@ def lib() -> ctypes.CDLL:
                                              ctypes.POINTER(u64)]
     L.mc_negf_walk_sampled.argtypes = [ctypes.POINTER(KernelStruct), u64, u32, u32, u64, u64,
                                        u32, vp, vp, vp, u64, vp]
+    L.mc_negf_walk_sampled_noalloc.argtypes = [ctypes.POINTER(KernelStruct), u64, u32, u32,
+                                               u64, u64, u32, vp, vp, vp]
     L.mc_negf_batch_bytes.argtypes = [ctypes.POINTER(KernelStruct), i32, ctypes.POINTER(u64)]
     L.mc_negf_batch_prepare.argtypes = [ctypes.POINTER(KernelStruct), i32,
                                         ctypes.POINTER(u32), u32, ctypes.POINTER(vp), vp, u64,
@@ -487,3 +490,19 @@ def mc_negf_walk_sampled(k: Kernel, seed: int, realization: int, inject_lead: in
                                       int(max_steps), _ptr(weights), _ptr(tallies), _ptr(scratch),
                                       int(scratch.numel()), _stream(stream))
     return _check("mc_negf_walk_sampled", code)
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def mc_negf_walk_sampled_noalloc(k: Kernel, seed: int, realization: int, inject_lead: int,
+                                 walker_begin: int, n_walkers: int, max_steps: int, weights,
+                                 tallies, stream=None) -> int:
+    """As mc_negf_walk_sampled, with the library's fixed per-device scratch instead of a
+    caller buffer (no device allocation)."""
+    code = lib().mc_negf_walk_sampled_noalloc(ctypes.byref(k.struct), int(seed),
+                                              int(realization), int(inject_lead),
+                                              int(walker_begin), int(n_walkers),
+                                              int(max_steps), _ptr(weights), _ptr(tallies),
+                                              _stream(stream))
+    return _check("mc_negf_walk_sampled_noalloc", code)

@@ -106,6 +106,13 @@ def test_host_validation_rejects_before_any_gpu_call():
                                     z) == M.EINVAL
     assert lib.mc_negf_walk_sampled(ctypes.byref(ks), 1, 0, 0, 7, (1 << 32) - 7, 10, w, t, w,
                                     1 << 40, z) == M.EINVAL
+    # the allocation-free variant: the same argument rules, and a walk too large for its fixed
+    # scratch is refused on the host (before it looks up the scratch on a device)
+    nw = lambda *a: lib.mc_negf_walk_sampled_noalloc(ctypes.byref(ks), *a)  # noqa: E731
+    assert nw(1, 0, 2, 0, 10, 10, w, t, z) == M.EINVAL                  # lead
+    assert nw(1, 0, 0, 0, 10, 10, z, t, z) == M.EINVAL                  # weights
+    assert nw(1, 0, 0, 0, 1 << 32, 10, w, t, z) == M.EINVAL             # range
+    assert nw(1, 0, 0, 0, 1 << 24, 10, w, t, z) == M.EWS                # beyond the scratch
     out = (ctypes.c_double * 2)()
     assert lib.mc_negf_current(ctypes.byref(ks), 0, 0, z, z, z, z,
                                ctypes.cast(out, ctypes.POINTER(ctypes.c_double)), z) == M.EINVAL
