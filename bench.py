@@ -4,17 +4,20 @@ One step = the whole path for the W=10 x L=100 disordered wire (N = 1000 sites, 
 midpoint energies in [-3.5 t, 3.5 t], disorder U[-0.25 t, 0.25 t]) at each dephasing rate
 eta in {0.01, 0.05, 0.1} t: build G / kernel rows / alias tables for all 256 energies,
 walk 1e6 walkers per energy, MC current, DIRECT current.  Inputs are resident in HBM before
-the timed region starts.  Every kernel launch inside the timed steps is timed with HIP
-events on its own stream (the library's opt-in launch timer).
+the timed region starts.  The timed steps run as they would in use; the same steps are then
+run again with every kernel launch timed by HIP events on its own stream (the library's
+opt-in launch timer), which gives the per-kernel times and the roofline of the dominant
+kernel.
 
 Printed (one JSON line): walk steps per second of the whole step, per-stage and per-kernel
 times, the roofline of the dominant kernel, time to a 1% relative deviation of the lead
-current for MC and for the DIRECT GPU solve, and the oracle timed on the host's cores for a
-bounded sample of the same workload.  A "grad" object adds the gradient (dI/dV_i for all
-sites, dI/dgamma_i) on the W=16 x L=200 differentiation workload with its own roofline and
-oracle sample.  A "batched" object adds the batched uneven workload (64 realizations x 256
-energies of W=8 wires of four lengths) walked in memory-bounded waves, each wave one replayed
-HIP graph with one batched walker launch.
+current for MC and for the DIRECT GPU solve (with the error realized at the stop), and the
+oracle timed on the host's cores for a bounded sample of the same workload.  Further
+objects: "chain" (the N = 50 chain, with the oracle's DIRECT and MC-to-1% times on all its
+energies), "grad" (dI/dV_i for all sites and dI/dgamma_i on the W=16 x L=200
+differentiation workload), "batched" (64 realizations x 256 energies of W=8 wires of four
+lengths, walked in memory-bounded waves, each wave one replayed HIP graph with one batched
+walker launch) and "scale" (all 512 energies of the W=32 x L=500 wire in 16 timed batches).
 """
 from __future__ import annotations
 
@@ -58,8 +61,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched uneven workload (64 realizations x 256 energies)")
     ap.add_argument("--no-scale", action="store_true",
-                    help="skip the W=32 x L=500 (N = 16000) batch of energies")
-    ap.add_argument("--only", choices=["grad", "batched", "scale"], default=None,
+                    help="skip the W=32 x L=500 (N = 16000) workload")
+    ap.add_argument("--no-chain", action="store_true", help="skip the N = 50 chain")
+    ap.add_argument("--only", choices=["grad", "batched", "scale", "chain"], default=None,
                     help="run only this leg and print its object (profiling; no top-level metric)")
     ap.add_argument("--batch-budget-gb", type=float, default=160.0,
                     help="device memory for one wave of build workspaces in the batched leg")
@@ -500,96 +504,98 @@ def realized_errors(mc_I, smp_I, I_dir):
     return out
 
 
-def scale_bench(torch, dev, steps, warmup, with_cpu, seed):
-    """The W=32 x L=500 wire (N = 16000, the paper's 32 x 32 blocks): one batch of SCALE_BATCH
-    of its 512 energies (every 16th) per build, as the full energy grid is processed: build,
-    1e7 walks per energy, MC and DIRECT currents, all FP64.  One energy's tables are 1 GB, so
-    here every walk step reads memory (no table stays in L2)."""
+def scale_bench(torch, dev, warmup, with_cpu, seed):
+    """The W=32 x L=500 wire (N = 16000, the paper's 32 x 32 blocks), all 512 energies in 16
+    batches of SCALE_BATCH (batch b takes every 16th energy from b), one build per batch:
+    build, 1e7 walks per energy, MC and DIRECT currents, all FP64.  Every batch is timed; the
+    current of the whole grid is the sum of the batches' currents.  One energy's tables are
+    1 GB, so here every walk step reads memory (no table stays in L2)."""
     wl = inputs.SCALE_W32_L500
     Eall, wall_w = inputs.energy_grid(wl.emin, wl.emax, wl.n_energies)
     n_batches = wl.n_energies // inputs.SCALE_BATCH
-    pick = np.arange(0, wl.n_energies, n_batches)
-    E, w = Eall[pick], wall_w[pick]
-    nE, nw = len(E), wl.walkers_per_energy
+    picks = [np.arange(b, wl.n_energies, n_batches) for b in range(n_batches)]
+    nE, nw = inputs.SCALE_BATCH, wl.walkers_per_energy
     sysm = M.make_system(wl.W, wl.L, wl.t, wl.lead_model, wl.gamma_l, wl.delta_lead)
     V = torch.tensor(inputs.onsite(wl), device=dev)
     g = torch.tensor(inputs.dephasing(wl), device=dev)
-    tE, tw = torch.tensor(E, device=dev), torch.tensor(w, device=dev)
+    tE = [torch.tensor(Eall[pk], device=dev) for pk in picks]
+    tw = [torch.tensor(wall_w[pk], device=dev) for pk in picks]
     ws = M.allocate_workspace(sysm, nE, dev)
-    tal = torch.zeros((nE, M.TALLY_N), dtype=torch.int64, device=dev)
-    T, sg = torch.empty(nE, dtype=torch.float64, device=dev), torch.empty(nE, dtype=torch.float64,
-                                                                          device=dev)
-    Td, sgd = torch.empty_like(T), torch.empty_like(T)
-    out = torch.zeros((2, 2), dtype=torch.float64, device=dev)
+    tal = torch.zeros((n_batches, nE, M.TALLY_N), dtype=torch.int64, device=dev)
+    T = torch.empty((n_batches, nE), dtype=torch.float64, device=dev)
+    sg = torch.empty_like(T)
+    Td = torch.empty_like(T)
+    sgd = torch.empty_like(T)
+    out = torch.zeros((n_batches, 2, 2), dtype=torch.float64, device=dev)
     holder = {}
 
-    def one_batch():
-        k = M.mc_negf_build_kernel(sysm, V, g, tE, ws)
-        tal.zero_()
-        M.mc_negf_walk(k, seed, 0, 0, 0, nw, 1_000_000, tal)
-        M.mc_negf_current_async(k, 0, 0, tal, tw, T, sg, out[0])
-        M.mc_negf_current_async(k, 1, 0, None, tw, Td, sgd, out[1])
+    def one_batch(b, sysx=sysm):
+        k = M.mc_negf_build_kernel(sysx, V, g, tE[b], ws)
+        tal[b].zero_()
+        M.mc_negf_walk(k, seed, 0, 0, 0, nw, 1_000_000, tal[b])
+        M.mc_negf_current_async(k, 0, 0, tal[b], tw[b], T[b], sg[b], out[b, 0])
+        M.mc_negf_current_async(k, 1, 0, None, tw[b], Td[b], sgd[b], out[b, 1])
         holder["k"] = k
 
     for _ in range(max(1, warmup)):
-        one_batch()
+        one_batch(0)
     torch.cuda.synchronize()
     # one timing window per batch: a batch launches about 270 kernels (the factorization of
     # a 16000-row system is one launch per 64-column block) and a window records 512
     records = []
+    flags = 0
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for b in range(n_batches):
         with M.LaunchTimes() as lt:
-            one_batch()
-        if lt.dropped:
-            raise RuntimeError("launch timer dropped records")
-        records += lt.records
+            one_batch(b)
+        records += require_complete(lt).records
+        flags |= M.mc_negf_status(holder["k"])
     torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) / steps
-    lt = M.LaunchTimes()
-    lt.records = records
-    k = holder["k"]
+    wall = time.perf_counter() - t0
     o = out.cpu().numpy()
-    flags = M.mc_negf_status(k)
     ta = tal.cpu().numpy()
-    walk_steps = int(ta[:, M.TALLY_STEPS].sum())
-    names = sorted(set(n for n, _ in lt.records))
-    per_kernel = {n: {"launches": lt.count(n) // steps, "ms_per_batch": lt.total_ms(n) / steps}
-                  for n in names}
-    walk_ms = lt.total_ms("walk_kernel") / steps
-    chol_ms = lt.total_ms("cholesky_kernel") / steps
+    walk_steps = int(ta[:, :, M.TALLY_STEPS].sum())
+    per_kernel = per_kernel_table(records, n_batches)
+    for v in per_kernel.values():
+        v["ms_per_batch"] = v.pop("ms_per_step")
+    walk_ms = per_kernel["walk_kernel"]["ms_per_batch"] * n_batches
+    n_walk = per_kernel["walk_kernel"]["launches"]
+    chol_ms = per_kernel["cholesky_kernel"]["ms_per_batch"]
     chol_flop = nE * (wl.N ** 3 / 3.0 + 2.0 * wl.N * wl.N)
-    fi_ms = lt.total_ms("fullinv_kernel") / steps
+    fi_ms = per_kernel["fullinv_kernel"]["ms_per_launch"]
     fi_flop = nE * 8.0 * wl.W ** 3 * wl.L * (wl.L - 1)
+    I_mc, s_mc = float(o[:, 0, 0].sum()), float(np.sqrt(np.sum(o[:, 0, 1] ** 2)))
+    I_d = float(o[:, 1, 0].sum())
 
     def per_batch_traffic(name, pk):
         t = measured_traffic(name, "scale_W32_L500")
-        return None if t is None else t * pk[name]["launches"]
+        return None if t is None else t * pk[name]["launches"] / n_batches
 
+    walk_roof = {"bound": "hbm", "achieved": walk_steps * STEP_BYTES / 1e9 / (walk_ms * 1e-3),
+                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "algorithmic_per_launch": walk_steps * STEP_BYTES / n_walk,
+                 "avg_launch_ms": walk_ms / n_walk,
+                 "traffic": measured_traffic("walk_kernel", "scale_W32_L500")}
+    walk_roof["frac"] = walk_roof["achieved"] / HBM_PEAK_GBS
+    walk_roof.update(walker_entry_figures(walk_steps / n_walk, walk_ms / n_walk))
     res = {
         "workload": f"W={wl.W} L={wl.L} N={wl.N}, eta={wl.eta}t, disorder U[-{wl.disorder},"
                     f"{wl.disorder}]t, {wl.n_energies} energies in [{wl.emin},{wl.emax}]t in "
-                    f"{n_batches} batches of {nE} (timed: every {n_batches}th energy), "
-                    f"{nw} walkers/energy",
-        "ms_per_batch": 1e3 * wall,
-        "projected_s_all_energies": wall * n_batches,
-        "walk_steps_per_batch": walk_steps,
-        "walker_kernel_steps_per_s": walk_steps / (walk_ms * 1e-3) if walk_ms else None,
-        "mean_steps_per_walker": float(ta[:, M.TALLY_STEPS].sum() / ta[:, :3].sum()),
-        "truncated": int(ta[:, M.TALLY_TRUNC].sum()),
-        "I_direct_batch": float(o[1, 0]), "I_mc_batch": float(o[0, 0]),
-        "sigma_I_mc_batch": float(o[0, 1]),
-        "mc_minus_direct_in_sigma": float((o[0, 0] - o[1, 0]) / o[0, 1]) if o[0, 1] else None,
+                    f"{n_batches} batches of {nE} (all timed), {nw} walkers/energy",
+        "s_all_energies": wall,
+        "ms_per_batch": 1e3 * wall / n_batches,
+        "walk_steps": walk_steps,
+        "walker_kernel_steps_per_s": walk_steps / (walk_ms * 1e-3),
+        "mean_steps_per_walker": float(ta[:, :, M.TALLY_STEPS].sum() / ta[:, :, :3].sum()),
+        "truncated": int(ta[:, :, M.TALLY_TRUNC].sum()),
+        "I_direct": I_d, "I_mc": I_mc, "sigma_I_mc": s_mc,
+        "mc_minus_direct_in_sigma": (I_mc - I_d) / s_mc if s_mc else None,
+        "per_batch_mc_minus_direct_in_sigma": [float((o[b, 0, 0] - o[b, 1, 0]) / o[b, 0, 1])
+                                               for b in range(n_batches)],
         "status_flags": int(flags),
         "per_kernel": per_kernel,
         "rooflines": {
-            "walk_kernel": {"bound": "hbm", "achieved": walk_steps * ALIAS_ENTRY_BYTES / 1e9 /
-                            (walk_ms * 1e-3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": walk_steps * ALIAS_ENTRY_BYTES / 1e9 / (walk_ms * 1e-3) /
-                            HBM_PEAK_GBS,
-                            "algorithmic_per_launch": walk_steps * ALIAS_ENTRY_BYTES,
-                            "avg_launch_ms": walk_ms,
-                            "traffic": measured_traffic("walk_kernel", "scale_W32_L500")},
+            "walk_kernel": walk_roof,
             # the factorization is one launch per 64-column block: figures per batch
             "cholesky_kernel": {"bound": "mfma", "achieved": chol_flop / 1e12 / (chol_ms * 1e-3),
                                 "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -609,55 +615,48 @@ def scale_bench(torch, dev, steps, warmup, with_cpu, seed):
     }
     add_traffic_rate(res["rooflines"]["walk_kernel"])
     add_traffic_rate(res["rooflines"]["fullinv_kernel"])
-    j = 1  # an energy of the batch away from the window's edge
-    T_gpu = float(Td[j].item())
-    T64 = Td.cpu().numpy()
-    I64 = float(o[1, 0])
+    j = 1  # an energy of batch 0 away from the window's edge
+    E0, w0 = Eall[picks[0]], wall_w[picks[0]]
+    T64 = Td[0].cpu().numpy()
+    I64 = float(o[0, 1, 0])
+    T_gpu = float(T64[j])
 
-    # the same batch with the full inverse's block products in FP32 (same workspace)
+    # batch 0 again with the full inverse's block products in FP32 (same workspace)
     sys32 = M.make_system(wl.W, wl.L, wl.t, wl.lead_model, wl.gamma_l, wl.delta_lead,
                           M.BUILD_FP32_PRODUCTS)
-
-    def one_batch32():
-        k32 = M.mc_negf_build_kernel(sys32, V, g, tE, ws)
-        tal.zero_()
-        M.mc_negf_walk(k32, seed, 0, 0, 0, nw, 1_000_000, tal)
-        M.mc_negf_current_async(k32, 0, 0, tal, tw, T, sg, out[0])
-        M.mc_negf_current_async(k32, 1, 0, None, tw, Td, sgd, out[1])
-        holder["k"] = k32
-
-    one_batch32()
+    one_batch(0, sys32)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with M.LaunchTimes() as lt32:
-        one_batch32()
+        one_batch(0, sys32)
     torch.cuda.synchronize()
     wall32 = time.perf_counter() - t0
+    require_complete(lt32)
     o32 = out.cpu().numpy()
-    T32 = Td.cpu().numpy()
+    T32 = Td[0].cpu().numpy()
     flags32 = M.mc_negf_status(holder["k"])
     res["fp32_products"] = {
-        "what": "full-inverse block products in FP32 on the matrix cores (FP64 RGF blocks, "
-                "|G|^2, alias tables, probe solve, tallies); no refinement step",
+        "what": "batch 0 with the full-inverse block products in FP32 on the matrix cores "
+                "(FP64 RGF blocks, |G|^2, alias tables, probe solve, tallies); no refinement",
         "ms_per_batch": 1e3 * wall32,
         "fullinv_ms": lt32.total_ms("fullinv_kernel"),
         "fullinv_ms_fp64": fi_ms,
         "max_rel_err_T_direct_vs_fp64": float(np.max(np.abs(T32 - T64) / np.abs(T64))),
-        "rel_err_I_direct_vs_fp64": abs(float(o32[1, 0]) - I64) / abs(I64),
-        "mc_minus_fp64_direct_in_sigma": (float(o32[0, 0]) - I64) / float(o32[0, 1]),
+        "rel_err_I_direct_vs_fp64": abs(float(o32[0, 1, 0]) - I64) / abs(I64),
+        "mc_minus_fp64_direct_in_sigma": (float(o32[0, 0, 0]) - I64) / float(o32[0, 0, 1]),
         "status_flags": int(flags32),
     }
     T_gpu32 = float(T32[j])
-    del holder, k, ws
+    del holder, ws
     torch.cuda.empty_cache()
     if with_cpu:
-        # the oracle's T_eff at one energy of the batch: every column of G by a sparse LU,
+        # the oracle's T_eff at one energy of batch 0: every column of G by a sparse LU,
         # then the dense probe system
         from oracle import columns as OC
         import threadpoolctl
         blas = max((i["num_threads"] for i in threadpoolctl.threadpool_info()), default=1)
         t0 = time.perf_counter()
-        ora = OC.SparseEnergy(E[j], wl.W, wl.L, wl.t, inputs.onsite(wl), inputs.dephasing(wl),
+        ora = OC.SparseEnergy(E0[j], wl.W, wl.L, wl.t, inputs.onsite(wl), inputs.dephasing(wl),
                               wl.lead_model, wl.delta_lead, wl.gamma_l)
         T_ref = ora.effective_transmission()
         dt = time.perf_counter() - t0
@@ -665,12 +664,91 @@ def scale_bench(torch, dev, steps, warmup, with_cpu, seed):
         res["cpu_baseline"] = {
             "value": 1.0 / dt, "unit": "energies/s (DIRECT T_eff)", "cores": blas,
             "kind": "oracle",
-            "sample": f"energy {E[j]:.6f}t (1 of {wl.n_energies}): sparse LU columns (one "
+            "sample": f"energy {E0[j]:.6f}t (1 of {wl.n_energies}): sparse LU columns (one "
                       f"thread) + dense probe solve ({blas} BLAS threads), {dt:.1f} s",
+            "oracle_direct_s_projected_all_energies": dt * wl.n_energies,
             "T_oracle": T_ref, "T_gpu_direct": T_gpu,
             "rel_err_direct": abs(T_gpu - T_ref) / abs(T_ref),
             "rel_err_direct_fp32_products": abs(T_gpu32 - T_ref) / abs(T_ref)}
     return res
+
+
+def oracle_mc_to_1pct(K, c, w, seed, first=1024, cap=1 << 20):
+    """The oracle's walker (the paper's cumulative-sum sampler) in batches sized from the
+    measured sigma_I, as the GPU's time-to-1% runs, until sigma_I <= 1% of I: (walkers per
+    energy, I, sigma_I, tallies)."""
+    from oracle import walker as OW
+    tal = np.zeros((K.shape[0], 5), np.int64)
+    done, batch = 0, first
+    while True:
+        OW.walk_cdf(K, seed, 0, 0, done, batch, tallies=tal)
+        done += batch
+        _, _, I, sI = OW.mc_current(tal, c, w)
+        if sI <= 0.01 * abs(I) or done >= cap:
+            return done, I, sI, tal
+        batch = next_batch(done, I, sI, first, cap)
+
+
+def chain_bench(torch, dev, steps, warmup, seed, with_cpu):
+    """The N = 50 chain (eta = 0.05 t, 64 midpoint energies in [-1.9 t, 1.9 t], 1e5 walkers
+    per energy): one step = build, walks, MC and DIRECT currents, timed like the wire; time to
+    1% for MC and DIRECT; the oracle's DIRECT solve and its MC to 1% on all 64 energies."""
+    wl = inputs.CHAIN50
+    p = Problem(wl, torch, dev)
+    walkers = wl.walkers_per_energy
+    for _ in range(max(1, warmup)):
+        run_step(p, walkers, seed, True)
+    torch.cuda.synchronize()
+    with M.LaunchTimes() as lt0:
+        run_step(p, walkers, seed, True)
+    per_step = len(require_complete(lt0).records)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    records = timed_records(steps, per_step, lambda: run_step(p, walkers, seed, True))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st_mc, I_mc, s_mc, st_d, I_d = step_results(p, True)
+    tal = p.tal.cpu().numpy()
+    steps_total = steps * int(tal[:, M.TALLY_STEPS].sum())
+    per_kernel = per_kernel_table(records, steps)
+    walk_ms = per_kernel["walk_kernel"]["ms_per_step"] * steps
+    out = {
+        "workload": f"chain W=1 L={wl.L} N={wl.N}, eta={wl.eta}t, {wl.n_energies} energies in "
+                    f"[{wl.emin},{wl.emax}]t, {walkers} walkers/energy",
+        "value": steps_total / wall, "unit": "walk steps/s", "ms_per_step": 1e3 * wall / steps,
+        "walker_kernel_steps_per_s": steps_total / (walk_ms * 1e-3),
+        "I_mc": I_mc, "sigma_I_mc": s_mc, "status_mc": st_mc, "I_direct": I_d,
+        "status_direct": st_d, "mc_minus_direct_in_sigma": (I_mc - I_d) / s_mc if s_mc else None,
+        "mean_steps_per_walker": float(tal[:, 3].sum() / tal[:, :3].sum()),
+        "per_kernel": per_kernel,
+        "time_to_1pct": time_to_1pct(p, torch, seed, True),
+    }
+    if with_cpu:
+        from oracle import dense as D
+        E, w = inputs.energy_grid(wl.emin, wl.emax, wl.n_energies)
+        V, g = inputs.onsite(wl), inputs.dephasing(wl)
+        t0 = time.perf_counter()
+        sols = D.solve_workload(wl.W, wl.L, wl.t, V, g, E)
+        I_ref = D.current(sols, w)
+        t_dir = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        sols = D.solve_workload(wl.W, wl.L, wl.t, V, g, E)
+        K = np.stack([s_.transition_kernel() for s_ in sols])
+        c = K[:, wl.N, :].sum(axis=1)
+        n_mc, I_o, sI_o, otal = oracle_mc_to_1pct(K, c, w, seed)
+        t_mc = time.perf_counter() - t0
+        from oracle import walker as OW
+        out["oracle"] = {
+            "cores": OW.num_threads(), "I": I_ref,
+            "rel_err_gpu_direct": abs(I_d - I_ref) / abs(I_ref),
+            "direct_s": t_dir, "mc_to_1pct_s": t_mc, "mc_walkers_per_energy": n_mc,
+            "mc_rel_err_at_stop": abs(I_o - I_ref) / abs(I_ref),
+            "what": "dense LAPACK G per energy, transmissions and probe solve (DIRECT); the same "
+                    "plus kernel rows and the C walker with the paper's cumulative-sum "
+                    "sampler in batches until sigma_I <= 1% of I (MC); all 64 energies"}
+    del p
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(wl: inputs.Workload, seed: int):
@@ -685,15 +763,30 @@ def cpu_baseline(wl: inputs.Workload, seed: int):
     nw = 25_000
     t0 = time.perf_counter()
     sols = D.solve_workload(wl.W, wl.L, wl.t, V, g, E[idx])
+    t_solve = time.perf_counter() - t0
     K = np.stack([s.transition_kernel() for s in sols])
+    t_kernel = time.perf_counter() - t0 - t_solve
+    t1 = time.perf_counter()
     tal = OW.walk_cdf(K, seed, 0, 0, 0, nw)
+    t_walk = time.perf_counter() - t1
     dt = time.perf_counter() - t0
     steps = int(tal[:, 3].sum())
+    scale = wl.n_energies / len(idx)
+    steps_per_walker = steps / (len(idx) * nw)
     return {"value": steps / dt, "unit": "walk steps/s", "cores": OW.num_threads(),
             "kind": "oracle",
             "sample": f"{len(idx)} of {wl.n_energies} energies x {nw} walkers at eta={wl.eta}: "
                       f"dense LAPACK G per energy + C walker (cumulative-sum sampler), "
-                      f"{steps} steps in {dt:.1f} s"}
+                      f"{steps} steps in {dt:.1f} s",
+            "walker_steps_per_s": steps / t_walk,
+            "solve_s_per_energy": t_solve / len(idx),
+            "kernel_rows_s_per_energy": t_kernel / len(idx),
+            # projections of the sample to all energies (the whole oracle run takes minutes)
+            "direct_s_projected": t_solve * scale,
+            "mc_to_1pct_s_projected_1024_walkers": (t_solve + t_kernel) * scale +
+            1024 * wl.n_energies * steps_per_walker / (steps / t_walk),
+            "projection": f"sample times x {scale:.2f} energies; MC adds 1024 walkers per energy "
+                          f"(the GPU's first batch, which reaches 1%) at the sample's walker rate"}
 
 
 def calibration_copy(torch, dev, mib):
@@ -722,11 +815,13 @@ def main():
         with_cpu = not args.no_cpu_baseline
         if args.only == "grad":
             leg = grad_bench(torch, dev, args.steps, args.warmup, with_cpu)
+        elif args.only == "chain":
+            leg = chain_bench(torch, dev, args.steps, args.warmup, inputs.RNG_SEED, with_cpu)
         elif args.only == "batched":
             leg = batched_bench(torch, dev, args.steps, args.warmup, args.batch_budget_gb,
                                 inputs.RNG_SEED)
         else:
-            leg = scale_bench(torch, dev, args.steps, args.warmup, with_cpu, inputs.RNG_SEED)
+            leg = scale_bench(torch, dev, args.warmup, with_cpu, inputs.RNG_SEED)
         print(json.dumps({args.only: leg}), flush=True)
         return
     base = inputs.WIRE_W10_L100
@@ -751,11 +846,18 @@ def main():
     with M.LaunchTimes() as lt0:
         one_step()
     per_step = len(require_complete(lt0).records)
+    # the timed steps run without the launch timer (its two events per launch slow a step by
+    # about 9%); the same steps are then run again under the timer for the per-kernel figures
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
     t0 = time.perf_counter()
     records = timed_records(args.steps, per_step, one_step)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    wall_instrumented = time.perf_counter() - t0
     # every step walks the same seeded walkers, so each step's counts are the last step's
     results = [(p, step_results(p, walk_on)) for p in probs]
     steps_total = args.steps * sum(int(p.tal[:, M.TALLY_STEPS].sum()) for p in probs) if walk_on else 0
@@ -788,6 +890,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": 1e3 * wall / args.steps,
+        "ms_per_step_with_launch_timer": 1e3 * wall_instrumented / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -814,6 +917,9 @@ def main():
         line["cpu_baseline"] = cpu_baseline(mid, seed)
     del probs, results
     torch.cuda.empty_cache()
+    if not args.no_chain:
+        line["chain"] = chain_bench(torch, dev, args.steps, args.warmup, seed,
+                                    not args.no_cpu_baseline)
     if not args.no_grad:
         line["grad"] = grad_bench(torch, dev, args.steps, args.warmup, not args.no_cpu_baseline)
     if not args.no_batched:
@@ -821,8 +927,8 @@ def main():
                                         seed)
         torch.cuda.empty_cache()
     if not args.no_scale:
-        line["scale"] = scale_bench(torch, dev, min(args.steps, 2), args.warmup,
-                                    not args.no_cpu_baseline, seed)
+        line["scale"] = scale_bench(torch, dev, min(args.warmup, 1), not args.no_cpu_baseline,
+                                    seed)
     print(json.dumps(line), flush=True)
 
 

@@ -120,3 +120,29 @@ def test_walker_single_site_exit_probability():
     pin = K[1, 0] / K[1].sum()
     mean_steps = 1 + pin / (1 - q)
     assert abs(t[3] / n - mean_steps) < 5 * np.sqrt(t[4] / n - (t[3] / n) ** 2) / np.sqrt(n)
+
+
+def test_golden_redraw_walkers_are_rejected_by_the_bucket_rule():
+    # each listed walker's injection word a (word 0 of counter (0, w, 0, tag)) is rejected by
+    # Lemire's rule (a * n mod 2^32 < 2^32 mod n); listed double redraws also have their
+    # first redraw word (counter (0, w, 0, tag | 2^31), key (key0, key1 ^ 1)) rejected
+    path = os.path.join(HERE, "golden", "lemire_redraws.txt")
+    if not os.path.exists(path):
+        pytest.skip("golden file not generated")
+    rows = [tuple(int(x) for x in line.split()) for line in open(path)
+            if line.strip() and not line.startswith("#")]
+    assert rows
+    for n, seed, real, lead, w, redraws, bucket in rows:
+        tag = (real << 1) | lead
+        key = [seed & 0xFFFFFFFF, seed >> 32]
+        thresh = (1 << 32) % n
+        a = walker.philox4x32_10([0, w, 0, tag], key)[0]
+        assert (a * n) % (1 << 32) < thresh
+        words = [a]
+        for r in range(1, redraws + 1):
+            words.append(walker.philox4x32_10([0, w, 0, tag | 0x80000000],
+                                              [key[0], key[1] ^ r])[0])
+        for x in words[:-1]:
+            assert (x * n) % (1 << 32) < thresh
+        assert (words[-1] * n) % (1 << 32) >= thresh
+        assert (words[-1] * n) >> 32 == bucket
