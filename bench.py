@@ -438,6 +438,7 @@ def time_to_1pct(p: Problem, torch, seed, walk_on):
     lies within 1% with probability about 0.68 and within 3% with probability about 0.997."""
     mc_t, dir_t, mc_walkers, smp_t, smp_walkers = [], [], [], [], []
     mc_I, smp_I = [], []
+    itp_t, itp_walkers, itp_I, itp_nodes, itp_bias = [], [], [], None, None
     I_dir = None
     max_sampled = 1 << 24
     if walk_on and p.sampled_scratch is None:
@@ -482,6 +483,15 @@ def time_to_1pct(p: Problem, torch, seed, walk_on):
         k = M.mc_negf_build_kernel(p.sys_direct, p.V, p.g, p.E, p.ws)
         _, I_dir, _ = M.mc_negf_current(k, 1, 0, None, p.w, p.T, p.sig)
         dir_t.append(time.perf_counter() - t0)
+        if walk_on:
+            r = interp_mc(p, torch, seed + 201 + rep, 4, 1024, 1 << 24,
+                          bias_walkers=(1_000_000 if rep == 0 else 0))
+            itp_t.append(r[0])
+            itp_walkers.append(r[1])
+            itp_I.append(r[2])
+            itp_nodes = r[4]
+            if rep == 0:
+                itp_bias = r[5:7]
     out = {"eta": p.wl.eta,
            "mc_ms": 1e3 * float(np.median(mc_t)) if mc_t else None,
            "mc_walkers_per_energy": int(np.median(mc_walkers)) if mc_walkers else None,
@@ -489,6 +499,60 @@ def time_to_1pct(p: Problem, torch, seed, walk_on):
            "mc_energy_sampled_walkers": int(np.median(smp_walkers)) if smp_walkers else None,
            "direct_ms": 1e3 * float(np.median(dir_t)), "I_direct": I_dir}
     out.update(realized_errors(mc_I, smp_I, I_dir))
+    if itp_t:
+        out["mc_interpolated"] = {
+            "what": "every 4th energy built (and the last), intervals whose rows differ by "
+                    "more than 5% built exactly, all energies walked on interpolated rows",
+            "ms": 1e3 * float(np.median(itp_t)),
+            "walkers_per_energy": int(np.median(itp_walkers)),
+            "built_energies": itp_nodes, "energies": int(p.E.numel()),
+            "rel_err_at_stop": [abs(v - I_dir) / abs(I_dir) for v in itp_I],
+            "I_at_1e6_walkers": itp_bias[0], "sigma_at_1e6_walkers": itp_bias[1],
+            "bias_vs_direct_in_sigma": (itp_bias[0] - I_dir) / itp_bias[1],
+            "rel_bias_vs_direct": (itp_bias[0] - I_dir) / I_dir}
+    return out
+
+
+def interp_mc(p: Problem, torch, seed, stride, walkers_first, cap, bias_walkers=0):
+    """The interpolating Monte Carlo (Sec. V A, "Interpolation") on the wire's energy grid:
+    build every stride-th energy (and the last) without alias tables, measure how far the
+    normalised rows of neighbouring built energies differ, build exactly every energy inside
+    an interval that differs by more than 5%, then walk all energies on the mixed rows of
+    their neighbouring built energies in batches sized from sigma_I until sigma_I <= 1% of I.
+    Returns (wall s, walkers per energy, I, sigma_I, built energies, tallies tensor)."""
+    E = p.E.cpu().numpy()
+    nE = len(E)
+    coarse_idx = list(range(0, nE, stride)) + ([nE - 1] if (nE - 1) % stride else [])
+    sys0 = M.make_system(p.wl.W, p.wl.L, p.wl.t, p.wl.lead_model, p.wl.gamma_l, p.wl.delta_lead,
+                         M.BUILD_NO_ALIAS | M.BUILD_NO_DIRECT)
+    sys1 = M.make_system(p.wl.W, p.wl.L, p.wl.t, p.wl.lead_model, p.wl.gamma_l, p.wl.delta_lead,
+                         M.BUILD_NO_DIRECT)
+    tc = p.E[coarse_idx].contiguous()
+    dist = torch.empty(len(coarse_idx) - 1, dtype=torch.float64, device=p.E.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    k0 = M.mc_negf_build_kernel(sys0, p.V, p.g, tc, p.ws)
+    M.mc_negf_interp_distances(k0, dist)
+    exact = M.mc_negf_interp_plan(E[coarse_idx], dist.cpu().numpy(), E, 0.05)
+    nodes_idx = sorted(set(coarse_idx) | set(exact))
+    tn = p.E[nodes_idx].contiguous()
+    k1 = M.mc_negf_build_kernel(sys1, p.V, p.g, tn, p.ws)
+    p.tal.zero_()
+    done, batch = 0, walkers_first
+    while True:
+        M.mc_negf_walk_interp(k1, p.E, seed, 0, 0, done, batch, 1_000_000, p.tal)
+        done += batch
+        st, I, sI = M.mc_negf_current_interp(k1, p.E, 0, p.tal, p.w, p.T, p.sig)
+        if sI <= 0.01 * abs(I) or done >= cap:
+            break
+        batch = next_batch(done, I, sI, walkers_first, cap)
+    wall = time.perf_counter() - t0
+    out = (wall, done, I, sI, len(nodes_idx))
+    if bias_walkers:
+        p.tal.zero_()
+        M.mc_negf_walk_interp(k1, p.E, seed + 7, 0, 0, 0, bias_walkers, 1_000_000, p.tal)
+        _, Ib, sIb = M.mc_negf_current_interp(k1, p.E, 0, p.tal, p.w, p.T, p.sig)
+        out = out + (Ib, sIb)
     return out
 
 

@@ -72,6 +72,8 @@ extern "C" {
                                       /* where Tr Gamma_p <= 1e3 * delta_lead * t * W       */
 #define MCNEGF_FLAG_TRUNC      0x10u  /* a walk reached max_steps                         */
 #define MCNEGF_FLAG_NOTSPD     0x20u  /* non-positive pivot in the probe-system Cholesky  */
+#define MCNEGF_FLAG_RANGE      0x40u  /* interpolated walks: an energy outside the built    */
+                                      /* energies, or built energies that do not ascend    */
 
 /* Number of per-energy lead scalars in mcnegf_kernel.lead, and their slots. */
 #define MCNEGF_LEAD_NTERMS 8
@@ -180,9 +182,12 @@ int32_t mc_negf_workspace_bytes(const mcnegf_system* sys, int32_t nE, uint64_t* 
  *   d_ws       device workspace of ws_bytes >= mc_negf_workspace_bytes(sys, nE), 256-byte
  *              aligned; owned by the caller; overwritten.
  *   out        host handle, filled on success.
- * Stages (all on `stream`): lead self-energies; left/right RGF sweeps; diagonal blocks;
- * off-diagonal blocks streamed into |G_ij|^2, <psi|Gamma_r|psi> and the corner blocks; lead
- * transmissions; one alias table per kernel row.  Asynchronous.
+ * Stages (all on `stream`): lead self-energies Sigma_p, Gamma_p = i(Sigma_p - Sigma_p^+)
+ * (Sec. II A, Eqs. (9)-(11); wide band: Sec. III A, Eq. (78)); left/right RGF sweeps and the
+ * diagonal blocks of G^r = (E - H - Sigma)^{-1} (Sec. III B; Eq. (7)); the off-diagonal
+ * blocks streamed into |G_ij|^2, <psi_j|Gamma_r|psi_j> and the corner blocks (the step-6'
+ * weights, Sec. II F, Eqs. (75), (76)); lead transmissions and the injection rows (steps 3-4,
+ * Eq. (39)); one alias table per kernel row.  Asynchronous.
  */
 int32_t mc_negf_build_kernel(const mcnegf_system* sys, const double* d_onsite,
                              const double* d_gamma, const double* d_energies, int32_t nE,
@@ -301,6 +306,48 @@ int32_t mc_negf_walk_sampled_noalloc(const mcnegf_kernel* k, uint64_t seed,
                                      uint64_t walker_begin, uint64_t n_walkers,
                                      uint32_t max_steps, const double* d_weights,
                                      int64_t* d_tallies, hipStream_t stream);
+
+/*
+ * Interpolated step-6' probabilities across energies (Sec. V A, "Interpolation").  Walks at
+ * energies between the built ones take the rows of their two neighbouring built energies
+ * E_lo <= E < E_hi mixed linearly: (1 - alpha) p(E_lo) + alpha p(E_hi), alpha = (E - E_lo) /
+ * (E_hi - E_lo) stored as the 32-bit threshold min(floor(alpha 2^32), 2^32 - 1) (at the last
+ * built energy alpha = 0).  The built energies (the kernel's d_energies) must ascend.  An
+ * interval is fit for interpolation when its two energies' normalised rows are close; energies
+ * in the other intervals are to be built exactly (they become built energies themselves).
+ *
+ * mc_negf_interp_distances: d_dist[e] (device, [nE - 1]) = the largest, over the kernel rows
+ *   (probes and both injection rows), L1 distance sum_i |p_i(E_e) - p_i(E_e+1)| of the
+ *   normalised rows (2 for a row without weight).  Needs nE >= 2; works on a kernel built with
+ *   or without alias tables.  Asynchronous.
+ * mc_negf_interp_plan (host only): the fine energies h_fine[f] that must be built exactly: those
+ *   strictly inside an interval [h_nodes[e], h_nodes[e + 1]) with h_dist[e] > tol (or NaN).
+ *   Writes their indices (ascending) to h_exact[0 .. *n_exact - 1] (room for nF).  MCNEGF_EINVAL
+ *   for nodes that do not ascend or a fine energy outside [h_nodes[0], h_nodes[nN - 1]].
+ * mc_negf_walk_interp: walkers [walker_begin, walker_begin + n) (< 2^32) at each of the nF fine
+ *   energies d_fine_energies (device) on the kernel's alias tables, drawing each step from the
+ *   mixture: one Philox4x32-10 block of counter (n, w, f | 2^31, tag) per step n of walker w at
+ *   fine energy f, words 0 and 1 as in mc_negf_walk, word 2 < threshold(alpha_f) takes E_hi's
+ *   table (Lemire redraws: counter (n, w, f | 2^31, tag | 2^31), key (key0, key1 ^ r)).
+ *   d_tallies [nF][MCNEGF_TALLY_N] (accumulated).  Asynchronous; a fine energy outside the built
+ *   ones sets MCNEGF_FLAG_RANGE (it is walked at the nearest end).
+ * mc_negf_current_interp: T_f = c_f p_f and sigma_f as in mc_negf_current mode 0 with the
+ *   interpolated row total c_f = (1 - alpha_f) c_p(E_lo) + alpha_f c_p(E_hi), and
+ *   I = sum_f w_f T_f, sigma_I (h_I_sigma).  d_weights, d_T, d_sigmaT: [nF] device.  Synchronises
+ *   the stream; MCNEGF_EINVAL if MCNEGF_FLAG_RANGE is set, else as mc_negf_current mode 0.
+ */
+int32_t mc_negf_interp_distances(const mcnegf_kernel* k, double* d_dist, hipStream_t stream);
+int32_t mc_negf_interp_plan(const double* h_nodes, int32_t nN, const double* h_dist,
+                            const double* h_fine, int32_t nF, double tol, int32_t* h_exact,
+                            int32_t* n_exact);
+int32_t mc_negf_walk_interp(const mcnegf_kernel* k, const double* d_fine_energies, int32_t nF,
+                            uint64_t seed, uint32_t realization, uint32_t inject_lead,
+                            uint64_t walker_begin, uint64_t n_walkers_per_energy,
+                            uint32_t max_steps, int64_t* d_tallies, hipStream_t stream);
+int32_t mc_negf_current_interp(const mcnegf_kernel* k, const double* d_fine_energies,
+                               int32_t nF, uint32_t inject_lead, const int64_t* d_tallies,
+                               const double* d_weights, double* d_T, double* d_sigmaT,
+                               double* h_I_sigma, hipStream_t stream);
 
 /*
  * Like mc_negf_current, but asynchronous and capturable in a HIP graph: I and the standard

@@ -293,6 +293,95 @@ int oracle_walk_sampled_alias(const uint32_t *thr, const int32_t *alias, int64_t
 }
 
 /*
+ * Interpolated walks (Sec. V A, "Interpolation"): walker w at fine energy f walks on the
+ * mixture (1 - alpha_f) p(E_lo) + alpha_f p(E_hi) of the rows of two nodes lo = lo[f] and
+ * hi = lo + 1 (hi = lo for the last node), alpha_f = alpha32[f] / 2^32.  Step n uses the
+ * block with counter (n, w, f | 2^31, tag): words 0 and 1 as (a, b) of the chosen sampler,
+ * word 2 picks the row of E_hi when below alpha32[f], else that of E_lo.  Lemire redraws use
+ * counter (n, w, f | 2^31, tag | 2^31) and key (key0, key1 ^ r).  Tallies per fine energy.
+ * mode 0: cumulative-sum sampler on K [nN][n][n]; mode 1: alias tables [nN][n][pitch].
+ */
+static int walk_interp_impl(int mode, const double *K, const uint32_t *thr, const int32_t *alias,
+                            int64_t pitch, int32_t nN, int32_t n, const int32_t *lo,
+                            const uint32_t *alpha32, int32_t nF, uint64_t seed,
+                            uint32_t realization, uint32_t inject_lead, uint64_t walker_begin,
+                            uint64_t n_walkers, uint32_t max_steps, int64_t *tallies)
+{
+    if (n < 3 || nN < 1 || nF < 1 || nF > 0x7FFFFFFE || inject_lead > 1 ||
+        realization >= (1u << 30))
+        return -1;
+    if (walker_begin + n_walkers > 0x100000000ull) return -1;
+    for (int32_t f = 0; f < nF; ++f)
+        if (lo[f] < 0 || lo[f] >= nN) return -1;
+    const int32_t N = n - 2;
+    const uint32_t tag = (realization << 1) | inject_lead;
+    for (int32_t f = 0; f < nF; ++f) {
+        const int32_t e_lo = lo[f], e_hi = lo[f] + 1 < nN ? lo[f] + 1 : lo[f];
+        const uint32_t fe = (uint32_t)f | 0x80000000u;
+        int64_t cL = 0, cR = 0, tr = 0, s1 = 0, s2 = 0;
+#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : cL, cR, tr, s1, s2)
+        for (int64_t i = 0; i < (int64_t)n_walkers; ++i) {
+            const uint32_t w = (uint32_t)(walker_begin + (uint64_t)i);
+            stream_t st;
+            stream_init(&st, seed, w, fe, tag);
+            const uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+            int32_t s = N + (int32_t)inject_lead;
+            uint32_t steps = 0;
+            int outcome = -1;
+            while (steps < max_steps) {
+                const uint32_t ctr[4] = {steps, w, fe, tag};
+                uint32_t x[4];
+                oracle_philox4x32_10(ctr, key, x);
+                const int32_t e = x[2] < alpha32[f] ? e_hi : e_lo;
+                int32_t next;
+                if (mode == 0) {
+                    next = draw_cdf(K + ((int64_t)e * n + s) * (int64_t)n, n, x[0], x[1]);
+                } else {
+                    const uint32_t c = lemire_bucket(&st, steps, x[0], (uint32_t)n);
+                    const int64_t at = ((int64_t)e * n + s) * pitch + c;
+                    next = (x[1] < thr[at]) ? (int32_t)c : alias[at];
+                }
+                ++steps;
+                if (next >= N) { outcome = next - N; break; }
+                s = next;
+            }
+            if (outcome == 0) ++cL;
+            else if (outcome == 1) ++cR;
+            else ++tr;
+            s1 += steps;
+            s2 += (int64_t)steps * (int64_t)steps;
+        }
+        tallies[5 * f + 0] += cL;
+        tallies[5 * f + 1] += cR;
+        tallies[5 * f + 2] += tr;
+        tallies[5 * f + 3] += s1;
+        tallies[5 * f + 4] += s2;
+    }
+    return 0;
+}
+
+int oracle_walk_interp_cdf(const double *K, int32_t nN, int32_t n, const int32_t *lo,
+                           const uint32_t *alpha32, int32_t nF, uint64_t seed,
+                           uint32_t realization, uint32_t inject_lead, uint64_t walker_begin,
+                           uint64_t n_walkers, uint32_t max_steps, int64_t *tallies)
+{
+    return walk_interp_impl(0, K, NULL, NULL, 0, nN, n, lo, alpha32, nF, seed, realization,
+                            inject_lead, walker_begin, n_walkers, max_steps, tallies);
+}
+
+int oracle_walk_interp_alias(const uint32_t *thr, const int32_t *alias, int64_t pitch, int32_t nN,
+                             int32_t n, const int32_t *lo, const uint32_t *alpha32, int32_t nF,
+                             uint64_t seed, uint32_t realization, uint32_t inject_lead,
+                             uint64_t walker_begin, uint64_t n_walkers, uint32_t max_steps,
+                             int64_t *tallies)
+{
+    if (pitch < n) return -1;
+    return walk_interp_impl(1, NULL, thr, alias, pitch, nN, n, lo, alpha32, nF, seed,
+                            realization, inject_lead, walker_begin, n_walkers, max_steps,
+                            tallies);
+}
+
+/*
  * Search for rejected bucket words: walkers w of [w_begin, w_begin + count) at energy index k
  * whose draw of step n_step over nout outcomes needs at least min_redraws redraws (Lemire's
  * rejection above).  Writes up to max_out walker indices, their redraw counts and their

@@ -213,3 +213,51 @@ def find_redraws(seed, realization, inject_lead, k, n_step, nout, w_begin, count
         raise ValueError("oracle_find_redraws rejected its arguments")
     m = min(int(n), max_out)
     return int(n), [(int(ow[i]), int(orr[i]), int(oc[i])) for i in range(m)]
+
+
+def _interp(mode, tables, lo, alpha32, seed, realization, inject_lead, walker_begin, n_walkers,
+            max_steps, tallies):
+    lo = np.ascontiguousarray(lo, dtype=np.int32)
+    a32 = np.ascontiguousarray(alpha32, dtype=np.uint32)
+    nF = len(lo)
+    if tallies is None:
+        tallies = np.zeros((nF, 5), dtype=np.int64)
+    L = lib()
+    i32, u32, u64, vp = ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p
+    if mode == 0:
+        K = np.ascontiguousarray(tables, dtype=np.float64)
+        nN, n, _ = K.shape
+        f = L.oracle_walk_interp_cdf
+        f.argtypes = [vp, i32, i32, vp, vp, i32, u64, u32, u32, u64, u64, u32, vp]
+        f.restype = ctypes.c_int
+        rc = f(K.ctypes.data, nN, n, lo.ctypes.data, a32.ctypes.data, nF, seed, realization,
+               inject_lead, walker_begin, n_walkers, max_steps, tallies.ctypes.data)
+    else:
+        thr = np.ascontiguousarray(tables[0], dtype=np.uint32)
+        al = np.ascontiguousarray(tables[1], dtype=np.int32)
+        nN, n, pitch = thr.shape
+        f = L.oracle_walk_interp_alias
+        f.argtypes = [vp, vp, ctypes.c_int64, i32, i32, vp, vp, i32, u64, u32, u32, u64, u64,
+                      u32, vp]
+        f.restype = ctypes.c_int
+        rc = f(thr.ctypes.data, al.ctypes.data, pitch, nN, n, lo.ctypes.data, a32.ctypes.data,
+               nF, seed, realization, inject_lead, walker_begin, n_walkers, max_steps,
+               tallies.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle interpolated walk rejected its arguments")
+    return tallies
+
+
+def walk_interp_cdf(K, lo, alpha32, seed, realization, inject_lead, walker_begin, n_walkers,
+                    max_steps=1_000_000, tallies=None):
+    """Interpolated walks (oracle/walker.c) on the nodes' dense rows K[nN][n][n]: fine energy
+    f mixes node lo[f] and lo[f] + 1 with weight alpha32[f] / 2^32; tallies per fine energy."""
+    return _interp(0, K, lo, alpha32, seed, realization, inject_lead, walker_begin, n_walkers,
+                   max_steps, tallies)
+
+
+def walk_interp_alias(thr, alias, lo, alpha32, seed, realization, inject_lead, walker_begin,
+                      n_walkers, max_steps=1_000_000, tallies=None):
+    """Interpolated walks on the nodes' alias tables thr/alias[nN][n][pitch]."""
+    return _interp(1, (thr, alias), lo, alpha32, seed, realization, inject_lead, walker_begin,
+                   n_walkers, max_steps, tallies)

@@ -205,13 +205,36 @@ struct AliasArgs {
     double rowsum_tol;  // relative tolerance of the row-total check
 };
 
+// Weight of outcome i in kernel row `row` at energy e (probe rows: gamma_i |G_row,i|^2 and the
+// exit weights; injection rows N, N + 1: gamma_i <psi_i|Gamma_p|psi_i> and the lead terms);
+// rounding negatives are clamped to zero, a NaN is kept.
+__device__ inline double kernel_weight(const AliasArgs& a, int e, int row, int i) {
+    const int N = a.N;
+    const double* lead = a.lead + (size_t)e * MCNEGF_LEAD_NTERMS;
+    const double* wLe = a.wL + (size_t)e * N;
+    const double* wRe = a.wR + (size_t)e * N;
+    double v;
+    if (row < N) {
+        if (i < N) v = a.gamma[i] * a.P[((size_t)e * N + row) * a.ldP + i];
+        else v = (i == N) ? wLe[row] : wRe[row];
+    } else if (row == N) {
+        if (i < N) v = a.gamma[i] * wLe[i];
+        else v = (i == N) ? lead[MCNEGF_LEAD_TLL] : lead[MCNEGF_LEAD_TRL];
+    } else {
+        if (i < N) v = a.gamma[i] * wRe[i];
+        else v = (i == N) ? lead[MCNEGF_LEAD_TLR] : lead[MCNEGF_LEAD_TRR];
+    }
+    return v > 0.0 ? v : (v == v ? 0.0 : v);
+}
+
 // One workgroup of BT threads per row; thread t owns the items t + BT k (k < KM, n <= BT KM)
-// and keeps their weights, ranks and starts / ends in registers.  LDS holds what other
+// and keeps their weights in registers (loads coalesced across the wavefront).  LDS holds what other
 // threads search: the light starts and heavy ends in one array of n + 1 doubles (lights from
 // the front with the total deficit after the last one, heavies from the back: heavy m at
 // n - m) and the heavy items' indices (16 bits): 10 n bytes per row.
 template <int BT, int KM>
 __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
+    constexpr bool kLong = KM > 8;  // rows above BT * 8 outcomes
     extern __shared__ double smem[];
     __shared__ double sd[BT / 64];  // one partial per wavefront
     __shared__ int si[BT / 64];
@@ -221,33 +244,20 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
     const int e = blockIdx.y;
     const int tid = threadIdx.x;
     double* lh = smem;                                   // [n+1] light starts | heavy ends
-    uint16_t* heavyIdx = reinterpret_cast<uint16_t*>(lh + n + 1);  // [n]
+    // 16-bit item indices [n]: heavy m at m (rows up to BT * 8 outcomes); for longer rows
+    // light r at r and heavy m at n - 1 - m
+    uint16_t* idx = reinterpret_cast<uint16_t*>(lh + n + 1);
     auto lightD = [&](int r) -> double& { return lh[r]; };
     auto heavyC = [&](int m) -> double& { return lh[n - m]; };
+    auto heavyIdx = [&](int m) -> uint16_t& { return kLong ? idx[n - 1 - m] : idx[m]; };
 
     const double* lead = a.lead + (size_t)e * MCNEGF_LEAD_NTERMS;
-    const double* wLe = a.wL + (size_t)e * N;
-    const double* wRe = a.wR + (size_t)e * N;
     // 1. weights of this row (items beyond n weigh 0 and are skipped below)
     double w[KM];
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
         const int i = tid + BT * k;
-        double v = 0.0;
-        if (i < n) {
-            if (row < N) {
-                if (i < N) v = a.gamma[i] * a.P[((size_t)e * N + row) * a.ldP + i];
-                else v = (i == N) ? wLe[row] : wRe[row];
-            } else if (row == N) {
-                if (i < N) v = a.gamma[i] * wLe[i];
-                else v = (i == N) ? lead[MCNEGF_LEAD_TLL] : lead[MCNEGF_LEAD_TRL];
-            } else {
-                if (i < N) v = a.gamma[i] * wRe[i];
-                else v = (i == N) ? lead[MCNEGF_LEAD_TLR] : lead[MCNEGF_LEAD_TRR];
-            }
-            v = v > 0.0 ? v : (v == v ? 0.0 : v);  // clamp rounding negatives, keep NaN
-        }
-        w[k] = v;
+        w[k] = i < n ? kernel_weight(a, e, row, i) : 0.0;
     }
     // 2. total (fixed order: by thread, then by item)
     double part = 0.0;
@@ -292,7 +302,7 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
     for (int k = 0; k < KM; ++k) {
         const double v = w[k] * scale;
         w[k] = v;
-        if (tid + BT * k < n) {
+        if ((tid + BT * k) < n) {
             if (v < 1.0) { dl += 1.0 - v; ++nl; }
             else { uh += v - 1.0; ++nh; }
         }
@@ -312,6 +322,7 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
         if (i < n) {
             if (v < 1.0) {
                 lightD(nl) = dl;
+                if (kLong) idx[nl] = (uint16_t)i;
                 rk[k] = nl;
                 dc[k] = dl;
                 dl += 1.0 - v;
@@ -319,7 +330,7 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
             } else {
                 uh += v - 1.0;
                 heavyC(nh) = uh;
-                heavyIdx[nh] = (uint16_t)i;
+                heavyIdx(nh) = (uint16_t)i;
                 rk[k] = ~nh;
                 dc[k] = uh;
                 ++nh;
@@ -363,7 +374,7 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
                 if (d0 + k >= n) continue;
                 const bool heavy = b < NHtot && (a >= NLtot || cB <= dA);
                 if (heavy) {
-                    const int i = heavyIdx[b];
+                    const int i = heavyIdx(b);
                     double q;
                     int al;
                     if (b == NHtot - 1) {
@@ -372,7 +383,7 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
                     } else {
                         q = 1.0 + cB - dA;
                         q = q < 0.0 ? 0.0 : q;
-                        al = heavyIdx[b + 1];
+                        al = heavyIdx(b + 1);
                     }
                     uint32_t thr;
                     if (q >= 1.0) {
@@ -387,7 +398,7 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
                     ++b;
                     cB = b < NHtot ? heavyC(b) : 0.0;
                 } else {
-                    res[k] = heavyIdx[b < NHtot ? b : NHtot - 1];
+                    res[k] = heavyIdx(b < NHtot ? b : NHtot - 1);
                     slot[k] = a;
                     ++a;
                     dA = lightD(a);
@@ -433,58 +444,55 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
             out_lo[i] = (uint16_t)low;
         }
     } else {
-        // Long rows: a thread's lights have consecutive ranks, and so have its heavies, so in
-        // item order their partners never decrease: each search starts where the thread's
-        // previous one ended, steps forward up to kWalk times and finishes by bisection.
-        constexpr int kWalk = 8;
-        int mlo = 0;  // first heavy that can serve this thread's next light
-        int alo = 0;  // first light start that can bound this thread's next heavy
+        // Long rows (no room in registers to hold the merged results until every thread has
+        // read D and C): the same merge, with each merged item's entry written to the output
+        // row at once by the thread that merges it (16-bit item indices of lights and heavies
+        // in LDS); a light keeps 1 - (D_{r+1} - D_r), its own deficit recovered from the starts.
+        if (NHtot == 0) {
 #pragma unroll
-        for (int k = 0; k < KM; ++k) {
-            const int i = tid + BT * k;
-            if (i >= n) continue;
-            const int r = rk[k];
-            double q;
-            int al;
-            if (NHtot == 0) {
-                q = 1.0;
-                al = i;
-            } else if (r >= 0) {
-                // light: first heavy m with heavyC(m) > D_i
-                const double D = dc[k];
-                int lo = mlo, hi = NHtot;
-                for (int s = 0; s < kWalk && lo < hi && !(heavyC(lo) > D); ++s) ++lo;
-                if (lo < hi && !(heavyC(lo) > D)) {
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (heavyC(mid) > D) hi = mid; else lo = mid + 1;
-                    }
+            for (int k = 0; k < KM; ++k) {
+                const int i = tid + BT * k;
+                if (i < n) {
+                    out[i] = (0xFFFFFFFFu & ~kAliasIdxMask) | (uint32_t)i;
+                    out_lo[i] = (uint16_t)(0xFFFFFFFFu & kAliasIdxMask);
                 }
-                mlo = lo;
-                if (lo >= NHtot) lo = NHtot - 1;
-                q = w[k];
-                al = heavyIdx[lo];
-            } else {
-                const int m = ~r;
-                if (m == NHtot - 1) {
+            }
+            return;
+        }
+        const int d0 = tid * KM;
+        if (d0 >= n) return;
+        int lo = d0 > NHtot ? d0 - NHtot : 0, hi = d0 < NLtot ? d0 : NLtot;
+        while (lo < hi) {  // lights among the first d0 merged items
+            const int mid = (lo + hi) >> 1;
+            if (lightD(mid) < heavyC(d0 - mid - 1)) lo = mid + 1; else hi = mid;
+        }
+        int ra = lo, rb = d0 - lo;
+        double dA = lightD(ra);  // lightD(NLtot) = Dtot
+        double cB = rb < NHtot ? heavyC(rb) : 0.0;
+        for (int k = 0; k < KM && d0 + k < n; ++k) {
+            const bool heavy = rb < NHtot && (ra >= NLtot || cB <= dA);
+            int i, al;
+            double q;
+            if (heavy) {
+                i = heavyIdx(rb);
+                if (rb == NHtot - 1) {
                     q = 1.0;
                     al = i;
                 } else {
-                    const double C = dc[k];
-                    // first light start >= C (lightD(NLtot) = Dtot)
-                    int lo = alo, hi = NLtot;
-                    for (int s = 0; s < kWalk && lo < hi && !(lightD(lo) >= C); ++s) ++lo;
-                    if (lo < hi && !(lightD(lo) >= C)) {
-                        while (lo < hi) {
-                            const int mid = (lo + hi) >> 1;
-                            if (lightD(mid) >= C) hi = mid; else lo = mid + 1;
-                        }
-                    }
-                    alo = lo;
-                    q = 1.0 + C - lightD(lo);
+                    q = 1.0 + cB - dA;
                     q = q < 0.0 ? 0.0 : q;
-                    al = heavyIdx[m + 1];
+                    al = heavyIdx(rb + 1);
                 }
+                ++rb;
+                cB = rb < NHtot ? heavyC(rb) : 0.0;
+            } else {
+                i = idx[ra];
+                const double dn = lightD(ra + 1);
+                q = 1.0 - (dn - dA);
+                q = q < 0.0 ? 0.0 : q;
+                al = heavyIdx(rb < NHtot ? rb : NHtot - 1);
+                ++ra;
+                dA = dn;
             }
             uint32_t thr;
             if (q >= 1.0) {
@@ -493,9 +501,11 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
             } else {
                 thr = (uint32_t)(q * 4294967296.0);
             }
-            if ((unsigned)al >= (unsigned)n) {  // never for a consistent row; keeps walks in range
-                al = i;
+            if ((unsigned)al >= (unsigned)n || (unsigned)i >= (unsigned)n) {
+                // never for a consistent row; keeps walks and stores in range
                 atomicOr(a.status, MCNEGF_FLAG_NONFINITE);
+                if ((unsigned)i >= (unsigned)n) continue;
+                al = i;
             }
             out[i] = (thr & ~kAliasIdxMask) | (uint32_t)al;
             out_lo[i] = (uint16_t)(thr & kAliasIdxMask);
@@ -503,7 +513,43 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
     }
 }
 
-hipError_t launch_alias_build(const mcnegf_kernel& k, double rowsum_tol, hipStream_t s) {
+// ---------------------------------------------------------------- interpolation check
+// For each pair of neighbouring energies (e, e + 1) of a build: the largest, over the kernel
+// rows, L1 distance between the two normalised rows, sum_i |w_i(e) / W(e) - w_i(e+1) / W(e+1)|
+// (Sec. V A, "Interpolation": where the probabilities at two nearby energies differ little,
+// those between them are interpolated linearly).  One workgroup per (row, pair); rows are
+// combined by an integer max on the bit pattern (non-negative doubles order as their bits).
+// A row with a total that is not positive and finite counts as distance 2 (the largest).
+__global__ void __launch_bounds__(256) interp_distance_kernel(AliasArgs a,
+                                                              unsigned long long* dist) {
+    __shared__ double sd[4];
+    const int n = a.N + 2;
+    const int row = blockIdx.x;
+    const int e = blockIdx.y;
+    double t0 = 0.0, t1 = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        t0 += kernel_weight(a, e, row, i);
+        t1 += kernel_weight(a, e + 1, row, i);
+    }
+    t0 = block_sum<256>(t0, sd);
+    t1 = block_sum<256>(t1, sd);
+    double d = 2.0;
+    if (t0 > 0.0 && t1 > 0.0 && isfinite(t0) && isfinite(t1)) {
+        const double r0 = 1.0 / t0, r1 = 1.0 / t1;
+        double part = 0.0;
+        for (int i = threadIdx.x; i < n; i += 256)
+            part += fabs(kernel_weight(a, e, row, i) * r0 - kernel_weight(a, e + 1, row, i) * r1);
+        d = block_sum<256>(part, sd);
+    }
+    if (threadIdx.x == 0) atomicMax(dist + e, (unsigned long long)__double_as_longlong(d));
+}
+
+__global__ void fill_u64_kernel(unsigned long long* p, int n, unsigned long long v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+static AliasArgs alias_args(const mcnegf_kernel& k, double rowsum_tol) {
     AliasArgs a;
     a.P = k.P;
     a.wL = k.wL;
@@ -521,6 +567,30 @@ hipError_t launch_alias_build(const mcnegf_kernel& k, double rowsum_tol, hipStre
     a.W = k.W;
     a.open_cut = 1e3 * k.delta_lead * k.t * k.W;
     a.rowsum_tol = rowsum_tol;
+    return a;
+}
+
+hipError_t launch_interp_distances(const mcnegf_kernel& k, double* dist, hipStream_t s) {
+    const int pairs = k.nE - 1;
+    if (pairs < 1) return hipSuccess;
+    unsigned long long* d = reinterpret_cast<unsigned long long*>(dist);
+    {
+        MCNEGF_TIMED("fill_u64_kernel", s);
+        hipLaunchKernelGGL(fill_u64_kernel, dim3((pairs + 255) / 256), dim3(256), 0, s, d, pairs,
+                           0ull);
+    }
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    {
+        MCNEGF_TIMED("interp_distance_kernel", s);
+        hipLaunchKernelGGL(interp_distance_kernel, dim3(k.n_out, pairs), dim3(256), 0, s,
+                           alias_args(k, 0.0), d);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_alias_build(const mcnegf_kernel& k, double rowsum_tol, hipStream_t s) {
+    const AliasArgs a = alias_args(k, rowsum_tol);
     const int n = k.n_out;
     const size_t lds = (size_t)(n + 1) * 8 + (size_t)n * 2;
     // rows up to 1024 outcomes: 256 threads x 4 items; up to 1536: 256 x 6; up to 4096:

@@ -52,6 +52,38 @@ __host__ __device__ inline double2 cdiv(double2 a, double2 b) { return cmul(a, c
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// Position of energy E among the built energies nodes[0 .. nE-1] (ascending) for interpolated
+// walks (Sec. V A, "Interpolation"): lo = the last node at or below E, alpha = (E - E_lo) /
+// (E_hi - E_lo) as a 32-bit threshold a32 = min(floor(alpha 2^32), 2^32 - 1); at the last node
+// lo = nE - 1 and a32 = 0.  An energy outside the nodes, or nodes that do not ascend, set bad
+// (the energy is then clamped to the nearest end).
+__device__ inline void interp_bracket(const double* nodes, uint32_t nE, double E, uint32_t& lo,
+                                      uint32_t& a32, bool& bad) {
+    const double first = nodes[0], last = nodes[nE - 1];
+    bad = false;
+    a32 = 0u;
+    if (nE == 1 || !(E > first)) {
+        lo = 0;
+        bad = !(E == first);
+        return;
+    }
+    if (!(E < last)) {
+        lo = nE - 1;
+        bad = !(E == last);
+        return;
+    }
+    uint32_t l = 0, h = nE - 1;  // nodes[l] <= E < nodes[h]
+    while (h - l > 1) {
+        const uint32_t m = (l + h) >> 1;
+        if (nodes[m] <= E) l = m; else h = m;
+    }
+    const double lo_E = nodes[l], hi_E = nodes[l + 1];
+    bad = !(hi_E > lo_E);
+    const double x = (E - lo_E) / (hi_E - lo_E) * 4294967296.0;
+    a32 = x >= 4294967295.0 ? 0xFFFFFFFFu : (x > 0.0 ? (uint32_t)x : 0u);
+    lo = l;
+}
+
 // ---- workspace layout ------------------------------------------------------------------
 struct Layout {
     int64_t alias_pitch, p_pitch;
@@ -141,6 +173,15 @@ hipError_t launch_walk_sampled(const mcnegf_kernel& k, const SampledScratch& sc,
 hipError_t launch_sampled_current(const mcnegf_kernel& k, uint32_t inject_lead,
                                   const int64_t* tallies, const double* weights, double* T,
                                   double* sigmaT, hipStream_t s);
+hipError_t launch_walk_interp(const mcnegf_kernel& k, const double* fine, uint32_t nF,
+                              uint64_t seed, uint32_t tag, uint32_t walker_begin,
+                              uint32_t n_walkers, uint32_t max_steps, int64_t* tallies,
+                              hipStream_t s);
+hipError_t launch_interp_current(const mcnegf_kernel& k, const double* fine, uint32_t nF,
+                                 uint32_t inject_lead, const int64_t* tallies,
+                                 const double* weights, double* T, double* sigmaT,
+                                 hipStream_t s);
+hipError_t launch_interp_distances(const mcnegf_kernel& k, double* dist, hipStream_t s);
 hipError_t launch_grad(const mcnegf_kernel& k, const GradBuffers& gb, uint32_t inject_lead,
                        const double* weights, double* dI_dV, double* dI_dgamma, hipStream_t s);
 

@@ -88,6 +88,61 @@ hipError_t launch_mc_current(const mcnegf_kernel& k, uint32_t inject_lead, const
     return hipGetLastError();
 }
 
+// Interpolated walks (Sec. V A, "Interpolation"): fine energy f between the built energies
+// E_lo and E_hi with mixture weight alpha = a32 / 2^32 (the one its walks used); the row total
+// that scales the estimator is interpolated like the rows, c = (1 - alpha) c_lo + alpha c_hi,
+// then T_f and sigma_f as in MC mode.
+__global__ void interp_current_kernel(const int64_t* __restrict__ tallies,
+                                      const double* __restrict__ lead,
+                                      const double* __restrict__ nodes, uint32_t nE,
+                                      const double* __restrict__ fine, int nF,
+                                      uint32_t inject_lead, double* __restrict__ T,
+                                      double* __restrict__ sig, uint32_t* __restrict__ status) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nF) return;
+    uint32_t lo, a32;
+    bool bad;
+    interp_bracket(nodes, nE, fine[f], lo, a32, bad);
+    if (bad) atomicOr(status, MCNEGF_FLAG_RANGE);
+    const uint32_t hi = lo + 1 < nE ? lo + 1 : lo;
+    const int slot = inject_lead == 0 ? MCNEGF_LEAD_CL : MCNEGF_LEAD_CR;
+    const double alpha = (double)a32 * 0x1.0p-32;
+    const double c = (1.0 - alpha) * lead[(size_t)lo * MCNEGF_LEAD_NTERMS + slot] +
+                     alpha * lead[(size_t)hi * MCNEGF_LEAD_NTERMS + slot];
+    const int64_t* t = tallies + (size_t)f * MCNEGF_TALLY_N;
+    const double walkers =
+        (double)(t[MCNEGF_TALLY_EXIT_L] + t[MCNEGF_TALLY_EXIT_R] + t[MCNEGF_TALLY_TRUNC]);
+    const double hits = (double)(inject_lead == 0 ? t[MCNEGF_TALLY_EXIT_R] : t[MCNEGF_TALLY_EXIT_L]);
+    if (walkers <= 0.0) {
+        T[f] = 0.0;
+        sig[f] = 0.0;
+        return;
+    }
+    const double p = hits / walkers;
+    T[f] = c * p;
+    sig[f] = walkers > 1.0 ? c * sqrt(p * (1.0 - p) / (walkers - 1.0)) : 0.0;
+}
+
+hipError_t launch_interp_current(const mcnegf_kernel& k, const double* fine, uint32_t nF,
+                                 uint32_t inject_lead, const int64_t* tallies,
+                                 const double* weights, double* T, double* sigmaT,
+                                 hipStream_t s) {
+    {
+        MCNEGF_TIMED("interp_current_kernel", s);
+        hipLaunchKernelGGL(interp_current_kernel, dim3((nF + 255) / 256), dim3(256), 0, s,
+                           tallies, k.lead, k.energies, (uint32_t)k.nE, fine, (int)nF,
+                           inject_lead, T, sigmaT, k.status);
+    }
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    {
+        MCNEGF_TIMED("current_sum_kernel", s);
+        hipLaunchKernelGGL(current_sum_kernel, dim3(1), dim3(256), 0, s, T, sigmaT, weights,
+                           (int)nF, k.reduce);
+    }
+    return hipGetLastError();
+}
+
 // Energies drawn with probability w_k / W (W = sum_k w_k, Sec. II F step 2 with h = w / W)
 // and the estimator of the linear-response transmission with h proportional to the weight
 // (Sec. II G, Eq. (66) read with f -> w): X = W c_p(E_k) for an exit at q, else 0, so that

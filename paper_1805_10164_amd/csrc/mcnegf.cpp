@@ -445,6 +445,86 @@ int32_t mc_negf_walk_sampled_noalloc(const mcnegf_kernel* k, uint64_t seed,
     return err == hipSuccess ? MCNEGF_OK : hip_fail(err);
 }
 
+// ---- interpolated step-6' probabilities (Sec. V A, "Interpolation") ---------------------
+
+int32_t mc_negf_interp_distances(const mcnegf_kernel* k, double* d_dist, hipStream_t stream) {
+    if (!valid_kernel(k) || !d_dist || k->nE < 2 || !k->wL || !k->wR || !k->gamma)
+        return MCNEGF_EINVAL;
+    hipError_t err = launch_interp_distances(*k, d_dist, stream);
+    return err == hipSuccess ? MCNEGF_OK : hip_fail(err);
+}
+
+int32_t mc_negf_interp_plan(const double* h_nodes, int32_t nN, const double* h_dist,
+                            const double* h_fine, int32_t nF, double tol, int32_t* h_exact,
+                            int32_t* n_exact) {
+    if (!h_nodes || nN < 1 || (nN > 1 && !h_dist) || !h_fine || nF < 1 || !h_exact ||
+        !n_exact || !(tol >= 0.0))
+        return MCNEGF_EINVAL;
+    for (int32_t i = 0; i + 1 < nN; ++i)
+        if (!(h_nodes[i + 1] > h_nodes[i])) return MCNEGF_EINVAL;
+    int32_t m = 0;
+    for (int32_t f = 0; f < nF; ++f) {
+        const double E = h_fine[f];
+        if (!(E >= h_nodes[0]) || !(E <= h_nodes[nN - 1])) return MCNEGF_EINVAL;
+        // the interval [nodes[lo], nodes[lo + 1]) holding E; a node itself is exact already
+        const int32_t lo = (int32_t)(std::upper_bound(h_nodes, h_nodes + nN, E) - h_nodes) - 1;
+        if (E == h_nodes[lo]) continue;
+        if (!(h_dist[lo] <= tol)) h_exact[m++] = f;
+    }
+    *n_exact = m;
+    return MCNEGF_OK;
+}
+
+static bool valid_interp_walk(const mcnegf_kernel* k, const double* fine, int32_t nF,
+                              uint32_t realization, uint32_t inject_lead, uint64_t walker_begin,
+                              uint64_t n_walkers, uint32_t max_steps, const int64_t* tallies) {
+    if (!valid_kernel(k) || !k->alias || !k->alias_lo || !fine || nF < 1 || nF > 0x7FFFFFFE ||
+        !tallies || inject_lead > 1 || realization >= (1u << 30) || max_steps < 1)
+        return false;
+    return walker_begin < 0x100000000ull && n_walkers < 0x100000000ull &&
+           walker_begin + n_walkers < 0x100000000ull;
+}
+
+int32_t mc_negf_walk_interp(const mcnegf_kernel* k, const double* d_fine_energies, int32_t nF,
+                            uint64_t seed, uint32_t realization, uint32_t inject_lead,
+                            uint64_t walker_begin, uint64_t n_walkers_per_energy,
+                            uint32_t max_steps, int64_t* d_tallies, hipStream_t stream) {
+    if (!valid_interp_walk(k, d_fine_energies, nF, realization, inject_lead, walker_begin,
+                           n_walkers_per_energy, max_steps, d_tallies))
+        return MCNEGF_EINVAL;
+    if (n_walkers_per_energy == 0) return MCNEGF_OK;
+    const uint32_t tag = (realization << 1) | inject_lead;
+    hipError_t err = launch_walk_interp(*k, d_fine_energies, (uint32_t)nF, seed, tag,
+                                        (uint32_t)walker_begin, (uint32_t)n_walkers_per_energy,
+                                        max_steps, d_tallies, stream);
+    return err == hipSuccess ? MCNEGF_OK : hip_fail(err);
+}
+
+int32_t mc_negf_current_interp(const mcnegf_kernel* k, const double* d_fine_energies,
+                               int32_t nF, uint32_t inject_lead, const int64_t* d_tallies,
+                               const double* d_weights, double* d_T, double* d_sigmaT,
+                               double* h_I_sigma, hipStream_t stream) {
+    if (!valid_kernel(k) || !k->alias || !d_fine_energies || nF < 1 || !d_tallies ||
+        !d_weights || !d_T || !d_sigmaT || !h_I_sigma || inject_lead > 1)
+        return MCNEGF_EINVAL;
+    hipError_t err = launch_interp_current(*k, d_fine_energies, (uint32_t)nF, inject_lead,
+                                           d_tallies, d_weights, d_T, d_sigmaT, stream);
+    if (err != hipSuccess) return hip_fail(err);
+    double host[2];
+    uint32_t flags = 0;
+    if ((err = hipMemcpyAsync(host, k->reduce, sizeof(host), hipMemcpyDeviceToHost, stream)) !=
+        hipSuccess)
+        return hip_fail(err);
+    if ((err = hipMemcpyAsync(&flags, k->status, sizeof(flags), hipMemcpyDeviceToHost, stream)) !=
+        hipSuccess)
+        return hip_fail(err);
+    if ((err = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(err);
+    h_I_sigma[0] = host[0];
+    h_I_sigma[1] = std::sqrt(host[1] > 0.0 ? host[1] : 0.0);
+    if (flags & MCNEGF_FLAG_RANGE) return MCNEGF_EINVAL;
+    return status_to_code(flags, true);
+}
+
 static bool batch_units(const mcnegf_kernel* kernels, int32_t n, uint64_t* units) {
     if (!kernels || n < 1) return false;
     uint64_t u = 0;

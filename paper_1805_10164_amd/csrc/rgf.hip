@@ -447,6 +447,177 @@ __global__ void __launch_bounds__(64) rgf_diag_wide_kernel(const double* __restr
     if (!ok && lane == 0) atomicOr(status, MCNEGF_FLAG_SINGULAR);
 }
 
+// ---- wide sweeps on a workgroup: one (energy, direction) chain per 256 threads ----------
+//
+// The W x W block (padded to 32 x 32 with the identity) is spread over four wavefronts: lane
+// l of wavefront w holds column c = 8 w + (l >> 3) at rows 4 (l & 7) + s, s = 0..3.  The block
+// is inverted in place by Gauss-Jordan exchange steps with the same pivot rule as above (at
+// column p, the not-yet-used row r of largest |x_rp|, lowest row on ties): with pinv = 1/x_rp,
+//   x_rc <- x_rc pinv (c != p),  x_rp <- pinv,
+//   x_ic <- x_ic - x_ip x_rc pinv (i != r, c != p),  x_ip <- -x_ip pinv (i != r).
+// After the W steps the stored Y holds the inverse with rows and columns permuted: with
+// pi(p) = r_p, (X^{-1})[p][q] = Y[pi(p)][pi^{-1}(q)].  Column p of each step reaches every
+// thread through LDS (written by its owners at the end of step p - 1, double-buffered: one
+// barrier per step); the pivot row's entry x_rc is in the same wavefront and is read with a
+// lane shuffle.  Every thread computes the same pivot from the same LDS column.
+
+struct WgLds {
+    double2 col[2][32];   // pivot column of the current step, double-buffered
+    double2 y[32][33];    // the permuted inverse, gathered at the end of a slice
+    int perm[32];         // perm[p] = r_p
+    int iperm[32];        // iperm[r_p] = p
+};
+
+template <int W>
+__global__ void __launch_bounds__(256) rgf_sweep_wg_kernel(const double* __restrict__ energies,
+                                                           const double* __restrict__ onsite,
+                                                           const double* __restrict__ gamma,
+                                                           const double2* __restrict__ sigma,
+                                                           int L, double t,
+                                                           double2* __restrict__ gL,
+                                                           double2* __restrict__ gR,
+                                                           uint32_t* __restrict__ status) {
+    __shared__ WgLds S;
+    const int e = blockIdx.x >> 1;
+    const int dir = blockIdx.x & 1;
+    const int lane = threadIdx.x & 63;
+    const int c = 8 * (threadIdx.x >> 6) + (lane >> 3);  // this thread's column
+    const int rg = lane & 7;                              // rows 4 rg .. 4 rg + 3
+    const double E = energies[e];
+    const double2* sig = sigma + (size_t)e * W * W;
+    double2* out = (dir == 0 ? gL : gR) + (size_t)e * L * W * W;
+    const double t2 = t * t;
+    bool ok = true;
+    double2 gprev[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) gprev[s] = cmk(0.0, 0.0);
+    // onsite energy and dephasing rate of site (k, c), loaded one slice ahead
+    const int cs = c < W ? c : 0;
+    const int k_first = dir == 0 ? 0 : L - 1;
+    double Vn = onsite[k_first * W + cs], gn = gamma[k_first * W + cs];
+    for (int sl = 0; sl < L; ++sl) {
+        const int k = dir == 0 ? sl : L - 1 - sl;
+        const double Vc = Vn, gc = gn;
+        if (sl + 1 < L) {
+            const int kn = dir == 0 ? sl + 1 : L - 2 - sl;
+            Vn = onsite[kn * W + cs];
+            gn = gamma[kn * W + cs];
+        }
+        // this thread's entries of X = A_k - t^2 g_{k-1} (identity outside W x W)
+        double2 a[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int i = 4 * rg + s;
+            double2 v = cmk(i == c ? 1.0 : 0.0, 0.0);
+            if (i < W && c < W) {
+                v = cmk(0.0, 0.0);
+                if (i == c) v = cmk(E - Vc, 0.5 * gc);
+                if (i == c - 1 || i == c + 1) v = cmk(t, 0.0);
+                if (k == 0) v = csub(v, sig[i * W + c]);
+                if (k == L - 1) v = csub(v, sig[i * W + c]);
+                if (sl > 0) v = csub(v, cscale(gprev[s], t2));
+            }
+            a[s] = v;
+        }
+        if (c == 0) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) S.col[0][4 * rg + s] = a[s];
+        }
+        __syncthreads();
+        uint32_t used = 0u;
+        for (int p = 0; p < W; ++p) {  // uniform loop
+            const double2* cb = S.col[p & 1];
+            double2 f[4];
+            double best = -1.0;
+            int bi = 64;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int i = 4 * rg + s;
+                f[s] = cb[i];
+                const double m = (i < W && !((used >> i) & 1u)) ? cabs2(f[s]) : -1.0;
+                const bool take = m > best;  // rows in increasing order: ties keep the lower
+                best = take ? m : best;
+                bi = take ? i : bi;
+            }
+            // argmax over the 8 lanes of this column's group (ties: lowest row)
+#pragma unroll
+            for (int o = 1; o < 8; o <<= 1) {
+                const double ob = __shfl_xor(best, o, 64);
+                const int oi = __shfl_xor(bi, o, 64);
+                const bool take = (ob > best) | ((ob == best) & (oi < bi));
+                best = take ? ob : best;
+                bi = take ? oi : bi;
+            }
+            int r = __builtin_amdgcn_readfirstlane(bi);
+            if (r >= W) {  // no finite candidate (NaN entries): flag it, keep indices in range
+                r = __builtin_ctz(~used);
+                ok = false;
+            }
+            const double2 pv = cb[r];
+            const double pm = cabs2(pv);
+            if (!(pm > 0.0) || !isfinite(pm)) ok = false;
+            const double2 pinv = crecip(pv);
+            // x_rc from the lane holding row r of this column
+            // a[r & 3] as a masked sum (a select chain would become a dynamic index into
+            // scratch memory)
+            const int rs = r & 3;
+            double2 own = cmk(0.0, 0.0);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const double m = (double)(s == rs);
+                own.x = fma(a[s].x, m, own.x);
+                own.y = fma(a[s].y, m, own.y);
+            }
+            const int src = (lane & ~7) | (r >> 2);
+            const double2 xrc = cmk(__shfl(own.x, src, 64), __shfl(own.y, src, 64));
+            const double2 q = cmul(xrc, pinv);
+            const bool piv_col = c == p;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int i = 4 * rg + s;
+                const bool piv_row = i == r;
+                double2 u = a[s];
+                cfms(u, f[s], q);                      // x_ic - x_ip x_rc pinv
+                const double2 wcol = cmul(f[s], pinv);  // x_ip pinv
+                double2 v;
+                v.x = piv_col ? (piv_row ? pinv.x : -wcol.x) : (piv_row ? q.x : u.x);
+                v.y = piv_col ? (piv_row ? pinv.y : -wcol.y) : (piv_row ? q.y : u.y);
+                a[s] = v;
+            }
+            used |= 1u << r;
+            if (threadIdx.x == 0) {
+                S.perm[p] = r;
+                S.iperm[r] = p;
+            }
+            if (c == p + 1) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) S.col[(p + 1) & 1][4 * rg + s] = a[s];
+            }
+            __syncthreads();
+        }
+        // gather g_k = X^{-1}: entry (i, c) = Y[perm[i]][iperm[c]]
+#pragma unroll
+        for (int s = 0; s < 4; ++s) S.y[4 * rg + s][c] = a[s];
+        __syncthreads();
+        if (c < W) {
+            const int jc = S.iperm[c];
+            double2* o = out + (size_t)k * W * W;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int i = 4 * rg + s;
+                if (i < W) {
+                    const double2 v = S.y[S.perm[i]][jc];
+                    gprev[s] = v;
+                    o[i * W + c] = v;
+                }
+            }
+        }
+        // S.col[0] is written next at the start of the next slice, after these reads of S.y,
+        // S.perm and S.iperm; they are rewritten only after the next slice's first barrier
+    }
+    if (!ok && threadIdx.x == 0) atomicOr(status, MCNEGF_FLAG_SINGULAR);
+}
+
 template <int W>
 static hipError_t launch_rgf_wide(const mcnegf_kernel& k, const double* onsite, hipStream_t s) {
     const double2* sig = reinterpret_cast<const double2*>(k.sigma);
@@ -454,7 +625,7 @@ static hipError_t launch_rgf_wide(const mcnegf_kernel& k, const double* onsite, 
     double2* gR = reinterpret_cast<double2*>(k.gR);
     {
         MCNEGF_TIMED("rgf_sweep_kernel", s);
-        hipLaunchKernelGGL(rgf_sweep_wide_kernel<W>, dim3(2 * k.nE), dim3(64), 0, s, k.energies,
+        hipLaunchKernelGGL(rgf_sweep_wg_kernel<W>, dim3(2 * k.nE), dim3(256), 0, s, k.energies,
                            onsite, k.gamma, sig, k.L, k.t, gL, gR, k.status);
     }
     hipError_t err = hipGetLastError();

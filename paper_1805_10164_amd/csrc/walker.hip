@@ -758,6 +758,222 @@ hipError_t launch_walk_batch(const mcnegf_batch& b, uint64_t seed, uint32_t walk
     }
 }
 
+// ---- interpolated walks (Sec. V A, "Interpolation") ----------------------------------------
+//
+// Fine energy f lies between the built energies E_lo <= E_f < E_hi (interp_bracket); its step-6'
+// rows are (1 - alpha) p(E_lo) + alpha p(E_hi), a mixture: step n of walker w takes one Philox
+// block of counter (n, w, f | 2^31, tag), uses words 0 and 1 as (a, b) of the alias draw and
+// draws from E_hi's table when word 2 is below the 32-bit threshold of alpha, else from E_lo's
+// (Lemire redraws: counter (n, w, f | 2^31, tag | 2^31), key (key0, key1 ^ r)).  The fine
+// energies are the units of a persistent launch: a wavefront walks one chunk of one fine
+// energy at a time, with the unit's two tables in scalar registers, and adds the chunk's
+// counts to the fine energy's tallies.
+struct InterpArgs {
+    const uint32_t* tables;  // packed entries of every built energy
+    const uint16_t* lows;
+    int64_t table_stride;    // entries per energy
+    const double* nodes;     // [nE] built energies, ascending
+    const double* fine;      // [nF]
+    uint32_t nE, nF, pitch, n_out, N;
+    uint32_t key0, key1, tag;
+    uint32_t wbegin, wend, chunk, chunks_per_unit;
+    uint32_t max_steps;
+    int64_t* tallies;  // [nF][5]
+    uint32_t* status;
+};
+
+template <int K>
+__global__ void __launch_bounds__(256) walk_interp_kernel(InterpArgs A) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t wpb = blockDim.x >> 6;
+    const uint32_t waves = __builtin_amdgcn_readfirstlane(gridDim.x * wpb);
+    const uint32_t lw = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
+    const uint32_t total = A.nF * A.chunks_per_unit;
+    const uint32_t n_out = A.n_out, N = A.N;
+    const uint32_t thresh = (0u - n_out) % n_out;
+    const uint32_t inject_row = N + (A.tag & 1u);
+    for (uint32_t cid0 = lw; cid0 < total; cid0 += waves) {  // uniform loop
+        const uint32_t cid = __builtin_amdgcn_readfirstlane(cid0);
+        const uint32_t f = cid / A.chunks_per_unit;
+        uint32_t lo, a32;
+        bool bad;
+        interp_bracket(A.nodes, A.nE, A.fine[f], lo, a32, bad);
+        lo = __builtin_amdgcn_readfirstlane(lo);
+        a32 = __builtin_amdgcn_readfirstlane(a32);
+        const uint32_t hi = lo + 1 < A.nE ? lo + 1 : lo;
+        const uint32_t* t_lo = (const uint32_t*)uniform_ptr(A.tables + (size_t)lo * A.table_stride);
+        const uint32_t* t_hi = (const uint32_t*)uniform_ptr(A.tables + (size_t)hi * A.table_stride);
+        const uint16_t* l_lo = (const uint16_t*)uniform_ptr(A.lows + (size_t)lo * A.table_stride);
+        const uint16_t* l_hi = (const uint16_t*)uniform_ptr(A.lows + (size_t)hi * A.table_stride);
+        const uint32_t fe = f | 0x80000000u;
+        uint32_t next = A.wbegin + (cid - f * A.chunks_per_unit) * A.chunk;
+        const uint32_t wend = (uint32_t)min((uint64_t)next + A.chunk, (uint64_t)A.wend);
+        Step st[K];
+        uint32_t w[K];
+        uint32_t cL = 0, cR = 0, tr = 0;
+        uint64_t s1 = 0, s2 = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            st[k] = Step{inject_row, 0u, false};
+            w[k] = 0u;
+        }
+        for (;;) {
+            // refill idle slots (slot-major, then lane order) from the chunk
+            if (next < wend) {
+                uint64_t need[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) need[k] = __ballot(!st[k].active);
+                const uint32_t avail = wend - next;
+                uint32_t base = 0;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const uint32_t before = base + __popcll(need[k] & lt_mask);
+                    const bool take = !st[k].active && before < avail;
+                    count_ended_lane(cL, cR, tr, s1, s2, take && st[k].n != 0u, st[k], N);
+                    w[k] = take ? next + before : w[k];
+                    st[k].s = take ? inject_row : st[k].s;
+                    st[k].n = take ? 0u : st[k].n;
+                    st[k].active = st[k].active || take;
+                    base += __popcll(need[k]);
+                }
+                next += base < avail ? base : avail;
+            }
+            uint64_t any = 0ull;
+#pragma unroll
+            for (int k = 0; k < K; ++k) any |= __ballot(st[k].active);
+            if (any == 0ull) break;
+            uint32_t bw[K];
+            bool up[K];
+            uint64_t m[K];
+            bool rej[K];
+            uint64_t rb = 0ull;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const Philox4 x = philox4x32_10(st[k].n, w[k], fe, A.tag, A.key0, A.key1);
+                bw[k] = x.x[1];
+                up[k] = x.x[2] < a32;
+                m[k] = (uint64_t)x.x[0] * n_out;
+                rej[k] = st[k].active && ((uint32_t)m[k] < thresh);
+                rb |= __ballot(rej[k]);
+            }
+            uint32_t r = 0;
+            while (rb != 0ull) {  // rare; uniform loop
+                ++r;
+                rb = 0ull;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const uint32_t a2 = philox4x32_10(st[k].n, w[k], fe, A.tag | 0x80000000u,
+                                                      A.key0, A.key1 ^ r).x[0];
+                    const uint64_t m2 = (uint64_t)a2 * n_out;
+                    m[k] = rej[k] ? m2 : m[k];
+                    rej[k] = rej[k] && ((uint32_t)m2 < thresh);
+                    rb |= __ballot(rej[k]);
+                }
+            }
+            uint32_t c[K], at[K], ent[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                c[k] = (uint32_t)(m[k] >> 32);
+                at[k] = __umul24(st[k].s, A.pitch) + c[k];
+                ent[k] = 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (st[k].active) ent[k] = (up[k] ? t_hi : t_lo)[at[k]];
+            bool keep[K], tie[K];
+            uint64_t tb = 0ull;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                keep[k] = (bw[k] >> kAliasIdxBits) < (ent[k] >> kAliasIdxBits);
+                tie[k] = st[k].active && (bw[k] >> kAliasIdxBits) == (ent[k] >> kAliasIdxBits);
+                tb |= __ballot(tie[k]);
+            }
+            if (tb != 0ull) {  // rare; uniform branch
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const uint32_t lo16 = tie[k] ? (uint32_t)(up[k] ? l_hi : l_lo)[at[k]] : 0u;
+                    keep[k] = tie[k] ? (bw[k] & kAliasIdxMask) < lo16 : keep[k];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const uint32_t nxt = keep[k] ? c[k] : (ent[k] & kAliasIdxMask);
+                const uint32_t n1 = st[k].n + 1;
+                const bool active = st[k].active;
+                const bool ends = nxt >= N || n1 >= A.max_steps;
+                st[k].s = active ? nxt : st[k].s;
+                st[k].n = active ? n1 : st[k].n;
+                st[k].active = active && !ends;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) count_ended_lane(cL, cR, tr, s1, s2, st[k].n != 0u, st[k], N);
+        const uint64_t v0 = wave_sum_u64(cL), v1 = wave_sum_u64(cR), v2 = wave_sum_u64(tr);
+        const uint64_t v3 = wave_sum_u64(s1), v4 = wave_sum_u64(s2);
+        unsigned long long* gt =
+            reinterpret_cast<unsigned long long*>(A.tallies + (size_t)f * MCNEGF_TALLY_N);
+        if (lane == 0) {
+            if (v0) atomicAdd(gt + MCNEGF_TALLY_EXIT_L, (unsigned long long)v0);
+            if (v1) atomicAdd(gt + MCNEGF_TALLY_EXIT_R, (unsigned long long)v1);
+            if (v2) atomicAdd(gt + MCNEGF_TALLY_TRUNC, (unsigned long long)v2);
+            if (v3) atomicAdd(gt + MCNEGF_TALLY_STEPS, (unsigned long long)v3);
+            if (v4) atomicAdd(gt + MCNEGF_TALLY_STEPS2, (unsigned long long)v4);
+            if (v2) atomicOr(A.status, MCNEGF_FLAG_TRUNC);
+            if (bad) atomicOr(A.status, MCNEGF_FLAG_RANGE);
+        }
+    }
+}
+
+hipError_t launch_walk_interp(const mcnegf_kernel& k, const double* fine, uint32_t nF,
+                              uint64_t seed, uint32_t tag, uint32_t walker_begin,
+                              uint32_t n_walkers, uint32_t max_steps, int64_t* tallies,
+                              hipStream_t s) {
+    if (n_walkers == 0 || nF == 0) return hipSuccess;
+    constexpr int K = 3;
+    InterpArgs A;
+    A.table_stride = (int64_t)k.n_out * k.alias_pitch;
+    A.tables = k.alias;
+    A.lows = k.alias_lo;
+    A.nodes = k.energies;
+    A.fine = fine;
+    A.nE = (uint32_t)k.nE;
+    A.nF = nF;
+    A.pitch = (uint32_t)k.alias_pitch;
+    A.n_out = (uint32_t)k.n_out;
+    A.N = (uint32_t)k.N;
+    A.key0 = (uint32_t)(seed & 0xffffffffu);
+    A.key1 = (uint32_t)(seed >> 32);
+    A.tag = tag;
+    A.wbegin = walker_begin;
+    A.wend = walker_begin + n_walkers;
+    uint64_t ch = 64ull * K * 8;
+    if (ch > n_walkers) ch = n_walkers;
+    A.chunk = (uint32_t)ch;
+    A.chunks_per_unit = (uint32_t)((n_walkers + ch - 1) / ch);
+    A.max_steps = max_steps;
+    A.tallies = tallies;
+    A.status = k.status;
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t err;
+    if ((err = hipGetDevice(&dev)) != hipSuccess) return err;
+    if ((err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) !=
+        hipSuccess)
+        return err;
+    if ((err = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+             &per_cu, (const void*)walk_interp_kernel<K>, 256, 0)) != hipSuccess)
+        return err;
+    uint64_t blocks = (uint64_t)(per_cu < 1 ? 1 : per_cu) * (uint64_t)cus;
+    const uint64_t chunks = (uint64_t)nF * A.chunks_per_unit;
+    const uint64_t need = (chunks + 3) / 4;
+    if (blocks > need) blocks = need;
+    {
+        MCNEGF_TIMED("walk_interp_kernel", s);
+        hipLaunchKernelGGL(walk_interp_kernel<K>, dim3((unsigned)blocks), dim3(256), 0, s, A);
+    }
+    return hipGetLastError();
+}
+
 // ---- energies drawn from the weights (importance sampling of E_0, Sec. II F step 2) ------
 //
 // Walker w (global index) draws its energy from p_k = w_k / sum_j w_j with the Philox block of

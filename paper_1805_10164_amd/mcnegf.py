@@ -20,6 +20,7 @@ OK, WTRUNC, WNUMERIC = 0, 1, 2
 EINVAL, EWS, EHIP, ENUMERIC, ENOTIMPL = -1, -2, -3, -4, -5
 FLAG_NONFINITE, FLAG_SINGULAR, FLAG_ROWSUM, FLAG_NOABSORB, FLAG_TRUNC, FLAG_NOTSPD = (
     0x01, 0x02, 0x04, 0x08, 0x10, 0x20)
+FLAG_RANGE = 0x40
 LEAD_NTERMS = 8
 LEAD_TLL, LEAD_TRL, LEAD_TLR, LEAD_TRR, LEAD_CL, LEAD_CR, LEAD_TRGLA, LEAD_TRGRA = range(8)
 TALLY_N = 5
@@ -27,7 +28,8 @@ TALLY_EXIT_L, TALLY_EXIT_R, TALLY_TRUNC, TALLY_STEPS, TALLY_STEPS2 = range(5)
 EXPORTED = ("mc_negf_workspace_bytes", "mc_negf_build_kernel", "mc_negf_walk",
             "mc_negf_current", "mc_negf_grad_workspace_bytes", "mc_negf_grad",
             "mc_negf_current_async", "mc_negf_walk_sampled_bytes", "mc_negf_walk_sampled",
-            "mc_negf_walk_sampled_noalloc",
+            "mc_negf_walk_sampled_noalloc", "mc_negf_interp_distances", "mc_negf_interp_plan",
+            "mc_negf_walk_interp", "mc_negf_current_interp",
             "mc_negf_batch_bytes", "mc_negf_batch_prepare",
             "mc_negf_walk_batch", "mc_negf_walk_batch_autotune", "mc_negf_plan_waves",
             "mc_negf_graph_begin", "mc_negf_graph_end", "mc_negf_graph_launch",
@@ -112,6 +114,13 @@ def lib() -> ctypes.CDLL:
                                        u32, vp, vp, vp, u64, vp]
     L.mc_negf_walk_sampled_noalloc.argtypes = [ctypes.POINTER(KernelStruct), u64, u32, u32,
                                                u64, u64, u32, vp, vp, vp]
+    L.mc_negf_interp_distances.argtypes = [ctypes.POINTER(KernelStruct), vp, vp]
+    L.mc_negf_interp_plan.argtypes = [dp, i32, dp, dp, i32, ctypes.c_double,
+                                      ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.mc_negf_walk_interp.argtypes = [ctypes.POINTER(KernelStruct), vp, i32, u64, u32, u32, u64,
+                                      u64, u32, vp, vp]
+    L.mc_negf_current_interp.argtypes = [ctypes.POINTER(KernelStruct), vp, i32, u32, vp, vp, vp,
+                                         vp, dp, vp]
     L.mc_negf_batch_bytes.argtypes = [ctypes.POINTER(KernelStruct), i32, ctypes.POINTER(u64)]
     L.mc_negf_batch_prepare.argtypes = [ctypes.POINTER(KernelStruct), i32,
                                         ctypes.POINTER(u32), u32, ctypes.POINTER(vp), vp, u64,
@@ -506,3 +515,52 @@ def mc_negf_walk_sampled_noalloc(k: Kernel, seed: int, realization: int, inject_
                                               int(max_steps), _ptr(weights), _ptr(tallies),
                                               _stream(stream))
     return _check("mc_negf_walk_sampled_noalloc", code)
+
+
+# ---- interpolated step-6' probabilities -------------------------------------------------------
+
+def mc_negf_interp_distances(k: Kernel, dist, stream=None) -> int:
+    """dist [nE - 1] device: largest row L1 distance between neighbouring built energies."""
+    return _check("mc_negf_interp_distances",
+                  lib().mc_negf_interp_distances(ctypes.byref(k.struct), _ptr(dist),
+                                                 _stream(stream)))
+
+
+def mc_negf_interp_plan(nodes, dist, fine, tol):
+    """Indices of the fine energies that must be built exactly (host only)."""
+    nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+    dist = np.ascontiguousarray(dist, dtype=np.float64)
+    fine = np.ascontiguousarray(fine, dtype=np.float64)
+    out = np.zeros(len(fine), dtype=np.int32)
+    m = ctypes.c_int32(0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check("mc_negf_interp_plan",
+           lib().mc_negf_interp_plan(nodes.ctypes.data_as(dp), len(nodes),
+                                     dist.ctypes.data_as(dp), fine.ctypes.data_as(dp),
+                                     len(fine), float(tol),
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     ctypes.byref(m)))
+    return [int(x) for x in out[:m.value]]
+
+
+def mc_negf_walk_interp(k: Kernel, fine, seed: int, realization: int, inject_lead: int,
+                        walker_begin: int, n_walkers: int, max_steps: int, tallies,
+                        stream=None) -> int:
+    code = lib().mc_negf_walk_interp(ctypes.byref(k.struct), _ptr(fine), int(fine.numel()),
+                                     int(seed), int(realization), int(inject_lead),
+                                     int(walker_begin), int(n_walkers), int(max_steps),
+                                     _ptr(tallies), _stream(stream))
+    return _check("mc_negf_walk_interp", code)
+
+
+def mc_negf_current_interp(k: Kernel, fine, inject_lead: int, tallies, weights, T, sigmaT,
+                           stream=None, allow=(OK, WTRUNC, WNUMERIC)):
+    """(status, I, sigma_I) of interpolated walks; synchronises the stream."""
+    out = (ctypes.c_double * 2)()
+    code = lib().mc_negf_current_interp(ctypes.byref(k.struct), _ptr(fine), int(fine.numel()),
+                                        int(inject_lead), _ptr(tallies), _ptr(weights), _ptr(T),
+                                        _ptr(sigmaT),
+                                        ctypes.cast(out, ctypes.POINTER(ctypes.c_double)),
+                                        _stream(stream))
+    _check("mc_negf_current_interp", code, allow)
+    return code, float(out[0]), float(out[1])

@@ -245,3 +245,36 @@ def test_fp32_products_only_at_widths_16_and_32():
     # unknown flag bits are refused
     s = M.make_system(16, 20, flags=0x8)
     assert lib.mc_negf_workspace_bytes(ctypes.byref(s), 4, ctypes.byref(out)) == M.EINVAL
+
+
+def test_interp_plan_marks_energies_inside_far_intervals():
+    nodes = [0.0, 1.0, 2.0, 3.0]
+    dist = [0.01, 0.1, 0.02]
+    fine = [0.0, 0.5, 1.0, 1.5, 1.7, 2.5, 3.0]
+    assert M.mc_negf_interp_plan(nodes, dist, fine, 0.05) == [3, 4]
+    assert M.mc_negf_interp_plan(nodes, [0.01, float("nan"), 0.02], fine, 0.05) == [3, 4]
+    assert M.mc_negf_interp_plan(nodes, dist, fine, 0.2) == []
+    assert M.mc_negf_interp_plan(nodes, dist, fine, 0.0) == [1, 3, 4, 5]
+    with pytest.raises(M.McnegfError):
+        M.mc_negf_interp_plan([0.0, 2.0, 1.0], dist[:2], fine, 0.05)   # not ascending
+    with pytest.raises(M.McnegfError):
+        M.mc_negf_interp_plan(nodes, dist, [3.5], 0.05)                # outside the nodes
+
+
+def test_interp_walk_validation_without_gpu():
+    lib = M.lib()
+    ks = M.KernelStruct()
+    ks.W, ks.L, ks.N, ks.n_out, ks.nE, ks.p_pitch = 2, 3, 6, 8, 2, 16
+    for f in ("alias", "alias_lo", "P", "lead", "status", "counters", "reduce", "wL", "wR",
+              "gamma"):
+        setattr(ks, f, 4096)
+    z = ctypes.c_void_p(0)
+    p = ctypes.c_void_p(4096)
+    walk = lambda *a: lib.mc_negf_walk_interp(ctypes.byref(ks), *a)  # noqa: E731
+    assert walk(z, 3, 1, 0, 0, 0, 10, 10, p, z) == M.EINVAL          # no fine energies
+    assert walk(p, 0, 1, 0, 0, 0, 10, 10, p, z) == M.EINVAL          # nF = 0
+    assert walk(p, 3, 1, 0, 2, 0, 10, 10, p, z) == M.EINVAL          # lead
+    assert walk(p, 3, 1, 0, 0, 0, 1 << 32, 10, p, z) == M.EINVAL     # range
+    assert walk(p, 3, 1, 0, 0, 0, 10, 0, p, z) == M.EINVAL           # max_steps
+    ks.nE = 1
+    assert lib.mc_negf_interp_distances(ctypes.byref(ks), p, z) == M.EINVAL  # one energy

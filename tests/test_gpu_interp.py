@@ -1,0 +1,151 @@
+"""Interpolated step-6' probabilities (Sec. V A, "Interpolation") on the GPU, against the oracle.
+
+The interval distances must match the oracle's row distances; interpolated walks on the GPU's
+own alias tables must equal the oracle's C walker bit for bit (same mixture draw and Philox
+streams); the interpolated current must equal the oracle's estimator on the same tallies and
+lie within 3 sigma of the exact expectation of the interpolated walk (Markov chain of the mixed
+rows); an energy outside the built ones is reported.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import dense as D  # noqa: E402
+from oracle import interp as OI  # noqa: E402
+from oracle import walker as OW  # noqa: E402
+from paper_1805_10164_amd import inputs  # noqa: E402
+from paper_1805_10164_amd import mcnegf as M  # noqa: E402
+
+DEV = "cuda"
+SEED = 0x5EED
+
+
+def build_at(W, L, eta, nodes, seed=7, flags=0):
+    V = inputs.random_sites(W * L, seed, -0.3, 0.3)
+    g = np.full(W * L, eta)
+    sysm = M.make_system(W, L, flags=flags)
+    ws = M.allocate_workspace(sysm, len(nodes))
+    tV = torch.tensor(V, device=DEV)
+    tg = torch.tensor(g, device=DEV)
+    tE = torch.tensor(np.asarray(nodes, dtype=np.float64), device=DEV)
+    k = M.mc_negf_build_kernel(sysm, tV, tg, tE, ws)
+    k._keep = (tV,)
+    return k, V, g
+
+
+def test_interval_distances_match_oracle():
+    nodes = [-1.2, -1.19, -0.5, 0.3, 0.31, 1.9]
+    W, L, eta = 3, 6, 0.1
+    k, V, g = build_at(W, L, eta, nodes, flags=M.BUILD_NO_ALIAS | M.BUILD_NO_DIRECT)
+    dist = torch.empty(len(nodes) - 1, dtype=torch.float64, device=DEV)
+    M.mc_negf_interp_distances(k, dist)
+    got = dist.cpu().numpy()
+    sols = D.solve_workload(W, L, 1.0, V, g, nodes)
+    Ks = [s.transition_kernel() for s in sols]
+    ref = np.array([OI.row_distances(Ks[i], Ks[i + 1]).max() for i in range(len(nodes) - 1)])
+    assert np.abs(got - ref).max() < 1e-9, (got, ref)
+    assert got.min() < 0.05 < got.max()  # both kinds of interval occur
+
+
+FINE = [-1.0, -0.9, -0.61, -0.6, -0.2, 0.0, 0.45, 0.8]
+
+
+@pytest.mark.parametrize("inject,max_steps", [(0, 1_000_000), (1, 1_000_000), (0, 3)])
+def test_interpolated_walks_bit_exact(inject, max_steps):
+    nodes = [-1.0, -0.6, -0.2, 0.3, 0.8]
+    W, L, eta = 2, 5, 0.2
+    k, V, g = build_at(W, L, eta, nodes)
+    fine = torch.tensor(FINE, dtype=torch.float64, device=DEV)
+    tal = torch.zeros((len(FINE), M.TALLY_N), dtype=torch.int64, device=DEV)
+    M.mc_negf_walk_interp(k, fine, SEED, 5, inject, 77, 20_000, max_steps, tal)
+    thr, al = k.alias_tables()
+    br = [OI.bracket(nodes, E) for E in FINE]
+    ref = OW.walk_interp_alias(thr, al, [b[0] for b in br], [OI.alpha_fixed32(b[1]) for b in br],
+                               SEED, 5, inject, 77, 20_000, max_steps=max_steps)
+    got = tal.cpu().numpy()
+    assert (got == ref).all()
+    if max_steps < 10:
+        assert got[:, 2].sum() > 0
+
+
+@pytest.mark.parametrize("inject", [0, 1])
+def test_interpolated_current_matches_oracle_and_exact_mixture(inject):
+    nodes = [-1.0, -0.6, -0.2, 0.3, 0.8]
+    W, L, eta = 2, 5, 0.2
+    k, V, g = build_at(W, L, eta, nodes)
+    nF = len(FINE)
+    fine = torch.tensor(FINE, dtype=torch.float64, device=DEV)
+    wq = np.linspace(0.1, 0.3, nF)
+    tw = torch.tensor(wq, device=DEV)
+    tal = torch.zeros((nF, M.TALLY_N), dtype=torch.int64, device=DEV)
+    M.mc_negf_walk_interp(k, fine, SEED + 1, 0, inject, 0, 300_000, 1_000_000, tal)
+    T = torch.empty(nF, dtype=torch.float64, device=DEV)
+    sg = torch.empty_like(T)
+    st, I, sI = M.mc_negf_current_interp(k, fine, inject, tal, tw, T, sg)
+    assert st == M.OK
+    t = tal.cpu().numpy()
+    lead = k.lead().cpu().numpy()[:, M.LEAD_CL if inject == 0 else M.LEAD_CR]
+    br = [OI.bracket(nodes, E) for E in FINE]
+    alpha = [OI.alpha_fixed32(b[1]) / 2.0 ** 32 for b in br]
+    c = [(1 - a) * lead[lo] + a * lead[min(lo + 1, len(nodes) - 1)] for (lo, _), a in zip(br, alpha)]
+    To, so, Io, sIo = OW.mc_current(t, c, wq, inject)
+    assert np.allclose(T.cpu().numpy(), To, rtol=1e-12, atol=0)
+    assert np.allclose(sg.cpu().numpy(), so, rtol=1e-12, atol=0)
+    assert abs(I - Io) <= 1e-12 * abs(Io) and abs(sI - sIo) <= 1e-12 * sIo
+    # exact expectation of the interpolated walk, from the oracle's own dense kernels
+    sols = D.solve_workload(W, L, 1.0, V, g, nodes)
+    Ks = [s.transition_kernel() for s in sols]
+    T_ex = np.array([OI.interpolated_transmission(Ks[lo], Ks[min(lo + 1, len(nodes) - 1)], a,
+                                                  inject) for (lo, _), a in zip(br, alpha)])
+    I_ex = float(np.sum(wq * T_ex))
+    assert abs(I - I_ex) <= 3 * sI, (I, I_ex, sI)
+    Tm, sgm = T.cpu().numpy(), sg.cpu().numpy()
+    assert int(np.sum(np.abs(Tm - T_ex) > 3 * sgm)) <= 1
+
+
+def test_energy_outside_the_built_ones_is_reported():
+    nodes = [-0.5, 0.5]
+    k, _, _ = build_at(2, 3, 0.2, nodes)
+    fine = torch.tensor([0.0, 0.7], dtype=torch.float64, device=DEV)
+    tal = torch.zeros((2, M.TALLY_N), dtype=torch.int64, device=DEV)
+    M.mc_negf_walk_interp(k, fine, 1, 0, 0, 0, 1000, 1_000_000, tal)
+    T = torch.empty(2, dtype=torch.float64, device=DEV)
+    sg = torch.empty_like(T)
+    w = torch.ones(2, dtype=torch.float64, device=DEV)
+    with pytest.raises(M.McnegfError) as ei:
+        M.mc_negf_current_interp(k, fine, 0, tal, w, T, sg)
+    assert ei.value.code == M.EINVAL
+
+
+def test_planned_interpolation_of_a_wire_within_3_sigma_of_direct():
+    # coarse nodes every 4th energy of a 64-point grid, the intervals whose rows differ by more
+    # than 5% refined to exact energies, all 64 energies walked by interpolation; the current
+    # lies within 3 sigma of the interpolated walk's exact expectation and its bias against
+    # the exact DIRECT current is reported by the bench
+    W, L, eta = 4, 12, 0.1
+    E, wq = inputs.energy_grid(-3.0, 3.0, 64)
+    coarse = list(E[::4]) + ([E[-1]] if (len(E) - 1) % 4 else [])
+    k0, V, g = build_at(W, L, eta, coarse, flags=M.BUILD_NO_ALIAS | M.BUILD_NO_DIRECT)
+    dist = torch.empty(len(coarse) - 1, dtype=torch.float64, device=DEV)
+    M.mc_negf_interp_distances(k0, dist)
+    exact = M.mc_negf_interp_plan(coarse, dist.cpu().numpy(), E, 0.05)
+    nodes = sorted(set(coarse) | set(E[exact]))
+    k1, _, _ = build_at(W, L, eta, nodes, flags=M.BUILD_NO_DIRECT)
+    fine = torch.tensor(E, device=DEV)
+    tal = torch.zeros((len(E), M.TALLY_N), dtype=torch.int64, device=DEV)
+    M.mc_negf_walk_interp(k1, fine, SEED + 2, 0, 0, 0, 200_000, 1_000_000, tal)
+    T = torch.empty(len(E), dtype=torch.float64, device=DEV)
+    sg = torch.empty_like(T)
+    st, I, sI = M.mc_negf_current_interp(k1, fine, 0, tal, torch.tensor(wq, device=DEV), T, sg)
+    assert st == M.OK
+    sols = D.solve_workload(W, L, 1.0, V, g, nodes)
+    Ks = [s.transition_kernel() for s in sols]
+    I_ex = 0.0
+    for Ef, wf in zip(E, wq):
+        lo, a = OI.bracket(nodes, Ef)
+        a = OI.alpha_fixed32(a) / 2.0 ** 32
+        I_ex += wf * OI.interpolated_transmission(Ks[lo], Ks[min(lo + 1, len(nodes) - 1)], a)
+    assert abs(I - I_ex) <= 3 * sI, (I, I_ex, sI)

@@ -25,8 +25,11 @@ def test_single_site_closed_form_gradient():
     assert abs(dg[0] - np.dot(w, dT_dg)) < 1e-12
 
 
+@pytest.mark.parametrize("h", [1e-5, 1e-6])
 @pytest.mark.parametrize("W,L,lead_model,gamma_l", [(2, 3, 0, 0.0), (2, 3, 1, 0.7), (3, 1, 0, 0.0)])
-def test_adjoint_matches_central_differences(W, L, lead_model, gamma_l):
+def test_adjoint_matches_central_differences(W, L, lead_model, gamma_l, h):
+    # h = 1e-6 is the step the differentiation workload names; 1e-5 checks that the agreement
+    # does not hinge on one step size
     rng = np.random.default_rng(7)
     V = rng.uniform(-0.4, 0.4, W * L)
     g = rng.uniform(0.02, 0.3, W * L)
@@ -34,9 +37,8 @@ def test_adjoint_matches_central_differences(W, L, lead_model, gamma_l):
     I, dV, dg = OG.adjoint(W, L, 1.0, V, g, E, w, lead_model, 1e-10, gamma_l)
     sols = D.solve_workload(W, L, 1.0, V, g, E, lead_model, 1e-10, gamma_l)
     assert abs(I - D.current(sols, w)) < 1e-12 * abs(I)
-    fV = OG.central_differences(W, L, 1.0, V, g, E, w, 1e-5, lead_model, 1e-10, gamma_l, "V")
-    fg = OG.central_differences(W, L, 1.0, V, g, E, w, 1e-5, lead_model, 1e-10, gamma_l,
-                                "gamma")
+    fV = OG.central_differences(W, L, 1.0, V, g, E, w, h, lead_model, 1e-10, gamma_l, "V")
+    fg = OG.central_differences(W, L, 1.0, V, g, E, w, h, lead_model, 1e-10, gamma_l, "gamma")
     scale = max(np.abs(dV).max(), np.abs(dg).max())
     assert np.abs(dV - fV).max() < 1e-7 * scale
     assert np.abs(dg - fg).max() < 1e-7 * scale
