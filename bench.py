@@ -304,6 +304,7 @@ def grad_bench(torch, dev, steps, warmup, with_cpu):
     add_traffic_rate(out["roofline"])
     del k, ws, gws
     torch.cuda.empty_cache()
+    out["w32"] = grad_w32_bench(torch, dev, steps)
     if with_cpu:
         # the oracle's reverse-mode dense adjoint on one of the energies, scaled to all of them
         from oracle import grad as OG
@@ -317,6 +318,41 @@ def grad_bench(torch, dev, steps, warmup, with_cpu):
                                "cores": _t.get_num_threads(), "kind": "oracle",
                                "sample": f"1 of {wl.n_energies} energies (dense torch adjoint, "
                                          f"{dt:.1f} s), scaled to all energies"}
+    return out
+
+
+def grad_w32_bench(torch, dev, steps, chunk=16):
+    """The gradient at the paper's 32 x 32 blocks: W = 32, L = 130 (N = 4160), the
+    differentiation workload's disorder, dephasing and 128 energies, differentiated in chunks
+    of `chunk` energies (each chunk's G regenerated from the stored RGF blocks)."""
+    wl = inputs.DIFF_W16_L200.replace(W=32, L=130)
+    sysm = M.make_system(wl.W, wl.L, wl.t, wl.lead_model, wl.gamma_l, wl.delta_lead,
+                         M.BUILD_NO_ALIAS)
+    E, w = inputs.energy_grid(wl.emin, wl.emax, wl.n_energies)
+    V = torch.tensor(inputs.onsite(wl), device=dev)
+    g = torch.tensor(inputs.dephasing(wl), device=dev)
+    tE, tw = torch.tensor(E, device=dev), torch.tensor(w, device=dev)
+    ws = M.allocate_workspace(sysm, wl.n_energies, dev)
+    k = M.mc_negf_build_kernel(sysm, V, g, tE, ws)
+    nb = M.mc_negf_grad_workspace_bytes_chunk(k, chunk)
+    gws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    dV = torch.empty(wl.N, dtype=torch.float64, device=dev)
+    dg = torch.empty_like(dV)
+    M.mc_negf_grad(k, 0, tw, gws, dV, dg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, min(steps, 3))):
+        st, I = M.mc_negf_grad(k, 0, tw, gws, dV, dg)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / max(1, min(steps, 3))
+    out = {"workload": f"W=32 L=130 N={wl.N}, eta={wl.eta}t, disorder U[-{wl.disorder},"
+                       f"{wl.disorder}]t, {wl.n_energies} energies in [{wl.emin},{wl.emax}]t",
+           "ms_per_grad": 1e3 * wall, "I": I, "status": st, "chunk_energies": chunk,
+           "workspace_gb": nb / 1e9,
+           "workspace_gb_all_energies_at_once": M.mc_negf_grad_workspace_bytes(k) / 1e9,
+           "build_workspace_gb": ws.numel() / 1e9}
+    del k, ws, gws
+    torch.cuda.empty_cache()
     return out
 
 
@@ -711,6 +747,38 @@ def scale_bench(torch, dev, warmup, with_cpu, seed):
         "status_flags": int(flags32),
     }
     T_gpu32 = float(T32[j])
+    # batch 0 with FP32 block products and one FP64 refinement step (a larger workspace)
+    del ws
+    holder.clear()
+    torch.cuda.empty_cache()
+    sysr = M.make_system(wl.W, wl.L, wl.t, wl.lead_model, wl.gamma_l, wl.delta_lead,
+                         M.BUILD_FP32_PRODUCTS | M.BUILD_FP32_REFINE)
+    ws = M.allocate_workspace(sysr, nE, dev)
+    one_batch(0, sysr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with M.LaunchTimes() as ltr:
+        one_batch(0, sysr)
+    torch.cuda.synchronize()
+    wallr = time.perf_counter() - t0
+    require_complete(ltr)
+    orr = out.cpu().numpy()
+    Tr = Td[0].cpu().numpy()
+    flagsr = M.mc_negf_status(holder["k"])
+    res["fp32_refined"] = {
+        "what": "batch 0 with FP32 block products, then one FP64 refinement step on G (FP64 "
+                "residual from the stencil, FP32 correction solve with the RGF blocks)",
+        "ms_per_batch": 1e3 * wallr,
+        "fullinv_fp32_store_ms": ltr.total_ms("fullinv_store_g_kernel"),
+        "refine_ms": ltr.total_ms("refine_kernel"),
+        "fullinv_ms_fp64": fi_ms,
+        "max_rel_err_T_direct_vs_fp64": float(np.max(np.abs(Tr - T64) / np.abs(T64))),
+        "rel_err_I_direct_vs_fp64": abs(float(orr[0, 1, 0]) - I64) / abs(I64),
+        "mc_minus_fp64_direct_in_sigma": (float(orr[0, 0, 0]) - I64) / float(orr[0, 0, 1]),
+        "status_flags": int(flagsr),
+        "workspace_gb": ws.numel() / 1e9,
+    }
+    T_gpur = float(Tr[j])
     del holder, ws
     torch.cuda.empty_cache()
     if with_cpu:
@@ -733,7 +801,8 @@ def scale_bench(torch, dev, warmup, with_cpu, seed):
             "oracle_direct_s_projected_all_energies": dt * wl.n_energies,
             "T_oracle": T_ref, "T_gpu_direct": T_gpu,
             "rel_err_direct": abs(T_gpu - T_ref) / abs(T_ref),
-            "rel_err_direct_fp32_products": abs(T_gpu32 - T_ref) / abs(T_ref)}
+            "rel_err_direct_fp32_products": abs(T_gpu32 - T_ref) / abs(T_ref),
+            "rel_err_direct_fp32_refined": abs(T_gpur - T_ref) / abs(T_ref)}
     return res
 
 

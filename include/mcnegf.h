@@ -36,8 +36,7 @@
  *   - Kernels record numerical trouble in a device status word inside the workspace; it is
  *     read by mc_negf_current / mc_negf_status.
  *   - Sizes: 1 <= W <= 32, 1 <= L, N = W*L, N + 2 <= 16320 (the alias build keeps 10 bytes
- *     per outcome of a row in one workgroup's LDS), 1 <= nE; mc_negf_grad needs W <= 16 and
- *     N <= 4096.
+ *     per outcome of a row in one workgroup's LDS), 1 <= nE.
  */
 #ifndef MCNEGF_H
 #define MCNEGF_H
@@ -121,8 +120,16 @@ typedef struct mcnegf_system {
  * Only W = 16 and W = 32 (mc_negf_build_kernel returns MCNEGF_EINVAL for other widths);
  * |G_ij|^2 then carries FP32 rounding (relative error of order 1e-6 after hundreds of
  * slices), and so do the currents, and the probe solve inside mc_negf_grad on such a build
- * (its complex G is recomputed in FP64).  No refinement step is applied. */
+ * (its complex G is recomputed in FP64); MCNEGF_BUILD_FP32_REFINE adds one refinement step. */
 #define MCNEGF_BUILD_FP32_PRODUCTS 0x4u
+/* MCNEGF_BUILD_FP32_REFINE (with MCNEGF_BUILD_FP32_PRODUCTS only): the FP32 sweeps store every
+ * block of G0, and one step of iterative refinement of (E - H - Sigma) G = I (Sec. II A,
+ * Eq. (7)) corrects it before |G|^2, the exit weights and the corners are formed: the residual
+ * I - A G0 in FP64 (5-point stencil and lead blocks), the correction solved in FP32 with the
+ * block LU of the left-connected RGF blocks, G1 = G0 + correction in FP64.  |G_ij|^2 and the
+ * currents then agree with an FP64 build to about 1e-12 relative.  The workspace grows by
+ * 24 bytes per entry of G for 4 energies at a time (refined 4 energies per pass). */
+#define MCNEGF_BUILD_FP32_REFINE 0x8u
 
 /*
  * Handle filled by mc_negf_build_kernel: shapes plus device pointers into the caller's
@@ -240,10 +247,14 @@ int32_t mc_negf_current(const mcnegf_kernel* k, int32_t mode, uint32_t inject_le
 
 /*
  * Bytes of device workspace mc_negf_grad needs for the built kernel `k` (host only): the
- * complex G [nE][N][p_pitch], the adjoint solves [nE][N][roundup(N + W, 16)] and O(nE N)
- * vectors.  MCNEGF_EINVAL for a bad handle.
+ * complex G [chunk][N][p_pitch], the adjoint solves [chunk][N][roundup(N + W, 16)] and
+ * O(chunk N) vectors for `chunk` energies at a time, plus O(nE N) per-energy derivatives.
+ * mc_negf_grad_workspace_bytes gives the size for all energies at once (chunk = nE),
+ * mc_negf_grad_workspace_bytes_chunk for 1 <= chunk <= nE.  MCNEGF_EINVAL for a bad handle.
  */
 int32_t mc_negf_grad_workspace_bytes(const mcnegf_kernel* k, uint64_t* bytes_out);
+int32_t mc_negf_grad_workspace_bytes_chunk(const mcnegf_kernel* k, int32_t chunk,
+                                           uint64_t* bytes_out);
 
 /*
  * Gradient of the DIRECT current I = sum_k w_k T_eff(E_k) (Sec. III C, Eq. (79) read as the
@@ -254,11 +265,13 @@ int32_t mc_negf_grad_workspace_bytes(const mcnegf_kernel* k, uint64_t* bytes_out
  *   k            handle from mc_negf_build_kernel (reads its tables; reruns the DIRECT solve).
  *   inject_lead  0: T_RL (f_L = 1), 1: T_LR.
  *   d_weights    [nE] device, quadrature weights w_k.
- *   d_gws        device workspace of >= mc_negf_grad_workspace_bytes, caller-owned.
+ *   d_gws        device workspace, caller-owned: with mc_negf_grad_workspace_bytes bytes all
+ *                energies are differentiated at once; a smaller one (at least the one-energy
+ *                size of mc_negf_grad_workspace_bytes_chunk) takes the energies in the largest
+ *                chunks it holds, regenerating each chunk's G from the stored RGF blocks.
  *   d_dI_dV      [N] device output dI/dV_i;  d_dI_dgamma [N] device output dI/dgamma_i.
  *   h_I          host output, the DIRECT current I.
- * Needs W <= 16, N <= 4096 and a kernel built with the DIRECT workspace (else
- * MCNEGF_EINVAL).
+ * Needs a kernel built with the DIRECT workspace (else MCNEGF_EINVAL); any W <= 32 and N.
  * Synchronises `stream`; status as mc_negf_current in DIRECT mode.  MCNEGF_EWS if the
  * workspace is too small; MCNEGF_EHIP if a launch fails.
  */

@@ -9,11 +9,11 @@
 namespace mcnegf {
 
 constexpr int kMaxW = 32;
-constexpr int kMaxGradW = 16;  // the gradient kernels keep W-vectors in registers
+constexpr int kMaxGradW = 32;  // the gradient kernels keep W-vectors in registers
 // Outcomes per row (N + 2): the alias build holds 10 bytes per outcome of its row in LDS
 // (160 KB per CU), and a packed alias entry has a 16-bit outcome index.
 constexpr int kMaxOut = 16320;
-constexpr int kMaxGradOut = 4096;  // the back substitution keeps a row in registers
+constexpr int kMaxGradOut = 16384;  // the back substitution keeps a row in registers
 // Packed alias entry: the high 16 bits of the 32-bit threshold over the 16-bit alias; the
 // low 16 threshold bits sit in a separate u16 array.
 constexpr uint32_t kAliasIdxBits = 16;
@@ -84,29 +84,57 @@ __device__ inline void interp_bracket(const double* nodes, uint32_t nE, double E
     lo = l;
 }
 
+// The handle restricted to energies [e0, e0 + n): every per-energy array starts at energy e0
+// (the status word, counters and reduction scratch are shared).
+inline mcnegf_kernel energy_slice(const mcnegf_kernel& k, int e0, int n) {
+    mcnegf_kernel c = k;
+    const size_t N = k.N, WW = (size_t)k.W * k.W, e = (size_t)e0;
+    c.nE = n;
+    c.energies = k.energies + e;
+    if (k.alias) c.alias = k.alias + e * k.n_out * k.alias_pitch;
+    if (k.alias_lo) c.alias_lo = k.alias_lo + e * k.n_out * k.alias_pitch;
+    c.P = k.P + e * N * k.p_pitch;
+    c.wL = k.wL + e * N;
+    c.wR = k.wR + e * N;
+    c.Adiag = k.Adiag + e * N;
+    c.lead = k.lead + e * MCNEGF_LEAD_NTERMS;
+    c.sigma = k.sigma + e * 2 * WW;
+    c.gam_lead = k.gam_lead + e * WW;
+    c.gL = k.gL + e * 2 * k.L * WW;
+    c.gR = k.gR + e * 2 * k.L * WW;
+    c.Gd = k.Gd + e * 2 * k.L * WW;
+    c.corner = k.corner + e * 4 * WW;
+    if (k.direct) c.direct = k.direct + e * (k.p_pitch + 2) * k.p_pitch;
+    if (k.direct_vec) c.direct_vec = k.direct_vec + e * 4 * N;
+    return c;
+}
+
 // ---- workspace layout ------------------------------------------------------------------
 struct Layout {
     int64_t alias_pitch, p_pitch;
     uint64_t off_status, off_counters, off_reduce, off_lead, off_sigma, off_gam, off_gL, off_gR,
         off_Gd, off_corner, off_wL, off_wR, off_Adiag, off_P, off_alias, off_alias_lo, off_direct,
-        off_direct_vec, total;
+        off_direct_vec, off_refine, total;
+    int refine_chunk;  // energies refined at a time (FP32 products with one refinement step)
 };
-Layout make_layout(int W, int L, int nE, bool with_alias, bool with_direct);
+Layout make_layout(int W, int L, int nE, bool with_alias, bool with_direct, bool refine = false);
+constexpr int kRefineChunk = 4;  // energies refined at a time
 
 // gradient workspace (caller-owned, separate from the build workspace)
 struct GradBuffers {
-    double2* G;       // [nE][N][ld] complex G, row-major
-    double2* Y;       // [nE][N][ldY] adjoint solves, column c: Q (c < N) or R (c = N + b)
-    double2* part_k;  // [nE][2][N] dense and diagonal parts of K per site
-    double* part_p;   // [nE][2][N] (P v)_i, (P u)_i
-    double* xl;       // [nE][2][ld] x, lambda
+    double2* G;       // [chunk][N][ld] complex G, row-major
+    double2* Y;       // [chunk][N][ldY] adjoint solves, column c: Q (c < N) or R (c = N + b)
+    double2* part_k;  // [chunk][2][N] dense and diagonal parts of K per site
+    double* part_p;   // [chunk][2][N] (P v)_i, (P u)_i
+    double* xl;       // [chunk][2][ld] x, lambda
     double* gV;       // [nE][N] dT/dV per energy
     double* gG;       // [nE][N] dT/dgamma per energy
     double* T;        // [nE] DIRECT transmissions (scratch)
     double* sig;      // [nE] (zero)
     int64_t ld, ldY;
 };
-uint64_t grad_layout(const mcnegf_kernel& k, void* base, GradBuffers* out);
+// Workspace of mc_negf_grad with the G-sized buffers for `chunk` energies at a time.
+uint64_t grad_layout(const mcnegf_kernel& k, int chunk, void* base, GradBuffers* out);
 
 // ---- opt-in launch timing: events around every launch while a profile is attached ------
 struct LaunchTimer {
@@ -173,6 +201,13 @@ hipError_t launch_walk_sampled(const mcnegf_kernel& k, const SampledScratch& sc,
 hipError_t launch_sampled_current(const mcnegf_kernel& k, uint32_t inject_lead,
                                   const int64_t* tallies, const double* weights, double* T,
                                   double* sigmaT, hipStream_t s);
+// The full inverse with FP32 block products, writing the complex G (row-major, pitch ldG).
+hipError_t launch_fullinv_fp32_store_g(const mcnegf_kernel& k, double2* Gc, int64_t ldG,
+                                       hipStream_t s);
+// One FP64 refinement step on the stored G0 (Y: FP32 scratch of the same shape), writing
+// |G|^2, the exit weights and the corners of k.
+hipError_t launch_refine(const mcnegf_kernel& k, const double* onsite, const double2* G0,
+                         float2* Y, int64_t ld, hipStream_t s);
 hipError_t launch_walk_interp(const mcnegf_kernel& k, const double* fine, uint32_t nF,
                               uint64_t seed, uint32_t tag, uint32_t walker_begin,
                               uint32_t n_walkers, uint32_t max_steps, int64_t* tallies,
@@ -183,6 +218,7 @@ hipError_t launch_interp_current(const mcnegf_kernel& k, const double* fine, uin
                                  hipStream_t s);
 hipError_t launch_interp_distances(const mcnegf_kernel& k, double* dist, hipStream_t s);
 hipError_t launch_grad(const mcnegf_kernel& k, const GradBuffers& gb, uint32_t inject_lead,
-                       const double* weights, double* dI_dV, double* dI_dgamma, hipStream_t s);
+                       const double* weights, double* dI_dV, double* dI_dgamma, int chunk,
+                       hipStream_t s);
 
 }  // namespace mcnegf

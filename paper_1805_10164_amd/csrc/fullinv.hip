@@ -499,6 +499,13 @@ hipError_t launch_fullinv_fp32(const mcnegf_kernel& k, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_fullinv_fp32_store_g(const mcnegf_kernel& k, double2* Gc, int64_t ldG,
+                                       hipStream_t s) {
+    if (k.W == 16) return launch_fullinv_mfma<16, 4, kFullinvWaves16, true, float>(k, Gc, ldG, s);
+    if (k.W == 32) return launch_fullinv_mfma<32, 2, kFullinvWaves32, true, float>(k, Gc, ldG, s);
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_fullinv_store_g(const mcnegf_kernel& k, double2* Gc, int64_t ldG,
                                   hipStream_t s) {
     return launch_fullinv_any<true>(k, Gc, ldG, s);

@@ -46,8 +46,9 @@ __device__ inline double readlane_dbl(double v, int lane) {
 // Thread tid owns the stored positions p = tid + 1024 q of r (in registers), so the update
 // reads the rows of block I coalesced with 64 independent loads per position.
 constexpr int BSV_THREADS = 1024;
-constexpr int BSV_Q = kMaxGradOut / BSV_THREADS;  // positions per thread (Np <= kMaxGradOut)
 
+// BSV_Q: positions per thread (Np <= BSV_THREADS * BSV_Q)
+template <int BSV_Q>
 __global__ void __launch_bounds__(BSV_THREADS) backsolve_kernel(const double* __restrict__ Lall,
                                                                 const double* __restrict__ vec,
                                                                 int N, int Np, int64_t ld,
@@ -380,32 +381,57 @@ static hipError_t launch_adjoint_w(const mcnegf_kernel& k, const GradBuffers& gb
     return hipGetLastError();
 }
 
-hipError_t launch_grad(const mcnegf_kernel& k, const GradBuffers& gb, uint32_t inject_lead,
-                       const double* weights, double* dI_dV, double* dI_dgamma, hipStream_t s) {
+static hipError_t launch_backsolve(const mcnegf_kernel& k, double* xl, hipStream_t s) {
     const int N = k.N, nE = k.nE;
     const int Np = (int)k.p_pitch;
-    hipError_t err;
     {
         MCNEGF_TIMED("backsolve_kernel", s);
-        hipLaunchKernelGGL(backsolve_kernel, dim3(nE), dim3(BSV_THREADS), 0, s, k.direct,
-                           k.direct_vec,
-                           N, Np, k.p_pitch, gb.xl);
+        if (Np <= BSV_THREADS * 4)
+            hipLaunchKernelGGL(backsolve_kernel<4>, dim3(nE), dim3(BSV_THREADS), 0, s, k.direct,
+                               k.direct_vec, N, Np, k.p_pitch, xl);
+        else if (Np <= BSV_THREADS * 8)
+            hipLaunchKernelGGL(backsolve_kernel<8>, dim3(nE), dim3(BSV_THREADS), 0, s, k.direct,
+                               k.direct_vec, N, Np, k.p_pitch, xl);
+        else
+            hipLaunchKernelGGL(backsolve_kernel<16>, dim3(nE), dim3(BSV_THREADS), 0, s, k.direct,
+                               k.direct_vec, N, Np, k.p_pitch, xl);
     }
-    if ((err = hipGetLastError()) != hipSuccess) return err;
-    if ((err = launch_fullinv_store_g(k, gb.G, gb.ld, s)) != hipSuccess) return err;
-    switch (k.W) {
-#define MCNEGF_CASE(w)                                                        \
-    case w:                                                                   \
-        if ((err = launch_adjoint_w<w>(k, gb, inject_lead, s)) != hipSuccess) \
-            return err;                                                       \
+    return hipGetLastError();
+}
+
+// Energies are processed in chunks of `chunk`: the complex G, the adjoint solves and the
+// per-site partials of one chunk live in the workspace at a time (the stored RGF blocks of
+// every energy regenerate each chunk's G); gV, gG hold every energy for the final sum.
+hipError_t launch_grad(const mcnegf_kernel& k, const GradBuffers& gb, uint32_t inject_lead,
+                       const double* weights, double* dI_dV, double* dI_dgamma, int chunk,
+                       hipStream_t s) {
+    const int N = k.N, nE = k.nE;
+    hipError_t err;
+    for (int e0 = 0; e0 < nE; e0 += chunk) {
+        const int nc = min(chunk, nE - e0);
+        const mcnegf_kernel kc = energy_slice(k, e0, nc);
+        GradBuffers g = gb;
+        g.gV = gb.gV + (size_t)e0 * N;
+        g.gG = gb.gG + (size_t)e0 * N;
+        if ((err = launch_backsolve(kc, g.xl, s)) != hipSuccess) return err;
+        if ((err = launch_fullinv_store_g(kc, g.G, g.ld, s)) != hipSuccess) return err;
+        switch (k.W) {
+#define MCNEGF_CASE(w)                                                         \
+    case w:                                                                    \
+        if ((err = launch_adjoint_w<w>(kc, g, inject_lead, s)) != hipSuccess) \
+            return err;                                                        \
         break;
-        MCNEGF_CASE(1) MCNEGF_CASE(2) MCNEGF_CASE(3) MCNEGF_CASE(4) MCNEGF_CASE(5)
-        MCNEGF_CASE(6) MCNEGF_CASE(7) MCNEGF_CASE(8) MCNEGF_CASE(9) MCNEGF_CASE(10)
-        MCNEGF_CASE(11) MCNEGF_CASE(12) MCNEGF_CASE(13) MCNEGF_CASE(14) MCNEGF_CASE(15)
-        MCNEGF_CASE(16)
+            MCNEGF_CASE(1) MCNEGF_CASE(2) MCNEGF_CASE(3) MCNEGF_CASE(4) MCNEGF_CASE(5)
+            MCNEGF_CASE(6) MCNEGF_CASE(7) MCNEGF_CASE(8) MCNEGF_CASE(9) MCNEGF_CASE(10)
+            MCNEGF_CASE(11) MCNEGF_CASE(12) MCNEGF_CASE(13) MCNEGF_CASE(14) MCNEGF_CASE(15)
+            MCNEGF_CASE(16) MCNEGF_CASE(17) MCNEGF_CASE(18) MCNEGF_CASE(19) MCNEGF_CASE(20)
+            MCNEGF_CASE(21) MCNEGF_CASE(22) MCNEGF_CASE(23) MCNEGF_CASE(24) MCNEGF_CASE(25)
+            MCNEGF_CASE(26) MCNEGF_CASE(27) MCNEGF_CASE(28) MCNEGF_CASE(29) MCNEGF_CASE(30)
+            MCNEGF_CASE(31) MCNEGF_CASE(32)
 #undef MCNEGF_CASE
-        default:
-            return hipErrorInvalidValue;
+            default:
+                return hipErrorInvalidValue;
+        }
     }
     {
         MCNEGF_TIMED("grad_reduce_kernel", s);

@@ -35,7 +35,7 @@ static int32_t hip_fail(hipError_t e) {
 
 static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
-Layout make_layout(int W, int L, int nE, bool with_alias, bool with_direct) {
+Layout make_layout(int W, int L, int nE, bool with_alias, bool with_direct, bool refine) {
     Layout o;
     const int64_t N = (int64_t)W * L;
     const int64_t n = N + 2;
@@ -65,6 +65,9 @@ Layout make_layout(int W, int L, int nE, bool with_alias, bool with_direct) {
     o.off_alias = take(with_alias ? (uint64_t)nE * n * o.alias_pitch * 4 : 0);
     o.off_alias_lo = take(with_alias ? (uint64_t)nE * n * o.alias_pitch * 2 : 0);
     o.off_direct = take(with_direct ? (uint64_t)nE * (o.p_pitch + 2) * o.p_pitch * 8 : 0);
+    // refinement scratch: G0 (complex FP64) and the FP32 forward solves, for a chunk of energies
+    o.refine_chunk = refine ? (nE < kRefineChunk ? nE : kRefineChunk) : 0;
+    o.off_refine = take((uint64_t)o.refine_chunk * N * o.p_pitch * 24);
     o.total = off;
     return o;
 }
@@ -81,16 +84,20 @@ static bool valid_system(const mcnegf_system* s) {
     } else {
         return false;
     }
-    if (s->flags & ~(MCNEGF_BUILD_NO_ALIAS | MCNEGF_BUILD_NO_DIRECT | MCNEGF_BUILD_FP32_PRODUCTS))
+    if (s->flags & ~(MCNEGF_BUILD_NO_ALIAS | MCNEGF_BUILD_NO_DIRECT | MCNEGF_BUILD_FP32_PRODUCTS |
+                     MCNEGF_BUILD_FP32_REFINE))
         return false;
     if ((s->flags & MCNEGF_BUILD_FP32_PRODUCTS) && s->W != 16 && s->W != 32) return false;
+    if ((s->flags & MCNEGF_BUILD_FP32_REFINE) && !(s->flags & MCNEGF_BUILD_FP32_PRODUCTS))
+        return false;
     return true;
 }
 
 static bool with_alias(const mcnegf_system* s) { return !(s->flags & MCNEGF_BUILD_NO_ALIAS); }
 static bool with_direct(const mcnegf_system* s) { return !(s->flags & MCNEGF_BUILD_NO_DIRECT); }
+static bool with_refine(const mcnegf_system* s) { return (s->flags & MCNEGF_BUILD_FP32_REFINE) != 0; }
 static Layout layout_of(const mcnegf_system* s, int nE) {
-    return make_layout(s->W, s->L, nE, with_alias(s), with_direct(s));
+    return make_layout(s->W, s->L, nE, with_alias(s), with_direct(s), with_refine(s));
 }
 
 static bool valid_kernel(const mcnegf_kernel* k) {
@@ -107,19 +114,20 @@ static int32_t status_to_code(uint32_t flags, bool mc) {
     return MCNEGF_OK;
 }
 
-uint64_t grad_layout(const mcnegf_kernel& k, void* base, GradBuffers* out) {
+uint64_t grad_layout(const mcnegf_kernel& k, int chunk, void* base, GradBuffers* out) {
     const int64_t N = k.N, nE = k.nE, ld = k.p_pitch, ldY = round_up(N + k.W, 16);
+    const int64_t nc = chunk;
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) {
         const uint64_t at = off;
         off = align256(off + bytes);
         return at;
     };
-    const uint64_t oG = take((uint64_t)nE * N * ld * 16);
-    const uint64_t oY = take((uint64_t)nE * N * ldY * 16);
-    const uint64_t oK = take((uint64_t)nE * 2 * N * 16);
-    const uint64_t oP = take((uint64_t)nE * 2 * N * 8);
-    const uint64_t oX = take((uint64_t)nE * 2 * ld * 8);
+    const uint64_t oG = take((uint64_t)nc * N * ld * 16);
+    const uint64_t oY = take((uint64_t)nc * N * ldY * 16);
+    const uint64_t oK = take((uint64_t)nc * 2 * N * 16);
+    const uint64_t oP = take((uint64_t)nc * 2 * N * 8);
+    const uint64_t oX = take((uint64_t)nc * 2 * ld * 8);
     const uint64_t oV = take((uint64_t)nE * N * 8);
     const uint64_t oGg = take((uint64_t)nE * N * 8);
     const uint64_t oT = take((uint64_t)nE * 8);
@@ -211,14 +219,28 @@ int32_t mc_negf_build_kernel(const mcnegf_system* sys, const double* d_onsite,
     if ((err = launch_lead_sigma(k, sys->gamma_l, sys->delta_lead, stream)) != hipSuccess)
         return hip_fail(err);
     if ((err = launch_rgf(k, d_onsite, stream)) != hipSuccess) return hip_fail(err);
-    if ((err = (sys->flags & MCNEGF_BUILD_FP32_PRODUCTS) ? launch_fullinv_fp32(k, stream)
-                                                            : launch_fullinv(k, stream)) !=
-        hipSuccess)
+    if (with_refine(sys)) {
+        // FP32 block products, then one FP64 refinement step, a chunk of energies at a time
+        double2* G0 = reinterpret_cast<double2*>(base + lay.off_refine);
+        float2* Y = reinterpret_cast<float2*>(base + lay.off_refine +
+                                              (uint64_t)lay.refine_chunk * k.N * k.p_pitch * 16);
+        for (int e0 = 0; e0 < nE; e0 += lay.refine_chunk) {
+            const mcnegf_kernel kc = energy_slice(k, e0, std::min(lay.refine_chunk, nE - e0));
+            if ((err = launch_fullinv_fp32_store_g(kc, G0, k.p_pitch, stream)) != hipSuccess)
+                return hip_fail(err);
+            if ((err = launch_refine(kc, d_onsite, G0, Y, k.p_pitch, stream)) != hipSuccess)
+                return hip_fail(err);
+        }
+    } else if ((err = (sys->flags & MCNEGF_BUILD_FP32_PRODUCTS) ? launch_fullinv_fp32(k, stream)
+                                                                   : launch_fullinv(k, stream)) !=
+               hipSuccess) {
         return hip_fail(err);
+    }
     if ((err = launch_lead_terms(k, stream)) != hipSuccess) return hip_fail(err);
-    // row totals against A_jj and Tr Gamma_p A: FP64 products agree to rounding, FP32 block
-    // products to their own rounding accumulated over the slices
-    const double rowsum_tol = (sys->flags & MCNEGF_BUILD_FP32_PRODUCTS) ? 1e-4 : 1e-8;
+    // row totals against A_jj and Tr Gamma_p A: FP64 products (and refined FP32 products)
+    // agree to rounding, FP32 block products to their own rounding accumulated over the slices
+    const double rowsum_tol =
+        (sys->flags & MCNEGF_BUILD_FP32_PRODUCTS) && !with_refine(sys) ? 1e-4 : 1e-8;
     if (with_alias(sys) && (err = launch_alias_build(k, rowsum_tol, stream)) != hipSuccess)
         return hip_fail(err);
     *out = k;
@@ -278,7 +300,14 @@ int32_t mc_negf_current(const mcnegf_kernel* k, int32_t mode, uint32_t inject_le
 
 int32_t mc_negf_grad_workspace_bytes(const mcnegf_kernel* k, uint64_t* bytes_out) {
     if (!valid_kernel(k) || !bytes_out) return MCNEGF_EINVAL;
-    *bytes_out = grad_layout(*k, nullptr, nullptr);
+    *bytes_out = grad_layout(*k, k->nE, nullptr, nullptr);
+    return MCNEGF_OK;
+}
+
+int32_t mc_negf_grad_workspace_bytes_chunk(const mcnegf_kernel* k, int32_t chunk,
+                                           uint64_t* bytes_out) {
+    if (!valid_kernel(k) || !bytes_out || chunk < 1 || chunk > k->nE) return MCNEGF_EINVAL;
+    *bytes_out = grad_layout(*k, chunk, nullptr, nullptr);
     return MCNEGF_OK;
 }
 
@@ -289,11 +318,19 @@ int32_t mc_negf_grad(const mcnegf_kernel* k, uint32_t inject_lead, const double*
         inject_lead > 1 || !k->direct || !k->direct_vec || k->W > kMaxGradW ||
         k->p_pitch > kMaxGradOut)
         return MCNEGF_EINVAL;
+    // the largest chunk of energies whose G-sized buffers fit the workspace
+    if (grad_layout(*k, 1, nullptr, nullptr) > gws_bytes) return MCNEGF_EWS;
+    int lo = 1, hi = k->nE;
+    while (lo < hi) {
+        const int mid = lo + (hi - lo + 1) / 2;
+        if (grad_layout(*k, mid, nullptr, nullptr) <= gws_bytes) lo = mid; else hi = mid - 1;
+    }
+    const int chunk = lo;
     GradBuffers gb;
-    if (grad_layout(*k, d_gws, &gb) > gws_bytes) return MCNEGF_EWS;
+    grad_layout(*k, chunk, d_gws, &gb);
     hipError_t err = launch_direct_current(*k, inject_lead, d_weights, gb.T, gb.sig, stream);
     if (err != hipSuccess) return hip_fail(err);
-    if ((err = launch_grad(*k, gb, inject_lead, d_weights, d_dI_dV, d_dI_dgamma, stream)) !=
+    if ((err = launch_grad(*k, gb, inject_lead, d_weights, d_dI_dV, d_dI_dgamma, chunk, stream)) !=
         hipSuccess)
         return hip_fail(err);
     double host[2];

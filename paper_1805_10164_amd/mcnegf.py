@@ -26,7 +26,8 @@ LEAD_TLL, LEAD_TRL, LEAD_TLR, LEAD_TRR, LEAD_CL, LEAD_CR, LEAD_TRGLA, LEAD_TRGRA
 TALLY_N = 5
 TALLY_EXIT_L, TALLY_EXIT_R, TALLY_TRUNC, TALLY_STEPS, TALLY_STEPS2 = range(5)
 EXPORTED = ("mc_negf_workspace_bytes", "mc_negf_build_kernel", "mc_negf_walk",
-            "mc_negf_current", "mc_negf_grad_workspace_bytes", "mc_negf_grad",
+            "mc_negf_current", "mc_negf_grad_workspace_bytes",
+            "mc_negf_grad_workspace_bytes_chunk", "mc_negf_grad",
             "mc_negf_current_async", "mc_negf_walk_sampled_bytes", "mc_negf_walk_sampled",
             "mc_negf_walk_sampled_noalloc", "mc_negf_interp_distances", "mc_negf_interp_plan",
             "mc_negf_walk_interp", "mc_negf_current_interp",
@@ -104,6 +105,8 @@ def lib() -> ctypes.CDLL:
     L.mc_negf_walk.argtypes = [ctypes.POINTER(KernelStruct), u64, u32, u32, u64, u64, u32, vp, vp]
     L.mc_negf_current.argtypes = [ctypes.POINTER(KernelStruct), i32, u32, vp, vp, vp, vp, dp, vp]
     L.mc_negf_grad_workspace_bytes.argtypes = [ctypes.POINTER(KernelStruct), ctypes.POINTER(u64)]
+    L.mc_negf_grad_workspace_bytes_chunk.argtypes = [ctypes.POINTER(KernelStruct), i32,
+                                                     ctypes.POINTER(u64)]
     L.mc_negf_grad.argtypes = [ctypes.POINTER(KernelStruct), u32, vp, vp, u64, vp, vp, dp, vp]
     L.mc_negf_status.argtypes = [ctypes.POINTER(KernelStruct), ctypes.POINTER(u32), vp]
     L.mc_negf_current_async.argtypes = [ctypes.POINTER(KernelStruct), i32, u32, vp, vp, vp, vp,
@@ -167,6 +170,7 @@ def _ptr(t) -> ctypes.c_void_p:
 BUILD_NO_ALIAS = 0x1
 BUILD_NO_DIRECT = 0x2
 BUILD_FP32_PRODUCTS = 0x4
+BUILD_FP32_REFINE = 0x8
 
 
 def make_system(W: int, L: int, t: float = 1.0, lead_model: int = 0, gamma_l: float = 0.0,
@@ -314,6 +318,14 @@ def mc_negf_grad_workspace_bytes(k: Kernel) -> int:
     out = ctypes.c_uint64(0)
     _check("mc_negf_grad_workspace_bytes",
            lib().mc_negf_grad_workspace_bytes(ctypes.byref(k.struct), ctypes.byref(out)))
+    return int(out.value)
+
+
+def mc_negf_grad_workspace_bytes_chunk(k: Kernel, chunk: int) -> int:
+    out = ctypes.c_uint64(0)
+    _check("mc_negf_grad_workspace_bytes_chunk",
+           lib().mc_negf_grad_workspace_bytes_chunk(ctypes.byref(k.struct), int(chunk),
+                                                    ctypes.byref(out)))
     return int(out.value)
 
 

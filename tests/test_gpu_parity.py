@@ -378,15 +378,72 @@ def test_no_alias_build_serves_direct_and_grad():
     assert ei.value.code == M.EINVAL
 
 
-def test_grad_rejects_wide_blocks():
-    c = case(W=20, L=2, eta=0.1, disorder=0.0, nE=1, emin=0.0, emax=0.1)
+WIDE_GRAD_CASES = {
+    "w20l2": dict(W=20, L=2, eta=0.1, disorder=0.2, nE=2, emin=-1.0, emax=1.0),
+    "w24l3_wideband": dict(W=24, L=3, eta=0.05, disorder=0.3, nE=2, emin=-2.0, emax=2.5,
+                           lead_model=1, gamma_l=0.6),
+    "w32l3": dict(W=32, L=3, eta=0.02, disorder=0.3, nE=3, emin=-3.0, emax=3.0),
+}
+
+
+@pytest.mark.parametrize("name", sorted(WIDE_GRAD_CASES))
+def test_grad_wide_blocks_match_adjoint_oracle(name):
+    # the paper's block widths up to 32 (Sec. IV: 32 x 32 blocks)
+    c = case(**WIDE_GRAD_CASES[name])
+    k = gpu_build(c)
+    Iref, dVref, dgref = OG.adjoint(c["W"], c["L"], 1.0, c["V"], c["g"], c["E"], c["w"],
+                                    c["lead_model"], 1e-10, c["gamma_l"])
+    for lead in (0, 1):
+        st, I, dV, dg = gpu_grad(k, c, lead)
+        assert st == M.OK, (name, lead)
+        assert abs(I - Iref) <= 1e-10 * abs(Iref), (name, lead)
+        assert rel(dV, dVref) < 1e-9, (name, lead, rel(dV, dVref))
+        assert rel(dg, dgref) < 1e-9, (name, lead, rel(dg, dgref))
+
+
+def test_grad_in_energy_chunks_equals_all_at_once():
+    # a workspace that holds one or two energies' G at a time gives the same derivatives bit
+    # for bit (each energy is differentiated by the same kernels; the final sum is in order)
+    c = case(W=6, L=7, eta=0.08, disorder=0.3, nE=5, emin=-2.0, emax=2.0)
     k = gpu_build(c)
     w = torch.tensor(c["w"], dtype=torch.float64, device=DEV)
-    gws = torch.empty(M.mc_negf_grad_workspace_bytes(k), dtype=torch.uint8, device=DEV)
-    x = torch.empty(40, dtype=torch.float64, device=DEV)
-    with pytest.raises(M.McnegfError) as ei:
-        M.mc_negf_grad(k, 0, w, gws, x, x)
-    assert ei.value.code == M.EINVAL
+    N = c["W"] * c["L"]
+    ref = gpu_grad(k, c, 0)
+    for chunk in (1, 2):
+        nb = M.mc_negf_grad_workspace_bytes_chunk(k, chunk)
+        assert nb < M.mc_negf_grad_workspace_bytes(k)
+        gws = torch.empty(nb, dtype=torch.uint8, device=DEV)
+        dV = torch.empty(N, dtype=torch.float64, device=DEV)
+        dg = torch.empty(N, dtype=torch.float64, device=DEV)
+        st, I = M.mc_negf_grad(k, 0, w, gws, dV, dg)
+        assert st == M.OK and I == ref[1]
+        assert (dV.cpu().numpy() == ref[2]).all() and (dg.cpu().numpy() == ref[3]).all()
+
+
+def test_full_size_w32_grad_in_chunks_on_sampled_energies():
+    # W = 32 x L = 130 (N = 4160, the paper's 32 x 32 blocks; the back substitution holds 8
+    # positions per thread) with 8 energies differentiated two at a time; weights vanish
+    # except at two energies, which the dense oracle differentiates
+    W, L = 32, 130
+    wl = inputs.DIFF_W16_L200.replace(W=W, L=L, n_energies=8)
+    E, wq = inputs.energy_grid(wl.emin, wl.emax, wl.n_energies)
+    idx = [2, 5]
+    w = np.zeros_like(wq)
+    w[idx] = wq[idx]
+    c = dict(W=W, L=L, V=inputs.onsite(wl), g=inputs.dephasing(wl), E=E, w=w, lead_model=0,
+             gamma_l=0.0)
+    k = gpu_build(c)
+    Iref, dVref, dgref = OG.adjoint(W, L, 1.0, c["V"], c["g"], E[idx], w[idx], 0, 1e-10, 0.0)
+    tw = torch.tensor(w, device=DEV)
+    gws = torch.empty(M.mc_negf_grad_workspace_bytes_chunk(k, 2), dtype=torch.uint8, device=DEV)
+    for lead in (0, 1):
+        dV = torch.empty(W * L, dtype=torch.float64, device=DEV)
+        dg = torch.empty(W * L, dtype=torch.float64, device=DEV)
+        st, I = M.mc_negf_grad(k, lead, tw, gws, dV, dg)
+        assert st == M.OK
+        assert abs(I - Iref) <= 1e-10 * abs(Iref)
+        assert rel(dV.cpu().numpy(), dVref) < 1e-9, rel(dV.cpu().numpy(), dVref)
+        assert rel(dg.cpu().numpy(), dgref) < 1e-9, rel(dg.cpu().numpy(), dgref)
 
 
 def test_grad_single_site_closed_form():
@@ -409,7 +466,7 @@ def test_grad_rejects_small_workspace():
     c = case(W=2, L=3, eta=0.1, disorder=0.0, nE=2, emin=-1.0, emax=1.0)
     k = gpu_build(c)
     w = torch.tensor(c["w"], dtype=torch.float64, device=DEV)
-    need = M.mc_negf_grad_workspace_bytes(k)
+    need = M.mc_negf_grad_workspace_bytes_chunk(k, 1)  # one energy at a time
     gws = torch.empty(need - 1, dtype=torch.uint8, device=DEV)
     x = torch.empty(6, dtype=torch.float64, device=DEV)
     with pytest.raises(M.McnegfError) as ei:
@@ -502,6 +559,40 @@ def test_every_narrow_width_blocks_and_direct_current(W):
     assert st == M.OK
     Tref = np.array([s.T_eff for s in sols])
     assert rel(T.cpu().numpy(), Tref) < 1e-10, W
+
+
+@pytest.mark.parametrize("W,L,nE", [(16, 9, 3), (32, 7, 6), (16, 1, 2), (32, 40, 5)])
+def test_fp32_refined_build_against_fp64_and_oracle(W, L, nE):
+    # FP32 block products plus one FP64 refinement step: |G|^2, the exit weights, the corners
+    # (through the lead terms) and T_eff back at FP64 accuracy (1e-10 of the FP64 build and of
+    # the oracle); more energies than one refinement pass holds (4)
+    c = case(W=W, L=L, eta=0.05, disorder=0.3, nE=nE, emin=-2.7, emax=2.2, seed=W + L)
+    k64 = gpu_build(c)
+    sr = M.make_system(W, L, 1.0, 0, 0.0, 1e-10, M.BUILD_FP32_PRODUCTS | M.BUILD_FP32_REFINE)
+    s32 = M.make_system(W, L, 1.0, 0, 0.0, 1e-10, M.BUILD_FP32_PRODUCTS)
+    assert M.mc_negf_workspace_bytes(sr, nE) > M.mc_negf_workspace_bytes(s32, nE)
+    ws = M.allocate_workspace(sr, nE)
+    V = torch.tensor(c["V"], dtype=torch.float64, device=DEV)
+    g = torch.tensor(c["g"], dtype=torch.float64, device=DEV)
+    E = torch.tensor(c["E"], dtype=torch.float64, device=DEV)
+    kr = M.mc_negf_build_kernel(sr, V, g, E, ws)
+    P64, Pr = k64.P().cpu().numpy(), kr.P().cpu().numpy()
+    scale = np.abs(P64).max(axis=2, keepdims=True)
+    assert (np.abs(Pr - P64) / scale).max() < 1e-10
+    for f in ("wL", "wR"):
+        assert rel(getattr(kr, f)().cpu().numpy(), getattr(k64, f)().cpu().numpy()) < 1e-10, f
+    lr, l64 = kr.lead().cpu().numpy(), k64.lead().cpu().numpy()
+    for slot in (M.LEAD_TLL, M.LEAD_TRL, M.LEAD_TLR, M.LEAD_TRR):
+        assert rel(lr[:, slot], l64[:, slot]) < 1e-10, slot
+    sols = oracle_solve(c)
+    Tref = np.array([s_.T_eff for s_ in sols])
+    wt = torch.tensor(c["w"], device=DEV)
+    T = torch.empty(nE, dtype=torch.float64, device=DEV)
+    sg = torch.empty_like(T)
+    st, I, _ = M.mc_negf_current(kr, 1, 0, None, wt, T, sg)
+    assert st == M.OK  # no row-total warning at the FP64 tolerance
+    assert rel(T.cpu().numpy(), Tref) < 1e-10
+    assert abs(I - D.current(sols, c["w"])) <= 1e-10 * abs(I)
 
 
 @pytest.mark.parametrize("W,L", [(16, 9), (32, 7)])
