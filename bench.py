@@ -721,64 +721,54 @@ def scale_bench(torch, dev, warmup, with_cpu, seed):
     I64 = float(o[0, 1, 0])
     T_gpu = float(T64[j])
 
-    # batch 0 again with the full inverse's block products in FP32 (same workspace)
-    sys32 = M.make_system(wl.W, wl.L, wl.t, wl.lead_model, wl.gamma_l, wl.delta_lead,
-                          M.BUILD_FP32_PRODUCTS)
-    one_batch(0, sys32)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    with M.LaunchTimes() as lt32:
-        one_batch(0, sys32)
-    torch.cuda.synchronize()
-    wall32 = time.perf_counter() - t0
-    require_complete(lt32)
-    o32 = out.cpu().numpy()
-    T32 = Td[0].cpu().numpy()
-    flags32 = M.mc_negf_status(holder["k"])
-    res["fp32_products"] = {
-        "what": "batch 0 with the full-inverse block products in FP32 on the matrix cores "
-                "(FP64 RGF blocks, |G|^2, alias tables, probe solve, tallies); no refinement",
-        "ms_per_batch": 1e3 * wall32,
-        "fullinv_ms": lt32.total_ms("fullinv_kernel"),
-        "fullinv_ms_fp64": fi_ms,
-        "max_rel_err_T_direct_vs_fp64": float(np.max(np.abs(T32 - T64) / np.abs(T64))),
-        "rel_err_I_direct_vs_fp64": abs(float(o32[0, 1, 0]) - I64) / abs(I64),
-        "mc_minus_fp64_direct_in_sigma": (float(o32[0, 0, 0]) - I64) / float(o32[0, 0, 1]),
-        "status_flags": int(flags32),
-    }
-    T_gpu32 = float(T32[j])
-    # batch 0 with FP32 block products and one FP64 refinement step (a larger workspace)
-    del ws
-    holder.clear()
-    torch.cuda.empty_cache()
-    sysr = M.make_system(wl.W, wl.L, wl.t, wl.lead_model, wl.gamma_l, wl.delta_lead,
-                         M.BUILD_FP32_PRODUCTS | M.BUILD_FP32_REFINE)
-    ws = M.allocate_workspace(sysr, nE, dev)
-    one_batch(0, sysr)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    with M.LaunchTimes() as ltr:
-        one_batch(0, sysr)
-    torch.cuda.synchronize()
-    wallr = time.perf_counter() - t0
-    require_complete(ltr)
-    orr = out.cpu().numpy()
-    Tr = Td[0].cpu().numpy()
-    flagsr = M.mc_negf_status(holder["k"])
-    res["fp32_refined"] = {
-        "what": "batch 0 with FP32 block products, then one FP64 refinement step on G (FP64 "
-                "residual from the stencil, FP32 correction solve with the RGF blocks)",
-        "ms_per_batch": 1e3 * wallr,
-        "fullinv_fp32_store_ms": ltr.total_ms("fullinv_store_g_kernel"),
-        "refine_ms": ltr.total_ms("refine_kernel"),
-        "fullinv_ms_fp64": fi_ms,
-        "max_rel_err_T_direct_vs_fp64": float(np.max(np.abs(Tr - T64) / np.abs(T64))),
-        "rel_err_I_direct_vs_fp64": abs(float(orr[0, 1, 0]) - I64) / abs(I64),
-        "mc_minus_fp64_direct_in_sigma": (float(orr[0, 0, 0]) - I64) / float(orr[0, 0, 1]),
-        "status_flags": int(flagsr),
-        "workspace_gb": ws.numel() / 1e9,
-    }
-    T_gpur = float(Tr[j])
+    sweep64_ms = per_kernel.get("rgf_sweep_kernel", {}).get("ms_per_batch")
+
+    def fp32_variant(flags, what):
+        # batch 0 again, built with FP32 options (workspace as the flags need); errors against
+        # the FP64 batch 0 above
+        nonlocal ws
+        need = M.mc_negf_workspace_bytes(M.make_system(wl.W, wl.L, wl.t, wl.lead_model,
+                                                       wl.gamma_l, wl.delta_lead, flags), nE)
+        if ws.numel() < need:
+            del ws
+            holder.clear()
+            torch.cuda.empty_cache()
+            ws = M.allocate_workspace(M.make_system(wl.W, wl.L, wl.t, wl.lead_model, wl.gamma_l,
+                                                    wl.delta_lead, flags), nE, dev)
+        sysx = M.make_system(wl.W, wl.L, wl.t, wl.lead_model, wl.gamma_l, wl.delta_lead, flags)
+        one_batch(0, sysx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with M.LaunchTimes() as ltx:
+            one_batch(0, sysx)
+        torch.cuda.synchronize()
+        wallx = time.perf_counter() - t0
+        require_complete(ltx)
+        ox = out.cpu().numpy()
+        Tx = Td[0].cpu().numpy()
+        r = {"what": what, "ms_per_batch": 1e3 * wallx,
+             "fullinv_ms": ltx.total_ms("fullinv_kernel") +
+             ltx.total_ms("fullinv_store_g_kernel"),
+             "fullinv_ms_fp64": fi_ms,
+             "rgf_sweep_ms": ltx.total_ms("rgf_sweep_kernel"), "rgf_sweep_ms_fp64": sweep64_ms,
+             "refine_ms": ltx.total_ms("refine_kernel"),
+             "max_rel_err_T_direct_vs_fp64": float(np.max(np.abs(Tx - T64) / np.abs(T64))),
+             "rel_err_I_direct_vs_fp64": abs(float(ox[0, 1, 0]) - I64) / abs(I64),
+             "mc_minus_fp64_direct_in_sigma": (float(ox[0, 0, 0]) - I64) / float(ox[0, 0, 1]),
+             "status_flags": int(M.mc_negf_status(holder["k"])),
+             "workspace_gb": ws.numel() / 1e9}
+        return r, float(Tx[j])
+
+    P, R, S = M.BUILD_FP32_PRODUCTS, M.BUILD_FP32_REFINE, M.BUILD_FP32_SWEEPS
+    res["fp32_products"], T_gpu32 = fp32_variant(
+        P, "batch 0 with the full-inverse block products in FP32 on the matrix cores (FP64 RGF "
+           "sweeps, |G|^2, alias tables, probe solve, tallies); no refinement")
+    res["fp32_refined"], T_gpur = fp32_variant(
+        P | R, "batch 0 with FP32 block products, then one FP64 refinement step on G (FP64 "
+               "residual from the stencil, FP32 correction solve with the RGF blocks)")
+    res["fp32_sweeps_refined"], T_gpus = fp32_variant(
+        P | R | S, "batch 0 with FP32 RGF sweeps and FP32 block products, then one FP64 "
+                   "refinement step on G")
     del holder, ws
     torch.cuda.empty_cache()
     if with_cpu:
@@ -802,7 +792,8 @@ def scale_bench(torch, dev, warmup, with_cpu, seed):
             "T_oracle": T_ref, "T_gpu_direct": T_gpu,
             "rel_err_direct": abs(T_gpu - T_ref) / abs(T_ref),
             "rel_err_direct_fp32_products": abs(T_gpu32 - T_ref) / abs(T_ref),
-            "rel_err_direct_fp32_refined": abs(T_gpur - T_ref) / abs(T_ref)}
+            "rel_err_direct_fp32_refined": abs(T_gpur - T_ref) / abs(T_ref),
+            "rel_err_direct_fp32_sweeps_refined": abs(T_gpus - T_ref) / abs(T_ref)}
     return res
 
 

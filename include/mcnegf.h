@@ -127,9 +127,16 @@ typedef struct mcnegf_system {
  * Eq. (7)) corrects it before |G|^2, the exit weights and the corners are formed: the residual
  * I - A G0 in FP64 (5-point stencil and lead blocks), the correction solved in FP32 with the
  * block LU of the left-connected RGF blocks, G1 = G0 + correction in FP64.  |G_ij|^2 and the
- * currents then agree with an FP64 build to about 1e-12 relative.  The workspace grows by
- * 24 bytes per entry of G for 4 energies at a time (refined 4 energies per pass). */
+ * currents then agree with an FP64 build to about 1e-12 relative.  The refinement also
+ * rewrites the diagonal blocks and A_jj from G1.  The workspace grows by 24 bytes per entry of
+ * G for 8 energies at a time (refined 8 energies per pass). */
 #define MCNEGF_BUILD_FP32_REFINE 0x8u
+/* MCNEGF_BUILD_FP32_SWEEPS (with MCNEGF_BUILD_FP32_PRODUCTS only): the left and right RGF
+ * sweeps (g_k = (A_k - t^2 g_{k-1})^{-1}, Sec. III B) also run in FP32; the diagonal blocks
+ * are then formed in FP64 from the FP32 sweep blocks.  Errors grow with the length: at
+ * W = 32, L = 500 about 2e-5 relative in T_eff without refinement and 5e-11 with
+ * MCNEGF_BUILD_FP32_REFINE (whose correction solve then uses the FP32 blocks). */
+#define MCNEGF_BUILD_FP32_SWEEPS 0x10u
 
 /*
  * Handle filled by mc_negf_build_kernel: shapes plus device pointers into the caller's

@@ -293,6 +293,101 @@ int oracle_walk_sampled_alias(const uint32_t *thr, const int32_t *alias, int64_t
 }
 
 /*
+ * Importance-sampled walks (Sec. V A, "Improved estimator"): step 6' draws from the modified
+ * rows p'_ij = p_ij b_j / rho_i, rho_i = sum_j p_ij b_j, for a non-negative bias b over the
+ * outcomes, and the walker carries the likelihood ratio of its path, the product over its
+ * steps i -> j of p_ij / p'_ij = rho_i / b_j.  The score of a walk that exits at the
+ * collecting lead q is that product (times c_p, applied by the caller); any other walk scores
+ * 0.  The stream layout is that of the plain walk, so with b = 1 the paths and counts are the
+ * plain walker's.  mode 0: cumulative-sum sampler on the modified dense rows Kb [nE][n][n]
+ * (any positive multiple of p'); mode 1: alias tables of the modified rows [nE][n][pitch].
+ * rho and bias are [nE][n].  Tallies as above; wsum[2 k] += sum of scores, wsum[2 k + 1] +=
+ * sum of squared scores at energy k.
+ */
+static int walk_weighted_impl(int mode, const double *Kb, const uint32_t *thr,
+                              const int32_t *alias, int64_t pitch, int32_t nE, int32_t n,
+                              const double *rho, const double *bias, uint64_t seed,
+                              uint32_t realization, uint32_t inject_lead, uint64_t walker_begin,
+                              uint64_t n_walkers, uint32_t max_steps, int64_t *tallies,
+                              double *wsum)
+{
+    if (n < 3 || nE < 1 || inject_lead > 1 || realization >= (1u << 30)) return -1;
+    if (walker_begin + n_walkers > 0x100000000ull) return -1;
+    const int32_t N = n - 2;
+    const int32_t q = N + 1 - (int32_t)inject_lead;
+    const uint32_t tag = (realization << 1) | inject_lead;
+    for (int32_t k = 0; k < nE; ++k) {
+        const double *rk = rho + (int64_t)k * n;
+        const double *bk = bias + (int64_t)k * n;
+        int64_t cL = 0, cR = 0, tr = 0, s1 = 0, s2 = 0;
+        double sx = 0.0, sx2 = 0.0;
+#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : cL, cR, tr, s1, s2, sx, sx2)
+        for (int64_t i = 0; i < (int64_t)n_walkers; ++i) {
+            uint32_t w = (uint32_t)(walker_begin + (uint64_t)i);
+            stream_t st;
+            stream_init(&st, seed, w, (uint32_t)k, tag);
+            int32_t s = N + (int32_t)inject_lead;
+            uint32_t steps = 0;
+            int outcome = -1;
+            double ratio = 1.0;
+            while (steps < max_steps) {
+                uint32_t a, b;
+                stream_pair(&st, steps, &a, &b);
+                int32_t next;
+                if (mode == 0) {
+                    next = draw_cdf(Kb + ((int64_t)k * n + s) * (int64_t)n, n, a, b);
+                } else {
+                    uint32_t c = lemire_bucket(&st, steps, a, (uint32_t)n);
+                    int64_t e = ((int64_t)k * n + s) * pitch + c;
+                    next = (b < thr[e]) ? (int32_t)c : alias[e];
+                }
+                ++steps;
+                if (next < N || next == q) ratio *= rk[s] / bk[next];
+                if (next >= N) { outcome = next - N; break; }
+                s = next;
+            }
+            if (outcome == 0) ++cL;
+            else if (outcome == 1) ++cR;
+            else ++tr;
+            s1 += steps;
+            s2 += (int64_t)steps * (int64_t)steps;
+            if (outcome >= 0 && N + outcome == q) {
+                sx += ratio;
+                sx2 += ratio * ratio;
+            }
+        }
+        tallies[5 * k + 0] += cL;
+        tallies[5 * k + 1] += cR;
+        tallies[5 * k + 2] += tr;
+        tallies[5 * k + 3] += s1;
+        tallies[5 * k + 4] += s2;
+        wsum[2 * k] += sx;
+        wsum[2 * k + 1] += sx2;
+    }
+    return 0;
+}
+
+int oracle_walk_weighted_cdf(const double *Kb, int32_t nE, int32_t n, const double *rho,
+                             const double *bias, uint64_t seed, uint32_t realization,
+                             uint32_t inject_lead, uint64_t walker_begin, uint64_t n_walkers,
+                             uint32_t max_steps, int64_t *tallies, double *wsum)
+{
+    return walk_weighted_impl(0, Kb, NULL, NULL, 0, nE, n, rho, bias, seed, realization,
+                              inject_lead, walker_begin, n_walkers, max_steps, tallies, wsum);
+}
+
+int oracle_walk_weighted_alias(const uint32_t *thr, const int32_t *alias, int64_t pitch,
+                               int32_t nE, int32_t n, const double *rho, const double *bias,
+                               uint64_t seed, uint32_t realization, uint32_t inject_lead,
+                               uint64_t walker_begin, uint64_t n_walkers, uint32_t max_steps,
+                               int64_t *tallies, double *wsum)
+{
+    if (pitch < n) return -1;
+    return walk_weighted_impl(1, NULL, thr, alias, pitch, nE, n, rho, bias, seed, realization,
+                              inject_lead, walker_begin, n_walkers, max_steps, tallies, wsum);
+}
+
+/*
  * Interpolated walks (Sec. V A, "Interpolation"): walker w at fine energy f walks on the
  * mixture (1 - alpha_f) p(E_lo) + alpha_f p(E_hi) of the rows of two nodes lo = lo[f] and
  * hi = lo + 1 (hi = lo for the last node), alpha_f = alpha32[f] / 2^32.  Step n uses the

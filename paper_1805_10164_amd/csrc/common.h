@@ -118,7 +118,7 @@ struct Layout {
     int refine_chunk;  // energies refined at a time (FP32 products with one refinement step)
 };
 Layout make_layout(int W, int L, int nE, bool with_alias, bool with_direct, bool refine = false);
-constexpr int kRefineChunk = 4;  // energies refined at a time
+constexpr int kRefineChunk = 8;  // energies refined at a time
 
 // gradient workspace (caller-owned, separate from the build workspace)
 struct GradBuffers {
@@ -201,6 +201,8 @@ hipError_t launch_walk_sampled(const mcnegf_kernel& k, const SampledScratch& sc,
 hipError_t launch_sampled_current(const mcnegf_kernel& k, uint32_t inject_lead,
                                   const int64_t* tallies, const double* weights, double* T,
                                   double* sigmaT, hipStream_t s);
+// RGF sweeps in FP32 (W = 16 or 32) and the FP64 diagonal blocks, for FP32-products builds.
+hipError_t launch_rgf_fp32(const mcnegf_kernel& k, const double* onsite, hipStream_t s);
 // The full inverse with FP32 block products, writing the complex G (row-major, pitch ldG).
 hipError_t launch_fullinv_fp32_store_g(const mcnegf_kernel& k, double2* Gc, int64_t ldG,
                                        hipStream_t s);

@@ -85,10 +85,11 @@ static bool valid_system(const mcnegf_system* s) {
         return false;
     }
     if (s->flags & ~(MCNEGF_BUILD_NO_ALIAS | MCNEGF_BUILD_NO_DIRECT | MCNEGF_BUILD_FP32_PRODUCTS |
-                     MCNEGF_BUILD_FP32_REFINE))
+                     MCNEGF_BUILD_FP32_REFINE | MCNEGF_BUILD_FP32_SWEEPS))
         return false;
     if ((s->flags & MCNEGF_BUILD_FP32_PRODUCTS) && s->W != 16 && s->W != 32) return false;
-    if ((s->flags & MCNEGF_BUILD_FP32_REFINE) && !(s->flags & MCNEGF_BUILD_FP32_PRODUCTS))
+    if ((s->flags & (MCNEGF_BUILD_FP32_REFINE | MCNEGF_BUILD_FP32_SWEEPS)) &&
+        !(s->flags & MCNEGF_BUILD_FP32_PRODUCTS))
         return false;
     return true;
 }
@@ -218,7 +219,10 @@ int32_t mc_negf_build_kernel(const mcnegf_system* sys, const double* d_onsite,
     if ((err = launch_clear_status(k.status, k.counters, stream)) != hipSuccess) return hip_fail(err);
     if ((err = launch_lead_sigma(k, sys->gamma_l, sys->delta_lead, stream)) != hipSuccess)
         return hip_fail(err);
-    if ((err = launch_rgf(k, d_onsite, stream)) != hipSuccess) return hip_fail(err);
+    if ((err = (sys->flags & MCNEGF_BUILD_FP32_SWEEPS) ? launch_rgf_fp32(k, d_onsite, stream)
+                                                            : launch_rgf(k, d_onsite, stream)) !=
+        hipSuccess)
+        return hip_fail(err);
     if (with_refine(sys)) {
         // FP32 block products, then one FP64 refinement step, a chunk of energies at a time
         double2* G0 = reinterpret_cast<double2*>(base + lay.off_refine);

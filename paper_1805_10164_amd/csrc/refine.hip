@@ -9,7 +9,7 @@
 //       forward  y_k = gL_k (r_k - t y_{k-1}),  backward  d_k = y_k - t gL_k d_{k+1};
 //   G1 = G0 + D in FP64,
 // and G1 goes straight into what the build keeps: |G1_ij|^2 (P), the exit weights
-// <psi_j|Gamma_r|psi_j> and the corner blocks.  One lane per column (a wavefront owns 64
+// <psi_j|Gamma_r|psi_j>, the corner and diagonal blocks and A_jj = -2 Im G1_jj.  One lane per column (a wavefront owns 64
 // consecutive columns); the RGF block of each slice is staged in LDS in FP32 one slice ahead
 // (double-buffered) and read by every lane at the same address.
 #include "common.h"
@@ -50,7 +50,8 @@ __global__ void __launch_bounds__(64) refine_kernel(
     int64_t ld, const double* __restrict__ energies, const double* __restrict__ onsite,
     const double* __restrict__ gamma, const double2* __restrict__ sigma,
     const double* __restrict__ gam_lead, int L, double t, double* __restrict__ P, int64_t ldP,
-    double* __restrict__ wL, double* __restrict__ wR, double2* __restrict__ corner) {
+    double* __restrict__ wL, double* __restrict__ wR, double2* __restrict__ corner,
+    double2* __restrict__ Gd, double* __restrict__ Adiag) {
     const int N = W * L;
     const int e = blockIdx.y;
     const int lane = threadIdx.x;
@@ -67,6 +68,7 @@ __global__ void __launch_bounds__(64) refine_kernel(
     double* Pe = P + (size_t)e * N * ldP;
     double2* cRL = corner + (size_t)e * 2 * W * W;
     double2* cLR = cRL + W * W;
+    double2* Gde = Gd + ((size_t)e * L + lc) * W * W;  // diagonal block of this column's slice
     const float tf = (float)t;
     constexpr int BS = 2 * W * W;
     __shared__ float Ms_raw[2 * BS];
@@ -88,7 +90,8 @@ __global__ void __launch_bounds__(64) refine_kernel(
         matvec_f32<W>(acc, y, M);
 #pragma unroll
         for (int x = 0; x < W; ++x) acc[x] = make_float2(-tf * acc[x].x, -tf * acc[x].y);
-        for (int r = 0; r < W; ++r) {  // one residual row at a time, added as column r of M
+#pragma unroll 4
+        for (int r = 0; r < W; ++r) {  // residual rows, each added as column r of M
             const int i = k * W + r;
             const double2 g = g0(i);
             const double d = E - onsite[i], h = 0.5 * gamma[i];
@@ -144,6 +147,10 @@ __global__ void __launch_bounds__(64) refine_kernel(
             const double2 g1 = cmk(g.x + (double)y[r].x, g.y + (double)y[r].y);
             if (valid) Pe[(size_t)(k * W + r) * ldP + c] = g1.x * g1.x + g1.y * g1.y;
             if (end) endv[r][lane] = g1;
+            if (valid && k == lc) {
+                Gde[r * W + yc] = g1;
+                if (r == yc) Adiag[(size_t)e * N + c] = -2.0 * g1.y;
+            }
         }
         if (end && valid) {
             // Re v^+ Gamma v over the end slice, Gamma real symmetric
@@ -180,7 +187,8 @@ static hipError_t launch_refine_w(const mcnegf_kernel& k, const double* onsite,
     hipLaunchKernelGGL(refine_kernel<W>, dim3((k.N + 63) / 64, k.nE), dim3(64), 0, s,
                        reinterpret_cast<const double2*>(k.gL), G0, Y, ld, k.energies, onsite,
                        k.gamma, reinterpret_cast<const double2*>(k.sigma), k.gam_lead, k.L, k.t,
-                       k.P, k.p_pitch, k.wL, k.wR, reinterpret_cast<double2*>(k.corner));
+                       k.P, k.p_pitch, k.wL, k.wR, reinterpret_cast<double2*>(k.corner),
+                       reinterpret_cast<double2*>(k.Gd), k.Adiag);
     return hipGetLastError();
 }
 

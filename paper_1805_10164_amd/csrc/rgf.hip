@@ -461,14 +461,36 @@ __global__ void __launch_bounds__(64) rgf_diag_wide_kernel(const double* __restr
 // barrier per step); the pivot row's entry x_rc is in the same wavefront and is read with a
 // lane shuffle.  Every thread computes the same pivot from the same LDS column.
 
+// Complex arithmetic in the sweep's precision: C = double2 (FP64) or float2 (FP32 sweeps of a
+// build with FP32 block products; the blocks are stored in FP64 either way).
+__device__ inline float2 cmk_t(float re, float im, float2) { return make_float2(re, im); }
+__device__ inline double2 cmk_t(double re, double im, double2) { return cmk(re, im); }
+__device__ inline float cabs2(float2 a) { return a.x * a.x + a.y * a.y; }
+__device__ inline float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline void cfms(float2& a, float2 b, float2 c) {
+    a.x = fmaf(-b.x, c.x, fmaf(b.y, c.y, a.x));
+    a.y = fmaf(-b.x, c.y, fmaf(-b.y, c.x, a.y));
+}
+__device__ inline float2 crecip(float2 a) {
+    if (fabsf(a.x) >= fabsf(a.y)) {
+        const float r = a.y / a.x, d = a.x + a.y * r;
+        return make_float2(1.0f / d, -r / d);
+    }
+    const float r = a.x / a.y, d = a.y + a.x * r;
+    return make_float2(r / d, -1.0f / d);
+}
+
+template <typename C>
 struct WgLds {
-    double2 col[2][32];   // pivot column of the current step, double-buffered
-    double2 y[32][33];    // the permuted inverse, gathered at the end of a slice
-    int perm[32];         // perm[p] = r_p
-    int iperm[32];        // iperm[r_p] = p
+    C col[2][32];   // pivot column of the current step, double-buffered
+    C y[32][33];    // the permuted inverse, gathered at the end of a slice
+    int perm[32];   // perm[p] = r_p
+    int iperm[32];  // iperm[r_p] = p
 };
 
-template <int W>
+template <int W, typename C = double2>
 __global__ void __launch_bounds__(256) rgf_sweep_wg_kernel(const double* __restrict__ energies,
                                                            const double* __restrict__ onsite,
                                                            const double* __restrict__ gamma,
@@ -477,7 +499,8 @@ __global__ void __launch_bounds__(256) rgf_sweep_wg_kernel(const double* __restr
                                                            double2* __restrict__ gL,
                                                            double2* __restrict__ gR,
                                                            uint32_t* __restrict__ status) {
-    __shared__ WgLds S;
+    typedef decltype(C().x) R;  // real type of the sweep
+    __shared__ WgLds<C> S;
     const int e = blockIdx.x >> 1;
     const int dir = blockIdx.x & 1;
     const int lane = threadIdx.x & 63;
@@ -488,9 +511,9 @@ __global__ void __launch_bounds__(256) rgf_sweep_wg_kernel(const double* __restr
     double2* out = (dir == 0 ? gL : gR) + (size_t)e * L * W * W;
     const double t2 = t * t;
     bool ok = true;
-    double2 gprev[4];
+    C gprev[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) gprev[s] = cmk(0.0, 0.0);
+    for (int s = 0; s < 4; ++s) gprev[s] = cmk_t((R)0, (R)0, C());
     // onsite energy and dephasing rate of site (k, c), loaded one slice ahead
     const int cs = c < W ? c : 0;
     const int k_first = dir == 0 ? 0 : L - 1;
@@ -504,7 +527,7 @@ __global__ void __launch_bounds__(256) rgf_sweep_wg_kernel(const double* __restr
             gn = gamma[kn * W + cs];
         }
         // this thread's entries of X = A_k - t^2 g_{k-1} (identity outside W x W)
-        double2 a[4];
+        C a[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int i = 4 * rg + s;
@@ -515,9 +538,13 @@ __global__ void __launch_bounds__(256) rgf_sweep_wg_kernel(const double* __restr
                 if (i == c - 1 || i == c + 1) v = cmk(t, 0.0);
                 if (k == 0) v = csub(v, sig[i * W + c]);
                 if (k == L - 1) v = csub(v, sig[i * W + c]);
-                if (sl > 0) v = csub(v, cscale(gprev[s], t2));
             }
-            a[s] = v;
+            C u = cmk_t((R)v.x, (R)v.y, C());
+            if (i < W && c < W && sl > 0) {
+                u.x -= (R)t2 * gprev[s].x;
+                u.y -= (R)t2 * gprev[s].y;
+            }
+            a[s] = u;
         }
         if (c == 0) {
 #pragma unroll
@@ -526,15 +553,15 @@ __global__ void __launch_bounds__(256) rgf_sweep_wg_kernel(const double* __restr
         __syncthreads();
         uint32_t used = 0u;
         for (int p = 0; p < W; ++p) {  // uniform loop
-            const double2* cb = S.col[p & 1];
-            double2 f[4];
-            double best = -1.0;
+            const C* cb = S.col[p & 1];
+            C f[4];
+            R best = (R)-1;
             int bi = 64;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int i = 4 * rg + s;
                 f[s] = cb[i];
-                const double m = (i < W && !((used >> i) & 1u)) ? cabs2(f[s]) : -1.0;
+                const R m = (i < W && !((used >> i) & 1u)) ? cabs2(f[s]) : (R)-1;
                 const bool take = m > best;  // rows in increasing order: ties keep the lower
                 best = take ? m : best;
                 bi = take ? i : bi;
@@ -542,7 +569,7 @@ __global__ void __launch_bounds__(256) rgf_sweep_wg_kernel(const double* __restr
             // argmax over the 8 lanes of this column's group (ties: lowest row)
 #pragma unroll
             for (int o = 1; o < 8; o <<= 1) {
-                const double ob = __shfl_xor(best, o, 64);
+                const R ob = __shfl_xor(best, o, 64);
                 const int oi = __shfl_xor(bi, o, 64);
                 const bool take = (ob > best) | ((ob == best) & (oi < bi));
                 best = take ? ob : best;
@@ -553,33 +580,33 @@ __global__ void __launch_bounds__(256) rgf_sweep_wg_kernel(const double* __restr
                 r = __builtin_ctz(~used);
                 ok = false;
             }
-            const double2 pv = cb[r];
-            const double pm = cabs2(pv);
-            if (!(pm > 0.0) || !isfinite(pm)) ok = false;
-            const double2 pinv = crecip(pv);
+            const C pv = cb[r];
+            const R pm = cabs2(pv);
+            if (!(pm > (R)0) || !isfinite(pm)) ok = false;
+            const C pinv = crecip(pv);
             // x_rc from the lane holding row r of this column
             // a[r & 3] as a masked sum (a select chain would become a dynamic index into
             // scratch memory)
             const int rs = r & 3;
-            double2 own = cmk(0.0, 0.0);
+            C own = cmk_t((R)0, (R)0, C());
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                const double m = (double)(s == rs);
+                const R m = (R)(s == rs);
                 own.x = fma(a[s].x, m, own.x);
                 own.y = fma(a[s].y, m, own.y);
             }
             const int src = (lane & ~7) | (r >> 2);
-            const double2 xrc = cmk(__shfl(own.x, src, 64), __shfl(own.y, src, 64));
-            const double2 q = cmul(xrc, pinv);
+            const C xrc = cmk_t(__shfl(own.x, src, 64), __shfl(own.y, src, 64), C());
+            const C q = cmul(xrc, pinv);
             const bool piv_col = c == p;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int i = 4 * rg + s;
                 const bool piv_row = i == r;
-                double2 u = a[s];
-                cfms(u, f[s], q);                      // x_ic - x_ip x_rc pinv
-                const double2 wcol = cmul(f[s], pinv);  // x_ip pinv
-                double2 v;
+                C u = a[s];
+                cfms(u, f[s], q);                 // x_ic - x_ip x_rc pinv
+                const C wcol = cmul(f[s], pinv);  // x_ip pinv
+                C v;
                 v.x = piv_col ? (piv_row ? pinv.x : -wcol.x) : (piv_row ? q.x : u.x);
                 v.y = piv_col ? (piv_row ? pinv.y : -wcol.y) : (piv_row ? q.y : u.y);
                 a[s] = v;
@@ -606,9 +633,9 @@ __global__ void __launch_bounds__(256) rgf_sweep_wg_kernel(const double* __restr
             for (int s = 0; s < 4; ++s) {
                 const int i = 4 * rg + s;
                 if (i < W) {
-                    const double2 v = S.y[S.perm[i]][jc];
+                    const C v = S.y[S.perm[i]][jc];
                     gprev[s] = v;
-                    o[i * W + c] = v;
+                    o[i * W + c] = cmk((double)v.x, (double)v.y);
                 }
             }
         }
@@ -618,16 +645,29 @@ __global__ void __launch_bounds__(256) rgf_sweep_wg_kernel(const double* __restr
     if (!ok && threadIdx.x == 0) atomicOr(status, MCNEGF_FLAG_SINGULAR);
 }
 
+// The left/right sweeps on a workgroup per chain, in FP64 or (fp32) in FP32.
+template <int W>
+static hipError_t launch_rgf_sweep_wg(const mcnegf_kernel& k, const double* onsite, bool fp32,
+                                      hipStream_t s) {
+    const double2* sig = reinterpret_cast<const double2*>(k.sigma);
+    double2* gL = reinterpret_cast<double2*>(k.gL);
+    double2* gR = reinterpret_cast<double2*>(k.gR);
+    MCNEGF_TIMED("rgf_sweep_kernel", s);
+    if (fp32)
+        hipLaunchKernelGGL((rgf_sweep_wg_kernel<W, float2>), dim3(2 * k.nE), dim3(256), 0, s,
+                           k.energies, onsite, k.gamma, sig, k.L, k.t, gL, gR, k.status);
+    else
+        hipLaunchKernelGGL((rgf_sweep_wg_kernel<W, double2>), dim3(2 * k.nE), dim3(256), 0, s,
+                           k.energies, onsite, k.gamma, sig, k.L, k.t, gL, gR, k.status);
+    return hipGetLastError();
+}
+
 template <int W>
 static hipError_t launch_rgf_wide(const mcnegf_kernel& k, const double* onsite, hipStream_t s) {
     const double2* sig = reinterpret_cast<const double2*>(k.sigma);
     double2* gL = reinterpret_cast<double2*>(k.gL);
     double2* gR = reinterpret_cast<double2*>(k.gR);
-    {
-        MCNEGF_TIMED("rgf_sweep_kernel", s);
-        hipLaunchKernelGGL(rgf_sweep_wg_kernel<W>, dim3(2 * k.nE), dim3(256), 0, s, k.energies,
-                           onsite, k.gamma, sig, k.L, k.t, gL, gR, k.status);
-    }
+    if (launch_rgf_sweep_wg<W>(k, onsite, false, s) != hipSuccess) return hipGetLastError();
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     {
@@ -637,6 +677,31 @@ static hipError_t launch_rgf_wide(const mcnegf_kernel& k, const double* onsite, 
                            reinterpret_cast<double2*>(k.Gd), k.Adiag, k.status);
     }
     return hipGetLastError();
+}
+
+// FP32 sweeps (a build with FP32 block products, W = 16 or 32), then the FP64 diagonal blocks.
+hipError_t launch_rgf_fp32(const mcnegf_kernel& k, const double* onsite, hipStream_t s) {
+    const double2* sig = reinterpret_cast<const double2*>(k.sigma);
+    const double2* gL = reinterpret_cast<const double2*>(k.gL);
+    const double2* gR = reinterpret_cast<const double2*>(k.gR);
+    hipError_t err;
+    if (k.W == 16) {
+        if ((err = launch_rgf_sweep_wg<16>(k, onsite, true, s)) != hipSuccess) return err;
+        MCNEGF_TIMED("rgf_diag_kernel", s);
+        hipLaunchKernelGGL(rgf_diag_kernel<16>, dim3(k.nE * k.L), dim3(64), 0, s, k.energies,
+                           onsite, k.gamma, sig, k.L, k.t, gL, gR,
+                           reinterpret_cast<double2*>(k.Gd), k.Adiag, k.status);
+        return hipGetLastError();
+    }
+    if (k.W == 32) {
+        if ((err = launch_rgf_sweep_wg<32>(k, onsite, true, s)) != hipSuccess) return err;
+        MCNEGF_TIMED("rgf_diag_kernel", s);
+        hipLaunchKernelGGL(rgf_diag_wide_kernel<32>, dim3(k.nE * k.L), dim3(64), 0, s,
+                           k.energies, onsite, k.gamma, sig, k.L, k.t, gL, gR,
+                           reinterpret_cast<double2*>(k.Gd), k.Adiag, k.status);
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_rgf(const mcnegf_kernel& k, const double* onsite, hipStream_t s) {

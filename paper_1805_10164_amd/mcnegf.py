@@ -171,13 +171,16 @@ BUILD_NO_ALIAS = 0x1
 BUILD_NO_DIRECT = 0x2
 BUILD_FP32_PRODUCTS = 0x4
 BUILD_FP32_REFINE = 0x8
+BUILD_FP32_SWEEPS = 0x10
 
 
 def make_system(W: int, L: int, t: float = 1.0, lead_model: int = 0, gamma_l: float = 0.0,
                 delta_lead: float = 1e-10, flags: int = 0) -> System:
     """flags: BUILD_NO_ALIAS builds no alias tables (DIRECT current and gradient only),
     BUILD_NO_DIRECT reserves nothing for the DIRECT solve (Monte Carlo only),
-    BUILD_FP32_PRODUCTS runs the full inverse's block products in FP32 (W = 16, 32)."""
+    BUILD_FP32_PRODUCTS runs the full inverse's block products in FP32 (W = 16, 32), with
+    BUILD_FP32_REFINE one FP64 refinement step on G and with BUILD_FP32_SWEEPS the RGF sweeps
+    in FP32 too."""
     return System(W, L, t, lead_model, gamma_l, delta_lead, flags)
 
 

@@ -242,16 +242,17 @@ def test_fp32_products_only_at_widths_16_and_32():
         s = M.make_system(W, 20, flags=M.BUILD_FP32_PRODUCTS)
         code = lib.mc_negf_workspace_bytes(ctypes.byref(s), 4, ctypes.byref(out))
         assert (code == M.OK) == ok, (W, code)
-    # the refinement step only with FP32 products (and so only at widths 16 and 32)
-    for W, flags, ok in ((16, M.BUILD_FP32_PRODUCTS | M.BUILD_FP32_REFINE, True),
-                         (32, M.BUILD_FP32_PRODUCTS | M.BUILD_FP32_REFINE, True),
-                         (16, M.BUILD_FP32_REFINE, False),
-                         (10, M.BUILD_FP32_PRODUCTS | M.BUILD_FP32_REFINE, False)):
+    # the refinement step and the FP32 sweeps only with FP32 products (and so only at widths
+    # 16 and 32)
+    P, R, S = M.BUILD_FP32_PRODUCTS, M.BUILD_FP32_REFINE, M.BUILD_FP32_SWEEPS
+    for W, flags, ok in ((16, P | R, True), (32, P | R, True), (16, R, False), (10, P | R, False),
+                         (32, P | S, True), (16, P | S | R, True), (32, S, False),
+                         (16, S | R, False), (8, P | S, False)):
         s = M.make_system(W, 20, flags=flags)
         code = lib.mc_negf_workspace_bytes(ctypes.byref(s), 4, ctypes.byref(out))
         assert (code == M.OK) == ok, (W, flags, code)
     # unknown flag bits are refused
-    s = M.make_system(16, 20, flags=0x10)
+    s = M.make_system(16, 20, flags=0x20)
     assert lib.mc_negf_workspace_bytes(ctypes.byref(s), 4, ctypes.byref(out)) == M.EINVAL
 
 

@@ -561,14 +561,19 @@ def test_every_narrow_width_blocks_and_direct_current(W):
     assert rel(T.cpu().numpy(), Tref) < 1e-10, W
 
 
-@pytest.mark.parametrize("W,L,nE", [(16, 9, 3), (32, 7, 6), (16, 1, 2), (32, 40, 5)])
-def test_fp32_refined_build_against_fp64_and_oracle(W, L, nE):
-    # FP32 block products plus one FP64 refinement step: |G|^2, the exit weights, the corners
-    # (through the lead terms) and T_eff back at FP64 accuracy (1e-10 of the FP64 build and of
-    # the oracle); more energies than one refinement pass holds (4)
+@pytest.mark.parametrize("W,L,nE,sweeps", [(16, 9, 3, False), (32, 7, 6, False),
+                                           (16, 1, 2, False), (32, 40, 5, False),
+                                           (16, 5, 11, False), (16, 9, 3, True),
+                                           (32, 40, 5, True), (32, 7, 10, True)])
+def test_fp32_refined_build_against_fp64_and_oracle(W, L, nE, sweeps):
+    # FP32 block products (and, with sweeps, FP32 RGF sweeps) plus one FP64 refinement step:
+    # |G|^2, the exit weights, the diagonal blocks and A_jj, the corners (through the lead
+    # terms) and T_eff back at FP64 accuracy (1e-10 of the FP64 build and of the oracle);
+    # nE = 10, 11 take more energies than one refinement pass holds (8)
     c = case(W=W, L=L, eta=0.05, disorder=0.3, nE=nE, emin=-2.7, emax=2.2, seed=W + L)
     k64 = gpu_build(c)
-    sr = M.make_system(W, L, 1.0, 0, 0.0, 1e-10, M.BUILD_FP32_PRODUCTS | M.BUILD_FP32_REFINE)
+    flags = M.BUILD_FP32_PRODUCTS | M.BUILD_FP32_REFINE | (M.BUILD_FP32_SWEEPS if sweeps else 0)
+    sr = M.make_system(W, L, 1.0, 0, 0.0, 1e-10, flags)
     s32 = M.make_system(W, L, 1.0, 0, 0.0, 1e-10, M.BUILD_FP32_PRODUCTS)
     assert M.mc_negf_workspace_bytes(sr, nE) > M.mc_negf_workspace_bytes(s32, nE)
     ws = M.allocate_workspace(sr, nE)
@@ -579,7 +584,7 @@ def test_fp32_refined_build_against_fp64_and_oracle(W, L, nE):
     P64, Pr = k64.P().cpu().numpy(), kr.P().cpu().numpy()
     scale = np.abs(P64).max(axis=2, keepdims=True)
     assert (np.abs(Pr - P64) / scale).max() < 1e-10
-    for f in ("wL", "wR"):
+    for f in ("wL", "wR", "Adiag", "Gd"):
         assert rel(getattr(kr, f)().cpu().numpy(), getattr(k64, f)().cpu().numpy()) < 1e-10, f
     lr, l64 = kr.lead().cpu().numpy(), k64.lead().cpu().numpy()
     for slot in (M.LEAD_TLL, M.LEAD_TRL, M.LEAD_TLR, M.LEAD_TRR):
@@ -595,14 +600,16 @@ def test_fp32_refined_build_against_fp64_and_oracle(W, L, nE):
     assert abs(I - D.current(sols, c["w"])) <= 1e-10 * abs(I)
 
 
-@pytest.mark.parametrize("W,L", [(16, 9), (32, 7)])
-def test_fp32_products_build_against_fp64_and_oracle(W, L):
-    # the full inverse's block products in FP32: |G|^2, the exit weights and T_eff carry FP32
-    # rounding only (well within 1e-5 relative at these lengths); the tables still sample
-    # within the walker's statistics
+@pytest.mark.parametrize("W,L,sweeps", [(16, 9, False), (32, 7, False), (16, 9, True),
+                                        (32, 7, True)])
+def test_fp32_products_build_against_fp64_and_oracle(W, L, sweeps):
+    # the full inverse's block products (and, with sweeps, the RGF sweeps) in FP32: |G|^2, the
+    # exit weights and T_eff carry FP32 rounding only (well within 1e-5 relative at these
+    # lengths); the tables still sample within the walker's statistics
     c = case(W=W, L=L, eta=0.05, disorder=0.3, nE=3, emin=-2.7, emax=2.2, seed=W + L)
     k64 = gpu_build(c)
-    s32 = M.make_system(W, L, 1.0, 0, 0.0, 1e-10, M.BUILD_FP32_PRODUCTS)
+    flags = M.BUILD_FP32_PRODUCTS | (M.BUILD_FP32_SWEEPS if sweeps else 0)
+    s32 = M.make_system(W, L, 1.0, 0, 0.0, 1e-10, flags)
     ws = M.allocate_workspace(s32, len(c["E"]))
     V = torch.tensor(c["V"], dtype=torch.float64, device=DEV)
     g = torch.tensor(c["g"], dtype=torch.float64, device=DEV)
