@@ -370,6 +370,56 @@ int32_t mc_negf_current_interp(const mcnegf_kernel* k, const double* d_fine_ener
                                double* h_I_sigma, hipStream_t stream);
 
 /*
+ * Importance-sampled walks (Sec. V A, "Improved estimator": step-6' probabilities p replaced
+ * by other probabilities p', the estimator of Eq. (66) weighted by p / p' along the path).
+ * For a bias b over the n_out outcomes of each energy,
+ *   p'_ij = p_ij b_j / rho_i,   rho_i = sum_j p_ij b_j,
+ * so a step i -> j multiplies the path's likelihood ratio by rho_i / b_j.  A walk injected at
+ * lead p that exits at the other lead q scores c_p times the product of its ratios, any other
+ * walk scores 0.  The mean is T_qp whenever b is finite and non-negative, positive at q and at
+ * every probe a walk to q can pass through; b = P(exit at q | state) gives zero variance, and
+ * b = 1 is the plain walk.  A poor b can make the variance infinite (the sample variance then
+ * understates the error).
+ *
+ * mc_negf_weighted_tables_bytes (host only): device bytes of the modified tables of kernel k.
+ * mc_negf_weighted_tables: from the kernel k (built with alias tables) and d_bias [nE][n_out]
+ *   (device, FP64), writes into d_tables (caller-owned device memory of >= that size, 256-byte
+ *   aligned) the alias tables of the modified rows in the kernel's format - packed entries
+ *   [nE][n_out][alias_pitch] (uint32), then the low threshold bits (uint16, same shape), then
+ *   rho [nE][n_out] (FP64), each part starting at a multiple of 256 bytes.  A negative or
+ *   non-finite bias entry sets MCNEGF_FLAG_NONFINITE.  Asynchronous.
+ * mc_negf_walk_weighted_bytes (host only): device scratch bytes mc_negf_walk_weighted needs for
+ *   n_walkers walkers per energy (16 bytes per energy per 2048 walkers).
+ * mc_negf_walk_weighted: walkers [walker_begin, walker_begin + n_walkers) (< 2^32) at every
+ *   energy, drawing exactly as mc_negf_walk does, on the modified tables d_tables (as written
+ *   above, tables_bytes their size) with the same d_bias; adds their exit counts to d_tallies
+ *   [nE][MCNEGF_TALLY_N] (int64, as mc_negf_walk) and to d_wsum [nE][2] (FP64) the sum of the
+ *   scores / c_p and the sum of their squares.  The sums for a given walker range do not
+ *   depend on scheduling.  d_scratch: caller-owned, 256-byte aligned, >=
+ *   mc_negf_walk_weighted_bytes.  Asynchronous.
+ * mc_negf_current_weighted: per energy, with N_k walkers and score sums S1, S2 (without c_p),
+ *   T_k = c_p S1 / N_k and sigma_k = c_p sqrt(s^2 / N_k), s^2 = (S2 - S1^2 / N_k) / (N_k - 1);
+ *   I and sigma_I as mc_negf_current.  Synchronises `stream`; status as mc_negf_current in
+ *   MC mode.
+ * All four: MCNEGF_EINVAL for a bad handle or argument, MCNEGF_EWS for a short or misaligned
+ * buffer, MCNEGF_EHIP if a launch fails.
+ */
+int32_t mc_negf_weighted_tables_bytes(const mcnegf_kernel* k, uint64_t* bytes_out);
+int32_t mc_negf_weighted_tables(const mcnegf_kernel* k, const double* d_bias, void* d_tables,
+                                uint64_t tables_bytes, hipStream_t stream);
+int32_t mc_negf_walk_weighted_bytes(const mcnegf_kernel* k, uint64_t n_walkers,
+                                    uint64_t* bytes_out);
+int32_t mc_negf_walk_weighted(const mcnegf_kernel* k, const void* d_tables, uint64_t tables_bytes,
+                              const double* d_bias, uint64_t seed, uint32_t realization,
+                              uint32_t inject_lead, uint64_t walker_begin, uint64_t n_walkers,
+                              uint32_t max_steps, int64_t* d_tallies, double* d_wsum,
+                              void* d_scratch, uint64_t scratch_bytes, hipStream_t stream);
+int32_t mc_negf_current_weighted(const mcnegf_kernel* k, uint32_t inject_lead,
+                                 const int64_t* d_tallies, const double* d_wsum,
+                                 const double* d_weights, double* d_T, double* d_sigmaT,
+                                 double* h_I_sigma, hipStream_t stream);
+
+/*
  * Like mc_negf_current, but asynchronous and capturable in a HIP graph: I and the standard
  * error go to d_I_sigma ([2] device) instead of the host, nothing is synchronised and the
  * status word is left for mc_negf_status to read.  Same argument rules and errors

@@ -203,6 +203,11 @@ struct AliasArgs {
     int N, W;
     double open_cut;  // an injection row needs Tr Gamma_p > open_cut
     double rowsum_tol;  // relative tolerance of the row-total check
+    // Modified rows (importance-sampled walks): outcome i of every row of energy e weighs
+    // bias[e * n + i] times its kernel weight, and rho[e * n + row] receives the ratio of the
+    // modified row's total to the unmodified one (0 for a row of total 0).
+    const double* bias;
+    double* rho;
 };
 
 // Weight of outcome i in kernel row `row` at energy e (probe rows: gamma_i |G_row,i|^2 and the
@@ -232,7 +237,10 @@ __device__ inline double kernel_weight(const AliasArgs& a, int e, int row, int i
 // threads search: the light starts and heavy ends in one array of n + 1 doubles (lights from
 // the front with the total deficit after the last one, heavies from the back: heavy m at
 // n - m) and the heavy items' indices (16 bits): 10 n bytes per row.
-template <int BT, int KM>
+// With kBias the row is the modified one of an importance-sampled walk (outcome i weighs
+// b_i K_row,i), written to the caller's tables; the lead terms and the row-total checks of
+// the build are left alone, and rho = modified total / unmodified total is stored per row.
+template <int BT, int KM, bool kBias = false>
 __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
     constexpr bool kLong = KM > 8;  // rows above BT * 8 outcomes
     extern __shared__ double smem[];
@@ -254,26 +262,42 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
     const double* lead = a.lead + (size_t)e * MCNEGF_LEAD_NTERMS;
     // 1. weights of this row (items beyond n weigh 0 and are skipped below)
     double w[KM];
+    double part0 = 0.0;  // (kBias) the unmodified row's part, in the order of part below
+    bool bad_bias = false;
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
         const int i = tid + BT * k;
-        w[k] = i < n ? kernel_weight(a, e, row, i) : 0.0;
+        double v = i < n ? kernel_weight(a, e, row, i) : 0.0;
+        if constexpr (kBias) {
+            const double b = i < n ? a.bias[(size_t)e * n + i] : 0.0;
+            bad_bias |= !(b >= 0.0 && b <= 1.7976931348623157e308);
+            part0 += v;
+            v *= b;
+        }
+        w[k] = v;
     }
     // 2. total (fixed order: by thread, then by item)
     double part = 0.0;
 #pragma unroll
     for (int k = 0; k < KM; ++k) part += w[k];
     double total = block_sum<BT>(part, sd);
+    double total0 = kBias ? block_sum<BT>(part0, sd) : total;
     if (row >= N) {
         // no open channel in this lead (outside its band, Gamma only from the regulator)
         double trg = 0.0;
         for (int y = 0; y < a.W; ++y) trg += a.gam_lead[((size_t)e * a.W + y) * a.W + y];
-        if (!(trg > a.open_cut)) total = 0.0;
+        if (!(trg > a.open_cut)) total = total0 = 0.0;
     }
 
     uint32_t* out = a.alias + ((size_t)e * n + row) * a.pitch;
     uint16_t* out_lo = a.alias_lo + ((size_t)e * n + row) * a.pitch;
-    if (tid == 0) {
+    if constexpr (kBias) {
+        if (tid == 0) {
+            a.rho[(size_t)e * n + row] = total0 > 0.0 ? total / total0 : 0.0;
+            if (!isfinite(total)) atomicOr(a.status, MCNEGF_FLAG_NONFINITE);
+        }
+        if (bad_bias) atomicOr(a.status, MCNEGF_FLAG_NONFINITE);
+    } else if (tid == 0) {
         double ref;
         if (row < N) ref = a.Adiag[(size_t)e * N + row];
         else ref = lead[row == N ? MCNEGF_LEAD_TRGLA : MCNEGF_LEAD_TRGRA];
@@ -567,6 +591,8 @@ static AliasArgs alias_args(const mcnegf_kernel& k, double rowsum_tol) {
     a.W = k.W;
     a.open_cut = 1e3 * k.delta_lead * k.t * k.W;
     a.rowsum_tol = rowsum_tol;
+    a.bias = nullptr;
+    a.rho = nullptr;
     return a;
 }
 
@@ -589,18 +615,21 @@ hipError_t launch_interp_distances(const mcnegf_kernel& k, double* dist, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_alias_build(const mcnegf_kernel& k, double rowsum_tol, hipStream_t s) {
-    const AliasArgs a = alias_args(k, rowsum_tol);
+// Alias tables of every row of every energy from the arguments a (the kernel's own tables,
+// or with kBias the modified rows into the caller's tables).
+template <bool kBias>
+static hipError_t launch_alias_rows(const mcnegf_kernel& k, const AliasArgs& a,
+                                    const char* name, hipStream_t s) {
     const int n = k.n_out;
     const size_t lds = (size_t)(n + 1) * 8 + (size_t)n * 2;
     // rows up to 1024 outcomes: 256 threads x 4 items; up to 1536: 256 x 6; up to 4096:
     // 512 x 8; up to 8192: 512 x 16; longer rows (n <= kMaxOut): 512 x 32
     const int shape = n <= 256 * 4 ? 0 : n <= 256 * 6 ? 1 : n <= 512 * 8 ? 2 : n <= 512 * 16 ? 3 : 4;
-    const void* fns[5] = {(const void*)alias_build_kernel<256, 4>,
-                          (const void*)alias_build_kernel<256, 6>,
-                          (const void*)alias_build_kernel<512, 8>,
-                          (const void*)alias_build_kernel<512, 16>,
-                          (const void*)alias_build_kernel<512, 32>};
+    const void* fns[5] = {(const void*)alias_build_kernel<256, 4, kBias>,
+                          (const void*)alias_build_kernel<256, 6, kBias>,
+                          (const void*)alias_build_kernel<512, 8, kBias>,
+                          (const void*)alias_build_kernel<512, 16, kBias>,
+                          (const void*)alias_build_kernel<512, 32, kBias>};
     const int bts[5] = {256, 256, 512, 512, 512};
     if (lds > 65536) {
         // rows beyond 6.5k outcomes need more than 64 KB of LDS per workgroup (gfx950: 160 KB)
@@ -622,17 +651,31 @@ hipError_t launch_alias_build(const mcnegf_kernel& k, double rowsum_tol, hipStre
         if (err != hipSuccess) return err;
     }
     {
-        MCNEGF_TIMED("alias_build_kernel", s);
+        MCNEGF_TIMED(name, s);
         const dim3 grid(n, k.nE), block(bts[shape]);
         switch (shape) {
-            case 0: hipLaunchKernelGGL((alias_build_kernel<256, 4>), grid, block, lds, s, a); break;
-            case 1: hipLaunchKernelGGL((alias_build_kernel<256, 6>), grid, block, lds, s, a); break;
-            case 2: hipLaunchKernelGGL((alias_build_kernel<512, 8>), grid, block, lds, s, a); break;
-            case 3: hipLaunchKernelGGL((alias_build_kernel<512, 16>), grid, block, lds, s, a); break;
-            default: hipLaunchKernelGGL((alias_build_kernel<512, 32>), grid, block, lds, s, a); break;
+            case 0: hipLaunchKernelGGL((alias_build_kernel<256, 4, kBias>), grid, block, lds, s, a); break;
+            case 1: hipLaunchKernelGGL((alias_build_kernel<256, 6, kBias>), grid, block, lds, s, a); break;
+            case 2: hipLaunchKernelGGL((alias_build_kernel<512, 8, kBias>), grid, block, lds, s, a); break;
+            case 3: hipLaunchKernelGGL((alias_build_kernel<512, 16, kBias>), grid, block, lds, s, a); break;
+            default: hipLaunchKernelGGL((alias_build_kernel<512, 32, kBias>), grid, block, lds, s, a); break;
         }
     }
     return hipGetLastError();
+}
+
+hipError_t launch_alias_build(const mcnegf_kernel& k, double rowsum_tol, hipStream_t s) {
+    return launch_alias_rows<false>(k, alias_args(k, rowsum_tol), "alias_build_kernel", s);
+}
+
+hipError_t launch_alias_bias(const mcnegf_kernel& k, const double* bias, uint32_t* tables,
+                             uint16_t* lows, double* rho, hipStream_t s) {
+    AliasArgs a = alias_args(k, 0.0);
+    a.alias = tables;
+    a.alias_lo = lows;
+    a.bias = bias;
+    a.rho = rho;
+    return launch_alias_rows<true>(k, a, "alias_bias_kernel", s);
 }
 
 }  // namespace mcnegf

@@ -158,6 +158,20 @@ hipError_t launch_fullinv_store_g(const mcnegf_kernel& k, double2* Gc, int64_t l
 hipError_t launch_lead_terms(const mcnegf_kernel& k, hipStream_t s);
 // rowsum_tol: relative tolerance of the check of each row's total against its spectral value
 hipError_t launch_alias_build(const mcnegf_kernel& k, double rowsum_tol, hipStream_t s);
+// Importance-sampled walks: alias tables of the modified rows K_ij b_j into the caller's
+// tables and rho (per row: modified total / unmodified total); the walks; their estimator.
+hipError_t launch_alias_bias(const mcnegf_kernel& k, const double* bias, uint32_t* tables,
+                             uint16_t* lows, double* rho, hipStream_t s);
+uint64_t weighted_scratch_bytes(int nE, uint64_t n_walkers);
+hipError_t launch_walk_weighted(const mcnegf_kernel& k, const uint32_t* tables,
+                                const uint16_t* lows, const double* rho, const double* bias,
+                                uint64_t seed, uint32_t tag, uint32_t walker_begin,
+                                uint32_t n_walkers, uint32_t max_steps, int64_t* tallies,
+                                double* wsum, double* partial, hipStream_t s);
+hipError_t launch_weighted_current(const mcnegf_kernel& k, uint32_t inject_lead,
+                                   const int64_t* tallies, const double* wsum,
+                                   const double* weights, double* T, double* sigmaT,
+                                   hipStream_t s);
 hipError_t launch_walk(const mcnegf_kernel& k, uint64_t seed, uint32_t tag,
                        uint32_t walker_begin, uint32_t n_walkers, uint32_t max_steps,
                        int64_t* tallies, hipStream_t s);

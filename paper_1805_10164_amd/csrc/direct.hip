@@ -88,6 +88,51 @@ hipError_t launch_mc_current(const mcnegf_kernel& k, uint32_t inject_lead, const
     return hipGetLastError();
 }
 
+// Importance-sampled walks (Sec. V A, "Improved estimator"): per energy the N_k walkers'
+// scores (path likelihood ratios at an exit at q, else 0) have sums S1, S2; then
+//   T_k = c_p S1 / N_k,  sigma_k = c_p sqrt(s^2 / N_k),  s^2 = (S2 - S1^2 / N_k) / (N_k - 1).
+__global__ void weighted_current_kernel(const int64_t* __restrict__ tallies,
+                                        const double* __restrict__ wsum,
+                                        const double* __restrict__ lead, int nE,
+                                        uint32_t inject_lead, double* __restrict__ T,
+                                        double* __restrict__ sig) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nE) return;
+    const int64_t* t = tallies + (size_t)k * MCNEGF_TALLY_N;
+    const double walkers =
+        (double)(t[MCNEGF_TALLY_EXIT_L] + t[MCNEGF_TALLY_EXIT_R] + t[MCNEGF_TALLY_TRUNC]);
+    const double c = lead[(size_t)k * MCNEGF_LEAD_NTERMS +
+                          (inject_lead == 0 ? MCNEGF_LEAD_CL : MCNEGF_LEAD_CR)];
+    if (walkers <= 0.0) {
+        T[k] = 0.0;
+        sig[k] = 0.0;
+        return;
+    }
+    const double s1 = wsum[2 * (size_t)k], s2 = wsum[2 * (size_t)k + 1];
+    T[k] = c * s1 / walkers;
+    const double var = walkers > 1.0 ? fmax(s2 - s1 * s1 / walkers, 0.0) / (walkers - 1.0) : 0.0;
+    sig[k] = c * sqrt(var / walkers);
+}
+
+hipError_t launch_weighted_current(const mcnegf_kernel& k, uint32_t inject_lead,
+                                   const int64_t* tallies, const double* wsum,
+                                   const double* weights, double* T, double* sigmaT,
+                                   hipStream_t s) {
+    {
+        MCNEGF_TIMED("weighted_current_kernel", s);
+        hipLaunchKernelGGL(weighted_current_kernel, dim3((k.nE + 255) / 256), dim3(256), 0, s,
+                           tallies, wsum, k.lead, k.nE, inject_lead, T, sigmaT);
+    }
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    {
+        MCNEGF_TIMED("current_sum_kernel", s);
+        hipLaunchKernelGGL(current_sum_kernel, dim3(1), dim3(256), 0, s, T, sigmaT, weights, k.nE,
+                           k.reduce);
+    }
+    return hipGetLastError();
+}
+
 // Interpolated walks (Sec. V A, "Interpolation"): fine energy f between the built energies
 // E_lo and E_hi with mixture weight alpha = a32 / 2^32 (the one its walks used); the row total
 // that scales the estimator is interpolated like the rows, c = (1 - alpha) c_lo + alpha c_hi,

@@ -566,6 +566,103 @@ int32_t mc_negf_current_interp(const mcnegf_kernel* k, const double* d_fine_ener
     return status_to_code(flags, true);
 }
 
+// ---- importance-sampled walks (Sec. V A, "Improved estimator") ------------------------
+
+struct WeightedTables {
+    uint64_t off_lo, off_rho, bytes;
+};
+
+static WeightedTables weighted_tables_layout(const mcnegf_kernel& k) {
+    WeightedTables t;
+    const uint64_t entries = (uint64_t)k.nE * (uint64_t)k.n_out * (uint64_t)k.alias_pitch;
+    t.off_lo = align256(entries * 4);
+    t.off_rho = t.off_lo + align256(entries * 2);
+    t.bytes = t.off_rho + align256((uint64_t)k.nE * (uint64_t)k.n_out * 8);
+    return t;
+}
+
+static bool valid_weighted_kernel(const mcnegf_kernel* k) {
+    return valid_kernel(k) && k->alias && k->alias_lo && k->alias_pitch >= k->n_out;
+}
+
+int32_t mc_negf_weighted_tables_bytes(const mcnegf_kernel* k, uint64_t* bytes_out) {
+    if (!valid_weighted_kernel(k) || !bytes_out) return MCNEGF_EINVAL;
+    *bytes_out = weighted_tables_layout(*k).bytes;
+    return MCNEGF_OK;
+}
+
+int32_t mc_negf_weighted_tables(const mcnegf_kernel* k, const double* d_bias, void* d_tables,
+                                uint64_t tables_bytes, hipStream_t stream) {
+    if (!valid_weighted_kernel(k) || !d_bias || !d_tables) return MCNEGF_EINVAL;
+    const WeightedTables t = weighted_tables_layout(*k);
+    if (((uintptr_t)d_tables & 255u) != 0 || tables_bytes < t.bytes) return MCNEGF_EWS;
+    char* base = static_cast<char*>(d_tables);
+    hipError_t err = launch_alias_bias(*k, d_bias, reinterpret_cast<uint32_t*>(base),
+                                       reinterpret_cast<uint16_t*>(base + t.off_lo),
+                                       reinterpret_cast<double*>(base + t.off_rho), stream);
+    return err == hipSuccess ? MCNEGF_OK : hip_fail(err);
+}
+
+int32_t mc_negf_walk_weighted_bytes(const mcnegf_kernel* k, uint64_t n_walkers,
+                                    uint64_t* bytes_out) {
+    if (!valid_weighted_kernel(k) || !bytes_out || n_walkers >= 0x100000000ull)
+        return MCNEGF_EINVAL;
+    *bytes_out = weighted_scratch_bytes(k->nE, n_walkers);
+    return MCNEGF_OK;
+}
+
+int32_t mc_negf_walk_weighted(const mcnegf_kernel* k, const void* d_tables, uint64_t tables_bytes,
+                              const double* d_bias, uint64_t seed, uint32_t realization,
+                              uint32_t inject_lead, uint64_t walker_begin, uint64_t n_walkers,
+                              uint32_t max_steps, int64_t* d_tallies, double* d_wsum,
+                              void* d_scratch, uint64_t scratch_bytes, hipStream_t stream) {
+    if (!valid_weighted_kernel(k) || !d_tables || !d_bias || !d_tallies || !d_wsum ||
+        !d_scratch || inject_lead > 1 || realization >= (1u << 30) || max_steps < 1)
+        return MCNEGF_EINVAL;
+    if (walker_begin >= 0x100000000ull || n_walkers >= 0x100000000ull ||
+        walker_begin + n_walkers >= 0x100000000ull)
+        return MCNEGF_EINVAL;
+    const WeightedTables t = weighted_tables_layout(*k);
+    if (((uintptr_t)d_tables & 255u) != 0 || tables_bytes < t.bytes) return MCNEGF_EWS;
+    if (((uintptr_t)d_scratch & 255u) != 0 ||
+        scratch_bytes < weighted_scratch_bytes(k->nE, n_walkers))
+        return MCNEGF_EWS;
+    if (n_walkers == 0) return MCNEGF_OK;
+    const char* base = static_cast<const char*>(d_tables);
+    const uint32_t tag = (realization << 1) | inject_lead;
+    hipError_t err = launch_walk_weighted(
+        *k, reinterpret_cast<const uint32_t*>(base),
+        reinterpret_cast<const uint16_t*>(base + t.off_lo),
+        reinterpret_cast<const double*>(base + t.off_rho), d_bias, seed, tag,
+        (uint32_t)walker_begin, (uint32_t)n_walkers, max_steps, d_tallies, d_wsum,
+        static_cast<double*>(d_scratch), stream);
+    return err == hipSuccess ? MCNEGF_OK : hip_fail(err);
+}
+
+int32_t mc_negf_current_weighted(const mcnegf_kernel* k, uint32_t inject_lead,
+                                 const int64_t* d_tallies, const double* d_wsum,
+                                 const double* d_weights, double* d_T, double* d_sigmaT,
+                                 double* h_I_sigma, hipStream_t stream) {
+    if (!valid_kernel(k) || !d_tallies || !d_wsum || !d_weights || !d_T || !d_sigmaT ||
+        !h_I_sigma || inject_lead > 1)
+        return MCNEGF_EINVAL;
+    hipError_t err = launch_weighted_current(*k, inject_lead, d_tallies, d_wsum, d_weights, d_T,
+                                             d_sigmaT, stream);
+    if (err != hipSuccess) return hip_fail(err);
+    double host[2];
+    uint32_t flags = 0;
+    if ((err = hipMemcpyAsync(host, k->reduce, sizeof(host), hipMemcpyDeviceToHost, stream)) !=
+        hipSuccess)
+        return hip_fail(err);
+    if ((err = hipMemcpyAsync(&flags, k->status, sizeof(flags), hipMemcpyDeviceToHost, stream)) !=
+        hipSuccess)
+        return hip_fail(err);
+    if ((err = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(err);
+    h_I_sigma[0] = host[0];
+    h_I_sigma[1] = std::sqrt(host[1] > 0.0 ? host[1] : 0.0);
+    return status_to_code(flags, true);
+}
+
 static bool batch_units(const mcnegf_kernel* kernels, int32_t n, uint64_t* units) {
     if (!kernels || n < 1) return false;
     uint64_t u = 0;

@@ -1251,4 +1251,244 @@ hipError_t launch_walk_sampled(const mcnegf_kernel& k, const SampledScratch& sc,
                              seed, max_steps, s);
 }
 
+// ---- importance-sampled walks (Sec. V A, "Improved estimator") ------------------------
+//
+// The tables sample the modified rows p'_ij = p_ij b_j / rho_i (rho_i = sum_j p_ij b_j) and
+// each walker carries the likelihood ratio of its path, the product of p_ij / p'_ij =
+// rho_i / b_j over its steps i -> j; a walk that exits at the collecting lead q scores that
+// product (the estimator's c_p is applied by the current), any other walk scores 0.  The
+// draws are those of mc_negf_walk (same counters), so the paths are the plain walker's paths
+// on these tables.
+//
+// Work layout: energy e belongs to group e % groups (one group per XCD with 8 groups, so an
+// energy's tables stay in one L2); every wavefront walks one chunk of kWeightedChunk
+// consecutive walkers of one energy, its K slots per lane refilling from the chunk in ballot
+// order.  That assignment, and with it every sum below, depends only on the walks, not on
+// scheduling: counts go to the tallies as integers; each chunk's two score sums (per lane,
+// then a fixed butterfly across the wavefront) go to partial[e][chunk] and are added per
+// energy in chunk order by weighted_reduce_kernel.
+struct WeightedArgs {
+    WalkArgs w;                  // tables of the modified rows; stage_inject = 0
+    const double* rho;           // [nE][n_out]
+    const double* bias;          // [nE][n_out]
+    double* partial;             // [nE][chunks][2]
+    uint32_t chunks;             // chunks per energy
+    uint32_t blocks_per_energy;  // workgroups of 4 wavefronts per energy
+};
+
+constexpr uint32_t kWeightedChunk = 2048;
+constexpr int kWeightedSlots = 2;
+
+template <int K>
+__device__ inline void weighted_steps(Step (&st)[K], const gtable_ptr (&tb)[K],
+                                      const uint32_t (&w)[K], const uint32_t (&el)[K],
+                                      const uint32_t (&lq)[K], const uint32_t (&a)[K],
+                                      const uint32_t (&b)[K], double (&ratio)[K],
+                                      const double* rho, const double* bias, uint32_t q,
+                                      const WalkArgs& A) {
+    uint32_t from[K];
+    bool was[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        from[k] = st[k].s;
+        was[k] = st[k].active;
+    }
+    walk_steps<K>(st, tb, w, el, lq, nullptr, a, b, A);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const uint32_t to = st[k].s;
+        // divergent: loads and arithmetic only
+        if (was[k] && (to < A.N || to == q)) ratio[k] *= rho[from[k]] / bias[to];
+    }
+}
+
+template <int K>
+__global__ void __launch_bounds__(256) walk_weighted_kernel(WeightedArgs A) {
+    const WalkArgs& W = A.w;
+    const uint32_t G = W.groups;
+    const uint32_t grp = blockIdx.x % G, j = blockIdx.x / G;
+    const uint32_t e = grp + G * (j / A.blocks_per_energy);
+    const uint32_t cid = (j % A.blocks_per_energy) * 4 + (threadIdx.x >> 6);
+    if (e >= W.nE || cid >= A.chunks) return;  // whole wavefronts; the kernel has no barrier
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t N = W.N, n_out = W.n_out;
+    const uint32_t inject_row = N + (W.tag & 1u);
+    const uint32_t q = N + 1u - (W.tag & 1u);
+    const double* rho = A.rho + (size_t)e * n_out;
+    const double* bias = A.bias + (size_t)e * n_out;
+    uint32_t next = W.wbegin + cid * W.chunk;
+    const uint32_t wend = (uint32_t)min((uint64_t)next + W.chunk, (uint64_t)W.wend);
+
+    Step st[K];
+    uint32_t w[K], el[K], lq[K];
+    gtable_ptr tb[K];
+    double ratio[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        st[k] = Step{inject_row, 0u, false};
+        w[k] = lq[k] = 0u;
+        el[k] = e;
+        tb[k] = (gtable_ptr)(W.tables + (size_t)e * W.table_stride);
+        ratio[k] = 1.0;
+    }
+    uint32_t cL = 0, cR = 0, tr = 0;
+    uint64_t s1 = 0, s2 = 0;
+    double sx = 0.0, sx2 = 0.0;
+    // a walk that ended in slot k (done: not counted yet) scores its ratio at an exit at q
+    auto finish = [&](bool done, const Step& s, double r) {
+        count_ended_lane(cL, cR, tr, s1, s2, done, s, N);
+        const double v = (done && s.s == q) ? r : 0.0;
+        sx += v;
+        sx2 += v * v;
+    };
+    for (;;) {
+        if (next < wend) {  // uniform
+            uint64_t need[K];
+            uint32_t tot = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                need[k] = __ballot(!st[k].active);
+                tot += __popcll(need[k]);
+            }
+            const uint32_t avail = wend - next;
+            uint32_t base = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const uint32_t before = base + __popcll(need[k] & lt_mask);
+                const bool take = !st[k].active && before < avail;
+                finish(take && st[k].n != 0u, st[k], ratio[k]);
+                w[k] = take ? next + before : w[k];
+                st[k].s = take ? inject_row : st[k].s;
+                st[k].n = take ? 0u : st[k].n;
+                st[k].active = st[k].active || take;
+                ratio[k] = take ? 1.0 : ratio[k];
+                base += __popcll(need[k]);
+            }
+            next += tot < avail ? tot : avail;
+        }
+        uint64_t any = 0ull;
+#pragma unroll
+        for (int k = 0; k < K; ++k) any |= __ballot(st[k].active);
+        if (any == 0ull) break;
+        uint32_t a0[K], b0[K], a1[K], b1[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const Philox4 x =
+                philox4x32_10(st[k].n >> 1, w[k], W.e_off + e, W.tag, W.key0, W.key1);
+            a0[k] = x.x[0];
+            b0[k] = x.x[1];
+            a1[k] = x.x[2];
+            b1[k] = x.x[3];
+        }
+        weighted_steps<K>(st, tb, w, el, lq, a0, b0, ratio, rho, bias, q, W);
+        weighted_steps<K>(st, tb, w, el, lq, a1, b1, ratio, rho, bias, q, W);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) finish(st[k].n != 0u, st[k], ratio[k]);
+    // wavefront totals by a fixed butterfly (every lane ends with the same bits)
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        sx += __shfl_xor(sx, o, 64);
+        sx2 += __shfl_xor(sx2, o, 64);
+        cL += __shfl_xor(cL, o, 64);
+        cR += __shfl_xor(cR, o, 64);
+        tr += __shfl_xor(tr, o, 64);
+        s1 += __shfl_xor(s1, o, 64);
+        s2 += __shfl_xor(s2, o, 64);
+    }
+    if (lane == 0) {
+        unsigned long long* t =
+            reinterpret_cast<unsigned long long*>(W.tallies + (size_t)e * MCNEGF_TALLY_N);
+        if (cL) atomicAdd(t + MCNEGF_TALLY_EXIT_L, (unsigned long long)cL);
+        if (cR) atomicAdd(t + MCNEGF_TALLY_EXIT_R, (unsigned long long)cR);
+        if (tr) atomicAdd(t + MCNEGF_TALLY_TRUNC, (unsigned long long)tr);
+        if (s1) atomicAdd(t + MCNEGF_TALLY_STEPS, (unsigned long long)s1);
+        if (s2) atomicAdd(t + MCNEGF_TALLY_STEPS2, (unsigned long long)s2);
+        double* pp = A.partial + ((size_t)e * A.chunks + cid) * 2;
+        pp[0] = sx;
+        pp[1] = sx2;
+        if (tr) atomicOr(W.status, MCNEGF_FLAG_TRUNC);
+    }
+}
+
+// wsum[e] += the chunk partials of energy e, in chunk order (lane-strided sums, then a fixed
+// butterfly).
+__global__ void __launch_bounds__(64) weighted_reduce_kernel(const double* __restrict__ partial,
+                                                             uint32_t chunks,
+                                                             double* __restrict__ wsum) {
+    const uint32_t e = blockIdx.x;
+    const int lane = threadIdx.x;
+    double a = 0.0, b = 0.0;
+    for (uint32_t c = lane; c < chunks; c += 64) {
+        a += partial[((size_t)e * chunks + c) * 2];
+        b += partial[((size_t)e * chunks + c) * 2 + 1];
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+    }
+    if (lane == 0) {
+        wsum[2 * (size_t)e] += a;
+        wsum[2 * (size_t)e + 1] += b;
+    }
+}
+
+uint64_t weighted_scratch_bytes(int nE, uint64_t n_walkers) {
+    const uint64_t chunks = (n_walkers + kWeightedChunk - 1) / kWeightedChunk;
+    return ((uint64_t)nE * chunks * 16 + 255) & ~uint64_t(255);
+}
+
+hipError_t launch_walk_weighted(const mcnegf_kernel& k, const uint32_t* tables,
+                                const uint16_t* lows, const double* rho, const double* bias,
+                                uint64_t seed, uint32_t tag, uint32_t walker_begin,
+                                uint32_t n_walkers, uint32_t max_steps, int64_t* tallies,
+                                double* wsum, double* partial, hipStream_t s) {
+    if (n_walkers == 0) return hipSuccess;
+    WeightedArgs A;
+    WalkArgs& W = A.w;
+    W.table_stride = (int64_t)k.n_out * k.alias_pitch;
+    W.tables = tables;
+    W.lows = lows;
+    W.pitch32 = (uint32_t)k.alias_pitch;
+    W.n_out = (uint32_t)k.n_out;
+    W.N = (uint32_t)k.N;
+    W.nE = (uint32_t)k.nE;
+    W.e_off = 0;
+    W.key0 = (uint32_t)(seed & 0xffffffffu);
+    W.key1 = (uint32_t)(seed >> 32);
+    W.tag = tag;
+    W.wbegin = walker_begin;
+    W.wend = walker_begin + n_walkers;
+    W.chunk = kWeightedChunk;
+    W.chunks_per_energy = (n_walkers + kWeightedChunk - 1) / kWeightedChunk;
+    W.groups = k.nE >= 8 ? 8u : 1u;
+    W.max_steps = max_steps;
+    W.stage_inject = 0u;
+    W.tallies = tallies;
+    W.status = k.status;
+    A.rho = rho;
+    A.bias = bias;
+    A.partial = partial;
+    A.chunks = W.chunks_per_energy;
+    A.blocks_per_energy = (A.chunks + 3) / 4;
+    const uint64_t per_group = ((uint64_t)k.nE + W.groups - 1) / W.groups;
+    const uint64_t blocks = per_group * W.groups * A.blocks_per_energy;
+    if (blocks >= (1ull << 31)) return hipErrorInvalidValue;
+    {
+        MCNEGF_TIMED("walk_weighted_kernel", s);
+        hipLaunchKernelGGL(walk_weighted_kernel<kWeightedSlots>, dim3((uint32_t)blocks),
+                           dim3(256), 0, s, A);
+    }
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    {
+        MCNEGF_TIMED("weighted_reduce_kernel", s);
+        hipLaunchKernelGGL(weighted_reduce_kernel, dim3(k.nE), dim3(64), 0, s, partial,
+                           A.chunks, wsum);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace mcnegf

@@ -31,6 +31,8 @@ EXPORTED = ("mc_negf_workspace_bytes", "mc_negf_build_kernel", "mc_negf_walk",
             "mc_negf_current_async", "mc_negf_walk_sampled_bytes", "mc_negf_walk_sampled",
             "mc_negf_walk_sampled_noalloc", "mc_negf_interp_distances", "mc_negf_interp_plan",
             "mc_negf_walk_interp", "mc_negf_current_interp",
+            "mc_negf_weighted_tables_bytes", "mc_negf_weighted_tables",
+            "mc_negf_walk_weighted_bytes", "mc_negf_walk_weighted", "mc_negf_current_weighted",
             "mc_negf_batch_bytes", "mc_negf_batch_prepare",
             "mc_negf_walk_batch", "mc_negf_walk_batch_autotune", "mc_negf_plan_waves",
             "mc_negf_graph_begin", "mc_negf_graph_end", "mc_negf_graph_launch",
@@ -124,6 +126,15 @@ def lib() -> ctypes.CDLL:
                                       u64, u32, vp, vp]
     L.mc_negf_current_interp.argtypes = [ctypes.POINTER(KernelStruct), vp, i32, u32, vp, vp, vp,
                                          vp, dp, vp]
+    L.mc_negf_weighted_tables_bytes.argtypes = [ctypes.POINTER(KernelStruct),
+                                                ctypes.POINTER(u64)]
+    L.mc_negf_weighted_tables.argtypes = [ctypes.POINTER(KernelStruct), vp, vp, u64, vp]
+    L.mc_negf_walk_weighted_bytes.argtypes = [ctypes.POINTER(KernelStruct), u64,
+                                              ctypes.POINTER(u64)]
+    L.mc_negf_walk_weighted.argtypes = [ctypes.POINTER(KernelStruct), vp, u64, vp, u64, u32, u32,
+                                        u64, u64, u32, vp, vp, vp, u64, vp]
+    L.mc_negf_current_weighted.argtypes = [ctypes.POINTER(KernelStruct), u32, vp, vp, vp, vp, vp,
+                                           dp, vp]
     L.mc_negf_batch_bytes.argtypes = [ctypes.POINTER(KernelStruct), i32, ctypes.POINTER(u64)]
     L.mc_negf_batch_prepare.argtypes = [ctypes.POINTER(KernelStruct), i32,
                                         ctypes.POINTER(u32), u32, ctypes.POINTER(vp), vp, u64,
@@ -530,6 +541,72 @@ def mc_negf_walk_sampled_noalloc(k: Kernel, seed: int, realization: int, inject_
                                               int(max_steps), _ptr(weights), _ptr(tallies),
                                               _stream(stream))
     return _check("mc_negf_walk_sampled_noalloc", code)
+
+
+# ---- importance-sampled walks ---------------------------------------------------------------
+
+def mc_negf_weighted_tables_bytes(k: Kernel) -> int:
+    out = ctypes.c_uint64(0)
+    _check("mc_negf_weighted_tables_bytes",
+           lib().mc_negf_weighted_tables_bytes(ctypes.byref(k.struct), ctypes.byref(out)))
+    return int(out.value)
+
+
+def mc_negf_weighted_tables(k: Kernel, bias, tables, stream=None) -> int:
+    """Alias tables of the modified rows K_ij b_j (bias [nE][n_out] device) and rho into the
+    byte tensor `tables` (mc_negf_weighted_tables_bytes long)."""
+    return _check("mc_negf_weighted_tables",
+                  lib().mc_negf_weighted_tables(ctypes.byref(k.struct), _ptr(bias), _ptr(tables),
+                                                int(tables.numel()), _stream(stream)))
+
+
+def weighted_tables_views(k: Kernel, tables):
+    """(packed [nE][n_out][pitch] int32, low bits uint16, rho [nE][n_out] float64) views of
+    a modified-tables buffer, in the layout the library writes."""
+    import torch
+    ent = k.nE * k.n_out * k.alias_pitch
+    a256 = lambda x: (x + 255) & ~255
+    off_lo = a256(ent * 4)
+    off_rho = off_lo + a256(ent * 2)
+    shape = (k.nE, k.n_out, k.alias_pitch)
+    packed = tables[:ent * 4].view(torch.int32).view(shape)
+    low = tables[off_lo:off_lo + ent * 2].view(torch.int16).view(shape)
+    rho = tables[off_rho:off_rho + k.nE * k.n_out * 8].view(torch.float64).view(k.nE, k.n_out)
+    return packed, low, rho
+
+
+def mc_negf_walk_weighted_bytes(k: Kernel, n_walkers: int) -> int:
+    out = ctypes.c_uint64(0)
+    _check("mc_negf_walk_weighted_bytes",
+           lib().mc_negf_walk_weighted_bytes(ctypes.byref(k.struct), int(n_walkers),
+                                             ctypes.byref(out)))
+    return int(out.value)
+
+
+def mc_negf_walk_weighted(k: Kernel, tables, bias, seed: int, realization: int,
+                          inject_lead: int, walker_begin: int, n_walkers: int, max_steps: int,
+                          tallies, wsum, scratch, stream=None) -> int:
+    """Importance-sampled walks on the modified tables; counts to tallies, score sums to
+    wsum [nE][2]."""
+    code = lib().mc_negf_walk_weighted(ctypes.byref(k.struct), _ptr(tables),
+                                       int(tables.numel()), _ptr(bias), int(seed),
+                                       int(realization), int(inject_lead), int(walker_begin),
+                                       int(n_walkers), int(max_steps), _ptr(tallies), _ptr(wsum),
+                                       _ptr(scratch), int(scratch.numel()), _stream(stream))
+    return _check("mc_negf_walk_weighted", code)
+
+
+def mc_negf_current_weighted(k: Kernel, inject_lead: int, tallies, wsum, weights, T, sigmaT,
+                             stream=None, allow=(OK, WTRUNC, WNUMERIC)):
+    """(status, I, sigma_I) of importance-sampled walks; synchronises the stream."""
+    out = (ctypes.c_double * 2)()
+    code = lib().mc_negf_current_weighted(ctypes.byref(k.struct), int(inject_lead),
+                                          _ptr(tallies), _ptr(wsum), _ptr(weights), _ptr(T),
+                                          _ptr(sigmaT),
+                                          ctypes.cast(out, ctypes.POINTER(ctypes.c_double)),
+                                          _stream(stream))
+    _check("mc_negf_current_weighted", code, allow)
+    return code, float(out[0]), float(out[1])
 
 
 # ---- interpolated step-6' probabilities -------------------------------------------------------

@@ -287,3 +287,45 @@ def test_interp_walk_validation_without_gpu():
     assert walk(p, 3, 1, 0, 0, 0, 10, 0, p, z) == M.EINVAL           # max_steps
     ks.nE = 1
     assert lib.mc_negf_interp_distances(ctypes.byref(ks), p, z) == M.EINVAL  # one energy
+
+
+def test_weighted_walk_sizes_and_validation_without_gpu():
+    # importance-sampled walks: buffer sizes from the handle alone, and every bad argument
+    # refused on the host
+    lib = M.lib()
+    ks = M.KernelStruct()
+    ks.W, ks.L, ks.N, ks.n_out, ks.nE, ks.p_pitch, ks.alias_pitch = 2, 3, 6, 8, 3, 16, 16
+    for f in ("alias", "alias_lo", "P", "lead", "status", "counters", "reduce"):
+        setattr(ks, f, 4096)
+    out = ctypes.c_uint64(0)
+    assert lib.mc_negf_weighted_tables_bytes(ctypes.byref(ks), ctypes.byref(out)) == M.OK
+    ent = 3 * 8 * 16
+    a256 = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    tb = a256(ent * 4) + a256(ent * 2) + a256(3 * 8 * 8)
+    assert out.value == tb
+    assert lib.mc_negf_walk_weighted_bytes(ctypes.byref(ks), 4096, ctypes.byref(out)) == M.OK
+    assert out.value == a256(3 * 2 * 16)  # two chunks of 2048 walkers per energy
+    assert lib.mc_negf_walk_weighted_bytes(ctypes.byref(ks), 1 << 32,
+                                           ctypes.byref(out)) == M.EINVAL
+    z = ctypes.c_void_p(0)
+    p = ctypes.c_void_p(4096)
+    big = 1 << 40
+    walk = lambda *a: lib.mc_negf_walk_weighted(ctypes.byref(ks), *a)  # noqa: E731
+    assert walk(z, tb, p, 1, 0, 0, 0, 10, 10, p, p, p, big, z) == M.EINVAL   # no tables
+    assert walk(p, tb, z, 1, 0, 0, 0, 10, 10, p, p, p, big, z) == M.EINVAL   # no bias
+    assert walk(p, tb, p, 1, 0, 2, 0, 10, 10, p, p, p, big, z) == M.EINVAL   # lead
+    assert walk(p, tb, p, 1, 1 << 30, 0, 0, 10, 10, p, p, p, big, z) == M.EINVAL  # realization
+    assert walk(p, tb, p, 1, 0, 0, 0, 10, 0, p, p, p, big, z) == M.EINVAL   # max_steps
+    assert walk(p, tb, p, 1, 0, 0, 5, (1 << 32) - 5, 10, p, p, p, big, z) == M.EINVAL  # range
+    assert walk(p, tb - 1, p, 1, 0, 0, 0, 10, 10, p, p, p, big, z) == M.EWS  # short tables
+    assert walk(p, tb, p, 1, 0, 0, 0, 10, 10, p, p, p, 16, z) == M.EWS      # short scratch
+    assert walk(ctypes.c_void_p(4096 + 8), tb, p, 1, 0, 0, 0, 10, 10, p, p, p, big,
+                z) == M.EWS                                                   # misaligned
+    assert lib.mc_negf_weighted_tables(ctypes.byref(ks), p, p, tb - 256, z) == M.EWS
+    assert lib.mc_negf_weighted_tables(ctypes.byref(ks), z, p, tb, z) == M.EINVAL
+    res = (ctypes.c_double * 2)()
+    assert lib.mc_negf_current_weighted(ctypes.byref(ks), 2, p, p, p, p, p,
+                                        ctypes.cast(res, ctypes.POINTER(ctypes.c_double)),
+                                        z) == M.EINVAL
+    ks.alias = 0  # a kernel built without alias tables
+    assert lib.mc_negf_weighted_tables_bytes(ctypes.byref(ks), ctypes.byref(out)) == M.EINVAL
