@@ -90,6 +90,7 @@ class Problem:
         self.ws = M.allocate_workspace(self.sys, wl.n_energies, dev)
         self.tal = torch.zeros((wl.n_energies, M.TALLY_N), dtype=torch.int64, device=dev)
         self.sampled_scratch = None  # energy-sampled walks (time-to-1%), allocated on first use
+        self.weighted = None  # importance-sampled walks (time-to-1%), allocated on first use
         self.T = torch.empty(wl.n_energies, dtype=torch.float64, device=dev)
         self.sig = torch.empty_like(self.T)
         self.Td = torch.empty_like(self.T)
@@ -467,6 +468,9 @@ def time_to_1pct(p: Problem, torch, seed, walk_on):
     measured sigma_I until sigma_I <= 1% of I.
     MC, energy-sampled (the paper's estimator: energies drawn from the weights, constant
     estimator): build + a first batch of 4096 walkers over all energies, then likewise.
+    MC, importance-sampled (Sec. V A, improved estimator): build without the plain tables +
+    the modified tables of a ramp bias + a first batch of 256 walkers per energy, then
+    likewise (the weights cut the variance per walker).
     DIRECT: build without alias tables + probe-system solve (deterministic; its error is the
     quadrature's).
     The stop is sigma_I / I <= 1%, a one-sigma rule: the realized deviation from the DIRECT
@@ -474,6 +478,7 @@ def time_to_1pct(p: Problem, torch, seed, walk_on):
     lies within 1% with probability about 0.68 and within 3% with probability about 0.997."""
     mc_t, dir_t, mc_walkers, smp_t, smp_walkers = [], [], [], [], []
     mc_I, smp_I = [], []
+    wt_t, wt_walkers, wt_I, wt_sig = [], [], [], []
     itp_t, itp_walkers, itp_I, itp_nodes, itp_bias = [], [], [], None, None
     I_dir = None
     max_sampled = 1 << 24
@@ -481,6 +486,8 @@ def time_to_1pct(p: Problem, torch, seed, walk_on):
         k0 = M.mc_negf_build_kernel(p.sys, p.V, p.g, p.E, p.ws)
         p.sampled_scratch = torch.empty(M.mc_negf_walk_sampled_bytes(k0, max_sampled),
                                         dtype=torch.uint8, device=p.E.device)
+    if walk_on and p.weighted is None:
+        p.weighted = weighted_setup(p, torch, max_sampled)
     for rep in range(5):
         if walk_on:
             torch.cuda.synchronize()
@@ -514,6 +521,28 @@ def time_to_1pct(p: Problem, torch, seed, walk_on):
             smp_t.append(time.perf_counter() - t0)
             smp_walkers.append(done)
             smp_I.append(I)
+            # importance-sampled walks: build without the kernel's own tables, the modified
+            # tables of the ramp bias, then batches until sigma_I <= 1% of I
+            tables, bias, wscratch, wsum = p.weighted
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            k = M.mc_negf_build_kernel(p.sys_direct, p.V, p.g, p.E, p.ws)
+            M.mc_negf_weighted_tables(k, bias, tables)
+            p.tal.zero_()
+            wsum.zero_()
+            done, batch = 0, 256
+            while True:
+                M.mc_negf_walk_weighted(k, tables, bias, seed + 301 + rep, 0, 0, done, batch,
+                                        1_000_000, p.tal, wsum, wscratch)
+                done += batch
+                st, I, s = M.mc_negf_current_weighted(k, 0, p.tal, wsum, p.w, p.T, p.sig)
+                if s <= 0.01 * abs(I) or done >= max_sampled:
+                    break
+                batch = next_batch(done, I, s, 256, max_sampled)
+            wt_t.append(time.perf_counter() - t0)
+            wt_walkers.append(done)
+            wt_I.append(I)
+            wt_sig.append(s)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         k = M.mc_negf_build_kernel(p.sys_direct, p.V, p.g, p.E, p.ws)
@@ -535,6 +564,16 @@ def time_to_1pct(p: Problem, torch, seed, walk_on):
            "mc_energy_sampled_walkers": int(np.median(smp_walkers)) if smp_walkers else None,
            "direct_ms": 1e3 * float(np.median(dir_t)), "I_direct": I_dir}
     out.update(realized_errors(mc_I, smp_I, I_dir))
+    if wt_t:
+        out["mc_weighted"] = {
+            "what": "importance-sampled walks (Sec. V A, improved estimator): step-6' rows "
+                    f"reweighted by a ramp bias along the wire (contact length "
+                    f"{WEIGHTED_RAMP_A:g} slices), scores = path likelihood ratios; build "
+                    "without the plain tables",
+            "ms": 1e3 * float(np.median(wt_t)),
+            "walkers_per_energy": int(np.median(wt_walkers)),
+            "rel_err_at_stop": [abs(v - I_dir) / abs(I_dir) for v in wt_I],
+            "err_at_stop_in_sigma": [(v - I_dir) / sg for v, sg in zip(wt_I, wt_sig)]}
     if itp_t:
         out["mc_interpolated"] = {
             "what": "every 4th energy built (and the last), intervals whose rows differ by "
@@ -590,6 +629,24 @@ def interp_mc(p: Problem, torch, seed, stride, walkers_first, cap, bias_walkers=
         _, Ib, sIb = M.mc_negf_current_interp(k1, p.E, 0, p.tal, p.w, p.T, p.sig)
         out = out + (Ib, sIb)
     return out
+
+
+WEIGHTED_RAMP_A = 10.0  # contact length (slices) of the ramp bias of the weighted walks
+
+
+def weighted_setup(p: Problem, torch, max_walkers):
+    """Buffers of the importance-sampled walks on p's wire: the modified tables, the ramp bias
+    (the harmonic function of 1D diffusion from L to R, the same for every energy), walker
+    scratch and the score sums."""
+    dev = p.E.device
+    k0 = M.mc_negf_build_kernel(p.sys_direct, p.V, p.g, p.E, p.ws)
+    tables = torch.empty(M.mc_negf_weighted_tables_bytes(k0), dtype=torch.uint8, device=dev)
+    b = torch.tensor(inputs.ramp_bias(p.wl.W, p.wl.L, WEIGHTED_RAMP_A), device=dev)
+    bias = b.unsqueeze(0).repeat(p.wl.n_energies, 1).contiguous()
+    scratch = torch.empty(M.mc_negf_walk_weighted_bytes(k0, max_walkers), dtype=torch.uint8,
+                          device=dev)
+    wsum = torch.zeros((p.wl.n_energies, 2), dtype=torch.float64, device=dev)
+    return tables, bias, scratch, wsum
 
 
 def realized_errors(mc_I, smp_I, I_dir):

@@ -382,11 +382,13 @@ int32_t mc_negf_current_interp(const mcnegf_kernel* k, const double* d_fine_ener
  * understates the error).
  *
  * mc_negf_weighted_tables_bytes (host only): device bytes of the modified tables of kernel k.
- * mc_negf_weighted_tables: from the kernel k (built with alias tables) and d_bias [nE][n_out]
- *   (device, FP64), writes into d_tables (caller-owned device memory of >= that size, 256-byte
- *   aligned) the alias tables of the modified rows in the kernel's format - packed entries
- *   [nE][n_out][alias_pitch] (uint32), then the low threshold bits (uint16, same shape), then
- *   rho [nE][n_out] (FP64), each part starting at a multiple of 256 bytes.  A negative or
+ * mc_negf_weighted_tables: from the kernel k (built with or without its own alias tables,
+ *   MCNEGF_BUILD_NO_ALIAS) and d_bias [nE][n_out] (device, FP64), writes into d_tables
+ *   (caller-owned device memory of >= that size, 256-byte aligned) the alias tables of the
+ *   modified rows in the kernel's format - packed entries [nE][n_out][alias_pitch] (uint32),
+ *   then the low threshold bits (uint16, same shape), then rho [nE][n_out] (FP64), each part
+ *   starting at a multiple of 256 bytes - and the injection rows' totals c_p into the lead
+ *   terms (MCNEGF_LEAD_CL, _CR, the values the kernel's own build stores).  A negative or
  *   non-finite bias entry sets MCNEGF_FLAG_NONFINITE.  Asynchronous.
  * mc_negf_walk_weighted_bytes (host only): device scratch bytes mc_negf_walk_weighted needs for
  *   n_walkers walkers per energy (16 bytes per energy per 2048 walkers).

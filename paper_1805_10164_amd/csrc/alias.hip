@@ -238,8 +238,9 @@ __device__ inline double kernel_weight(const AliasArgs& a, int e, int row, int i
 // the front with the total deficit after the last one, heavies from the back: heavy m at
 // n - m) and the heavy items' indices (16 bits): 10 n bytes per row.
 // With kBias the row is the modified one of an importance-sampled walk (outcome i weighs
-// b_i K_row,i), written to the caller's tables; the lead terms and the row-total checks of
-// the build are left alone, and rho = modified total / unmodified total is stored per row.
+// b_i K_row,i), written to the caller's tables; rho = modified total / unmodified total is
+// stored per row, the injection rows' unmodified totals c_p as the plain build stores them,
+// and the row-total checks of the build are left alone.
 template <int BT, int KM, bool kBias = false>
 __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
     constexpr bool kLong = KM > 8;  // rows above BT * 8 outcomes
@@ -294,6 +295,10 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
     if constexpr (kBias) {
         if (tid == 0) {
             a.rho[(size_t)e * n + row] = total0 > 0.0 ? total / total0 : 0.0;
+            // c_p, as the kernel's own build writes it (a kernel built without its own
+            // tables has it only from here)
+            if (row == N) a.lead[(size_t)e * MCNEGF_LEAD_NTERMS + MCNEGF_LEAD_CL] = total0;
+            if (row == N + 1) a.lead[(size_t)e * MCNEGF_LEAD_NTERMS + MCNEGF_LEAD_CR] = total0;
             if (!isfinite(total)) atomicOr(a.status, MCNEGF_FLAG_NONFINITE);
         }
         if (bad_bias) atomicOr(a.status, MCNEGF_FLAG_NONFINITE);

@@ -581,8 +581,11 @@ static WeightedTables weighted_tables_layout(const mcnegf_kernel& k) {
     return t;
 }
 
+// The modified tables need the kernel rows' ingredients (|G|^2, the exit weights, the lead
+// terms), not the kernel's own tables: a kernel built with MCNEGF_BUILD_NO_ALIAS will do.
 static bool valid_weighted_kernel(const mcnegf_kernel* k) {
-    return valid_kernel(k) && k->alias && k->alias_lo && k->alias_pitch >= k->n_out;
+    return valid_kernel(k) && k->wL && k->wR && k->gamma && k->Adiag && k->gam_lead &&
+           k->alias_pitch >= k->n_out && k->alias_pitch % 16 == 0;
 }
 
 int32_t mc_negf_weighted_tables_bytes(const mcnegf_kernel* k, uint64_t* bytes_out) {

@@ -121,3 +121,18 @@ def energy_grid(emin: float, emax: float, n: int):
     rule of Sec. III C.  The library forms the weighted sum over energies itself."""
     dE = (emax - emin) / n
     return emin + (np.arange(n) + 0.5) * dE, np.full(n, dE)
+
+
+def ramp_bias(W: int, L: int, a: float, inject_lead: int = 0, floor_p: float = 1e-3):
+    """A bias over the N + 2 outcomes for importance-sampled walks (a caller input of the
+    library): probes on slice x weigh (x + 1/2 + a) / (L + 2 a), x counted from the injecting
+    lead p; the collecting lead weighs 1 and lead p weighs floor_p.  It is the exit
+    probability of one-dimensional diffusion along the wire with contact length a (slices)."""
+    x = np.repeat(np.arange(L, dtype=np.float64), W)
+    if inject_lead == 1:
+        x = (L - 1) - x
+    b = np.empty(W * L + 2, dtype=np.float64)
+    b[:W * L] = (x + 0.5 + a) / (L + 2.0 * a)
+    b[W * L + 1 - inject_lead] = 1.0
+    b[W * L + inject_lead] = floor_p
+    return b

@@ -295,7 +295,8 @@ def test_weighted_walk_sizes_and_validation_without_gpu():
     lib = M.lib()
     ks = M.KernelStruct()
     ks.W, ks.L, ks.N, ks.n_out, ks.nE, ks.p_pitch, ks.alias_pitch = 2, 3, 6, 8, 3, 16, 16
-    for f in ("alias", "alias_lo", "P", "lead", "status", "counters", "reduce"):
+    for f in ("P", "lead", "status", "counters", "reduce", "wL", "wR", "gamma", "Adiag",
+              "gam_lead"):
         setattr(ks, f, 4096)
     out = ctypes.c_uint64(0)
     assert lib.mc_negf_weighted_tables_bytes(ctypes.byref(ks), ctypes.byref(out)) == M.OK
@@ -327,5 +328,7 @@ def test_weighted_walk_sizes_and_validation_without_gpu():
     assert lib.mc_negf_current_weighted(ctypes.byref(ks), 2, p, p, p, p, p,
                                         ctypes.cast(res, ctypes.POINTER(ctypes.c_double)),
                                         z) == M.EINVAL
-    ks.alias = 0  # a kernel built without alias tables
+    ks.wL = 0  # a handle without the exit weights
+    assert lib.mc_negf_weighted_tables_bytes(ctypes.byref(ks), ctypes.byref(out)) == M.EINVAL
+    ks.wL, ks.alias_pitch = 4096, 4  # a pitch shorter than a row
     assert lib.mc_negf_weighted_tables_bytes(ctypes.byref(ks), ctypes.byref(out)) == M.EINVAL

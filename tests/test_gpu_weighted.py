@@ -220,3 +220,24 @@ def test_weighted_sums_are_deterministic_and_argument_checks():
     bad[1, 3] = -1.0
     tables_for(k, bad)
     assert M.mc_negf_status(k) & M.FLAG_NONFINITE
+
+
+def test_modified_tables_from_a_kernel_without_its_own_tables():
+    # a MCNEGF_BUILD_NO_ALIAS kernel has the rows' ingredients: its modified tables, rho and
+    # c_p equal those of the full build bit for bit
+    c = case(W=5, L=6, eta=0.15, disorder=0.3, nE=3, emin=-2.0, emax=2.0)
+    k = gpu_build(c)
+    s0 = M.make_system(5, 6, 1.0, 0, 0.0, 1e-10, M.BUILD_NO_ALIAS)
+    ws0 = M.allocate_workspace(s0, 3)
+    V = torch.tensor(c["V"], dtype=torch.float64, device=DEV)
+    g = torch.tensor(c["g"], dtype=torch.float64, device=DEV)
+    E = torch.tensor(c["E"], dtype=torch.float64, device=DEV)
+    k0 = M.mc_negf_build_kernel(s0, V, g, E, ws0)
+    bias = np.tile(WT.ramp_bias(5, 6, 1, a=2.0, floor_p=0.0), (3, 1))
+    buf, b = tables_for(k, bias)
+    buf0, _ = tables_for(k0, bias)
+    assert torch.equal(buf, buf0)
+    assert torch.equal(k.lead()[:, M.LEAD_CL:M.LEAD_CR + 1], k0.lead()[:, M.LEAD_CL:M.LEAD_CR + 1])
+    tal, ws = walk(k0, buf0, b, 20_000, inject=1)
+    t2, w2 = walk(k, buf, b, 20_000, inject=1)
+    assert torch.equal(tal, t2) and torch.equal(ws, w2)
