@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--no-chain", action="store_true", help="skip the N = 50 chain")
     ap.add_argument("--only", choices=["grad", "batched", "scale", "chain"], default=None,
                     help="run only this leg and print its object (profiling; no top-level metric)")
+    ap.add_argument("--scale-batches", type=int, default=None,
+                    help="time only this many energy batches of the N = 16000 leg and skip its "
+                         "FP32 variants (profiling runs)")
     ap.add_argument("--batch-budget-gb", type=float, default=160.0,
                     help="device memory for one wave of build workspaces in the batched leg")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -661,7 +664,7 @@ def realized_errors(mc_I, smp_I, I_dir):
     return out
 
 
-def scale_bench(torch, dev, warmup, with_cpu, seed):
+def scale_bench(torch, dev, warmup, with_cpu, seed, timed_batches=None, fp32=True):
     """The W=32 x L=500 wire (N = 16000, the paper's 32 x 32 blocks), all 512 energies in 16
     batches of SCALE_BATCH (batch b takes every 16th energy from b), one build per batch:
     build, 1e7 walks per energy, MC and DIRECT currents, all FP64.  Every batch is timed; the
@@ -702,20 +705,22 @@ def scale_bench(torch, dev, warmup, with_cpu, seed):
     records = []
     flags = 0
     t0 = time.perf_counter()
-    for b in range(n_batches):
+    # (profiling runs may time fewer batches; the reported totals then cover those only)
+    n_timed = n_batches if timed_batches is None else max(1, min(timed_batches, n_batches))
+    for b in range(n_timed):
         with M.LaunchTimes() as lt:
             one_batch(b)
         records += require_complete(lt).records
         flags |= M.mc_negf_status(holder["k"])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    o = out.cpu().numpy()
-    ta = tal.cpu().numpy()
+    o = out.cpu().numpy()[:n_timed]
+    ta = tal.cpu().numpy()[:n_timed]
     walk_steps = int(ta[:, :, M.TALLY_STEPS].sum())
-    per_kernel = per_kernel_table(records, n_batches)
+    per_kernel = per_kernel_table(records, n_timed)
     for v in per_kernel.values():
         v["ms_per_batch"] = v.pop("ms_per_step")
-    walk_ms = per_kernel["walk_kernel"]["ms_per_batch"] * n_batches
+    walk_ms = per_kernel["walk_kernel"]["ms_per_batch"] * n_timed
     n_walk = per_kernel["walk_kernel"]["launches"]
     chol_ms = per_kernel["cholesky_kernel"]["ms_per_batch"]
     chol_flop = nE * (wl.N ** 3 / 3.0 + 2.0 * wl.N * wl.N)
@@ -726,7 +731,7 @@ def scale_bench(torch, dev, warmup, with_cpu, seed):
 
     def per_batch_traffic(name, pk):
         t = measured_traffic(name, "scale_W32_L500")
-        return None if t is None else t * pk[name]["launches"] / n_batches
+        return None if t is None else t * pk[name]["launches"] / n_timed
 
     walk_roof = {"bound": "hbm", "achieved": walk_steps * STEP_BYTES / 1e9 / (walk_ms * 1e-3),
                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -738,9 +743,12 @@ def scale_bench(torch, dev, warmup, with_cpu, seed):
     res = {
         "workload": f"W={wl.W} L={wl.L} N={wl.N}, eta={wl.eta}t, disorder U[-{wl.disorder},"
                     f"{wl.disorder}]t, {wl.n_energies} energies in [{wl.emin},{wl.emax}]t in "
-                    f"{n_batches} batches of {nE} (all timed), {nw} walkers/energy",
-        "s_all_energies": wall,
-        "ms_per_batch": 1e3 * wall / n_batches,
+                    f"{n_batches} batches of {nE} ("
+                    + ("all" if n_timed == n_batches else f"{n_timed}") + f" timed), {nw} "
+                    "walkers/energy",
+        "s_all_energies": wall if n_timed == n_batches else None,
+        "batches_timed": n_timed,
+        "ms_per_batch": 1e3 * wall / n_timed,
         "walk_steps": walk_steps,
         "walker_kernel_steps_per_s": walk_steps / (walk_ms * 1e-3),
         "mean_steps_per_walker": float(ta[:, :, M.TALLY_STEPS].sum() / ta[:, :, :3].sum()),
@@ -748,7 +756,7 @@ def scale_bench(torch, dev, warmup, with_cpu, seed):
         "I_direct": I_d, "I_mc": I_mc, "sigma_I_mc": s_mc,
         "mc_minus_direct_in_sigma": (I_mc - I_d) / s_mc if s_mc else None,
         "per_batch_mc_minus_direct_in_sigma": [float((o[b, 0, 0] - o[b, 1, 0]) / o[b, 0, 1])
-                                               for b in range(n_batches)],
+                                               for b in range(n_timed)],
         "status_flags": int(flags),
         "per_kernel": per_kernel,
         "rooflines": {
@@ -817,6 +825,10 @@ def scale_bench(torch, dev, warmup, with_cpu, seed):
         return r, float(Tx[j])
 
     P, R, S = M.BUILD_FP32_PRODUCTS, M.BUILD_FP32_REFINE, M.BUILD_FP32_SWEEPS
+    if not fp32:
+        del holder, ws
+        torch.cuda.empty_cache()
+        return res
     res["fp32_products"], T_gpu32 = fp32_variant(
         P, "batch 0 with the full-inverse block products in FP32 on the matrix cores (FP64 RGF "
            "sweeps, |G|^2, alias tables, probe solve, tallies); no refinement")
@@ -1002,7 +1014,8 @@ def main():
             leg = batched_bench(torch, dev, args.steps, args.warmup, args.batch_budget_gb,
                                 inputs.RNG_SEED)
         else:
-            leg = scale_bench(torch, dev, args.warmup, with_cpu, inputs.RNG_SEED)
+            leg = scale_bench(torch, dev, args.warmup, with_cpu, inputs.RNG_SEED,
+                              args.scale_batches, args.scale_batches is None)
         print(json.dumps({args.only: leg}), flush=True)
         return
     base = inputs.WIRE_W10_L100
@@ -1109,7 +1122,7 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_scale:
         line["scale"] = scale_bench(torch, dev, min(args.warmup, 1), not args.no_cpu_baseline,
-                                    seed)
+                                    seed, args.scale_batches, args.scale_batches is None)
     print(json.dumps(line), flush=True)
 
 

@@ -473,10 +473,12 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
             out_lo[i] = (uint16_t)low;
         }
     } else {
-        // Long rows (no room in registers to hold the merged results until every thread has
-        // read D and C): the same merge, with each merged item's entry written to the output
-        // row at once by the thread that merges it (16-bit item indices of lights and heavies
-        // in LDS); a light keeps 1 - (D_{r+1} - D_r), its own deficit recovered from the starts.
+        // Long rows: the same merge with the 16-bit item indices of lights and heavies in LDS
+        // (a light keeps 1 - (D_{r+1} - D_r), its own deficit recovered from the starts).  The
+        // merged results wait in registers (the row's weights, ranks and prefix values are no
+        // longer needed) until every merge has read D and C, then go through the lh array by
+        // item index (one 64-bit slot per item) to the threads that own the items, which write
+        // coalesced entries.
         if (NHtot == 0) {
 #pragma unroll
             for (int k = 0; k < KM; ++k) {
@@ -486,58 +488,84 @@ __global__ void __launch_bounds__(BT) alias_build_kernel(AliasArgs a) {
                     out_lo[i] = (uint16_t)(0xFFFFFFFFu & kAliasIdxMask);
                 }
             }
-            return;
+            return;  // uniform: NHtot is the block's total
+        }
+        uint64_t res[KM];
+        int itm[KM];  // item of each merged result (-1: none)
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            res[k] = 0;
+            itm[k] = -1;
         }
         const int d0 = tid * KM;
-        if (d0 >= n) return;
-        int lo = d0 > NHtot ? d0 - NHtot : 0, hi = d0 < NLtot ? d0 : NLtot;
-        while (lo < hi) {  // lights among the first d0 merged items
-            const int mid = (lo + hi) >> 1;
-            if (lightD(mid) < heavyC(d0 - mid - 1)) lo = mid + 1; else hi = mid;
-        }
-        int ra = lo, rb = d0 - lo;
-        double dA = lightD(ra);  // lightD(NLtot) = Dtot
-        double cB = rb < NHtot ? heavyC(rb) : 0.0;
-        for (int k = 0; k < KM && d0 + k < n; ++k) {
-            const bool heavy = rb < NHtot && (ra >= NLtot || cB <= dA);
-            int i, al;
-            double q;
-            if (heavy) {
-                i = heavyIdx(rb);
-                if (rb == NHtot - 1) {
-                    q = 1.0;
+        if (d0 < n) {
+            int lo = d0 > NHtot ? d0 - NHtot : 0, hi = d0 < NLtot ? d0 : NLtot;
+            while (lo < hi) {  // lights among the first d0 merged items
+                const int mid = (lo + hi) >> 1;
+                if (lightD(mid) < heavyC(d0 - mid - 1)) lo = mid + 1; else hi = mid;
+            }
+            int ra = lo, rb = d0 - lo;
+            double dA = lightD(ra);  // lightD(NLtot) = Dtot
+            double cB = rb < NHtot ? heavyC(rb) : 0.0;
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                if (d0 + k >= n) continue;
+                const bool heavy = rb < NHtot && (ra >= NLtot || cB <= dA);
+                int i, al;
+                double q;
+                if (heavy) {
+                    i = heavyIdx(rb);
+                    if (rb == NHtot - 1) {
+                        q = 1.0;
+                        al = i;
+                    } else {
+                        q = 1.0 + cB - dA;
+                        q = q < 0.0 ? 0.0 : q;
+                        al = heavyIdx(rb + 1);
+                    }
+                    ++rb;
+                    cB = rb < NHtot ? heavyC(rb) : 0.0;
+                } else {
+                    i = idx[ra];
+                    const double dn = lightD(ra + 1);
+                    q = 1.0 - (dn - dA);
+                    q = q < 0.0 ? 0.0 : q;
+                    al = heavyIdx(rb < NHtot ? rb : NHtot - 1);
+                    ++ra;
+                    dA = dn;
+                }
+                uint32_t thr;
+                if (q >= 1.0) {
+                    thr = 0xFFFFFFFFu;
                     al = i;
                 } else {
-                    q = 1.0 + cB - dA;
-                    q = q < 0.0 ? 0.0 : q;
-                    al = heavyIdx(rb + 1);
+                    thr = (uint32_t)(q * 4294967296.0);
                 }
-                ++rb;
-                cB = rb < NHtot ? heavyC(rb) : 0.0;
-            } else {
-                i = idx[ra];
-                const double dn = lightD(ra + 1);
-                q = 1.0 - (dn - dA);
-                q = q < 0.0 ? 0.0 : q;
-                al = heavyIdx(rb < NHtot ? rb : NHtot - 1);
-                ++ra;
-                dA = dn;
+                if ((unsigned)al >= (unsigned)n || (unsigned)i >= (unsigned)n) {
+                    // never for a consistent row; keeps walks and stores in range
+                    atomicOr(a.status, MCNEGF_FLAG_NONFINITE);
+                    if ((unsigned)i >= (unsigned)n) continue;
+                    al = i;
+                }
+                res[k] = (uint64_t)((thr & ~kAliasIdxMask) | (uint32_t)al) |
+                         ((uint64_t)(thr & kAliasIdxMask) << 32);
+                itm[k] = i;
             }
-            uint32_t thr;
-            if (q >= 1.0) {
-                thr = 0xFFFFFFFFu;
-                al = i;
-            } else {
-                thr = (uint32_t)(q * 4294967296.0);
+        }
+        __syncthreads();  // every merge has read D and C
+        uint64_t* slots = reinterpret_cast<uint64_t*>(lh);
+#pragma unroll
+        for (int k = 0; k < KM; ++k)
+            if (itm[k] >= 0) slots[itm[k]] = res[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            const int i = tid + BT * k;
+            if (i < n) {
+                const uint64_t v = slots[i];
+                out[i] = (uint32_t)v;
+                out_lo[i] = (uint16_t)(v >> 32);
             }
-            if ((unsigned)al >= (unsigned)n || (unsigned)i >= (unsigned)n) {
-                // never for a consistent row; keeps walks and stores in range
-                atomicOr(a.status, MCNEGF_FLAG_NONFINITE);
-                if ((unsigned)i >= (unsigned)n) continue;
-                al = i;
-            }
-            out[i] = (thr & ~kAliasIdxMask) | (uint32_t)al;
-            out_lo[i] = (uint16_t)(thr & kAliasIdxMask);
         }
     }
 }
