@@ -388,6 +388,93 @@ int oracle_walk_weighted_alias(const uint32_t *thr, const int32_t *alias, int64_
 }
 
 /*
+ * Transition counts of the walks that reach the collecting lead q (the data of the
+ * score-function gradient of Eq. (66)): the same walks as walk_impl; every walk that exits at
+ * q adds one to counts[k][o][s] for each of its steps s -> o (s a probe or the injection row
+ * N + p, o a probe or q), outcome-major.  Tallies as walk_impl.  mode 0: cdf on K [nE][n][n];
+ * mode 1: alias tables [nE][n][pitch].
+ */
+static int walk_counts_impl(int mode, const double *K, const uint32_t *thr, const int32_t *alias,
+                            int64_t pitch, int32_t nE, int32_t n, uint64_t seed,
+                            uint32_t realization, uint32_t inject_lead, uint64_t walker_begin,
+                            uint64_t n_walkers, uint32_t max_steps, int64_t *tallies,
+                            int64_t *counts)
+{
+    if (n < 3 || nE < 1 || inject_lead > 1 || realization >= (1u << 30)) return -1;
+    if (walker_begin + n_walkers > 0x100000000ull) return -1;
+    const int32_t N = n - 2;
+    const int32_t q = N + 1 - (int32_t)inject_lead;
+    const uint32_t tag = (realization << 1) | inject_lead;
+    for (int32_t k = 0; k < nE; ++k) {
+        int64_t *ck = counts + (int64_t)k * n * n;
+        int64_t cL = 0, cR = 0, tr = 0, s1 = 0, s2 = 0;
+#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : cL, cR, tr, s1, s2)
+        for (int64_t i = 0; i < (int64_t)n_walkers; ++i) {
+            const uint32_t w = (uint32_t)(walker_begin + (uint64_t)i);
+            int outcome = -1;
+            uint32_t steps = 0;
+            for (int pass = 0; pass < 2; ++pass) {  /* pass 1 replays a walk that reached q */
+                stream_t st;
+                stream_init(&st, seed, w, (uint32_t)k, tag);
+                int32_t s = N + (int32_t)inject_lead;
+                steps = 0;
+                outcome = -1;
+                while (steps < max_steps) {
+                    uint32_t a, b;
+                    stream_pair(&st, steps, &a, &b);
+                    int32_t next;
+                    if (mode == 0) {
+                        next = draw_cdf(K + ((int64_t)k * n + s) * (int64_t)n, n, a, b);
+                    } else {
+                        uint32_t c = lemire_bucket(&st, steps, a, (uint32_t)n);
+                        int64_t e = ((int64_t)k * n + s) * pitch + c;
+                        next = (b < thr[e]) ? (int32_t)c : alias[e];
+                    }
+                    ++steps;
+                    if (pass == 1) {
+#pragma omp atomic
+                        ck[(int64_t)next * n + s] += 1;
+                    }
+                    if (next >= N) { outcome = next - N; break; }
+                    s = next;
+                }
+                if (pass == 0 && !(outcome >= 0 && N + outcome == q)) break;
+            }
+            if (outcome == 0) ++cL;
+            else if (outcome == 1) ++cR;
+            else ++tr;
+            s1 += steps;
+            s2 += (int64_t)steps * (int64_t)steps;
+        }
+        tallies[5 * k + 0] += cL;
+        tallies[5 * k + 1] += cR;
+        tallies[5 * k + 2] += tr;
+        tallies[5 * k + 3] += s1;
+        tallies[5 * k + 4] += s2;
+    }
+    return 0;
+}
+
+int oracle_walk_counts_cdf(const double *K, int32_t nE, int32_t n, uint64_t seed,
+                           uint32_t realization, uint32_t inject_lead, uint64_t walker_begin,
+                           uint64_t n_walkers, uint32_t max_steps, int64_t *tallies,
+                           int64_t *counts)
+{
+    return walk_counts_impl(0, K, NULL, NULL, 0, nE, n, seed, realization, inject_lead,
+                            walker_begin, n_walkers, max_steps, tallies, counts);
+}
+
+int oracle_walk_counts_alias(const uint32_t *thr, const int32_t *alias, int64_t pitch,
+                             int32_t nE, int32_t n, uint64_t seed, uint32_t realization,
+                             uint32_t inject_lead, uint64_t walker_begin, uint64_t n_walkers,
+                             uint32_t max_steps, int64_t *tallies, int64_t *counts)
+{
+    if (pitch < n) return -1;
+    return walk_counts_impl(1, NULL, thr, alias, pitch, nE, n, seed, realization, inject_lead,
+                            walker_begin, n_walkers, max_steps, tallies, counts);
+}
+
+/*
  * Interpolated walks (Sec. V A, "Interpolation"): walker w at fine energy f walks on the
  * mixture (1 - alpha_f) p(E_lo) + alpha_f p(E_hi) of the rows of two nodes lo = lo[f] and
  * hi = lo + 1 (hi = lo for the last node), alpha_f = alpha32[f] / 2^32.  Step n uses the
