@@ -287,6 +287,38 @@ int32_t mc_negf_grad(const mcnegf_kernel* k, uint32_t inject_lead, const double*
                      double* h_I, hipStream_t stream);
 
 /*
+ * Score-function gradient of the Monte Carlo current: the derivative of the reweighted path
+ * estimator of Eq. (66) (Sec. V A, "Improved estimator": walks drawn at the current
+ * parameters, weighted by their likelihood ratio at perturbed ones).  For walks injected at p,
+ *   dT/dtheta ~ (c_p / N_w) d/dtheta [ sum_so C_so K_so / K_so(0) - sum_s n_s A_ss / A_ss(0) ]
+ * with C_so the steps s -> o of the walks that reached q, n_s = sum_o C_so, K the kernel
+ * weights (Eqs. (75), (76)), theta = V_i or gamma_i; its mean is the exact derivative of the
+ * current (the library's mc_negf_grad gives that exactly).
+ * mc_negf_walk_counts_bytes (host only): bytes of the counts array, nE * n_out^2 * 4.
+ * mc_negf_walk_counts: walkers [walker_begin, walker_begin + n_walkers) (< 2^32) at every
+ *   energy, drawing exactly as mc_negf_walk; adds to d_counts [nE][n_out][n_out] (uint32,
+ *   device, outcome-major: d_counts[e][o][s] counts steps s -> o; caller-owned, zeroed by the
+ *   caller before the first call) the steps of every walk that exits at q, and their exit
+ *   counts to d_tallies as mc_negf_walk.  Needs a kernel with alias tables.  Asynchronous.
+ * mc_negf_grad_mc: from those counts and tallies, d_dI_dV [N] and d_dI_dgamma [N] (device)
+ *   = sum_k w_k times the estimate above at energy k (dgamma: gamma_i > 0; for gamma_i = 0 the
+ *   walks never enter site i and the explicit term is taken as 0).  d_gws: the workspace of
+ *   mc_negf_grad (mc_negf_grad_workspace_bytes[_chunk]; energies in chunks as there).  Any
+ *   W <= 32; the kernel needs no DIRECT workspace.  Asynchronous; MCNEGF_EINVAL for bad
+ *   arguments, MCNEGF_EWS for a workspace below the one-energy size, MCNEGF_EHIP on a failed
+ *   launch.
+ */
+int32_t mc_negf_walk_counts_bytes(const mcnegf_kernel* k, uint64_t* bytes_out);
+int32_t mc_negf_walk_counts(const mcnegf_kernel* k, uint64_t seed, uint32_t realization,
+                            uint32_t inject_lead, uint64_t walker_begin, uint64_t n_walkers,
+                            uint32_t max_steps, uint32_t* d_counts, int64_t* d_tallies,
+                            hipStream_t stream);
+int32_t mc_negf_grad_mc(const mcnegf_kernel* k, uint32_t inject_lead, const uint32_t* d_counts,
+                        const int64_t* d_tallies, const double* d_weights, void* d_gws,
+                        uint64_t gws_bytes, double* d_dI_dV, double* d_dI_dgamma,
+                        hipStream_t stream);
+
+/*
  * Energy-sampled walks (Sec. II F step 2: the starting energy drawn from a density h; with
  * h proportional to the quadrature weights the estimator of Eq. (66) becomes the constant
  * W c_p(E_0) [exit at q], W = sum_k w_k — the paper's choice h = Th(E) when w_k = Th(E_k) dE).

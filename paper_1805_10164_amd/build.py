@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmcnegf.so")
 SOURCES = ["mcnegf.cpp", "lead.hip", "rgf.hip", "fullinv.hip", "alias.hip", "walker.hip",
-           "direct.hip", "grad.hip", "refine.hip"]
+           "direct.hip", "grad.hip", "refine.hip", "score.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature",
          "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-result"]
 # The walker keeps every lane of a wavefront active at each cross-lane operation; the atomic

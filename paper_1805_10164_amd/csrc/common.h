@@ -133,7 +133,8 @@ struct GradBuffers {
     double* sig;      // [nE] (zero)
     int64_t ld, ldY;
 };
-// Workspace of mc_negf_grad with the G-sized buffers for `chunk` energies at a time.
+// Workspace of mc_negf_grad (and mc_negf_grad_mc) with the G-sized buffers for `chunk`
+// energies at a time.
 uint64_t grad_layout(const mcnegf_kernel& k, int chunk, void* base, GradBuffers* out);
 
 // ---- opt-in launch timing: events around every launch while a profile is attached ------
@@ -158,6 +159,17 @@ hipError_t launch_fullinv_store_g(const mcnegf_kernel& k, double2* Gc, int64_t l
 hipError_t launch_lead_terms(const mcnegf_kernel& k, hipStream_t s);
 // rowsum_tol: relative tolerance of the check of each row's total against its spectral value
 hipError_t launch_alias_build(const mcnegf_kernel& k, double rowsum_tol, hipStream_t s);
+// Transition counts of the walks that reach the collecting lead ([nE][n][n] uint32,
+// outcome-major), and the score-function gradient of the Monte Carlo estimator from them.
+hipError_t launch_walk_counts(const mcnegf_kernel& k, uint64_t seed, uint32_t tag,
+                              uint32_t walker_begin, uint32_t n_walkers, uint32_t max_steps,
+                              uint32_t* counts, int64_t* tallies, hipStream_t s);
+hipError_t launch_score_grad(const mcnegf_kernel& k, const GradBuffers& gb,
+                             const uint32_t* counts, const int64_t* tallies,
+                             uint32_t inject_lead, const double* weights, double* dI_dV,
+                             double* dI_dgamma, int chunk, hipStream_t s);
+hipError_t launch_grad_reduce(const GradBuffers& gb, const double* weights, int nE, int N,
+                              double* dI_dV, double* dI_dgamma, hipStream_t s);
 // Importance-sampled walks: alias tables of the modified rows K_ij b_j into the caller's
 // tables and rho (per row: modified total / unmodified total); the walks; their estimator.
 hipError_t launch_alias_bias(const mcnegf_kernel& k, const double* bias, uint32_t* tables,

@@ -433,6 +433,11 @@ hipError_t launch_grad(const mcnegf_kernel& k, const GradBuffers& gb, uint32_t i
                 return hipErrorInvalidValue;
         }
     }
+    return launch_grad_reduce(gb, weights, nE, N, dI_dV, dI_dgamma, s);
+}
+
+hipError_t launch_grad_reduce(const GradBuffers& gb, const double* weights, int nE, int N,
+                              double* dI_dV, double* dI_dgamma, hipStream_t s) {
     {
         MCNEGF_TIMED("grad_reduce_kernel", s);
         hipLaunchKernelGGL(grad_reduce_kernel, dim3((N + 255) / 256), dim3(256), 0, s, gb.gV,

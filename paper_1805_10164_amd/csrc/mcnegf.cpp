@@ -116,7 +116,7 @@ static int32_t status_to_code(uint32_t flags, bool mc) {
 }
 
 uint64_t grad_layout(const mcnegf_kernel& k, int chunk, void* base, GradBuffers* out) {
-    const int64_t N = k.N, nE = k.nE, ld = k.p_pitch, ldY = round_up(N + k.W, 16);
+    const int64_t N = k.N, nE = k.nE, ld = k.p_pitch, ldY = round_up(N + 2 * k.W, 16);
     const int64_t nc = chunk;
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) {
@@ -348,6 +348,52 @@ int32_t mc_negf_grad(const mcnegf_kernel* k, uint32_t inject_lead, const double*
     if ((err = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(err);
     *h_I = host[0];
     return status_to_code(flags, false);
+}
+
+// ---- score-function gradient of the Monte Carlo estimator ------------------------------
+
+int32_t mc_negf_walk_counts_bytes(const mcnegf_kernel* k, uint64_t* bytes_out) {
+    if (!valid_kernel(k) || !bytes_out) return MCNEGF_EINVAL;
+    *bytes_out = (uint64_t)k->nE * (uint64_t)k->n_out * (uint64_t)k->n_out * 4;
+    return MCNEGF_OK;
+}
+
+int32_t mc_negf_walk_counts(const mcnegf_kernel* k, uint64_t seed, uint32_t realization,
+                            uint32_t inject_lead, uint64_t walker_begin, uint64_t n_walkers,
+                            uint32_t max_steps, uint32_t* d_counts, int64_t* d_tallies,
+                            hipStream_t stream) {
+    if (!valid_kernel(k) || !k->alias || !k->alias_lo || !d_counts || !d_tallies ||
+        inject_lead > 1 || realization >= (1u << 30) || max_steps < 1)
+        return MCNEGF_EINVAL;
+    if (walker_begin >= 0x100000000ull || n_walkers >= 0x100000000ull ||
+        walker_begin + n_walkers >= 0x100000000ull)
+        return MCNEGF_EINVAL;
+    const uint32_t tag = (realization << 1) | inject_lead;
+    hipError_t err = launch_walk_counts(*k, seed, tag, (uint32_t)walker_begin,
+                                        (uint32_t)n_walkers, max_steps, d_counts, d_tallies,
+                                        stream);
+    return err == hipSuccess ? MCNEGF_OK : hip_fail(err);
+}
+
+int32_t mc_negf_grad_mc(const mcnegf_kernel* k, uint32_t inject_lead, const uint32_t* d_counts,
+                        const int64_t* d_tallies, const double* d_weights, void* d_gws,
+                        uint64_t gws_bytes, double* d_dI_dV, double* d_dI_dgamma,
+                        hipStream_t stream) {
+    if (!valid_kernel(k) || !d_counts || !d_tallies || !d_weights || !d_gws || !d_dI_dV ||
+        !d_dI_dgamma || inject_lead > 1 || k->W > kMaxGradW || !k->wL || !k->wR ||
+        !k->Adiag || !k->gam_lead || !k->corner || !k->gamma)
+        return MCNEGF_EINVAL;
+    if (grad_layout(*k, 1, nullptr, nullptr) > gws_bytes) return MCNEGF_EWS;
+    int lo = 1, hi = k->nE;
+    while (lo < hi) {
+        const int mid = lo + (hi - lo + 1) / 2;
+        if (grad_layout(*k, mid, nullptr, nullptr) <= gws_bytes) lo = mid; else hi = mid - 1;
+    }
+    GradBuffers gb;
+    grad_layout(*k, lo, d_gws, &gb);
+    hipError_t err = launch_score_grad(*k, gb, d_counts, d_tallies, inject_lead, d_weights,
+                                       d_dI_dV, d_dI_dgamma, lo, stream);
+    return err == hipSuccess ? MCNEGF_OK : hip_fail(err);
 }
 
 int32_t mc_negf_profile_begin(mcnegf_profile* p) {

@@ -1491,4 +1491,131 @@ hipError_t launch_walk_weighted(const mcnegf_kernel& k, const uint32_t* tables,
     return hipGetLastError();
 }
 
+// ---- transition counts for the score-function gradient ----------------------------------
+//
+// Each lane walks one walker exactly as mc_negf_walk does (same counters, Lemire redraws,
+// packed entries); a walk that exits at the collecting lead q is walked again from its first
+// step (the counter-based draws repeat it exactly) and adds one to counts[e][o][s] for each
+// step s -> o.  The counts are integers, so the result does not depend on the order of the
+// atomic adds.  Lanes walk divergent loops with no cross-lane operation inside; the tallies
+// are reduced across the wavefront after every lane has left its loops.
+struct CountArgs {
+    const uint32_t* tables;
+    const uint16_t* lows;
+    uint32_t pitch32;
+    int64_t table_stride;
+    uint32_t n_out, N, nE;
+    uint32_t key0, key1, tag;
+    uint32_t wbegin, n_walkers, max_steps;
+    uint32_t* counts;  // [nE][n_out][n_out], outcome-major
+    int64_t* tallies;
+    uint32_t* status;
+};
+
+// One step of a single walker from row `row` with Philox words (a, b) of step n_step.
+__device__ inline uint32_t draw_step(const CountArgs& A, gtable_ptr tb, const uint16_t* lo,
+                                     uint32_t row, uint32_t n_step, uint32_t w, uint32_t e,
+                                     uint32_t a, uint32_t b) {
+    const uint32_t n_out = A.n_out;
+    const uint32_t thresh = (0u - n_out) % n_out;
+    uint64_t m = (uint64_t)a * n_out;
+    uint32_t r = 0;
+    while ((uint32_t)m < thresh) {  // per lane, rare
+        ++r;
+        m = (uint64_t)philox4x32_10(n_step, w, e, A.tag | 0x80000000u, A.key0, A.key1 ^ r).x[0] *
+            n_out;
+    }
+    const uint32_t c = (uint32_t)(m >> 32);
+    const uint32_t off = __umul24(row, A.pitch32) + c;
+    const uint32_t ent = tb[off];
+    bool keep = b < (ent & ~kAliasIdxMask);
+    if (((b ^ ent) >> kAliasIdxBits) == 0u) keep = (b & kAliasIdxMask) < (uint32_t)lo[off];
+    return keep ? c : (ent & kAliasIdxMask);
+}
+
+__global__ void __launch_bounds__(256) walk_counts_kernel(CountArgs A) {
+    const uint32_t e = blockIdx.y;
+    const uint64_t wi = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = wi < A.n_walkers;
+    const uint32_t w = A.wbegin + (uint32_t)(valid ? wi : 0);
+    const uint32_t N = A.N, n = A.n_out;
+    const uint32_t p = A.tag & 1u;
+    const uint32_t q = N + 1u - p;
+    const gtable_ptr tb = (gtable_ptr)(A.tables + (size_t)e * A.table_stride);
+    const uint16_t* lo = A.lows + (size_t)e * A.table_stride;
+    uint32_t* cnt = A.counts + (size_t)e * n * n;
+    uint32_t steps = 0, fin = N;  // final state of the walk (a probe when truncated)
+    for (int pass = 0; pass < 2 && valid; ++pass) {
+        uint32_t s = N + p;
+        steps = 0;
+        Philox4 blk;
+        bool ended = false;
+        while (steps < A.max_steps) {
+            if ((steps & 1u) == 0u) blk = philox4x32_10(steps >> 1, w, e, A.tag, A.key0, A.key1);
+            const uint32_t a = blk.x[2 * (steps & 1u)], b = blk.x[2 * (steps & 1u) + 1];
+            const uint32_t next = draw_step(A, tb, lo, s, steps, w, e, a, b);
+            ++steps;
+            if (pass == 1) atomicAdd(cnt + (size_t)next * n + s, 1u);
+            s = next;
+            if (next >= N) {
+                ended = true;
+                break;
+            }
+        }
+        fin = s;
+        if (pass == 0 && !(ended && s == q)) break;
+    }
+    uint32_t cL = valid && fin == N ? 1u : 0u;
+    uint32_t cR = valid && fin == N + 1 ? 1u : 0u;
+    uint32_t tr = valid && fin < N ? 1u : 0u;
+    uint64_t s1 = valid ? steps : 0u, s2 = valid ? (uint64_t)steps * steps : 0u;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        cL += __shfl_xor(cL, o, 64);
+        cR += __shfl_xor(cR, o, 64);
+        tr += __shfl_xor(tr, o, 64);
+        s1 += __shfl_xor(s1, o, 64);
+        s2 += __shfl_xor(s2, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        unsigned long long* t =
+            reinterpret_cast<unsigned long long*>(A.tallies + (size_t)e * MCNEGF_TALLY_N);
+        if (cL) atomicAdd(t + MCNEGF_TALLY_EXIT_L, (unsigned long long)cL);
+        if (cR) atomicAdd(t + MCNEGF_TALLY_EXIT_R, (unsigned long long)cR);
+        if (tr) atomicAdd(t + MCNEGF_TALLY_TRUNC, (unsigned long long)tr);
+        if (s1) atomicAdd(t + MCNEGF_TALLY_STEPS, (unsigned long long)s1);
+        if (s2) atomicAdd(t + MCNEGF_TALLY_STEPS2, (unsigned long long)s2);
+        if (tr) atomicOr(A.status, MCNEGF_FLAG_TRUNC);
+    }
+}
+
+hipError_t launch_walk_counts(const mcnegf_kernel& k, uint64_t seed, uint32_t tag,
+                              uint32_t walker_begin, uint32_t n_walkers, uint32_t max_steps,
+                              uint32_t* counts, int64_t* tallies, hipStream_t s) {
+    if (n_walkers == 0) return hipSuccess;
+    CountArgs A;
+    A.tables = k.alias;
+    A.lows = k.alias_lo;
+    A.pitch32 = (uint32_t)k.alias_pitch;
+    A.table_stride = (int64_t)k.n_out * k.alias_pitch;
+    A.n_out = (uint32_t)k.n_out;
+    A.N = (uint32_t)k.N;
+    A.nE = (uint32_t)k.nE;
+    A.key0 = (uint32_t)(seed & 0xffffffffu);
+    A.key1 = (uint32_t)(seed >> 32);
+    A.tag = tag;
+    A.wbegin = walker_begin;
+    A.n_walkers = n_walkers;
+    A.max_steps = max_steps;
+    A.counts = counts;
+    A.tallies = tallies;
+    A.status = k.status;
+    {
+        MCNEGF_TIMED("walk_counts_kernel", s);
+        hipLaunchKernelGGL(walk_counts_kernel, dim3((n_walkers + 255) / 256, k.nE), dim3(256), 0,
+                           s, A);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace mcnegf

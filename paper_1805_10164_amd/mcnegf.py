@@ -31,6 +31,7 @@ EXPORTED = ("mc_negf_workspace_bytes", "mc_negf_build_kernel", "mc_negf_walk",
             "mc_negf_current_async", "mc_negf_walk_sampled_bytes", "mc_negf_walk_sampled",
             "mc_negf_walk_sampled_noalloc", "mc_negf_interp_distances", "mc_negf_interp_plan",
             "mc_negf_walk_interp", "mc_negf_current_interp",
+            "mc_negf_walk_counts_bytes", "mc_negf_walk_counts", "mc_negf_grad_mc",
             "mc_negf_weighted_tables_bytes", "mc_negf_weighted_tables",
             "mc_negf_walk_weighted_bytes", "mc_negf_walk_weighted", "mc_negf_current_weighted",
             "mc_negf_batch_bytes", "mc_negf_batch_prepare",
@@ -126,6 +127,11 @@ def lib() -> ctypes.CDLL:
                                       u64, u32, vp, vp]
     L.mc_negf_current_interp.argtypes = [ctypes.POINTER(KernelStruct), vp, i32, u32, vp, vp, vp,
                                          vp, dp, vp]
+    L.mc_negf_walk_counts_bytes.argtypes = [ctypes.POINTER(KernelStruct), ctypes.POINTER(u64)]
+    L.mc_negf_walk_counts.argtypes = [ctypes.POINTER(KernelStruct), u64, u32, u32, u64, u64,
+                                      u32, vp, vp, vp]
+    L.mc_negf_grad_mc.argtypes = [ctypes.POINTER(KernelStruct), u32, vp, vp, vp, vp, u64, vp,
+                                  vp, vp]
     L.mc_negf_weighted_tables_bytes.argtypes = [ctypes.POINTER(KernelStruct),
                                                 ctypes.POINTER(u64)]
     L.mc_negf_weighted_tables.argtypes = [ctypes.POINTER(KernelStruct), vp, vp, u64, vp]
@@ -541,6 +547,38 @@ def mc_negf_walk_sampled_noalloc(k: Kernel, seed: int, realization: int, inject_
                                               int(max_steps), _ptr(weights), _ptr(tallies),
                                               _stream(stream))
     return _check("mc_negf_walk_sampled_noalloc", code)
+
+
+# ---- score-function gradient of the Monte Carlo current ----------------------------------------
+
+def mc_negf_walk_counts_bytes(k: Kernel) -> int:
+    out = ctypes.c_uint64(0)
+    _check("mc_negf_walk_counts_bytes",
+           lib().mc_negf_walk_counts_bytes(ctypes.byref(k.struct), ctypes.byref(out)))
+    return int(out.value)
+
+
+def mc_negf_walk_counts(k: Kernel, seed: int, realization: int, inject_lead: int,
+                        walker_begin: int, n_walkers: int, max_steps: int, counts, tallies,
+                        stream=None) -> int:
+    """Walks as mc_negf_walk; the steps of the walks that exit at q are added to counts
+    [nE][n_out][n_out] (int32 storage of uint32 counts, outcome-major)."""
+    return _check("mc_negf_walk_counts",
+                  lib().mc_negf_walk_counts(ctypes.byref(k.struct), int(seed), int(realization),
+                                            int(inject_lead), int(walker_begin), int(n_walkers),
+                                            int(max_steps), _ptr(counts), _ptr(tallies),
+                                            _stream(stream)))
+
+
+def mc_negf_grad_mc(k: Kernel, inject_lead: int, counts, tallies, weights, gws, dI_dV,
+                    dI_dgamma, stream=None) -> int:
+    """Score-function estimate of dI/dV_i and dI/dgamma_i from transition counts (workspace of
+    mc_negf_grad)."""
+    return _check("mc_negf_grad_mc",
+                  lib().mc_negf_grad_mc(ctypes.byref(k.struct), int(inject_lead), _ptr(counts),
+                                        _ptr(tallies), _ptr(weights), _ptr(gws),
+                                        int(gws.numel()), _ptr(dI_dV), _ptr(dI_dgamma),
+                                        _stream(stream)))
 
 
 # ---- importance-sampled walks ---------------------------------------------------------------
