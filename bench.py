@@ -306,7 +306,10 @@ def grad_bench(torch, dev, steps, warmup, with_cpu):
                      "traffic": measured_traffic("adjoint_solve_kernel", "diff_W16_L200")},
     }
     add_traffic_rate(out["roofline"])
+    exact_V, exact_eta = dV.cpu().numpy(), float(dg.sum().item())
     del k, ws, gws
+    torch.cuda.empty_cache()
+    out["mc"] = grad_mc_bench(torch, dev, wl, V, g, tE, tw, exact_V, exact_eta)
     torch.cuda.empty_cache()
     out["w32"] = grad_w32_bench(torch, dev, steps)
     if with_cpu:
@@ -322,6 +325,52 @@ def grad_bench(torch, dev, steps, warmup, with_cpu):
                                "cores": _t.get_num_threads(), "kind": "oracle",
                                "sample": f"1 of {wl.n_energies} energies (dense torch adjoint, "
                                          f"{dt:.1f} s), scaled to all energies"}
+    return out
+
+
+def grad_mc_bench(torch, dev, wl, V, g, tE, tw, exact_V, exact_eta, walkers=100_000,
+                  batches=4, seed=inputs.RNG_SEED):
+    """The score-function gradient of the Monte Carlo current on the differentiation workload:
+    per batch, walks with transition counts (mc_negf_walk_counts) and the gradient from them
+    (mc_negf_grad_mc), against the exact adjoint gradient: dI/deta and the relative error of
+    dI/dV over the sites, the spread over independent batches giving the standard error."""
+    sysm = M.make_system(wl.W, wl.L, wl.t, wl.lead_model, wl.gamma_l, wl.delta_lead,
+                         M.BUILD_NO_DIRECT)
+    ws = M.allocate_workspace(sysm, wl.n_energies, dev)
+    k = M.mc_negf_build_kernel(sysm, V, g, tE, ws)
+    cnt = torch.zeros(M.mc_negf_walk_counts_bytes(k) // 4, dtype=torch.int32, device=dev)
+    tal = torch.zeros((wl.n_energies, M.TALLY_N), dtype=torch.int64, device=dev)
+    gws = torch.empty(M.mc_negf_grad_workspace_bytes(k), dtype=torch.uint8, device=dev)
+    dV = torch.empty(wl.N, dtype=torch.float64, device=dev)
+    dg = torch.empty_like(dV)
+    etas, errs, walk_ms, grad_ms = [], [], [], []
+    for b in range(batches):
+        cnt.zero_()
+        tal.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        M.mc_negf_walk_counts(k, seed, 0, 0, b * walkers, walkers, 1_000_000, cnt, tal)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        M.mc_negf_grad_mc(k, 0, cnt, tal, tw, gws, dV, dg)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        walk_ms.append(1e3 * (t1 - t0))
+        grad_ms.append(1e3 * (t2 - t1))
+        etas.append(float(dg.sum().item()))
+        d = dV.cpu().numpy()
+        errs.append(float(np.linalg.norm(d - exact_V) / np.linalg.norm(exact_V)))
+    m, sd = float(np.mean(etas)), float(np.std(etas, ddof=1) / np.sqrt(batches))
+    out = {"what": "score-function gradient of the Monte Carlo current: walks with transition "
+                   "counts, then per-row block-tridiagonal solves of the count-weighted "
+                   "adjoint (all sites), against the exact adjoint",
+           "walkers_per_energy_per_batch": walkers, "batches": batches,
+           "walk_counts_ms": float(np.median(walk_ms)), "grad_from_counts_ms":
+               float(np.median(grad_ms)),
+           "dI_deta_batches": etas, "dI_deta_mean": m, "dI_deta_stderr": sd,
+           "dI_deta_exact": exact_eta, "dI_deta_err_in_sigma": (m - exact_eta) / sd if sd else None,
+           "rel_l2_err_dI_dV_per_batch": errs}
+    del k, ws, cnt, gws
     return out
 
 

@@ -332,3 +332,29 @@ def test_weighted_walk_sizes_and_validation_without_gpu():
     assert lib.mc_negf_weighted_tables_bytes(ctypes.byref(ks), ctypes.byref(out)) == M.EINVAL
     ks.wL, ks.alias_pitch = 4096, 4  # a pitch shorter than a row
     assert lib.mc_negf_weighted_tables_bytes(ctypes.byref(ks), ctypes.byref(out)) == M.EINVAL
+
+
+def test_score_gradient_entry_points_validate_on_the_host():
+    lib = M.lib()
+    ks = M.KernelStruct()
+    ks.W, ks.L, ks.N, ks.n_out, ks.nE, ks.p_pitch, ks.alias_pitch = 2, 3, 6, 8, 3, 16, 16
+    for f in ("alias", "alias_lo", "P", "lead", "status", "counters", "reduce", "wL", "wR",
+              "gamma", "Adiag", "gam_lead", "corner", "gL"):
+        setattr(ks, f, 4096)
+    out = ctypes.c_uint64(0)
+    assert lib.mc_negf_walk_counts_bytes(ctypes.byref(ks), ctypes.byref(out)) == M.OK
+    assert out.value == 3 * 8 * 8 * 4
+    z = ctypes.c_void_p(0)
+    p = ctypes.c_void_p(4096)
+    wc = lambda *a: lib.mc_negf_walk_counts(ctypes.byref(ks), *a)  # noqa: E731
+    assert wc(1, 0, 2, 0, 10, 10, p, p, z) == M.EINVAL               # lead
+    assert wc(1, 1 << 30, 0, 0, 10, 10, p, p, z) == M.EINVAL         # realization
+    assert wc(1, 0, 0, 0, 10, 0, p, p, z) == M.EINVAL                # max_steps
+    assert wc(1, 0, 0, 7, (1 << 32) - 7, 10, p, p, z) == M.EINVAL    # range
+    assert wc(1, 0, 0, 0, 10, 10, z, p, z) == M.EINVAL               # no counts
+    gm = lambda *a: lib.mc_negf_grad_mc(ctypes.byref(ks), *a)  # noqa: E731
+    assert gm(2, p, p, p, p, 1 << 40, p, p, z) == M.EINVAL           # lead
+    assert gm(0, z, p, p, p, 1 << 40, p, p, z) == M.EINVAL           # no counts
+    assert gm(0, p, p, p, p, 16, p, p, z) == M.EWS                   # workspace too small
+    ks.alias = 0  # counting walks need the kernel's own tables
+    assert wc(1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL

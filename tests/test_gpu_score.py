@@ -16,7 +16,6 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
-from oracle import dense as D  # noqa: E402
 from oracle import score as SC  # noqa: E402
 from paper_1805_10164_amd import mcnegf as M  # noqa: E402
 from test_gpu_parity import DEV, SEED, case, gpu_build, oracle_solve  # noqa: E402
@@ -124,3 +123,26 @@ def test_counts_argument_checks():
     with pytest.raises(M.McnegfError) as ei:
         M.mc_negf_grad_mc(k, 0, cnt, tal, torch.tensor(c["w"], device=DEV), small, dV, dV)
     assert ei.value.code == M.EWS
+
+
+def test_autograd_mc_current_uses_the_score_gradient():
+    from paper_1805_10164_amd import autograd as AG
+    c = case(W=3, L=5, eta=0.2, disorder=0.3, nE=3, emin=-1.2, emax=1.4, seed=2)
+    sysm = M.make_system(3, 5, 1.0, 0, 0.0, 1e-10)
+    V = torch.tensor(c["V"], dtype=torch.float64, device=DEV, requires_grad=True)
+    eta = torch.tensor(0.2, dtype=torch.float64, device=DEV, requires_grad=True)
+    E = torch.tensor(c["E"], dtype=torch.float64, device=DEV)
+    w = torch.tensor(c["w"], dtype=torch.float64, device=DEV)
+    I = AG.mc_current(sysm, V, eta * torch.ones(15, dtype=torch.float64, device=DEV), E, w,
+                      50_000, SEED)
+    I.backward()
+    # the same walks through the C ABI directly
+    k = gpu_build(c)
+    cnt, tal = gpu_counts(k, 50_000)
+    dV, dG = grad_mc(k, cnt, tal, c["w"])
+    T = torch.empty(3, dtype=torch.float64, device=DEV)
+    sg = torch.empty_like(T)
+    _, I_ref, _ = M.mc_negf_current(k, 0, 0, tal, w, T, sg)
+    assert float(I) == pytest.approx(I_ref, rel=1e-12)
+    assert np.abs(V.grad.cpu().numpy() - dV).max() <= 1e-12 * np.abs(dV).max()
+    assert float(eta.grad) == pytest.approx(dG.sum(), rel=1e-10)
