@@ -43,9 +43,8 @@ __device__ inline void block_matvec(double2 (&out)[W], const double2 (&in)[W], c
     }
 }
 
-// Per energy: mu_s = n_s / A_ss (n_s = steps out of probe s) into sv[0], and the number of
-// steps into probe o into sv[1] ([chunk][2][ld]).  Thread per site; the column sums read the
-// counts coalesced, the row sums stream each thread's own row.
+// Per energy: mu_s = n_s / A_ss (n_s = steps out of probe s, a column sum of the
+// outcome-major counts: threads over s read each row coalesced) into sv[0] ([chunk][2][ld]).
 __global__ void __launch_bounds__(256) score_prep_kernel(const uint32_t* __restrict__ counts,
                                                          const double* __restrict__ Adiag, int N,
                                                          int64_t ld, double* __restrict__ sv) {
@@ -54,13 +53,26 @@ __global__ void __launch_bounds__(256) score_prep_kernel(const uint32_t* __restr
     if (i >= N) return;
     const int n = N + 2;
     const uint32_t* C = counts + (size_t)e * n * n;
-    uint64_t out = 0, in = 0;
+    uint64_t out = 0;
     for (int o = 0; o < n; ++o) out += C[(size_t)o * n + i];
-    for (int s = 0; s < n; ++s) in += C[(size_t)i * n + s];
-    double* se = sv + (size_t)e * 2 * ld;
     const double a = Adiag[(size_t)e * N + i];
-    se[i] = out ? (double)out / a : 0.0;
-    se[ld + i] = (double)in;
+    sv[(size_t)e * 2 * ld + i] = out ? (double)out / a : 0.0;
+}
+
+// Per energy: the steps into probe o (a row sum of the counts) into sv[1]; one wavefront per
+// row, lanes striding along it.
+__global__ void __launch_bounds__(64) score_rowsum_kernel(const uint32_t* __restrict__ counts,
+                                                          int N, int64_t ld,
+                                                          double* __restrict__ sv) {
+    const int e = blockIdx.y;
+    const int o = blockIdx.x;
+    const int n = N + 2;
+    const uint32_t* row = counts + (size_t)e * n * n + (size_t)o * n;
+    uint64_t in = 0;
+    for (int s = threadIdx.x; s < n; s += 64) in += row[s];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) in += __shfl_xor(in, d, 64);
+    if (threadIdx.x == 0) sv[(size_t)e * 2 * ld + ld + o] = (double)in;
 }
 
 // One lane per right-hand side: c < N is row c of Psi (its probe entries and the diagonal
@@ -272,6 +284,12 @@ static hipError_t launch_score_w(const mcnegf_kernel& k, const GradBuffers& gb,
     }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
+    {
+        MCNEGF_TIMED("score_rowsum_kernel", s);
+        hipLaunchKernelGGL(score_rowsum_kernel, dim3(k.N, k.nE), dim3(64), 0, s, counts, k.N,
+                           gb.ld, gb.xl);
+    }
+    if ((err = hipGetLastError()) != hipSuccess) return err;
     {
         MCNEGF_TIMED("score_solve_kernel", s);
         hipLaunchKernelGGL(score_solve_kernel<W>, dim3((k.N + 2 * W + 63) / 64, k.nE), dim3(64),

@@ -358,3 +358,12 @@ def test_score_gradient_entry_points_validate_on_the_host():
     assert gm(0, p, p, p, p, 16, p, p, z) == M.EWS                   # workspace too small
     ks.alias = 0  # counting walks need the kernel's own tables
     assert wc(1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL
+
+
+def test_walker_build_keeps_the_atomic_optimizer_off():
+    # the walkers keep every lane active at each cross-lane operation; the AMDGPU atomic
+    # optimizer would put their uniform-address LDS atomics into first-lane-only regions
+    from paper_1805_10164_amd import build as B
+    assert "-amdgpu-atomic-optimizer-strategy=None" in B.EXTRA["walker.hip"]
+    assert all(f in B.FLAGS for f in ("-Xclang", "-packed-fp32-ops"))
+    assert "walker.hip" in B.SOURCES and "score.hip" in B.SOURCES

@@ -143,6 +143,6 @@ def test_autograd_mc_current_uses_the_score_gradient():
     T = torch.empty(3, dtype=torch.float64, device=DEV)
     sg = torch.empty_like(T)
     _, I_ref, _ = M.mc_negf_current(k, 0, 0, tal, w, T, sg)
-    assert float(I) == pytest.approx(I_ref, rel=1e-12)
+    assert float(I.detach()) == pytest.approx(I_ref, rel=1e-12)
     assert np.abs(V.grad.cpu().numpy() - dV).max() <= 1e-12 * np.abs(dV).max()
     assert float(eta.grad) == pytest.approx(dG.sum(), rel=1e-10)
