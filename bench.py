@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--no-chain", action="store_true", help="skip the N = 50 chain")
     ap.add_argument("--only", choices=["grad", "batched", "scale", "chain"], default=None,
                     help="run only this leg and print its object (profiling; no top-level metric)")
+    ap.add_argument("--serial-builds", action="store_true",
+                    help="issue the three dephasing rates' builds one after another on one stream")
     ap.add_argument("--scale-batches", type=int, default=None,
                     help="time only this many energy batches of the N = 16000 leg and skip its "
                          "FP32 variants (profiling runs)")
@@ -111,6 +113,31 @@ def run_step(p: Problem, walkers, seed, walk_on):
         M.mc_negf_walk(p.k, seed, p.wl.realization, 0, 0, walkers, 1_000_000, p.tal)
         M.mc_negf_current_async(p.k, 0, 0, p.tal, p.w, p.T, p.sig, p.out[0])
     M.mc_negf_current_async(p.k, 1, 0, None, p.w, p.Td, p.sigd, p.out[1])
+
+
+def run_step_overlapped(probs, streams, walkers, seed, walk_on):
+    """The step of run_step for several problems, with their builds (RGF sweeps, full inverse,
+    lead terms, alias tables: independent workspaces) issued on their own streams so that they
+    overlap, and the walks and both currents issued afterwards in order on the current stream
+    (a walk runs alone: its tables stay in the XCDs' L2)."""
+    import torch
+    main = torch.cuda.current_stream()
+    start = torch.cuda.Event()
+    start.record(main)
+    done = []
+    for p, st in zip(probs, streams):
+        st.wait_event(start)
+        p.k = M.mc_negf_build_kernel(p.sys, p.V, p.g, p.E, p.ws, stream=st)
+        ev = torch.cuda.Event()
+        ev.record(st)
+        done.append(ev)
+    for p, ev in zip(probs, done):
+        main.wait_event(ev)
+        if walk_on:
+            p.tal.zero_()
+            M.mc_negf_walk(p.k, seed, p.wl.realization, 0, 0, walkers, 1_000_000, p.tal)
+            M.mc_negf_current_async(p.k, 0, 0, p.tal, p.w, p.T, p.sig, p.out[0])
+        M.mc_negf_current_async(p.k, 1, 0, None, p.w, p.Td, p.sigd, p.out[1])
 
 
 def step_results(p: Problem, walk_on):
@@ -1081,9 +1108,14 @@ def main():
     if args.calib_copy_mb > 0:
         calibration_copy(torch, dev, args.calib_copy_mb)
 
+    build_streams = [torch.cuda.Stream(device=dev) for _ in probs]  # default priority
+
     def one_step():
-        for p in probs:
-            run_step(p, walkers, seed, walk_on)
+        if args.serial_builds:
+            for p in probs:
+                run_step(p, walkers, seed, walk_on)
+        else:
+            run_step_overlapped(probs, build_streams, walkers, seed, walk_on)
 
     # launches per step, from one more untimed step
     with M.LaunchTimes() as lt0:
