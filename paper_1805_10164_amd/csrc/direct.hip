@@ -279,7 +279,7 @@ __global__ void direct_prep_kernel(const double* __restrict__ P, const double* _
 //   L_JJ = chol(V_JJ),  Z = L_JJ^{-1}                (one wavefront, lane per row / column)
 //   L[below, J] = V_below L_JJ^{-T}   computed as (Z V_below^T)^T   (MFMA)
 // After the last block column, rows Np and Np+1 of L hold L^{-1} S T_p and L^{-1} S T_q.
-// One workgroup of 8 wavefronts per energy; each wavefront owns two 16-row tiles of a
+// One workgroup of 8 wavefronts per energy; each wavefront owns two 16-row tiles (w, w + 8) of a
 // 256-row super-tile and keeps their 16 x 64 updates in accumulators.  Block-column rows
 // L[J, 0:c0] are staged through LDS in 64-wide K chunks and serve as the MFMA A operand;
 // the tile rows stream from global memory as the B operand, so the accumulator holds the
@@ -355,16 +355,21 @@ __device__ inline void aorig4(const CholArgs& a, const double* Pe, const double*
 }
 
 // Staging of a block-column row segment (4 doubles at column col) through registers into LDS.
-// Rows beyond R read row R - 1 and are then zeroed by a select, so no load is predicated.
+// Rows beyond R read row R - 1 and are then scaled by 0 (a select would let the compiler turn
+// the load into a predicated one, and the branch around it makes every later wait for any load
+// a wait for all of them, the prefetched tile rows included).  Such rows only feed results
+// that are never stored (rows or columns beyond the matrix), so a non-finite value there is
+// harmless.
 __device__ inline double4 stage_load(const double* Le, int64_t ld, int R, int row, int col) {
     const bool ok = row < R;
     const double4 v = *reinterpret_cast<const double4*>(Le + (size_t)(ok ? row : R - 1) * ld + col);
-    return ok ? v : double4{0.0, 0.0, 0.0, 0.0};
+    const double m = ok ? 1.0 : 0.0;
+    return double4{v.x * m, v.y * m, v.z * m, v.w * m};
 }
 
-// MFMAs of one staged chunk for a wavefront's two 16-row tiles: NCB 16-column blocks of the
-// block column (A operand from LDS), tile rows (B operand) from registers.
-template <int NCB>
+// MFMAs of one staged chunk for the first NT of a wavefront's two 16-row tiles: NCB 16-column
+// blocks of the block column (A operand from LDS), tile rows (B operand) from registers.
+template <int NCB, int NT = 2>
 __device__ inline void chunk_mfma(const double* B, const double4 (&av)[2][CH_KG],
                                   dmfma4 (&acc)[2][4], int ln, int cq) {
 #pragma unroll
@@ -376,7 +381,7 @@ __device__ inline void chunk_mfma(const double* B, const double4 (&av)[2][CH_KG]
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
+            for (int t = 0; t < NT; ++t) {
                 const double bv = q == 0 ? av[t][kg].x : q == 1 ? av[t][kg].y
                                 : q == 2 ? av[t][kg].z : av[t][kg].w;
 #pragma unroll
@@ -551,7 +556,10 @@ __global__ void __launch_bounds__(512) cholesky_kernel(CholArgs a) {
 
         // ---- rows below the diagonal block, in super-tiles of 256 rows
         for (int st = c0 + wJ + part * CH_ROWS; st < R; st += a.nsplit * CH_ROWS) {
-            const int r0 = st + wave * 32;  // this wave's rows r0 .. r0 + 31
+            // this wave's tiles: rows rw[t] .. rw[t] + 15 for t = 0, 1, tile wave + 8 t of the
+            // super-tile, so that a partial super-tile gives each wavefront at most one tile
+            // when it holds at most 8 (the wavefronts' MFMA work is then halved)
+            const int rw[2] = {st + 16 * wave, st + 16 * (wave + 8)};
             dmfma4 acc[2][4];
 #pragma unroll
             for (int t = 0; t < 2; ++t)
@@ -568,43 +576,54 @@ __global__ void __launch_bounds__(512) cholesky_kernel(CholArgs a) {
                 for (int t = 0; t < 2; ++t)
 #pragma unroll
                     for (int kg = 0; kg < CH_KG; ++kg)
-                        av[t][kg] = stage_load(Le, ld, R, r0 + 16 * t + ln, 16 * kg + cq);
+                        av[t][kg] = stage_load(Le, ld, R, rw[t] + ln, 16 * kg + cq);
                 stage_store(Bs[0], sm, sc, stage_load(Le, ld, R, c0 + sm, sc));
                 __syncthreads();
-                for (int kc = 0, it = 0; kc < c0; kc += CH_KC, ++it) {
-                    const double* B = Bs[it & 1];
-                    const bool more = kc + CH_KC < c0;
-                    const int kn = more ? kc + CH_KC : kc;
-                    const double4 bst = stage_load(Le, ld, R, c0 + sm, kn + sc);
-                    double4 an[2][CH_KG];
+                // c0 = 64 J is a whole number of chunk pairs: the loop takes two chunks per
+                // iteration in straight-line code, the tile rows alternating between two
+                // register sets (chunk 2i multiplies av while an is loaded, chunk 2i + 1 the
+                // reverse) and the staged block-column rows between the two LDS buffers, so
+                // neither the loads nor the accumulators are copied.  All four 16-column
+                // blocks are multiplied (a narrower last block column's extra blocks are
+                // never stored), so the accumulators keep their registers.
+                double4 an[2][CH_KG];
+                for (int kc = 0; kc < c0; kc += 2 * CH_KC) {
+                    {
+                        const int kn = kc + CH_KC;  // always inside: c0 is a multiple of 64
+                        const double4 bst = stage_load(Le, ld, R, c0 + sm, kn + sc);
 #pragma unroll
-                    for (int t = 0; t < 2; ++t)
+                        for (int t = 0; t < 2; ++t)
 #pragma unroll
-                        for (int kg = 0; kg < CH_KG; ++kg)
-                            an[t][kg] = stage_load(Le, ld, R, r0 + 16 * t + ln, kn + 16 * kg + cq);
-                    if (r0 < R) {
-                        switch (ncb) {
-                            case 4: chunk_mfma<4>(B, av, acc, ln, cq); break;
-                            case 3: chunk_mfma<3>(B, av, acc, ln, cq); break;
-                            case 2: chunk_mfma<2>(B, av, acc, ln, cq); break;
-                            default: chunk_mfma<1>(B, av, acc, ln, cq); break;
-                        }
+                            for (int kg = 0; kg < CH_KG; ++kg)
+                                an[t][kg] = stage_load(Le, ld, R, rw[t] + ln, kn + 16 * kg + cq);
+                        if (rw[1] < R) chunk_mfma<4, 2>(Bs[0], av, acc, ln, cq);
+                        else if (rw[0] < R) chunk_mfma<4, 1>(Bs[0], av, acc, ln, cq);
+                        stage_store(Bs[1], sm, sc, bst);
+                        __syncthreads();
                     }
-                    if (more) stage_store(Bs[(it & 1) ^ 1], sm, sc, bst);
-                    __syncthreads();
+                    {
+                        const bool more = kc + 2 * CH_KC < c0;
+                        const int kn = more ? kc + 2 * CH_KC : kc + CH_KC;
+                        const double4 bst = stage_load(Le, ld, R, c0 + sm, kn + sc);
 #pragma unroll
-                    for (int t = 0; t < 2; ++t)
+                        for (int t = 0; t < 2; ++t)
 #pragma unroll
-                        for (int kg = 0; kg < CH_KG; ++kg) av[t][kg] = an[t][kg];
+                            for (int kg = 0; kg < CH_KG; ++kg)
+                                av[t][kg] = stage_load(Le, ld, R, rw[t] + ln, kn + 16 * kg + cq);
+                        if (rw[1] < R) chunk_mfma<4, 2>(Bs[1], an, acc, ln, cq);
+                        else if (rw[0] < R) chunk_mfma<4, 1>(Bs[1], an, acc, ln, cq);
+                        if (more) stage_store(Bs[0], sm, sc, bst);
+                        __syncthreads();
+                    }
                 }
             }
-            // V = A - update (lane: row r0 + 16 t + ln, columns c0 + 16 cb + 4 r + g), then
+            // V = A - update (lane: row rw[t] + ln, columns c0 + 16 cb + 4 r + g), then
             // X L_JJ^T = V by 16-column blocks: X_b^T = L_bb^{-1} (V_b^T - sum_{a<b} L_ba X_a^T),
             // stored as rows of L.  V^T and X^T blocks are in accumulator layout, which is the
             // B-operand layout of the next product.
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
-                const int rt = r0 + 16 * t;
+                const int rt = rw[t];
                 if (rt < R) {
                     dmfma4 y[4];
 #pragma unroll
@@ -612,8 +631,10 @@ __global__ void __launch_bounds__(512) cholesky_kernel(CholArgs a) {
                         double ao[4];
                         if (cb < ncb) aorig4(a, Pe, ve, rt + ln, c0 + 16 * cb + g, ao);
                         else ao[0] = ao[1] = ao[2] = ao[3] = 0.0;
+                        // blocks beyond the block column's width hold the unused products of
+                        // the update: zero, as the bordered rows' dot product below reads them
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) y[cb][r] = ao[r] - acc[t][cb][r];
+                        for (int r = 0; r < 4; ++r) y[cb][r] = cb < ncb ? ao[r] - acc[t][cb][r] : 0.0;
                     }
 #pragma unroll
                     for (int mb = 0; mb < 4; ++mb) {
