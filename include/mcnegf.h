@@ -299,7 +299,9 @@ int32_t mc_negf_grad(const mcnegf_kernel* k, uint32_t inject_lead, const double*
  *   energy, drawing exactly as mc_negf_walk; adds to d_counts [nE][n_out][n_out] (uint32,
  *   device, outcome-major: d_counts[e][o][s] counts steps s -> o; caller-owned, zeroed by the
  *   caller before the first call) the steps of every walk that exits at q, and their exit
- *   counts to d_tallies as mc_negf_walk.  Needs a kernel with alias tables.  Asynchronous.
+ *   counts to d_tallies as mc_negf_walk.  Each entry is a 32-bit count (it wraps beyond
+ *   2^32 - 1 steps s -> o; split larger runs and sum the gradients).  Needs a kernel with
+ *   alias tables.  Asynchronous.
  * mc_negf_grad_mc: from those counts and tallies, d_dI_dV [N] and d_dI_dgamma [N] (device)
  *   = sum_k w_k times the estimate above at energy k (dgamma: gamma_i > 0; for gamma_i = 0 the
  *   walks never enter site i and the explicit term is taken as 0).  d_gws: the workspace of
