@@ -1110,19 +1110,23 @@ def main():
 
     build_streams = [torch.cuda.Stream(device=dev) for _ in probs]  # default priority
 
+    def one_step_serial():
+        for p in probs:
+            run_step(p, walkers, seed, walk_on)
+
     def one_step():
         if args.serial_builds:
-            for p in probs:
-                run_step(p, walkers, seed, walk_on)
+            one_step_serial()
         else:
             run_step_overlapped(probs, build_streams, walkers, seed, walk_on)
 
     # launches per step, from one more untimed step
     with M.LaunchTimes() as lt0:
-        one_step()
+        one_step_serial()
     per_step = len(require_complete(lt0).records)
     # the timed steps run without the launch timer (its two events per launch slow a step by
-    # about 9%); the same steps are then run again under the timer for the per-kernel figures
+    # about 9%); the same steps are then run again under the timer for the per-kernel figures,
+    # with the builds issued one after another so that every launch's duration is its own
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -1130,7 +1134,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     t0 = time.perf_counter()
-    records = timed_records(args.steps, per_step, one_step)
+    records = timed_records(args.steps, per_step, one_step_serial)
     torch.cuda.synchronize()
     wall_instrumented = time.perf_counter() - t0
     # every step walks the same seeded walkers, so each step's counts are the last step's
@@ -1166,6 +1170,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": 1e3 * wall / args.steps,
         "ms_per_step_with_launch_timer": 1e3 * wall_instrumented / args.steps,
+        "per_kernel_timing": "every launch timed with HIP events, builds issued serially",
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
