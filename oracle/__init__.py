@@ -14,4 +14,12 @@ Contents:
   walker.py   ctypes wrapper and build step for walker.c.
   grad.py     dI/dV_i and dI/dgamma_i of the DIRECT current: reverse-mode differentiation
               (torch autograd, CPU) of a dense evaluation, and central differences.
+  columns.py  sampled columns of G at sizes the dense solve cannot hold (sparse LU).
+  interp.py   step-6' rows interpolated between energy nodes (Sec. V A, "Interpolation").
+  weighted.py importance-sampled walks and their path-ratio estimator (Sec. V A,
+              "Improved estimator").
+  score.py    score-function gradient of the Monte Carlo estimator and expected counts.
+  inelastic.py  step 7' (Sec. II F): the energy draw of inelastic Buttiker walks, its
+              threshold table, the exact exit distribution of the (energy, probe) chain and
+              the energy-resolved current; walks by walker.c.
 """

@@ -564,6 +564,122 @@ int oracle_walk_interp_alias(const uint32_t *thr, const int32_t *alias, int64_t 
 }
 
 /*
+ * Inelastic walks (Sec. II F, step 7'): after step 6' draws a probe i at energy E_n, the walk
+ * draws its next energy E_n + Delta_k, k in [0, n_off), from the table `etab` and continues
+ * from probe i's row at that energy.  etab[e][i][k] (uint64) holds cumulative thresholds on the
+ * 2^32 scale: the first k with r < etab[e][i][k] is drawn (k = n_off - 1 if none is).  The walk
+ * keeps the random stream of its injection energy e0 (block j of the step-6' words: counter
+ * (j, w, e0, tag), Lemire redraws as above); the 32-bit word r of step n is word (n & 3) of
+ * Philox(counter = (n >> 2, w, e0, tag), key = (~key0, key1)).  A drawn energy outside
+ * [0, nE) ends the walk as truncated and sets *bad.  Tallies per injection energy (as above);
+ * hist[r][e0][e] (int64, accumulated) counts the walks injected at e0 that exit at lead r
+ * with energy index e.
+ * mode 0: cumulative-sum sampler on K [nE][n][n]; mode 1: alias tables [nE][n][pitch].
+ */
+static int walk_inelastic_impl(int mode, const double *K, const uint32_t *thr,
+                               const int32_t *alias, int64_t pitch, int32_t nE, int32_t n,
+                               const uint64_t *etab, const int32_t *offsets, int32_t n_off,
+                               uint64_t seed, uint32_t realization, uint32_t inject_lead,
+                               uint64_t walker_begin, uint64_t n_walkers, uint32_t max_steps,
+                               int64_t *tallies, int64_t *hist, int32_t *bad)
+{
+    if (n < 3 || nE < 1 || n_off < 1 || inject_lead > 1 || realization >= (1u << 30)) return -1;
+    if (walker_begin + n_walkers > 0x100000000ull) return -1;
+    const int32_t N = n - 2;
+    const uint32_t tag = (realization << 1) | inject_lead;
+    int32_t any_bad = 0;
+    for (int32_t e0 = 0; e0 < nE; ++e0) {
+        int64_t cL = 0, cR = 0, tr = 0, s1 = 0, s2 = 0;
+        int64_t *hL = hist + (int64_t)e0 * nE;
+        int64_t *hR = hist + ((int64_t)nE + e0) * nE;
+#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : cL, cR, tr, s1, s2) \
+    reduction(| : any_bad)
+        for (int64_t i = 0; i < (int64_t)n_walkers; ++i) {
+            const uint32_t w = (uint32_t)(walker_begin + (uint64_t)i);
+            stream_t st;
+            stream_init(&st, seed, w, (uint32_t)e0, tag);
+            const uint32_t ekey[2] = {~st.key[0], st.key[1]};
+            uint32_t eblock = 0xffffffffu, ewords[4];
+            int32_t s = N + (int32_t)inject_lead, e = e0;
+            uint32_t steps = 0;
+            int outcome = -1;
+            while (steps < max_steps) {
+                uint32_t a, b;
+                stream_pair(&st, steps, &a, &b);
+                int32_t next;
+                if (mode == 0) {
+                    next = draw_cdf(K + ((int64_t)e * n + s) * (int64_t)n, n, a, b);
+                } else {
+                    uint32_t c = lemire_bucket(&st, steps, a, (uint32_t)n);
+                    int64_t x = ((int64_t)e * n + s) * pitch + c;
+                    next = (b < thr[x]) ? (int32_t)c : alias[x];
+                }
+                const uint32_t n_step = steps++;
+                if (next >= N) { outcome = next - N; break; }
+                /* step 7': the energy of the next row */
+                if (eblock != n_step >> 2) {
+                    const uint32_t ctr[4] = {n_step >> 2, w, (uint32_t)e0, tag};
+                    oracle_philox4x32_10(ctr, ekey, ewords);
+                    eblock = n_step >> 2;
+                }
+                const uint32_t r = ewords[n_step & 3];
+                const uint64_t *t = etab + ((int64_t)e * N + next) * n_off;
+                int32_t k = 0;
+                while (k < n_off - 1 && (uint64_t)r >= t[k]) ++k;
+                const int32_t en = e + offsets[k];
+                if (en < 0 || en >= nE) { any_bad = 1; break; }
+                e = en;
+                s = next;
+            }
+            if (outcome == 0) {
+                ++cL;
+#pragma omp atomic
+                hL[e] += 1;
+            } else if (outcome == 1) {
+                ++cR;
+#pragma omp atomic
+                hR[e] += 1;
+            } else {
+                ++tr;
+            }
+            s1 += steps;
+            s2 += (int64_t)steps * (int64_t)steps;
+        }
+        tallies[5 * e0 + 0] += cL;
+        tallies[5 * e0 + 1] += cR;
+        tallies[5 * e0 + 2] += tr;
+        tallies[5 * e0 + 3] += s1;
+        tallies[5 * e0 + 4] += s2;
+    }
+    if (bad) *bad = any_bad;
+    return 0;
+}
+
+int oracle_walk_inelastic_cdf(const double *K, int32_t nE, int32_t n, const uint64_t *etab,
+                              const int32_t *offsets, int32_t n_off, uint64_t seed,
+                              uint32_t realization, uint32_t inject_lead, uint64_t walker_begin,
+                              uint64_t n_walkers, uint32_t max_steps, int64_t *tallies,
+                              int64_t *hist, int32_t *bad)
+{
+    return walk_inelastic_impl(0, K, NULL, NULL, 0, nE, n, etab, offsets, n_off, seed,
+                               realization, inject_lead, walker_begin, n_walkers, max_steps,
+                               tallies, hist, bad);
+}
+
+int oracle_walk_inelastic_alias(const uint32_t *thr, const int32_t *alias, int64_t pitch,
+                                int32_t nE, int32_t n, const uint64_t *etab,
+                                const int32_t *offsets, int32_t n_off, uint64_t seed,
+                                uint32_t realization, uint32_t inject_lead,
+                                uint64_t walker_begin, uint64_t n_walkers, uint32_t max_steps,
+                                int64_t *tallies, int64_t *hist, int32_t *bad)
+{
+    if (pitch < n) return -1;
+    return walk_inelastic_impl(1, NULL, thr, alias, pitch, nE, n, etab, offsets, n_off, seed,
+                               realization, inject_lead, walker_begin, n_walkers, max_steps,
+                               tallies, hist, bad);
+}
+
+/*
  * Search for rejected bucket words: walkers w of [w_begin, w_begin + count) at energy index k
  * whose draw of step n_step over nout outcomes needs at least min_redraws redraws (Lemire's
  * rejection above).  Writes up to max_out walker indices, their redraw counts and their
