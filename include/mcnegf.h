@@ -321,6 +321,57 @@ int32_t mc_negf_grad_mc(const mcnegf_kernel* k, uint32_t inject_lead, const uint
                         hipStream_t stream);
 
 /*
+ * Inelastic walks: step 7' of Sec. II F.  With Buttiker's approximation and an energy-changing
+ * coupling lambda~_i(E, E'), a walker that step 6' sends to probe i at energy E_n draws its next
+ * energy from p(E) = lambda~_i(E, E_n) A_ii(E) / (integral over E of the same) (the probability
+ * that follows the choice of the index, Sec. II F) and continues from probe i's row at that
+ * energy.  The coupling here is a set of lines on the energy grid of the handle,
+ *   lambda~_i(E, E_n) = sum_k lambda_k delta(E - E_n - Delta_k),  Delta_k = offsets[k] grid steps,
+ * the same for every site (e.g. an elastic line at 0 and phonon emission / absorption lines at
+ * -m / +m); a line that leaves the grid has weight 0.  The energies must be evenly spaced for
+ * a line to be a fixed energy transfer (not checked).  The dephasing rates gamma_i of the build
+ * stay the caller's: condition (iv) of Sec. II F ties them to the coupling, but the walk is a
+ * proper Markov chain either way (step 7' is normalised by its own sum).
+ *   n_lines    1 .. 8 lines; h_offsets [n_lines] host, |offset| < nE; h_lambda [n_lines] host,
+ *              finite, >= 0, and from every energy some line of positive weight stays on the grid
+ *              (else MCNEGF_EINVAL).
+ * mc_negf_energy_table_bytes (host only): nE * N * n_lines * 8.
+ * mc_negf_energy_table: d_table [nE][N][n_lines] (uint64, device, caller-owned) from the
+ *   handle's A_jj: x_k = lambda_k A_ii(E_e + Delta_k) summed in order (FP64, cum_k), then
+ *   t_k = floor(2^32 cum_k / cum_last).  A non-positive or non-finite total writes 2^32
+ *   everywhere (line 0 is drawn) and sets MCNEGF_FLAG_NONFINITE.  MCNEGF_EWS if table_bytes is
+ *   too small.  Asynchronous.
+ * mc_negf_walk_inelastic: walkers [walker_begin, walker_begin + n_walkers) (< 2^32) injected at
+ *   lead inject_lead at every energy e0 of the handle (nE <= 4096), on its alias tables, with
+ *   step 7' drawn from d_table (the offsets must be those the table was built with): the first
+ *   k with r < t_k (k = n_lines - 1 if none) for the 32-bit word r of the step.  A walker keeps
+ *   the random stream of its injection energy: step-6' words and Lemire redraws as
+ *   mc_negf_walk at e0; the word of step n's energy draw is word (n & 3) of Philox4x32-10 at
+ *   counter (n >> 2, w, e0, tag), key (~key0, key1).  With the single line Delta = 0 the walks
+ *   are mc_negf_walk's.  Adds to d_tallies [nE][MCNEGF_TALLY_N] (device, per injection energy,
+ *   as mc_negf_walk; mc_negf_current in mode 0 gives the current: a walker scores c_p(e0) at an
+ *   exit at q) and to d_hist [2][nE][nE] (int64, device, caller-zeroed): hist[r][e0][e] counts
+ *   walkers from e0 absorbed at lead r with energy e.  A table that sends a walk off the grid
+ *   ends it as truncated and sets MCNEGF_FLAG_RANGE; max_steps truncation sets
+ *   MCNEGF_FLAG_TRUNC.  Asynchronous.
+ * mc_negf_spectrum: d_spectrum [2][nE] (device) = the energy-resolved current
+ *   S[r][e] = sum_e0 w_e0 c_p(e0) hist[r][e0][e] / N_e0 (N_e0 the walkers injected at e0);
+ *   sum_e S[q][e] is the current of the tallies.  Asynchronous.
+ */
+int32_t mc_negf_energy_table_bytes(const mcnegf_kernel* k, int32_t n_lines, uint64_t* bytes_out);
+int32_t mc_negf_energy_table(const mcnegf_kernel* k, int32_t n_lines, const int32_t* h_offsets,
+                             const double* h_lambda, uint64_t* d_table, uint64_t table_bytes,
+                             hipStream_t stream);
+int32_t mc_negf_walk_inelastic(const mcnegf_kernel* k, int32_t n_lines, const int32_t* h_offsets,
+                               const uint64_t* d_table, uint64_t seed, uint32_t realization,
+                               uint32_t inject_lead, uint64_t walker_begin, uint64_t n_walkers,
+                               uint32_t max_steps, int64_t* d_tallies, int64_t* d_hist,
+                               hipStream_t stream);
+int32_t mc_negf_spectrum(const mcnegf_kernel* k, uint32_t inject_lead, const int64_t* d_tallies,
+                         const int64_t* d_hist, const double* d_weights, double* d_spectrum,
+                         hipStream_t stream);
+
+/*
  * Energy-sampled walks (Sec. II F step 2: the starting energy drawn from a density h; with
  * h proportional to the quadrature weights the estimator of Eq. (66) becomes the constant
  * W c_p(E_0) [exit at q], W = sum_k w_k — the paper's choice h = Th(E) when w_k = Th(E_k) dE).

@@ -161,6 +161,19 @@ hipError_t launch_lead_terms(const mcnegf_kernel& k, hipStream_t s);
 hipError_t launch_alias_build(const mcnegf_kernel& k, double rowsum_tol, hipStream_t s);
 // Transition counts of the walks that reach the collecting lead ([nE][n][n] uint32,
 // outcome-major), and the score-function gradient of the Monte Carlo estimator from them.
+// Inelastic walks (step 7'): at most kMaxLines energy lines; the walker keeps an exit-energy
+// histogram of 2 nE counters in LDS, so nE <= kMaxInelasticE.
+constexpr int kMaxLines = 8;
+constexpr int kMaxInelasticE = 4096;
+hipError_t launch_energy_table(const mcnegf_kernel& k, int n_lines, const int32_t* off,
+                               const double* lam, uint64_t* table, hipStream_t s);
+hipError_t launch_walk_inelastic(const mcnegf_kernel& k, int n_lines, const int32_t* off,
+                                 const uint64_t* table, uint64_t seed, uint32_t tag,
+                                 uint32_t walker_begin, uint32_t n_walkers, uint32_t max_steps,
+                                 int64_t* tallies, int64_t* hist, hipStream_t s);
+hipError_t launch_spectrum(const mcnegf_kernel& k, uint32_t inject_lead, const int64_t* tallies,
+                           const int64_t* hist, const double* weights, double* spectrum,
+                           hipStream_t s);
 hipError_t launch_walk_counts(const mcnegf_kernel& k, uint64_t seed, uint32_t tag,
                               uint32_t walker_begin, uint32_t n_walkers, uint32_t max_steps,
                               uint32_t* counts, int64_t* tallies, hipStream_t s);

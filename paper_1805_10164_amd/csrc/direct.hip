@@ -88,6 +88,44 @@ hipError_t launch_mc_current(const mcnegf_kernel& k, uint32_t inject_lead, const
     return hipGetLastError();
 }
 
+// Energy-resolved current of inelastic walks (step 7'): a walker injected at lead p at energy
+// e0 scores c_p(e0) at its exit, so the exits at lead r with energy e give
+//   S[r][e] = sum_e0 w_e0 c_p(e0) hist[r][e0][e] / N_e0
+// (N_e0 the walkers injected at e0, truncated ones included); sum_e S[q][e] is the current of
+// the tallies.  One thread per (r, e); the sum over e0 runs in order.
+__global__ void __launch_bounds__(256) spectrum_kernel(const int64_t* __restrict__ tallies,
+                                                       const int64_t* __restrict__ hist,
+                                                       const double* __restrict__ lead,
+                                                       const double* __restrict__ weights,
+                                                       int nE, uint32_t inject_lead,
+                                                       double* __restrict__ S) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 2 * nE) return;
+    const int r = idx / nE, e = idx % nE;
+    double acc = 0.0;
+    for (int e0 = 0; e0 < nE; ++e0) {
+        const int64_t* t = tallies + (size_t)e0 * MCNEGF_TALLY_N;
+        const int64_t nw = t[MCNEGF_TALLY_EXIT_L] + t[MCNEGF_TALLY_EXIT_R] + t[MCNEGF_TALLY_TRUNC];
+        const int64_t h = hist[((size_t)r * nE + e0) * nE + e];
+        if (nw <= 0 || h == 0) continue;
+        const double c = lead[(size_t)e0 * MCNEGF_LEAD_NTERMS +
+                              (inject_lead == 0 ? MCNEGF_LEAD_CL : MCNEGF_LEAD_CR)];
+        acc += weights[e0] * c / (double)nw * (double)h;
+    }
+    S[idx] = acc;
+}
+
+hipError_t launch_spectrum(const mcnegf_kernel& k, uint32_t inject_lead, const int64_t* tallies,
+                           const int64_t* hist, const double* weights, double* spectrum,
+                           hipStream_t s) {
+    {
+        MCNEGF_TIMED("spectrum_kernel", s);
+        hipLaunchKernelGGL(spectrum_kernel, dim3((2 * k.nE + 255) / 256), dim3(256), 0, s,
+                           tallies, hist, k.lead, weights, k.nE, inject_lead, spectrum);
+    }
+    return hipGetLastError();
+}
+
 // Importance-sampled walks (Sec. V A, "Improved estimator"): per energy the N_k walkers'
 // scores (path likelihood ratios at an exit at q, else 0) have sums S1, S2; then
 //   T_k = c_p S1 / N_k,  sigma_k = c_p sqrt(s^2 / N_k),  s^2 = (S2 - S1^2 / N_k) / (N_k - 1).

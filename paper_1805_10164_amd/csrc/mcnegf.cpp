@@ -396,6 +396,78 @@ int32_t mc_negf_grad_mc(const mcnegf_kernel* k, uint32_t inject_lead, const uint
     return err == hipSuccess ? MCNEGF_OK : hip_fail(err);
 }
 
+// ---- inelastic walks (step 7') -----------------------------------------------------------
+
+// Host check of the energy lines: 1..kMaxLines lines, |offset| < nE, lambda finite and >= 0,
+// and from every energy some line of positive weight stays on the grid.
+static bool valid_lines(const mcnegf_kernel& k, int32_t n_lines, const int32_t* off,
+                        const double* lam) {
+    if (n_lines < 1 || n_lines > kMaxLines || !off) return false;
+    for (int j = 0; j < n_lines; ++j)
+        if (off[j] <= -k.nE || off[j] >= k.nE) return false;
+    if (lam) {
+        for (int j = 0; j < n_lines; ++j)
+            if (!(lam[j] >= 0.0) || !std::isfinite(lam[j])) return false;
+        for (int e = 0; e < k.nE; ++e) {
+            bool any = false;
+            for (int j = 0; j < n_lines; ++j)
+                any = any || (lam[j] > 0.0 && e + off[j] >= 0 && e + off[j] < k.nE);
+            if (!any) return false;
+        }
+    }
+    return true;
+}
+
+int32_t mc_negf_energy_table_bytes(const mcnegf_kernel* k, int32_t n_lines,
+                                   uint64_t* bytes_out) {
+    if (!valid_kernel(k) || !bytes_out || n_lines < 1 || n_lines > kMaxLines)
+        return MCNEGF_EINVAL;
+    *bytes_out = (uint64_t)k->nE * (uint64_t)k->N * (uint64_t)n_lines * 8;
+    return MCNEGF_OK;
+}
+
+int32_t mc_negf_energy_table(const mcnegf_kernel* k, int32_t n_lines, const int32_t* h_offsets,
+                             const double* h_lambda, uint64_t* d_table, uint64_t table_bytes,
+                             hipStream_t stream) {
+    if (!valid_kernel(k) || !k->Adiag || !d_table || !h_lambda ||
+        !valid_lines(*k, n_lines, h_offsets, h_lambda))
+        return MCNEGF_EINVAL;
+    if (table_bytes < (uint64_t)k->nE * (uint64_t)k->N * (uint64_t)n_lines * 8)
+        return MCNEGF_EWS;
+    hipError_t err = launch_energy_table(*k, n_lines, h_offsets, h_lambda, d_table, stream);
+    return err == hipSuccess ? MCNEGF_OK : hip_fail(err);
+}
+
+int32_t mc_negf_walk_inelastic(const mcnegf_kernel* k, int32_t n_lines, const int32_t* h_offsets,
+                               const uint64_t* d_table, uint64_t seed, uint32_t realization,
+                               uint32_t inject_lead, uint64_t walker_begin, uint64_t n_walkers,
+                               uint32_t max_steps, int64_t* d_tallies, int64_t* d_hist,
+                               hipStream_t stream) {
+    if (!valid_kernel(k) || !k->alias || !k->alias_lo || !d_table || !d_tallies || !d_hist ||
+        !valid_lines(*k, n_lines, h_offsets, nullptr) || k->nE > kMaxInelasticE ||
+        inject_lead > 1 || realization >= (1u << 30) || max_steps < 1)
+        return MCNEGF_EINVAL;
+    if (walker_begin >= 0x100000000ull || n_walkers >= 0x100000000ull ||
+        walker_begin + n_walkers >= 0x100000000ull)
+        return MCNEGF_EINVAL;
+    const uint32_t tag = (realization << 1) | inject_lead;
+    hipError_t err = launch_walk_inelastic(*k, n_lines, h_offsets, d_table, seed, tag,
+                                           (uint32_t)walker_begin, (uint32_t)n_walkers,
+                                           max_steps, d_tallies, d_hist, stream);
+    return err == hipSuccess ? MCNEGF_OK : hip_fail(err);
+}
+
+int32_t mc_negf_spectrum(const mcnegf_kernel* k, uint32_t inject_lead, const int64_t* d_tallies,
+                         const int64_t* d_hist, const double* d_weights, double* d_spectrum,
+                         hipStream_t stream) {
+    if (!valid_kernel(k) || !k->lead || !d_tallies || !d_hist || !d_weights || !d_spectrum ||
+        inject_lead > 1)
+        return MCNEGF_EINVAL;
+    hipError_t err = launch_spectrum(*k, inject_lead, d_tallies, d_hist, d_weights, d_spectrum,
+                                     stream);
+    return err == hipSuccess ? MCNEGF_OK : hip_fail(err);
+}
+
 int32_t mc_negf_profile_begin(mcnegf_profile* p) {
     if (!p || g_profile) return MCNEGF_EINVAL;
     std::memset(p, 0, sizeof(*p));

@@ -1618,4 +1618,232 @@ hipError_t launch_walk_counts(const mcnegf_kernel& k, uint64_t seed, uint32_t ta
     return hipGetLastError();
 }
 
+// ---- inelastic walks (Sec. II F, step 7') -------------------------------------------------
+//
+// After step 6' draws probe i at energy E_n, step 7' draws the next energy: with the coupling
+// lambda~_i(E, E_n) = sum_k lambda_k delta(E - E_n - Delta_k) (lines on the energy grid,
+// Delta_k = off[k] grid steps) the walk moves to E_n + Delta_k with probability
+// x_k / sum x, x_k = lambda_k A_ii(E_n + Delta_k) (zero off the grid), and continues from
+// probe i's row at that energy.  The table holds, per (energy, probe), the running sums of x
+// on the 2^32 scale: t_k = floor(2^32 cum_k / total); the first k with r < t_k is drawn for
+// a 32-bit word r (k = n_lines - 1 if none is).
+
+struct LineArgs {
+    const double* Adiag;  // [nE][N]
+    uint64_t* table;      // [nE][N][n_lines]
+    uint32_t* status;
+    int32_t N, nE, n_lines;
+    int32_t off[kMaxLines];
+    double lam[kMaxLines];
+};
+
+__global__ void __launch_bounds__(256) energy_table_kernel(LineArgs A) {
+    // plain products and sums in order: a fused multiply-add would round differently from
+    // the threshold definition
+#pragma clang fp contract(off)
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)A.nE * A.N) return;
+    const int e = (int)(idx / A.N), i = (int)(idx % A.N);
+    double cum[kMaxLines];
+    double c = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxLines; ++k) {
+        if (k < A.n_lines) {
+            const int en = e + A.off[k];
+            const double x = (en >= 0 && en < A.nE) ? A.lam[k] * A.Adiag[(int64_t)en * A.N + i]
+                                                     : 0.0;
+            c = c + x;
+            cum[k] = c;
+        }
+    }
+    const bool ok = c > 0.0 && c < __builtin_inf();
+    uint64_t* t = A.table + idx * A.n_lines;
+#pragma unroll
+    for (int k = 0; k < kMaxLines; ++k)
+        if (k < A.n_lines) t[k] = ok ? (uint64_t)(cum[k] / c * 4294967296.0) : (1ull << 32);
+    if (!ok) atomicOr(A.status, MCNEGF_FLAG_NONFINITE);
+}
+
+hipError_t launch_energy_table(const mcnegf_kernel& k, int n_lines, const int32_t* off,
+                               const double* lam, uint64_t* table, hipStream_t s) {
+    LineArgs A;
+    A.Adiag = k.Adiag;
+    A.table = table;
+    A.status = k.status;
+    A.N = k.N;
+    A.nE = k.nE;
+    A.n_lines = n_lines;
+    for (int j = 0; j < kMaxLines; ++j) {
+        A.off[j] = j < n_lines ? off[j] : 0;
+        A.lam[j] = j < n_lines ? lam[j] : 0.0;
+    }
+    const int64_t n = (int64_t)k.nE * k.N;
+    {
+        MCNEGF_TIMED("energy_table_kernel", s);
+        hipLaunchKernelGGL(energy_table_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                           s, A);
+    }
+    return hipGetLastError();
+}
+
+// The walk: a walker keeps the random stream of its injection energy e0 (step-6' words and
+// Lemire redraws exactly as the elastic walker at e0); the word r of step n's energy draw is
+// word (n & 3) of Philox(counter (n >> 2, w, e0, tag), key (~key0, key1)).  With the single
+// line Delta = 0 the walk is the elastic walk, step for step.
+struct InelasticArgs {
+    CountArgs c;             // tables, stream, walkers, tallies, status (counts unused)
+    const uint64_t* table;   // [nE][N][n_lines]
+    unsigned long long* hist;  // [2][nE][nE]: exits at lead r of walkers from e0 at energy e
+    int32_t n_lines;
+    int32_t off[kMaxLines];
+};
+
+// Walkers per lane: a workgroup walks 256 * kInelasticPerLane walkers of one injection energy
+// and flushes its exit-energy histogram (LDS, 2 nE counters) once.
+constexpr uint32_t kInelasticPerLane = 16;
+
+__global__ void __launch_bounds__(256) walk_inelastic_kernel(InelasticArgs A) {
+    extern __shared__ uint32_t hsh[];  // [2][nE]
+    const CountArgs& C = A.c;
+    const uint32_t e0 = blockIdx.y, nE = C.nE, N = C.N;
+    for (uint32_t b = threadIdx.x; b < 2 * nE; b += blockDim.x) hsh[b] = 0;
+    __syncthreads();
+    const uint32_t p = C.tag & 1u;
+    const uint32_t ekey0 = ~C.key0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t wi = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t cL = 0, cR = 0, tr = 0;
+    uint64_t s1 = 0, s2 = 0;
+    bool bad = false;
+    // one step per iteration for every live lane; a lane whose walk ends takes its next
+    // walker at once (per-lane state, no cross-lane operation inside the loop)
+    bool live = wi < C.n_walkers;
+    uint32_t w = C.wbegin + (uint32_t)(live ? wi : 0);
+    uint32_t s = N + p, e = e0, steps = 0, eblk_i = 0xffffffffu;
+    Philox4 blk, eblk;
+    while (live) {
+        if ((steps & 1u) == 0u) blk = philox4x32_10(steps >> 1, w, e0, C.tag, C.key0, C.key1);
+        // words by selects (a dynamic index would place the block in scratch memory)
+        const bool odd = (steps & 1u) != 0u;
+        const uint32_t a = odd ? blk.x[2] : blk.x[0], b = odd ? blk.x[3] : blk.x[1];
+        const gtable_ptr tb = (gtable_ptr)(C.tables + (size_t)e * C.table_stride);
+        const uint16_t* lo = C.lows + (size_t)e * C.table_stride;
+        const uint32_t next = draw_step(C, tb, lo, s, steps, w, e0, a, b);
+        const uint32_t n = steps++;
+        int outcome = -2;  // -2: walking on; -1: truncated or off the grid; 0/1: lead
+        if (next >= N) {
+            outcome = (int)(next - N);
+        } else {
+            if (eblk_i != (n >> 2)) {
+                eblk = philox4x32_10(n >> 2, w, e0, C.tag, ekey0, C.key1);
+                eblk_i = n >> 2;
+            }
+            const uint32_t q = n & 3u;
+            const uint32_t r = q == 0u ? eblk.x[0] : q == 1u ? eblk.x[1] : q == 2u ? eblk.x[2]
+                                                                       : eblk.x[3];
+            const uint64_t* t = A.table + ((size_t)e * N + next) * A.n_lines;
+            int k = 0;
+            while (k < A.n_lines - 1 && (uint64_t)r >= t[k]) ++k;
+            int d = A.off[0];
+#pragma unroll
+            for (int j = 1; j < kMaxLines; ++j) d = k == j ? A.off[j] : d;
+            const int en = (int)e + d;
+            if (en < 0 || en >= (int)nE) {
+                bad = true;
+                outcome = -1;
+            } else {
+                e = (uint32_t)en;
+                s = next;
+                if (steps >= C.max_steps) outcome = -1;
+            }
+        }
+        if (outcome != -2) {
+            if (outcome == 0) {
+                ++cL;
+                atomicAdd(&hsh[e], 1u);
+            } else if (outcome == 1) {
+                ++cR;
+                atomicAdd(&hsh[nE + e], 1u);
+            } else {
+                ++tr;
+            }
+            s1 += steps;
+            s2 += (uint64_t)steps * steps;
+            wi += stride;
+            live = wi < C.n_walkers;
+            w = C.wbegin + (uint32_t)(live ? wi : 0);
+            s = N + p;
+            e = e0;
+            steps = 0;
+            eblk_i = 0xffffffffu;
+        }
+    }
+    __syncthreads();
+    uint32_t nbad = bad ? 1u : 0u;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        cL += __shfl_xor(cL, o, 64);
+        cR += __shfl_xor(cR, o, 64);
+        tr += __shfl_xor(tr, o, 64);
+        s1 += __shfl_xor(s1, o, 64);
+        s2 += __shfl_xor(s2, o, 64);
+        nbad += __shfl_xor(nbad, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        unsigned long long* t =
+            reinterpret_cast<unsigned long long*>(C.tallies + (size_t)e0 * MCNEGF_TALLY_N);
+        if (cL) atomicAdd(t + MCNEGF_TALLY_EXIT_L, (unsigned long long)cL);
+        if (cR) atomicAdd(t + MCNEGF_TALLY_EXIT_R, (unsigned long long)cR);
+        if (tr) atomicAdd(t + MCNEGF_TALLY_TRUNC, (unsigned long long)tr);
+        if (s1) atomicAdd(t + MCNEGF_TALLY_STEPS, (unsigned long long)s1);
+        if (s2) atomicAdd(t + MCNEGF_TALLY_STEPS2, (unsigned long long)s2);
+        if (tr > nbad) atomicOr(C.status, MCNEGF_FLAG_TRUNC);
+        if (nbad) atomicOr(C.status, MCNEGF_FLAG_RANGE);
+    }
+    for (uint32_t b = threadIdx.x; b < 2 * nE; b += blockDim.x) {
+        const uint32_t v = hsh[b];
+        if (v) {
+            const uint32_t r = b >= nE ? 1u : 0u, ex = b - r * nE;
+            atomicAdd(A.hist + ((size_t)r * nE + e0) * nE + ex, (unsigned long long)v);
+        }
+    }
+}
+
+hipError_t launch_walk_inelastic(const mcnegf_kernel& k, int n_lines, const int32_t* off,
+                                 const uint64_t* table, uint64_t seed, uint32_t tag,
+                                 uint32_t walker_begin, uint32_t n_walkers, uint32_t max_steps,
+                                 int64_t* tallies, int64_t* hist, hipStream_t s) {
+    if (n_walkers == 0) return hipSuccess;
+    InelasticArgs A;
+    CountArgs& C = A.c;
+    C.tables = k.alias;
+    C.lows = k.alias_lo;
+    C.pitch32 = (uint32_t)k.alias_pitch;
+    C.table_stride = (int64_t)k.n_out * k.alias_pitch;
+    C.n_out = (uint32_t)k.n_out;
+    C.N = (uint32_t)k.N;
+    C.nE = (uint32_t)k.nE;
+    C.key0 = (uint32_t)(seed & 0xffffffffu);
+    C.key1 = (uint32_t)(seed >> 32);
+    C.tag = tag;
+    C.wbegin = walker_begin;
+    C.n_walkers = n_walkers;
+    C.max_steps = max_steps;
+    C.counts = nullptr;
+    C.tallies = tallies;
+    C.status = k.status;
+    A.table = table;
+    A.hist = reinterpret_cast<unsigned long long*>(hist);
+    A.n_lines = n_lines;
+    for (int j = 0; j < kMaxLines; ++j) A.off[j] = j < n_lines ? off[j] : 0;
+    const uint64_t per_block = 256ull * kInelasticPerLane;
+    const unsigned gx = (unsigned)((n_walkers + per_block - 1) / per_block);
+    {
+        MCNEGF_TIMED("walk_inelastic_kernel", s);
+        hipLaunchKernelGGL(walk_inelastic_kernel, dim3(gx, k.nE), dim3(256),
+                           (size_t)8 * k.nE, s, A);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace mcnegf

@@ -58,6 +58,15 @@ WIRE_W10_L100 = Workload(name="wire_W10_L100", W=10, L=100, eta=0.05, disorder=0
                          emin=-3.5, emax=3.5, n_energies=256, walkers_per_energy=1_000_000)
 WIRE_ETAS = (0.01, 0.05, 0.1)
 
+# Inelastic walks (step 7') on the wire's grid (spacing 7 t / 256 = 0.0273 t): an elastic line
+# and optical-phonon lines at hbar omega = 8 grid steps (0.219 t), emission (offset -8) weighted
+# by n_B + 1 and absorption (+8) by n_B, n_B = 1 / (exp(hbar omega / kT) - 1) at kT = 0.1 t,
+# both with coupling 0.5 against 1 for the elastic line.
+PHONON_STEPS = 8
+_N_BOSE = 1.0 / (np.exp(PHONON_STEPS * 7.0 / 256 / 0.1) - 1.0)
+PHONON_LINES = (-PHONON_STEPS, 0, PHONON_STEPS)
+PHONON_WEIGHTS = (0.5 * (_N_BOSE + 1.0), 1.0, 0.5 * _N_BOSE)
+
 # Differentiation workload: W = 16, L = 200 (N = 3200), eta = 0.02 t, disorder U[-0.5 t, 0.5 t],
 # 128 energies in [-3.5 t, 3.5 t]; dI/dV_i for every site and dI/deta = sum_i dI/dgamma_i.
 DIFF_W16_L200 = Workload(name="diff_W16_L200", W=16, L=200, eta=0.02, disorder=0.5,

@@ -34,6 +34,8 @@ EXPORTED = ("mc_negf_workspace_bytes", "mc_negf_build_kernel", "mc_negf_walk",
             "mc_negf_walk_counts_bytes", "mc_negf_walk_counts", "mc_negf_grad_mc",
             "mc_negf_weighted_tables_bytes", "mc_negf_weighted_tables",
             "mc_negf_walk_weighted_bytes", "mc_negf_walk_weighted", "mc_negf_current_weighted",
+            "mc_negf_energy_table_bytes", "mc_negf_energy_table", "mc_negf_walk_inelastic",
+            "mc_negf_spectrum",
             "mc_negf_batch_bytes", "mc_negf_batch_prepare",
             "mc_negf_walk_batch", "mc_negf_walk_batch_autotune", "mc_negf_plan_waves",
             "mc_negf_graph_begin", "mc_negf_graph_end", "mc_negf_graph_launch",
@@ -141,6 +143,12 @@ def lib() -> ctypes.CDLL:
                                         u64, u64, u32, vp, vp, vp, u64, vp]
     L.mc_negf_current_weighted.argtypes = [ctypes.POINTER(KernelStruct), u32, vp, vp, vp, vp, vp,
                                            dp, vp]
+    L.mc_negf_energy_table_bytes.argtypes = [ctypes.POINTER(KernelStruct), i32,
+                                             ctypes.POINTER(u64)]
+    L.mc_negf_energy_table.argtypes = [ctypes.POINTER(KernelStruct), i32, vp, vp, vp, u64, vp]
+    L.mc_negf_walk_inelastic.argtypes = [ctypes.POINTER(KernelStruct), i32, vp, vp, u64, u32, u32,
+                                         u64, u64, u32, vp, vp, vp]
+    L.mc_negf_spectrum.argtypes = [ctypes.POINTER(KernelStruct), u32, vp, vp, vp, vp, vp]
     L.mc_negf_batch_bytes.argtypes = [ctypes.POINTER(KernelStruct), i32, ctypes.POINTER(u64)]
     L.mc_negf_batch_prepare.argtypes = [ctypes.POINTER(KernelStruct), i32,
                                         ctypes.POINTER(u32), u32, ctypes.POINTER(vp), vp, u64,
@@ -579,6 +587,59 @@ def mc_negf_grad_mc(k: Kernel, inject_lead: int, counts, tallies, weights, gws, 
                                         _ptr(tallies), _ptr(weights), _ptr(gws),
                                         int(gws.numel()), _ptr(dI_dV), _ptr(dI_dgamma),
                                         _stream(stream)))
+
+
+# ---- inelastic walks (step 7') -----------------------------------------------------------------
+
+def _lines(offsets, lambdas=None):
+    off = np.ascontiguousarray(offsets, dtype=np.int32)
+    lam = None if lambdas is None else np.ascontiguousarray(lambdas, dtype=np.float64)
+    if lam is not None and lam.shape != off.shape:
+        raise ValueError("offsets and lambdas must have the same length")
+    return off, lam
+
+
+def mc_negf_energy_table_bytes(k: Kernel, n_lines: int) -> int:
+    out = ctypes.c_uint64(0)
+    _check("mc_negf_energy_table_bytes",
+           lib().mc_negf_energy_table_bytes(ctypes.byref(k.struct), int(n_lines),
+                                            ctypes.byref(out)))
+    return int(out.value)
+
+
+def mc_negf_energy_table(k: Kernel, offsets, lambdas, table, stream=None) -> int:
+    """Step-7' thresholds [nE][N][n_lines] (int64 storage of uint64) from the handle's A_jj for
+    energy lines at `offsets` grid steps with weights `lambdas` (host sequences)."""
+    off, lam = _lines(offsets, lambdas)
+    return _check("mc_negf_energy_table",
+                  lib().mc_negf_energy_table(ctypes.byref(k.struct), int(off.size),
+                                             off.ctypes.data_as(ctypes.c_void_p),
+                                             lam.ctypes.data_as(ctypes.c_void_p), _ptr(table),
+                                             int(table.numel() * table.element_size()),
+                                             _stream(stream)))
+
+
+def mc_negf_walk_inelastic(k: Kernel, offsets, table, seed: int, realization: int,
+                           inject_lead: int, walker_begin: int, n_walkers: int, max_steps: int,
+                           tallies, hist, stream=None) -> int:
+    """Inelastic walks on the handle's alias tables with step 7' drawn from `table`; adds to
+    tallies [nE][TALLY_N] and hist [2][nE][nE] (int64)."""
+    off, _ = _lines(offsets)
+    return _check("mc_negf_walk_inelastic",
+                  lib().mc_negf_walk_inelastic(ctypes.byref(k.struct), int(off.size),
+                                               off.ctypes.data_as(ctypes.c_void_p), _ptr(table),
+                                               int(seed), int(realization), int(inject_lead),
+                                               int(walker_begin), int(n_walkers), int(max_steps),
+                                               _ptr(tallies), _ptr(hist), _stream(stream)))
+
+
+def mc_negf_spectrum(k: Kernel, inject_lead: int, tallies, hist, weights, spectrum,
+                     stream=None) -> int:
+    """Energy-resolved current [2][nE] of inelastic walks."""
+    return _check("mc_negf_spectrum",
+                  lib().mc_negf_spectrum(ctypes.byref(k.struct), int(inject_lead), _ptr(tallies),
+                                         _ptr(hist), _ptr(weights), _ptr(spectrum),
+                                         _stream(stream)))
 
 
 # ---- importance-sampled walks ---------------------------------------------------------------

@@ -360,6 +360,55 @@ def test_score_gradient_entry_points_validate_on_the_host():
     assert wc(1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL
 
 
+def test_inelastic_entry_points_validate_on_the_host():
+    # step 7': table size from the handle; every bad line set or walk argument refused on the
+    # host before any GPU call
+    lib = M.lib()
+    ks = M.KernelStruct()
+    ks.W, ks.L, ks.N, ks.n_out, ks.nE, ks.p_pitch, ks.alias_pitch = 2, 3, 6, 8, 5, 16, 16
+    for f in ("alias", "alias_lo", "P", "lead", "status", "counters", "reduce", "Adiag"):
+        setattr(ks, f, 4096)
+    out = ctypes.c_uint64(0)
+    assert lib.mc_negf_energy_table_bytes(ctypes.byref(ks), 3, ctypes.byref(out)) == M.OK
+    assert out.value == 5 * 6 * 3 * 8
+    assert lib.mc_negf_energy_table_bytes(ctypes.byref(ks), 9, ctypes.byref(out)) == M.EINVAL
+    assert lib.mc_negf_energy_table_bytes(ctypes.byref(ks), 0, ctypes.byref(out)) == M.EINVAL
+    z = ctypes.c_void_p(0)
+    p = ctypes.c_void_p(4096)
+    I32 = lambda *v: (ctypes.c_int32 * len(v))(*v)  # noqa: E731
+    F64 = lambda *v: (ctypes.c_double * len(v))(*v)  # noqa: E731
+    tb = 5 * 6 * 3 * 8
+    et = lambda n, o, lam, nb=tb: lib.mc_negf_energy_table(  # noqa: E731
+        ctypes.byref(ks), n, o, lam, p, nb, z)
+    assert et(3, I32(-2, 0, 2), F64(0.5, 0.0, 0.5), tb - 1) == M.EWS
+    assert et(3, I32(-5, 0, 2), F64(0.5, 1.0, 0.5)) == M.EINVAL      # |offset| >= nE
+    assert et(3, I32(-2, 0, 2), F64(0.5, -1.0, 0.5)) == M.EINVAL     # negative weight
+    assert et(3, I32(-2, 0, 2), F64(0.5, float("nan"), 0.5)) == M.EINVAL
+    # energies 2 and (with only +/-3 lines) nowhere to go from the middle of a 5-point grid
+    assert et(2, I32(-3, 3), F64(1.0, 1.0)) == M.EINVAL
+    assert et(2, I32(0, 4), F64(0.0, 1.0)) == M.EINVAL               # e = 1..4 stranded
+    assert lib.mc_negf_energy_table(ctypes.byref(ks), 1, I32(0), z, p, tb, z) == M.EINVAL
+    assert lib.mc_negf_energy_table(ctypes.byref(ks), 9, I32(*range(9)), F64(*[1.0] * 9), p,
+                                    1 << 20, z) == M.EINVAL          # too many lines
+    wi = lambda *a: lib.mc_negf_walk_inelastic(ctypes.byref(ks), *a)  # noqa: E731
+    off = I32(-1, 0, 1)
+    assert wi(3, off, z, 1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL    # no table
+    assert wi(3, off, p, 1, 0, 2, 0, 10, 10, p, p, z) == M.EINVAL    # lead
+    assert wi(3, off, p, 1, 1 << 30, 0, 0, 10, 10, p, p, z) == M.EINVAL  # realization
+    assert wi(3, off, p, 1, 0, 0, 0, 10, 0, p, p, z) == M.EINVAL     # max_steps
+    assert wi(3, off, p, 1, 0, 0, 7, (1 << 32) - 7, 10, p, p, z) == M.EINVAL  # range
+    assert wi(3, off, p, 1, 0, 0, 0, 10, 10, p, z, z) == M.EINVAL    # no histogram
+    assert wi(3, I32(-1, 0, 5), p, 1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL  # offset
+    assert wi(0, off, p, 1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL    # no lines
+    sp = lambda *a: lib.mc_negf_spectrum(ctypes.byref(ks), *a)  # noqa: E731
+    assert sp(2, p, p, p, p, z) == M.EINVAL                          # lead
+    assert sp(0, p, z, p, p, z) == M.EINVAL                          # no histogram
+    ks.nE = 4097  # the walker's exit-energy histogram lives in LDS
+    assert wi(3, off, p, 1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL
+    ks.nE, ks.alias = 5, 0  # the walks need the kernel's own alias tables
+    assert wi(3, off, p, 1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL
+
+
 def test_walker_build_keeps_the_atomic_optimizer_off():
     # the walkers keep every lane active at each cross-lane operation; the AMDGPU atomic
     # optimizer would put their uniform-address LDS atomics into first-lane-only regions
