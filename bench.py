@@ -63,7 +63,10 @@ def parse():
     ap.add_argument("--no-scale", action="store_true",
                     help="skip the W=32 x L=500 (N = 16000) workload")
     ap.add_argument("--no-chain", action="store_true", help="skip the N = 50 chain")
-    ap.add_argument("--only", choices=["grad", "batched", "scale", "chain"], default=None,
+    ap.add_argument("--no-inelastic", action="store_true",
+                    help="skip the inelastic walks (step 7') on the wire")
+    ap.add_argument("--only", choices=["grad", "batched", "scale", "chain", "inelastic"],
+                    default=None,
                     help="run only this leg and print its object (profiling; no top-level metric)")
     ap.add_argument("--serial-builds", action="store_true",
                     help="issue the three dephasing rates' builds one after another on one stream")
@@ -1020,6 +1023,135 @@ def chain_bench(torch, dev, steps, warmup, seed, with_cpu):
     return out
 
 
+def inelastic_bench(torch, dev, steps, warmup, seed, with_cpu, walkers=None):
+    """Inelastic walks (step 7') on the wire (W = 10, L = 100, eta = 0.05 t, 256 energies,
+    1e6 walkers per energy) with an elastic line and optical-phonon emission / absorption lines
+    8 grid steps away (inputs.PHONON_LINES / PHONON_WEIGHTS).  One step = build (no DIRECT
+    workspace), step-7' table, walks, MC current and energy-resolved current; the walker's
+    roofline counts 12 bytes per step plus the 8-byte thresholds a probe step compares."""
+    wl = inputs.WIRE_W10_L100
+    walkers = walkers or wl.walkers_per_energy
+    nE, N = wl.n_energies, wl.N
+    off, lam = list(inputs.PHONON_LINES), [float(x) for x in inputs.PHONON_WEIGHTS]
+    sysm = M.make_system(wl.W, wl.L, wl.t, wl.lead_model, wl.gamma_l, wl.delta_lead,
+                         M.BUILD_NO_DIRECT)
+    E, w = inputs.energy_grid(wl.emin, wl.emax, nE)
+    V = torch.tensor(inputs.onsite(wl), device=dev)
+    g = torch.tensor(inputs.dephasing(wl), device=dev)
+    tE = torch.tensor(E, device=dev)
+    tw = torch.tensor(w, device=dev)
+    ws = M.allocate_workspace(sysm, nE, dev)
+    tal = torch.zeros((nE, M.TALLY_N), dtype=torch.int64, device=dev)
+    hist = torch.zeros((2, nE, nE), dtype=torch.int64, device=dev)
+    T = torch.empty(nE, dtype=torch.float64, device=dev)
+    sg = torch.empty_like(T)
+    out_I = torch.zeros(2, dtype=torch.float64, device=dev)
+    S = torch.empty((2, nE), dtype=torch.float64, device=dev)
+    state = {}
+
+    def one_step():
+        k = M.mc_negf_build_kernel(sysm, V, g, tE, ws)
+        table = state.get("table")
+        if table is None:
+            table = state["table"] = torch.empty(M.mc_negf_energy_table_bytes(k, len(off)) // 8,
+                                                 dtype=torch.int64, device=dev)
+        M.mc_negf_energy_table(k, off, lam, table)
+        tal.zero_()
+        hist.zero_()
+        M.mc_negf_walk_inelastic(k, off, table, seed, 0, 0, 0, walkers, 1_000_000, tal, hist)
+        M.mc_negf_current_async(k, 0, 0, tal, tw, T, sg, out_I)
+        M.mc_negf_spectrum(k, 0, tal, hist, tw, S)
+        state["k"] = k
+
+    for _ in range(max(1, warmup)):
+        one_step()
+    torch.cuda.synchronize()
+    with M.LaunchTimes() as lt0:
+        one_step()
+    per_step = len(require_complete(lt0).records)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    records = timed_records(steps, per_step, one_step)
+    torch.cuda.synchronize()
+    k = state["k"]
+    flags = M.mc_negf_status(k)
+    t = tal.cpu().numpy()
+    h = hist.cpu().numpy().astype(np.float64)
+    I, sI = (float(x) for x in out_I.cpu().numpy())
+    Sg = S.cpu().numpy()
+    walk_steps = int(t[:, M.TALLY_STEPS].sum())
+    exits = int(t[:, :2].sum())
+    probe_steps = walk_steps - exits
+    per_kernel = per_kernel_table(records, steps)
+    walk_ms = per_kernel["walk_inelastic_kernel"]["ms_per_launch"]
+    algo = STEP_BYTES * walk_steps + 8 * (len(off) - 1) * probe_steps
+    roof = {"kernel": "walk_inelastic_kernel", "bound": "hbm",
+            "achieved": algo / 1e9 / (walk_ms * 1e-3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "algorithmic_per_launch": algo, "avg_launch_ms": walk_ms,
+            "bytes": f"{STEP_BYTES} per step + {8 * (len(off) - 1)} per probe step (thresholds)",
+            "traffic": measured_traffic("walk_inelastic_kernel")}
+    roof["frac"] = roof["achieved"] / HBM_PEAK_GBS
+    add_traffic_rate(roof)
+    # energy transfer: exit energy minus injection energy over the walks absorbed at R
+    de = np.subtract.outer(np.arange(nE), np.arange(nE)).T * (E[1] - E[0])  # [e0][e]
+    hR = h[1]
+    elastic_R = float(np.trace(hR))
+    out = {
+        "workload": f"wire W={wl.W} L={wl.L} N={N}, eta={wl.eta}t, {nE} energies in "
+                    f"[{wl.emin},{wl.emax}]t, {walkers} walkers/energy; step 7' with lines "
+                    f"{off} grid steps (spacing {E[1] - E[0]:.4f}t), weights "
+                    f"{[round(x, 4) for x in lam]}",
+        "value": walk_steps / (wall / steps), "unit": "walk steps/s",
+        "ms_per_step": 1e3 * wall / steps,
+        "walker_kernel_steps_per_s": walk_steps / (walk_ms * 1e-3),
+        "I_mc": I, "sigma_I_mc": sI,
+        "I_spectrum_sum": float(Sg[1].sum()),
+        "mean_steps_per_walker": walk_steps / float(t[:, :3].sum()),
+        "mean_energy_change_at_R_t": float((hR * de).sum() / hR.sum()),
+        "fraction_exits_at_R_with_changed_energy": 1.0 - elastic_R / float(hR.sum()),
+        "status_flags": int(flags),
+        "per_kernel": per_kernel,
+        "roofline": roof,
+    }
+    if with_cpu:
+        out["cpu_baseline"] = inelastic_cpu_baseline(wl, off, lam, seed)
+    del ws, state
+    torch.cuda.empty_cache()
+    return out
+
+
+def inelastic_cpu_baseline(wl, off, lam, seed, n_sample=16, nw=20_000):
+    """The oracle's inelastic walker (C, the paper's cumulative-sum sampler) on n_sample
+    consecutive energies of the wire's grid from the middle of the band, taken as a closed
+    window (dense LAPACK rows and A_jj per energy): its rate in walk steps/s."""
+    from oracle import dense as D
+    from oracle import inelastic as IN
+    from oracle import walker as OW
+    E, _ = inputs.energy_grid(wl.emin, wl.emax, wl.n_energies)
+    lo = wl.n_energies // 2 - n_sample // 2
+    V, g = inputs.onsite(wl), inputs.dephasing(wl)
+    t0 = time.perf_counter()
+    sols = D.solve_workload(wl.W, wl.L, wl.t, V, g, E[lo:lo + n_sample])
+    K = np.stack([s_.transition_kernel() for s_ in sols])
+    A = np.stack([s_.Adiag for s_ in sols])
+    table = IN.energy_table(A, off, lam)
+    t_build = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    tal, _, _ = IN.walk_cdf(K, table, off, seed, 0, 0, 0, nw)
+    t_walk = time.perf_counter() - t1
+    steps = int(tal[:, 3].sum())
+    return {"value": steps / t_walk, "unit": "walk steps/s", "cores": OW.num_threads(),
+            "kind": "oracle",
+            "sample": f"energies {lo}..{lo + n_sample - 1} of {wl.n_energies} as a closed window "
+                      f"x {nw} walkers: C walker, {steps} steps in {t_walk:.1f} s (dense rows "
+                      f"and A_jj {t_build:.1f} s)",
+            "build_s_per_energy": t_build / n_sample}
+
+
 def cpu_baseline(wl: inputs.Workload, seed: int):
     """The oracle on the host cores for a bounded sample of the workload (about 10 s): dense
     LAPACK solves plus the C walker (the paper's cumulative-sum sampler), 24 of the 256
@@ -1086,6 +1218,8 @@ def main():
             leg = grad_bench(torch, dev, args.steps, args.warmup, with_cpu)
         elif args.only == "chain":
             leg = chain_bench(torch, dev, args.steps, args.warmup, inputs.RNG_SEED, with_cpu)
+        elif args.only == "inelastic":
+            leg = inelastic_bench(torch, dev, args.steps, args.warmup, inputs.RNG_SEED, with_cpu)
         elif args.only == "batched":
             leg = batched_bench(torch, dev, args.steps, args.warmup, args.batch_budget_gb,
                                 inputs.RNG_SEED)
@@ -1200,6 +1334,9 @@ def main():
     if not args.no_chain:
         line["chain"] = chain_bench(torch, dev, args.steps, args.warmup, seed,
                                     not args.no_cpu_baseline)
+    if not args.no_inelastic:
+        line["inelastic"] = inelastic_bench(torch, dev, args.steps, args.warmup, seed,
+                                            not args.no_cpu_baseline)
     if not args.no_grad:
         line["grad"] = grad_bench(torch, dev, args.steps, args.warmup, not args.no_cpu_baseline)
     if not args.no_batched:

@@ -19,6 +19,7 @@
 // high 16 bits of b with the bucket's packed entry and reads the low 16 threshold bits only
 // on a tie.  A walk's first step reads its injection row from an LDS copy when the launch
 // staged one; a finished walk is counted once, when its slot takes the next walker.
+#include <algorithm>
 #include <mutex>
 
 #include "common.h"
@@ -1694,67 +1695,86 @@ struct InelasticArgs {
     CountArgs c;             // tables, stream, walkers, tallies, status (counts unused)
     const uint64_t* table;   // [nE][N][n_lines]
     unsigned long long* hist;  // [2][nE][nE]: exits at lead r of walkers from e0 at energy e
+    uint32_t gx;               // workgroups per injection energy
     int32_t n_lines;
     int32_t off[kMaxLines];
 };
 
 // Walkers per lane: a workgroup walks 256 * kInelasticPerLane walkers of one injection energy
 // and flushes its exit-energy histogram (LDS, 2 nE counters) once.
+//
+// XCD-aware order: workgroups are dealt to the eight XCDs in turn, so workgroup b runs on XCD
+// b % 8.  XCD x takes the injection energies x, x + 8, x + 16, ... one after another (gx
+// workgroups each): its L2 then serves mostly one energy's table at a time, and lines that
+// move by multiples of 8 grid steps stay within the energies of the same XCD.
 constexpr uint32_t kInelasticPerLane = 16;
 
 __global__ void __launch_bounds__(256) walk_inelastic_kernel(InelasticArgs A) {
     extern __shared__ uint32_t hsh[];  // [2][nE]
     const CountArgs& C = A.c;
-    const uint32_t e0 = blockIdx.y, nE = C.nE, N = C.N;
+    const uint32_t nE = C.nE, N = C.N;
+    const uint32_t xcd = blockIdx.x & 7u, j = blockIdx.x >> 3;
+    const uint32_t e0 = xcd + 8u * (j / A.gx), chunk = j % A.gx;
+    if (e0 >= nE) return;  // padding of the last round (whole workgroup)
     for (uint32_t b = threadIdx.x; b < 2 * nE; b += blockDim.x) hsh[b] = 0;
     __syncthreads();
     const uint32_t p = C.tag & 1u;
     const uint32_t ekey0 = ~C.key0;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    uint64_t wi = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)A.gx * blockDim.x;
+    uint64_t wi = (uint64_t)chunk * blockDim.x + threadIdx.x;
     uint32_t cL = 0, cR = 0, tr = 0;
     uint64_t s1 = 0, s2 = 0;
     bool bad = false;
-    // one step per iteration for every live lane; a lane whose walk ends takes its next
-    // walker at once (per-lane state, no cross-lane operation inside the loop)
+    // a lane whose walk ends takes its next walker at the next iteration (per-lane state, no
+    // cross-lane operation inside the loop)
     bool live = wi < C.n_walkers;
     uint32_t w = C.wbegin + (uint32_t)(live ? wi : 0);
-    uint32_t s = N + p, e = e0, steps = 0, eblk_i = 0xffffffffu;
-    Philox4 blk, eblk;
+    uint32_t s = N + p, e = e0, steps = 0;
+    // Each iteration takes two steps n, n + 1 (n even) of every live lane: both use words of
+    // step-6' block n >> 1 and of energy block n >> 2, so one block of each serves the pair.
+    // A walk that ends on the first step leaves its lane idle for the second; the next walker
+    // starts at the next iteration (with an even step count).
     while (live) {
-        if ((steps & 1u) == 0u) blk = philox4x32_10(steps >> 1, w, e0, C.tag, C.key0, C.key1);
-        // words by selects (a dynamic index would place the block in scratch memory)
-        const bool odd = (steps & 1u) != 0u;
-        const uint32_t a = odd ? blk.x[2] : blk.x[0], b = odd ? blk.x[3] : blk.x[1];
-        const gtable_ptr tb = (gtable_ptr)(C.tables + (size_t)e * C.table_stride);
-        const uint16_t* lo = C.lows + (size_t)e * C.table_stride;
-        const uint32_t next = draw_step(C, tb, lo, s, steps, w, e0, a, b);
-        const uint32_t n = steps++;
+        const Philox4 blk = philox4x32_10(steps >> 1, w, e0, C.tag, C.key0, C.key1);
+        const Philox4 eblk = philox4x32_10(steps >> 2, w, e0, C.tag, ekey0, C.key1);
+        const bool high = (steps & 2u) != 0u;  // words 2, 3 of the energy block
         int outcome = -2;  // -2: walking on; -1: truncated or off the grid; 0/1: lead
-        if (next >= N) {
-            outcome = (int)(next - N);
-        } else {
-            if (eblk_i != (n >> 2)) {
-                eblk = philox4x32_10(n >> 2, w, e0, C.tag, ekey0, C.key1);
-                eblk_i = n >> 2;
-            }
-            const uint32_t q = n & 3u;
-            const uint32_t r = q == 0u ? eblk.x[0] : q == 1u ? eblk.x[1] : q == 2u ? eblk.x[2]
-                                                                       : eblk.x[3];
-            const uint64_t* t = A.table + ((size_t)e * N + next) * A.n_lines;
-            int k = 0;
-            while (k < A.n_lines - 1 && (uint64_t)r >= t[k]) ++k;
-            int d = A.off[0];
 #pragma unroll
-            for (int j = 1; j < kMaxLines; ++j) d = k == j ? A.off[j] : d;
-            const int en = (int)e + d;
-            if (en < 0 || en >= (int)nE) {
-                bad = true;
-                outcome = -1;
-            } else {
-                e = (uint32_t)en;
-                s = next;
-                if (steps >= C.max_steps) outcome = -1;
+        for (int h = 0; h < 2; ++h) {
+            if (outcome == -2) {
+                const uint32_t a = h ? blk.x[2] : blk.x[0], b = h ? blk.x[3] : blk.x[1];
+                const gtable_ptr tb = (gtable_ptr)(C.tables + (size_t)e * C.table_stride);
+                const uint16_t* lo = C.lows + (size_t)e * C.table_stride;
+                const uint32_t next = draw_step(C, tb, lo, s, steps, w, e0, a, b);
+                ++steps;
+                if (next >= N) {
+                    outcome = (int)(next - N);
+                } else {
+                    const uint32_t r = high ? (h ? eblk.x[3] : eblk.x[2])
+                                            : (h ? eblk.x[1] : eblk.x[0]);
+                    // the thresholds below the last line, loaded together; the first k with
+                    // r < t_k by a select chain from the top
+                    const uint64_t* t = A.table + ((size_t)e * N + next) * A.n_lines;
+                    uint64_t tv[kMaxLines - 1];
+#pragma unroll
+                    for (int j = 0; j < kMaxLines - 1; ++j)
+                        tv[j] = j < A.n_lines - 1 ? t[j] : 0ull;
+                    int d = A.off[0];
+#pragma unroll
+                    for (int j = 1; j < kMaxLines; ++j) d = j < A.n_lines ? A.off[j] : d;
+#pragma unroll
+                    for (int j = kMaxLines - 2; j >= 0; --j)
+                        d = (j < A.n_lines - 1 && (uint64_t)r < tv[j]) ? A.off[j] : d;
+                    const int en = (int)e + d;
+                    if (en < 0 || en >= (int)nE) {
+                        bad = true;
+                        outcome = -1;
+                    } else {
+                        e = (uint32_t)en;
+                        s = next;
+                        if (steps >= C.max_steps) outcome = -1;
+                    }
+                }
             }
         }
         if (outcome != -2) {
@@ -1775,7 +1795,6 @@ __global__ void __launch_bounds__(256) walk_inelastic_kernel(InelasticArgs A) {
             s = N + p;
             e = e0;
             steps = 0;
-            eblk_i = 0xffffffffu;
         }
     }
     __syncthreads();
@@ -1837,10 +1856,16 @@ hipError_t launch_walk_inelastic(const mcnegf_kernel& k, int n_lines, const int3
     A.n_lines = n_lines;
     for (int j = 0; j < kMaxLines; ++j) A.off[j] = j < n_lines ? off[j] : 0;
     const uint64_t per_block = 256ull * kInelasticPerLane;
-    const unsigned gx = (unsigned)((n_walkers + per_block - 1) / per_block);
+    // every lane loops over its walkers with the stride of its energy's workgroups, so any
+    // gx >= 1 covers them all; gx is capped to keep the grid within 2^31 - 1 workgroups
+    const uint64_t rounds = 8ull * (uint64_t)((k.nE + 7) / 8);
+    const uint64_t gx = std::min<uint64_t>((n_walkers + per_block - 1) / per_block,
+                                           0x7fffffffull / rounds);
+    A.gx = (uint32_t)std::max<uint64_t>(gx, 1);
+    const uint64_t blocks = rounds * A.gx;
     {
         MCNEGF_TIMED("walk_inelastic_kernel", s);
-        hipLaunchKernelGGL(walk_inelastic_kernel, dim3(gx, k.nE), dim3(256),
+        hipLaunchKernelGGL(walk_inelastic_kernel, dim3((unsigned)blocks), dim3(256),
                            (size_t)8 * k.nE, s, A);
     }
     return hipGetLastError();
