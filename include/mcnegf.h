@@ -342,7 +342,8 @@ int32_t mc_negf_grad_mc(const mcnegf_kernel* k, uint32_t inject_lead, const uint
  *   everywhere (line 0 is drawn) and sets MCNEGF_FLAG_NONFINITE.  MCNEGF_EWS if table_bytes is
  *   too small.  Asynchronous.
  * mc_negf_walk_inelastic: walkers [walker_begin, walker_begin + n_walkers) (< 2^32) injected at
- *   lead inject_lead at every energy e0 of the handle (nE <= 4096), on its alias tables, with
+ *   lead inject_lead at every energy e0 of the handle (nE <= 4096, one energy's alias table
+ *   below 2^32 entries), on its alias tables, with
  *   step 7' drawn from d_table (the offsets must be those the table was built with): the first
  *   k with r < t_k (k = n_lines - 1 if none) for the 32-bit word r of the step.  A walker keeps
  *   the random stream of its injection energy: step-6' words and Lemire redraws as

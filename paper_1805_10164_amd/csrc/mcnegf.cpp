@@ -445,6 +445,7 @@ int32_t mc_negf_walk_inelastic(const mcnegf_kernel* k, int32_t n_lines, const in
                                hipStream_t stream) {
     if (!valid_kernel(k) || !k->alias || !k->alias_lo || !d_table || !d_tallies || !d_hist ||
         !valid_lines(*k, n_lines, h_offsets, nullptr) || k->nE > kMaxInelasticE ||
+        (uint64_t)k->n_out * (uint64_t)k->alias_pitch >= 0x100000000ull ||
         inject_lead > 1 || realization >= (1u << 30) || max_steps < 1)
         return MCNEGF_EINVAL;
     if (walker_begin >= 0x100000000ull || n_walkers >= 0x100000000ull ||

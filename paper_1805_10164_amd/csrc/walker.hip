@@ -1709,6 +1709,10 @@ struct InelasticArgs {
 // move by multiples of 8 grid steps stay within the energies of the same XCD.
 constexpr uint32_t kInelasticPerLane = 16;
 
+// NL: the number of lines (a compile-time count, so the thresholds and offsets are plain
+// registers).  Index arithmetic in 32 bits where it fits: an energy's table has fewer than
+// 2^32 entries, and nE N NL < 2^32 (nE <= 4096, N < 2^16, NL <= 8).
+template <int NL>
 __global__ void __launch_bounds__(256) walk_inelastic_kernel(InelasticArgs A) {
     extern __shared__ uint32_t hsh[];  // [2][nE]
     const CountArgs& C = A.c;
@@ -1743,8 +1747,9 @@ __global__ void __launch_bounds__(256) walk_inelastic_kernel(InelasticArgs A) {
         for (int h = 0; h < 2; ++h) {
             if (outcome == -2) {
                 const uint32_t a = h ? blk.x[2] : blk.x[0], b = h ? blk.x[3] : blk.x[1];
-                const gtable_ptr tb = (gtable_ptr)(C.tables + (size_t)e * C.table_stride);
-                const uint16_t* lo = C.lows + (size_t)e * C.table_stride;
+                const uint64_t base = (uint64_t)e * (uint32_t)C.table_stride;
+                const gtable_ptr tb = (gtable_ptr)(C.tables + base);
+                const uint16_t* lo = C.lows + base;
                 const uint32_t next = draw_step(C, tb, lo, s, steps, w, e0, a, b);
                 ++steps;
                 if (next >= N) {
@@ -1754,17 +1759,13 @@ __global__ void __launch_bounds__(256) walk_inelastic_kernel(InelasticArgs A) {
                                             : (h ? eblk.x[1] : eblk.x[0]);
                     // the thresholds below the last line, loaded together; the first k with
                     // r < t_k by a select chain from the top
-                    const uint64_t* t = A.table + ((size_t)e * N + next) * A.n_lines;
-                    uint64_t tv[kMaxLines - 1];
+                    const uint64_t* t = A.table + (e * N + next) * (uint32_t)NL;
+                    uint64_t tv[NL > 1 ? NL - 1 : 1];
 #pragma unroll
-                    for (int j = 0; j < kMaxLines - 1; ++j)
-                        tv[j] = j < A.n_lines - 1 ? t[j] : 0ull;
-                    int d = A.off[0];
+                    for (int j = 0; j < NL - 1; ++j) tv[j] = t[j];
+                    int d = A.off[NL - 1];
 #pragma unroll
-                    for (int j = 1; j < kMaxLines; ++j) d = j < A.n_lines ? A.off[j] : d;
-#pragma unroll
-                    for (int j = kMaxLines - 2; j >= 0; --j)
-                        d = (j < A.n_lines - 1 && (uint64_t)r < tv[j]) ? A.off[j] : d;
+                    for (int j = NL - 2; j >= 0; --j) d = (uint64_t)r < tv[j] ? A.off[j] : d;
                     const int en = (int)e + d;
                     if (en < 0 || en >= (int)nE) {
                         bad = true;
@@ -1865,8 +1866,18 @@ hipError_t launch_walk_inelastic(const mcnegf_kernel& k, int n_lines, const int3
     const uint64_t blocks = rounds * A.gx;
     {
         MCNEGF_TIMED("walk_inelastic_kernel", s);
-        hipLaunchKernelGGL(walk_inelastic_kernel, dim3((unsigned)blocks), dim3(256),
-                           (size_t)8 * k.nE, s, A);
+        const dim3 grid((unsigned)blocks), block(256);
+        const size_t lds = (size_t)8 * k.nE;
+        switch (n_lines) {
+            case 1: hipLaunchKernelGGL(walk_inelastic_kernel<1>, grid, block, lds, s, A); break;
+            case 2: hipLaunchKernelGGL(walk_inelastic_kernel<2>, grid, block, lds, s, A); break;
+            case 3: hipLaunchKernelGGL(walk_inelastic_kernel<3>, grid, block, lds, s, A); break;
+            case 4: hipLaunchKernelGGL(walk_inelastic_kernel<4>, grid, block, lds, s, A); break;
+            case 5: hipLaunchKernelGGL(walk_inelastic_kernel<5>, grid, block, lds, s, A); break;
+            case 6: hipLaunchKernelGGL(walk_inelastic_kernel<6>, grid, block, lds, s, A); break;
+            case 7: hipLaunchKernelGGL(walk_inelastic_kernel<7>, grid, block, lds, s, A); break;
+            default: hipLaunchKernelGGL(walk_inelastic_kernel<8>, grid, block, lds, s, A); break;
+        }
     }
     return hipGetLastError();
 }

@@ -405,7 +405,9 @@ def test_inelastic_entry_points_validate_on_the_host():
     assert sp(0, p, z, p, p, z) == M.EINVAL                          # no histogram
     ks.nE = 4097  # the walker's exit-energy histogram lives in LDS
     assert wi(3, off, p, 1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL
-    ks.nE, ks.alias = 5, 0  # the walks need the kernel's own alias tables
+    ks.nE, ks.alias_pitch = 5, 1 << 29  # one energy's table must stay below 2^32 entries
+    assert wi(3, off, p, 1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL
+    ks.alias_pitch, ks.alias = 16, 0  # the walks need the kernel's own alias tables
     assert wi(3, off, p, 1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL
 
 
