@@ -3,7 +3,7 @@
     python -m paper_1805_10164_amd.profiling stats KERNEL_STATS_CSV --command CMD
         per-kernel calls, total / average / min / max duration and share of GPU time.
 
-    python -m paper_1805_10164_amd.profiling valu COUNTERS_CSV --command CMD [--steps-per-launch K=S]
+    python -m paper_1805_10164_amd.profiling valu COUNTERS_CSV --command CMD [--work K=UNITS]
         per-kernel averages of the SQ / GRBM counters of one --pmc run, with the VALU issue
         fraction SQ_ACTIVE_INST_VALU * 4 / (SIMDs * GRBM_GUI_ACTIVE per XCD) and, for kernels
         given a work count, VALU lane-instructions per unit of work.
