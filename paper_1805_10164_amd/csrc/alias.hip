@@ -655,15 +655,15 @@ static hipError_t launch_alias_rows(const mcnegf_kernel& k, const AliasArgs& a,
                                     const char* name, hipStream_t s) {
     const int n = k.n_out;
     const size_t lds = (size_t)(n + 1) * 8 + (size_t)n * 2;
-    // rows up to 1024 outcomes: 256 threads x 4 items; up to 1536: 256 x 6; up to 4096:
+    // rows up to 1024 outcomes: 128 threads x 8 items; up to 1536: 256 x 6; up to 4096:
     // 512 x 8; up to 8192: 512 x 16; longer rows (n <= kMaxOut): 512 x 32
-    const int shape = n <= 256 * 4 ? 0 : n <= 256 * 6 ? 1 : n <= 512 * 8 ? 2 : n <= 512 * 16 ? 3 : 4;
-    const void* fns[5] = {(const void*)alias_build_kernel<256, 4, kBias>,
+    const int shape = n <= 128 * 8 ? 0 : n <= 256 * 6 ? 1 : n <= 512 * 8 ? 2 : n <= 512 * 16 ? 3 : 4;
+    const void* fns[5] = {(const void*)alias_build_kernel<128, 8, kBias>,
                           (const void*)alias_build_kernel<256, 6, kBias>,
                           (const void*)alias_build_kernel<512, 8, kBias>,
                           (const void*)alias_build_kernel<512, 16, kBias>,
                           (const void*)alias_build_kernel<512, 32, kBias>};
-    const int bts[5] = {256, 256, 512, 512, 512};
+    const int bts[5] = {128, 256, 512, 512, 512};
     if (lds > 65536) {
         // rows beyond 6.5k outcomes need more than 64 KB of LDS per workgroup (gfx950: 160 KB)
         int dev = 0, per_block = 0, optin = 0;
@@ -687,7 +687,7 @@ static hipError_t launch_alias_rows(const mcnegf_kernel& k, const AliasArgs& a,
         MCNEGF_TIMED(name, s);
         const dim3 grid(n, k.nE), block(bts[shape]);
         switch (shape) {
-            case 0: hipLaunchKernelGGL((alias_build_kernel<256, 4, kBias>), grid, block, lds, s, a); break;
+            case 0: hipLaunchKernelGGL((alias_build_kernel<128, 8, kBias>), grid, block, lds, s, a); break;
             case 1: hipLaunchKernelGGL((alias_build_kernel<256, 6, kBias>), grid, block, lds, s, a); break;
             case 2: hipLaunchKernelGGL((alias_build_kernel<512, 8, kBias>), grid, block, lds, s, a); break;
             case 3: hipLaunchKernelGGL((alias_build_kernel<512, 16, kBias>), grid, block, lds, s, a); break;

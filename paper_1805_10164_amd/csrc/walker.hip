@@ -1534,6 +1534,32 @@ __device__ inline uint32_t draw_step(const CountArgs& A, gtable_ptr tb, const ui
     return keep ? c : (ent & kAliasIdxMask);
 }
 
+// The same draw with the first step's injection row staged in LDS (inj, inj_lo: the row of
+// the walker's own energy): lanes at step 0 read the bucket's entry there, the others from
+// the global table; both take the same bucket and the same keep rule.
+__device__ inline uint32_t draw_step_staged(const CountArgs& A, gtable_ptr tb, const uint16_t* lo,
+                                            const uint32_t* inj, const uint16_t* inj_lo,
+                                            uint32_t row, uint32_t n_step, uint32_t w, uint32_t e,
+                                            uint32_t a, uint32_t b) {
+    const uint32_t n_out = A.n_out;
+    const uint32_t thresh = (0u - n_out) % n_out;
+    uint64_t m = (uint64_t)a * n_out;
+    uint32_t r = 0;
+    while ((uint32_t)m < thresh) {  // per lane, rare
+        ++r;
+        m = (uint64_t)philox4x32_10(n_step, w, e, A.tag | 0x80000000u, A.key0, A.key1 ^ r).x[0] *
+            n_out;
+    }
+    const uint32_t c = (uint32_t)(m >> 32);
+    const bool staged = n_step == 0u;
+    const uint32_t off = __umul24(row, A.pitch32) + c;
+    const uint32_t ent = staged ? inj[c] : tb[off];
+    bool keep = b < (ent & ~kAliasIdxMask);
+    if (((b ^ ent) >> kAliasIdxBits) == 0u)
+        keep = (b & kAliasIdxMask) < (uint32_t)(staged ? inj_lo[c] : lo[off]);
+    return keep ? c : (ent & kAliasIdxMask);
+}
+
 __global__ void __launch_bounds__(256) walk_counts_kernel(CountArgs A) {
     const uint32_t e = blockIdx.y;
     const uint64_t wi = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1696,6 +1722,7 @@ struct InelasticArgs {
     const uint64_t* table;   // [nE][N][n_lines]
     unsigned long long* hist;  // [2][nE][nE]: exits at lead r of walkers from e0 at energy e
     uint32_t gx;               // workgroups per injection energy
+    uint32_t staged;           // 1: the injection row of e0 is staged in LDS
     int32_t n_lines;
     int32_t off[kMaxLines];
 };
@@ -1720,9 +1747,20 @@ __global__ void __launch_bounds__(256) walk_inelastic_kernel(InelasticArgs A) {
     const uint32_t xcd = blockIdx.x & 7u, j = blockIdx.x >> 3;
     const uint32_t e0 = xcd + 8u * (j / A.gx), chunk = j % A.gx;
     if (e0 >= nE) return;  // padding of the last round (whole workgroup)
-    for (uint32_t b = threadIdx.x; b < 2 * nE; b += blockDim.x) hsh[b] = 0;
-    __syncthreads();
     const uint32_t p = C.tag & 1u;
+    // LDS: exit-energy histogram [2][nE], then the injection row of e0 (packed entries and
+    // their low threshold bits, pitch of each)
+    uint32_t* inj = hsh + 2 * nE;
+    uint16_t* inj_lo = reinterpret_cast<uint16_t*>(inj + C.pitch32);
+    for (uint32_t b = threadIdx.x; b < 2 * nE; b += blockDim.x) hsh[b] = 0;
+    if (A.staged) {
+        const size_t row0 = (size_t)e0 * C.table_stride + (size_t)(N + p) * C.pitch32;
+        for (uint32_t b = threadIdx.x; b < C.pitch32; b += blockDim.x) {
+            inj[b] = C.tables[row0 + b];
+            inj_lo[b] = C.lows[row0 + b];
+        }
+    }
+    __syncthreads();
     const uint32_t ekey0 = ~C.key0;
     const uint64_t stride = (uint64_t)A.gx * blockDim.x;
     uint64_t wi = (uint64_t)chunk * blockDim.x + threadIdx.x;
@@ -1750,7 +1788,12 @@ __global__ void __launch_bounds__(256) walk_inelastic_kernel(InelasticArgs A) {
                 const uint64_t base = (uint64_t)e * (uint32_t)C.table_stride;
                 const gtable_ptr tb = (gtable_ptr)(C.tables + base);
                 const uint16_t* lo = C.lows + base;
-                const uint32_t next = draw_step(C, tb, lo, s, steps, w, e0, a, b);
+                // a walk's first step (always the first half of an iteration) reads the staged
+                // injection row
+                const uint32_t next =
+                    h == 0 && A.staged
+                        ? draw_step_staged(C, tb, lo, inj, inj_lo, s, steps, w, e0, a, b)
+                        : draw_step(C, tb, lo, s, steps, w, e0, a, b);
                 ++steps;
                 if (next >= N) {
                     outcome = (int)(next - N);
@@ -1867,7 +1910,10 @@ hipError_t launch_walk_inelastic(const mcnegf_kernel& k, int n_lines, const int3
     {
         MCNEGF_TIMED("walk_inelastic_kernel", s);
         const dim3 grid((unsigned)blocks), block(256);
-        const size_t lds = (size_t)8 * k.nE;
+        // the staged row while the LDS stays within the default 64 KB per workgroup
+        const size_t lds_hist = (size_t)8 * k.nE, lds_row = (size_t)6 * k.alias_pitch;
+        A.staged = lds_hist + lds_row <= 65536 ? 1u : 0u;
+        const size_t lds = lds_hist + (A.staged ? lds_row : 0);
         switch (n_lines) {
             case 1: hipLaunchKernelGGL(walk_inelastic_kernel<1>, grid, block, lds, s, A); break;
             case 2: hipLaunchKernelGGL(walk_inelastic_kernel<2>, grid, block, lds, s, A); break;
