@@ -6,8 +6,8 @@ injection draw is rejected once, or at least twice, found by brute force with th
 Philox (tests/golden/make_lemire_redraws.py).  Each is walked alone on tables built so that
 its step count reveals the injection bucket: the injection rows keep every bucket, and probe
 j moves to j - 1 with certainty (probe 0 to lead R), so a walk injected into probe c takes
-c + 2 steps.  The per-kernel, batched and energy-sampled walkers must give the oracle's
-tallies, which must show the listed bucket.
+c + 2 steps.  The per-kernel, batched, energy-sampled, counting and inelastic (single elastic
+line) walkers must give the oracle's tallies, which must show the listed bucket.
 """
 import os
 
@@ -110,6 +110,24 @@ def test_redraw_walker_bit_exact(built, row):
     M.mc_negf_walk_sampled(k, seed, real, lead, w, 1, 1_000_000, wts, ts, scratch)
     torch.cuda.synchronize()
     assert (ts.cpu().numpy() == ref).all()
+    # inelastic walker with the single elastic line (its table is never read); at n = 1002 the
+    # injection row is staged in LDS, at n = 16138 it is read from the global table
+    ti = torch.zeros((1, M.TALLY_N), dtype=torch.int64, device=DEV)
+    hist = torch.zeros((2, 1, 1), dtype=torch.int64, device=DEV)
+    et = torch.full((n - 2,), 2 ** 32, dtype=torch.int64, device=DEV)
+    M.mc_negf_walk_inelastic(k, [0], et, seed, real, lead, w, 1, 1_000_000, ti, hist)
+    torch.cuda.synchronize()
+    assert (ti.cpu().numpy() == ref).all()
+    assert hist.cpu().numpy()[:, 0, 0].tolist() == ref[0, :2].tolist()
+    # counting walker (score-function gradient): same tallies; the walk to q is counted
+    if n == 1002:
+        tc = torch.zeros((1, M.TALLY_N), dtype=torch.int64, device=DEV)
+        cnt = torch.zeros(n * n, dtype=torch.int32, device=DEV)
+        M.mc_negf_walk_counts(k, seed, real, lead, w, 1, 1_000_000, cnt, tc)
+        torch.cuda.synchronize()
+        assert (tc.cpu().numpy() == ref).all()
+        q_hits = ref[0, 1 - lead]
+        assert int(cnt.sum()) == (ref[0, 3] if q_hits else 0)
 
 
 def test_redraw_walkers_among_neighbours(built):
