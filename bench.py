@@ -65,7 +65,10 @@ def parse():
     ap.add_argument("--no-chain", action="store_true", help="skip the N = 50 chain")
     ap.add_argument("--no-inelastic", action="store_true",
                     help="skip the inelastic walks (step 7') on the wire")
-    ap.add_argument("--only", choices=["grad", "batched", "scale", "chain", "inelastic"],
+    ap.add_argument("--no-resistance", action="store_true",
+                    help="skip the resistance-versus-length sweep")
+    ap.add_argument("--only", choices=["grad", "batched", "scale", "chain", "inelastic",
+                                       "resistance"],
                     default=None,
                     help="run only this leg and print its object (profiling; no top-level metric)")
     ap.add_argument("--serial-builds", action="store_true",
@@ -1124,6 +1127,61 @@ def inelastic_bench(torch, dev, steps, warmup, seed, with_cpu, walkers=None):
     return out
 
 
+def resistance_bench(torch, dev, seed, walkers=100_000):
+    """Linear-in-length resistance (Sec. IV A): clean W = 10 wires of L = 50, 100, 200, 400
+    slices at eta = 0.1 t, 64 energies in [-3.5 t, 3.5 t]; per length the DIRECT current (build
+    without alias tables plus the probe solve) and the Monte Carlo current (build plus walks),
+    timed after one warm-up, then the straight line 1/I = a + b L through the DIRECT currents."""
+    W, eta, nE = 10, 0.1, 64
+    E, w = inputs.energy_grid(-3.5, 3.5, nE)
+    tE = torch.tensor(E, device=dev)
+    tw = torch.tensor(w, device=dev)
+    rows = []
+    for L in (50, 100, 200, 400):
+        V = torch.zeros(W * L, dtype=torch.float64, device=dev)
+        g = torch.full((W * L,), eta, dtype=torch.float64, device=dev)
+        T = torch.empty(nE, dtype=torch.float64, device=dev)
+        sg = torch.empty_like(T)
+        rec = {"L": L}
+        sys_d = M.make_system(W, L, flags=M.BUILD_NO_ALIAS)
+        ws = M.allocate_workspace(sys_d, nE, dev)
+        for timed in (False, True):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            k = M.mc_negf_build_kernel(sys_d, V, g, tE, ws)
+            st, I, _ = M.mc_negf_current(k, 1, 0, None, tw, T, sg)
+            if timed:
+                rec.update(I_direct=I, status_direct=st,
+                           direct_ms=1e3 * (time.perf_counter() - t0))
+        del ws
+        sys_m = M.make_system(W, L, flags=M.BUILD_NO_DIRECT)
+        ws = M.allocate_workspace(sys_m, nE, dev)
+        tal = torch.zeros((nE, M.TALLY_N), dtype=torch.int64, device=dev)
+        for timed in (False, True):
+            tal.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            k = M.mc_negf_build_kernel(sys_m, V, g, tE, ws)
+            M.mc_negf_walk(k, seed, 0, 0, 0, walkers, 1_000_000, tal)
+            st, I, sI = M.mc_negf_current(k, 0, 0, tal, tw, T, sg)
+            if timed:
+                t = tal.cpu().numpy()
+                rec.update(I_mc=I, sigma_I_mc=sI, status_mc=st,
+                           mc_ms=1e3 * (time.perf_counter() - t0),
+                           mean_steps_per_walker=float(t[:, 3].sum() / t[:, :3].sum()))
+        rec["mc_minus_direct_in_sigma"] = (rec["I_mc"] - rec["I_direct"]) / rec["sigma_I_mc"]
+        rows.append(rec)
+        del ws
+        torch.cuda.empty_cache()
+    Ls = np.array([r["L"] for r in rows], dtype=np.float64)
+    R = np.array([1.0 / r["I_direct"] for r in rows])
+    b, a = np.polyfit(Ls, R, 1)
+    return {"workload": f"clean wires W={W}, L in {[r['L'] for r in rows]}, eta={eta}t, {nE} "
+                        f"energies in [-3.5,3.5]t, {walkers} walkers/energy",
+            "lengths": rows, "slope_per_slice": float(b), "contact_resistance": float(a),
+            "max_rel_residual": float(np.abs(a + b * Ls - R).max() / R.min())}
+
+
 def inelastic_cpu_baseline(wl, off, lam, seed, n_sample=16, nw=20_000):
     """The oracle's inelastic walker (C, the paper's cumulative-sum sampler) on n_sample
     consecutive energies of the wire's grid from the middle of the band, taken as a closed
@@ -1218,6 +1276,8 @@ def main():
             leg = grad_bench(torch, dev, args.steps, args.warmup, with_cpu)
         elif args.only == "chain":
             leg = chain_bench(torch, dev, args.steps, args.warmup, inputs.RNG_SEED, with_cpu)
+        elif args.only == "resistance":
+            leg = resistance_bench(torch, dev, inputs.RNG_SEED)
         elif args.only == "inelastic":
             leg = inelastic_bench(torch, dev, args.steps, args.warmup, inputs.RNG_SEED, with_cpu)
         elif args.only == "batched":
@@ -1334,6 +1394,8 @@ def main():
     if not args.no_chain:
         line["chain"] = chain_bench(torch, dev, args.steps, args.warmup, seed,
                                     not args.no_cpu_baseline)
+    if not args.no_resistance:
+        line["resistance"] = resistance_bench(torch, dev, seed)
     if not args.no_inelastic:
         line["inelastic"] = inelastic_bench(torch, dev, args.steps, args.warmup, seed,
                                             not args.no_cpu_baseline)
