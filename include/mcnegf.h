@@ -354,7 +354,8 @@ int32_t mc_negf_grad_mc(const mcnegf_kernel* k, uint32_t inject_lead, const uint
  *   exit at q) and to d_hist [2][nE][nE] (int64, device, caller-zeroed): hist[r][e0][e] counts
  *   walkers from e0 absorbed at lead r with energy e.  A table that sends a walk off the grid
  *   ends it as truncated and sets MCNEGF_FLAG_RANGE; max_steps truncation sets
- *   MCNEGF_FLAG_TRUNC.  Asynchronous.
+ *   MCNEGF_FLAG_TRUNC.  table_bytes: the size of d_table (MCNEGF_EWS below
+ *   mc_negf_energy_table_bytes).  Asynchronous.
  * mc_negf_spectrum: d_spectrum [2][nE] (device) = the energy-resolved current
  *   S[r][e] = sum_e0 w_e0 c_p(e0) hist[r][e0][e] / N_e0 (N_e0 the walkers injected at e0);
  *   sum_e S[q][e] is the current of the tallies.  Asynchronous.
@@ -364,7 +365,8 @@ int32_t mc_negf_energy_table(const mcnegf_kernel* k, int32_t n_lines, const int3
                              const double* h_lambda, uint64_t* d_table, uint64_t table_bytes,
                              hipStream_t stream);
 int32_t mc_negf_walk_inelastic(const mcnegf_kernel* k, int32_t n_lines, const int32_t* h_offsets,
-                               const uint64_t* d_table, uint64_t seed, uint32_t realization,
+                               const uint64_t* d_table, uint64_t table_bytes, uint64_t seed,
+                               uint32_t realization,
                                uint32_t inject_lead, uint64_t walker_begin, uint64_t n_walkers,
                                uint32_t max_steps, int64_t* d_tallies, int64_t* d_hist,
                                hipStream_t stream);

@@ -439,7 +439,8 @@ int32_t mc_negf_energy_table(const mcnegf_kernel* k, int32_t n_lines, const int3
 }
 
 int32_t mc_negf_walk_inelastic(const mcnegf_kernel* k, int32_t n_lines, const int32_t* h_offsets,
-                               const uint64_t* d_table, uint64_t seed, uint32_t realization,
+                               const uint64_t* d_table, uint64_t table_bytes, uint64_t seed,
+                               uint32_t realization,
                                uint32_t inject_lead, uint64_t walker_begin, uint64_t n_walkers,
                                uint32_t max_steps, int64_t* d_tallies, int64_t* d_hist,
                                hipStream_t stream) {
@@ -451,6 +452,7 @@ int32_t mc_negf_walk_inelastic(const mcnegf_kernel* k, int32_t n_lines, const in
     if (walker_begin >= 0x100000000ull || n_walkers >= 0x100000000ull ||
         walker_begin + n_walkers >= 0x100000000ull)
         return MCNEGF_EINVAL;
+    if (table_bytes < (uint64_t)k->nE * (uint64_t)k->N * (uint64_t)n_lines * 8) return MCNEGF_EWS;
     const uint32_t tag = (realization << 1) | inject_lead;
     hipError_t err = launch_walk_inelastic(*k, n_lines, h_offsets, d_table, seed, tag,
                                            (uint32_t)walker_begin, (uint32_t)n_walkers,

@@ -146,8 +146,8 @@ def lib() -> ctypes.CDLL:
     L.mc_negf_energy_table_bytes.argtypes = [ctypes.POINTER(KernelStruct), i32,
                                              ctypes.POINTER(u64)]
     L.mc_negf_energy_table.argtypes = [ctypes.POINTER(KernelStruct), i32, vp, vp, vp, u64, vp]
-    L.mc_negf_walk_inelastic.argtypes = [ctypes.POINTER(KernelStruct), i32, vp, vp, u64, u32, u32,
-                                         u64, u64, u32, vp, vp, vp]
+    L.mc_negf_walk_inelastic.argtypes = [ctypes.POINTER(KernelStruct), i32, vp, vp, u64, u64, u32,
+                                         u32, u64, u64, u32, vp, vp, vp]
     L.mc_negf_spectrum.argtypes = [ctypes.POINTER(KernelStruct), u32, vp, vp, vp, vp, vp]
     L.mc_negf_batch_bytes.argtypes = [ctypes.POINTER(KernelStruct), i32, ctypes.POINTER(u64)]
     L.mc_negf_batch_prepare.argtypes = [ctypes.POINTER(KernelStruct), i32,
@@ -628,6 +628,7 @@ def mc_negf_walk_inelastic(k: Kernel, offsets, table, seed: int, realization: in
     return _check("mc_negf_walk_inelastic",
                   lib().mc_negf_walk_inelastic(ctypes.byref(k.struct), int(off.size),
                                                off.ctypes.data_as(ctypes.c_void_p), _ptr(table),
+                                               int(table.numel() * table.element_size()),
                                                int(seed), int(realization), int(inject_lead),
                                                int(walker_begin), int(n_walkers), int(max_steps),
                                                _ptr(tallies), _ptr(hist), _stream(stream)))

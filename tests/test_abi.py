@@ -392,23 +392,25 @@ def test_inelastic_entry_points_validate_on_the_host():
                                     1 << 20, z) == M.EINVAL          # too many lines
     wi = lambda *a: lib.mc_negf_walk_inelastic(ctypes.byref(ks), *a)  # noqa: E731
     off = I32(-1, 0, 1)
-    assert wi(3, off, z, 1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL    # no table
-    assert wi(3, off, p, 1, 0, 2, 0, 10, 10, p, p, z) == M.EINVAL    # lead
-    assert wi(3, off, p, 1, 1 << 30, 0, 0, 10, 10, p, p, z) == M.EINVAL  # realization
-    assert wi(3, off, p, 1, 0, 0, 0, 10, 0, p, p, z) == M.EINVAL     # max_steps
-    assert wi(3, off, p, 1, 0, 0, 7, (1 << 32) - 7, 10, p, p, z) == M.EINVAL  # range
-    assert wi(3, off, p, 1, 0, 0, 0, 10, 10, p, z, z) == M.EINVAL    # no histogram
-    assert wi(3, I32(-1, 0, 5), p, 1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL  # offset
-    assert wi(0, off, p, 1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL    # no lines
+    big = 1 << 40
+    assert wi(3, off, p, tb - 1, 1, 0, 0, 0, 10, 10, p, p, z) == M.EWS  # short table
+    assert wi(3, off, z, big, 1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL    # no table
+    assert wi(3, off, p, big, 1, 0, 2, 0, 10, 10, p, p, z) == M.EINVAL    # lead
+    assert wi(3, off, p, big, 1, 1 << 30, 0, 0, 10, 10, p, p, z) == M.EINVAL  # realization
+    assert wi(3, off, p, big, 1, 0, 0, 0, 10, 0, p, p, z) == M.EINVAL     # max_steps
+    assert wi(3, off, p, big, 1, 0, 0, 7, (1 << 32) - 7, 10, p, p, z) == M.EINVAL  # range
+    assert wi(3, off, p, big, 1, 0, 0, 0, 10, 10, p, z, z) == M.EINVAL    # no histogram
+    assert wi(3, I32(-1, 0, 5), p, big, 1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL  # offset
+    assert wi(0, off, p, big, 1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL    # no lines
     sp = lambda *a: lib.mc_negf_spectrum(ctypes.byref(ks), *a)  # noqa: E731
     assert sp(2, p, p, p, p, z) == M.EINVAL                          # lead
     assert sp(0, p, z, p, p, z) == M.EINVAL                          # no histogram
     ks.nE = 4097  # the walker's exit-energy histogram lives in LDS
-    assert wi(3, off, p, 1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL
+    assert wi(3, off, p, big, 1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL
     ks.nE, ks.alias_pitch = 5, 1 << 29  # one energy's table must stay below 2^32 entries
-    assert wi(3, off, p, 1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL
+    assert wi(3, off, p, big, 1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL
     ks.alias_pitch, ks.alias = 16, 0  # the walks need the kernel's own alias tables
-    assert wi(3, off, p, 1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL
+    assert wi(3, off, p, big, 1, 0, 0, 0, 10, 10, p, p, z) == M.EINVAL
 
 
 def test_walker_build_keeps_the_atomic_optimizer_off():
