@@ -16,6 +16,10 @@
  *   4. the effective L->R transmission either from the walk tallies (MC) or from the
  *      deterministic probe-conservation system (Sec. III C, Eq. (79)), and the current
  *      I = sum_k w_k T_eff(E_k) (midpoint quadrature, Sec. III C).
+ * Further entry points, each declared below with its passage: the gradient of the DIRECT
+ * current, batched walks over many built systems, energy-sampled walks, interpolated
+ * step-6' rows, importance-sampled walks, the score-function gradient of the MC current,
+ * inelastic walks (step 7') and one allocation-free walk.
  *
  * Model.  Sites i = x*W + y (x = 0..L-1 slices, y = 0..W-1), H_ii = V_i, H_ij = -t between
  * nearest neighbours, hard wall in y.  Leads attach to slices 0 (L) and L-1 (R).  Buttiker
