@@ -277,6 +277,9 @@ def add_traffic_rate(roof):
     if t is not None and ms:
         roof["traffic_gbs"] = t / 1e9 / (ms * 1e-3)
         roof["traffic_frac_of_hbm_peak"] = roof["traffic_gbs"] / HBM_PEAK_GBS
+        # the useful fraction of what moves: algorithmic bytes over measured bytes
+        if roof.get("unit") == "GB/s" and roof.get("algorithmic_per_launch"):
+            roof["useful_fraction_of_traffic"] = roof["algorithmic_per_launch"] / t
     return roof
 
 

@@ -64,6 +64,12 @@ def test_traffic_rate():
     assert r["traffic_gbs"] == pytest.approx(4000.0)
     assert r["traffic_frac_of_hbm_peak"] == pytest.approx(0.5)
     assert "traffic_gbs" not in bench.add_traffic_rate({"traffic": None, "avg_launch_ms": 0.5})
+    r = bench.add_traffic_rate({"traffic": 2e9, "avg_launch_ms": 0.5, "unit": "GB/s",
+                                "algorithmic_per_launch": 1.2e9})
+    assert r["useful_fraction_of_traffic"] == pytest.approx(0.6)
+    r = bench.add_traffic_rate({"traffic": 2e9, "avg_launch_ms": 0.5, "unit": "TFLOP/s",
+                                "algorithmic_per_launch": 1e12})
+    assert "useful_fraction_of_traffic" not in r
 
 
 def test_measured_traffic_only_for_the_profiled_source(tmp_path, monkeypatch):
