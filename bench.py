@@ -1123,6 +1123,34 @@ def inelastic_bench(torch, dev, steps, warmup, seed, with_cpu, walkers=None):
         "per_kernel": per_kernel,
         "roofline": roof,
     }
+    # time to sigma_I <= 1% of I (median of 5 warm repetitions): build, step-7' table, then
+    # batches of inelastic walks (1024 per energy first, then sized from sigma_I); the
+    # realized deviation is measured against the 1e6-walker current above
+    times, counts, devs = [], [], []
+    table = state["table"]
+    for rep in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k = M.mc_negf_build_kernel(sysm, V, g, tE, ws)
+        M.mc_negf_energy_table(k, off, lam, table)
+        tal.zero_()
+        hist.zero_()
+        done, batch = 0, 1024
+        while True:
+            M.mc_negf_walk_inelastic(k, off, table, seed + 1 + rep, 0, 0, done, batch, 1_000_000,
+                                     tal, hist)
+            done += batch
+            _, Ib, sb = M.mc_negf_current(k, 0, 0, tal, tw, T, sg)
+            if sb <= 0.01 * abs(Ib) or done >= 1 << 24:
+                break
+            batch = next_batch(done, Ib, sb, 1024, 1 << 24)
+        times.append(time.perf_counter() - t0)
+        counts.append(done)
+        devs.append(abs(Ib - I) / abs(I))
+    out["time_to_1pct"] = {"mc_ms": 1e3 * float(np.median(times)),
+                           "mc_walkers_per_energy": int(np.median(counts)),
+                           "rel_dev_from_1e6_walker_current": devs,
+                           "stop_rule": "sigma_I / I <= 0.01"}
     if with_cpu:
         out["cpu_baseline"] = inelastic_cpu_baseline(wl, off, lam, seed)
     del ws, state
