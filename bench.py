@@ -1001,6 +1001,30 @@ def chain_bench(torch, dev, steps, warmup, seed, with_cpu):
         "per_kernel": per_kernel,
         "time_to_1pct": time_to_1pct(p, torch, seed, True),
     }
+    # the same step captured once as a HIP graph and replayed: at N = 50 its dozen small
+    # kernels take less time than their launches
+    gs = torch.cuda.Stream(device=dev)  # default priority
+    torch.cuda.synchronize()
+    with torch.cuda.stream(gs):
+        M.mc_negf_graph_begin(gs)
+        run_step(p, walkers, seed, True)
+        graph = M.mc_negf_graph_end(gs)
+    try:
+        for _ in range(max(1, warmup)):
+            graph.launch(gs)
+        gs.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            graph.launch(gs)
+        gs.synchronize()
+        gwall = time.perf_counter() - t0
+    finally:
+        graph.destroy()
+    g_mc, g_I, g_s, g_d, g_Id = step_results(p, True)
+    out["graph"] = {"ms_per_step": 1e3 * gwall / steps, "value": steps_total / gwall,
+                    "same_results": bool(g_I == I_mc and g_s == s_mc and g_Id == I_d),
+                    "what": "one step captured as a HIP graph (build, walks, MC and DIRECT "
+                            "currents) and replayed"}
     if with_cpu:
         from oracle import dense as D
         E, w = inputs.energy_grid(wl.emin, wl.emax, wl.n_energies)
