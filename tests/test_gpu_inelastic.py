@@ -12,6 +12,7 @@
 - Statistics: the GPU's exit distribution and current agree with the exact chain within 5
   sigma (bins) and 4 sigma (current); the energy-resolved current equals the oracle's from the
   same histogram and sums to the current of the tallies.
+- The benchmark's configuration (full wire, phonon lines): properties that hold at any size.
 """
 import numpy as np
 import pytest
@@ -215,3 +216,35 @@ def test_inelastic_argument_checks():
     with pytest.raises(M.McnegfError) as ei:
         M.mc_negf_energy_table(k, [-1, 0, 1], [1.0, 1.0, 1.0], small)
     assert ei.value.code == M.EWS
+
+
+def test_wire_walks_with_the_phonon_lines():
+    # the benchmark's configuration (W = 10, L = 100, 256 energies, lines 0 and -/+8) with
+    # 1e5 walkers per energy, checked by properties that hold at any size: every walker is
+    # tallied once, every exit is in the histogram, exits differ from their injection energy
+    # by multiples of the line spacing only, the energy-resolved current sums to the current,
+    # and emission (weight 0.563) outweighs absorption (0.063)
+    wl = inputs.WIRE_W10_L100
+    c = case(W=wl.W, L=wl.L, eta=wl.eta, disorder=0.0, nE=wl.n_energies, emin=wl.emin,
+             emax=wl.emax)
+    c["V"] = inputs.onsite(wl)
+    k = gpu_build(c)
+    off, lam = list(inputs.PHONON_LINES), [float(x) for x in inputs.PHONON_WEIGHTS]
+    t = gpu_table(k, off, lam)
+    nw = 100_000
+    tal, hist = gpu_walk(k, off, t, nw)
+    assert (tal[:, :3].sum(axis=1) == nw).all() and tal[:, 2].sum() == 0
+    assert (hist.sum(axis=2) == tal[:, :2].T).all()
+    de = np.subtract.outer(np.arange(wl.n_energies), np.arange(wl.n_energies)).T  # e - e0
+    assert hist[:, de % inputs.PHONON_STEPS != 0].sum() == 0
+    assert hist[:, de < 0].sum() > 5 * hist[:, de > 0].sum() > 0
+    assert M.mc_negf_status(k) & (M.FLAG_TRUNC | M.FLAG_RANGE | M.FLAG_NONFINITE) == 0
+    w = torch.tensor(c["w"], device=DEV)
+    T = torch.empty(k.nE, dtype=torch.float64, device=DEV)
+    sg = torch.empty_like(T)
+    _, I, sI = M.mc_negf_current(k, 0, 0, torch.from_numpy(tal).to(DEV), w, T, sg)
+    S = torch.empty((2, k.nE), dtype=torch.float64, device=DEV)
+    M.mc_negf_spectrum(k, 0, torch.from_numpy(tal).to(DEV), torch.from_numpy(hist).to(DEV), w, S)
+    torch.cuda.synchronize()
+    assert float(S[1].sum()) == pytest.approx(I, rel=1e-12)
+    assert sI < 0.01 * I
