@@ -542,15 +542,19 @@ __global__ void __launch_bounds__(512) cholesky_kernel(CholArgs a) {
         // Wavefront w owns the 16 x 16 blocks p = w and p = w + 8 (block row p / 4, column p % 4).
         {
             dmfma4 accd[2] = {dmfma4{0.0, 0.0, 0.0, 0.0}, dmfma4{0.0, 0.0, 0.0, 0.0}};
+            // chunk it + 1 is in registers while chunk it + 2 is loaded (two chunks ahead: this
+            // pass has little MFMA work to cover a load); loads past the last chunk re-read it
+            // and their data is never used, so neither loads nor stores are predicated
+            double4 bnext = {0.0, 0.0, 0.0, 0.0};
             if (c0 > 0) {
                 stage_store(Bs[0], sm, sc, stage_load(Le, ld, R, c0 + sm, sc));
+                bnext = stage_load(Le, ld, R, c0 + sm, min(CH_KC, c0 - CH_KC) + sc);
                 __syncthreads();
             }
             for (int kc = 0, it = 0; kc < c0; kc += CH_KC, ++it) {
                 const double* B = Bs[it & 1];
-                const bool more = kc + CH_KC < c0;
-                double4 bst = {0.0, 0.0, 0.0, 0.0};
-                if (more) bst = stage_load(Le, ld, R, c0 + sm, kc + CH_KC + sc);
+                const double4 bst = bnext;
+                bnext = stage_load(Le, ld, R, c0 + sm, min(kc + 2 * CH_KC, c0 - CH_KC) + sc);
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int p = wave + 8 * h;
@@ -569,7 +573,7 @@ __global__ void __launch_bounds__(512) cholesky_kernel(CholArgs a) {
                         }
                     }
                 }
-                if (more) stage_store(Bs[(it & 1) ^ 1], sm, sc, bst);
+                stage_store(Bs[(it & 1) ^ 1], sm, sc, bst);  // unread after the last chunk
                 __syncthreads();
             }
 #pragma unroll
