@@ -1053,7 +1053,7 @@ def chain_bench(torch, dev, steps, warmup, seed, with_cpu):
     return out
 
 
-def inelastic_bench(torch, dev, steps, warmup, seed, with_cpu, walkers=None):
+def inelastic_bench(torch, dev, steps, warmup, seed, with_cpu, walkers=None, ttp=True):
     """Inelastic walks (step 7') on the wire (W = 10, L = 100, eta = 0.05 t, 256 energies,
     1e6 walkers per energy) with an elastic line and optical-phonon emission / absorption lines
     8 grid steps away (inputs.PHONON_LINES / PHONON_WEIGHTS).  One step = build (no DIRECT
@@ -1152,7 +1152,7 @@ def inelastic_bench(torch, dev, steps, warmup, seed, with_cpu, walkers=None):
     # realized deviation is measured against the 1e6-walker current above
     times, counts, devs = [], [], []
     table = state["table"]
-    for rep in range(5):
+    for rep in range(5 if ttp else 0):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         k = M.mc_negf_build_kernel(sysm, V, g, tE, ws)
@@ -1171,10 +1171,11 @@ def inelastic_bench(torch, dev, steps, warmup, seed, with_cpu, walkers=None):
         times.append(time.perf_counter() - t0)
         counts.append(done)
         devs.append(abs(Ib - I) / abs(I))
-    out["time_to_1pct"] = {"mc_ms": 1e3 * float(np.median(times)),
-                           "mc_walkers_per_energy": int(np.median(counts)),
-                           "rel_dev_from_1e6_walker_current": devs,
-                           "stop_rule": "sigma_I / I <= 0.01"}
+    if ttp:
+        out["time_to_1pct"] = {"mc_ms": 1e3 * float(np.median(times)),
+                               "mc_walkers_per_energy": int(np.median(counts)),
+                               "rel_dev_from_1e6_walker_current": devs,
+                               "stop_rule": "sigma_I / I <= 0.01"}
     if with_cpu:
         out["cpu_baseline"] = inelastic_cpu_baseline(wl, off, lam, seed)
     del ws, state
@@ -1334,7 +1335,8 @@ def main():
         elif args.only == "resistance":
             leg = resistance_bench(torch, dev, inputs.RNG_SEED)
         elif args.only == "inelastic":
-            leg = inelastic_bench(torch, dev, args.steps, args.warmup, inputs.RNG_SEED, with_cpu)
+            leg = inelastic_bench(torch, dev, args.steps, args.warmup, inputs.RNG_SEED, with_cpu,
+                                  ttp=not args.no_ttp)
         elif args.only == "batched":
             leg = batched_bench(torch, dev, args.steps, args.warmup, args.batch_budget_gb,
                                 inputs.RNG_SEED)
@@ -1453,7 +1455,8 @@ def main():
         line["resistance"] = resistance_bench(torch, dev, seed)
     if not args.no_inelastic:
         line["inelastic"] = inelastic_bench(torch, dev, args.steps, args.warmup, seed,
-                                            not args.no_cpu_baseline)
+                                            with_cpu=not args.no_cpu_baseline,
+                                            ttp=not args.no_ttp)
     if not args.no_grad:
         line["grad"] = grad_bench(torch, dev, args.steps, args.warmup, not args.no_cpu_baseline)
     if not args.no_batched:
