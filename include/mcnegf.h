@@ -327,15 +327,15 @@ int32_t mc_negf_grad_mc(const mcnegf_kernel* k, uint32_t inject_lead, const uint
 /*
  * Inelastic walks: step 7' of Sec. II F.  With Buttiker's approximation and an energy-changing
  * coupling lambda~_i(E, E'), a walker that step 6' sends to probe i at energy E_n draws its next
- * energy from p(E) = lambda~_i(E, E_n) A_ii(E) / (integral over E of the same) (the probability
- * that follows the choice of the index, Sec. II F) and continues from probe i's row at that
- * energy.  The coupling here is a set of lines on the energy grid of the handle,
+ * energy from p(E) = lambda~_i(E, E_n) A_ii(E) / (integral over E of the same) (Eq. (74),
+ * the probability that follows the choice of the index, Sec. II F) and continues from probe
+ * i's row at that energy.  The coupling here is a set of lines on the energy grid of the handle,
  *   lambda~_i(E, E_n) = sum_k lambda_k delta(E - E_n - Delta_k),  Delta_k = offsets[k] grid steps,
  * the same for every site (e.g. an elastic line at 0 and phonon emission / absorption lines at
  * -m / +m); a line that leaves the grid has weight 0.  The energies must be evenly spaced for
  * a line to be a fixed energy transfer (not checked).  The dephasing rates gamma_i of the build
- * stay the caller's: condition (iv) of Sec. II F ties them to the coupling, but the walk is a
- * proper Markov chain either way (step 7' is normalised by its own sum).
+ * stay the caller's: condition (iv) of Sec. II F (Eq. (69)) ties them to the coupling, but the
+ * walk is a proper Markov chain either way (step 7' is normalised by its own sum).
  *   n_lines    1 .. 8 lines; h_offsets [n_lines] host, |offset| < nE; h_lambda [n_lines] host,
  *              finite, >= 0, and from every energy some line of positive weight stays on the grid
  *              (else MCNEGF_EINVAL).

@@ -5,7 +5,7 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).  Never called by the HIP libr
 
 Model.  Buttiker's approximation with an energy-changing coupling lambda~_i(E, E') (Sec. II F):
 after step 6' has drawn a probe i at energy E_n, step 7' draws the next energy with
-    p(E) = lambda~_i(E, E_n) A_ii(E) / integral dE lambda~_i(E, E_n) A_ii(E)      (Eq. draw_E_last)
+    p(E) = lambda~_i(E, E_n) A_ii(E) / integral dE lambda~_i(E, E_n) A_ii(E)      (Eq. (74))
 and the walk continues from probe i's row at that energy (step 11: psi = G(E)|i>).  Here the
 coupling is a sum of lines on the energy grid, lambda~_i(E, E_n) = sum_k lambda_k
 delta(E - E_n - Delta_k) with Delta_k = offsets[k] grid steps (an elastic line at 0, phonon
@@ -13,7 +13,7 @@ emission and absorption at -/+ hbar omega, ...), the same for every site; a line
 outside the grid has weight 0 (the energy window is closed).  So from (E_n, i) the walk moves
 to E_n + Delta_k with probability x_k / sum x, x_k = lambda_k A_ii(E_n + Delta_k).
 
-Condition (iv) of Sec. II F ties the dephasing rates to the coupling, gamma_i(E) =
+Condition (iv) of Sec. II F (Eq. (69)) ties the dephasing rates to the coupling, gamma_i(E) =
 integral dE' lambda~_i(E', E) A_ii(E'); the walk is a proper Markov chain whether or not the
 caller's gamma satisfies it (step 7' is normalised by its own sum).
 

@@ -1647,8 +1647,8 @@ hipError_t launch_walk_counts(const mcnegf_kernel& k, uint64_t seed, uint32_t ta
 
 // ---- inelastic walks (Sec. II F, step 7') -------------------------------------------------
 //
-// After step 6' draws probe i at energy E_n, step 7' draws the next energy: with the coupling
-// lambda~_i(E, E_n) = sum_k lambda_k delta(E - E_n - Delta_k) (lines on the energy grid,
+// After step 6' draws probe i at energy E_n, step 7' draws the next energy (Eq. (74)): with
+// the coupling lambda~_i(E, E_n) = sum_k lambda_k delta(E - E_n - Delta_k) (lines on the grid,
 // Delta_k = off[k] grid steps) the walk moves to E_n + Delta_k with probability
 // x_k / sum x, x_k = lambda_k A_ii(E_n + Delta_k) (zero off the grid), and continues from
 // probe i's row at that energy.  The table holds, per (energy, probe), the running sums of x
