@@ -74,11 +74,18 @@ __global__ void __launch_bounds__(64) fullinv_kernel(const double2* __restrict__
                                                       double* __restrict__ wL,
                                                       double* __restrict__ wR,
                                                       double2* __restrict__ corner,
-                                                      double2* __restrict__ Gc, int64_t ldG) {
+                                                      double2* __restrict__ Gc, int64_t ldG,
+                                                      int nE) {
     const int N = W * L;
-    const int e = blockIdx.y;
+    // XCD-aware order: workgroups are dealt to the eight XCDs in turn (workgroup b on XCD
+    // b % 8); every column tile of energy e runs on XCD e % 8, whose L2 then fetches that
+    // energy's RGF blocks once for all its tiles
+    const int tiles = (N + 63) / 64;
+    const int xcd = blockIdx.x & 7, jb = blockIdx.x >> 3;
+    const int e = xcd + 8 * (jb / tiles);
+    if (e >= nE) return;  // padding of the last round (whole workgroup)
     const int lane = threadIdx.x;
-    const int wave_first = blockIdx.x * 64;
+    const int wave_first = (jb % tiles) * 64;
     const int col = wave_first + lane;
     const bool valid = col < N;
     const int colc = valid ? col : N - 1;
@@ -178,14 +185,16 @@ __global__ void __launch_bounds__(64) fullinv_kernel(const double2* __restrict__
 template <int W, bool STORE_G>
 static hipError_t launch_fullinv_w(const mcnegf_kernel& k, double2* Gc, int64_t ldG,
                                    hipStream_t s) {
-    dim3 grid((k.N + 63) / 64, k.nE);
+    const unsigned tiles = (unsigned)((k.N + 63) / 64);
+    dim3 grid(8u * tiles * (unsigned)((k.nE + 7) / 8));
     {
         MCNEGF_TIMED(STORE_G ? "fullinv_store_g_kernel" : "fullinv_kernel", s);
         hipLaunchKernelGGL((fullinv_kernel<W, STORE_G>), grid, dim3(64), 0, s,
                            reinterpret_cast<const double2*>(k.gL),
                            reinterpret_cast<const double2*>(k.gR),
                            reinterpret_cast<const double2*>(k.Gd), k.gam_lead, k.L, k.t, k.p_pitch,
-                           k.P, k.wL, k.wR, reinterpret_cast<double2*>(k.corner), Gc, ldG);
+                           k.P, k.wL, k.wR, reinterpret_cast<double2*>(k.corner), Gc, ldG,
+                           k.nE);
     }
     return hipGetLastError();
 }
