@@ -4,7 +4,9 @@ to the full N = 16000 workload, against the sparse-column oracle (oracle/columns
 At N = 4160 and 8320 (the two large-row shapes of the alias build) every energy's DIRECT
 T_eff is compared with the oracle's probe solve over all N columns (1e-10 relative), the
 walker replays the GPU's own tables bit for bit in the oracle's C walker (N = 4160), and
-sampled columns of |G|^2 and sampled alias rows are compared one by one.  At N = 16000, with
+sampled columns of |G|^2 and sampled alias rows are compared one by one; rows of the maximum
+length (N + 2 = 16320 outcomes, a W = 2 wire of 8159 slices) get the same sampled checks, the
+bit-for-bit walker replay and the Monte Carlo/DIRECT agreement.  At N = 16000, with
 the batch of energies the benchmark builds at once, the oracle computes sampled columns and
 kernel rows one by one and the T_eff of one energy from all 16000 columns (1e-10 relative,
 about a minute on the host); the other energies' T_eff are checked by the property that
@@ -109,6 +111,48 @@ def test_w32_l130_walker_replays_long_tables_bit_for_bit():
         ref = OW.walk_alias(thr, al, SEED, 3, inject, 500, nw)
         assert (tal.cpu().numpy() == ref).all()
         assert ref[:, 3].sum() > 3 * nw  # walks of several steps visit many rows
+
+
+def test_rows_of_the_maximum_length():
+    # N + 2 = 16320 outcomes, the longest row the alias build holds in one workgroup's LDS
+    # (10 bytes per outcome), on a thin wire: W = 2, L = 8159 (N = 16318), two energies in
+    # both transverse bands
+    wl = inputs.WIRE_W10_L100.replace(W=2, L=8159, n_energies=2, eta=0.1)
+    E, w = inputs.energy_grid(-1.5, 0.5, 2)
+    k = build(wl, E)
+    N, n = k.N, k.n_out
+    assert n == 16320
+    wt = torch.tensor(w, device=DEV)
+    Td = torch.empty(2, dtype=torch.float64, device=DEV)
+    sd = torch.empty_like(Td)
+    st, I_d, _ = M.mc_negf_current(k, 1, 0, None, wt, Td, sd)
+    assert st == M.OK and flags_ok(k)
+    rng = np.random.default_rng(16320)
+    for e in range(2):
+        ora = oracle_energy(wl, E[e])
+        cols = [0, int(rng.integers(1, N - 1)), N - 1]
+        rows = sorted({0, int(rng.integers(1, N - 1)), N - 1, N, N + 1})
+        check_columns_and_rows(k, e, ora, cols, rows)
+    # the oracle's C walker replays the GPU walker on the GPU's own tables (alias indices up
+    # to 16319 in the packed entries)
+    thr, al = k.alias_tables()
+    nw = 20_000
+    tal = torch.zeros((2, M.TALLY_N), dtype=torch.int64, device=DEV)
+    M.mc_negf_walk(k, SEED, 0, 0, 0, nw, 1_000_000, tal)
+    ref = OW.walk_alias(thr, al, SEED, 0, 0, 0, nw)
+    assert (tal.cpu().numpy() == ref).all()
+    del thr, al
+    # Monte Carlo against DIRECT (a property at any size)
+    nw = 400_000
+    tal.zero_()
+    M.mc_negf_walk(k, SEED, 1, 0, 0, nw, 1_000_000, tal)
+    T = torch.empty(2, dtype=torch.float64, device=DEV)
+    sg = torch.empty_like(T)
+    st, I_mc, s_mc = M.mc_negf_current(k, 0, 0, tal, wt, T, sg)
+    assert st == M.OK
+    assert abs(I_mc - I_d) <= 4.0 * s_mc, (I_mc, I_d, s_mc)
+    del k, tal
+    torch.cuda.empty_cache()
 
 
 def test_full_size_w32_l500_batch():
