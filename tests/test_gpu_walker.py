@@ -189,3 +189,33 @@ def test_mc_estimator_matches_oracle_estimator(inject, max_steps):
     To, so, Io, sIo = OW.mc_current(t, c_ora, c["w"], inject)
     assert np.allclose(T, To, rtol=1e-10, atol=0) and np.allclose(sg, so, rtol=1e-10, atol=0)
     assert abs(I - Io) <= 1e-10 * abs(Io) and abs(sI - sIo) <= 1e-10 * sIo
+
+
+def test_zero_walkers_launch_nothing_and_estimate_zero():
+    # n_walkers = 0 is a valid request: every walk entry returns OK without touching its
+    # outputs, and the estimators of empty tallies give T = 0, sigma = 0 (no division by zero)
+    c = case(W=2, L=3, eta=0.2, disorder=0.1, nE=4, emin=-1.2, emax=1.2)
+    k = gpu_build(c)
+    sentinel = 7
+    tal = torch.full((4, M.TALLY_N), sentinel, dtype=torch.int64, device=DEV)
+    assert M.mc_negf_walk(k, SEED, 0, 0, 0, 0, 1_000_000, tal) == M.OK
+    w = torch.full((4,), 0.25, dtype=torch.float64, device=DEV)
+    scratch = torch.empty(max(256, M.mc_negf_walk_sampled_bytes(k, 0)), dtype=torch.uint8,
+                          device=DEV)
+    assert M.mc_negf_walk_sampled(k, SEED, 0, 0, 0, 0, 1_000_000, w, tal, scratch) == M.OK
+    assert M.mc_negf_walk_sampled_noalloc(k, SEED, 0, 0, 0, 0, 1_000_000, w, tal) == M.OK
+    counts = torch.full((M.mc_negf_walk_counts_bytes(k) // 4,), sentinel, dtype=torch.int32,
+                        device=DEV)
+    assert M.mc_negf_walk_counts(k, SEED, 0, 0, 0, 0, 1_000_000, counts, tal) == M.OK
+    et = torch.empty(M.mc_negf_energy_table_bytes(k, 1) // 8, dtype=torch.int64, device=DEV)
+    M.mc_negf_energy_table(k, [0], [1.0], et)
+    hist = torch.full((2, 4, 4), sentinel, dtype=torch.int64, device=DEV)
+    assert M.mc_negf_walk_inelastic(k, [0], et, SEED, 0, 0, 0, 0, 1_000_000, tal, hist) == M.OK
+    torch.cuda.synchronize()
+    assert (tal == sentinel).all() and (hist == sentinel).all() and (counts == sentinel).all()
+    tal.zero_()
+    T = torch.full((4,), -1.0, dtype=torch.float64, device=DEV)
+    sg = torch.full((4,), -1.0, dtype=torch.float64, device=DEV)
+    st, I, sI = M.mc_negf_current(k, 0, 0, tal, w, T, sg)
+    assert st == M.OK and I == 0.0 and sI == 0.0
+    assert (T == 0).all() and (sg == 0).all()
