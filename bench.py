@@ -50,8 +50,8 @@ PROFILES = os.path.join(ROOT, "profiles")
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--walkers", type=int, default=None, help="walkers per energy (default 1e6)")
     ap.add_argument("--etas", type=str, default=None, help="comma-separated dephasing rates")
     ap.add_argument("--no-cpu-baseline", action="store_true")
