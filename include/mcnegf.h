@@ -609,7 +609,9 @@ int32_t mc_negf_graph_destroy(mcnegf_graph g);
  * events and the kernel names.  At most MCNEGF_PROFILE_MAX launches are recorded; later ones
  * are counted in `dropped`.  mc_negf_profile_end synchronises the events, writes each
  * launch's duration in milliseconds to ms_out[0 .. p->n - 1] (host, may be null), destroys
- * the events and detaches p.  Only one profile per thread is active at a time.
+ * the events and detaches p.  Only one profile per thread is active at a time.  Timing never
+ * changes a launch's own result: a launch whose events could not be recorded makes
+ * mc_negf_profile_end return MCNEGF_EHIP (its duration reads 0).
  */
 #define MCNEGF_PROFILE_MAX 512
 typedef struct mcnegf_profile {

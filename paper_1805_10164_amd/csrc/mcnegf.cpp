@@ -13,6 +13,8 @@ namespace mcnegf {
 static thread_local int32_t g_last_hip_error = 0;
 static thread_local mcnegf_profile* g_profile = nullptr;
 
+// A failed event record is not checked here (timing must not change a launch's result): the
+// slot's elapsed time then cannot be read, and mc_negf_profile_end returns MCNEGF_EHIP.
 LaunchTimer::LaunchTimer(const char* name, hipStream_t stream) : p(g_profile), slot(-1), s(stream) {
     if (!p) return;
     if (p->n >= MCNEGF_PROFILE_MAX) {
@@ -21,11 +23,11 @@ LaunchTimer::LaunchTimer(const char* name, hipStream_t stream) : p(g_profile), s
     }
     slot = p->n++;
     p->name[slot] = name;
-    hipEventRecord(p->start[slot], s);
+    (void)hipEventRecord(p->start[slot], s);
 }
 
 LaunchTimer::~LaunchTimer() {
-    if (p && slot >= 0) hipEventRecord(p->stop[slot], s);
+    if (p && slot >= 0) (void)hipEventRecord(p->stop[slot], s);
 }
 
 static int32_t hip_fail(hipError_t e) {
@@ -478,9 +480,9 @@ int32_t mc_negf_profile_begin(mcnegf_profile* p) {
         hipError_t err;
         if ((err = hipEventCreate(&p->start[i])) != hipSuccess ||
             (err = hipEventCreate(&p->stop[i])) != hipSuccess) {
-            for (int j = 0; j <= i; ++j) {
-                if (p->start[j]) hipEventDestroy(p->start[j]);
-                if (p->stop[j]) hipEventDestroy(p->stop[j]);
+            for (int j = 0; j <= i; ++j) {  // cleanup: a failed destroy leaves nothing to do
+                if (p->start[j]) (void)hipEventDestroy(p->start[j]);
+                if (p->stop[j]) (void)hipEventDestroy(p->stop[j]);
             }
             std::memset(p, 0, sizeof(*p));
             return hip_fail(err);
@@ -502,8 +504,8 @@ int32_t mc_negf_profile_end(mcnegf_profile* p, float* ms_out) {
         if (ms_out) ms_out[i] = ms;
     }
     for (int i = 0; i < MCNEGF_PROFILE_MAX; ++i) {
-        hipEventDestroy(p->start[i]);
-        hipEventDestroy(p->stop[i]);
+        (void)hipEventDestroy(p->start[i]);
+        (void)hipEventDestroy(p->stop[i]);
     }
     return rc;
 }
