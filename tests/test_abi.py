@@ -81,6 +81,17 @@ def test_workspace_bytes_and_validation():
     assert 16000 * 16000 * (8 + 6 + 8) < nb < 16016 * 16016 * 23
 
 
+def test_workspace_bytes_do_not_wrap_at_the_largest_sizes():
+    # the longest rows (N + 2 = 16320) with the most energies an int32 count allows: about
+    # 1.3e19 bytes, below 2^64, and linear in the energy count (no 64-bit wrap-around)
+    for W, L in [(2, 8159), (32, 509)]:
+        s = M.make_system(W, L)
+        one = M.mc_negf_workspace_bytes(s, 1)
+        big = M.mc_negf_workspace_bytes(s, 2**31 - 1)
+        assert big == pytest.approx(one * (2**31 - 1), rel=1e-5)
+        assert big > M.mc_negf_workspace_bytes(s, 2**30)
+
+
 def test_host_validation_rejects_before_any_gpu_call():
     # null device pointers and bad sizes are rejected on the host, so this runs without a GPU
     lib = M.lib()
