@@ -103,10 +103,13 @@ static Layout layout_of(const mcnegf_system* s, int nE) {
     return make_layout(s->W, s->L, nE, with_alias(s), with_direct(s), with_refine(s));
 }
 
+// A handle as mc_negf_build_kernel fills it: sizes consistent (compared in 64 bits, so a
+// corrupt handle cannot overflow them), rows within the 16-bit alias indices, buffers set.
 static bool valid_kernel(const mcnegf_kernel* k) {
-    return k && k->W >= 1 && k->W <= kMaxW && k->L >= 1 && k->N == k->W * k->L &&
-           k->n_out == k->N + 2 && k->nE >= 1 && k->p_pitch >= k->N && k->p_pitch % 16 == 0 && k->P && k->lead && k->status &&
-           k->counters && k->reduce;
+    return k && k->W >= 1 && k->W <= kMaxW && k->L >= 1 &&
+           (int64_t)k->N == (int64_t)k->W * k->L && (int64_t)k->n_out == (int64_t)k->N + 2 &&
+           k->n_out <= kMaxOut && k->nE >= 1 && k->p_pitch >= k->N && k->p_pitch % 16 == 0 &&
+           k->P && k->lead && k->status && k->counters && k->reduce;
 }
 
 static int32_t status_to_code(uint32_t flags, bool mc) {

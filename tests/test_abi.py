@@ -431,3 +431,69 @@ def test_walker_build_keeps_the_atomic_optimizer_off():
     assert "-amdgpu-atomic-optimizer-strategy=None" in B.EXTRA["walker.hip"]
     assert all(f in B.FLAGS for f in ("-Xclang", "-packed-fp32-ops"))
     assert "walker.hip" in B.SOURCES and "score.hip" in B.SOURCES
+
+
+# ---- property tests of the host validation (hypothesis; nothing reaches the GPU) ----------------
+
+from hypothesis import assume, given, settings, strategies as st  # noqa: E402
+
+U32, U64 = 2**32, 2**64
+
+
+def _edges(*points, top):
+    """Integers near the given boundaries plus anything in [0, top)."""
+    near = [st.integers(max(0, p - 2), min(top - 1, p + 2)) for p in points]
+    return st.one_of(*near, st.integers(0, top - 1))
+
+
+def _fake_handle(W=2, L=3, N=None, n_out=None, nE=1, p_pitch=16):
+    ks = M.KernelStruct()
+    ks.W, ks.L, ks.nE, ks.p_pitch = W, L, nE, p_pitch
+    ks.N = W * L if N is None else N
+    ks.n_out = ks.N + 2 if n_out is None else n_out
+    for f in ("alias", "alias_lo", "P", "lead", "status", "counters", "reduce"):
+        setattr(ks, f, 4096)  # never dereferenced: validation fails before any GPU work
+    return ks
+
+
+@settings(max_examples=400, deadline=None)
+@given(lead=_edges(0, 1, top=U32), real=_edges(0, 2**30, top=U32),
+       begin=_edges(0, 2**32, top=U64), n=_edges(0, 2**32, top=U64),
+       max_steps=_edges(0, 1, top=U32))
+def test_walk_arguments_outside_their_ranges_are_rejected(lead, real, begin, n, max_steps):
+    ok = lead <= 1 and real < 2**30 and max_steps >= 1 and begin + n < 2**32
+    assume(not ok)
+    ks = _fake_handle()
+    t = ctypes.c_void_p(4096)
+    assert M.lib().mc_negf_walk(ctypes.byref(ks), 1, real, lead, begin, n, max_steps, t,
+                                None) == M.EINVAL
+
+
+I32 = 2**31
+
+
+@settings(max_examples=400, deadline=None)
+@given(W=st.integers(-1, 34), L=_edges(1, 8160, I32 - 1, top=I32), dN=st.integers(-1, 1),
+       dn=st.integers(-1, 1), nE=st.integers(-1, 2), dp=st.integers(-17, 17))
+def test_inconsistent_kernel_handles_are_rejected(W, L, dN, dn, nE, dp):
+    N = W * L + dN
+    n_out = N + 2 + dn
+    p_pitch = max(0, ((N + 15) // 16) * 16 + dp)
+    assume(-I32 <= N < I32 and -I32 <= n_out < I32)
+    ok = (1 <= W <= 32 and L >= 1 and dN == 0 and dn == 0 and n_out <= 16320 and nE >= 1
+          and p_pitch >= N and p_pitch % 16 == 0)
+    assume(not ok)
+    ks = _fake_handle(W, L, N, n_out, nE, p_pitch)
+    t = ctypes.c_void_p(4096)
+    assert M.lib().mc_negf_walk(ctypes.byref(ks), 1, 0, 0, 0, 10, 10, t, None) == M.EINVAL
+
+
+def test_handle_whose_size_wraps_in_32_bits_is_rejected():
+    # W L = 2 (2^31 - 1) wraps to -2 in 32 bits; a handle carrying the wrapped N (and n_out =
+    # N + 2 = 0) must not pass as consistent
+    ks = _fake_handle(W=2, L=2**31 - 1, N=-2, n_out=0, nE=1, p_pitch=0)
+    t = ctypes.c_void_p(4096)
+    assert M.lib().mc_negf_walk(ctypes.byref(ks), 1, 0, 0, 0, 10, 10, t, None) == M.EINVAL
+    # rows above 16320 outcomes do not fit the walker's 16-bit alias indices
+    ks = _fake_handle(W=32, L=510, nE=1, p_pitch=16320)
+    assert M.lib().mc_negf_walk(ctypes.byref(ks), 1, 0, 0, 0, 10, 10, t, None) == M.EINVAL
