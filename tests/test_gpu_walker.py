@@ -219,3 +219,27 @@ def test_zero_walkers_launch_nothing_and_estimate_zero():
     st, I, sI = M.mc_negf_current(k, 0, 0, tal, w, T, sg)
     assert st == M.OK and I == 0.0 and sI == 0.0
     assert (T == 0).all() and (sg == 0).all()
+
+
+def test_more_energies_than_the_reported_grid_height():
+    # the alias build launches rows x energies; 70000 energies exceed the 65536 the runtime
+    # reports as the grid's y extent: the tables beyond it must equal single-energy builds, and
+    # the walker on all 70000 energies must replay in the oracle walker
+    nE = 70_000
+    sysm = M.make_system(1, 2)
+    V = torch.zeros(2, dtype=torch.float64, device=DEV)
+    g = torch.full((2,), 0.1, dtype=torch.float64, device=DEV)
+    E, _ = inputs.energy_grid(-1.5, 1.5, nE)
+    ws = M.allocate_workspace(sysm, nE)
+    k = M.mc_negf_build_kernel(sysm, V, g, torch.tensor(E, device=DEV), ws)
+    rows = list(range(k.n_out))
+    for e in (0, 65535, 65536, nE - 1):
+        thr, al = k.alias_rows(e, rows)
+        ws1 = M.allocate_workspace(sysm, 1)
+        k1 = M.mc_negf_build_kernel(sysm, V, g, torch.tensor(E[e:e + 1], device=DEV), ws1)
+        thr1, al1 = k1.alias_rows(0, rows)
+        assert (thr == thr1).all() and (al == al1).all(), e
+    thr, al = k.alias_tables()
+    tal = torch.zeros((nE, M.TALLY_N), dtype=torch.int64, device=DEV)
+    M.mc_negf_walk(k, SEED, 0, 0, 0, 50, 1_000_000, tal)
+    assert (tal.cpu().numpy() == OW.walk_alias(thr, al, SEED, 0, 0, 0, 50)).all()
