@@ -6,7 +6,8 @@
   differ by at most one unit of 2^-32.
 - Walks: on the oracle's alias and step-7' tables the GPU's tallies and exit-energy histogram
   equal the oracle walker's exactly (integers), for both leads, several line sets, truncated
-  walks, a walker range that does not fill the last workgroup, and up to 8 lines.
+  walks, a walker range that does not fill the last workgroup, up to 8 lines, and the largest
+  energy grid (4096 energies).
 - Elastic limit: with the single line at 0 the GPU's inelastic walks are mc_negf_walk's, tally
   for tally, on the GPU's own tables (also at the full wire size).
 - Statistics: the GPU's exit distribution and current agree with the exact chain within 5
@@ -248,3 +249,25 @@ def test_wire_walks_with_the_phonon_lines():
     torch.cuda.synchronize()
     assert float(S[1].sum()) == pytest.approx(I, rel=1e-12)
     assert sI < 0.01 * I
+
+
+def test_the_largest_energy_grid_equals_the_oracle_walker():
+    # nE = 4096, the most energies the walker's exit-energy histogram holds in LDS (2 nE
+    # counters), on a two-site chain: tallies and the full histogram equal the oracle walker's
+    nE = 4096
+    c = case(W=1, L=2, eta=0.5, disorder=0.2, nE=nE, emin=-1.9, emax=1.9)
+    k = gpu_build(c)
+    sols = oracle_solve(c)
+    thr, al = oracle_alias_tables(sols, k.alias_pitch)
+    k.set_alias_tables(thr, al)
+    A = np.array([s.Adiag for s in sols])
+    offsets, lambdas = [-8, 0, 8], [0.5, 1.0, 0.5]
+    et = IN.energy_table(A, offsets, lambdas)
+    nw = 300
+    tal, hist = gpu_walk(k, offsets, to_device_table(et), nw, 1, 9, 4)
+    rt, rh, bad = IN.walk_alias(thr, al, et, offsets, SEED, 4, 1, 9, nw)
+    assert not bad
+    assert np.array_equal(tal, rt)
+    assert np.array_equal(hist, rh)
+    assert (tal[:, :3].sum(axis=1) == nw).all()
+    assert hist[:, :, :8].sum() > 0 and hist[:, :, -8:].sum() > 0   # walks reach both ends
