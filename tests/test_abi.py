@@ -497,3 +497,18 @@ def test_handle_whose_size_wraps_in_32_bits_is_rejected():
     # rows above 16320 outcomes do not fit the walker's 16-bit alias indices
     ks = _fake_handle(W=32, L=510, nE=1, p_pitch=16320)
     assert M.lib().mc_negf_walk(ctypes.byref(ks), 1, 0, 0, 0, 10, 10, t, None) == M.EINVAL
+
+
+def test_sampled_walk_energy_limit_on_the_host():
+    # the energy-sampled walk counts walkers per energy in LDS: at most 16384 energies
+    lib = M.lib()
+    ks = _fake_handle(nE=16384)
+    out = ctypes.c_uint64(0)
+    assert lib.mc_negf_walk_sampled_bytes(ctypes.byref(ks), 10, ctypes.byref(out)) == M.OK
+    ks.nE = 16385
+    assert lib.mc_negf_walk_sampled_bytes(ctypes.byref(ks), 10, ctypes.byref(out)) == M.EINVAL
+    p = ctypes.c_void_p(4096)
+    assert lib.mc_negf_walk_sampled(ctypes.byref(ks), 1, 0, 0, 0, 10, 10, p, p, p, 1 << 40,
+                                    None) == M.EINVAL
+    assert lib.mc_negf_walk_sampled_noalloc(ctypes.byref(ks), 1, 0, 0, 0, 10, 10, p, p,
+                                            None) == M.EINVAL

@@ -105,3 +105,20 @@ def test_sampled_rejects_bad_arguments():
     with pytest.raises(M.McnegfError) as ei:
         M.mc_negf_walk_sampled(k, 1, 0, 2, 0, 1000, 100, tw, tal, scratch)
     assert ei.value.code == M.EINVAL
+
+
+def test_the_largest_energy_grid_replays_in_the_oracle():
+    # nE = 16384, the most energies the sampled walk's per-energy counters hold in LDS; a
+    # thermal window puts the draws on a few hundred of them and leaves the rest at zero
+    nE = 16384
+    k, E, V, g = setup(1, 2, 0.3, nE, 0.2, 5)
+    w = thermal_weights(E, 0.2, 0.05)
+    tw = torch.tensor(w, device=DEV)
+    seed, r, wbegin, n = 0xC0FFEE, 1, 3, 200_000
+    tal = torch.zeros((nE, M.TALLY_N), dtype=torch.int64, device=DEV)
+    scratch = torch.empty(M.mc_negf_walk_sampled_bytes(k, n), dtype=torch.uint8, device=DEV)
+    M.mc_negf_walk_sampled(k, seed, r, 0, wbegin, n, 1_000_000, tw, tal, scratch)
+    got = tal.cpu().numpy()
+    thr, al = k.alias_tables()
+    assert (got == OW.walk_sampled_alias(thr, al, w, seed, r, 0, wbegin, n)).all()
+    assert got[:, :3].sum() == n and (got[:, :3].sum(axis=1) > 0).sum() > 100
