@@ -363,6 +363,7 @@ int32_t mc_negf_grad_mc(const mcnegf_kernel* k, uint32_t inject_lead, const uint
  * mc_negf_spectrum: d_spectrum [2][nE] (device) = the energy-resolved current
  *   S[r][e] = sum_e0 w_e0 c_p(e0) hist[r][e0][e] / N_e0 (N_e0 the walkers injected at e0);
  *   sum_e S[q][e] is the current of the tallies.  Asynchronous.
+ * All three launch one kernel each and are capturable in a HIP graph (mc_negf_graph_begin).
  */
 int32_t mc_negf_energy_table_bytes(const mcnegf_kernel* k, int32_t n_lines, uint64_t* bytes_out);
 int32_t mc_negf_energy_table(const mcnegf_kernel* k, int32_t n_lines, const int32_t* h_offsets,
@@ -593,7 +594,8 @@ int32_t mc_negf_plan_waves(const mcnegf_system* systems, int32_t n, int32_t nE,
  * mc_negf_graph_begin starts capturing `stream`; mc_negf_graph_end stops it and instantiates
  * the graph into *out (a host handle, freed by mc_negf_graph_destroy); mc_negf_graph_launch
  * replays it on `stream`.  Between begin and end only asynchronous calls may be made
- * (mc_negf_build_kernel, mc_negf_walk, mc_negf_walk_batch, mc_negf_current_async): the
+ * (mc_negf_build_kernel, mc_negf_walk, mc_negf_walk_batch, mc_negf_walk_sampled,
+ * mc_negf_current_async, mc_negf_energy_table, mc_negf_walk_inelastic, mc_negf_spectrum): the
  * synchronising calls fail inside a capture.  No launch timing while capturing.
  */
 typedef struct mcnegf_graph_s* mcnegf_graph;

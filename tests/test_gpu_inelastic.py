@@ -14,6 +14,7 @@
   sigma (bins) and 4 sigma (current); the energy-resolved current equals the oracle's from the
   same histogram and sums to the current of the tallies.
 - The benchmark's configuration (full wire, phonon lines): properties that hold at any size.
+- Graph capture: table, walks and spectrum captured once; every replay equals the eager run.
 """
 import numpy as np
 import pytest
@@ -271,3 +272,50 @@ def test_the_largest_energy_grid_equals_the_oracle_walker():
     assert np.array_equal(hist, rh)
     assert (tal[:, :3].sum(axis=1) == nw).all()
     assert hist[:, :, :8].sum() > 0 and hist[:, :, -8:].sum() > 0   # walks reach both ends
+
+
+def test_graph_replays_match_eager():
+    # Capture: the step-7' table, zeroed tallies and histogram (fill kernels, no memset node),
+    # the inelastic walks and the energy-resolved current.  Replay three times with eager
+    # work and synchronisations between replays; every replay must equal the eager run.
+    c = case(W=3, L=4, eta=0.3, disorder=0.3, nE=10, emin=-1.8, emax=1.6)
+    k = gpu_build(c)
+    off, lam = [-1, 0, 1], [0.5, 1.0, 0.5]
+    table = torch.empty(M.mc_negf_energy_table_bytes(k, 3) // 8, dtype=torch.int64, device=DEV)
+    tal = torch.zeros((k.nE, M.TALLY_N), dtype=torch.int64, device=DEV)
+    hist = torch.zeros((2, k.nE, k.nE), dtype=torch.int64, device=DEV)
+    S = torch.empty((2, k.nE), dtype=torch.float64, device=DEV)
+    wts = torch.tensor(c["w"], device=DEV)
+
+    def step(stream):
+        tal.zero_()
+        hist.zero_()
+        M.mc_negf_energy_table(k, off, lam, table, stream)
+        M.mc_negf_walk_inelastic(k, off, table, SEED, 1, 0, 0, 20_000, 1_000_000, tal, hist,
+                                 stream)
+        M.mc_negf_spectrum(k, 0, tal, hist, wts, S, stream)
+
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        step(s)
+    s.synchronize()
+    eager = [x.cpu().numpy().copy() for x in (table, tal, hist, S)]
+    assert eager[2].sum() == 20_000 * k.nE - eager[1][:, 2].sum()
+    with torch.cuda.stream(s):
+        M.mc_negf_graph_begin(s)
+        step(s)
+        g = M.mc_negf_graph_end(s)
+    try:
+        for rep in range(3):
+            for x in (table, tal, hist):
+                x.fill_(-1)
+            S.fill_(float("nan"))
+            y = torch.randn(1 << 16, device=DEV, dtype=torch.float64)
+            (y * y).sum().item()
+            g.launch(s)
+            s.synchronize()
+            for x, e in zip((table, tal, hist, S), eager):
+                assert (x.cpu().numpy() == e).all(), rep
+    finally:
+        g.destroy()
