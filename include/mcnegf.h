@@ -32,8 +32,11 @@
  *   - Pointers named d_* are device pointers (HBM of the current HIP device); h_* are host.
  *     The caller owns every buffer.  The library allocates no device memory and keeps no
  *     global state; calls on different streams with different workspaces are independent.
- *   - All calls are asynchronous on `stream` except mc_negf_workspace_bytes (host only),
- *     mc_negf_current and mc_negf_status (both synchronise `stream`).
+ *   - All calls are asynchronous on `stream` except the host-only ones (the *_bytes size
+ *     queries, mc_negf_interp_plan, mc_negf_plan_waves) and those that synchronise `stream`
+ *     to return host results: mc_negf_current, mc_negf_current_interp,
+ *     mc_negf_current_weighted, mc_negf_grad, mc_negf_status, mc_negf_batch_prepare,
+ *     mc_negf_walk_batch_autotune (and mc_negf_profile_end, which waits for its events).
  *   - Every call returns an int32 status: 0 OK, > 0 warning, < 0 error (codes below).
  *     Arguments are validated on the host before any GPU work; on an error nothing is
  *     launched.  No C++ exception crosses the ABI.
