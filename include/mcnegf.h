@@ -598,8 +598,10 @@ int32_t mc_negf_plan_waves(const mcnegf_system* systems, int32_t n, int32_t nE,
  * the graph into *out (a host handle, freed by mc_negf_graph_destroy); mc_negf_graph_launch
  * replays it on `stream`.  Between begin and end only asynchronous calls may be made
  * (mc_negf_build_kernel, mc_negf_walk, mc_negf_walk_batch, mc_negf_walk_sampled,
- * mc_negf_current_async, mc_negf_energy_table, mc_negf_walk_inelastic, mc_negf_spectrum): the
- * synchronising calls fail inside a capture.  No launch timing while capturing.
+ * mc_negf_current_async, mc_negf_energy_table, mc_negf_walk_inelastic, mc_negf_spectrum,
+ * mc_negf_weighted_tables, mc_negf_walk_weighted, mc_negf_interp_distances,
+ * mc_negf_walk_interp; each has a replay test): the synchronising calls fail inside a
+ * capture.  No launch timing while capturing.
  */
 typedef struct mcnegf_graph_s* mcnegf_graph;
 int32_t mc_negf_graph_begin(hipStream_t stream);

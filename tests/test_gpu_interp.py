@@ -4,7 +4,8 @@ The interval distances must match the oracle's row distances; interpolated walks
 own alias tables must equal the oracle's C walker bit for bit (same mixture draw and Philox
 streams); the interpolated current must equal the oracle's estimator on the same tallies and
 lie within 3 sigma of the exact expectation of the interpolated walk (Markov chain of the mixed
-rows); an energy outside the built ones is reported.
+rows); an energy outside the built ones is reported; distances and walks captured in a HIP
+graph give the eager results on every replay.
 """
 import numpy as np
 import pytest
@@ -149,3 +150,42 @@ def test_planned_interpolation_of_a_wire_within_3_sigma_of_direct():
         a = OI.alpha_fixed32(a) / 2.0 ** 32
         I_ex += wf * OI.interpolated_transmission(Ks[lo], Ks[min(lo + 1, len(nodes) - 1)], a)
     assert abs(I - I_ex) <= 3 * sI, (I, I_ex, sI)
+
+
+def test_graph_replays_match_eager():
+    # Capture: the interval distances, zeroed tallies (a fill kernel, no memset node) and the
+    # interpolated walks.  Replay three times with eager work and synchronisations between
+    # replays; every replay must equal the eager run.
+    nodes = [-1.0, -0.6, -0.2, 0.3, 0.8]
+    k, V, g = build_at(2, 5, 0.2, nodes)
+    fine = torch.tensor(FINE, dtype=torch.float64, device=DEV)
+    dist = torch.empty(len(nodes) - 1, dtype=torch.float64, device=DEV)
+    tal = torch.zeros((len(FINE), M.TALLY_N), dtype=torch.int64, device=DEV)
+
+    def step(stream):
+        tal.zero_()
+        M.mc_negf_interp_distances(k, dist, stream)
+        M.mc_negf_walk_interp(k, fine, SEED, 2, 0, 0, 20_000, 1_000_000, tal, stream)
+
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        step(s)
+    s.synchronize()
+    eager = [x.cpu().numpy().copy() for x in (dist, tal)]
+    with torch.cuda.stream(s):
+        M.mc_negf_graph_begin(s)
+        step(s)
+        gr = M.mc_negf_graph_end(s)
+    try:
+        for rep in range(3):
+            dist.fill_(float("nan"))
+            tal.fill_(-1)
+            y = torch.randn(1 << 16, device=DEV, dtype=torch.float64)
+            (y * y).sum().item()
+            gr.launch(s)
+            s.synchronize()
+            for x, e in zip((dist, tal), eager):
+                assert (x.cpu().numpy() == e).all(), rep
+    finally:
+        gr.destroy()

@@ -10,6 +10,8 @@ against the oracle (oracle/weighted.py).
   estimate is the oracle's DIRECT T_eff at 1e-9 with a standard error below 1e-7 of it.
 - With a ramp bias the estimate is unbiased (within 4 sigma of DIRECT) and its sigma is well
   below the plain walk's at the same walker count.
+- Graph capture: modified tables and weighted walks captured once; every replay equals the
+  eager run.
 """
 import numpy as np
 import pytest
@@ -241,3 +243,60 @@ def test_modified_tables_from_a_kernel_without_its_own_tables():
     tal, ws = walk(k0, buf0, b, 20_000, inject=1)
     t2, w2 = walk(k, buf, b, 20_000, inject=1)
     assert torch.equal(tal, t2) and torch.equal(ws, w2)
+
+
+def test_graph_replays_match_eager():
+    # Capture: the modified tables, zeroed counts and score sums (fill kernels, no memset node)
+    # and the importance-sampled walks.  Replay three times with eager work and
+    # synchronisations between replays; every replay must equal the eager run.
+    W, L, nE = 3, 4, 4
+    c = case(W=W, L=L, eta=0.3, disorder=0.3, nE=nE, emin=-1.5, emax=1.5)
+    k = gpu_build(c)
+    bias = np.stack([WT.ramp_bias(W, L, 0, a=3.0, floor_p=0.01) for _ in range(nE)])
+    b = torch.tensor(bias, device=DEV)
+    buf = torch.empty(M.mc_negf_weighted_tables_bytes(k), dtype=torch.uint8, device=DEV)
+    nw = 20_000
+    tal = torch.zeros((nE, M.TALLY_N), dtype=torch.int64, device=DEV)
+    wsum = torch.zeros((nE, 2), dtype=torch.float64, device=DEV)
+    scratch = torch.empty(max(M.mc_negf_walk_weighted_bytes(k, nw), 256), dtype=torch.uint8,
+                          device=DEV)
+
+    def step(stream):
+        tal.zero_()
+        wsum.zero_()
+        M.mc_negf_weighted_tables(k, b, buf, stream)
+        M.mc_negf_walk_weighted(k, buf, b, SEED, 0, 0, 0, nw, 1_000_000, tal, wsum, scratch,
+                                stream)
+
+    def written():
+        # what the build writes: the entries of the n outcomes of every row, and rho (the
+        # pitch padding and alignment gaps of the buffer are never written)
+        packed, low, rho = M.weighted_tables_views(k, buf)
+        n = k.n_out
+        return [packed[..., :n].cpu().numpy().copy(), low[..., :n].cpu().numpy().copy(),
+                rho.cpu().numpy().copy(), tal.cpu().numpy().copy(), wsum.cpu().numpy().copy()]
+
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        step(s)
+    s.synchronize()
+    eager = written()
+    assert eager[3][:, :3].sum() == nw * nE
+    with torch.cuda.stream(s):
+        M.mc_negf_graph_begin(s)
+        step(s)
+        g = M.mc_negf_graph_end(s)
+    try:
+        for rep in range(3):
+            buf.fill_(0xAB)
+            tal.fill_(-1)
+            wsum.fill_(float("nan"))
+            y = torch.randn(1 << 16, device=DEV, dtype=torch.float64)
+            (y * y).sum().item()
+            g.launch(s)
+            s.synchronize()
+            for i, (x, e) in enumerate(zip(written(), eager)):
+                assert (x == e).all(), (rep, i)
+    finally:
+        g.destroy()
