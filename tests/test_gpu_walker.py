@@ -243,3 +243,55 @@ def test_more_energies_than_the_reported_grid_height():
     tal = torch.zeros((nE, M.TALLY_N), dtype=torch.int64, device=DEV)
     M.mc_negf_walk(k, SEED, 0, 0, 0, 50, 1_000_000, tal)
     assert (tal.cpu().numpy() == OW.walk_alias(thr, al, SEED, 0, 0, 0, 50)).all()
+
+
+def test_graph_of_a_whole_step_matches_eager():
+    # Capture: the kernel build, zeroed tallies (a fill kernel, no memset node), one walk and
+    # both currents into device outputs (mc_negf_current_async).  Replay three times with eager
+    # work and synchronisations between replays; every replay must equal the eager run.
+    c = case(W=3, L=4, eta=0.3, disorder=0.3, nE=6, emin=-1.5, emax=1.5)
+    sysm = M.make_system(3, 4)
+    ws = M.allocate_workspace(sysm, 6)
+    V = torch.tensor(c["V"], device=DEV)
+    g = torch.tensor(c["g"], device=DEV)
+    E = torch.tensor(c["E"], device=DEV)
+    w = torch.tensor(c["w"], device=DEV)
+    tal = torch.zeros((6, M.TALLY_N), dtype=torch.int64, device=DEV)
+    T = torch.empty(6, dtype=torch.float64, device=DEV)
+    sg = torch.empty_like(T)
+    out = torch.zeros((2, 2), dtype=torch.float64, device=DEV)
+
+    def step(stream):
+        k = M.mc_negf_build_kernel(sysm, V, g, E, ws, stream)
+        tal.zero_()
+        M.mc_negf_walk(k, SEED, 0, 0, 0, 20_000, 1_000_000, tal, stream)
+        M.mc_negf_current_async(k, 0, 0, tal, w, T, sg, out[0], stream)
+        M.mc_negf_current_async(k, 1, 0, None, w, T, sg, out[1], stream)
+        return k
+
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        k = step(s)
+    s.synchronize()
+    n = k.n_out
+    eager = [x.cpu().numpy().copy() for x in (tal, out, k.P(), k.alias_packed()[..., :n])]
+    with torch.cuda.stream(s):
+        M.mc_negf_graph_begin(s)
+        step(s)
+        gr = M.mc_negf_graph_end(s)
+    try:
+        for rep in range(3):
+            tal.fill_(-1)
+            out.fill_(float("nan"))
+            k.P().fill_(float("nan"))
+            k.alias_packed().fill_(-1)
+            y = torch.randn(1 << 16, device=DEV, dtype=torch.float64)
+            (y * y).sum().item()
+            gr.launch(s)
+            s.synchronize()
+            for i, (x, e) in enumerate(zip((tal, out, k.P(), k.alias_packed()[..., :n]),
+                                           eager)):
+                assert (x.cpu().numpy() == e).all(), (rep, i)
+    finally:
+        gr.destroy()
