@@ -460,8 +460,10 @@ __device__ __noinline__ void factor_diag_block(lds_double* VZs, lds_double* Ls, 
             const bool good = piv > 0.0 && isfinite(piv);
             bad |= !good;
             piv = good ? piv : 1.0;
-            const double d = sqrt(piv);
-            const double lik = (i >= k) ? rw[k] / d : 0.0;
+            // one reciprocal square root and a product per lane: a shorter dependent chain
+            // per pivot than a square root followed by a division
+            const double rs = rsqrt(piv);
+            const double lik = (i >= k) ? rw[k] * rs : 0.0;
             rw[k] = lik;
             colbuf[i] = lik;
 #pragma unroll
