@@ -80,8 +80,12 @@ __device__ inline bool gj_invert(double2 (&a)[Narrow<W>::M], int i, int q, int& 
         const double2 pp = cmk(readlane_d(a[mp].x, r + 16 * qp), readlane_d(a[mp].y, r + 16 * qp));
         const double pm = cabs2(pp);
         if (!(pm > 0.0) || !isfinite(pm)) ok = false;
-        // 1 / pp = conj(pp) / |pp|^2: one division on the pivot step's critical path
-        const double rpm = 1.0 / pm;
+        // 1 / pp = conj(pp) / |pp|^2: the reciprocal of |pp|^2 is on the pivot step's critical
+        // path, so it is the hardware estimate refined by two Newton steps (each doubles the
+        // correct bits) rather than a full division, a shorter dependent chain
+        double rpm = __builtin_amdgcn_rcp(pm);
+        rpm = fma(rpm, fma(-pm, rpm, 1.0), rpm);
+        rpm = fma(rpm, fma(-pm, rpm, 1.0), rpm);
         const double2 pinv = cmk(pp.x * rpm, -pp.y * rpm);
         // per-lane choices as selects: every lane stays active for the next pivot's cross-lane
         // reads
